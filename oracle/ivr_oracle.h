@@ -1,0 +1,108 @@
+/*
+ * FP64 CPU oracle for isogeometric volume rendering (Fuchs & Hjelmervik,
+ * "Interactive Isogeometric Volume Visualization with Pixel-Accurate Geometry").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header or table with the GPU library; the two meet only through the seeded
+ * scene generators.
+ *
+ * What it computes (per pixel, for the ray e + s*d, s > 0):
+ *   - every crossing of the ray with the six boundary faces of every block
+ *     (Sec. "View-Ray Intersections with Surfaces"), found by Bezier extraction,
+ *     convex-hull culling and subdivision, then FP64 Newton;
+ *   - the entry/exit pairs of Algorithm "Blockwise depth-sorting";
+ *   - the emission-absorption integral of Eq. (volRenderIntegral) with
+ *     rho_gamma(s) = rho(phi^-1(gamma(s))) of Eq. (rhoPhiInv), by the midpoint
+ *     rule on fine panels (Algorithm "Front-to-back compositing" applied to
+ *     constant panels, which is exact for them) with the preimage of every panel
+ *     midpoint found by Newton's method of Eq. (newtonsmethod), plus one
+ *     Richardson extrapolation;
+ *   - the explicit Runge-Kutta family of Sec. "ODE Based Algorithm" on the
+ *     analytic map of the convergence study (Table "2dcomparisonefficiency").
+ * All arithmetic is IEEE double.  Errors are returned as negative ints.
+ */
+#ifndef IVR_ORACLE_H
+#define IVR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t deg[3];
+    int32_t ncp[3];
+    const double *knots[3];   /* ncp[d]+deg[d]+1 values, clamped, on [0,1] */
+    const double *cp;         /* ncp0*ncp1*ncp2 x (x,y,z,w), i fastest     */
+    const double *scalar;     /* ncp0*ncp1*ncp2 coefficients of rho         */
+    int32_t rational;         /* 1: NURBS (w used), 0: plain B-spline       */
+} orc_patch;
+
+typedef struct {
+    int32_t n;                /* number of knots of the transfer function   */
+    const double *x;          /* n abscissae on [0,1], increasing           */
+    const double *rgba;       /* n x (R,G,B,A)                              */
+    double extinction;        /* kappa = extinction * A                     */
+    double domain[2];         /* rho -> (rho - lo) / (hi - lo), clamped     */
+} orc_tf;
+
+typedef struct {
+    double eye[3], target[3], up[3];
+    double fov_y_deg;
+    int32_t width, height;
+} orc_camera;
+
+typedef struct {
+    double panels_per_scale;  /* panel width = scale / panels_per_scale      */
+    int32_t richardson;       /* 1: combine h and h/2 as (4 I_{h/2} - I_h)/3 */
+    int32_t nthreads;         /* 0: all online cores                         */
+    double self_tol;          /* halve the panels while |I_h - I_{h/2}| > this */
+} orc_opts;
+
+typedef struct orc_scene orc_scene;
+
+/* Fragment record returned by orc_ray_fragments. */
+typedef struct {
+    double t;                 /* ray parameter (unit direction)             */
+    double p[3];              /* parameter point on the block boundary      */
+    int32_t patch, face;      /* face 0..5 = u0,u1,v0,v1,w0,w1              */
+    int32_t entering;         /* 1: ray enters the block here               */
+    int32_t pad;
+} orc_fragment;
+
+/* Per-pixel diagnostics. */
+typedef struct {
+    int32_t n_fragments, n_segments, n_anomalies, n_newton_fail;
+    double self_error;        /* max |I_h - I_{h/2}| over channels/segments  */
+} orc_pixel_diag;
+
+orc_scene *orc_prepare(const orc_patch *patches, int32_t n, double scale);
+void orc_free(orc_scene *s);
+
+/* All B-spline basis functions N_{i,p}(u) and their derivatives, i=0..nk-p-2. */
+int32_t orc_basis(const double *t, int32_t nk, int32_t p, double u, double *N, double *dN);
+/* phi, its Jacobian (row-major J[r*3+c] = d phi_r / d p_c) and rho at p. */
+int32_t orc_eval(const orc_patch *P, const double p[3], double x[3], double J[9], double *rho);
+/* Newton preimage of g with line search and clamping to [0,1]^3. */
+int32_t orc_invert(const orc_patch *P, const double g[3], const double seed[3], double scale,
+                   double p_out[3], int32_t *iterations);
+/* Pinhole ray through pixel position (px, py) (pixel centres at i+0.5). */
+void orc_camera_ray(const orc_camera *c, double px, double py, double o[3], double d[3]);
+/* Transfer function at rho: (R,G,B,kappa). */
+void orc_transfer(const orc_tf *tf, double rho, double out[4]);
+/* Every non-grazing boundary crossing of the ray, sorted by t. Returns count or <0. */
+int32_t orc_ray_fragments(const orc_scene *s, const double o[3], const double d[3],
+                          orc_fragment *out, int32_t cap);
+/* Render a list of pixels (linear index row*width+col); NULL list = whole image. */
+int32_t orc_render_pixels(const orc_scene *s, const orc_camera *cam, const orc_tf *tf,
+                          const orc_opts *opts, const int64_t *pixels, int64_t npix,
+                          double *rgba, double *depth, orc_pixel_diag *diag);
+/* Convergence study: error of an explicit RK method on the analytic 2-D map.
+   method 1 Euler, 2 midpoint, 3 Kutta, 4 classic, 5 3/8-rule, 6 Fehlberg (5th). */
+double orc_table1(int32_t method, double ds, double c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

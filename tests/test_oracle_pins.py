@@ -1,0 +1,474 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: values printed
+in the paper, closed forms, library routines (scipy), invariants and brute force.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.interpolate import BSpline, insert as spl_insert
+
+import oracle
+from scenes import make_config, affine_patch, camera_from_angles, random_tf
+from scenes.configs import Patch, TransferFunction, open_uniform_knots, greville
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ Table 1
+
+def _read_table1():
+    rows = {}
+    with open(os.path.join(GOLDEN, "table1_convergence.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            rows[int(parts[0])] = (parts[1], [float(v) for v in parts[2:6]])
+    return rows
+
+
+def test_table1_explicit_rk_reproduces_printed_errors(oracle_lib):
+    """Sec. 'Convergence study', Table '2dcomparisonefficiency': the explicit RK family
+    (Euler, midpoint, Kutta, classic, 3/8, Fehlberg 5th order) with c = 1 and absolute
+    arc-length steps 2^-6..2^-9 reproduces the printed errors.  A wrong tableau entry
+    changes the order and misses by orders of magnitude."""
+    rows = _read_table1()
+    for mid, (name, printed) in rows.items():
+        ours = [oracle.table1(mid, 2.0 ** -e, 1.0) for e in (6, 7, 8, 9)]
+        for o, p in zip(ours, printed):
+            assert 0.75 <= o / p <= 1.35, (name, ours, printed)
+        # observed order between the first and last step size
+        slope = math.log(ours[0] / ours[-1]) / math.log(8.0)
+        expected = {1: 1, 2: 2, 3: 3, 4: 4, 5: 4, 6: 5}[mid]
+        assert abs(slope - expected) < 0.35, (name, slope)
+
+
+# ------------------------------------------------------------------ basis
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_basis_matches_scipy_and_identities(oracle_lib, p):
+    """Eq. (Bspline) basis: agrees with scipy's B-spline, partition of unity,
+    non-negativity, derivatives sum to zero; non-uniform knots with repeats."""
+    rng = np.random.default_rng(7 + p)
+    interior = np.sort(rng.uniform(0.05, 0.95, 5))
+    if p >= 2:
+        interior = np.concatenate([interior, interior[:1]])  # one repeated knot
+    t = np.concatenate([[0.0] * (p + 1), np.sort(interior), [1.0] * (p + 1)])
+    n = len(t) - p - 1
+    for u in np.concatenate([rng.uniform(0, 1, 50), [0.0, 1.0, interior[0]]]):
+        N, dN = oracle.basis(t, p, u)
+        assert abs(N.sum() - 1.0) < 1e-14
+        assert (N >= -1e-15).all()
+        assert abs(dN.sum()) < 1e-10 * max(1.0, np.abs(dN).max())
+        for i in range(n):
+            c = np.zeros(n)
+            c[i] = 1.0
+            s = BSpline(t, c, p)
+            assert abs(N[i] - s(u)) < 1e-13
+            if u not in t:                       # derivative is one-sided at knots
+                assert abs(dN[i] - s(u, nu=1)) < 1e-9 * max(1.0, abs(dN[i]))
+
+
+# ------------------------------------------------------------------ evaluation
+
+def _patches_for_eval():
+    c1 = make_config(1).patches[0]
+    c2 = make_config(2).patches[0]
+    c3 = make_config(3, 64, 36).patches[21]
+    c4 = make_config(4, 64, 36).patches[100]
+    return {"c1": c1, "c2": c2, "c3": c3, "c4_nurbs": c4}
+
+
+@pytest.fixture(scope="module")
+def eval_patches():
+    return _patches_for_eval()
+
+
+def test_affine_patch_is_affine(oracle_lib):
+    """Control points A*greville+b give phi(p) = A p + b and J = A exactly (linear
+    precision of B-splines)."""
+    A = np.array([[1.2, 0.3, -0.1], [0.1, 0.9, 0.2], [-0.2, 0.1, 1.5]])
+    b = np.array([0.3, -0.7, 2.0])
+    for deg, ncp in [((2, 2, 2), (4, 4, 4)), ((3, 3, 3), (7, 5, 6)), ((1, 2, 3), (3, 5, 4))]:
+        P = affine_patch(A, b, deg, ncp)
+        rng = np.random.default_rng(1)
+        for p in rng.uniform(0, 1, (20, 3)):
+            x, J, _ = oracle.evaluate(P, p)
+            assert np.allclose(x, A @ p + b, atol=1e-13)
+            assert np.allclose(J, A, atol=1e-12)
+
+
+def test_jacobian_matches_central_differences(oracle_lib, eval_patches):
+    rng = np.random.default_rng(3)
+    for name, P in eval_patches.items():
+        op = oracle.OraclePatch(P)
+        for p in rng.uniform(0.05, 0.95, (10, 3)):
+            _, J, _ = oracle.evaluate(op, p)
+            h = 1e-6
+            Jfd = np.zeros((3, 3))
+            for c in range(3):
+                e = np.zeros(3)
+                e[c] = h
+                xp, _, _ = oracle.evaluate(op, p + e)
+                xm, _, _ = oracle.evaluate(op, p - e)
+                Jfd[:, c] = (xp - xm) / (2 * h)
+            assert np.abs(J - Jfd).max() <= 1e-7 * max(1.0, np.abs(J).max()), name
+
+
+def test_nurbs_with_unit_weights_equals_bspline(oracle_lib):
+    P = make_config(3, 64, 36).patches[5]
+    Q = Patch(P.degree, P.ncp, P.knots, P.cp.copy(), P.scalar.copy(), rational=True)
+    for p in np.random.default_rng(4).uniform(0, 1, (10, 3)):
+        a = oracle.evaluate(P, p)
+        b = oracle.evaluate(Q, p)
+        assert np.allclose(a[0], b[0], atol=1e-13) and abs(a[2] - b[2]) < 1e-13
+        assert np.allclose(a[1], b[1], atol=1e-11)
+
+
+def test_nurbs_matches_homogeneous_scipy(oracle_lib):
+    """NURBS evaluation equals the projection of the tensor-product B-spline of the
+    homogeneous points, evaluated with scipy."""
+    P = make_config(4, 64, 36).patches[37]
+    n0, n1, n2 = P.ncp
+    H = np.empty((n2, n1, n0, 5))
+    g = P.grid()
+    H[..., :3] = g[..., :3] * g[..., 3:4]
+    H[..., 3] = g[..., 3]
+    H[..., 4] = P.scalar.reshape(n2, n1, n0) * g[..., 3]
+    rng = np.random.default_rng(5)
+    for p in rng.uniform(0, 1, (10, 3)):
+        bu = [BSpline(P.knots[0], np.eye(n0)[i], 3)(p[0]) for i in range(n0)]
+        bv = [BSpline(P.knots[1], np.eye(n1)[i], 3)(p[1]) for i in range(n1)]
+        bw = [BSpline(P.knots[2], np.eye(n2)[i], 3)(p[2]) for i in range(n2)]
+        h = np.einsum("i,j,k,kjic->c", bu, bv, bw, H)
+        x, _, rho = oracle.evaluate(P, p)
+        assert np.allclose(x, h[:3] / h[3], atol=1e-13)
+        assert abs(rho - h[4] / h[3]) < 1e-13
+
+
+def test_twisted_bar_det_close_to_eight(oracle_lib):
+    """The exact twisted map has det J = 8 everywhere; the spline stays within 1%."""
+    P = make_config(2).patches[0]
+    for p in np.random.default_rng(6).uniform(0, 1, (40, 3)):
+        _, J, _ = oracle.evaluate(P, p)
+        assert abs(np.linalg.det(J) - 8.0) < 0.08
+
+
+# ------------------------------------------------------------------ inversion
+
+def test_round_trip_inversion(oracle_lib, eval_patches):
+    """F(F^-1(x)) = x and F^-1(F(p)) = p at interior points, from the patch centre."""
+    rng = np.random.default_rng(8)
+    for name, P in eval_patches.items():
+        op = oracle.OraclePatch(P)
+        for p in rng.uniform(0.02, 0.98, (15, 3)):
+            x, _, _ = oracle.evaluate(op, p)
+            rc, q, it = oracle.invert(op, x, (0.5, 0.5, 0.5), scale=10.0)
+            assert rc == 0, name
+            assert np.abs(q - p).max() < 1e-10, (name, p, q)
+            x2, _, _ = oracle.evaluate(op, q)
+            assert np.linalg.norm(x2 - x) <= 1e-11
+
+
+# ------------------------------------------------------------------ camera, TF
+
+def test_camera_centre_ray_hits_target(oracle_lib):
+    cam = camera_from_angles([0.5, 0.5, 0.5], 3.0, 30.0, 20.0, 64, 64)
+    o, d = oracle.camera_ray(cam, 32.0, 32.0)
+    f = (cam.target - cam.eye) / np.linalg.norm(cam.target - cam.eye)
+    assert np.allclose(o, cam.eye) and np.allclose(d, f, atol=1e-15)
+    # the top-left pixel corner direction makes half the vertical fov with the axis
+    _, d2 = oracle.camera_ray(cam, 32.0, 0.0)
+    assert abs(math.degrees(math.acos(d2 @ f)) - 20.0) < 1e-10
+    # row 0 is at the top: its direction has a larger z component
+    assert d2[2] > d[2]
+
+
+def test_transfer_function_is_piecewise_linear(oracle_lib):
+    tf = random_tf(np.random.default_rng(9), 3.0, (2.0, 5.0))
+    for rho in np.linspace(1.0, 6.0, 101):
+        n = min(max((rho - 2.0) / 3.0, 0.0), 1.0)
+        ref = [np.interp(n, tf.x, tf.rgba[:, c]) for c in range(4)]
+        got = oracle.transfer(tf, rho)
+        assert np.allclose(got[:3], ref[:3], atol=1e-14)
+        assert abs(got[3] - 3.0 * ref[3]) < 1e-13
+
+
+# ------------------------------------------------------------------ fragments
+
+def _slab(o, d, lo, hi):
+    t0, t1 = -np.inf, np.inf
+    for c in range(3):
+        a, b = (lo[c] - o[c]) / d[c], (hi[c] - o[c]) / d[c]
+        t0, t1 = max(t0, min(a, b)), min(t1, max(a, b))
+    return t0, t1
+
+
+def test_fragments_of_affine_block_are_slab_roots(oracle_lib):
+    """For affine phi the preimage of the ray is the straight line A^-1(o-b) + t A^-1 d,
+    so the boundary crossings are the slab roots against [0,1]^3."""
+    A = np.array([[1.3, 0.2, 0.1], [-0.1, 0.8, 0.3], [0.2, -0.2, 1.1]])
+    b = np.array([0.1, 0.2, -0.3])
+    P = affine_patch(A, b, (3, 3, 3), (6, 5, 7))
+    sc = oracle.OracleScene([P], 3.0)
+    Ai = np.linalg.inv(A)
+    rng = np.random.default_rng(10)
+    checked = 0
+    for _ in range(60):
+        o = rng.uniform(-3, 3, 3) + np.array([0, 0, 5.0])
+        tgt = A @ rng.uniform(0.1, 0.9, 3) + b
+        d = (tgt - o) / np.linalg.norm(tgt - o)
+        t0, t1 = _slab(Ai @ (o - b), Ai @ d, np.zeros(3), np.ones(3))
+        fr = sc.fragments(o, d)
+        assert len(fr) == 2
+        assert fr[0][4] and not fr[1][4]
+        assert abs(fr[0][0] - t0) < 1e-9 and abs(fr[1][0] - t1) < 1e-9
+        for t, p, patch, face, ent in fr:
+            assert np.allclose(p, Ai @ (o + t * d - b), atol=1e-9)
+        checked += 1
+    assert checked == 60
+
+
+# ------------------------------------------------------------------ closed-form images
+
+def _box_chord(o, d):
+    t0, t1 = _slab(o, d, np.zeros(3), np.ones(3))
+    return (t0, t1) if t1 > max(t0, 0) else (None, None)
+
+
+def test_constant_field_gives_one_minus_exp(oracle_lib):
+    """Constant rho (partition of unity makes it exactly constant): alpha =
+    1-exp(-kappa L), RGB = E alpha, with L the chord through config 1's block, whose
+    boundary is the unit cube (un-jittered boundary layer), and depth its entry."""
+    sc = make_config(1)
+    P = sc.patches[0]
+    Pc = Patch(P.degree, P.ncp, P.knots, P.cp, np.full_like(P.scalar, 0.37), False)
+    tf = TransferFunction(sc.tf.x, sc.tf.rgba, 4.0, (0.0, 1.0))
+    cam = camera_from_angles([0.5, 0.5, 0.5], 3.0, 30.0, 20.0, 24, 24)
+    res = oracle.render([Pc], cam, tf, scale=sc.scale)
+    E = np.array([np.interp(0.37, tf.x, tf.rgba[:, c]) for c in range(4)])
+    kappa = 4.0 * E[3]
+    hits = 0
+    for pix in range(24 * 24):
+        o, d = oracle.camera_ray(cam, pix % 24 + 0.5, pix // 24 + 0.5)
+        t0, t1 = _box_chord(o, d)
+        if t0 is None:
+            assert res.rgba[pix, 3] == 0.0 and np.isinf(res.depth[pix])
+            continue
+        hits += 1
+        a = 1.0 - math.exp(-kappa * (t1 - t0))
+        assert abs(res.rgba[pix, 3] - a) < 1e-12
+        assert np.allclose(res.rgba[pix, :3], E[:3] * a, atol=1e-12)
+        assert abs(res.depth[pix] - t0) < 1e-10 * t0
+    assert hits > 100
+
+
+def test_linear_field_on_affine_block_matches_adaptive_quadrature(oracle_lib):
+    """Affine block and a field linear in p: along the ray rho is linear in s with a
+    closed-form preimage.  scipy's adaptive quadrature of the emission-absorption
+    integral (transfer function via numpy interp) agrees with the oracle."""
+    A = np.array([[1.0, 0.2, 0.0], [0.0, 1.1, 0.1], [0.1, 0.0, 0.9]])
+    b = np.array([-0.5, -0.5, -0.5])
+    c_lin = np.array([0.7, -0.4, 0.5])
+    P = affine_patch(A, b, (2, 3, 2), (4, 5, 4), scalar=lambda g: g @ c_lin + 0.2)
+    tf = random_tf(np.random.default_rng(11), 3.0, (-0.3, 1.5))
+    cam = camera_from_angles(A @ np.full(3, 0.5) + b, 4.0, 40.0, 25.0, 9, 9)
+    Ai = np.linalg.inv(A)
+    res = oracle.render([P], cam, tf, scale=2.0)
+    for pix in range(81):
+        o, d = oracle.camera_ray(cam, pix % 9 + 0.5, pix // 9 + 0.5)
+        po, pd = Ai @ (o - b), Ai @ d
+        t0, t1 = _slab(po, pd, np.zeros(3), np.ones(3))
+        if not t1 > max(t0, 0):
+            assert res.rgba[pix, 3] == 0.0
+            continue
+
+        def tfv(s, c):
+            rho = (po + s * pd) @ c_lin + 0.2
+            n = min(max((rho + 0.3) / 1.8, 0.0), 1.0)
+            return np.interp(n, tf.x, tf.rgba[:, c])
+
+        def kappa(s):
+            return 3.0 * tfv(s, 3)
+
+        def tau(s):
+            return quad(kappa, t0, s, epsabs=1e-13, epsrel=1e-13, limit=200)[0]
+        alpha = 1.0 - math.exp(-tau(t1))
+        rgb = [quad(lambda s, c=c: kappa(s) * tfv(s, c) * math.exp(-tau(s)), t0, t1,
+                    epsabs=1e-11, epsrel=1e-11, limit=200)[0] for c in range(3)]
+        assert abs(res.rgba[pix, 3] - alpha) < 2e-6, pix
+        assert np.abs(res.rgba[pix, :3] - rgb).max() < 2e-6, pix
+        assert abs(res.depth[pix] - t0) < 1e-9
+
+
+# ------------------------------------------------------------------ invariances
+
+def _refine(P, d, u, times=1):
+    """Insert knot u into direction d of a patch `times` times (scipy)."""
+    n = list(P.ncp)
+    g = P.grid()                                   # [k, j, i, c]
+    H = np.concatenate([g[..., :3] * g[..., 3:4], g[..., 3:4],
+                        (P.scalar.reshape(n[2], n[1], n[0]) * g[..., 3])[..., None]], axis=-1)
+    axis = 2 - d
+    Hm = np.moveaxis(H, axis, 0)
+    t = P.knots[d]
+    new_t = None
+    cols = []
+    flat = Hm.reshape(Hm.shape[0], -1)
+    for c in range(flat.shape[1]):
+        tck = (t, np.concatenate([flat[:, c], np.zeros(P.degree[d] + 1)]), P.degree[d])
+        tt, cc, _ = spl_insert(u, tck, m=times)
+        new_t = tt
+        cols.append(cc[:len(tt) - P.degree[d] - 1])
+    newn = len(new_t) - P.degree[d] - 1
+    Hn = np.stack(cols, axis=1).reshape((newn,) + Hm.shape[1:])
+    Hn = np.moveaxis(Hn, 0, axis)
+    n[d] = newn
+    w = Hn[..., 3]
+    cp = np.concatenate([Hn[..., :3] / w[..., None], w[..., None]], axis=-1).reshape(-1, 4)
+    knots = list(P.knots)
+    knots[d] = np.asarray(new_t)
+    return Patch(P.degree, tuple(n), knots, cp, (Hn[..., 4] / w).reshape(-1), P.rational)
+
+
+def test_knot_insertion_leaves_map_and_image_unchanged(oracle_lib):
+    sc = make_config(1)
+    P = sc.patches[0]
+    R = _refine(_refine(P, 0, 0.3), 2, 0.71)
+    for p in np.random.default_rng(12).uniform(0, 1, (20, 3)):
+        a, b = oracle.evaluate(P, p), oracle.evaluate(R, p)
+        assert np.allclose(a[0], b[0], atol=1e-13) and abs(a[2] - b[2]) < 1e-13
+    cam = camera_from_angles([0.5, 0.5, 0.5], 3.0, 30.0, 20.0, 16, 16)
+    r1 = oracle.render([P], cam, sc.tf, scale=sc.scale)
+    r2 = oracle.render([R], cam, sc.tf, scale=sc.scale)
+    assert np.abs(r1.rgba - r2.rgba).max() < 1e-9
+
+
+def _split_at(P, d, u):
+    """Split a patch into two C0 patches at parameter u of direction d."""
+    R = _refine(P, d, u, times=P.degree[d] - int(np.sum(np.isclose(P.knots[d], u))))
+    t = R.knots[d]
+    p = P.degree[d]
+    k = int(np.searchsorted(t, u))                    # first index of u
+    n = list(R.ncp)
+    g = R.cp.reshape(n[2], n[1], n[0], 4)
+    s = R.scalar.reshape(n[2], n[1], n[0])
+    axis = 2 - d
+    cut = k                                           # control point index shared by both
+    left = [np.take(a, range(0, cut), axis=axis) for a in (g, s)]
+    right = [np.take(a, range(cut - 1, n[d]), axis=axis) for a in (g, s)]
+    out = []
+    for (gg, ss), kn in [(left, np.append(t[:k + p], u)), (right, np.insert(t[k:], 0, u))]:
+        kn = (kn - kn[0]) / (kn[-1] - kn[0])
+        nn = list(n)
+        nn[d] = gg.shape[axis]
+        knots = list(R.knots)
+        knots[d] = kn
+        out.append(Patch(P.degree, tuple(nn), knots, gg.reshape(-1, 4), ss.reshape(-1), P.rational))
+    return out
+
+
+def test_split_block_gives_same_image(oracle_lib):
+    """Splitting config 1's block at u = 0.5 into two C0 blocks leaves the image
+    unchanged; exercises the blockwise pairing across an interface."""
+    sc = make_config(1)
+    P = sc.patches[0]
+    A, B = _split_at(P, 0, 0.5)
+    for p in np.random.default_rng(13).uniform(0, 1, (10, 3)):
+        q = p.copy()
+        if p[0] < 0.5:
+            q[0] = p[0] / 0.5
+            other = oracle.evaluate(A, q)
+        else:
+            q[0] = (p[0] - 0.5) / 0.5
+            other = oracle.evaluate(B, q)
+        ref = oracle.evaluate(P, p)
+        assert np.allclose(ref[0], other[0], atol=1e-13) and abs(ref[2] - other[2]) < 1e-13
+    cam = camera_from_angles([0.5, 0.5, 0.5], 3.0, 30.0, 20.0, 16, 16)
+    r1 = oracle.render([P], cam, sc.tf, scale=sc.scale)
+    r2 = oracle.render([A, B], cam, sc.tf, scale=sc.scale)
+    assert (r2.n_anomalies == 0).all()
+    assert np.abs(r1.rgba - r2.rgba).max() < 2e-6
+    assert np.nanmax(np.abs(r1.depth - r2.depth)[np.isfinite(r1.depth)]) < 1e-10
+
+
+# ------------------------------------------------------------------ brute force
+
+def test_brute_force_tiny_image(oracle_lib):
+    """Tiny image of config 1: dense sampling along each ray with a multi-seed Newton
+    inside test.  The inside/outside transitions agree with the oracle's fragments
+    within the sampling step, and the midpoint quadrature on that dense grid agrees
+    with the oracle's image to first order in the step."""
+    sc = make_config(1)
+    P = oracle.OraclePatch(sc.patches[0])
+    cam = camera_from_angles([0.5, 0.5, 0.5], 3.0, 30.0, 20.0, 6, 6)
+    res = oracle.render(sc, cam, sc.tf)
+    prep = oracle.OracleScene(sc.patches, sc.scale)
+    ds = 2.0e-3
+    seeds = [(a, b, c) for a in (0.2, 0.5, 0.8) for b in (0.2, 0.5, 0.8) for c in (0.2, 0.5, 0.8)]
+    for pix in range(36):
+        o, d = oracle.camera_ray(cam, pix % 6 + 0.5, pix // 6 + 0.5)
+        t0, t1 = _slab(o, d, np.full(3, -0.1), np.full(3, 1.1))
+        C = np.zeros(3)
+        Aacc = 0.0
+        inside_prev = False
+        trans = []
+        if t1 > max(t0, 0):
+            s = t0
+            prev = None
+            while s < t1:
+                sm = s + 0.5 * ds
+                g = o + sm * d
+                inside = False
+                seed = prev if prev is not None else (0.5, 0.5, 0.5)
+                for sd in [seed] + seeds:
+                    rc, q, _ = oracle.invert(P, g, sd, scale=sc.scale)
+                    if rc == 0:
+                        inside = True
+                        prev = q
+                        break
+                if inside != inside_prev:
+                    trans.append(s)
+                inside_prev = inside
+                if inside:
+                    _, _, rho = oracle.evaluate(P, prev)
+                    e = oracle.transfer(sc.tf, rho)
+                    T = math.exp(-e[3] * ds)
+                    C += (1 - T) * (1 - Aacc) * e[:3]
+                    Aacc += (1 - T) * (1 - Aacc)
+                else:
+                    prev = None
+                s += ds
+        fr = prep.fragments(o, d)
+        assert len(fr) == len(trans), pix
+        for (t, *_), tb in zip(fr, trans):
+            assert abs(t - tb) <= 2 * ds
+        assert abs(res.rgba[pix, 3] - Aacc) < 8 * ds
+        assert np.abs(res.rgba[pix, :3] - C).max() < 8 * ds
+
+
+# ------------------------------------------------------------------ configs
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_configs_pair_cleanly_and_converge(oracle_lib, k):
+    """A sample of pixels of configs 2-4: every fragment pairs (no anomaly), every
+    Newton solve converges and the quadrature's self-error is below 1e-5."""
+    sc = make_config(k, 96, 54) if k in (3, 4) else make_config(k)
+    cam = sc.cameras[0]
+    if k == 2:
+        cam = camera_from_angles(cam.target, np.linalg.norm(cam.eye - cam.target), 30.0, 10.0,
+                                 48, 48)
+    rng = np.random.default_rng(100 + k)
+    # pixels from the central part of the frame, where the object is
+    rows = rng.integers(cam.height // 4, 3 * cam.height // 4, 48)
+    cols = rng.integers(cam.width // 4, 3 * cam.width // 4, 48)
+    pix = rows * cam.width + cols
+    res = oracle.render(sc, cam, sc.tf, pixels=pix, panels_per_scale=1024.0)
+    assert (res.n_anomalies == 0).all()
+    assert (res.n_newton_fail == 0).all()
+    assert res.self_error.max() < 1e-5
+    assert (res.n_segments > 0).sum() >= (5 if k == 2 else 10)
