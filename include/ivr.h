@@ -1,0 +1,167 @@
+/*
+ * ivr — isogeometric volume rendering on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the per-pixel hot path of Fuchs & Hjelmervik, "Interactive
+ * Isogeometric Volume Visualization with Pixel-Accurate Geometry" (IEEE TVCG
+ * 2015).  For every pixel the library
+ *   1. finds every crossing of the view ray with the six boundary faces of every
+ *      block (Sec. "View-Ray Intersections with Surfaces"; here by Newton on the
+ *      face equations of Eq. (F)/(newtonsmethod), FP32 iterations followed by an
+ *      FP64 refinement), recording {depth, parameter, block, front-facing};
+ *   2. pairs them per block by Algorithm "Blockwise depth-sorting";
+ *   3. integrates the parameter-space ray p' = W(p), J_phi(p) W(p) = V(phi(p))
+ *      with V = V_par + c V_perp (Eqs. (odepar), (VgVp), (vec2)) from each entry
+ *      to its exit with an adaptive embedded Runge-Kutta-Fehlberg 4(5) scheme;
+ *   4. samples rho at every accepted step, applies the transfer function with
+ *      supersampling (Sec. "Quadrature of volume render integral") and composites
+ *      front to back by Algorithm "Front-to-back compositing";
+ *   5. merges the per-segment results of a pixel front to back.
+ *
+ * Conventions
+ *   - All functions return ivr_status: 0 on success, a negative code on error.
+ *     A failing call leaves the context as it was; ivr_last_error() describes
+ *     the failure.  No C++ exception or abort crosses this interface.
+ *   - A context belongs to one device and one HIP stream and is not thread-safe.
+ *   - Host arrays passed in are copied before the call returns; the caller keeps
+ *     ownership.  Output buffers are caller-owned device memory; results are
+ *     written asynchronously on the context's stream.
+ */
+#ifndef IVR_H
+#define IVR_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ivr_status;
+#define IVR_OK 0
+#define IVR_EINVAL (-1)     /* invalid argument                               */
+#define IVR_ENOMEM (-2)     /* device allocation failed                       */
+#define IVR_EDEVICE (-3)    /* no usable gfx950 device / HIP runtime error    */
+#define IVR_ESTATE (-4)     /* call not valid in the current state            */
+#define IVR_EOVERFLOW (-5)  /* a fixed capacity was exceeded                  */
+
+typedef struct ivr_ctx ivr_ctx;
+
+/* One block (patch) of the model, Eq. (Bspline) and Sec. "Approach and
+ * Implementation" (blocks G_alpha with phi_alpha and rho_alpha on P_alpha).
+ *   degree[d]   polynomial degree per direction, 1..3, equal in all directions
+ *   ncp[d]      control points per direction, >= degree+1
+ *   knots[d]    ncp[d]+degree[d]+1 non-decreasing values, clamped (first and last
+ *               value repeated degree+1 times); mapped affinely onto [0,1]
+ *   cp          ncp0*ncp1*ncp2 records (x, y, z, w), i fastest then j then k;
+ *               w > 0 is used only when rational != 0
+ *   scalar      ncp0*ncp1*ncp2 coefficients of rho (same layout); for NURBS rho
+ *               uses the same rational basis as the geometry                   */
+typedef struct {
+    int32_t degree[3];
+    int32_t ncp[3];
+    const double *knots[3];
+    const double *cp;
+    const double *scalar;
+    int32_t rational;
+} ivr_patch_desc;
+
+/* Pinhole camera: the ray of pixel (i, j), row 0 at the top, passes through the
+ * pixel centre (i+1/2, j+1/2); vertical field of view fov_y_deg. */
+typedef struct {
+    double eye[3], target[3], up[3];
+    double fov_y_deg;
+    int32_t width, height;
+} ivr_camera;
+
+/* Transfer function (Eq. (emissionabsorption)): piecewise-linear RGBA over the
+ * normalised value n = clamp((rho - domain[0]) / (domain[1] - domain[0]), 0, 1)
+ * with n_knots (2..16) increasing abscissae x[] from 0 to 1 and rgba[4*n_knots];
+ * extinction kappa = extinction * A, emission RGB (not premultiplied). */
+typedef struct {
+    int32_t n_knots;
+    const double *x;
+    const double *rgba;
+    double extinction;
+    double domain[2];
+} ivr_transfer_fn;
+
+#define IVR_PRECISION_FP32 0   /* FP32 kernels, FP64 boundary-root refinement  */
+#define IVR_PRECISION_FP64 1   /* every step in FP64                           */
+#define IVR_SEED_PLAIN 0
+#define IVR_SEED_MLP 1
+#define IVR_RHO_LINEAR 0       /* rho linear between samples (as in the paper)  */
+#define IVR_RHO_HERMITE 1      /* cubic Hermite from rho and d rho/ds           */
+
+/* Render options (ivr_default_opts fills the defaults given in brackets). */
+typedef struct {
+    int32_t precision;          /* IVR_PRECISION_*                          [FP32] */
+    double rk_tol;              /* RKF45 local error bound on p (inf-norm) [1e-5] */
+    double h_max;               /* largest step, in world units along the ray;
+                                   <= 0: scale/64                           [0]   */
+    double c_perp;              /* weight c of V_perp in Eq. (vec2)         [1]   */
+    int32_t n_super;            /* supersampling sub-steps per RK step      [4]   */
+    double det_fp64_threshold;  /* |det J| below it: solve in FP64          [1e-6] */
+    int32_t max_fragments;      /* boundary crossings kept per ray, 2..64   [64]  */
+    int32_t seed_mode;          /* IVR_SEED_*                               [PLAIN]*/
+    double early_term;          /* stop a segment once alpha >= 1-early_term [1e-4]*/
+    int32_t max_newton_iter;    /* FP32 Newton iterations per face root     [16]  */
+    int32_t rho_interp;         /* IVR_RHO_*: rho between two samples  [HERMITE] */
+} ivr_render_opts;
+
+/* Counters of one render (filled when a non-NULL ivr_stats* is passed; that
+ * forces a stream synchronisation). */
+typedef struct {
+    uint64_t rays;              /* pixels rendered                               */
+    uint64_t segments;          /* entry/exit pairs integrated                   */
+    uint64_t fragments;         /* boundary crossings kept                       */
+    uint64_t anomalies;         /* crossings left unpaired by the pairing        */
+    uint64_t fragment_overflow; /* crossings or seeds dropped (fixed capacities)  */
+    uint64_t segment_overflow;  /* segments dropped (per-pixel capacity)         */
+    uint64_t box_tests;         /* ray/box slab tests                            */
+    uint64_t face_newton;       /* face Newton solves started                    */
+    uint64_t face_newton_iter;  /* FP32 face Newton iterations                   */
+    uint64_t fp64_polish_iter;  /* FP64 refinement iterations                    */
+    uint64_t rk_steps;          /* RKF45 attempts (6 evaluations of W each)      */
+    uint64_t rk_rejected;       /* rejected attempts                             */
+    uint64_t samples;           /* accepted steps (rho + transfer function)      */
+    uint64_t w_evals;           /* evaluations of phi, J_phi and W               */
+    uint64_t fp64_solves;       /* 3x3 solves done in FP64 (small det J)         */
+    uint64_t rk_iter_cap;       /* segments stopped at the iteration cap         */
+    uint64_t mlp_queries;       /* MLP seed evaluations                          */
+    double ms_fragments, ms_integrate, ms_merge;  /* event times per phase      */
+} ivr_stats;
+
+/* Creates a context on `device` using `hip_stream` (a hipStream_t; NULL = the
+ * null stream).  IVR_EDEVICE if the device is not a gfx950. */
+ivr_status ivr_create(ivr_ctx **out, int32_t device, void *hip_stream);
+
+/* Fills *o with the defaults listed at ivr_render_opts. */
+void ivr_default_opts(ivr_render_opts *o);
+
+/* Replaces the model with n >= 1 blocks (Sec. "Approach and Implementation":
+ * knots and control points are all the method stores).  Validates every block
+ * (degrees, counts, clamped non-decreasing knots, finite values, positive
+ * weights) and returns IVR_EINVAL without touching the current model on
+ * failure.  Packs FP32 and FP64 copies, bounding boxes of every block, face and
+ * face element (convex hull of their control points), and uploads them.  A new
+ * model invalidates a trained MLP. */
+ivr_status ivr_upload_patches(ivr_ctx *ctx, const ivr_patch_desc *patches, int32_t n);
+
+/* Renders one view.  rgba_dev: width*height*4 floats (premultiplied RGBA over
+ * transparent black, row-major, row 0 at the top); depth_dev: width*height
+ * floats (ray parameter of the first entry, +inf where the ray misses) or NULL.
+ * opts NULL = defaults.  Returns after enqueueing the work unless stats != NULL.
+ * IVR_ESTATE before a model is uploaded or when opts->seed_mode is MLP and no
+ * MLP has been trained. */
+ivr_status ivr_render(ivr_ctx *ctx, const ivr_camera *cam, const ivr_transfer_fn *tf,
+                      const ivr_render_opts *opts, float *rgba_dev, float *depth_dev,
+                      ivr_stats *stats);
+
+/* Message for the last failing call of this context ("" if none). */
+const char *ivr_last_error(const ivr_ctx *ctx);
+
+/* Frees every device allocation of the context (waits for its stream). */
+void ivr_destroy(ivr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -58,7 +58,7 @@ class Fragment(C.Structure):
 class _Diag(C.Structure):
     _fields_ = [("n_fragments", C.c_int32), ("n_segments", C.c_int32),
                 ("n_anomalies", C.c_int32), ("n_newton_fail", C.c_int32),
-                ("self_error", C.c_double)]
+                ("self_error", C.c_double), ("first_chord", C.c_double)]
 
 
 _lib = None
@@ -228,6 +228,7 @@ class RenderResult:
         self.n_anomalies = np.array([d.n_anomalies for d in diag])
         self.n_newton_fail = np.array([d.n_newton_fail for d in diag])
         self.self_error = np.array([d.self_error for d in diag])
+        self.first_chord = np.array([d.first_chord for d in diag])
 
 
 def render(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None,

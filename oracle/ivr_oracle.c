@@ -769,7 +769,10 @@ static void render_one(const orc_scene *s, const orc_camera *cam, const orc_tf *
     double C[3] = {0, 0, 0}, A = 0.0;
     for (int k = 0; k < nseg; ++k) {
         const orc_fragment *fi = &fr[segs[k][0]], *fo = &fr[segs[k][1]];
-        if (k == 0) *depth = fi->t;
+        if (k == 0) {
+            *depth = fi->t;
+            dg->first_chord = fo->t - fi->t;
+        }
         double L = fo->t - fi->t;
         int npan = (int)ceil(L * opts->panels_per_scale / s->scale);
         if (npan < 1) npan = 1;

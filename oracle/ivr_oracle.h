@@ -75,6 +75,7 @@ typedef struct {
 typedef struct {
     int32_t n_fragments, n_segments, n_anomalies, n_newton_fail;
     double self_error;        /* max |I_h - I_{h/2}| over channels/segments  */
+    double first_chord;       /* t_out - t_in of the first segment (0: none) */
 } orc_pixel_diag;
 
 orc_scene *orc_prepare(const orc_patch *patches, int32_t n, double scale);

@@ -1,0 +1,707 @@
+// Host side of the C ABI declared in include/ivr.h: argument validation, model
+// packing (FP32 + FP64 control nets, knot vectors, block / face / face-element
+// bounding boxes), frame-buffer management and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ivr.h"
+#include "ivr_internal.h"
+#include "ivr_types.h"
+
+using namespace ivr;
+
+struct ivr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+    std::string err;
+    bool has_model = false;
+    // model
+    DevPatch *d_patches = nullptr;
+    float4 *d_cp32 = nullptr;
+    float *d_rho32 = nullptr;
+    double4 *d_cp64 = nullptr;
+    double *d_rho64 = nullptr;
+    float *d_knots32 = nullptr;
+    double *d_knots64 = nullptr;
+    FaceElem *d_elems = nullptr;
+    int npatch = 0, nelem = 0;
+    double scale = 1.0;
+    uint32_t class_mask = 0;
+    // frame buffers
+    size_t pix_cap = 0, seg_cap = 0, seg_bytes_cap = 0;
+    void *d_segs = nullptr;
+    float4 *d_results = nullptr;
+    uint2 *d_pixseg = nullptr;
+    uint32_t *d_queues = nullptr;
+    QueueState *d_qs = nullptr;
+    unsigned long long *d_ctr = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+ivr_status fail(ivr_ctx *c, ivr_status code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define IVR_HIP(ctx, call)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, IVR_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+float round_down(double v) {
+    float f = (float)v;
+    return (double)f > v ? std::nextafter(f, -INFINITY) : f;
+}
+float round_up(double v) {
+    float f = (float)v;
+    return (double)f < v ? std::nextafter(f, INFINITY) : f;
+}
+
+struct Box {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    void add(const double *p) {
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], p[c]);
+            hi[c] = std::max(hi[c], p[c]);
+        }
+    }
+    void store(float *dst, double pad) const {
+        for (int c = 0; c < 3; ++c) {
+            dst[c] = round_down(lo[c] - pad);
+            dst[3 + c] = round_up(hi[c] + pad);
+        }
+    }
+};
+
+std::string validate_patch(const ivr_patch_desc &P, int idx) {
+    char buf[256];
+    const int p = P.degree[0];
+    for (int d = 0; d < 3; ++d) {
+        if (P.degree[d] < 1 || P.degree[d] > kMaxDegree) {
+            snprintf(buf, sizeof buf, "patch %d: degree %d outside 1..3", idx, P.degree[d]);
+            return buf;
+        }
+        if (P.degree[d] != p) {
+            snprintf(buf, sizeof buf, "patch %d: degrees must be equal in all directions", idx);
+            return buf;
+        }
+        if (P.ncp[d] < p + 1 || P.ncp[d] > 4096) {
+            snprintf(buf, sizeof buf, "patch %d: ncp[%d]=%d outside degree+1..4096", idx, d, P.ncp[d]);
+            return buf;
+        }
+        if (!P.knots[d]) {
+            snprintf(buf, sizeof buf, "patch %d: knots[%d] is NULL", idx, d);
+            return buf;
+        }
+        const int nk = P.ncp[d] + p + 1, n = P.ncp[d];
+        const double *t = P.knots[d];
+        for (int i = 0; i < nk; ++i)
+            if (!std::isfinite(t[i]) || (i > 0 && t[i] < t[i - 1])) {
+                snprintf(buf, sizeof buf, "patch %d: knots[%d] not finite and non-decreasing", idx, d);
+                return buf;
+            }
+        for (int i = 1; i <= p; ++i)
+            if (t[i] != t[0] || t[n + i] != t[n]) {
+                snprintf(buf, sizeof buf, "patch %d: knots[%d] not clamped", idx, d);
+                return buf;
+            }
+        if (!(t[p] < t[n])) {
+            snprintf(buf, sizeof buf, "patch %d: knots[%d] span is empty", idx, d);
+            return buf;
+        }
+        for (int i = p + 1; i < n; ++i) {
+            int mult = 1;
+            while (i + mult < n && t[i + mult] == t[i]) ++mult;
+            if (mult > p || t[i] == t[p] || t[i] == t[n]) {
+                snprintf(buf, sizeof buf, "patch %d: knots[%d] interior multiplicity > degree", idx, d);
+                return buf;
+            }
+        }
+    }
+    if (!P.cp || !P.scalar) {
+        snprintf(buf, sizeof buf, "patch %d: cp or scalar is NULL", idx);
+        return buf;
+    }
+    const size_t N = (size_t)P.ncp[0] * P.ncp[1] * P.ncp[2];
+    for (size_t i = 0; i < N; ++i) {
+        const double *c = P.cp + 4 * i;
+        if (!finite3(c) || !std::isfinite(P.scalar[i]) ||
+            (P.rational && !(std::isfinite(c[3]) && c[3] > 0.0))) {
+            snprintf(buf, sizeof buf, "patch %d: control point %zu not finite or weight <= 0", idx, i);
+            return buf;
+        }
+    }
+    return "";
+}
+
+// sign of det J from the control net at the 8 corners (derivatives at a clamped
+// corner are positive multiples of the first edges of the net)
+float orientation(const ivr_patch_desc &P) {
+    const int n0 = P.ncp[0], n1 = P.ncp[1], n2 = P.ncp[2];
+    auto pt = [&](int i, int j, int k, double *o) {
+        const double *c = P.cp + 4 * ((size_t)i + (size_t)n0 * (j + (size_t)n1 * k));
+        for (int q = 0; q < 3; ++q) o[q] = c[q];
+    };
+    int pos = 0, neg = 0;
+    for (int ci = 0; ci < 8; ++ci) {
+        const int i = (ci & 1) ? n0 - 2 : 0, j = (ci & 2) ? n1 - 2 : 0, k = (ci & 4) ? n2 - 2 : 0;
+        const int i0 = (ci & 1) ? n0 - 1 : 0, j0 = (ci & 2) ? n1 - 1 : 0, k0 = (ci & 4) ? n2 - 1 : 0;
+        double c0[3], cu[3], cv[3], cw[3];
+        pt(i0, j0, k0, c0);
+        // forward differences in +u, +v, +w between the corner layer and the next layer
+        double a[3], b[3], c[3], t0[3], t1[3];
+        pt(i, j0, k0, t0); pt(i + 1, j0, k0, t1);
+        for (int q = 0; q < 3; ++q) a[q] = t1[q] - t0[q];
+        pt(i0, j, k0, t0); pt(i0, j + 1, k0, t1);
+        for (int q = 0; q < 3; ++q) b[q] = t1[q] - t0[q];
+        pt(i0, j0, k, t0); pt(i0, j0, k + 1, t1);
+        for (int q = 0; q < 3; ++q) c[q] = t1[q] - t0[q];
+        (void)cu; (void)cv; (void)cw;
+        const double det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                           a[2] * (b[0] * c[1] - b[1] * c[0]);
+        if (det > 0) ++pos;
+        else if (det < 0) ++neg;
+    }
+    return neg > pos ? -1.0f : 1.0f;
+}
+
+// Blossom of a degree-p B-spline segment on knot span s: de Boor's algorithm with
+// argument args[r-1] at level r.  Q holds the p+1 homogeneous control points
+// s-p..s.  The Bezier points of the span [t_s, t_{s+1}] are the blossoms at
+// (t_s^(p-j), t_{s+1}^j), j = 0..p.
+static void blossom(const double *t, int s, int p, const double (*Q)[4], const double *args,
+                    double out[4]) {
+    double d[kMaxDegree + 1][4];
+    for (int k = 0; k <= p; ++k)
+        for (int c = 0; c < 4; ++c) d[k][c] = Q[k][c];
+    for (int r = 1; r <= p; ++r) {
+        const double u = args[r - 1];
+        for (int i = s; i >= s - p + r; --i) {
+            const int k = i - (s - p);
+            const double alpha = (u - t[i]) / (t[i + p + 1 - r] - t[i]);
+            for (int c = 0; c < 4; ++c) d[k][c] = (1.0 - alpha) * d[k - 1][c] + alpha * d[k][c];
+        }
+    }
+    for (int c = 0; c < 4; ++c) out[c] = d[p][c];
+}
+
+// Bezier net (homogeneous, (p+1)^2, a fastest) of the face element on spans
+// (sa, sb); hq(ia, jb) returns the homogeneous face control point.
+template <typename HQ>
+static void bezier_net(const double *ta, const double *tb, int sa, int sb, int p, HQ hq,
+                       double (*net)[4]) {
+    double tmp[(kMaxDegree + 1) * (kMaxDegree + 1)][4];
+    double args[kMaxDegree];
+    for (int jb = 0; jb <= p; ++jb) {        // along a, for each of the p+1 rows
+        double row[kMaxDegree + 1][4];
+        for (int ia = 0; ia <= p; ++ia) hq(sa - p + ia, sb - p + jb, row[ia]);
+        for (int j = 0; j <= p; ++j) {
+            for (int r = 0; r < p; ++r) args[r] = r < p - j ? ta[sa] : ta[sa + 1];
+            blossom(ta, sa, p, row, args, tmp[jb * (p + 1) + j]);
+        }
+    }
+    for (int ia = 0; ia <= p; ++ia) {        // then along b
+        double col[kMaxDegree + 1][4];
+        for (int jb = 0; jb <= p; ++jb)
+            for (int c = 0; c < 4; ++c) col[jb][c] = tmp[jb * (p + 1) + ia][c];
+        for (int j = 0; j <= p; ++j) {
+            for (int r = 0; r < p; ++r) args[r] = r < p - j ? tb[sb] : tb[sb + 1];
+            blossom(tb, sb, p, col, args, net[j * (p + 1) + ia]);
+        }
+    }
+}
+
+// Oriented box around the projected Bezier points of a face element (the
+// element lies in their convex hull; positive weights keep this for NURBS).
+// Axes: the averaged edge directions of the net in a and b, orthonormalised,
+// and their normal; extents from projecting every point, padded.  Falls back
+// to the coordinate axes if an edge direction degenerates.
+static void build_obb(FaceElem &E, const double (*net)[4], int p, double pad) {
+    auto at = [&](int ia, int jb, double *o) {
+        const double *h = net[jb * (p + 1) + ia];
+        for (int q = 0; q < 3; ++q) o[q] = h[q] / h[3];
+    };
+    double u[3] = {0, 0, 0}, v[3] = {0, 0, 0}, c00[3], c10[3], c01[3], c11[3];
+    at(0, 0, c00); at(p, 0, c10); at(0, p, c01); at(p, p, c11);
+    for (int q = 0; q < 3; ++q) {
+        u[q] = 0.5 * (c10[q] - c00[q] + c11[q] - c01[q]);
+        v[q] = 0.5 * (c01[q] - c00[q] + c11[q] - c10[q]);
+    }
+    auto norm = [](double *w) {
+        double n = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        if (!(n > 0)) return false;
+        for (int q = 0; q < 3; ++q) w[q] /= n;
+        return true;
+    };
+    double ax[3][3];
+    bool ok = norm(u);
+    if (ok) {
+        const double dv = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+        for (int q = 0; q < 3; ++q) v[q] -= dv * u[q];
+        ok = norm(v);
+    }
+    if (ok) {
+        for (int q = 0; q < 3; ++q) { ax[0][q] = u[q]; ax[1][q] = v[q]; }
+        ax[2][0] = u[1] * v[2] - u[2] * v[1];
+        ax[2][1] = u[2] * v[0] - u[0] * v[2];
+        ax[2][2] = u[0] * v[1] - u[1] * v[0];
+    } else {
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) ax[r][q] = r == q ? 1.0 : 0.0;
+    }
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int jb = 0; jb <= p; ++jb)
+        for (int ia = 0; ia <= p; ++ia) {
+            double P[3];
+            at(ia, jb, P);
+            for (int r = 0; r < 3; ++r) {
+                const double pr = ax[r][0] * P[0] + ax[r][1] * P[1] + ax[r][2] * P[2];
+                lo[r] = std::min(lo[r], pr);
+                hi[r] = std::max(hi[r], pr);
+            }
+        }
+    for (int q = 0; q < 3; ++q) {
+        double cq = 0;
+        for (int r = 0; r < 3; ++r) cq += ax[r][q] * 0.5 * (lo[r] + hi[r]);
+        E.c[q] = (float)cq;
+    }
+    for (int r = 0; r < 3; ++r) {
+        for (int q = 0; q < 3; ++q) E.ax[r][q] = (float)ax[r][q];
+        // pad also covers the FP32 rounding of the centre and the axes
+        E.ext[r] = round_up(0.5 * (hi[r] - lo[r]) + pad);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void ivr_default_opts(ivr_render_opts *o) {
+    if (!o) return;
+    o->precision = IVR_PRECISION_FP32;
+    o->rk_tol = 1e-5;
+    o->h_max = 0.0;
+    o->c_perp = 1.0;
+    o->n_super = 4;
+    o->det_fp64_threshold = 1e-6;
+    o->max_fragments = kFragCap;
+    o->seed_mode = IVR_SEED_PLAIN;
+    o->early_term = 1e-4;
+    o->max_newton_iter = 16;
+    o->rho_interp = IVR_RHO_HERMITE;
+}
+
+ivr_status ivr_create(ivr_ctx **out, int32_t device, void *hip_stream) {
+    if (!out) return IVR_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return IVR_EDEVICE;
+    if (device < 0 || device >= ndev) return IVR_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return IVR_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return IVR_EDEVICE;
+    ivr_ctx *c = new (std::nothrow) ivr_ctx();
+    if (!c) return IVR_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->n_cu = prop.multiProcessorCount;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipMalloc((void **)&c->d_qs, sizeof(QueueState)) != hipSuccess ||
+        hipMalloc((void **)&c->d_ctr, sizeof(unsigned long long) * C_COUNT) != hipSuccess) {
+        ivr_destroy(c);
+        return IVR_ENOMEM;
+    }
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            ivr_destroy(c);
+            return IVR_EDEVICE;
+        }
+    *out = c;
+    return IVR_OK;
+}
+
+const char *ivr_last_error(const ivr_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+static void free_model(ivr_ctx *c) {
+    dfree(c->d_patches); dfree(c->d_cp32); dfree(c->d_rho32); dfree(c->d_cp64); dfree(c->d_rho64);
+    dfree(c->d_knots32); dfree(c->d_knots64); dfree(c->d_elems);
+    c->has_model = false;
+}
+
+static void free_frame(ivr_ctx *c) {
+    dfree(c->d_segs); dfree(c->d_results); dfree(c->d_pixseg); dfree(c->d_queues);
+    c->pix_cap = c->seg_cap = c->seg_bytes_cap = 0;
+}
+
+void ivr_destroy(ivr_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_model(c);
+    free_frame(c);
+    dfree(c->d_qs);
+    dfree(c->d_ctr);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t n) {
+    if (!c) return IVR_EINVAL;
+    if (!patches || n < 1) return fail(c, IVR_EINVAL, "need at least one patch");
+    for (int i = 0; i < n; ++i) {
+        std::string e = validate_patch(patches[i], i);
+        if (!e.empty()) return fail(c, IVR_EINVAL, e);
+    }
+    IVR_HIP(c, hipSetDevice(c->device));
+    // scale: diagonal of the box of all (projected) control points
+    Box all;
+    for (int i = 0; i < n; ++i) {
+        const auto &P = patches[i];
+        const size_t N = (size_t)P.ncp[0] * P.ncp[1] * P.ncp[2];
+        for (size_t q = 0; q < N; ++q) all.add(P.cp + 4 * q);
+    }
+    double diag = 0;
+    for (int q = 0; q < 3; ++q) diag += (all.hi[q] - all.lo[q]) * (all.hi[q] - all.lo[q]);
+    const double scale = std::max(std::sqrt(diag), 1e-30);
+    const double pad = 1e-5 * scale;
+
+    std::vector<DevPatch> hp(n);
+    std::vector<float4> cp32;
+    std::vector<float> rho32, knots32;
+    std::vector<double4> cp64;
+    std::vector<double> rho64, knots64;
+    std::vector<FaceElem> elems;
+    uint32_t class_mask = 0;
+    for (int pi = 0; pi < n; ++pi) {
+        const auto &P = patches[pi];
+        DevPatch &D = hp[pi];
+        std::memset(&D, 0, sizeof D);
+        const int p = P.degree[0];
+        D.deg = p;
+        D.rational = P.rational ? 1 : 0;
+        D.klass = 2 * (p - 1) + D.rational;
+        class_mask |= 1u << D.klass;
+        D.cp_off = (int)cp32.size();
+        D.orient = orientation(P);
+        std::vector<double> tn[3];
+        for (int d = 0; d < 3; ++d) {
+            const int nd = P.ncp[d], nk = nd + p + 1;
+            D.n[d] = nd;
+            D.nspan[d] = nd - p;
+            D.inv_nspan[d] = 1.0f / (float)(nd - p);
+            const double *t = P.knots[d];
+            const double t0 = t[p], t1 = t[nd];
+            tn[d].resize(nk);
+            for (int i = 0; i < nk; ++i) tn[d][i] = std::min(1.0, std::max(0.0, (t[i] - t0) / (t1 - t0)));
+            bool uni = true;
+            for (int i = p + 1; i < nd; ++i)
+                if (std::fabs(tn[d][i] - (double)(i - p) / (nd - p)) > 1e-12) uni = false;
+            if (uni) D.uniform |= 1 << d;
+            D.knot_off[d] = (int)knots32.size();
+            for (int i = 0; i < nk; ++i) {
+                knots32.push_back((float)tn[d][i]);
+                knots64.push_back(tn[d][i]);
+            }
+        }
+        const int n0 = P.ncp[0], n1 = P.ncp[1], n2 = P.ncp[2];
+        const size_t N = (size_t)n0 * n1 * n2;
+        Box pb;
+        for (size_t q = 0; q < N; ++q) {
+            const double *cc = P.cp + 4 * q;
+            const double w = P.rational ? cc[3] : 1.0;
+            cp32.push_back(make_float4((float)(w * cc[0]), (float)(w * cc[1]), (float)(w * cc[2]), (float)w));
+            cp64.push_back(make_double4(w * cc[0], w * cc[1], w * cc[2], w));
+            rho32.push_back((float)(w * P.scalar[q]));
+            rho64.push_back(w * P.scalar[q]);
+            pb.add(cc);
+        }
+        pb.store(D.box, pad);
+        auto idx = [&](int i, int j, int k) { return (size_t)i + (size_t)n0 * (j + (size_t)n1 * k); };
+        for (int f = 0; f < 6; ++f) {
+            const int dn = f >> 1, da = dn == 0 ? 1 : 0, db = dn == 2 ? 1 : 2;
+            const int fix = (f & 1) ? P.ncp[dn] - 1 : 0;
+            Box fb;
+            D.elem_off[f] = (int)elems.size();
+            auto at = [&](int ia, int jb) {
+                int ijk[3];
+                ijk[dn] = fix;
+                ijk[da] = ia;
+                ijk[db] = jb;
+                return P.cp + 4 * idx(ijk[0], ijk[1], ijk[2]);
+            };
+            for (int jb = 0; jb < P.ncp[db]; ++jb)
+                for (int ia = 0; ia < P.ncp[da]; ++ia) fb.add(at(ia, jb));
+            fb.store(D.fbox[f], pad);
+            for (int sb = p; sb < P.ncp[db]; ++sb) {
+                if (!(tn[db][sb] < tn[db][sb + 1])) continue;
+                for (int sa = p; sa < P.ncp[da]; ++sa) {
+                    if (!(tn[da][sa] < tn[da][sa + 1])) continue;
+                    FaceElem E;
+                    std::memset(&E, 0, sizeof E);
+                    double net[(kMaxDegree + 1) * (kMaxDegree + 1)][4];
+                    auto hq = [&](int ia, int jb, double *o) {
+                        const double *cc = at(ia, jb);
+                        const double w = P.rational ? cc[3] : 1.0;
+                        o[0] = w * cc[0]; o[1] = w * cc[1]; o[2] = w * cc[2]; o[3] = w;
+                    };
+                    bezier_net(tn[da].data(), tn[db].data(), sa, sb, p, hq, net);
+                    build_obb(E, net, p, pad);
+                    E.a0 = (float)tn[da][sa];
+                    E.a1 = (float)tn[da][sa + 1];
+                    E.b0 = (float)tn[db][sb];
+                    E.b1 = (float)tn[db][sb + 1];
+                    E.face = f;
+                    E.patch = pi;
+                    elems.push_back(E);
+                }
+            }
+        }
+        D.elem_off[6] = (int)elems.size();
+    }
+    // allocate and copy, then swap in
+    ivr_ctx tmp;
+    auto up = [&](auto *&dst, const auto &vec) -> bool {
+        using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+        if (hipMalloc((void **)&dst, sizeof(T) * std::max<size_t>(vec.size(), 1)) != hipSuccess) return false;
+        return hipMemcpy((void *)dst, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice) == hipSuccess;
+    };
+    bool ok = up(tmp.d_patches, hp) && up(tmp.d_cp32, cp32) && up(tmp.d_rho32, rho32) &&
+              up(tmp.d_cp64, cp64) && up(tmp.d_rho64, rho64) && up(tmp.d_knots32, knots32) &&
+              up(tmp.d_knots64, knots64) && up(tmp.d_elems, elems);
+    if (!ok) {
+        free_model(&tmp);
+        return fail(c, IVR_ENOMEM, "device allocation for the model failed");
+    }
+    IVR_HIP(c, hipStreamSynchronize(c->stream));
+    free_model(c);
+    c->d_patches = tmp.d_patches; c->d_cp32 = tmp.d_cp32; c->d_rho32 = tmp.d_rho32;
+    c->d_cp64 = tmp.d_cp64; c->d_rho64 = tmp.d_rho64; c->d_knots32 = tmp.d_knots32;
+    c->d_knots64 = tmp.d_knots64; c->d_elems = tmp.d_elems;
+    tmp.d_patches = nullptr; tmp.d_cp32 = nullptr; tmp.d_rho32 = nullptr; tmp.d_cp64 = nullptr;
+    tmp.d_rho64 = nullptr; tmp.d_knots32 = nullptr; tmp.d_knots64 = nullptr; tmp.d_elems = nullptr;
+    c->npatch = n;
+    c->nelem = (int)elems.size();
+    c->scale = scale;
+    c->class_mask = class_mask;
+    c->has_model = true;
+    c->err.clear();
+    return IVR_OK;
+}
+
+static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *tf,
+                             const ivr_render_opts &o, FrameParams &fp) {
+    std::memset(&fp, 0, sizeof fp);
+    if (!cam || !tf) return fail(c, IVR_EINVAL, "camera and transfer function are required");
+    if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384)
+        return fail(c, IVR_EINVAL, "image size outside 1..16384");
+    if (!(cam->fov_y_deg > 0.0 && cam->fov_y_deg < 179.0))
+        return fail(c, IVR_EINVAL, "fov_y_deg outside (0, 179)");
+    if (!finite3(cam->eye) || !finite3(cam->target) || !finite3(cam->up))
+        return fail(c, IVR_EINVAL, "camera vectors must be finite");
+    double f[3], r[3], u[3];
+    for (int q = 0; q < 3; ++q) f[q] = cam->target[q] - cam->eye[q];
+    double nf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(nf > 0)) return fail(c, IVR_EINVAL, "eye equals target");
+    for (int q = 0; q < 3; ++q) f[q] /= nf;
+    r[0] = f[1] * cam->up[2] - f[2] * cam->up[1];
+    r[1] = f[2] * cam->up[0] - f[0] * cam->up[2];
+    r[2] = f[0] * cam->up[1] - f[1] * cam->up[0];
+    double nr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(nr > 1e-12)) return fail(c, IVR_EINVAL, "up is parallel to the view direction");
+    for (int q = 0; q < 3; ++q) r[q] /= nr;
+    u[0] = r[1] * f[2] - r[2] * f[1];
+    u[1] = r[2] * f[0] - r[0] * f[2];
+    u[2] = r[0] * f[1] - r[1] * f[0];
+    for (int q = 0; q < 3; ++q) {
+        fp.eye[q] = cam->eye[q]; fp.fwd[q] = f[q]; fp.right[q] = r[q]; fp.up[q] = u[q];
+        fp.eyef[q] = (float)cam->eye[q]; fp.fwdf[q] = (float)f[q]; fp.rightf[q] = (float)r[q]; fp.upf[q] = (float)u[q];
+    }
+    fp.tan_half = std::tan(0.5 * cam->fov_y_deg * M_PI / 180.0);
+    fp.aspect = (double)cam->width / (double)cam->height;
+    fp.tan_halff = (float)fp.tan_half;
+    fp.aspectf = (float)fp.aspect;
+    fp.width = cam->width;
+    fp.height = cam->height;
+    // transfer function
+    const int nk = tf->n_knots;
+    if (nk < 2 || nk > kMaxTfKnots || !tf->x || !tf->rgba)
+        return fail(c, IVR_EINVAL, "transfer function needs 2..16 knots");
+    if (tf->x[0] != 0.0 || tf->x[nk - 1] != 1.0)
+        return fail(c, IVR_EINVAL, "transfer function knots must run from 0 to 1");
+    for (int k = 0; k < nk; ++k) {
+        if (!std::isfinite(tf->x[k]) || (k > 0 && !(tf->x[k] > tf->x[k - 1])))
+            return fail(c, IVR_EINVAL, "transfer function knots must increase strictly");
+        for (int q = 0; q < 4; ++q)
+            if (!std::isfinite(tf->rgba[4 * k + q]))
+                return fail(c, IVR_EINVAL, "transfer function values must be finite");
+    }
+    if (!(std::isfinite(tf->extinction) && tf->extinction >= 0))
+        return fail(c, IVR_EINVAL, "extinction must be finite and >= 0");
+    if (!(std::isfinite(tf->domain[0]) && std::isfinite(tf->domain[1]) && tf->domain[1] > tf->domain[0]))
+        return fail(c, IVR_EINVAL, "transfer function domain must satisfy lo < hi");
+    fp.tf_n = nk;
+    for (int k = 0; k < nk; ++k) {
+        double v[4];
+        for (int q = 0; q < 4; ++q) v[q] = tf->rgba[4 * k + q];
+        v[3] *= tf->extinction;
+        fp.tf_xd[k] = tf->x[k];
+        fp.tf_x[k] = (float)tf->x[k];
+        for (int q = 0; q < 4; ++q) {
+            fp.tf_vd[k][q] = v[q];
+            fp.tf_v[k][q] = (float)v[q];
+        }
+        if (k + 1 < nk) {
+            for (int q = 0; q < 4; ++q) {
+                double v1 = tf->rgba[4 * (k + 1) + q] * (q == 3 ? tf->extinction : 1.0);
+                double s = (v1 - v[q]) / (tf->x[k + 1] - tf->x[k]);
+                fp.tf_sd[k][q] = s;
+                fp.tf_s[k][q] = (float)s;
+            }
+        }
+    }
+    {   // supersampling resolution in n: half the smallest knot gap, within [1/64, 1/16]
+        double gap = 1.0;
+        for (int k = 0; k + 1 < nk; ++k) gap = std::min(gap, tf->x[k + 1] - tf->x[k]);
+        const double dn = std::min(1.0 / 16.0, std::max(1.0 / 64.0, 0.5 * gap));
+        fp.tf_dn = (float)dn;
+    }
+    fp.tf_lod = tf->domain[0];
+    fp.tf_inv_ranged = 1.0 / (tf->domain[1] - tf->domain[0]);
+    fp.tf_lo = (float)fp.tf_lod;
+    fp.tf_inv_range = (float)fp.tf_inv_ranged;
+    // integrator options
+    if (o.precision != IVR_PRECISION_FP32 && o.precision != IVR_PRECISION_FP64)
+        return fail(c, IVR_EINVAL, "unknown precision");
+    if (!(o.rk_tol > 0 && std::isfinite(o.rk_tol))) return fail(c, IVR_EINVAL, "rk_tol must be > 0");
+    if (!std::isfinite(o.h_max)) return fail(c, IVR_EINVAL, "h_max must be finite");
+    if (!(o.c_perp >= 0 && std::isfinite(o.c_perp))) return fail(c, IVR_EINVAL, "c_perp must be >= 0");
+    if (o.n_super < 1 || o.n_super > 64) return fail(c, IVR_EINVAL, "n_super outside 1..64");
+    if (!(o.det_fp64_threshold >= 0)) return fail(c, IVR_EINVAL, "det_fp64_threshold must be >= 0");
+    if (o.max_fragments < 2 || o.max_fragments > kFragCap)
+        return fail(c, IVR_EINVAL, "max_fragments outside 2..64");
+    if (o.rho_interp != IVR_RHO_LINEAR && o.rho_interp != IVR_RHO_HERMITE)
+        return fail(c, IVR_EINVAL, "unknown rho_interp");
+    if (o.seed_mode != IVR_SEED_PLAIN && o.seed_mode != IVR_SEED_MLP)
+        return fail(c, IVR_EINVAL, "unknown seed_mode");
+    if (o.seed_mode == IVR_SEED_MLP) return fail(c, IVR_ESTATE, "no inverse-map MLP has been trained");
+    if (!(o.early_term >= 0 && o.early_term < 1)) return fail(c, IVR_EINVAL, "early_term outside [0,1)");
+    if (o.max_newton_iter < 1 || o.max_newton_iter > 100)
+        return fail(c, IVR_EINVAL, "max_newton_iter outside 1..100");
+    const double hmax = o.h_max > 0 ? o.h_max : c->scale / 64.0;
+    const double hmin = std::max(1e-7 * c->scale, 1e-4 * hmax);
+    double tol = o.rk_tol;
+    if (o.precision == IVR_PRECISION_FP32) tol = std::max(tol, 32.0 * 1.1920929e-7);
+    fp.rk_told = tol; fp.rk_tol = (float)tol;
+    fp.h_maxd = hmax; fp.h_max = (float)hmax;
+    fp.h_mind = hmin; fp.h_min = (float)hmin;
+    fp.c_perpd = o.c_perp; fp.c_perp = (float)o.c_perp;
+    fp.early_termd = o.early_term; fp.early_term = (float)o.early_term;
+    fp.det_thrd = o.det_fp64_threshold; fp.det_thr = (float)o.det_fp64_threshold;
+    fp.n_super = o.n_super;
+    fp.max_frag = o.max_fragments;
+    fp.hermite = o.rho_interp == IVR_RHO_HERMITE ? 1 : 0;
+    fp.max_newton = o.max_newton_iter;
+    fp.scaled = c->scale;
+    fp.scale = (float)c->scale;
+    return IVR_OK;
+}
+
+static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
+    const size_t seg_cap = pixels * kSegCap;
+    const size_t seg_bytes = seg_cap * (fp64 ? sizeof(Seg<double>) : sizeof(Seg<float>));
+    if (pixels <= c->pix_cap && seg_bytes <= c->seg_bytes_cap) return IVR_OK;
+    IVR_HIP(c, hipStreamSynchronize(c->stream));
+    free_frame(c);
+    int ncls = 0;
+    for (int k = 0; k < kClasses; ++k) ncls += 1;  // one slab per class (indexed by class)
+    if (hipMalloc(&c->d_segs, seg_bytes) != hipSuccess ||
+        hipMalloc((void **)&c->d_results, sizeof(float4) * seg_cap) != hipSuccess ||
+        hipMalloc((void **)&c->d_pixseg, sizeof(uint2) * pixels) != hipSuccess ||
+        hipMalloc((void **)&c->d_queues, sizeof(uint32_t) * seg_cap * ncls) != hipSuccess) {
+        free_frame(c);
+        return fail(c, IVR_ENOMEM, "frame buffer allocation failed");
+    }
+    c->pix_cap = pixels;
+    c->seg_cap = seg_cap;
+    c->seg_bytes_cap = seg_bytes;
+    return IVR_OK;
+}
+
+ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *tf,
+                      const ivr_render_opts *opts, float *rgba_dev, float *depth_dev, ivr_stats *stats) {
+    if (!c) return IVR_EINVAL;
+    if (!c->has_model) return fail(c, IVR_ESTATE, "no model uploaded");
+    if (!rgba_dev) return fail(c, IVR_EINVAL, "rgba_dev is NULL");
+    ivr_render_opts o;
+    ivr_default_opts(&o);
+    if (opts) o = *opts;
+    FrameParams fp;
+    ivr_status st = make_frame(c, cam, tf, o, fp);
+    if (st != IVR_OK) return st;
+    fp.collect = stats ? 1 : 0;
+    const bool fp64 = o.precision == IVR_PRECISION_FP64;
+    IVR_HIP(c, hipSetDevice(c->device));
+    const size_t pixels = (size_t)cam->width * cam->height;
+    if (pixels * kSegCap > 0xFFFFFFFFull) return fail(c, IVR_EOVERFLOW, "image too large for 32-bit segment indices");
+    st = ensure_frame(c, pixels, fp64);
+    if (st != IVR_OK) return st;
+    Model m;
+    m.patches = c->d_patches; m.cp32 = c->d_cp32; m.rho32 = c->d_rho32; m.cp64 = c->d_cp64;
+    m.rho64 = c->d_rho64; m.knots32 = c->d_knots32; m.knots64 = c->d_knots64; m.elems = c->d_elems;
+    m.npatch = c->npatch; m.scale = (float)c->scale; m.scaled = c->scale;
+    IVR_HIP(c, hipMemsetAsync(c->d_qs, 0, sizeof(QueueState), c->stream));
+    if (stats) IVR_HIP(c, hipMemsetAsync(c->d_ctr, 0, sizeof(unsigned long long) * C_COUNT, c->stream));
+    if (stats) IVR_HIP(c, hipEventRecord(c->ev[0], c->stream));
+    IVR_HIP(c, launch_fragments(fp64, m, fp, c->d_segs, (uint32_t)c->seg_cap, c->d_queues,
+                                (uint32_t)c->seg_cap, c->class_mask, c->d_qs, c->d_pixseg, depth_dev,
+                                c->d_ctr, c->stream));
+    if (stats) IVR_HIP(c, hipEventRecord(c->ev[1], c->stream));
+    for (int k = 0; k < kClasses; ++k) {
+        if (!((c->class_mask >> k) & 1)) continue;
+        IVR_HIP(c, launch_integrate(fp64, k, m, fp, c->d_segs, c->d_queues + (size_t)k * c->seg_cap,
+                                    c->d_qs, &c->d_qs->qnext[k], c->d_results, c->d_ctr, c->n_cu,
+                                    c->stream));
+    }
+    if (stats) IVR_HIP(c, hipEventRecord(c->ev[2], c->stream));
+    IVR_HIP(c, launch_merge(fp, c->d_pixseg, c->d_results, rgba_dev, c->stream));
+    if (stats) {
+        IVR_HIP(c, hipEventRecord(c->ev[3], c->stream));
+        unsigned long long h[C_COUNT];
+        IVR_HIP(c, hipMemcpyAsync(h, c->d_ctr, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        IVR_HIP(c, hipStreamSynchronize(c->stream));
+        std::memset(stats, 0, sizeof *stats);
+        uint64_t *dst = &stats->rays;
+        for (int k = 0; k < C_COUNT; ++k) dst[k] = h[k];
+        float ms;
+        IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        stats->ms_fragments = ms;
+        IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+        stats->ms_integrate = ms;
+        IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+        stats->ms_merge = ms;
+    }
+    c->err.clear();
+    return IVR_OK;
+}
+
+}  // extern "C"

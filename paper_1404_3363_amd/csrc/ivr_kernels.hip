@@ -1,0 +1,661 @@
+// gfx950 kernels of the per-pixel hot path.
+//
+//   k_fragments  one wave per 8x8 pixel tile.  For every block whose box the
+//                tile's rays hit: every face element box hit by the ray starts a
+//                Newton solve of S_f(a,b) = o + t d from the element centre
+//                (FP32, then FP64 refinement), crossings are classified
+//                front/back facing, de-duplicated, sorted and paired per block
+//                by Algorithm "Blockwise depth-sorting".  Segments are written
+//                contiguously per pixel (sorted by entry depth) after a wave
+//                prefix sum, and their indices are appended to one queue per
+//                degree class.
+//   k_integrate  persistent: every lane owns one segment, runs one RKF45 attempt
+//                per loop iteration on p' = W(p) (Eqs. (odepar), (VgVp)), samples
+//                rho at every accepted step, applies the transfer function with
+//                supersampling and composites by Algorithm "Front-to-back
+//                compositing"; finished lanes take the next segment from the
+//                class queue (wave-aggregated atomic), so short and long
+//                segments share waves without idling.
+//   k_merge      per pixel: over-composites its segments front to back.
+#include <hip/hip_runtime.h>
+
+#include "ivr_internal.h"
+#include "ivr_spline.h"
+
+namespace ivr {
+
+using u32 = uint32_t;
+using u64 = unsigned long long;
+
+__device__ __forceinline__ int lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ int rank_in(u64 mask) {
+    return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
+}
+
+// sum over the wave, result in every lane
+__device__ __forceinline__ u64 wave_sum(u64 v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ void flush_counter(u64 *ctr, int idx, u64 v) {
+    const u64 s = wave_sum(v);
+    if (lane_id() == 0 && s) atomicAdd(ctr + idx, s);
+}
+
+// Ray through the centre of pixel (px, py), computed in FP64.
+__device__ __forceinline__ void ray_dir(const FrameParams &fp, int px, int py, double (&d)[3]) {
+    const double sx = (2.0 * (px + 0.5) / fp.width - 1.0) * fp.tan_half * fp.aspect;
+    const double sy = (1.0 - 2.0 * (py + 0.5) / fp.height) * fp.tan_half;
+    double n2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        d[q] = fp.fwd[q] + sx * fp.right[q] + sy * fp.up[q];
+        n2 += d[q] * d[q];
+    }
+    const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) d[q] *= inv;
+}
+
+__device__ __forceinline__ bool slab(const float (&o)[3], const float (&inv)[3], const float *lo,
+                                     const float *hi) {
+    float tmin = 0.f, tmax = INFINITY;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float t0 = (lo[c] - o[c]) * inv[c], t1 = (hi[c] - o[c]) * inv[c];
+        tmin = fmaxf(tmin, fminf(t0, t1));
+        tmax = fminf(tmax, fmaxf(t0, t1));
+    }
+    return tmin <= tmax;
+}
+
+template <typename R>
+struct Frag {
+    double t;
+    R p[3];
+    int patch;
+    int entering;
+};
+
+// Ray against the oriented box of a face element.
+__device__ __forceinline__ bool obb_hit(const FaceElem &E, const float (&o)[3], const float (&d)[3]) {
+    const float oc[3] = {o[0] - E.c[0], o[1] - E.c[1], o[2] - E.c[2]};
+    float tmin = 0.f, tmax = INFINITY;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const float po = E.ax[r][0] * oc[0] + E.ax[r][1] * oc[1] + E.ax[r][2] * oc[2];
+        const float pd = E.ax[r][0] * d[0] + E.ax[r][1] * d[1] + E.ax[r][2] * d[2];
+        const float inv = __fdividef(1.0f, pd);
+        const float t0 = (-E.ext[r] - po) * inv, t1 = (E.ext[r] - po) * inv;
+        tmin = fmaxf(tmin, fminf(t0, t1));
+        tmax = fminf(tmax, fmaxf(t0, t1));
+    }
+    return tmin <= tmax;
+}
+
+template <typename R>
+__device__ __forceinline__ bool is_dup(const Frag<R> *fr, int nfr, int patch, int entering, double t,
+                                       double tol) {
+    bool dup = false;
+    for (int q = 0; q < nfr; ++q)
+        dup |= fr[q].patch == patch && fr[q].entering == entering && fabs(fr[q].t - t) <= tol;
+    return dup;
+}
+
+// Front facing: the sign of (J^-1 d) along the face's inward normal.  By
+// Cramer's rule it equals the sign of d . (S_a x S_b) times the face's side,
+// the orientation of (a, b, n) and the block's orientation (sign of det J).
+template <typename R>
+__device__ __forceinline__ int facing(int face, float orient, const R (&Sa)[3], const R (&Sb)[3],
+                                      const R (&d)[3], bool &grazing) {
+    R nrm[3];
+    cross3(Sa, Sb, nrm);
+    const R g = dot3(nrm, d);
+    grazing = !(fabs(g) > R(1e-10) * sqrt(dot3(nrm, nrm)));
+    const R sigma = ((face >> 1) == 1) ? R(-1) : R(1), side = (face & 1) ? R(-1) : R(1);
+    return (side * sigma * g * R(orient)) > R(0);
+}
+
+// Boundary roots seeded at the centre of element E: Newton on
+// S_f(a,b) - (o + t d) = 0 (Eqs. (F), (newtonsmethod) restricted to the face) in
+// precision RN; a root that converges anywhere on the face and is new for this
+// ray is refined in FP64 and inserted into the depth-sorted fragment list.
+template <int P, bool RAT, typename RN>
+__device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E, const double (&od)[3],
+                          const double (&dd)[3], const FrameParams &fp, Frag<RN> *fr, int &nfr,
+                          u32 &n_iter, u32 &n_polish, u32 &n_ovf) {
+    const int face = E.face;
+    const PatchView<RN> pv = view_of<RN>(Pd);
+    const Arrays<RN> ar = arrays_of(m, RN(0));
+    const RN o[3] = {RN(od[0]), RN(od[1]), RN(od[2])}, d[3] = {RN(dd[0]), RN(dd[1]), RN(dd[2])};
+    RN a = RN(0.5) * (RN(E.a0) + RN(E.a1)), b = RN(0.5) * (RN(E.b0) + RN(E.b1));
+    RN S[3], Sa[3], Sb[3];
+    eval_face<P, RAT, RN>(pv, ar, face, a, b, S, Sa, Sb);
+    RN t = (S[0] - o[0]) * d[0] + (S[1] - o[1]) * d[1] + (S[2] - o[2]) * d[2];
+    const RN tol = (sizeof(RN) == 4 ? RN(2e-6) : RN(1e-12)) * RN(fp.scaled);
+    bool conv = false;
+    for (int it = 0; it < fp.max_newton; ++it) {
+        ++n_iter;
+        RN F[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) F[q] = S[q] - o[q] - t * d[q];
+        if (dot3(F, F) <= tol * tol) {
+            conv = true;
+            break;
+        }
+        RN nd[3] = {-d[0], -d[1], -d[2]}, rhs[3] = {-F[0], -F[1], -F[2]}, st[3];
+        solve_cols(Sa, Sb, nd, rhs, st);
+        a += st[0];
+        b += st[1];
+        t += st[2];
+        if (!(a >= RN(-1) && a <= RN(2) && b >= RN(-1) && b <= RN(2))) return;
+        eval_face<P, RAT, RN>(pv, ar, face, a, b, S, Sa, Sb);
+    }
+    const RN mg = RN(1e-4);
+    if (!conv || !(a >= -mg && a <= RN(1) + mg && b >= -mg && b <= RN(1) + mg && t > RN(0))) return;
+    bool grazing;
+    int ent = facing(face, Pd.orient, Sa, Sb, d, grazing);
+    const int patch = E.patch;
+    if (!grazing && is_dup(fr, nfr, patch, ent, double(t), 2e-5 * fp.scaled)) return;
+    // FP64 refinement of the boundary root
+    const PatchView<double> pv64 = view_of<double>(Pd);
+    const Arrays<double> ar64 = arrays_of(m, 0.0);
+    double A = a, B = b, T = t, S2[3], Sa2[3], Sb2[3], F2[3];
+    const double tol64 = 1e-12 * fp.scaled;
+    for (int k = 0;; ++k) {
+        eval_face<P, RAT, double>(pv64, ar64, face, A, B, S2, Sa2, Sb2);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) F2[q] = S2[q] - od[q] - T * dd[q];
+        if (dot3(F2, F2) <= tol64 * tol64 || k == 3) break;
+        ++n_polish;
+        double nd[3] = {-dd[0], -dd[1], -dd[2]}, rhs[3] = {-F2[0], -F2[1], -F2[2]}, st[3];
+        solve_cols(Sa2, Sb2, nd, rhs, st);
+        A += st[0];
+        B += st[1];
+        T += st[2];
+    }
+    if (!(dot3(F2, F2) <= 1e-18 * fp.scaled * fp.scaled)) return;
+    const double mg64 = 1e-7;
+    if (!(A >= -mg64 && A <= 1.0 + mg64 && B >= -mg64 && B <= 1.0 + mg64 && T > 0.0)) return;
+    ent = facing(face, Pd.orient, Sa2, Sb2, dd, grazing);
+    if (grazing) return;
+    if (is_dup(fr, nfr, patch, ent, T, 1e-6 * fp.scaled)) return;
+    if (nfr >= fp.max_frag) {
+        ++n_ovf;
+        return;
+    }
+    int dn, da, db;
+    face_dirs(face, dn, da, db);
+    Frag<RN> f;
+    f.t = T;
+    f.patch = patch;
+    f.entering = ent;
+    RN pp[3];
+    pp[dn] = (face & 1) ? RN(1) : RN(0);
+    pp[da] = RN(clamp01(A));
+    pp[db] = RN(clamp01(B));
+    f.p[0] = pp[0]; f.p[1] = pp[1]; f.p[2] = pp[2];
+    int q = nfr++;
+    while (q > 0 && fr[q - 1].t > T) {
+        fr[q] = fr[q - 1];
+        --q;
+    }
+    fr[q] = f;
+}
+
+template <typename R>
+__device__ __forceinline__ void face_root_any(const Model &m, const DevPatch &Pd, const FaceElem &E,
+                                              const double (&od)[3], const double (&dd)[3],
+                                              const FrameParams &fp, Frag<R> *fr, int &nfr, u32 &ni,
+                                              u32 &np, u32 &no) {
+    switch (Pd.deg * 2 + Pd.rational) {
+    case 2: face_root<1, false, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
+    case 3: face_root<1, true, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
+    case 4: face_root<2, false, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
+    case 5: face_root<2, true, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
+    case 6: face_root<3, false, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
+    default: face_root<3, true, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void rho_ds_any(const Model &m, const DevPatch &Pd, const R (&p)[3],
+                                           const R (&d)[3], R &rho, R &drho) {
+    const PatchView<R> pv = view_of<R>(Pd);
+    const Arrays<R> ar = arrays_of(m, R(0));
+    switch (Pd.deg * 2 + Pd.rational) {
+    case 2: eval_rho_ds<1, false>(pv, ar, p, d, rho, drho); break;
+    case 3: eval_rho_ds<1, true>(pv, ar, p, d, rho, drho); break;
+    case 4: eval_rho_ds<2, false>(pv, ar, p, d, rho, drho); break;
+    case 5: eval_rho_ds<2, true>(pv, ar, p, d, rho, drho); break;
+    case 6: eval_rho_ds<3, false>(pv, ar, p, d, rho, drho); break;
+    default: eval_rho_ds<3, true>(pv, ar, p, d, rho, drho); break;
+    }
+}
+
+__device__ __forceinline__ u32 wave_incl_scan(u32 v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const u32 x = __shfl_up(v, off);
+        if (lane >= off) v += x;
+    }
+    return v;
+}
+
+template <typename R>
+__global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R> *segs, u32 seg_cap,
+                                                  u32 *queues, u32 queue_stride, u32 class_mask,
+                                                  QueueState *qs, uint2 *pixseg, float *depth,
+                                                  u64 *ctr) {
+    const int lane = threadIdx.x;
+    const int tiles_x = (fp.width + 7) >> 3;
+    const int px = (blockIdx.x % tiles_x) * 8 + (lane & 7);
+    const int py = (blockIdx.x / tiles_x) * 8 + (lane >> 3);
+    const bool valid = px < fp.width && py < fp.height;
+    const u32 pixel = valid ? (u32)(py * fp.width + px) : 0u;
+
+    double dd[3];
+    ray_dir(fp, valid ? px : 0, valid ? py : 0, dd);
+    const double od[3] = {fp.eye[0], fp.eye[1], fp.eye[2]};
+    float of[3], df[3], inv[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        of[q] = float(od[q]);
+        df[q] = float(dd[q]);
+        inv[q] = 1.0f / df[q];
+    }
+    u32 c_anom = 0, c_fovf = 0, c_sovf = 0, c_box = 0, c_newton = 0, c_iter = 0, c_pol = 0;
+
+    // 1. face elements whose oriented box the ray hits (block and face boxes
+    //    first) become Newton seeds; 2. the seeds are solved with all lanes in
+    //    step, whenever a lane's list is full and at the end.
+    u32 cand[kCandCap];
+    int ncand = 0;
+    Frag<R> fr[kFragCap];
+    int nfr = 0;
+    auto solve_candidates = [&]() {
+        for (int k = 0; __ballot(k < ncand) != 0; ++k) {
+            if (k < ncand) {
+                const FaceElem E = m.elems[cand[k]];
+                ++c_newton;
+                face_root_any<R>(m, m.patches[E.patch], E, od, dd, fp, fr, nfr, c_iter, c_pol, c_fovf);
+            }
+        }
+        ncand = 0;
+    };
+    for (int pi = 0; pi < m.npatch; ++pi) {
+        const DevPatch &Pd = m.patches[pi];
+        ++c_box;
+        const bool hp = valid && slab(of, inv, Pd.box, Pd.box + 3);
+        if (__ballot(hp) == 0) continue;
+        for (int f = 0; f < 6; ++f) {
+            c_box += hp;
+            const bool hf = hp && slab(of, inv, Pd.fbox[f], Pd.fbox[f] + 3);
+            if (__ballot(hf) == 0) continue;
+            for (int e = Pd.elem_off[f]; e < Pd.elem_off[f + 1]; ++e) {
+                c_box += hf;
+                if (hf && obb_hit(m.elems[e], of, df)) cand[ncand++] = (u32)e;
+                if (__ballot(ncand == kCandCap) != 0) solve_candidates();
+            }
+        }
+    }
+    solve_candidates();
+    // 3. Algorithm "Blockwise depth-sorting": the nearest unused exit, then the
+    //    nearest unused entry of the same block in front of it.
+    unsigned char pin[kSegCap], pout[kSegCap];
+    int npair = 0;
+    u64 used = 0;
+    for (;;) {
+        int ib = -1;
+        for (int q = 0; q < nfr; ++q)
+            if (!((used >> q) & 1ull) && !fr[q].entering) { ib = q; break; }
+        if (ib < 0) break;
+        used |= 1ull << ib;
+        int ifr = -1;
+        for (int q = 0; q < ib; ++q)
+            if (!((used >> q) & 1ull) && fr[q].entering && fr[q].patch == fr[ib].patch) { ifr = q; break; }
+        if (ifr < 0) { ++c_anom; continue; }
+        used |= 1ull << ifr;
+        if (npair >= kSegCap) { ++c_sovf; continue; }
+        // keep the pairs ordered by entry depth
+        int q = npair++;
+        while (q > 0 && fr[pin[q - 1]].t > fr[ifr].t) {
+            pin[q] = pin[q - 1];
+            pout[q] = pout[q - 1];
+            --q;
+        }
+        pin[q] = (unsigned char)ifr;
+        pout[q] = (unsigned char)ib;
+    }
+    for (int q = 0; q < nfr; ++q) c_anom += !((used >> q) & 1ull);
+
+    // 4. contiguous per-pixel ranges: wave prefix sum, one atomic per wave
+    int nseg = npair;
+    const u32 incl = wave_incl_scan((u32)nseg, lane);
+    const u32 total = __shfl(incl, 63);
+    u32 base = 0;
+    if (lane == 63 && total) base = atomicAdd(&qs->seg_total, total);
+    base = __shfl(base, 63);
+    u32 first = base + incl - (u32)nseg;
+    if (base + total > seg_cap) {  // capacity exhausted: drop this wave's segments
+        c_sovf += nseg;
+        nseg = 0;
+        first = 0;
+    }
+    const R dr[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
+    for (int k = 0; k < nseg; ++k) {
+        const Frag<R> &fi = fr[pin[k]];
+        const Frag<R> &fo = fr[pout[k]];
+        Seg<R> s;
+        s.t_in = R(fi.t);
+        s.t_out = R(fo.t);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            s.p_in[q] = fi.p[q];
+            s.p_out[q] = fo.p[q];
+        }
+        rho_ds_any<R>(m, m.patches[fo.patch], fo.p, dr, s.rho_out, s.drho_out);
+        s.pixel = pixel;
+        s.patch = (u32)fo.patch;
+        segs[first + k] = s;
+    }
+    // one queue per degree class
+    for (int c = 0; c < kClasses; ++c) {
+        if (!((class_mask >> c) & 1)) continue;
+        u32 cnt = 0;
+        for (int k = 0; k < nseg; ++k) cnt += (u32)m.patches[fr[pout[k]].patch].klass == (u32)c;
+        const u32 ci = wave_incl_scan(cnt, lane);
+        const u32 ctot = __shfl(ci, 63);
+        u32 cb = 0;
+        if (lane == 63 && ctot) cb = atomicAdd(&qs->qcount[c], ctot);
+        cb = __shfl(cb, 63);
+        u32 w = cb + ci - cnt;
+        u32 *qc = queues + (size_t)c * queue_stride;
+        for (int k = 0; k < nseg; ++k)
+            if ((u32)m.patches[fr[pout[k]].patch].klass == (u32)c) qc[w++] = first + (u32)k;
+    }
+    if (valid) {
+        pixseg[pixel] = make_uint2(first, (u32)nseg);
+        if (depth) depth[pixel] = nseg ? float(fr[pin[0]].t) : INFINITY;
+    }
+    if (fp.collect) {
+        flush_counter(ctr, C_RAYS, valid ? 1 : 0);
+        flush_counter(ctr, C_SEGMENTS, nseg);
+        flush_counter(ctr, C_FRAGMENTS, nfr);
+        flush_counter(ctr, C_ANOMALIES, c_anom);
+        flush_counter(ctr, C_FRAG_OVF, c_fovf);
+        flush_counter(ctr, C_SEG_OVF, c_sovf);
+        flush_counter(ctr, C_BOX_TESTS, c_box);
+        flush_counter(ctr, C_FACE_NEWTON, c_newton);
+        flush_counter(ctr, C_FACE_NEWTON_ITER, c_iter);
+        flush_counter(ctr, C_FP64_POLISH, c_pol);
+    }
+}
+
+__device__ __forceinline__ float pow_fifth(float x) { return exp2f(0.2f * __log2f(x)); }
+__device__ __forceinline__ double pow_fifth(double x) { return pow(x, 0.2); }
+
+// Runge-Kutta-Fehlberg 4(5): stages, 5th-order weights (propagated) and the
+// difference of the 5th- and 4th-order weights (error estimate).
+template <typename R>
+struct RKF {
+    static constexpr R a21 = R(1) / R(4);
+    static constexpr R a31 = R(3) / R(32), a32 = R(9) / R(32);
+    static constexpr R a41 = R(1932) / R(2197), a42 = R(-7200) / R(2197), a43 = R(7296) / R(2197);
+    static constexpr R a51 = R(439) / R(216), a52 = R(-8), a53 = R(3680) / R(513),
+                       a54 = R(-845) / R(4104);
+    static constexpr R a61 = R(-8) / R(27), a62 = R(2), a63 = R(-3544) / R(2565),
+                       a64 = R(1859) / R(4104), a65 = R(-11) / R(40);
+    static constexpr R b1 = R(16) / R(135), b3 = R(6656) / R(12825), b4 = R(28561) / R(56430),
+                       b5 = R(-9) / R(50), b6 = R(2) / R(55);
+    static constexpr R e1 = R(1) / R(360), e3 = R(-128) / R(4275), e4 = R(-2197) / R(75240),
+                       e5 = R(1) / R(50), e6 = R(2) / R(55);
+};
+
+template <int P, bool RAT, typename R>
+__global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, const Seg<R> *segs,
+                                                   const u32 *queue, const QueueState *qs, int klass,
+                                                   u32 *qnext, float4 *results, u64 *ctr) {
+    using K = RKF<R>;
+    const u32 qcount = qs->qcount[klass];
+    const Arrays<R> ar = arrays_of(m, R(0));
+    const R tol = sizeof(R) == 4 ? R(fp.rk_tol) : R(fp.rk_told);
+    const R hmax = sizeof(R) == 4 ? R(fp.h_max) : R(fp.h_maxd);
+    const R hmin = sizeof(R) == 4 ? R(fp.h_min) : R(fp.h_mind);
+    const R cperp = sizeof(R) == 4 ? R(fp.c_perp) : R(fp.c_perpd);
+    const R early = sizeof(R) == 4 ? R(fp.early_term) : R(fp.early_termd);
+    const R dthr = sizeof(R) == 4 ? R(fp.det_thr) : R(fp.det_thrd);
+
+    bool active = false, queue_empty = false;
+    u32 sid = 0;
+    PatchView<R> pv;
+    R p[3] = {0, 0, 0}, gin[3] = {0, 0, 0}, d[3] = {0, 0, 0};
+    R s = 0, L = 0, h = 0, h_prev = 0, rho_prev = 0, m_prev = 0, rho_out = 0, m_out = 0;
+    R C[3] = {0, 0, 0}, A = 0;
+    bool pending = false, fresh = false;
+    int iters = 0;
+    u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_cap = 0;
+
+    for (;;) {
+        // refill idle lanes from the queue (one atomic per wave)
+        const u64 need = __ballot(!active);
+        if (need && !queue_empty) {
+            const int leader = __ffsll((long long)need) - 1;
+            u32 b = 0;
+            if (lane_id() == leader) b = atomicAdd(qnext, (u32)__popcll(need));
+            b = __shfl(b, leader);
+            if (b + (u32)__popcll(need) >= qcount) queue_empty = true;
+            if (!active) {
+                const u32 qi = b + (u32)rank_in(need);
+                if (qi < qcount) {
+                    sid = queue[qi];
+                    const Seg<R> sg = segs[sid];
+                    pv = view_of<R>(m.patches[sg.patch]);
+                    const int pxl = (int)(sg.pixel % (u32)fp.width), pyl = (int)(sg.pixel / (u32)fp.width);
+                    double dd[3];
+                    ray_dir(fp, pxl, pyl, dd);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        d[q] = R(dd[q]);
+                        gin[q] = R(fp.eye[q] + double(sg.t_in) * dd[q]);
+                        p[q] = sg.p_in[q];
+                    }
+                    L = sg.t_out - sg.t_in;
+                    s = R(0);
+                    h = L < hmax ? L : hmax;
+                    rho_out = sg.rho_out;
+                    m_out = sg.drho_out;
+                    C[0] = C[1] = C[2] = A = R(0);
+                    pending = false;
+                    fresh = true;
+                    iters = 0;
+                    active = true;
+                }
+            }
+        }
+        if (__ballot(active) == 0) break;
+        if (!active) continue;
+
+        bool done = false;
+        // stage 1 at the current point; also samples rho and d rho/ds there
+        R k1[3], k2[3], k3[3], k4[3], k5[3], k6[3], rho_cur = R(0), grho[3];
+        eval_W<P, RAT, 2>(pv, ar, p, gin, d, cperp, dthr, k1, rho_cur, grho, c_fp64);
+        ++c_w;
+        const R m_cur = dot3(grho, k1);
+        if (fresh) {
+            rho_prev = rho_cur;
+            m_prev = m_cur;
+            fresh = false;
+            if (!(L > R(1e-7) * R(fp.scaled))) done = true;   // empty chord
+        } else if (pending) {
+            composite(fp, rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A);
+            ++c_samp;
+            rho_prev = rho_cur;
+            m_prev = m_cur;
+            pending = false;
+            if (A >= R(1) - early) done = true;
+        }
+        if (!done) {
+            const R hh = (h < L - s) ? h : (L - s);
+            R q[3], dummy, dg[3];
+#define IVR_STAGE(KOUT, EXPR)                                                              \
+    _Pragma("unroll") for (int c = 0; c < 3; ++c) q[c] = clamp01(p[c] + hh * (EXPR));      \
+    eval_W<P, RAT, 0>(pv, ar, q, gin, d, cperp, dthr, KOUT, dummy, dg, c_fp64);            \
+    ++c_w;
+            IVR_STAGE(k2, K::a21 * k1[c])
+            IVR_STAGE(k3, K::a31 * k1[c] + K::a32 * k2[c])
+            IVR_STAGE(k4, K::a41 * k1[c] + K::a42 * k2[c] + K::a43 * k3[c])
+            IVR_STAGE(k5, K::a51 * k1[c] + K::a52 * k2[c] + K::a53 * k3[c] + K::a54 * k4[c])
+            IVR_STAGE(k6, K::a61 * k1[c] + K::a62 * k2[c] + K::a63 * k3[c] + K::a64 * k4[c] +
+                              K::a65 * k5[c])
+#undef IVR_STAGE
+            ++c_steps;
+            R err = R(0), p5[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                p5[c] = p[c] + hh * (K::b1 * k1[c] + K::b3 * k3[c] + K::b4 * k4[c] + K::b5 * k5[c] +
+                                     K::b6 * k6[c]);
+                const R e = fabs(hh * (K::e1 * k1[c] + K::e3 * k3[c] + K::e4 * k4[c] +
+                                       K::e5 * k5[c] + K::e6 * k6[c]));
+                err = e > err ? e : err;
+            }
+            const bool accept = (err <= tol) || (hh <= hmin);
+            if (accept) {
+                s += hh;
+                if (L - s <= R(1e-6) * L) {
+                    // last step ends on the exit fragment: use its rho
+                    composite(fp, rho_prev, m_prev, rho_out, m_out, hh, C, A);
+                    ++c_samp;
+                    done = true;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) p[c] = clamp01(p5[c]);
+                    pending = true;
+                    h_prev = hh;
+                }
+            } else {
+                ++c_rej;
+            }
+            // step-size control for a 4(5) pair
+            R fac = R(2.5);
+            if (err > R(0)) {
+                fac = R(0.9) * pow_fifth(tol / err);
+                fac = fac < R(0.2) ? R(0.2) : (fac > R(2.5) ? R(2.5) : fac);
+            }
+            h = hh * fac;
+            h = h > hmax ? hmax : h;
+            h = h < hmin ? hmin : h;
+            if (++iters >= 20000 && !done) {
+                ++c_cap;
+                done = true;
+            }
+        }
+        if (done) {
+            results[sid] = make_float4(float(C[0]), float(C[1]), float(C[2]), float(A));
+            active = false;
+        }
+    }
+    if (fp.collect) {
+        flush_counter(ctr, C_RK_STEPS, c_steps);
+        flush_counter(ctr, C_RK_REJECTED, c_rej);
+        flush_counter(ctr, C_SAMPLES, c_samp);
+        flush_counter(ctr, C_W_EVALS, c_w);
+        flush_counter(ctr, C_FP64_SOLVES, c_fp64);
+        flush_counter(ctr, C_RK_ITER_CAP, c_cap);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_merge(FrameParams fp, const uint2 *pixseg,
+                                               const float4 *results, float4 *rgba) {
+    const u32 pixel = blockIdx.x * 256u + threadIdx.x;
+    if (pixel >= (u32)(fp.width * fp.height)) return;
+    const uint2 ps = pixseg[pixel];
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+    for (u32 k = 0; k < ps.y; ++k) {
+        if (A >= 1.0f - fp.early_term) break;
+        const float4 r = results[ps.x + k];
+        const float w = 1.0f - A;
+        C0 += w * r.x;
+        C1 += w * r.y;
+        C2 += w * r.z;
+        A += w * r.w;
+    }
+    rgba[pixel] = make_float4(C0, C1, C2, A);
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename R>
+static hipError_t launch_fragments_t(const Model &m, const FrameParams &fp, void *segs,
+                                     uint32_t seg_cap, uint32_t *queues, uint32_t queue_stride,
+                                     uint32_t class_mask, QueueState *qs, uint2 *pixseg, float *depth,
+                                     unsigned long long *ctr, hipStream_t st) {
+    const int tiles = ((fp.width + 7) / 8) * ((fp.height + 7) / 8);
+    hipLaunchKernelGGL((k_fragments<R>), dim3(tiles), dim3(64), 0, st, m, fp, (Seg<R> *)segs, seg_cap,
+                       queues, queue_stride, class_mask, qs, pixseg, depth, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_fragments(bool fp64, const Model &m, const FrameParams &fp, void *segs,
+                            uint32_t seg_cap, uint32_t *queues, uint32_t queue_stride,
+                            uint32_t class_mask, QueueState *qs, uint2 *pixseg, float *depth,
+                            unsigned long long *ctr, hipStream_t st) {
+    return fp64 ? launch_fragments_t<double>(m, fp, segs, seg_cap, queues, queue_stride, class_mask,
+                                             qs, pixseg, depth, ctr, st)
+                : launch_fragments_t<float>(m, fp, segs, seg_cap, queues, queue_stride, class_mask,
+                                            qs, pixseg, depth, ctr, st);
+}
+
+template <int P, bool RAT, typename R>
+static hipError_t launch_integrate_t(const Model &m, const FrameParams &fp, const void *segs,
+                                     const uint32_t *queue, const QueueState *qs, int klass,
+                                     uint32_t *qnext, float4 *results, unsigned long long *ctr,
+                                     int n_cu, hipStream_t st) {
+    static int blocks_per_cu = -1;
+    if (blocks_per_cu < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<P, RAT, R>, 256, 0) !=
+                hipSuccess || nb < 1)
+            nb = 1;
+        blocks_per_cu = nb;
+    }
+    hipLaunchKernelGGL((k_integrate<P, RAT, R>), dim3(n_cu * blocks_per_cu), dim3(256), 0, st, m, fp,
+                       (const Seg<R> *)segs, queue, qs, klass, qnext, results, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate(bool fp64, int klass, const Model &m, const FrameParams &fp,
+                            const void *segs, const uint32_t *queue, const QueueState *qs,
+                            uint32_t *qnext, float4 *results, unsigned long long *ctr, int n_cu,
+                            hipStream_t st) {
+#define IVR_CASE(K, P, RAT)                                                                     \
+    case K:                                                                                     \
+        return fp64 ? launch_integrate_t<P, RAT, double>(m, fp, segs, queue, qs, klass, qnext,  \
+                                                         results, ctr, n_cu, st)                \
+                    : launch_integrate_t<P, RAT, float>(m, fp, segs, queue, qs, klass, qnext,   \
+                                                        results, ctr, n_cu, st);
+    switch (klass) {
+        IVR_CASE(0, 1, false)
+        IVR_CASE(1, 1, true)
+        IVR_CASE(2, 2, false)
+        IVR_CASE(3, 2, true)
+        IVR_CASE(4, 3, false)
+        IVR_CASE(5, 3, true)
+    default: return hipErrorInvalidValue;
+    }
+#undef IVR_CASE
+}
+
+hipError_t launch_merge(const FrameParams &fp, const uint2 *pixseg, const float4 *results, float *rgba,
+                        hipStream_t st) {
+    const int n = fp.width * fp.height;
+    hipLaunchKernelGGL(k_merge, dim3((n + 255) / 256), dim3(256), 0, st, fp, pixseg, results,
+                       (float4 *)rgba);
+    return hipGetLastError();
+}
+
+}  // namespace ivr

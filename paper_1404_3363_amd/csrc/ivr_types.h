@@ -1,0 +1,122 @@
+// Data layout shared by the host library and the gfx950 kernels.
+//
+// Model (uploaded once, read-only while rendering):
+//   DevPatch[npatch]      per-block metadata and bounding boxes (one 16-B aligned record)
+//   cp32 / cp64           control points, float4 / double4 per point: (x,y,z,1) for
+//                         B-splines, homogeneous (wx,wy,wz,w) for NURBS; i fastest
+//   rho32 / rho64         scalar coefficients (w*rho for NURBS), same order
+//   knots32 / knots64     knot vectors normalised to [0,1] (only read for
+//                         non-uniform directions)
+//   FaceElem[nelem]       one record per non-empty knot span of every boundary face
+// Frame buffers (grow-only, owned by the context):
+//   Seg[cap]              entry/exit pairs written by the fragment kernel
+//   queue[class][cap]     segment indices per degree class, consumed by the integrator
+//   results[cap]          premultiplied (C, alpha) per segment
+//   pixseg[pixels]        (first segment, count) per pixel, segments sorted by entry depth
+#pragma once
+#include <stdint.h>
+
+namespace ivr {
+
+constexpr int kMaxDegree = 3;
+constexpr int kMaxTfKnots = 16;
+constexpr int kClasses = 6;          // degree class = 2*(degree-1) + rational
+constexpr int kFragCap = 64;         // boundary crossings kept per ray (hard cap)
+constexpr int kSegCap = 32;          // segments kept per pixel
+constexpr int kCandCap = 128;        // face elements whose box a ray hits (Newton seeds)
+
+struct alignas(16) DevPatch {
+    int32_t deg;           // isotropic degree 1..3
+    int32_t n[3];          // control points per direction
+    int32_t nspan[3];      // n - deg (number of spans when uniform)
+    int32_t uniform;       // bit d: open-uniform knots in direction d
+    int32_t rational;      // 1: NURBS
+    int32_t cp_off;        // index of the first control point
+    int32_t knot_off[3];   // offset of each knot vector in the knot arrays
+    int32_t elem_off[7];   // face f owns elements [elem_off[f], elem_off[f+1])
+    int32_t klass;         // degree class
+    float orient;          // sign of det J over the block (+1 / -1)
+    float box[6];          // padded bounding box lo[3], hi[3]
+    float fbox[6][6];      // padded bounding box of each face
+    float inv_nspan[3];
+    float pad0;
+};
+
+// Face element: oriented box around the element's control points (axes from the
+// net's edge directions; the element lies in the convex hull of its points).
+struct alignas(16) FaceElem {
+    float c[3];            // box centre
+    float ax[3][3];        // orthonormal axes (rows)
+    float ext[3];          // padded half extents along the axes
+    float a0, a1, b0, b1;  // parameter rectangle in the face's (a, b) directions
+    int32_t face;
+    int32_t patch;
+    int32_t pad[2];
+};
+
+template <typename R>
+struct Seg {
+    R t_in, t_out;         // ray parameters of entry and exit
+    R p_in[3], p_out[3];   // parameter points of entry and exit
+    R rho_out;             // rho at the exit
+    R drho_out;            // d rho / ds at the exit (along the ray)
+    uint32_t pixel;        // linear pixel index
+    uint32_t patch;
+};
+
+struct Model {
+    const DevPatch *patches;
+    const float4 *cp32;
+    const float *rho32;
+    const double4 *cp64;
+    const double *rho64;
+    const float *knots32;
+    const double *knots64;
+    const FaceElem *elems;
+    int32_t npatch;
+    float scale;           // bounding-box diagonal of the model
+    double scaled;
+};
+
+// Device-side counters, one 64-bit slot each (ivr_stats order).
+enum Counter : int {
+    C_RAYS = 0, C_SEGMENTS, C_FRAGMENTS, C_ANOMALIES, C_FRAG_OVF, C_SEG_OVF, C_BOX_TESTS,
+    C_FACE_NEWTON, C_FACE_NEWTON_ITER, C_FP64_POLISH, C_RK_STEPS, C_RK_REJECTED, C_SAMPLES,
+    C_W_EVALS, C_FP64_SOLVES, C_RK_ITER_CAP, C_MLP_QUERIES, C_COUNT
+};
+
+// Queue bookkeeping written by the fragment kernel and read by the integrator.
+struct QueueState {
+    uint32_t seg_total;             // segments written
+    uint32_t qcount[kClasses];      // segments per class
+    uint32_t qnext[kClasses];       // next queue slot to hand out (integrator)
+    uint32_t pad;
+};
+
+struct FrameParams {
+    // camera (FP64 and FP32 copies of the same basis)
+    double eye[3], fwd[3], right[3], up[3];
+    double tan_half, aspect;
+    float eyef[3], fwdf[3], rightf[3], upf[3];
+    float tan_halff, aspectf;
+    int32_t width, height;
+    // transfer function: knots x[k] and per-interval value/slope
+    int32_t tf_n;
+    float tf_x[kMaxTfKnots];
+    float tf_v[kMaxTfKnots][4];     // value at knot k (RGB, kappa = extinction*A)
+    float tf_s[kMaxTfKnots][4];     // slope on [x_k, x_{k+1}]
+    float tf_lo, tf_inv_range;
+    float tf_dn;                    // target change of n per supersampling sub-step
+    double tf_xd[kMaxTfKnots];
+    double tf_vd[kMaxTfKnots][4];
+    double tf_sd[kMaxTfKnots][4];
+    double tf_lod, tf_inv_ranged;
+    // integrator
+    float rk_tol, h_max, h_min, c_perp, early_term, det_thr;
+    double rk_told, h_maxd, h_mind, c_perpd, early_termd, det_thrd;
+    int32_t n_super, max_frag, max_newton, collect, hermite;
+    float scale;
+    double scaled;
+};
+
+}  // namespace ivr

@@ -1,0 +1,223 @@
+"""ctypes binding of the C ABI in include/ivr.h.
+
+Argument marshalling only: every step of the render runs in the gfx950 kernels of
+``libivr.so``.  PyTorch provides device memory and the stream.  There is no CPU
+fallback: if the library or a GPU is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libivr.so")
+
+IVR_OK, IVR_EINVAL, IVR_ENOMEM, IVR_EDEVICE, IVR_ESTATE, IVR_EOVERFLOW = 0, -1, -2, -3, -4, -5
+PRECISION = {"fp32": 0, "fp64": 1}
+SEED = {"plain": 0, "mlp": 1}
+RHO_INTERP = {"linear": 0, "hermite": 1}
+
+EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_render",
+           "ivr_last_error", "ivr_destroy"]
+
+
+class PatchDesc(C.Structure):
+    _fields_ = [("degree", C.c_int32 * 3), ("ncp", C.c_int32 * 3),
+                ("knots", C.POINTER(C.c_double) * 3), ("cp", C.POINTER(C.c_double)),
+                ("scalar", C.POINTER(C.c_double)), ("rational", C.c_int32)]
+
+
+class CameraDesc(C.Structure):
+    _fields_ = [("eye", C.c_double * 3), ("target", C.c_double * 3), ("up", C.c_double * 3),
+                ("fov_y_deg", C.c_double), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class TransferDesc(C.Structure):
+    _fields_ = [("n_knots", C.c_int32), ("x", C.POINTER(C.c_double)),
+                ("rgba", C.POINTER(C.c_double)), ("extinction", C.c_double),
+                ("domain", C.c_double * 2)]
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("rk_tol", C.c_double), ("h_max", C.c_double),
+                ("c_perp", C.c_double), ("n_super", C.c_int32),
+                ("det_fp64_threshold", C.c_double), ("max_fragments", C.c_int32),
+                ("seed_mode", C.c_int32), ("early_term", C.c_double),
+                ("max_newton_iter", C.c_int32), ("rho_interp", C.c_int32)]
+
+
+STAT_FIELDS = ["rays", "segments", "fragments", "anomalies", "fragment_overflow",
+               "segment_overflow", "box_tests", "face_newton", "face_newton_iter",
+               "fp64_polish_iter", "rk_steps", "rk_rejected", "samples", "w_evals",
+               "fp64_solves", "rk_iter_cap", "mlp_queries"]
+
+
+class Stats(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [
+        ("ms_fragments", C.c_double), ("ms_integrate", C.c_double), ("ms_merge", C.c_double)]
+
+
+_lib = None
+
+
+def load_library() -> C.CDLL:
+    """Load libivr.so (built by __graft_entry__.build()); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.ivr_create.argtypes = [C.POINTER(vp), C.c_int32, vp]
+    L.ivr_create.restype = C.c_int32
+    L.ivr_default_opts.argtypes = [C.POINTER(RenderOpts)]
+    L.ivr_default_opts.restype = None
+    L.ivr_upload_patches.argtypes = [vp, C.POINTER(PatchDesc), C.c_int32]
+    L.ivr_upload_patches.restype = C.c_int32
+    L.ivr_render.argtypes = [vp, C.POINTER(CameraDesc), C.POINTER(TransferDesc),
+                             C.POINTER(RenderOpts), vp, vp, C.POINTER(Stats)]
+    L.ivr_render.restype = C.c_int32
+    L.ivr_last_error.argtypes = [vp]
+    L.ivr_last_error.restype = C.c_char_p
+    L.ivr_destroy.argtypes = [vp]
+    L.ivr_destroy.restype = None
+    _lib = L
+    return L
+
+
+class IvrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ivr error {code}: {msg}")
+        self.code = code
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def default_opts(**kw) -> RenderOpts:
+    o = RenderOpts()
+    load_library().ivr_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISION[v]
+        if k == "seed_mode" and isinstance(v, str):
+            v = SEED[v]
+        if k == "rho_interp" and isinstance(v, str):
+            v = RHO_INTERP[v]
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def camera_desc(cam) -> CameraDesc:
+    c = CameraDesc()
+    for q in range(3):
+        c.eye[q] = float(cam.eye[q])
+        c.target[q] = float(cam.target[q])
+        c.up[q] = float(cam.up[q])
+    c.fov_y_deg = float(cam.fov_y_deg)
+    c.width = int(cam.width)
+    c.height = int(cam.height)
+    return c
+
+
+class _TF:
+    def __init__(self, tf):
+        self.x = np.ascontiguousarray(tf.x, dtype=np.float64)
+        self.rgba = np.ascontiguousarray(np.asarray(tf.rgba, dtype=np.float64).reshape(-1))
+        d = TransferDesc()
+        d.n_knots = len(self.x)
+        d.x = _dp(self.x)
+        d.rgba = _dp(self.rgba)
+        d.extinction = float(tf.extinction)
+        d.domain[0] = float(tf.domain[0])
+        d.domain[1] = float(tf.domain[1])
+        self.desc = d
+
+
+class Renderer:
+    """One ivr context on a GPU.  Uses torch for output buffers and the stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("ivr needs a GPU (torch.cuda.is_available() is False)")
+        self.torch = torch
+        self.device = int(device)
+        self.lib = load_library()
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        handle = C.c_void_p(int(stream.cuda_stream))
+        ctx = C.c_void_p()
+        rc = self.lib.ivr_create(C.byref(ctx), self.device, handle)
+        if rc != IVR_OK:
+            raise IvrError(rc, "ivr_create failed (device missing or not gfx950)")
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.ivr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != IVR_OK:
+            raise IvrError(rc, self.lib.ivr_last_error(self.ctx).decode())
+
+    def upload(self, patches: Sequence) -> None:
+        keep = []
+        arr = (PatchDesc * len(patches))()
+        for i, p in enumerate(patches):
+            kn = [np.ascontiguousarray(k, dtype=np.float64) for k in p.knots]
+            cp = np.ascontiguousarray(p.cp, dtype=np.float64)
+            sc = np.ascontiguousarray(p.scalar, dtype=np.float64)
+            keep += kn + [cp, sc]
+            d = arr[i]
+            for q in range(3):
+                d.degree[q] = int(p.degree[q])
+                d.ncp[q] = int(p.ncp[q])
+                d.knots[q] = _dp(kn[q])
+            d.cp = _dp(cp)
+            d.scalar = _dp(sc)
+            d.rational = 1 if p.rational else 0
+        self._check(self.lib.ivr_upload_patches(self.ctx, arr, len(patches)))
+
+    def render(self, cam, tf, opts: Optional[RenderOpts] = None, rgba=None, depth=None,
+               stats: bool = False, **kw):
+        torch = self.torch
+        if opts is None:
+            opts = default_opts(**kw)
+        elif kw:
+            raise ValueError("pass either opts or keyword options")
+        dev = torch.device("cuda", self.device)
+        if rgba is None:
+            rgba = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=dev)
+        if depth is None:
+            depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device=dev)
+        assert rgba.is_contiguous() and rgba.numel() >= cam.width * cam.height * 4
+        assert depth.is_contiguous() and depth.numel() >= cam.width * cam.height
+        cd = camera_desc(cam)
+        td = _TF(tf)
+        st = Stats() if stats else None
+        rc = self.lib.ivr_render(self.ctx, C.byref(cd), C.byref(td.desc), C.byref(opts),
+                                 C.c_void_p(rgba.data_ptr()), C.c_void_p(depth.data_ptr()),
+                                 C.byref(st) if st is not None else None)
+        self._check(rc)
+        out = None
+        if st is not None:
+            out = {f: int(getattr(st, f)) for f in STAT_FIELDS}
+            out.update(ms_fragments=st.ms_fragments, ms_integrate=st.ms_integrate,
+                       ms_merge=st.ms_merge)
+        return rgba, depth, out

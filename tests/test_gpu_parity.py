@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar (the benchmark spec): max |RGBA_gpu - RGBA_oracle| <= 1e-3 per channel, entry depth
+within 1e-5 relative.  Full images at small sizes; at 512^2 and 1920x1080 the
+full GPU image is compared on seeded pixel samples (random plus silhouette
+pixels) that the oracle computes one by one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from scenes import make_config, camera_from_angles
+from scenes.configs import Patch, TransferFunction
+
+pytestmark = pytest.mark.gpu
+
+RGBA_TOL = 1e-3
+DEPTH_REL_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def renderer():
+    from paper_1404_3363_amd import Renderer
+    r = Renderer(0)
+    yield r
+    r.close()
+
+
+def _render(r, scene_patches, cam, tf, **kw):
+    import torch
+    r.upload(scene_patches)
+    rgba, depth, st = r.render(cam, tf, stats=True, **kw)
+    torch.cuda.synchronize()
+    return (rgba.cpu().numpy().reshape(-1, 4).astype(np.float64),
+            depth.cpu().numpy().reshape(-1).astype(np.float64), st)
+
+
+def _silhouette_pixels(depth, w, h):
+    d = np.isfinite(depth.reshape(h, w))
+    edge = np.zeros_like(d)
+    edge[:, 1:] |= d[:, 1:] != d[:, :-1]
+    edge[1:, :] |= d[1:, :] != d[:-1, :]
+    return np.flatnonzero(edge.reshape(-1))
+
+
+def _sample(cam, depth, n_random, n_edge, seed):
+    rng = np.random.default_rng(seed)
+    npx = cam.width * cam.height
+    covered = np.flatnonzero(np.isfinite(depth))
+    pick = [rng.choice(npx, n_random // 2, replace=False)]
+    if len(covered):
+        pick.append(rng.choice(covered, min(n_random // 2, len(covered)), replace=False))
+    edge = _silhouette_pixels(depth, cam.width, cam.height)
+    if len(edge):
+        pick.append(rng.choice(edge, min(n_edge, len(edge)), replace=False))
+    return np.unique(np.concatenate(pick))
+
+
+def _compare(name, img, depth, ref, pix=None, scale=1.0):
+    if pix is not None:
+        img, depth = img[pix], depth[pix]
+    err = np.abs(img - ref.rgba)
+    # depth is compared where both hit and the oracle's first chord is not a
+    # grazing sliver (< 1e-4 of the scene scale)
+    both = np.isfinite(depth) & np.isfinite(ref.depth) & (ref.first_chord >= 1e-4 * scale)
+    rel = np.abs(depth[both] - ref.depth[both]) / ref.depth[both] if both.any() else np.zeros(1)
+    cover_mismatch = int((np.isfinite(depth) != np.isfinite(ref.depth)).sum())
+    print(f"[parity] {name}: n={len(img)} max|rgba|={err.max():.3e} mean={err.mean():.3e} "
+          f"depth_rel={rel.max():.3e} coverage_mismatch={cover_mismatch}", flush=True)
+    assert (ref.n_anomalies == 0).all() and (ref.n_newton_fail == 0).all()
+    worst = int(np.unravel_index(err.argmax(), err.shape)[0])
+    wpix = int(pix[worst]) if pix is not None else worst
+    print(f"[parity] {name}: worst pixel {wpix} gpu={img[worst]} oracle={ref.rgba[worst]} "
+          f"gpu_depth={depth[worst]:.6f} oracle_depth={ref.depth[worst]:.6f} "
+          f"oracle_nseg={ref.n_segments[worst]}", flush=True)
+    assert err.max() <= RGBA_TOL, (name, err.max(), wpix)
+    assert rel.max() <= DEPTH_REL_TOL, (name, rel.max())
+    # a coverage mismatch is allowed only where the oracle's opacity is negligible
+    mism = np.isfinite(depth) != np.isfinite(ref.depth)
+    assert (ref.rgba[mism, 3] <= RGBA_TOL).all()
+
+
+def test_config1_fp64_full_image(renderer):
+    sc = make_config(1)
+    cam = sc.cameras[0]
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp64", rk_tol=1e-6)
+    ref = oracle.render(sc, cam, sc.tf)
+    _compare("config1 fp64 64x64", img, depth, ref, scale=sc.scale)
+    assert st["anomalies"] == 0 and st["fragment_overflow"] == 0 and st["segment_overflow"] == 0
+
+
+def test_config1_fp32_full_image(renderer):
+    sc = make_config(1)
+    cam = sc.cameras[0]
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32", rk_tol=1e-6)
+    ref = oracle.render(sc, cam, sc.tf)
+    _compare("config1 fp32 64x64", img, depth, ref, scale=sc.scale)
+
+
+def _box_chord(o, d):
+    t0, t1 = -np.inf, np.inf
+    for c in range(3):
+        a, b = (0 - o[c]) / d[c], (1 - o[c]) / d[c]
+        t0, t1 = max(t0, min(a, b)), min(t1, max(a, b))
+    return (t0, t1) if t1 > max(t0, 0) else (None, None)
+
+
+def test_constant_field_closed_form(renderer):
+    """Constant rho: alpha = 1 - exp(-kappa L), RGB = E alpha; L and the entry depth
+    from the ray-box closed form (config 1's boundary is the unit cube)."""
+    sc = make_config(1)
+    P = sc.patches[0]
+    Pc = Patch(P.degree, P.ncp, P.knots, P.cp, np.full_like(P.scalar, 0.37), False)
+    tf = TransferFunction(sc.tf.x, sc.tf.rgba, 4.0, (0.0, 1.0))
+    cam = camera_from_angles([0.5, 0.5, 0.5], 3.0, 30.0, 20.0, 40, 40)
+    img, depth, _ = _render(renderer, [Pc], cam, tf, precision="fp32")
+    E = np.array([np.interp(0.37, tf.x, tf.rgba[:, c]) for c in range(4)])
+    kappa = 4.0 * E[3]
+    worst = 0.0
+    for pix in range(40 * 40):
+        o, d = oracle.camera_ray(cam, pix % 40 + 0.5, pix // 40 + 0.5)
+        t0, t1 = _box_chord(o, d)
+        if t0 is None:
+            assert img[pix, 3] == 0.0 and np.isinf(depth[pix])
+            continue
+        a = 1.0 - math.exp(-kappa * (t1 - t0))
+        worst = max(worst, abs(img[pix, 3] - a), np.abs(img[pix, :3] - E[:3] * a).max())
+        assert abs(depth[pix] - t0) <= DEPTH_REL_TOL * t0
+    print(f"[parity] constant field closed form: max err {worst:.3e}", flush=True)
+    assert worst <= RGBA_TOL
+
+
+@pytest.mark.parametrize("view", [0, 1, 2])
+def test_config2_twisted_bar_sampled(renderer, view):
+    sc = make_config(2)
+    cam = sc.cameras[view]
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32", rk_tol=1e-5)
+    pix = _sample(cam, depth, 512, 256, 20 + view)
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    _compare(f"config2 view{view} 512x512", img, depth, ref, pix, sc.scale)
+    assert st["segment_overflow"] == 0
+
+
+def test_config3_bent_beam_1080p_sampled(renderer):
+    sc = make_config(3)
+    cam = sc.cameras[0]
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32")
+    pix = _sample(cam, depth, 768, 256, 31)
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    _compare("config3 1920x1080", img, depth, ref, pix, sc.scale)
+    print(f"[stats] config3: {st}", flush=True)
+    assert st["fragment_overflow"] == 0 and st["segment_overflow"] == 0
+
+
+def test_config4_nurbs_channel_1080p_sampled(renderer):
+    sc = make_config(4)
+    cam = sc.cameras[0]
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32")
+    pix = _sample(cam, depth, 512, 256, 41)
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    _compare("config4 1920x1080", img, depth, ref, pix, sc.scale)
+    print(f"[stats] config4: {st}", flush=True)
+
+
+@pytest.mark.parametrize("size", [(1, 1), (67, 35), (8, 8)])
+def test_ragged_and_tiny_images(renderer, size):
+    sc = make_config(1)
+    w, h = size
+    cam = camera_from_angles([0.5, 0.5, 0.5], 3.0, 30.0, 20.0, w, h)
+    img, depth, _ = _render(renderer, sc.patches, cam, sc.tf, precision="fp32")
+    ref = oracle.render(sc, cam, sc.tf)
+    _compare(f"config1 {w}x{h}", img, depth, ref, scale=sc.scale)
+
+
+def test_view_that_misses_everything(renderer):
+    sc = make_config(1)
+    # eye between the block and the target: every ray points away from the block
+    cam = camera_from_angles([5.0, 5.0, 5.0], 1.0, 225.0, -35.0, 32, 32)
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf)
+    assert (img == 0).all() and np.isinf(depth).all() and st["segments"] == 0
+
+
+def test_render_is_deterministic(renderer):
+    sc = make_config(3, 320, 180)
+    cam = sc.cameras[1]
+    a, da, _ = _render(renderer, sc.patches, cam, sc.tf)
+    b, db, _ = _render(renderer, sc.patches, cam, sc.tf)
+    assert np.array_equal(a, b) and np.array_equal(da, db)
+
+
+def test_error_codes(renderer):
+    from paper_1404_3363_amd import IvrError
+    sc = make_config(1)
+    P = sc.patches[0]
+    bad = Patch(P.degree, P.ncp, [P.knots[0][::-1], P.knots[1], P.knots[2]], P.cp, P.scalar)
+    with pytest.raises(IvrError) as e:
+        renderer.upload([bad])
+    assert e.value.code == -1
+    renderer.upload(sc.patches)
+    with pytest.raises(IvrError) as e:
+        renderer.render(sc.cameras[0], sc.tf, seed_mode="mlp")
+    assert e.value.code in (-4,)
+    bad_tf = TransferFunction(np.array([0.0, 0.7, 0.5, 1.0]), np.ones((4, 4)), 1.0, (0.0, 1.0))
+    with pytest.raises(IvrError) as e:
+        renderer.render(sc.cameras[0], bad_tf)
+    assert e.value.code == -1
