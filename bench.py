@@ -1,0 +1,170 @@
+"""Benchmark: Mrays/s at 1920x1080 on the 64-patch cubic bent beam (config 3).
+
+One step = one ivr_render of the view: boundary crossings and blockwise pairing,
+RKF45 integration with sampling and compositing, per-pixel merge.  The model is
+uploaded once (outside the timed region).  Every pixel counts as a ray.
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(algorithmic FP32 work per launch from the device counters times per-unit
+operation counts, divided by its average HIP-event duration over the timed
+steps) and the FP64 oracle timed on the host cores over a bounded pixel sample
+(whose parity against the GPU image is reported too).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s at 1080p, RGBA err ≤1e-3 vs FP64 oracle; MLP-seeded vs plain Newton"
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32, published (packed); 78.6 without packing
+
+
+def basis_flops(p):
+    """Triangular evaluation of the p+1 basis functions and first derivatives on a span."""
+    return 2 * p + 2.5 * p * (p + 1) + 6 * (p + 1)
+
+
+def contraction_flops(p, nc):
+    """Sum-factorised phi and its 3 partials over (p+1)^3 points, nc channels (FMA = 2)."""
+    q = p + 1
+    return 2 * (q ** 3 * 2 * nc + q ** 2 * 3 * nc + q * 4 * nc)
+
+
+def unit_flops(p, rational):
+    nc = 4 if rational else 3
+    q = p + 1
+    quotient = 25 if rational else 0
+    return {
+        # phi, J_phi, V = V_par + c V_perp and the 3x3 solve of J W = V
+        "w_eval": 3 * basis_flops(p) + contraction_flops(p, nc) + quotient + 80,
+        # rho and its parameter gradient in the first stage, plus d rho/ds
+        "stage1_rho": 2 * (q ** 3 * 2 + q ** 2 * 3 + q * 3) + 5,
+        # stage arguments, 5th-order update, error norm, step control
+        "rk_step": 200,
+        # Hermite value, transfer function, exp, front-to-back update
+        "subsample": 25,
+        # one FP32 face Newton iteration: bivariate value+2 partials, 3x3 solve
+        "face_iter": 2 * basis_flops(p) + 2 * (q ** 2 * 2 * nc + q * 3 * nc) + 70,
+        "box_test": 30,
+    }
+
+
+def kernel_flops(st, p, rational):
+    u = unit_flops(p, rational)
+    stage1 = max(st["w_evals"] - 5 * st["rk_steps"], 0)
+    k2 = (st["w_evals"] * u["w_eval"] + stage1 * u["stage1_rho"] + st["rk_steps"] * u["rk_step"] +
+          st["subsamples"] * u["subsample"])
+    k1 = (st["box_tests"] * u["box_test"] + st["face_newton_iter"] * u["face_iter"] +
+          st["fp64_polish_iter"] * u["face_iter"] + st["segments"] * (u["w_eval"] + u["stage1_rho"]))
+    return {"k_fragments": k1, "k_integrate": k2}
+
+
+def cpu_baseline(sc, cam, gpu_rgba, seconds_target=15.0, seed=7):
+    import oracle
+    rng = np.random.default_rng(seed)
+    npx = cam.width * cam.height
+    prep = oracle.OracleScene(sc.patches, sc.scale)
+    nthreads = min(16, os.cpu_count() or 1)
+    n = 512
+    pix = rng.choice(npx, n, replace=False)
+    t0 = time.perf_counter()
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix, prepared=prep, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    if dt < seconds_target / 4:
+        n = int(min(npx, max(n, n * seconds_target / max(dt, 1e-3))))
+        pix = rng.choice(npx, n, replace=False)
+        t0 = time.perf_counter()
+        ref = oracle.render(sc, cam, sc.tf, pixels=pix, prepared=prep, nthreads=nthreads)
+        dt = time.perf_counter() - t0
+    err = float(np.abs(gpu_rgba[pix] - ref.rgba).max())
+    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n} uniformly drawn pixels of the same 1920x1080 view, {dt:.1f} s"}, \
+        {"pixels": n, "max_abs_rgba_vs_oracle": err}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--view", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the path shards by image tiles or "
+              "views; see DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from scenes import make_config
+    from paper_1404_3363_amd import Renderer, default_opts
+
+    sc = make_config(3)
+    cam = sc.cameras[args.view]
+    r = Renderer(0)
+    r.upload(sc.patches)
+    dev = torch.device("cuda", 0)
+    rgba = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=dev)
+    depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device=dev)
+    opts = default_opts()
+    for _ in range(args.warmup):
+        r.render(cam, sc.tf, opts=opts, rgba=rgba, depth=depth)
+    torch.cuda.synchronize()
+    r.phase_times()                      # clear
+    topts = default_opts(timing=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r.render(cam, sc.tf, opts=topts, rgba=rgba, depth=depth)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    phases = r.phase_times()             # (steps, 3) ms from HIP events on the render stream
+    ms_step = 1e3 * elapsed / args.steps
+    rays = cam.width * cam.height
+    value = rays * args.steps / elapsed / 1e6
+
+    # counters of one render (deterministic work) -> algorithmic FLOPs per launch
+    _, _, st = r.render(cam, sc.tf, opts=opts, rgba=rgba, depth=depth, stats=True)
+    torch.cuda.synchronize()
+    flops = kernel_flops(st, 3, False)
+    avg_ms = {"k_fragments": float(phases[:, 0].mean()), "k_integrate": float(phases[:, 1].mean()),
+              "k_merge": float(phases[:, 2].mean())}
+    dom = max(("k_fragments", "k_integrate"), key=lambda k: avg_ms[k])
+    achieved = flops[dom] / (avg_ms[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "avg_ms": {k: round(v, 4) for k, v in avg_ms.items()},
+                "algorithmic_gflop_per_launch": {k: round(v / 1e9, 3) for k, v in flops.items()}}
+
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "config3: bent beam, 64 cubic B-spline patches of 10^3 control "
+                                  "points, 3-Gaussian+ramp field, 8-knot transfer function, "
+                                  f"1920x1080 view {args.view}",
+                      "width": cam.width, "height": cam.height, "patches": len(sc.patches),
+                      "rk_tol": opts.rk_tol, "rho_interp": "hermite", "n_super": opts.n_super},
+           "roofline": roofline,
+           "counters": {k: st[k] for k in ("segments", "fragments", "anomalies", "rk_steps",
+                                           "rk_rejected", "samples", "w_evals", "subsamples",
+                                           "face_newton", "face_newton_iter", "fp64_polish_iter",
+                                           "box_tests")}}
+    if not args.no_cpu_baseline:
+        img = rgba.cpu().numpy().reshape(-1, 4).astype(np.float64)
+        cpu, parity = cpu_baseline(sc, cam, img)
+        out["cpu_baseline"] = cpu
+        out["parity_sample"] = parity
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

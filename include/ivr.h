@@ -104,6 +104,8 @@ typedef struct {
     double early_term;          /* stop a segment once alpha >= 1-early_term [1e-4]*/
     int32_t max_newton_iter;    /* FP32 Newton iterations per face root     [16]  */
     int32_t rho_interp;         /* IVR_RHO_*: rho between two samples  [HERMITE] */
+    int32_t timing;             /* 1: record HIP events around every phase of
+                                   this render for ivr_phase_times (no sync) [0] */
 } ivr_render_opts;
 
 /* Counters of one render (filled when a non-NULL ivr_stats* is passed; that
@@ -126,6 +128,7 @@ typedef struct {
     uint64_t fp64_solves;       /* 3x3 solves done in FP64 (small det J)         */
     uint64_t rk_iter_cap;       /* segments stopped at the iteration cap         */
     uint64_t mlp_queries;       /* MLP seed evaluations                          */
+    uint64_t subsamples;        /* supersampling sub-steps (transfer function)   */
     double ms_fragments, ms_integrate, ms_merge;  /* event times per phase      */
 } ivr_stats;
 
@@ -154,6 +157,12 @@ ivr_status ivr_upload_patches(ivr_ctx *ctx, const ivr_patch_desc *patches, int32
 ivr_status ivr_render(ivr_ctx *ctx, const ivr_camera *cam, const ivr_transfer_fn *tf,
                       const ivr_render_opts *opts, float *rgba_dev, float *depth_dev,
                       ivr_stats *stats);
+
+/* Phase times of the renders recorded with opts->timing = 1 since the last call:
+ * waits for them, writes up to `cap` triples (fragments, integrate, merge) in
+ * milliseconds to ms_out (3*cap doubles), the number of renders to *n_out, and
+ * forgets them.  At most 4096 renders are kept (IVR_EOVERFLOW past that). */
+ivr_status ivr_phase_times(ivr_ctx *ctx, double *ms_out, int32_t cap, int32_t *n_out);
 
 /* Message for the last failing call of this context ("" if none). */
 const char *ivr_last_error(const ivr_ctx *ctx);

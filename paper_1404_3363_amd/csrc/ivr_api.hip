@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -31,6 +32,7 @@ struct ivr_ctx {
     float *d_knots32 = nullptr;
     double *d_knots64 = nullptr;
     FaceElem *d_elems = nullptr;
+    FaceTile *d_tiles = nullptr;
     int npatch = 0, nelem = 0;
     double scale = 1.0;
     uint32_t class_mask = 0;
@@ -43,6 +45,9 @@ struct ivr_ctx {
     QueueState *d_qs = nullptr;
     unsigned long long *d_ctr = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // phase events of renders recorded with opts.timing (4 per render)
+    std::vector<hipEvent_t> tev;
+    int n_timed = 0;
 };
 
 namespace {
@@ -235,13 +240,11 @@ static void bezier_net(const double *ta, const double *tb, int sa, int sb, int p
 // Axes: the averaged edge directions of the net in a and b, orthonormalised,
 // and their normal; extents from projecting every point, padded.  Falls back
 // to the coordinate axes if an edge direction degenerates.
-static void build_obb(FaceElem &E, const double (*net)[4], int p, double pad) {
-    auto at = [&](int ia, int jb, double *o) {
-        const double *h = net[jb * (p + 1) + ia];
-        for (int q = 0; q < 3; ++q) o[q] = h[q] / h[3];
-    };
-    double u[3] = {0, 0, 0}, v[3] = {0, 0, 0}, c00[3], c10[3], c01[3], c11[3];
-    at(0, 0, c00); at(p, 0, c10); at(0, p, c01); at(p, p, c11);
+// Box axes come from the four corner points (c00, c10 along a, c01 along b, c11).
+template <typename Box3>
+static void build_obb(Box3 &E, const std::vector<std::array<double, 3>> &pts, const double *c00,
+                      const double *c10, const double *c01, const double *c11, double pad) {
+    double u[3] = {0, 0, 0}, v[3] = {0, 0, 0};
     for (int q = 0; q < 3; ++q) {
         u[q] = 0.5 * (c10[q] - c00[q] + c11[q] - c01[q]);
         v[q] = 0.5 * (c01[q] - c00[q] + c11[q] - c10[q]);
@@ -269,15 +272,11 @@ static void build_obb(FaceElem &E, const double (*net)[4], int p, double pad) {
             for (int q = 0; q < 3; ++q) ax[r][q] = r == q ? 1.0 : 0.0;
     }
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int jb = 0; jb <= p; ++jb)
-        for (int ia = 0; ia <= p; ++ia) {
-            double P[3];
-            at(ia, jb, P);
-            for (int r = 0; r < 3; ++r) {
-                const double pr = ax[r][0] * P[0] + ax[r][1] * P[1] + ax[r][2] * P[2];
-                lo[r] = std::min(lo[r], pr);
-                hi[r] = std::max(hi[r], pr);
-            }
+    for (const auto &P : pts)
+        for (int r = 0; r < 3; ++r) {
+            const double pr = ax[r][0] * P[0] + ax[r][1] * P[1] + ax[r][2] * P[2];
+            lo[r] = std::min(lo[r], pr);
+            hi[r] = std::max(hi[r], pr);
         }
     for (int q = 0; q < 3; ++q) {
         double cq = 0;
@@ -343,7 +342,7 @@ const char *ivr_last_error(const ivr_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 static void free_model(ivr_ctx *c) {
     dfree(c->d_patches); dfree(c->d_cp32); dfree(c->d_rho32); dfree(c->d_cp64); dfree(c->d_rho64);
-    dfree(c->d_knots32); dfree(c->d_knots64); dfree(c->d_elems);
+    dfree(c->d_knots32); dfree(c->d_knots64); dfree(c->d_elems); dfree(c->d_tiles);
     c->has_model = false;
 }
 
@@ -361,6 +360,8 @@ void ivr_destroy(ivr_ctx *c) {
     dfree(c->d_qs);
     dfree(c->d_ctr);
     for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->tev)
         if (e) (void)hipEventDestroy(e);
     delete c;
 }
@@ -391,6 +392,7 @@ ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t
     std::vector<double4> cp64;
     std::vector<double> rho64, knots64;
     std::vector<FaceElem> elems;
+    std::vector<FaceTile> tiles;
     uint32_t class_mask = 0;
     for (int pi = 0; pi < n; ++pi) {
         const auto &P = patches[pi];
@@ -452,31 +454,58 @@ ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t
             for (int jb = 0; jb < P.ncp[db]; ++jb)
                 for (int ia = 0; ia < P.ncp[da]; ++ia) fb.add(at(ia, jb));
             fb.store(D.fbox[f], pad);
-            for (int sb = p; sb < P.ncp[db]; ++sb) {
-                if (!(tn[db][sb] < tn[db][sb + 1])) continue;
-                for (int sa = p; sa < P.ncp[da]; ++sa) {
-                    if (!(tn[da][sa] < tn[da][sa + 1])) continue;
-                    FaceElem E;
-                    std::memset(&E, 0, sizeof E);
-                    double net[(kMaxDegree + 1) * (kMaxDegree + 1)][4];
-                    auto hq = [&](int ia, int jb, double *o) {
-                        const double *cc = at(ia, jb);
-                        const double w = P.rational ? cc[3] : 1.0;
-                        o[0] = w * cc[0]; o[1] = w * cc[1]; o[2] = w * cc[2]; o[3] = w;
-                    };
-                    bezier_net(tn[da].data(), tn[db].data(), sa, sb, p, hq, net);
-                    build_obb(E, net, p, pad);
-                    E.a0 = (float)tn[da][sa];
-                    E.a1 = (float)tn[da][sa + 1];
-                    E.b0 = (float)tn[db][sb];
-                    E.b1 = (float)tn[db][sb + 1];
-                    E.face = f;
-                    E.patch = pi;
-                    elems.push_back(E);
+            std::vector<int> spa, spb;   // non-empty spans in a and b
+            for (int sa = p; sa < P.ncp[da]; ++sa)
+                if (tn[da][sa] < tn[da][sa + 1]) spa.push_back(sa);
+            for (int sb = p; sb < P.ncp[db]; ++sb)
+                if (tn[db][sb] < tn[db][sb + 1]) spb.push_back(sb);
+            auto hq = [&](int ia, int jb, double *o) {
+                const double *cc = at(ia, jb);
+                const double w = P.rational ? cc[3] : 1.0;
+                o[0] = w * cc[0]; o[1] = w * cc[1]; o[2] = w * cc[2]; o[3] = w;
+            };
+            D.tile_off[f] = (int)tiles.size();
+            for (size_t tb = 0; tb < spb.size(); tb += kTile)
+                for (size_t ta = 0; ta < spa.size(); ta += kTile) {
+                    FaceTile T;
+                    std::memset(&T, 0, sizeof T);
+                    T.elem_begin = (int)elems.size();
+                    std::vector<std::array<double, 3>> tpts;
+                    double corner[4][3];
+                    const size_t ea1 = std::min(spa.size(), ta + kTile), eb1 = std::min(spb.size(), tb + kTile);
+                    for (size_t ib = tb; ib < eb1; ++ib)
+                        for (size_t ia = ta; ia < ea1; ++ia) {
+                            const int sa = spa[ia], sb = spb[ib];
+                            double net[(kMaxDegree + 1) * (kMaxDegree + 1)][4];
+                            bezier_net(tn[da].data(), tn[db].data(), sa, sb, p, hq, net);
+                            std::vector<std::array<double, 3>> pts;
+                            for (int k = 0; k < (p + 1) * (p + 1); ++k)
+                                pts.push_back({net[k][0] / net[k][3], net[k][1] / net[k][3], net[k][2] / net[k][3]});
+                            FaceElem E;
+                            std::memset(&E, 0, sizeof E);
+                            build_obb(E, pts, pts[0].data(), pts[p].data(), pts[p * (p + 1)].data(),
+                                      pts[(p + 1) * (p + 1) - 1].data(), pad);
+                            E.a0 = (float)tn[da][sa];
+                            E.a1 = (float)tn[da][sa + 1];
+                            E.b0 = (float)tn[db][sb];
+                            E.b1 = (float)tn[db][sb + 1];
+                            E.face = f;
+                            E.patch = pi;
+                            elems.push_back(E);
+                            tpts.insert(tpts.end(), pts.begin(), pts.end());
+                            if (ia == ta && ib == tb) std::memcpy(corner[0], pts[0].data(), sizeof corner[0]);
+                            if (ia + 1 == ea1 && ib == tb) std::memcpy(corner[1], pts[p].data(), sizeof corner[1]);
+                            if (ia == ta && ib + 1 == eb1) std::memcpy(corner[2], pts[p * (p + 1)].data(), sizeof corner[2]);
+                            if (ia + 1 == ea1 && ib + 1 == eb1)
+                                std::memcpy(corner[3], pts[(p + 1) * (p + 1) - 1].data(), sizeof corner[3]);
+                        }
+                    T.elem_end = (int)elems.size();
+                    build_obb(T, tpts, corner[0], corner[1], corner[2], corner[3], pad);
+                    tiles.push_back(T);
                 }
-            }
         }
         D.elem_off[6] = (int)elems.size();
+        D.tile_off[6] = (int)tiles.size();
     }
     // allocate and copy, then swap in
     ivr_ctx tmp;
@@ -487,7 +516,7 @@ ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t
     };
     bool ok = up(tmp.d_patches, hp) && up(tmp.d_cp32, cp32) && up(tmp.d_rho32, rho32) &&
               up(tmp.d_cp64, cp64) && up(tmp.d_rho64, rho64) && up(tmp.d_knots32, knots32) &&
-              up(tmp.d_knots64, knots64) && up(tmp.d_elems, elems);
+              up(tmp.d_knots64, knots64) && up(tmp.d_elems, elems) && up(tmp.d_tiles, tiles);
     if (!ok) {
         free_model(&tmp);
         return fail(c, IVR_ENOMEM, "device allocation for the model failed");
@@ -496,7 +525,8 @@ ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t
     free_model(c);
     c->d_patches = tmp.d_patches; c->d_cp32 = tmp.d_cp32; c->d_rho32 = tmp.d_rho32;
     c->d_cp64 = tmp.d_cp64; c->d_rho64 = tmp.d_rho64; c->d_knots32 = tmp.d_knots32;
-    c->d_knots64 = tmp.d_knots64; c->d_elems = tmp.d_elems;
+    c->d_knots64 = tmp.d_knots64; c->d_elems = tmp.d_elems; c->d_tiles = tmp.d_tiles;
+    tmp.d_tiles = nullptr;
     tmp.d_patches = nullptr; tmp.d_cp32 = nullptr; tmp.d_rho32 = nullptr; tmp.d_cp64 = nullptr;
     tmp.d_rho64 = nullptr; tmp.d_knots32 = nullptr; tmp.d_knots64 = nullptr; tmp.d_elems = nullptr;
     c->npatch = n;
@@ -668,24 +698,39 @@ ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *
     Model m;
     m.patches = c->d_patches; m.cp32 = c->d_cp32; m.rho32 = c->d_rho32; m.cp64 = c->d_cp64;
     m.rho64 = c->d_rho64; m.knots32 = c->d_knots32; m.knots64 = c->d_knots64; m.elems = c->d_elems;
+    m.tiles = c->d_tiles;
     m.npatch = c->npatch; m.scale = (float)c->scale; m.scaled = c->scale;
+    // events for this render: the stats set, or the next timing slot
+    hipEvent_t *ev = nullptr;
+    if (stats) {
+        ev = c->ev;
+    } else if (o.timing) {
+        if (c->n_timed >= 4096) return fail(c, IVR_EOVERFLOW, "more than 4096 timed renders pending");
+        while ((int)c->tev.size() < 4 * (c->n_timed + 1)) {
+            hipEvent_t e;
+            IVR_HIP(c, hipEventCreate(&e));
+            c->tev.push_back(e);
+        }
+        ev = &c->tev[4 * c->n_timed];
+        ++c->n_timed;
+    }
     IVR_HIP(c, hipMemsetAsync(c->d_qs, 0, sizeof(QueueState), c->stream));
     if (stats) IVR_HIP(c, hipMemsetAsync(c->d_ctr, 0, sizeof(unsigned long long) * C_COUNT, c->stream));
-    if (stats) IVR_HIP(c, hipEventRecord(c->ev[0], c->stream));
+    if (ev) IVR_HIP(c, hipEventRecord(ev[0], c->stream));
     IVR_HIP(c, launch_fragments(fp64, m, fp, c->d_segs, (uint32_t)c->seg_cap, c->d_queues,
                                 (uint32_t)c->seg_cap, c->class_mask, c->d_qs, c->d_pixseg, depth_dev,
                                 c->d_ctr, c->stream));
-    if (stats) IVR_HIP(c, hipEventRecord(c->ev[1], c->stream));
+    if (ev) IVR_HIP(c, hipEventRecord(ev[1], c->stream));
     for (int k = 0; k < kClasses; ++k) {
         if (!((c->class_mask >> k) & 1)) continue;
         IVR_HIP(c, launch_integrate(fp64, k, m, fp, c->d_segs, c->d_queues + (size_t)k * c->seg_cap,
                                     c->d_qs, &c->d_qs->qnext[k], c->d_results, c->d_ctr, c->n_cu,
                                     c->stream));
     }
-    if (stats) IVR_HIP(c, hipEventRecord(c->ev[2], c->stream));
+    if (ev) IVR_HIP(c, hipEventRecord(ev[2], c->stream));
     IVR_HIP(c, launch_merge(fp, c->d_pixseg, c->d_results, rgba_dev, c->stream));
+    if (ev) IVR_HIP(c, hipEventRecord(ev[3], c->stream));
     if (stats) {
-        IVR_HIP(c, hipEventRecord(c->ev[3], c->stream));
         unsigned long long h[C_COUNT];
         IVR_HIP(c, hipMemcpyAsync(h, c->d_ctr, sizeof h, hipMemcpyDeviceToHost, c->stream));
         IVR_HIP(c, hipStreamSynchronize(c->stream));
@@ -700,6 +745,24 @@ ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *
         IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
         stats->ms_merge = ms;
     }
+    c->err.clear();
+    return IVR_OK;
+}
+
+ivr_status ivr_phase_times(ivr_ctx *c, double *ms_out, int32_t cap, int32_t *n_out) {
+    if (!c || !n_out || cap < 0 || (cap > 0 && !ms_out)) return fail(c, IVR_EINVAL, "bad arguments");
+    IVR_HIP(c, hipSetDevice(c->device));
+    const int n = c->n_timed;
+    for (int r = 0; r < n && r < cap; ++r) {
+        IVR_HIP(c, hipEventSynchronize(c->tev[4 * r + 3]));
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            IVR_HIP(c, hipEventElapsedTime(&ms, c->tev[4 * r + k], c->tev[4 * r + k + 1]));
+            ms_out[3 * r + k] = ms;
+        }
+    }
+    *n_out = n;
+    c->n_timed = 0;
     c->err.clear();
     return IVR_OK;
 }

@@ -81,10 +81,13 @@ struct Frag {
     int entering;
 };
 
-// Ray against the oriented box of a face element.
-__device__ __forceinline__ bool obb_hit(const FaceElem &E, const float (&o)[3], const float (&d)[3]) {
+// Ray (t >= 0) against an oriented box; [tmin, tmax] is the ray's interval inside.
+template <typename Box3>
+__device__ __forceinline__ bool obb_hit(const Box3 &E, const float (&o)[3], const float (&d)[3],
+                                        float &tmin, float &tmax) {
     const float oc[3] = {o[0] - E.c[0], o[1] - E.c[1], o[2] - E.c[2]};
-    float tmin = 0.f, tmax = INFINITY;
+    tmin = 0.f;
+    tmax = INFINITY;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         const float po = E.ax[r][0] * oc[0] + E.ax[r][1] * oc[1] + E.ax[r][2] * oc[2];
@@ -95,6 +98,12 @@ __device__ __forceinline__ bool obb_hit(const FaceElem &E, const float (&o)[3], 
         tmax = fminf(tmax, fmaxf(t0, t1));
     }
     return tmin <= tmax;
+}
+
+template <typename Box3>
+__device__ __forceinline__ bool obb_hit(const Box3 &E, const float (&o)[3], const float (&d)[3]) {
+    float t0, t1;
+    return obb_hit(E, o, d, t0, t1);
 }
 
 template <typename R>
@@ -120,40 +129,71 @@ __device__ __forceinline__ int facing(int face, float orient, const R (&Sa)[3], 
     return (side * sigma * g * R(orient)) > R(0);
 }
 
-// Boundary roots seeded at the centre of element E: Newton on
-// S_f(a,b) - (o + t d) = 0 (Eqs. (F), (newtonsmethod) restricted to the face) in
-// precision RN; a root that converges anywhere on the face and is new for this
-// ray is refined in FP64 and inserted into the depth-sorted fragment list.
+// Newton on S_f(a,b) - (o + t d) = 0 (Eqs. (F), (newtonsmethod) restricted to
+// the face) in precision RN from (a, b); true when it converges.
 template <int P, bool RAT, typename RN>
-__device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E, const double (&od)[3],
-                          const double (&dd)[3], const FrameParams &fp, Frag<RN> *fr, int &nfr,
-                          u32 &n_iter, u32 &n_polish, u32 &n_ovf) {
-    const int face = E.face;
-    const PatchView<RN> pv = view_of<RN>(Pd);
-    const Arrays<RN> ar = arrays_of(m, RN(0));
-    const RN o[3] = {RN(od[0]), RN(od[1]), RN(od[2])}, d[3] = {RN(dd[0]), RN(dd[1]), RN(dd[2])};
-    RN a = RN(0.5) * (RN(E.a0) + RN(E.a1)), b = RN(0.5) * (RN(E.b0) + RN(E.b1));
-    RN S[3], Sa[3], Sb[3];
+__device__ __forceinline__ bool face_newton(const PatchView<RN> &pv, const Arrays<RN> &ar, int face,
+                                            const RN (&o)[3], const RN (&d)[3], RN tol, int max_it,
+                                            RN &a, RN &b, RN &t, RN (&Sa)[3], RN (&Sb)[3], u32 &n_iter) {
+    RN S[3];
     eval_face<P, RAT, RN>(pv, ar, face, a, b, S, Sa, Sb);
-    RN t = (S[0] - o[0]) * d[0] + (S[1] - o[1]) * d[1] + (S[2] - o[2]) * d[2];
-    const RN tol = (sizeof(RN) == 4 ? RN(2e-6) : RN(1e-12)) * RN(fp.scaled);
-    bool conv = false;
-    for (int it = 0; it < fp.max_newton; ++it) {
+    t = (S[0] - o[0]) * d[0] + (S[1] - o[1]) * d[1] + (S[2] - o[2]) * d[2];
+    for (int it = 0; it < max_it; ++it) {
         ++n_iter;
         RN F[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) F[q] = S[q] - o[q] - t * d[q];
-        if (dot3(F, F) <= tol * tol) {
-            conv = true;
-            break;
-        }
+        if (dot3(F, F) <= tol * tol) return true;
         RN nd[3] = {-d[0], -d[1], -d[2]}, rhs[3] = {-F[0], -F[1], -F[2]}, st[3];
         solve_cols(Sa, Sb, nd, rhs, st);
         a += st[0];
         b += st[1];
         t += st[2];
-        if (!(a >= RN(-1) && a <= RN(2) && b >= RN(-1) && b <= RN(2))) return;
+        if (!(a >= RN(-1) && a <= RN(2) && b >= RN(-1) && b <= RN(2))) return false;
         eval_face<P, RAT, RN>(pv, ar, face, a, b, S, Sa, Sb);
+    }
+    return false;
+}
+
+// Boundary roots from one candidate element E.  Seeds: the point of the ray in
+// the middle of its passage through E's box, mapped to (a, b) through the box
+// axes; if Newton does not converge from it, the element centre and its four
+// quarter points.  A root that converges anywhere on the face and is new for
+// this ray is refined in FP64 and inserted into the depth-sorted fragment list.
+template <int P, bool RAT, typename RN>
+__device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E, const double (&od)[3],
+                          const double (&dd)[3], const float (&of)[3], const float (&df)[3],
+                          const FrameParams &fp, Frag<RN> *fr, int &nfr, u32 &n_iter,
+                          u32 &n_polish, u32 &n_ovf) {
+    const int face = E.face;
+    const PatchView<RN> pv = view_of<RN>(Pd);
+    const Arrays<RN> ar = arrays_of(m, RN(0));
+    const RN o[3] = {RN(od[0]), RN(od[1]), RN(od[2])}, d[3] = {RN(dd[0]), RN(dd[1]), RN(dd[2])};
+    const RN tol = (sizeof(RN) == 4 ? RN(2e-6) : RN(1e-12)) * RN(fp.scaled);
+    const RN ac = RN(0.5) * (RN(E.a0) + RN(E.a1)), bc = RN(0.5) * (RN(E.b0) + RN(E.b1));
+    const RN ha = RN(0.5) * (RN(E.a1) - RN(E.a0)), hb = RN(0.5) * (RN(E.b1) - RN(E.b0));
+    RN a, b, t, Sa[3], Sb[3];
+    bool conv = false;
+    for (int seed = 0; seed < 6 && !conv; ++seed) {
+        if (seed == 0) {
+            float t0, t1;
+            obb_hit(E, of, df, t0, t1);
+            const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
+            float x[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) x[q] = of[q] + tm * df[q] - E.c[q];
+            const float xu = (E.ax[0][0] * x[0] + E.ax[0][1] * x[1] + E.ax[0][2] * x[2]) / E.ext[0];
+            const float xv = (E.ax[1][0] * x[0] + E.ax[1][1] * x[1] + E.ax[1][2] * x[2]) / E.ext[1];
+            a = ac + ha * RN(fminf(fmaxf(xu, -1.f), 1.f));
+            b = bc + hb * RN(fminf(fmaxf(xv, -1.f), 1.f));
+        } else if (seed == 1) {
+            a = ac;
+            b = bc;
+        } else {
+            a = ac + ha * RN((seed & 1) ? -0.5 : 0.5);
+            b = bc + hb * RN((seed & 2) ? -0.5 : 0.5);
+        }
+        conv = face_newton<P, RAT, RN>(pv, ar, face, o, d, tol, fp.max_newton, a, b, t, Sa, Sb, n_iter);
     }
     const RN mg = RN(1e-4);
     if (!conv || !(a >= -mg && a <= RN(1) + mg && b >= -mg && b <= RN(1) + mg && t > RN(0))) return;
@@ -210,15 +250,16 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
 template <typename R>
 __device__ __forceinline__ void face_root_any(const Model &m, const DevPatch &Pd, const FaceElem &E,
                                               const double (&od)[3], const double (&dd)[3],
+                                              const float (&of)[3], const float (&df)[3],
                                               const FrameParams &fp, Frag<R> *fr, int &nfr, u32 &ni,
                                               u32 &np, u32 &no) {
     switch (Pd.deg * 2 + Pd.rational) {
-    case 2: face_root<1, false, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
-    case 3: face_root<1, true, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
-    case 4: face_root<2, false, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
-    case 5: face_root<2, true, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
-    case 6: face_root<3, false, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
-    default: face_root<3, true, R>(m, Pd, E, od, dd, fp, fr, nfr, ni, np, no); break;
+    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
+    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
+    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
+    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
+    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
+    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
     }
 }
 
@@ -282,7 +323,8 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
             if (k < ncand) {
                 const FaceElem E = m.elems[cand[k]];
                 ++c_newton;
-                face_root_any<R>(m, m.patches[E.patch], E, od, dd, fp, fr, nfr, c_iter, c_pol, c_fovf);
+                face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, fr, nfr, c_iter, c_pol,
+                                 c_fovf);
             }
         }
         ncand = 0;
@@ -296,10 +338,16 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
             c_box += hp;
             const bool hf = hp && slab(of, inv, Pd.fbox[f], Pd.fbox[f] + 3);
             if (__ballot(hf) == 0) continue;
-            for (int e = Pd.elem_off[f]; e < Pd.elem_off[f + 1]; ++e) {
+            for (int ti = Pd.tile_off[f]; ti < Pd.tile_off[f + 1]; ++ti) {
+                const FaceTile &T = m.tiles[ti];
                 c_box += hf;
-                if (hf && obb_hit(m.elems[e], of, df)) cand[ncand++] = (u32)e;
-                if (__ballot(ncand == kCandCap) != 0) solve_candidates();
+                const bool ht = hf && obb_hit(T, of, df);
+                if (__ballot(ht) == 0) continue;
+                for (int e = T.elem_begin; e < T.elem_end; ++e) {
+                    c_box += ht;
+                    if (ht && obb_hit(m.elems[e], of, df)) cand[ncand++] = (u32)e;
+                    if (__ballot(ncand == kCandCap) != 0) solve_candidates();
+                }
             }
         }
     }
@@ -438,7 +486,7 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
     R C[3] = {0, 0, 0}, A = 0;
     bool pending = false, fresh = false;
     int iters = 0;
-    u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_cap = 0;
+    u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_cap = 0, c_sub = 0;
 
     for (;;) {
         // refill idle lanes from the queue (one atomic per wave)
@@ -492,7 +540,7 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
             fresh = false;
             if (!(L > R(1e-7) * R(fp.scaled))) done = true;   // empty chord
         } else if (pending) {
-            composite(fp, rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A);
+            composite(fp, rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A, c_sub);
             ++c_samp;
             rho_prev = rho_cur;
             m_prev = m_cur;
@@ -528,7 +576,7 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
                 s += hh;
                 if (L - s <= R(1e-6) * L) {
                     // last step ends on the exit fragment: use its rho
-                    composite(fp, rho_prev, m_prev, rho_out, m_out, hh, C, A);
+                    composite(fp, rho_prev, m_prev, rho_out, m_out, hh, C, A, c_sub);
                     ++c_samp;
                     done = true;
                 } else {
@@ -566,6 +614,7 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
         flush_counter(ctr, C_W_EVALS, c_w);
         flush_counter(ctr, C_FP64_SOLVES, c_fp64);
         flush_counter(ctr, C_RK_ITER_CAP, c_cap);
+        flush_counter(ctr, C_SUBSAMPLES, c_sub);
     }
 }
 

@@ -437,11 +437,12 @@ __device__ __forceinline__ double fast_exp(double x) { return exp(x); }
 // sampling rate, not the spline), up to 64.
 template <typename R>
 __device__ __forceinline__ void composite(const FrameParams &fp, R ra, R ma, R rb, R mb, R len,
-                                          R (&C)[3], R &A) {
+                                          R (&C)[3], R &A, uint32_t &n_sub) {
     const R sa = fp.hermite ? ma * len : (rb - ra), sb = fp.hermite ? mb * len : (rb - ra);
     const R span = fmax(fabs(rb - ra), R(0.5) * (fabs(sa) + fabs(sb))) * R(fp.tf_inv_range);
     int ns = (int)ceil(span / R(fp.tf_dn));
     ns = ns < fp.n_super ? fp.n_super : (ns > 64 ? 64 : ns);
+    n_sub += (uint32_t)ns;
     const R inv = R(1) / R(ns);
     const R dl = len * inv;
     for (int j = 0; j < ns; ++j) {

@@ -34,6 +34,7 @@ struct alignas(16) DevPatch {
     int32_t cp_off;        // index of the first control point
     int32_t knot_off[3];   // offset of each knot vector in the knot arrays
     int32_t elem_off[7];   // face f owns elements [elem_off[f], elem_off[f+1])
+    int32_t tile_off[7];   // face f owns tiles [tile_off[f], tile_off[f+1])
     int32_t klass;         // degree class
     float orient;          // sign of det J over the block (+1 / -1)
     float box[6];          // padded bounding box lo[3], hi[3]
@@ -52,6 +53,17 @@ struct alignas(16) FaceElem {
     int32_t face;
     int32_t patch;
     int32_t pad[2];
+};
+
+// Up to kTile x kTile neighbouring elements of one face, with an oriented box
+// around all their Bezier points; its elements are contiguous.
+constexpr int kTile = 4;
+struct alignas(16) FaceTile {
+    float c[3];
+    float ax[3][3];
+    float ext[3];
+    int32_t elem_begin, elem_end;
+    int32_t pad[3];
 };
 
 template <typename R>
@@ -73,6 +85,7 @@ struct Model {
     const float *knots32;
     const double *knots64;
     const FaceElem *elems;
+    const FaceTile *tiles;
     int32_t npatch;
     float scale;           // bounding-box diagonal of the model
     double scaled;
@@ -82,7 +95,7 @@ struct Model {
 enum Counter : int {
     C_RAYS = 0, C_SEGMENTS, C_FRAGMENTS, C_ANOMALIES, C_FRAG_OVF, C_SEG_OVF, C_BOX_TESTS,
     C_FACE_NEWTON, C_FACE_NEWTON_ITER, C_FP64_POLISH, C_RK_STEPS, C_RK_REJECTED, C_SAMPLES,
-    C_W_EVALS, C_FP64_SOLVES, C_RK_ITER_CAP, C_MLP_QUERIES, C_COUNT
+    C_W_EVALS, C_FP64_SOLVES, C_RK_ITER_CAP, C_MLP_QUERIES, C_SUBSAMPLES, C_COUNT
 };
 
 // Queue bookkeeping written by the fragment kernel and read by the integrator.

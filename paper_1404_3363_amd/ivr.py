@@ -21,7 +21,7 @@ SEED = {"plain": 0, "mlp": 1}
 RHO_INTERP = {"linear": 0, "hermite": 1}
 
 EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_render",
-           "ivr_last_error", "ivr_destroy"]
+           "ivr_phase_times", "ivr_last_error", "ivr_destroy"]
 
 
 class PatchDesc(C.Structure):
@@ -46,13 +46,14 @@ class RenderOpts(C.Structure):
                 ("c_perp", C.c_double), ("n_super", C.c_int32),
                 ("det_fp64_threshold", C.c_double), ("max_fragments", C.c_int32),
                 ("seed_mode", C.c_int32), ("early_term", C.c_double),
-                ("max_newton_iter", C.c_int32), ("rho_interp", C.c_int32)]
+                ("max_newton_iter", C.c_int32), ("rho_interp", C.c_int32),
+                ("timing", C.c_int32)]
 
 
 STAT_FIELDS = ["rays", "segments", "fragments", "anomalies", "fragment_overflow",
                "segment_overflow", "box_tests", "face_newton", "face_newton_iter",
                "fp64_polish_iter", "rk_steps", "rk_rejected", "samples", "w_evals",
-               "fp64_solves", "rk_iter_cap", "mlp_queries"]
+               "fp64_solves", "rk_iter_cap", "mlp_queries", "subsamples"]
 
 
 class Stats(C.Structure):
@@ -81,6 +82,8 @@ def load_library() -> C.CDLL:
     L.ivr_render.argtypes = [vp, C.POINTER(CameraDesc), C.POINTER(TransferDesc),
                              C.POINTER(RenderOpts), vp, vp, C.POINTER(Stats)]
     L.ivr_render.restype = C.c_int32
+    L.ivr_phase_times.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]
+    L.ivr_phase_times.restype = C.c_int32
     L.ivr_last_error.argtypes = [vp]
     L.ivr_last_error.restype = C.c_char_p
     L.ivr_destroy.argtypes = [vp]
@@ -193,6 +196,15 @@ class Renderer:
             d.scalar = _dp(sc)
             d.rational = 1 if p.rational else 0
         self._check(self.lib.ivr_upload_patches(self.ctx, arr, len(patches)))
+
+    def phase_times(self, cap: int = 4096) -> np.ndarray:
+        """(n, 3) milliseconds (fragments, integrate, merge) of the renders recorded
+        with timing=1 since the last call."""
+        buf = np.zeros(3 * cap)
+        n = C.c_int32(0)
+        self._check(self.lib.ivr_phase_times(self.ctx, buf.ctypes.data_as(C.POINTER(C.c_double)),
+                                             cap, C.byref(n)))
+        return buf[:3 * min(n.value, cap)].reshape(-1, 3)
 
     def render(self, cam, tf, opts: Optional[RenderOpts] = None, rgba=None, depth=None,
                stats: bool = False, **kw):
