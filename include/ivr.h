@@ -106,6 +106,9 @@ typedef struct {
     int32_t rho_interp;         /* IVR_RHO_*: rho between two samples  [HERMITE] */
     int32_t timing;             /* 1: record HIP events around every phase of
                                    this render for ivr_phase_times (no sync) [0] */
+    double tf_step;             /* largest change of the transfer function's
+                                   output per step: limits h where the transfer
+                                   function is steep and rho is changing   [0.1] */
 } ivr_render_opts;
 
 /* Counters of one render (filled when a non-NULL ivr_stats* is passed; that

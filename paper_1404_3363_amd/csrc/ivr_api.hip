@@ -307,6 +307,8 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->early_term = 1e-4;
     o->max_newton_iter = 16;
     o->rho_interp = IVR_RHO_HERMITE;
+    o->timing = 0;
+    o->tf_step = 0.1;
 }
 
 ivr_status ivr_create(ivr_ctx **out, int32_t device, void *hip_stream) {
@@ -615,6 +617,17 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
         const double dn = std::min(1.0 / 16.0, std::max(1.0 / 64.0, 0.5 * gap));
         fp.tf_dn = (float)dn;
     }
+    {   // per-interval slope bound, widened to the neighbouring intervals
+        double sm[kMaxTfKnots] = {0};
+        for (int k = 0; k + 1 < nk; ++k)
+            for (int q = 0; q < 4; ++q) sm[k] = std::max(sm[k], std::fabs(fp.tf_sd[k][q] / (q == 3 && tf->extinction > 0 ? tf->extinction : 1.0)));
+        for (int k = 0; k + 1 < nk; ++k) {
+            double v = sm[k];
+            if (k > 0) v = std::max(v, sm[k - 1]);
+            if (k + 2 < nk) v = std::max(v, sm[k + 1]);
+            fp.tf_smax[k] = (float)v;
+        }
+    }
     fp.tf_lod = tf->domain[0];
     fp.tf_inv_ranged = 1.0 / (tf->domain[1] - tf->domain[0]);
     fp.tf_lo = (float)fp.tf_lod;
@@ -635,6 +648,8 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
         return fail(c, IVR_EINVAL, "unknown seed_mode");
     if (o.seed_mode == IVR_SEED_MLP) return fail(c, IVR_ESTATE, "no inverse-map MLP has been trained");
     if (!(o.early_term >= 0 && o.early_term < 1)) return fail(c, IVR_EINVAL, "early_term outside [0,1)");
+    if (!(o.tf_step > 0 && std::isfinite(o.tf_step))) return fail(c, IVR_EINVAL, "tf_step must be > 0");
+    fp.tf_step = (float)o.tf_step;
     if (o.max_newton_iter < 1 || o.max_newton_iter > 100)
         return fail(c, IVR_EINVAL, "max_newton_iter outside 1..100");
     const double hmax = o.h_max > 0 ? o.h_max : c->scale / 64.0;

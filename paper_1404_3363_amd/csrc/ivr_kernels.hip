@@ -548,6 +548,10 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
             if (A >= R(1) - early) done = true;
         }
         if (!done) {
+            // the transfer function's frequencies bound the step where rho changes
+            const R dn_ds = fabs(m_cur) * R(fp.tf_inv_ranged);
+            const R hf = R(fp.tf_step) / (dn_ds * tf_slope_near(fp, rho_cur) + R(1e-30));
+            h = h < hf ? h : (hf > hmin ? hf : hmin);
             const R hh = (h < L - s) ? h : (L - s);
             R q[3], dummy, dg[3];
 #define IVR_STAGE(KOUT, EXPR)                                                              \

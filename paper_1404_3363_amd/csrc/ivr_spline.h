@@ -422,6 +422,17 @@ __device__ __forceinline__ void tf_eval(const FrameParams &fp, double rho, doubl
     for (int c = 0; c < 4; ++c) out[c] = v[c] + s[c] * dn;
 }
 
+// Slope bound of the transfer function around rho (per unit of n).
+template <typename R>
+__device__ __forceinline__ R tf_slope_near(const FrameParams &fp, R rho) {
+    const float n = clamp01(float((rho - R(fp.tf_lod)) * R(fp.tf_inv_ranged)));
+    float sm = fp.tf_smax[0];
+#pragma unroll
+    for (int k = 1; k < kMaxTfKnots - 1; ++k)
+        if (k < fp.tf_n - 1) sm = n >= fp.tf_x[k] ? fp.tf_smax[k] : sm;
+    return R(sm);
+}
+
 __device__ __forceinline__ float fast_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double fast_exp(double x) { return exp(x); }
 
