@@ -85,8 +85,9 @@ typedef struct {
 
 #define IVR_PRECISION_FP32 0   /* FP32 kernels, FP64 boundary-root refinement  */
 #define IVR_PRECISION_FP64 1   /* every step in FP64                           */
-#define IVR_SEED_PLAIN 0
-#define IVR_SEED_MLP 1
+#define IVR_SEED_PLAIN 0       /* face Newton from the element centre              */
+#define IVR_SEED_MLP 1         /* from the block's trained inverse-map MLP         */
+#define IVR_SEED_BOX 2         /* from the ray's passage through the element box   */
 #define IVR_RHO_LINEAR 0       /* rho linear between samples (as in the paper)  */
 #define IVR_RHO_HERMITE 1      /* cubic Hermite from rho and d rho/ds           */
 
@@ -100,7 +101,7 @@ typedef struct {
     int32_t n_super;            /* supersampling sub-steps per RK step      [4]   */
     double det_fp64_threshold;  /* |det J| below it: solve in FP64          [1e-6] */
     int32_t max_fragments;      /* boundary crossings kept per ray, 2..64   [64]  */
-    int32_t seed_mode;          /* IVR_SEED_*                               [PLAIN]*/
+    int32_t seed_mode;          /* IVR_SEED_*: first Newton seed of a face root [BOX]*/
     double early_term;          /* stop a segment once alpha >= 1-early_term [1e-4]*/
     int32_t max_newton_iter;    /* FP32 Newton iterations per face root     [16]  */
     int32_t rho_interp;         /* IVR_RHO_*: rho between two samples  [HERMITE] */
@@ -160,6 +161,49 @@ ivr_status ivr_upload_patches(ivr_ctx *ctx, const ivr_patch_desc *patches, int32
 ivr_status ivr_render(ivr_ctx *ctx, const ivr_camera *cam, const ivr_transfer_fn *tf,
                       const ivr_render_opts *opts, float *rgba_dev, float *depth_dev,
                       ivr_stats *stats);
+
+/* ---- learned initialiser: one 3 -> 64 -> 64 -> 3 tanh MLP per block that maps a
+ * world point (normalised by the block's box to [-1,1]^3) to its parameter point;
+ * a surrogate of F^-1 used to seed the Newton solves of the boundary roots
+ * (seed_mode IVR_SEED_MLP).  Trained on the GPU on (F(p), p) pairs generated by
+ * the forward map with BF16 MFMA forward/backward kernels and Adam (FP32 master
+ * weights). */
+typedef struct {
+    int32_t samples_per_patch;  /* forward-map samples per block          [65536] */
+    int32_t steps;              /* Adam steps (minibatch 128 per block)    [2000] */
+    double lr;                  /* Adam step size                          [1e-3] */
+    uint32_t seed;              /* sample and initialisation seed          [5005] */
+    int32_t log_every;          /* record the loss every this many steps    [100] */
+} ivr_mlp_opts;
+
+typedef struct {
+    int32_t n_loss;             /* entries of loss[] written                     */
+    float loss[64];             /* minibatch loss (mean over blocks) at steps
+                                   0, log_every, 2*log_every, ...                 */
+    double heldout_mean_err;    /* mean and max over 4096 held-out samples per   */
+    double heldout_max_err;     /* block of max_c |MLP(F(p))_c - p_c|            */
+    double ms_samples, ms_train;
+} ivr_mlp_report;
+
+void ivr_default_mlp_opts(ivr_mlp_opts *o);
+
+/* Trains one MLP per uploaded block (IVR_ESTATE before an upload).  report may be
+ * NULL; when given, the call waits for the training to finish. */
+ivr_status ivr_train_inverse_mlp(ivr_ctx *ctx, const ivr_mlp_opts *opts, ivr_mlp_report *report);
+
+/* Gradient check of the training kernels: one forward/backward pass of the
+ * device code on n = 128 rows with the given parameters (kMlpParams = 4611 floats
+ * in the layout W1[3][64] b1[64] W2[64][64] b2[64] W3[64][3] b3[3]), normalised
+ * inputs x (n*3) and targets p (n*3), all host arrays.  Writes the loss
+ * (mean over rows of |y - p|^2) and the 4611 gradient entries.  Synchronous. */
+ivr_status ivr_mlp_forward_backward(ivr_ctx *ctx, const float *params, const float *x, const float *p,
+                                    int32_t n, float *loss, float *grad);
+
+/* Copies block `patch`'s FP32 master weights (4611 floats) to host memory. */
+ivr_status ivr_mlp_get_weights(ivr_ctx *ctx, int32_t patch, float *out);
+
+/* p_out[3i..] = MLP_{patch[i]}(x[3i..]) for n world points (host arrays). */
+ivr_status ivr_mlp_infer(ivr_ctx *ctx, const int32_t *patch, const float *x, int32_t n, float *p_out);
 
 /* Phase times of the renders recorded with opts->timing = 1 since the last call:
  * waits for them, writes up to `cap` triples (fragments, integrate, merge) in

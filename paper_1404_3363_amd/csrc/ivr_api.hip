@@ -48,6 +48,10 @@ struct ivr_ctx {
     // phase events of renders recorded with opts.timing (4 per render)
     std::vector<hipEvent_t> tev;
     int n_timed = 0;
+    // learned initialiser
+    std::vector<DevPatch> hpatch;
+    MlpState mlp = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool mlp_trained = false;
 };
 
 namespace {
@@ -303,7 +307,7 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->n_super = 4;
     o->det_fp64_threshold = 1e-6;
     o->max_fragments = kFragCap;
-    o->seed_mode = IVR_SEED_PLAIN;
+    o->seed_mode = IVR_SEED_BOX;
     o->early_term = 1e-4;
     o->max_newton_iter = 16;
     o->rho_interp = IVR_RHO_HERMITE;
@@ -348,6 +352,11 @@ static void free_model(ivr_ctx *c) {
     c->has_model = false;
 }
 
+static void free_mlp(ivr_ctx *c) {
+    dfree(c->mlp.w); dfree(c->mlp.m); dfree(c->mlp.v); dfree(c->mlp.wb); dfree(c->mlp.norm);
+    c->mlp_trained = false;
+}
+
 static void free_frame(ivr_ctx *c) {
     dfree(c->d_segs); dfree(c->d_results); dfree(c->d_pixseg); dfree(c->d_queues);
     c->pix_cap = c->seg_cap = c->seg_bytes_cap = 0;
@@ -359,6 +368,7 @@ void ivr_destroy(ivr_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     free_model(c);
     free_frame(c);
+    free_mlp(c);
     dfree(c->d_qs);
     dfree(c->d_ctr);
     for (auto &e : c->ev)
@@ -525,6 +535,8 @@ ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t
     }
     IVR_HIP(c, hipStreamSynchronize(c->stream));
     free_model(c);
+    free_mlp(c);
+    c->hpatch = hp;
     c->d_patches = tmp.d_patches; c->d_cp32 = tmp.d_cp32; c->d_rho32 = tmp.d_rho32;
     c->d_cp64 = tmp.d_cp64; c->d_rho64 = tmp.d_rho64; c->d_knots32 = tmp.d_knots32;
     c->d_knots64 = tmp.d_knots64; c->d_elems = tmp.d_elems; c->d_tiles = tmp.d_tiles;
@@ -644,9 +656,11 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
         return fail(c, IVR_EINVAL, "max_fragments outside 2..64");
     if (o.rho_interp != IVR_RHO_LINEAR && o.rho_interp != IVR_RHO_HERMITE)
         return fail(c, IVR_EINVAL, "unknown rho_interp");
-    if (o.seed_mode != IVR_SEED_PLAIN && o.seed_mode != IVR_SEED_MLP)
+    if (o.seed_mode != IVR_SEED_PLAIN && o.seed_mode != IVR_SEED_MLP && o.seed_mode != IVR_SEED_BOX)
         return fail(c, IVR_EINVAL, "unknown seed_mode");
-    if (o.seed_mode == IVR_SEED_MLP) return fail(c, IVR_ESTATE, "no inverse-map MLP has been trained");
+    if (o.seed_mode == IVR_SEED_MLP && !c->mlp_trained)
+        return fail(c, IVR_ESTATE, "no inverse-map MLP has been trained");
+    fp.seed_mode = o.seed_mode;
     if (!(o.early_term >= 0 && o.early_term < 1)) return fail(c, IVR_EINVAL, "early_term outside [0,1)");
     if (!(o.tf_step > 0 && std::isfinite(o.tf_step))) return fail(c, IVR_EINVAL, "tf_step must be > 0");
     fp.tf_step = (float)o.tf_step;
@@ -714,6 +728,8 @@ ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *
     m.patches = c->d_patches; m.cp32 = c->d_cp32; m.rho32 = c->d_rho32; m.cp64 = c->d_cp64;
     m.rho64 = c->d_rho64; m.knots32 = c->d_knots32; m.knots64 = c->d_knots64; m.elems = c->d_elems;
     m.tiles = c->d_tiles;
+    m.mlp_wb = c->mlp.wb;
+    m.mlp_norm = c->mlp.norm;
     m.npatch = c->npatch; m.scale = (float)c->scale; m.scaled = c->scale;
     // events for this render: the stats set, or the next timing slot
     hipEvent_t *ev = nullptr;
@@ -761,6 +777,196 @@ ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *
         stats->ms_merge = ms;
     }
     c->err.clear();
+    return IVR_OK;
+}
+
+// ---------------------------------------------------------------- learned initialiser
+
+static uint32_t host_pcg_hash(uint32_t v) {   // same published hash as the device side
+    const uint32_t state = v * 747796405u + 2891336453u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+void ivr_default_mlp_opts(ivr_mlp_opts *o) {
+    if (!o) return;
+    o->samples_per_patch = 65536;
+    o->steps = 2000;
+    o->lr = 1e-3;
+    o->seed = 5005;
+    o->log_every = 100;
+}
+
+static Model model_of(ivr_ctx *c) {
+    Model m;
+    std::memset(&m, 0, sizeof m);
+    m.patches = c->d_patches; m.cp32 = c->d_cp32; m.rho32 = c->d_rho32; m.cp64 = c->d_cp64;
+    m.rho64 = c->d_rho64; m.knots32 = c->d_knots32; m.knots64 = c->d_knots64; m.elems = c->d_elems;
+    m.tiles = c->d_tiles; m.mlp_wb = c->mlp.wb; m.mlp_norm = c->mlp.norm;
+    m.npatch = c->npatch; m.scale = (float)c->scale; m.scaled = c->scale;
+    return m;
+}
+
+ivr_status ivr_train_inverse_mlp(ivr_ctx *c, const ivr_mlp_opts *opts, ivr_mlp_report *report) {
+    if (!c) return IVR_EINVAL;
+    if (!c->has_model) return fail(c, IVR_ESTATE, "no model uploaded");
+    ivr_mlp_opts o;
+    ivr_default_mlp_opts(&o);
+    if (opts) o = *opts;
+    if (o.samples_per_patch < kMlpBatch || o.samples_per_patch > (1 << 22))
+        return fail(c, IVR_EINVAL, "samples_per_patch outside 128..4194304");
+    if (o.steps < 1 || o.steps > 1000000) return fail(c, IVR_EINVAL, "steps outside 1..1000000");
+    if (!(o.lr > 0 && o.lr < 1)) return fail(c, IVR_EINVAL, "lr outside (0,1)");
+    if (o.log_every < 1) return fail(c, IVR_EINVAL, "log_every must be >= 1");
+    IVR_HIP(c, hipSetDevice(c->device));
+    const int np = c->npatch;
+    free_mlp(c);
+    const size_t nw = (size_t)np * kMlpStride;
+    if (hipMalloc((void **)&c->mlp.w, nw * 4) != hipSuccess || hipMalloc((void **)&c->mlp.m, nw * 4) != hipSuccess ||
+        hipMalloc((void **)&c->mlp.v, nw * 4) != hipSuccess || hipMalloc((void **)&c->mlp.wb, nw * 2) != hipSuccess ||
+        hipMalloc((void **)&c->mlp.norm, (size_t)np * 12 * 4) != hipSuccess) {
+        free_mlp(c);
+        return fail(c, IVR_ENOMEM, "MLP allocation failed");
+    }
+    // Glorot-uniform initialisation (biases 0) from the hash of (seed, block, index)
+    std::vector<float> hw(nw, 0.0f), hn((size_t)np * 12, 0.0f);
+    for (int q = 0; q < np; ++q) {
+        float *W = hw.data() + (size_t)q * kMlpStride;
+        auto uni = [&](int idx, float a) {
+            const uint32_t h = host_pcg_hash(o.seed ^ host_pcg_hash((uint32_t)q * 0x9E3779B9u ^ host_pcg_hash((uint32_t)idx)));
+            return a * (2.0f * ((float)(h >> 8) * (1.0f / 16777216.0f)) - 1.0f);
+        };
+        const float a1 = std::sqrt(6.0f / (3 + 64)), a2 = std::sqrt(6.0f / (64 + 64)), a3 = std::sqrt(6.0f / (64 + 3));
+        for (int i = 0; i < 192; ++i) W[kOffW1 + i] = uni(kOffW1 + i, a1);
+        for (int i = 0; i < 4096; ++i) W[kOffW2 + i] = uni(kOffW2 + i, a2);
+        for (int i = 0; i < 192; ++i) W[kOffW3 + i] = uni(kOffW3 + i, a3);
+        const float *box = c->hpatch[q].box;
+        for (int d = 0; d < 3; ++d) {
+            const float half = std::max(0.5f * (box[3 + d] - box[d]), 1e-20f);
+            hn[12 * q + d] = box[d];
+            hn[12 * q + 3 + d] = 1.0f / half;
+            hn[12 * q + 6 + d] = 0.5f * (box[3 + d] + box[d]);
+        }
+    }
+    IVR_HIP(c, hipMemcpy(c->mlp.w, hw.data(), nw * 4, hipMemcpyHostToDevice));
+    IVR_HIP(c, hipMemset(c->mlp.m, 0, nw * 4));
+    IVR_HIP(c, hipMemset(c->mlp.v, 0, nw * 4));
+    IVR_HIP(c, hipMemcpy(c->mlp.norm, hn.data(), hn.size() * 4, hipMemcpyHostToDevice));
+    const int ns = o.samples_per_patch, nhold = 4096;
+    const int nlog = std::min(64, (o.steps + o.log_every - 1) / o.log_every);
+    float4 *xs = nullptr, *ps = nullptr, *hx = nullptr, *hpz = nullptr;
+    float *loss = nullptr, *err = nullptr;
+    auto cleanup = [&]() { dfree(xs); dfree(ps); dfree(hx); dfree(hpz); dfree(loss); dfree(err); };
+    if (hipMalloc((void **)&xs, (size_t)np * ns * 16) != hipSuccess || hipMalloc((void **)&ps, (size_t)np * ns * 16) != hipSuccess ||
+        hipMalloc((void **)&hx, (size_t)np * nhold * 16) != hipSuccess || hipMalloc((void **)&hpz, (size_t)np * nhold * 16) != hipSuccess ||
+        hipMalloc((void **)&loss, (size_t)np * std::max(nlog, 1) * 4) != hipSuccess ||
+        hipMalloc((void **)&err, (size_t)np * nhold * 4) != hipSuccess) {
+        cleanup();
+        free_mlp(c);
+        return fail(c, IVR_ENOMEM, "MLP sample allocation failed");
+    }
+    const Model m = model_of(c);
+    MlpTrainParams tp;
+    tp.steps = o.steps; tp.samples = ns; tp.log_every = o.log_every; tp.npatch = np;
+    tp.lr = (float)o.lr; tp.beta1 = 0.9f; tp.beta2 = 0.999f; tp.eps = 1e-8f; tp.seed = o.seed * 2654435761u + 17u;
+    hipError_t e = hipEventRecord(c->ev[0], c->stream);
+    if (e == hipSuccess) e = launch_mlp_samples(m, c->mlp, np, ns, o.seed, xs, ps, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
+    if (e == hipSuccess) e = launch_mlp_train(c->mlp, tp, xs, ps, loss, nlog, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev[2], c->stream);
+    if (e == hipSuccess) e = launch_mlp_samples(m, c->mlp, np, nhold, o.seed ^ 0x5A5A5A5Au, hx, hpz, c->stream);
+    if (e == hipSuccess) e = launch_mlp_heldout(c->mlp, np, nhold, hx, hpz, err, c->stream);
+    std::vector<float> herr((size_t)np * nhold), hloss((size_t)np * std::max(nlog, 1));
+    if (e == hipSuccess) e = hipMemcpyAsync(herr.data(), err, herr.size() * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hloss.data(), loss, hloss.size() * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        cleanup();
+        free_mlp(c);
+        return fail(c, IVR_EDEVICE, std::string("MLP training: ") + hipGetErrorString(e));
+    }
+    if (report) {
+        std::memset(report, 0, sizeof *report);
+        report->n_loss = nlog;
+        for (int k = 0; k < nlog; ++k) {
+            double acc = 0;
+            for (int q = 0; q < np; ++q) acc += hloss[(size_t)q * nlog + k];
+            report->loss[k] = (float)(acc / np);
+        }
+        double sum = 0, mx = 0;
+        for (float v : herr) { sum += v; mx = std::max(mx, (double)v); }
+        report->heldout_mean_err = sum / herr.size();
+        report->heldout_max_err = mx;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) report->ms_samples = ms;
+        if (hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess) report->ms_train = ms;
+    }
+    cleanup();
+    c->mlp_trained = true;
+    c->err.clear();
+    return IVR_OK;
+}
+
+ivr_status ivr_mlp_forward_backward(ivr_ctx *c, const float *params, const float *x, const float *p,
+                                    int32_t n, float *loss, float *grad) {
+    if (!c || !params || !x || !p || !loss || !grad) return fail(c, IVR_EINVAL, "NULL argument");
+    if (n != kMlpBatch) return fail(c, IVR_EINVAL, "n must be 128");
+    IVR_HIP(c, hipSetDevice(c->device));
+    float *dw = nullptr, *dx = nullptr, *dp = nullptr, *dout = nullptr;
+    auto cleanup = [&]() { dfree(dw); dfree(dx); dfree(dp); dfree(dout); };
+    if (hipMalloc((void **)&dw, kMlpStride * 4) != hipSuccess || hipMalloc((void **)&dx, n * 12) != hipSuccess ||
+        hipMalloc((void **)&dp, n * 12) != hipSuccess || hipMalloc((void **)&dout, (kMlpParams + 1) * 4) != hipSuccess) {
+        cleanup();
+        return fail(c, IVR_ENOMEM, "allocation failed");
+    }
+    MlpState st = {dw, nullptr, nullptr, nullptr, nullptr};
+    MlpTrainParams tp;
+    std::memset(&tp, 0, sizeof tp);
+    hipError_t e = hipMemcpy(dw, params, kMlpParams * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dx, x, n * 12, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dp, p, n * 12, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_mlp_grad(st, tp, dx, dp, dout, c->stream);
+    std::vector<float> out(kMlpParams + 1);
+    if (e == hipSuccess) e = hipMemcpyAsync(out.data(), dout, out.size() * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    cleanup();
+    if (e != hipSuccess) return fail(c, IVR_EDEVICE, std::string("MLP gradient: ") + hipGetErrorString(e));
+    std::memcpy(grad, out.data(), kMlpParams * 4);
+    *loss = out[kMlpParams];
+    return IVR_OK;
+}
+
+ivr_status ivr_mlp_get_weights(ivr_ctx *c, int32_t patch, float *out) {
+    if (!c || !out) return IVR_EINVAL;
+    if (!c->mlp_trained) return fail(c, IVR_ESTATE, "no inverse-map MLP has been trained");
+    if (patch < 0 || patch >= c->npatch) return fail(c, IVR_EINVAL, "patch out of range");
+    IVR_HIP(c, hipSetDevice(c->device));
+    IVR_HIP(c, hipStreamSynchronize(c->stream));
+    IVR_HIP(c, hipMemcpy(out, c->mlp.w + (size_t)patch * kMlpStride, kMlpParams * 4, hipMemcpyDeviceToHost));
+    return IVR_OK;
+}
+
+ivr_status ivr_mlp_infer(ivr_ctx *c, const int32_t *patch, const float *x, int32_t n, float *p_out) {
+    if (!c || !patch || !x || !p_out || n < 1) return fail(c, IVR_EINVAL, "bad arguments");
+    if (!c->mlp_trained) return fail(c, IVR_ESTATE, "no inverse-map MLP has been trained");
+    for (int i = 0; i < n; ++i)
+        if (patch[i] < 0 || patch[i] >= c->npatch) return fail(c, IVR_EINVAL, "patch out of range");
+    IVR_HIP(c, hipSetDevice(c->device));
+    int *dq = nullptr;
+    float *dx = nullptr, *dp = nullptr;
+    auto cleanup = [&]() { dfree(dq); dfree(dx); dfree(dp); };
+    if (hipMalloc((void **)&dq, (size_t)n * 4) != hipSuccess || hipMalloc((void **)&dx, (size_t)n * 12) != hipSuccess ||
+        hipMalloc((void **)&dp, (size_t)n * 12) != hipSuccess) {
+        cleanup();
+        return fail(c, IVR_ENOMEM, "allocation failed");
+    }
+    hipError_t e = hipMemcpy(dq, patch, (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dx, x, (size_t)n * 12, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_mlp_infer(c->mlp, dq, dx, n, dp, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p_out, dp, (size_t)n * 12, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    cleanup();
+    if (e != hipSuccess) return fail(c, IVR_EDEVICE, std::string("MLP inference: ") + hipGetErrorString(e));
     return IVR_OK;
 }
 

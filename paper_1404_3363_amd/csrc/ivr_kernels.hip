@@ -19,7 +19,9 @@
 //   k_merge      per pixel: over-composites its segments front to back.
 #include <hip/hip_runtime.h>
 
+#include "ivr.h"
 #include "ivr_internal.h"
+#include "ivr_mlp_dev.h"
 #include "ivr_spline.h"
 
 namespace ivr {
@@ -155,16 +157,20 @@ __device__ __forceinline__ bool face_newton(const PatchView<RN> &pv, const Array
     return false;
 }
 
-// Boundary roots from one candidate element E.  Seeds: the point of the ray in
-// the middle of its passage through E's box, mapped to (a, b) through the box
-// axes; if Newton does not converge from it, the element centre and its four
-// quarter points.  A root that converges anywhere on the face and is new for
+// Boundary roots from one candidate element E.  First seed by seed_mode:
+//   PLAIN  the element centre;
+//   BOX    the point of the ray in the middle of its passage through E's box,
+//          mapped to (a, b) through the box axes;
+//   MLP    the block's learned inverse map at that same point, restricted to the
+//          face's (a, b).
+// If Newton does not converge from it: the element centre and its four quarter
+// points.  A root that converges anywhere on the face and is new for
 // this ray is refined in FP64 and inserted into the depth-sorted fragment list.
 template <int P, bool RAT, typename RN>
 __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E, const double (&od)[3],
                           const double (&dd)[3], const float (&of)[3], const float (&df)[3],
                           const FrameParams &fp, Frag<RN> *fr, int &nfr, u32 &n_iter,
-                          u32 &n_polish, u32 &n_ovf) {
+                          u32 &n_polish, u32 &n_ovf, u32 &n_mlp) {
     const int face = E.face;
     const PatchView<RN> pv = view_of<RN>(Pd);
     const Arrays<RN> ar = arrays_of(m, RN(0));
@@ -174,18 +180,30 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
     const RN ha = RN(0.5) * (RN(E.a1) - RN(E.a0)), hb = RN(0.5) * (RN(E.b1) - RN(E.b0));
     RN a, b, t, Sa[3], Sb[3];
     bool conv = false;
-    for (int seed = 0; seed < 6 && !conv; ++seed) {
+    int dn, da, db;
+    face_dirs(face, dn, da, db);
+    for (int seed = (fp.seed_mode == IVR_SEED_PLAIN) ? 1 : 0; seed < 6 && !conv; ++seed) {
         if (seed == 0) {
             float t0, t1;
             obb_hit(E, of, df, t0, t1);
             const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
             float x[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) x[q] = of[q] + tm * df[q] - E.c[q];
-            const float xu = (E.ax[0][0] * x[0] + E.ax[0][1] * x[1] + E.ax[0][2] * x[2]) / E.ext[0];
-            const float xv = (E.ax[1][0] * x[0] + E.ax[1][1] * x[1] + E.ax[1][2] * x[2]) / E.ext[1];
-            a = ac + ha * RN(fminf(fmaxf(xu, -1.f), 1.f));
-            b = bc + hb * RN(fminf(fmaxf(xv, -1.f), 1.f));
+            for (int q = 0; q < 3; ++q) x[q] = of[q] + tm * df[q];
+            if (fp.seed_mode == IVR_SEED_MLP) {
+                float pm[3];
+                mlp_infer(m.mlp_wb, m.mlp_norm, E.patch, x, pm);
+                ++n_mlp;
+                a = RN(clamp01(pm[da]));
+                b = RN(clamp01(pm[db]));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) x[q] -= E.c[q];
+                const float xu = (E.ax[0][0] * x[0] + E.ax[0][1] * x[1] + E.ax[0][2] * x[2]) / E.ext[0];
+                const float xv = (E.ax[1][0] * x[0] + E.ax[1][1] * x[1] + E.ax[1][2] * x[2]) / E.ext[1];
+                a = ac + ha * RN(fminf(fmaxf(xu, -1.f), 1.f));
+                b = bc + hb * RN(fminf(fmaxf(xv, -1.f), 1.f));
+            }
         } else if (seed == 1) {
             a = ac;
             b = bc;
@@ -228,8 +246,6 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
         ++n_ovf;
         return;
     }
-    int dn, da, db;
-    face_dirs(face, dn, da, db);
     Frag<RN> f;
     f.t = T;
     f.patch = patch;
@@ -252,14 +268,14 @@ __device__ __forceinline__ void face_root_any(const Model &m, const DevPatch &Pd
                                               const double (&od)[3], const double (&dd)[3],
                                               const float (&of)[3], const float (&df)[3],
                                               const FrameParams &fp, Frag<R> *fr, int &nfr, u32 &ni,
-                                              u32 &np, u32 &no) {
+                                              u32 &np, u32 &no, u32 &nm) {
     switch (Pd.deg * 2 + Pd.rational) {
-    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
-    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
-    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
-    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
-    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
-    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no); break;
+    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
+    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
+    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
+    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
+    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
+    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
     }
 }
 
@@ -309,7 +325,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
         df[q] = float(dd[q]);
         inv[q] = 1.0f / df[q];
     }
-    u32 c_anom = 0, c_fovf = 0, c_sovf = 0, c_box = 0, c_newton = 0, c_iter = 0, c_pol = 0;
+    u32 c_anom = 0, c_fovf = 0, c_sovf = 0, c_box = 0, c_newton = 0, c_iter = 0, c_pol = 0, c_mlp = 0;
 
     // 1. face elements whose oriented box the ray hits (block and face boxes
     //    first) become Newton seeds; 2. the seeds are solved with all lanes in
@@ -324,7 +340,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
                 const FaceElem E = m.elems[cand[k]];
                 ++c_newton;
                 face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, fr, nfr, c_iter, c_pol,
-                                 c_fovf);
+                                 c_fovf, c_mlp);
             }
         }
         ncand = 0;
@@ -441,6 +457,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
         flush_counter(ctr, C_FACE_NEWTON, c_newton);
         flush_counter(ctr, C_FACE_NEWTON_ITER, c_iter);
         flush_counter(ctr, C_FP64_POLISH, c_pol);
+        flush_counter(ctr, C_MLP_QUERIES, c_mlp);
     }
 }
 

@@ -1,0 +1,31 @@
+// Per-block learned initialiser: a 3 -> 64 -> 64 -> 3 tanh MLP approximating the
+// inverse geometry map F^-1 on the block's image, trained on (F(p), p) pairs that
+// the forward map generates.  Parameter layout (floats), per block:
+//   W1[3][64] | b1[64] | W2[64][64] (row = input unit) | b2[64] | W3[64][3] | b3[3]
+// Inputs are the world point normalised by the block's box to [-1, 1]^3.
+#pragma once
+#include <stdint.h>
+
+namespace ivr {
+
+constexpr int kMlpIn = 3, kMlpH = 64, kMlpOut = 3;
+constexpr int kOffW1 = 0, kOffB1 = 192, kOffW2 = 256, kOffB2 = 4352, kOffW3 = 4416, kOffB3 = 4608;
+constexpr int kMlpParams = 4611;
+constexpr int kMlpStride = 4624;       // per-block stride (16-float aligned)
+constexpr int kMlpBatch = 128;         // minibatch per training step and block
+constexpr int kMlpSmall = 515;         // parameters outside W2
+
+struct MlpState {
+    float *w;            // FP32 master weights      [npatch][kMlpStride]
+    float *m, *v;        // Adam moments              [npatch][kMlpStride]
+    uint16_t *wb;        // BF16 weights (inference)  [npatch][kMlpStride]
+    float *norm;         // per block: lo[3], inv_half_extent[3], centre[3], pad
+};
+
+struct MlpTrainParams {
+    int32_t steps, samples, log_every, npatch;
+    float lr, beta1, beta2, eps;
+    uint32_t seed;
+};
+
+}  // namespace ivr

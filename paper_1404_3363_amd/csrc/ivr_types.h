@@ -86,6 +86,8 @@ struct Model {
     const double *knots64;
     const FaceElem *elems;
     const FaceTile *tiles;
+    const uint16_t *mlp_wb;    // BF16 MLP weights per block (seed_mode MLP)
+    const float *mlp_norm;     // per block: (unused[3], 1/half extent[3], centre[3], pad[3])
     int32_t npatch;
     float scale;           // bounding-box diagonal of the model
     double scaled;
@@ -129,7 +131,7 @@ struct FrameParams {
     // integrator
     float rk_tol, h_max, h_min, c_perp, early_term, det_thr;
     double rk_told, h_maxd, h_mind, c_perpd, early_termd, det_thrd;
-    int32_t n_super, max_frag, max_newton, collect, hermite;
+    int32_t n_super, max_frag, max_newton, collect, hermite, seed_mode;
     float scale;
     double scaled;
 };

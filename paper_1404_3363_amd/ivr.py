@@ -17,11 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libivr.so")
 
 IVR_OK, IVR_EINVAL, IVR_ENOMEM, IVR_EDEVICE, IVR_ESTATE, IVR_EOVERFLOW = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp32": 0, "fp64": 1}
-SEED = {"plain": 0, "mlp": 1}
+SEED = {"plain": 0, "mlp": 1, "box": 2}
 RHO_INTERP = {"linear": 0, "hermite": 1}
 
 EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_render",
-           "ivr_phase_times", "ivr_last_error", "ivr_destroy"]
+           "ivr_phase_times", "ivr_last_error", "ivr_destroy", "ivr_default_mlp_opts",
+           "ivr_train_inverse_mlp", "ivr_mlp_forward_backward", "ivr_mlp_get_weights",
+           "ivr_mlp_infer"]
+MLP_PARAMS = 4611
 
 
 class PatchDesc(C.Structure):
@@ -56,6 +59,17 @@ STAT_FIELDS = ["rays", "segments", "fragments", "anomalies", "fragment_overflow"
                "fp64_solves", "rk_iter_cap", "mlp_queries", "subsamples"]
 
 
+class MlpOpts(C.Structure):
+    _fields_ = [("samples_per_patch", C.c_int32), ("steps", C.c_int32), ("lr", C.c_double),
+                ("seed", C.c_uint32), ("log_every", C.c_int32)]
+
+
+class MlpReport(C.Structure):
+    _fields_ = [("n_loss", C.c_int32), ("loss", C.c_float * 64), ("heldout_mean_err", C.c_double),
+                ("heldout_max_err", C.c_double), ("ms_samples", C.c_double),
+                ("ms_train", C.c_double)]
+
+
 class Stats(C.Structure):
     _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [
         ("ms_fragments", C.c_double), ("ms_integrate", C.c_double), ("ms_merge", C.c_double)]
@@ -82,6 +96,17 @@ def load_library() -> C.CDLL:
     L.ivr_render.argtypes = [vp, C.POINTER(CameraDesc), C.POINTER(TransferDesc),
                              C.POINTER(RenderOpts), vp, vp, C.POINTER(Stats)]
     L.ivr_render.restype = C.c_int32
+    fp = C.POINTER(C.c_float)
+    L.ivr_default_mlp_opts.argtypes = [C.POINTER(MlpOpts)]
+    L.ivr_default_mlp_opts.restype = None
+    L.ivr_train_inverse_mlp.argtypes = [vp, C.POINTER(MlpOpts), C.POINTER(MlpReport)]
+    L.ivr_train_inverse_mlp.restype = C.c_int32
+    L.ivr_mlp_forward_backward.argtypes = [vp, fp, fp, fp, C.c_int32, fp, fp]
+    L.ivr_mlp_forward_backward.restype = C.c_int32
+    L.ivr_mlp_get_weights.argtypes = [vp, C.c_int32, fp]
+    L.ivr_mlp_get_weights.restype = C.c_int32
+    L.ivr_mlp_infer.argtypes = [vp, C.POINTER(C.c_int32), fp, C.c_int32, fp]
+    L.ivr_mlp_infer.restype = C.c_int32
     L.ivr_phase_times.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]
     L.ivr_phase_times.restype = C.c_int32
     L.ivr_last_error.argtypes = [vp]
@@ -196,6 +221,47 @@ class Renderer:
             d.scalar = _dp(sc)
             d.rational = 1 if p.rational else 0
         self._check(self.lib.ivr_upload_patches(self.ctx, arr, len(patches)))
+
+    # ---- learned initialiser
+    def train_mlp(self, **kw) -> dict:
+        o = MlpOpts()
+        self.lib.ivr_default_mlp_opts(C.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        rep = MlpReport()
+        self._check(self.lib.ivr_train_inverse_mlp(self.ctx, C.byref(o), C.byref(rep)))
+        return {"loss": list(rep.loss[:rep.n_loss]), "heldout_mean_err": rep.heldout_mean_err,
+                "heldout_max_err": rep.heldout_max_err, "ms_samples": rep.ms_samples,
+                "ms_train": rep.ms_train}
+
+    def mlp_forward_backward(self, params, x, p):
+        fptr = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert params.size == MLP_PARAMS and x.shape == p.shape == (x.shape[0], 3)
+        grad = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        self._check(self.lib.ivr_mlp_forward_backward(self.ctx, fptr(params), fptr(x), fptr(p),
+                                                      x.shape[0], fptr(loss), fptr(grad)))
+        return float(loss[0]), grad
+
+    def mlp_weights(self, patch: int) -> np.ndarray:
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        self._check(self.lib.ivr_mlp_get_weights(self.ctx, int(patch),
+                                                 out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def mlp_infer(self, patch, x) -> np.ndarray:
+        patch = np.ascontiguousarray(patch, dtype=np.int32)
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        out = np.zeros_like(x)
+        self._check(self.lib.ivr_mlp_infer(self.ctx, patch.ctypes.data_as(C.POINTER(C.c_int32)),
+                                           x.ctypes.data_as(C.POINTER(C.c_float)), len(x),
+                                           out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
 
     def phase_times(self, cap: int = 4096) -> np.ndarray:
         """(n, 3) milliseconds (fragments, integrate, merge) of the renders recorded

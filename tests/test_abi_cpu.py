@@ -29,7 +29,7 @@ def test_default_opts_match_header():
     from paper_1404_3363_amd import default_opts
     o = default_opts()
     assert o.precision == 0 and o.rk_tol == 1e-5 and o.h_max == 0.0 and o.c_perp == 1.0
-    assert o.n_super == 4 and o.max_fragments == 64 and o.seed_mode == 0 and o.rho_interp == 1
+    assert o.n_super == 4 and o.max_fragments == 64 and o.seed_mode == 2 and o.rho_interp == 1
     assert o.early_term == 1e-4 and o.max_newton_iter == 16
 
 

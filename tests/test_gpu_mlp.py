@@ -1,0 +1,121 @@
+"""GPU tests of the learned initialiser (per-block MLP surrogate of F^-1).
+
+* The training kernels' forward/backward (BF16 MFMA with FP32 accumulation) match
+  the FP64 reference of oracle/mlp.py (itself pinned to finite differences).
+* Training on the forward map's samples reduces the loss and inverts F on
+  held-out points; inference agrees with the oracle's forward map.
+* MLP-seeded rendering matches the oracle like the other seed modes and needs
+  fewer Newton iterations per boundary root than the plain (element-centre) seed.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as mlp_ref
+from scenes import make_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def renderer():
+    from paper_1404_3363_amd import Renderer
+    r = Renderer(0)
+    yield r
+    r.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_mlp_gradients_match_fp64_reference(renderer):
+    sc = make_config(1)
+    renderer.upload(sc.patches)
+    rng = np.random.default_rng(31)
+    theta = rng.normal(0.0, 0.25, mlp_ref.N_PARAMS)
+    x = rng.uniform(-1, 1, (128, 3))
+    p = rng.uniform(0, 1, (128, 3))
+    loss, grad = renderer.mlp_forward_backward(theta, x, p)
+    L, g = mlp_ref.loss_and_grad(theta.astype(np.float32).astype(np.float64),
+                                 x.astype(np.float32).astype(np.float64),
+                                 p.astype(np.float32).astype(np.float64))
+    print(f"[mlp] loss gpu {loss:.6f} fp64 {L:.6f}", flush=True)
+    assert abs(loss - L) <= 1e-2 * L
+    off = 0
+    for name, shape in mlp_ref.SIZES:
+        n = int(np.prod(shape))
+        r = _rel(grad[off:off + n].astype(np.float64), g[off:off + n])
+        print(f"[mlp] grad {name}: relative error {r:.2e}", flush=True)
+        assert r <= 2e-2, name
+        off += n
+
+
+@pytest.fixture(scope="module")
+def trained_c4(renderer):
+    sc = make_config(4, 480, 270)
+    renderer.upload(sc.patches)
+    rep = renderer.train_mlp()
+    print(f"[mlp] loss curve {np.round(rep['loss'][:3], 5)} ... {np.round(rep['loss'][-3:], 6)}; "
+          f"held-out mean {rep['heldout_mean_err']:.2e} max {rep['heldout_max_err']:.2e}; "
+          f"samples {rep['ms_samples']:.1f} ms train {rep['ms_train']:.1f} ms", flush=True)
+    return sc, rep
+
+
+def test_mlp_training_reduces_loss_and_inverts(renderer, trained_c4):
+    sc, rep = trained_c4
+    assert rep["loss"][-1] < 0.05 * rep["loss"][0]
+    assert rep["heldout_mean_err"] < 0.02
+    # inference on points of the oracle's forward map
+    rng = np.random.default_rng(41)
+    patches = rng.integers(0, len(sc.patches), 200)
+    ps = rng.uniform(0.02, 0.98, (200, 3))
+    xs = np.array([oracle.evaluate(sc.patches[q], p)[0] for q, p in zip(patches, ps)])
+    pred = renderer.mlp_infer(patches, xs)
+    err = np.abs(pred - ps).max(1)
+    print(f"[mlp] inference vs oracle forward map: mean {err.mean():.2e} max {err.max():.2e}",
+          flush=True)
+    assert err.mean() < 0.02 and err.max() < 0.15
+
+
+def test_mlp_inference_matches_reference_forward(renderer, trained_c4):
+    """BF16 inference on the device equals the FP64 reference forward pass of the
+    trained FP32 master weights, up to BF16 rounding."""
+    sc, _ = trained_c4
+    q = 17
+    theta = renderer.mlp_weights(q).astype(np.float64)
+    P = sc.patches[q]
+    lo, hi = P.cp[:, :3].min(0), P.cp[:, :3].max(0)
+    rng = np.random.default_rng(43)
+    xs = rng.uniform(lo, hi, (64, 3))
+    xh = (xs - 0.5 * (lo + hi)) / (0.5 * (hi - lo))
+    ref = mlp_ref.forward(theta, xh)
+    got = renderer.mlp_infer(np.full(64, q), xs)
+    assert np.abs(got - ref).max() < 2e-2
+
+
+def test_mlp_seeded_render_matches_oracle(renderer, trained_c4):
+    import torch
+    sc, _ = trained_c4
+    cam = sc.cameras[0]
+    out = {}
+    for mode in ("plain", "box", "mlp"):
+        rgba, depth, st = renderer.render(cam, sc.tf, stats=True, seed_mode=mode)
+        torch.cuda.synchronize()
+        out[mode] = (rgba.cpu().numpy().reshape(-1, 4).astype(np.float64), st)
+        print(f"[mlp] seed {mode}: newton iterations per solve "
+              f"{st['face_newton_iter'] / max(st['face_newton'], 1):.3f}, polish "
+              f"{st['fp64_polish_iter']}, mlp queries {st['mlp_queries']}, "
+              f"ms fragments {st['ms_fragments']:.3f}", flush=True)
+    rng = np.random.default_rng(47)
+    cov = np.flatnonzero(out["box"][0][:, 3] > 0)
+    pix = np.unique(np.concatenate([rng.choice(cov, 300, replace=False),
+                                    rng.choice(cam.width * cam.height, 100, replace=False)]))
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    for mode, (img, st) in out.items():
+        err = np.abs(img[pix] - ref.rgba).max()
+        print(f"[mlp] seed {mode}: max |rgba - oracle| = {err:.2e}", flush=True)
+        assert err <= 1e-3
+        assert st["anomalies"] == 0
+    it = {m: out[m][1]["face_newton_iter"] / max(out[m][1]["face_newton"], 1) for m in out}
+    assert it["mlp"] < it["plain"]

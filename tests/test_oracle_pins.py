@@ -472,3 +472,26 @@ def test_configs_pair_cleanly_and_converge(oracle_lib, k):
     assert (res.n_newton_fail == 0).all()
     assert res.self_error.max() < 1e-5
     assert (res.n_segments > 0).sum() >= (5 if k == 2 else 10)
+
+
+# ------------------------------------------------------------------ learned initialiser
+
+def test_mlp_reference_gradient_matches_finite_differences():
+    """The FP64 MLP reference's backpropagated gradient equals central finite
+    differences of its loss (relative 1e-6)."""
+    from oracle import mlp
+    rng = np.random.default_rng(21)
+    theta = rng.normal(0, 0.3, mlp.N_PARAMS)
+    x = rng.uniform(-1, 1, (16, 3))
+    p = rng.uniform(0, 1, (16, 3))
+    L, g = mlp.loss_and_grad(theta, x, p)
+    assert abs(L - mlp.loss(theta, x, p)) < 1e-14
+    idx = rng.choice(mlp.N_PARAMS, 60, replace=False)
+    idx = np.concatenate([idx, [0, 191, 192, 4351, 4352, 4415, 4416, 4607, 4608, 4610]])
+    for i in idx:
+        h = 1e-6
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (mlp.loss(tp, x, p) - mlp.loss(tm, x, p)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-9, (i, fd, g[i])
