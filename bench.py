@@ -89,6 +89,54 @@ def cpu_baseline(sc, cam, gpu_rgba, seconds_target=15.0, seed=7):
         {"pixels": n, "max_abs_rgba_vs_oracle": err}
 
 
+def time_renders(r, sc, cam, steps, warmup, **kw):
+    """Mrays/s of `steps` timed renders (after `warmup`) and the counters of one more."""
+    import torch
+    from paper_1404_3363_amd import default_opts
+    opts = default_opts(**kw)
+    dev = torch.device("cuda", 0)
+    rgba = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=dev)
+    depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device=dev)
+    for _ in range(warmup):
+        r.render(cam, sc.tf, opts=opts, rgba=rgba, depth=depth)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.render(cam, sc.tf, opts=opts, rgba=rgba, depth=depth)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    _, _, st = r.render(cam, sc.tf, opts=opts, rgba=rgba, depth=depth, stats=True)
+    torch.cuda.synchronize()
+    return cam.width * cam.height * steps / el / 1e6, 1e3 * el / steps, st, rgba
+
+
+def mlp_vs_plain(r, steps, warmup):
+    """Config 4 (256 NURBS blocks, 1920x1080): boundary-root Newton seeded by the
+    trained MLP versus the plain element-centre seed (and the box seed, the
+    default), same GPU, same image within the parity bar."""
+    from scenes import make_config
+    sc = make_config(4)
+    cam = sc.cameras[0]
+    r.upload(sc.patches)
+    rep = r.train_mlp()
+    res = {}
+    imgs = {}
+    for mode in ("plain", "mlp", "box"):
+        v, ms, st, rgba = time_renders(r, sc, cam, steps, warmup, seed_mode=mode)
+        imgs[mode] = rgba.cpu().numpy().reshape(-1, 4)
+        res[mode] = {"value": round(v, 3), "ms_per_step": round(ms, 4),
+                     "newton_iter_per_root": round(st["face_newton_iter"] / max(st["face_newton"], 1), 4),
+                     "ms_fragments": round(st["ms_fragments"], 4), "mlp_queries": st["mlp_queries"]}
+    return {"workload": "config4: step channel, 256 cubic NURBS patches of 8^3 control points, "
+                        "1920x1080 view 0", "unit": "Mrays/s",
+            "mlp_training": {"ms_samples": round(rep["ms_samples"], 2), "ms_train": round(rep["ms_train"], 2),
+                             "heldout_mean_err": rep["heldout_mean_err"],
+                             "heldout_max_err": rep["heldout_max_err"]},
+            "plain": res["plain"], "mlp": res["mlp"], "box": res["box"],
+            "speedup_mlp_over_plain": round(res["mlp"]["value"] / res["plain"]["value"], 4),
+            "max_abs_rgba_mlp_vs_plain": float(np.abs(imgs["mlp"] - imgs["plain"]).max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +144,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--view", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mlp", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path shards by image tiles or "
@@ -163,6 +212,8 @@ def main():
         cpu, parity = cpu_baseline(sc, cam, img)
         out["cpu_baseline"] = cpu
         out["parity_sample"] = parity
+    if not args.no_mlp:
+        out["mlp_vs_plain"] = mlp_vs_plain(r, args.steps, args.warmup)
     print(json.dumps(out))
 
 

@@ -823,7 +823,7 @@ ivr_status ivr_train_inverse_mlp(ivr_ctx *c, const ivr_mlp_opts *opts, ivr_mlp_r
     free_mlp(c);
     const size_t nw = (size_t)np * kMlpStride;
     if (hipMalloc((void **)&c->mlp.w, nw * 4) != hipSuccess || hipMalloc((void **)&c->mlp.m, nw * 4) != hipSuccess ||
-        hipMalloc((void **)&c->mlp.v, nw * 4) != hipSuccess || hipMalloc((void **)&c->mlp.wb, nw * 2) != hipSuccess ||
+        hipMalloc((void **)&c->mlp.v, nw * 4) != hipSuccess || hipMalloc((void **)&c->mlp.wb, (size_t)np * kMlpWbStride * 2) != hipSuccess ||
         hipMalloc((void **)&c->mlp.norm, (size_t)np * 12 * 4) != hipSuccess) {
         free_mlp(c);
         return fail(c, IVR_ENOMEM, "MLP allocation failed");

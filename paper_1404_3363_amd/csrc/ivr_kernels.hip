@@ -169,8 +169,8 @@ __device__ __forceinline__ bool face_newton(const PatchView<RN> &pv, const Array
 template <int P, bool RAT, typename RN>
 __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E, const double (&od)[3],
                           const double (&dd)[3], const float (&of)[3], const float (&df)[3],
-                          const FrameParams &fp, Frag<RN> *fr, int &nfr, u32 &n_iter,
-                          u32 &n_polish, u32 &n_ovf, u32 &n_mlp) {
+                          const FrameParams &fp, const float (&mseed)[3], Frag<RN> *fr, int &nfr,
+                          u32 &n_iter, u32 &n_polish, u32 &n_ovf) {
     const int face = E.face;
     const PatchView<RN> pv = view_of<RN>(Pd);
     const Arrays<RN> ar = arrays_of(m, RN(0));
@@ -191,11 +191,8 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
 #pragma unroll
             for (int q = 0; q < 3; ++q) x[q] = of[q] + tm * df[q];
             if (fp.seed_mode == IVR_SEED_MLP) {
-                float pm[3];
-                mlp_infer(m.mlp_wb, m.mlp_norm, E.patch, x, pm);
-                ++n_mlp;
-                a = RN(clamp01(pm[da]));
-                b = RN(clamp01(pm[db]));
+                a = RN(clamp01(mseed[da]));
+                b = RN(clamp01(mseed[db]));
             } else {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) x[q] -= E.c[q];
@@ -267,15 +264,15 @@ template <typename R>
 __device__ __forceinline__ void face_root_any(const Model &m, const DevPatch &Pd, const FaceElem &E,
                                               const double (&od)[3], const double (&dd)[3],
                                               const float (&of)[3], const float (&df)[3],
-                                              const FrameParams &fp, Frag<R> *fr, int &nfr, u32 &ni,
-                                              u32 &np, u32 &no, u32 &nm) {
+                                              const FrameParams &fp, const float (&ms)[3], Frag<R> *fr,
+                                              int &nfr, u32 &ni, u32 &np, u32 &no) {
     switch (Pd.deg * 2 + Pd.rational) {
-    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
-    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
-    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
-    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
-    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
-    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, fr, nfr, ni, np, no, nm); break;
+    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
+    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
+    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
+    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
+    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
+    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
     }
 }
 
@@ -334,13 +331,32 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
     int ncand = 0;
     Frag<R> fr[kFragCap];
     int nfr = 0;
-    auto solve_candidates = [&]() {
+    // seed_mode MLP: candidates are solved per block (flushed after each block), so
+    // the wave evaluates one block's MLP for all its lanes at once on MFMA
+    __shared__ uint16_t sA[64 * 72];
+    __shared__ float sY[64 * 4];
+    const bool mlp = fp.seed_mode == IVR_SEED_MLP;
+    auto solve_candidates = [&](int block) {
         for (int k = 0; __ballot(k < ncand) != 0; ++k) {
+            float ms[3] = {0.f, 0.f, 0.f};
+            if (mlp) {
+                float x[3] = {of[0], of[1], of[2]};
+                if (k < ncand) {
+                    const FaceElem &E = m.elems[cand[k]];
+                    float t0, t1;
+                    obb_hit(E, of, df, t0, t1);
+                    const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) x[q] = of[q] + tm * df[q];
+                    ++c_mlp;
+                }
+                mlp_infer_wave(m.mlp_wb, m.mlp_norm, block, x, ms, sA, sY);
+            }
             if (k < ncand) {
                 const FaceElem E = m.elems[cand[k]];
                 ++c_newton;
-                face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, fr, nfr, c_iter, c_pol,
-                                 c_fovf, c_mlp);
+                face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, fr, nfr, c_iter, c_pol,
+                                 c_fovf);
             }
         }
         ncand = 0;
@@ -362,12 +378,13 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
                 for (int e = T.elem_begin; e < T.elem_end; ++e) {
                     c_box += ht;
                     if (ht && obb_hit(m.elems[e], of, df)) cand[ncand++] = (u32)e;
-                    if (__ballot(ncand == kCandCap) != 0) solve_candidates();
+                    if (__ballot(ncand == kCandCap) != 0) solve_candidates(pi);
                 }
             }
         }
+        if (mlp && __ballot(ncand > 0) != 0) solve_candidates(pi);
     }
-    solve_candidates();
+    solve_candidates(0);
     // 3. Algorithm "Blockwise depth-sorting": the nearest unused exit, then the
     //    nearest unused entry of the same block in front of it.
     unsigned char pin[kSegCap], pout[kSegCap];

@@ -11,14 +11,16 @@ namespace ivr {
 constexpr int kMlpIn = 3, kMlpH = 64, kMlpOut = 3;
 constexpr int kOffW1 = 0, kOffB1 = 192, kOffW2 = 256, kOffB2 = 4352, kOffW3 = 4416, kOffB3 = 4608;
 constexpr int kMlpParams = 4611;
-constexpr int kMlpStride = 4624;       // per-block stride (16-float aligned)
+constexpr int kMlpStride = 4624;       // per-block stride of the FP32 arrays (16-float aligned)
+constexpr int kOffW2T = 4624;          // BF16 inference copy: W2 transposed, [n_out][k_in]
+constexpr int kMlpWbStride = 8720;     // per-block stride of the BF16 inference weights
 constexpr int kMlpBatch = 128;         // minibatch per training step and block
 constexpr int kMlpSmall = 515;         // parameters outside W2
 
 struct MlpState {
     float *w;            // FP32 master weights      [npatch][kMlpStride]
     float *m, *v;        // Adam moments              [npatch][kMlpStride]
-    uint16_t *wb;        // BF16 weights (inference)  [npatch][kMlpStride]
+    uint16_t *wb;        // BF16 weights (inference)  [npatch][kMlpWbStride]
     float *norm;         // per block: lo[3], inv_half_extent[3], centre[3], pad
 };
 

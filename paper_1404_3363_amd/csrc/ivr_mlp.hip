@@ -16,8 +16,6 @@
 
 namespace ivr {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ samples
 
@@ -328,8 +326,11 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpState st, MlpTrainParams t
         if (tid < 4) gb3[tid] = 0.f;
         __syncthreads();
     }
-    if (MODE == 0)
-        for (int i = tid; i < kMlpParams; i += 256) st.wb[(size_t)q * kMlpStride + i] = f2bf(W[i]);
+    if (MODE == 0) {
+        uint16_t *wb = st.wb + (size_t)q * kMlpWbStride;
+        for (int i = tid; i < kMlpParams; i += 256) wb[i] = f2bf(W[i]);
+        for (int i = tid; i < 64 * 64; i += 256) wb[kOffW2T + (i & 63) * 64 + (i >> 6)] = f2bf(W[kOffW2 + i]);
+    }
 }
 
 // ------------------------------------------------------------------ inference
