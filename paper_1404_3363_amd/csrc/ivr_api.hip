@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -518,6 +519,44 @@ ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t
         }
         D.elem_off[6] = (int)elems.size();
         D.tile_off[6] = (int)tiles.size();
+    }
+    // Faces shared by two blocks (identical boundary nets and knot vectors, as at
+    // conforming interfaces): test them from the first block only and emit the
+    // second block's crossing from the same root.
+    {
+        std::map<std::vector<double>, int> seen;
+        for (int pi = 0; pi < n; ++pi) {
+            for (int f = 0; f < 6; ++f) hp[pi].twin[f] = -1;
+            hp[pi].face_skip = 0;
+        }
+        for (int pi = 0; pi < n; ++pi) {
+            const auto &P = patches[pi];
+            const int p = P.degree[0], n0 = P.ncp[0], n1 = P.ncp[1];
+            for (int f = 0; f < 6; ++f) {
+                const int dn = f >> 1, da = dn == 0 ? 1 : 0, db = dn == 2 ? 1 : 2;
+                const int fix = (f & 1) ? P.ncp[dn] - 1 : 0;
+                std::vector<double> key = {(double)p, (double)P.rational, (double)P.ncp[da], (double)P.ncp[db]};
+                for (int d : {da, db}) {
+                    const double *t = P.knots[d];
+                    const double t0 = t[p], t1 = t[P.ncp[d]];
+                    for (int i = 0; i < P.ncp[d] + p + 1; ++i) key.push_back((t[i] - t0) / (t1 - t0));
+                }
+                for (int jb = 0; jb < P.ncp[db]; ++jb)
+                    for (int ia = 0; ia < P.ncp[da]; ++ia) {
+                        int ijk[3];
+                        ijk[dn] = fix; ijk[da] = ia; ijk[db] = jb;
+                        const double *cc = P.cp + 4 * ((size_t)ijk[0] + (size_t)n0 * (ijk[1] + (size_t)n1 * ijk[2]));
+                        key.insert(key.end(), {cc[0], cc[1], cc[2], P.rational ? cc[3] : 1.0});
+                    }
+                auto it = seen.find(key);
+                if (it == seen.end()) {
+                    seen.emplace(std::move(key), 8 * pi + f);
+                } else if ((it->second >> 3) != pi && hp[it->second >> 3].twin[it->second & 7] < 0) {
+                    hp[it->second >> 3].twin[it->second & 7] = 8 * pi + f;
+                    hp[pi].face_skip |= 1 << f;
+                }
+            }
+        }
     }
     // allocate and copy, then swap in
     ivr_ctx tmp;

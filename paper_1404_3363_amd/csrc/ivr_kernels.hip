@@ -131,6 +131,35 @@ __device__ __forceinline__ int facing(int face, float orient, const R (&Sa)[3], 
     return (side * sigma * g * R(orient)) > R(0);
 }
 
+// Adds a crossing of `patch` through `face` at face parameters (A, B), ray
+// parameter T, to the depth-sorted list unless it duplicates one already there.
+template <typename RN>
+__device__ __forceinline__ void insert_frag(Frag<RN> *fr, int &nfr, const FrameParams &fp, int patch,
+                                            int face, int ent, double A, double B, double T, u32 &n_ovf) {
+    if (is_dup(fr, nfr, patch, ent, T, 1e-6 * fp.scaled)) return;
+    if (nfr >= fp.max_frag) {
+        ++n_ovf;
+        return;
+    }
+    int dn, da, db;
+    face_dirs(face, dn, da, db);
+    Frag<RN> f;
+    f.t = T;
+    f.patch = patch;
+    f.entering = ent;
+    RN pp[3];
+    pp[dn] = (face & 1) ? RN(1) : RN(0);
+    pp[da] = RN(clamp01(A));
+    pp[db] = RN(clamp01(B));
+    f.p[0] = pp[0]; f.p[1] = pp[1]; f.p[2] = pp[2];
+    int q = nfr++;
+    while (q > 0 && fr[q - 1].t > T) {
+        fr[q] = fr[q - 1];
+        --q;
+    }
+    fr[q] = f;
+}
+
 // Newton on S_f(a,b) - (o + t d) = 0 (Eqs. (F), (newtonsmethod) restricted to
 // the face) in precision RN from (a, b); true when it converges.
 template <int P, bool RAT, typename RN>
@@ -238,26 +267,14 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
     if (!(A >= -mg64 && A <= 1.0 + mg64 && B >= -mg64 && B <= 1.0 + mg64 && T > 0.0)) return;
     ent = facing(face, Pd.orient, Sa2, Sb2, dd, grazing);
     if (grazing) return;
-    if (is_dup(fr, nfr, patch, ent, T, 1e-6 * fp.scaled)) return;
-    if (nfr >= fp.max_frag) {
-        ++n_ovf;
-        return;
+    insert_frag(fr, nfr, fp, patch, face, ent, A, B, T, n_ovf);
+    // the same root is the crossing of the block on the other side of a shared face
+    const int tw = Pd.twin[face];
+    if (tw >= 0) {
+        const int tp = tw >> 3, tf = tw & 7;
+        const int tent = facing(tf, m.patches[tp].orient, Sa2, Sb2, dd, grazing);
+        insert_frag(fr, nfr, fp, tp, tf, tent, A, B, T, n_ovf);
     }
-    Frag<RN> f;
-    f.t = T;
-    f.patch = patch;
-    f.entering = ent;
-    RN pp[3];
-    pp[dn] = (face & 1) ? RN(1) : RN(0);
-    pp[da] = RN(clamp01(A));
-    pp[db] = RN(clamp01(B));
-    f.p[0] = pp[0]; f.p[1] = pp[1]; f.p[2] = pp[2];
-    int q = nfr++;
-    while (q > 0 && fr[q - 1].t > T) {
-        fr[q] = fr[q - 1];
-        --q;
-    }
-    fr[q] = f;
 }
 
 template <typename R>
@@ -300,7 +317,7 @@ __device__ __forceinline__ u32 wave_incl_scan(u32 v, int lane) {
     return v;
 }
 
-template <typename R>
+template <typename R, bool MLP>
 __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R> *segs, u32 seg_cap,
                                                   u32 *queues, u32 queue_stride, u32 class_mask,
                                                   QueueState *qs, uint2 *pixseg, float *depth,
@@ -335,11 +352,11 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
     // the wave evaluates one block's MLP for all its lanes at once on MFMA
     __shared__ uint16_t sA[64 * 72];
     __shared__ float sY[64 * 4];
-    const bool mlp = fp.seed_mode == IVR_SEED_MLP;
+    constexpr bool mlp = MLP;   // a separate instantiation keeps the MFMA path's registers out of the others
     auto solve_candidates = [&](int block) {
         for (int k = 0; __ballot(k < ncand) != 0; ++k) {
             float ms[3] = {0.f, 0.f, 0.f};
-            if (mlp) {
+            if constexpr (mlp) {
                 float x[3] = {of[0], of[1], of[2]};
                 if (k < ncand) {
                     const FaceElem &E = m.elems[cand[k]];
@@ -367,6 +384,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
         const bool hp = valid && slab(of, inv, Pd.box, Pd.box + 3);
         if (__ballot(hp) == 0) continue;
         for (int f = 0; f < 6; ++f) {
+            if ((Pd.face_skip >> f) & 1) continue;   // tested from the neighbouring block
             c_box += hp;
             const bool hf = hp && slab(of, inv, Pd.fbox[f], Pd.fbox[f] + 3);
             if (__ballot(hf) == 0) continue;
@@ -382,7 +400,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
                 }
             }
         }
-        if (mlp && __ballot(ncand > 0) != 0) solve_candidates(pi);
+        if (mlp && __ballot(ncand > 0) != 0) solve_candidates(pi);   // one block per flush
     }
     solve_candidates(0);
     // 3. Algorithm "Blockwise depth-sorting": the nearest unused exit, then the
@@ -682,8 +700,12 @@ static hipError_t launch_fragments_t(const Model &m, const FrameParams &fp, void
                                      uint32_t class_mask, QueueState *qs, uint2 *pixseg, float *depth,
                                      unsigned long long *ctr, hipStream_t st) {
     const int tiles = ((fp.width + 7) / 8) * ((fp.height + 7) / 8);
-    hipLaunchKernelGGL((k_fragments<R>), dim3(tiles), dim3(64), 0, st, m, fp, (Seg<R> *)segs, seg_cap,
-                       queues, queue_stride, class_mask, qs, pixseg, depth, ctr);
+    if (fp.seed_mode == IVR_SEED_MLP)
+        hipLaunchKernelGGL((k_fragments<R, true>), dim3(tiles), dim3(64), 0, st, m, fp, (Seg<R> *)segs,
+                           seg_cap, queues, queue_stride, class_mask, qs, pixseg, depth, ctr);
+    else
+        hipLaunchKernelGGL((k_fragments<R, false>), dim3(tiles), dim3(64), 0, st, m, fp, (Seg<R> *)segs,
+                           seg_cap, queues, queue_stride, class_mask, qs, pixseg, depth, ctr);
     return hipGetLastError();
 }
 

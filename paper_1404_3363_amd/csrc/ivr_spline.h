@@ -154,7 +154,7 @@ __device__ __forceinline__ void eval_volume(const PatchView<R> &pv, const Arrays
     R X[NC], Xu[NC], Xv[NC], Xw[NC], rX = R(0), rXu = R(0), rXv = R(0), rXw = R(0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) X[c] = Xu[c] = Xv[c] = Xw[c] = R(0);
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k <= P; ++k) {
         R B0[NC], B1[NC], Bu[NC], rB = R(0), rB1 = R(0), rBu = R(0);
 #pragma unroll
@@ -270,7 +270,7 @@ __device__ __forceinline__ void eval_face(const PatchView<R> &pv, const Arrays<R
     R H[NC], Ha[NC], Hb[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) H[c] = Ha[c] = Hb[c] = R(0);
-#pragma unroll
+#pragma unroll 1
     for (int jb = 0; jb <= P; ++jb) {
         R A0[NC], A1[NC];
 #pragma unroll

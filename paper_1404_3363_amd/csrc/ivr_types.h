@@ -41,6 +41,9 @@ struct alignas(16) DevPatch {
     float fbox[6][6];      // padded bounding box of each face
     float inv_nspan[3];
     float pad0;
+    int32_t twin[6];       // face shared with another block: 8*block + face, or -1
+    int32_t face_skip;     // bit f: face f is the twin of a face tested from the other block
+    int32_t pad1;
 };
 
 // Face element: oriented box around the element's control points (axes from the
