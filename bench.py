@@ -137,6 +137,19 @@ def mlp_vs_plain(r, steps, warmup):
             "max_abs_rgba_mlp_vs_plain": float(np.abs(imgs["mlp"] - imgs["plain"]).max())}
 
 
+def copy_calibration(nbytes=256 << 20, reps=5):
+    """A plain copy of known size: under a counter profile, its FETCH_SIZE and
+    WRITE_SIZE per dispatch against nbytes/1024 KiB give the counters' scale."""
+    import torch
+    dev = torch.device("cuda", 0)
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_kib": nbytes // 1024, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,7 +158,13 @@ def main():
     ap.add_argument("--view", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy 5 times (reference "
+                         "for the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path shards by image tiles or "
               "views; see DESIGN.md); use --gpus 1", file=sys.stderr)

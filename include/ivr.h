@@ -133,6 +133,8 @@ typedef struct {
     uint64_t rk_iter_cap;       /* segments stopped at the iteration cap         */
     uint64_t mlp_queries;       /* MLP seed evaluations                          */
     uint64_t subsamples;        /* supersampling sub-steps (transfer function)   */
+    uint64_t degenerate;        /* segment ends with singular J (|det J| below
+                                   det_fp64_threshold), shrunk by Eq. (degeneracyfix) */
     double ms_fragments, ms_integrate, ms_merge;  /* event times per phase      */
 } ivr_stats;
 

@@ -444,8 +444,10 @@ ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t
         for (size_t q = 0; q < N; ++q) {
             const double *cc = P.cp + 4 * q;
             const double w = P.rational ? cc[3] : 1.0;
-            cp32.push_back(make_float4((float)(w * cc[0]), (float)(w * cc[1]), (float)(w * cc[2]), (float)w));
-            cp64.push_back(make_double4(w * cc[0], w * cc[1], w * cc[2], w));
+            // homogeneous (wx, wy, wz, w) for NURBS; (x, y, z, rho) for B-splines
+            const double w4 = P.rational ? w : P.scalar[q];
+            cp32.push_back(make_float4((float)(w * cc[0]), (float)(w * cc[1]), (float)(w * cc[2]), (float)w4));
+            cp64.push_back(make_double4(w * cc[0], w * cc[1], w * cc[2], w4));
             rho32.push_back((float)(w * P.scalar[q]));
             rho64.push_back(w * P.scalar[q]);
             pb.add(cc);

@@ -293,18 +293,19 @@ __device__ __forceinline__ void face_root_any(const Model &m, const DevPatch &Pd
     }
 }
 
+// rho and d rho/ds at a parameter point; returns det J_phi there.
 template <typename R>
-__device__ __forceinline__ void rho_ds_any(const Model &m, const DevPatch &Pd, const R (&p)[3],
-                                           const R (&d)[3], R &rho, R &drho) {
+__device__ __forceinline__ R rho_ds_any(const Model &m, const DevPatch &Pd, const R (&p)[3],
+                                        const R (&d)[3], R &rho, R &drho) {
     const PatchView<R> pv = view_of<R>(Pd);
     const Arrays<R> ar = arrays_of(m, R(0));
     switch (Pd.deg * 2 + Pd.rational) {
-    case 2: eval_rho_ds<1, false>(pv, ar, p, d, rho, drho); break;
-    case 3: eval_rho_ds<1, true>(pv, ar, p, d, rho, drho); break;
-    case 4: eval_rho_ds<2, false>(pv, ar, p, d, rho, drho); break;
-    case 5: eval_rho_ds<2, true>(pv, ar, p, d, rho, drho); break;
-    case 6: eval_rho_ds<3, false>(pv, ar, p, d, rho, drho); break;
-    default: eval_rho_ds<3, true>(pv, ar, p, d, rho, drho); break;
+    case 2: return eval_rho_ds<1, false>(pv, ar, p, d, rho, drho);
+    case 3: return eval_rho_ds<1, true>(pv, ar, p, d, rho, drho);
+    case 4: return eval_rho_ds<2, false>(pv, ar, p, d, rho, drho);
+    case 5: return eval_rho_ds<2, true>(pv, ar, p, d, rho, drho);
+    case 6: return eval_rho_ds<3, false>(pv, ar, p, d, rho, drho);
+    default: return eval_rho_ds<3, true>(pv, ar, p, d, rho, drho);
     }
 }
 
@@ -457,7 +458,11 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
             s.p_in[q] = fi.p[q];
             s.p_out[q] = fo.p[q];
         }
-        rho_ds_any<R>(m, m.patches[fo.patch], fo.p, dr, s.rho_out, s.drho_out);
+        const R det_out = rho_ds_any<R>(m, m.patches[fo.patch], fo.p, dr, s.rho_out, s.drho_out);
+        // singular J at the exit (a degenerate boundary): no slope; the
+        // integrator then stops short of the exit, Eq. (degeneracyfix)
+        if (!(fabs(det_out) >= (sizeof(R) == 4 ? R(fp.det_thr) : R(fp.det_thrd))))
+            s.drho_out = R(NAN);
         s.pixel = pixel;
         s.patch = (u32)fo.patch;
         segs[first + k] = s;
@@ -521,6 +526,8 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
                                                    const u32 *queue, const QueueState *qs, int klass,
                                                    u32 *qnext, float4 *results, u64 *ctr) {
     using K = RKF<R>;
+    __shared__ TfLds tfl;
+    tf_stage(fp, tfl);
     const u32 qcount = qs->qcount[klass];
     const Arrays<R> ar = arrays_of(m, R(0));
     const R tol = sizeof(R) == 4 ? R(fp.rk_tol) : R(fp.rk_told);
@@ -534,11 +541,16 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
     u32 sid = 0;
     PatchView<R> pv;
     R p[3] = {0, 0, 0}, gin[3] = {0, 0, 0}, d[3] = {0, 0, 0};
-    R s = 0, L = 0, h = 0, h_prev = 0, rho_prev = 0, m_prev = 0, rho_out = 0, m_out = 0;
+    R s = 0, L = 0, Lend = 0, h = 0, h_prev = 0, rho_prev = 0, m_prev = 0, rho_out = 0, m_out = 0;
     R C[3] = {0, 0, 0}, A = 0;
     bool pending = false, fresh = false;
     int iters = 0;
-    u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_cap = 0, c_sub = 0;
+    // Eq. (degeneracyfix) state: shrink > 0 (the attempt) while Newton seeks the
+    // preimage of the entry moved delta along the ray; gin is then that point (it
+    // stays on the ray, so V keeps its meaning)
+    int shrink = 0, newton_it = 0;
+    R delta = 0, rho_in = 0;
+    u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_cap = 0, c_sub = 0, c_deg = 0;
 
     for (;;) {
         // refill idle lanes from the queue (one atomic per wave)
@@ -569,10 +581,15 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
                     h = L < hmax ? L : hmax;
                     rho_out = sg.rho_out;
                     m_out = sg.drho_out;
+                    // singular J at the exit (flagged by a NaN slope): stop 1e-4 of
+                    // the chord short of it and close with the exit's rho
+                    Lend = isfinite(m_out) ? L : L - R(1e-4) * L;
+                    c_deg += !isfinite(m_out);
                     C[0] = C[1] = C[2] = A = R(0);
                     pending = false;
                     fresh = true;
                     iters = 0;
+                    shrink = 0;
                     active = true;
                 }
             }
@@ -581,34 +598,102 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
         if (!active) continue;
 
         bool done = false;
-        // stage 1 at the current point; also samples rho and d rho/ds there
-        R k1[3], k2[3], k3[3], k4[3], k5[3], k6[3], rho_cur = R(0), grho[3];
-        eval_W<P, RAT, 2>(pv, ar, p, gin, d, cperp, dthr, k1, rho_cur, grho, c_fp64);
+        // stage 1 at the current point; also samples rho and d rho/ds there.  While
+        // shrinking, the same evaluation gives the Newton step J^-1 (gin - phi(p)).
+        R k1[3], k2[3], k3[3], k4[3], k5[3], k6[3], rho_cur = R(0), grho[3], res2 = R(0);
+        const bool shrinking = shrink != 0;
+        const R det1 = eval_W<P, RAT, 2>(pv, ar, p, gin, d, cperp, dthr, k1, rho_cur,
+                                         grho, c_fp64, shrinking, res2);
         ++c_w;
         const R m_cur = dot3(grho, k1);
-        if (fresh) {
+        if (shrinking) {
+            // Eq. (degeneracyfix): Newton on phi(p) = gin, iterates clamped to P
+            const R tolx = (sizeof(R) == 4 ? R(2e-6) : R(1e-12)) * R(fp.scaled);
+            if (res2 <= tolx * tolx && fabs(det1) >= dthr) {
+                // the sliver [0, delta]: rho linear from the entry to the new entry
+                const R sl = (rho_cur - rho_in) / delta;
+                composite(fp, tfl, rho_in, sl, rho_cur, sl, delta, C, A, c_sub);
+                ++c_samp;
+                s = delta;
+                shrink = 0;
+                fresh = true;          // restart the ODE from the new entry
+            } else if (++newton_it < 16 && isfinite(k1[0] + k1[1] + k1[2])) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) p[c] = clamp01(p[c] + k1[c]);
+            } else if (shrink < 3) {
+                // grow delta tenfold and seed again
+                const Seg<R> &sg = segs[sid];
+                ++shrink;
+                delta *= R(10);
+                R dp[3], nrm;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dp[c] = sg.p_out[c] - sg.p_in[c];
+                nrm = sqrt(dot3(dp, dp));
+                const R eps = sqrt(delta / L);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    gin[c] += R(0.9) * delta * d[c];   // from the previous delta to this one
+                    p[c] = clamp01(sg.p_in[c] + eps * (nrm > R(0) ? dp[c] : R(0.5) - sg.p_in[c]));
+                }
+                newton_it = 0;
+            } else {
+                // no regular point near the entry: rho linear over the whole chord
+                const R sl = (rho_out - rho_in) / L;
+                composite(fp, tfl, rho_in, sl, rho_out, sl, L, C, A, c_sub);
+                ++c_samp;
+                done = true;
+            }
+        } else if (fresh) {
+            fresh = false;
+            if (!(L > R(1e-7) * R(fp.scaled))) {
+                done = true;   // empty chord
+            } else if (s == R(0) && !(fabs(det1) >= dthr)) {
+                // Eq. (degeneracyfix): J_phi singular at the entry.  Move the entry
+                // delta = 1e-4 L along the ray (tenfold more, up to twice, if Newton
+                // fails) and find its preimage by Newton from
+                // x0 = p_in + eps (p_out - p_in)/|p_out - p_in|, eps = sqrt(delta/L)
+                // |p_out - p_in| (the offset of a map whose normal derivative vanishes
+                // to first order at the face)
+                ++c_deg;
+                rho_in = rho_cur;
+                const Seg<R> &sg = segs[sid];
+                shrink = 1;
+                newton_it = 0;
+                delta = R(1e-4) * L;
+                R dp[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dp[c] = sg.p_out[c] - sg.p_in[c];
+                const R nrm = sqrt(dot3(dp, dp));
+                const R eps = sqrt(delta / L);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    gin[c] += delta * d[c];
+                    p[c] = clamp01(sg.p_in[c] + eps * (nrm > R(0) ? dp[c] : R(0.5) - sg.p_in[c]));
+                }
+            }
             rho_prev = rho_cur;
             m_prev = m_cur;
-            fresh = false;
-            if (!(L > R(1e-7) * R(fp.scaled))) done = true;   // empty chord
         } else if (pending) {
-            composite(fp, rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A, c_sub);
+            composite(fp, tfl, rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A, c_sub);
             ++c_samp;
             rho_prev = rho_cur;
             m_prev = m_cur;
             pending = false;
             if (A >= R(1) - early) done = true;
         }
-        if (!done) {
+        if (!done && !shrinking && !shrink) {
             // the transfer function's frequencies bound the step where rho changes
             const R dn_ds = fabs(m_cur) * R(fp.tf_inv_ranged);
-            const R hf = R(fp.tf_step) / (dn_ds * tf_slope_near(fp, rho_cur) + R(1e-30));
+            R slope;
+            if constexpr (sizeof(R) == 4) slope = tf_slope_near(fp, tfl, rho_cur);
+            else slope = tf_slope_near(fp, rho_cur);
+            const R hf = R(fp.tf_step) / (dn_ds * slope + R(1e-30));
             h = h < hf ? h : (hf > hmin ? hf : hmin);
-            const R hh = (h < L - s) ? h : (L - s);
-            R q[3], dummy, dg[3];
+            const R hh = (h < Lend - s) ? h : (Lend - s);
+            R q[3], dummy, dg[3], dr2;
 #define IVR_STAGE(KOUT, EXPR)                                                              \
     _Pragma("unroll") for (int c = 0; c < 3; ++c) q[c] = clamp01(p[c] + hh * (EXPR));      \
-    eval_W<P, RAT, 0>(pv, ar, q, gin, d, cperp, dthr, KOUT, dummy, dg, c_fp64);            \
+    eval_W<P, RAT, 0>(pv, ar, q, gin, d, cperp, dthr, KOUT, dummy, dg, c_fp64, false, dr2); \
     ++c_w;
             IVR_STAGE(k2, K::a21 * k1[c])
             IVR_STAGE(k3, K::a31 * k1[c] + K::a32 * k2[c])
@@ -625,14 +710,22 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
                                      K::b6 * k6[c]);
                 const R e = fabs(hh * (K::e1 * k1[c] + K::e3 * k3[c] + K::e4 * k4[c] +
                                        K::e5 * k5[c] + K::e6 * k6[c]));
-                err = e > err ? e : err;
+                err = (e > err || e != e) ? e : err;   // a non-finite stage rejects the step
             }
+            const bool finite = isfinite(err);
             const bool accept = (err <= tol) || (hh <= hmin);
             if (accept) {
                 s += hh;
-                if (L - s <= R(1e-6) * L) {
-                    // last step ends on the exit fragment: use its rho
-                    composite(fp, rho_prev, m_prev, rho_out, m_out, hh, C, A, c_sub);
+                if (!finite) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) p5[c] = p[c];   // at h_min: hold p
+                }
+                if (Lend - s <= R(1e-6) * L) {
+                    // last step ends on the exit fragment (or, at a singular exit,
+                    // 1e-4 of the chord short of it): close with the exit's rho
+                    const R hl = hh + (L - Lend);
+                    const R mo = isfinite(m_out) ? m_out : (rho_out - rho_prev) / hl;
+                    composite(fp, tfl, rho_prev, m_prev, rho_out, mo, hl, C, A, c_sub);
                     ++c_samp;
                     done = true;
                 } else {
@@ -646,7 +739,9 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
             }
             // step-size control for a 4(5) pair
             R fac = R(2.5);
-            if (err > R(0)) {
+            if (!finite) {
+                fac = R(0.2);
+            } else if (err > R(0)) {
                 fac = R(0.9) * pow_fifth(tol / err);
                 fac = fac < R(0.2) ? R(0.2) : (fac > R(2.5) ? R(2.5) : fac);
             }
@@ -671,6 +766,7 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
         flush_counter(ctr, C_FP64_SOLVES, c_fp64);
         flush_counter(ctr, C_RK_ITER_CAP, c_cap);
         flush_counter(ctr, C_SUBSAMPLES, c_sub);
+        flush_counter(ctr, C_DEGENERATE, c_deg);
     }
 }
 

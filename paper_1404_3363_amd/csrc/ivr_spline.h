@@ -60,6 +60,10 @@ __device__ __forceinline__ PatchView<R> view_of(const DevPatch &P) {
     return v;
 }
 
+// a / b: FP32 as a times the hardware reciprocal (1 ulp), FP64 exact.
+__device__ __forceinline__ float div_fast(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double div_fast(double a, double b) { return a / b; }
+
 template <typename R> __device__ __forceinline__ R clamp01(R v) {
     return v < R(0) ? R(0) : (v > R(1) ? R(1) : v);
 }
@@ -94,7 +98,7 @@ __device__ __forceinline__ int span_knots(R u_in, int n, int nspan, R inv_nspan,
 
 // The P+1 non-zero basis functions on the span and their first derivatives
 // (triangular evaluation of the recurrence; derivative from the degree P-1 row).
-template <int P, typename R>
+template <int P, typename R, bool FAST = false>
 __device__ __forceinline__ void basis_d1(R u, const R (&t)[2 * P], R (&N)[P + 1],
                                          R (&dN)[P + 1]) {
     R left[P + 1], right[P + 1], M[P + 1];
@@ -110,7 +114,7 @@ __device__ __forceinline__ void basis_d1(R u, const R (&t)[2 * P], R (&N)[P + 1]
         R saved = R(0);
 #pragma unroll
         for (int r = 0; r < j; ++r) {
-            R temp = N[r] / (right[r + 1] + left[j - r]);
+            R temp = FAST ? div_fast(N[r], right[r + 1] + left[j - r]) : N[r] / (right[r + 1] + left[j - r]);
             N[r] = saved + right[r + 1] * temp;
             saved = left[j - r] * temp;
         }
@@ -119,8 +123,8 @@ __device__ __forceinline__ void basis_d1(R u, const R (&t)[2 * P], R (&N)[P + 1]
 #pragma unroll
     for (int r = 0; r <= P; ++r) {
         R v = R(0);
-        if (r > 0) v += M[r - 1] / (t[P - 1 + r] - t[r - 1]);
-        if (r < P) v -= M[r] / (t[P + r] - t[r]);
+        if (r > 0) v += FAST ? div_fast(M[r - 1], t[P - 1 + r] - t[r - 1]) : M[r - 1] / (t[P - 1 + r] - t[r - 1]);
+        if (r < P) v -= FAST ? div_fast(M[r], t[P + r] - t[r]) : M[r] / (t[P + r] - t[r]);
         dN[r] = R(P) * v;
     }
 }
@@ -145,9 +149,9 @@ __device__ __forceinline__ void eval_volume(const PatchView<R> &pv, const Arrays
     const int sw = span_knots<P>(pc[2], pv.n[2], pv.nspan[2], pv.inv_nspan[2], pv.uniform & 4,
                                  ar.knots + pv.knot_off[2], tw);
     R Nu[P + 1], dNu[P + 1], Nv[P + 1], dNv[P + 1], Nw[P + 1], dNw[P + 1];
-    basis_d1<P>(pc[0], tu, Nu, dNu);
-    basis_d1<P>(pc[1], tv, Nv, dNv);
-    basis_d1<P>(pc[2], tw, Nw, dNw);
+    basis_d1<P, R, true>(pc[0], tu, Nu, dNu);
+    basis_d1<P, R, true>(pc[1], tv, Nv, dNv);
+    basis_d1<P, R, true>(pc[2], tw, Nw, dNw);
     constexpr int NC = RAT ? 4 : 3;
     const int n0 = pv.n[0], n01 = pv.n[0] * pv.n[1];
     const int base = pv.cp_off + (su - P) + n0 * (sv - P) + n01 * (sw - P);
@@ -175,7 +179,8 @@ __device__ __forceinline__ void eval_volume(const PatchView<R> &pv, const Arrays
                     A1[c] += dNu[i] * v[c];
                 }
                 if (RHO >= 1) {
-                    const R r = ar.rho[row + i];
+                    // B-spline blocks carry rho in the fourth lane of the point
+                    const R r = RAT ? ar.rho[row + i] : v[3];
                     rA += Nu[i] * r;
                     if (RHO == 2) rA1 += dNu[i] * r;
                 }
@@ -329,7 +334,7 @@ __device__ __forceinline__ R solve_cols(const R (&c0)[3], const R (&c1)[3], cons
     cross3(c2, c0, k20);
     cross3(c0, c1, k01);
     const R det = dot3(c0, k12);
-    const R inv = R(1) / det;
+    const R inv = div_fast(R(1), det);
     x[0] = dot3(r, k12) * inv;
     x[1] = dot3(r, k20) * inv;
     x[2] = dot3(r, k01) * inv;
@@ -338,32 +343,37 @@ __device__ __forceinline__ R solve_cols(const R (&c0)[3], const R (&c1)[3], cons
 
 // rho at p and its derivative along the ray, d rho/ds = grad rho . W with
 // J W = d (W on the ray itself, where V_perp vanishes).
+// Returns det J_phi(p).
 template <int P, bool RAT, typename R>
-__device__ __forceinline__ void eval_rho_ds(const PatchView<R> &pv, const Arrays<R> &ar,
-                                            const R (&p)[3], const R (&d)[3], R &rho, R &drho) {
+__device__ __forceinline__ R eval_rho_ds(const PatchView<R> &pv, const Arrays<R> &ar,
+                                         const R (&p)[3], const R (&d)[3], R &rho, R &drho) {
     R x[3], J[3][3], g[3];
     eval_volume<P, RAT, 2>(pv, ar, p, x, J, rho, g);
     R ju[3] = {J[0][0], J[1][0], J[2][0]}, jv[3] = {J[0][1], J[1][1], J[2][1]},
       jw[3] = {J[0][2], J[1][2], J[2][2]}, W[3];
     const R det = solve_cols(ju, jv, jw, d, W);
     drho = (det != R(0) && isfinite(det)) ? dot3(g, W) : R(0);
+    return det;
 }
 
 // Pulled-back ray field, Eq. (VgVp): J_phi(p) W = V(phi(p)) with
 // V(g) = V_par + c V_perp(g), V_perp(g) = (g_in - g) - <g_in - g, V_par> V_par (Eq. (vec2)).
 // The view ray itself gives V_par = d and g_in.  Returns the determinant of J;
 // near-singular systems are solved again in FP64.
+// With newton set, the right-hand side is r = gin - phi(p) instead, so W is the
+// Newton step of phi(p) = gin (Eq. (newtonsmethod)); res2 = |r|^2.
 template <int P, bool RAT, int RHO, typename R>
-__device__ __forceinline__ void eval_W(const PatchView<R> &pv, const Arrays<R> &ar, const R (&p)[3],
-                                       const R (&gin)[3], const R (&d)[3], R c, R det_thr, R (&W)[3],
-                                       R &rho, R (&grho)[3], uint32_t &n_fp64) {
+__device__ __forceinline__ R eval_W(const PatchView<R> &pv, const Arrays<R> &ar, const R (&p)[3],
+                                    const R (&gin)[3], const R (&d)[3], R c, R det_thr, R (&W)[3],
+                                    R &rho, R (&grho)[3], uint32_t &n_fp64, bool newton, R &res2) {
     R x[3], J[3][3];
     eval_volume<P, RAT, RHO>(pv, ar, p, x, J, rho, grho);
     R r[3] = {gin[0] - x[0], gin[1] - x[1], gin[2] - x[2]};
     const R rd = dot3(r, d);
+    res2 = dot3(r, r);
     R V[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) V[q] = d[q] + c * (r[q] - rd * d[q]);
+    for (int q = 0; q < 3; ++q) V[q] = newton ? r[q] : d[q] + c * (r[q] - rd * d[q]);
     R ju[3] = {J[0][0], J[1][0], J[2][0]}, jv[3] = {J[0][1], J[1][1], J[2][1]},
       jw[3] = {J[0][2], J[1][2], J[2][2]};
     const R det = solve_cols(ju, jv, jw, V, W);
@@ -374,6 +384,7 @@ __device__ __forceinline__ void eval_W(const PatchView<R> &pv, const Arrays<R> &
         W[0] = R(dW[0]); W[1] = R(dW[1]); W[2] = R(dW[2]);
         ++n_fp64;
     }
+    return det;
 }
 
 // Transfer function: value on the interval that contains n (exact piecewise
@@ -422,6 +433,55 @@ __device__ __forceinline__ void tf_eval(const FrameParams &fp, double rho, doubl
     for (int c = 0; c < 4; ++c) out[c] = v[c] + s[c] * dn;
 }
 
+// The transfer function as the integrator's workgroup keeps it in LDS: on
+// interval k (x_k <= n < x_{k+1}) channel c is a[k].c + b[k].c * n; smax[k] bounds
+// the slope on intervals k-1..k+1.
+struct TfLds {
+    float4 a[kMaxTfKnots];
+    float4 b[kMaxTfKnots];
+    float smax[kMaxTfKnots];
+};
+
+// One lane fills the table (static indices keep the kernel argument in SGPRs).
+__device__ __forceinline__ void tf_stage(const FrameParams &fp, TfLds &t) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kMaxTfKnots; ++k) {
+            const float x = fp.tf_x[k];
+            t.b[k] = make_float4(fp.tf_s[k][0], fp.tf_s[k][1], fp.tf_s[k][2], fp.tf_s[k][3]);
+            t.a[k] = make_float4(fp.tf_v[k][0] - fp.tf_s[k][0] * x, fp.tf_v[k][1] - fp.tf_s[k][1] * x,
+                                 fp.tf_v[k][2] - fp.tf_s[k][2] * x, fp.tf_v[k][3] - fp.tf_s[k][3] * x);
+            t.smax[k] = fp.tf_smax[k];
+        }
+    }
+    __syncthreads();
+}
+
+// Interval of n: the number of interior knots at or below it.
+__device__ __forceinline__ int tf_interval(const FrameParams &fp, float n) {
+    int k = 0;
+#pragma unroll
+    for (int m = 1; m < kMaxTfKnots - 1; ++m) k += (m < fp.tf_n - 1 && n >= fp.tf_x[m]) ? 1 : 0;
+    return k;
+}
+
+__device__ __forceinline__ void tf_eval(const FrameParams &fp, const TfLds &t, float rho, float (&out)[4]) {
+    const float n = clamp01((rho - fp.tf_lo) * fp.tf_inv_range);
+    const int k = tf_interval(fp, n);
+    const float4 a = t.a[k], b = t.b[k];
+    out[0] = a.x + b.x * n;
+    out[1] = a.y + b.y * n;
+    out[2] = a.z + b.z * n;
+    out[3] = a.w + b.w * n;
+}
+__device__ __forceinline__ void tf_eval(const FrameParams &fp, const TfLds &, double rho, double (&out)[4]) {
+    tf_eval(fp, rho, out);
+}
+
+__device__ __forceinline__ float tf_slope_near(const FrameParams &fp, const TfLds &t, float rho) {
+    return t.smax[tf_interval(fp, clamp01((rho - fp.tf_lo) * fp.tf_inv_range))];
+}
+
 // Slope bound of the transfer function around rho (per unit of n).
 template <typename R>
 __device__ __forceinline__ R tf_slope_near(const FrameParams &fp, R rho) {
@@ -447,8 +507,8 @@ __device__ __forceinline__ double fast_exp(double x) { return exp(x); }
 // normalised value n over the step (the transfer function's frequencies set the
 // sampling rate, not the spline), up to 64.
 template <typename R>
-__device__ __forceinline__ void composite(const FrameParams &fp, R ra, R ma, R rb, R mb, R len,
-                                          R (&C)[3], R &A, uint32_t &n_sub) {
+__device__ __forceinline__ void composite(const FrameParams &fp, const TfLds &tl, R ra, R ma, R rb,
+                                          R mb, R len, R (&C)[3], R &A, uint32_t &n_sub) {
     const R sa = fp.hermite ? ma * len : (rb - ra), sb = fp.hermite ? mb * len : (rb - ra);
     const R span = fmax(fabs(rb - ra), R(0.5) * (fabs(sa) + fabs(sb))) * R(fp.tf_inv_range);
     int ns = (int)ceil(span / R(fp.tf_dn));
@@ -462,7 +522,7 @@ __device__ __forceinline__ void composite(const FrameParams &fp, R ra, R ma, R r
         const R rho = (R(2) * t3 - R(3) * t2 + R(1)) * ra + (t3 - R(2) * t2 + tau) * sa +
                       (R(3) * t2 - R(2) * t3) * rb + (t3 - t2) * sb;
         R e[4];
-        tf_eval(fp, rho, e);
+        tf_eval(fp, tl, rho, e);
         const R T = fast_exp(-e[3] * dl);
         const R w = (R(1) - T) * (R(1) - A);
         C[0] += w * e[0];

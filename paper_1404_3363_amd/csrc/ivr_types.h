@@ -2,8 +2,9 @@
 //
 // Model (uploaded once, read-only while rendering):
 //   DevPatch[npatch]      per-block metadata and bounding boxes (one 16-B aligned record)
-//   cp32 / cp64           control points, float4 / double4 per point: (x,y,z,1) for
-//                         B-splines, homogeneous (wx,wy,wz,w) for NURBS; i fastest
+//   cp32 / cp64           control points, float4 / double4 per point: (x,y,z,rho) for
+//                         B-splines (the scalar coefficient rides in the fourth lane),
+//                         homogeneous (wx,wy,wz,w) for NURBS; i fastest
 //   rho32 / rho64         scalar coefficients (w*rho for NURBS), same order
 //   knots32 / knots64     knot vectors normalised to [0,1] (only read for
 //                         non-uniform directions)
@@ -100,7 +101,7 @@ struct Model {
 enum Counter : int {
     C_RAYS = 0, C_SEGMENTS, C_FRAGMENTS, C_ANOMALIES, C_FRAG_OVF, C_SEG_OVF, C_BOX_TESTS,
     C_FACE_NEWTON, C_FACE_NEWTON_ITER, C_FP64_POLISH, C_RK_STEPS, C_RK_REJECTED, C_SAMPLES,
-    C_W_EVALS, C_FP64_SOLVES, C_RK_ITER_CAP, C_MLP_QUERIES, C_SUBSAMPLES, C_COUNT
+    C_W_EVALS, C_FP64_SOLVES, C_RK_ITER_CAP, C_MLP_QUERIES, C_SUBSAMPLES, C_DEGENERATE, C_COUNT
 };
 
 // Queue bookkeeping written by the fragment kernel and read by the integrator.

@@ -56,7 +56,7 @@ class RenderOpts(C.Structure):
 STAT_FIELDS = ["rays", "segments", "fragments", "anomalies", "fragment_overflow",
                "segment_overflow", "box_tests", "face_newton", "face_newton_iter",
                "fp64_polish_iter", "rk_steps", "rk_rejected", "samples", "w_evals",
-               "fp64_solves", "rk_iter_cap", "mlp_queries", "subsamples"]
+               "fp64_solves", "rk_iter_cap", "mlp_queries", "subsamples", "degenerate"]
 
 
 class MlpOpts(C.Structure):

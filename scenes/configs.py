@@ -455,6 +455,35 @@ def _config5():
     return a, b, views
 
 
+def make_degenerate(constant_field: bool = False, width: int = 96, height: int = 96) -> Scene:
+    """A block with a degenerate boundary (Sec. "Degeneracies and Points Outside
+    Domain"): the unit cube as a degree-2 patch with 4^3 control points whose first
+    two layers in u coincide, so d phi/du = 0 and det J = 0 on the whole face u = 0
+    (x = 0), while the face itself is a regular unit square.  The geometry is still
+    exactly the unit cube.  rho is uniform [0,1] coefficients (seed 6002) or, with
+    constant_field, 0.5 everywhere.  Camera 0 looks at the face x = 0 from outside
+    (rays enter through the degenerate face), camera 1 from the opposite side
+    (rays leave through it)."""
+    p, n = (2, 2, 2), (4, 4, 4)
+    knots = [open_uniform_knots(4, 2)] * 3
+    gr = greville(knots[0], 2)                        # [0,.25,.75,1]
+    gu = gr.copy()
+    gu[1] = gu[0]                                     # layers i = 0 and 1 coincide
+    xyz = _grid_points(gu, gr, gr)
+    if constant_field:
+        scalar = np.full(64, 0.5)
+    else:
+        scalar = np.random.default_rng(np.random.PCG64(6002)).uniform(0.0, 1.0, 64)
+    patch = _make_patch(p, n, knots, xyz, scalar)
+    dom = [0.0, 1.0] if constant_field else scalar_domain([patch])
+    tf = random_tf(np.random.default_rng(np.random.PCG64(6003)), 4.0, dom)
+    cams = [camera_from_angles([0.5, 0.5, 0.5], 2.4, 180.0 + az, el, width, height)
+            for az, el in ((25.0, 15.0),)]
+    cams.append(camera_from_angles([0.5, 0.5, 0.5], 2.4, -20.0, -10.0, width, height))
+    return Scene("degenerate_face_cube", [patch], tf, cams, bbox_of([patch]),
+                 dict(precision="fp32", rk_tol=1e-5))
+
+
 def make_config(k: int, width: Optional[int] = None, height: Optional[int] = None):
     """Build config k (1..4) as a Scene; config 5 returns (model_a, model_b, views)."""
     if k == 1:

@@ -37,7 +37,7 @@ def test_struct_layouts_match_header():
     from paper_1404_3363_amd import ivr
     assert ctypes.sizeof(ivr.PatchDesc) == 6 * 4 + 3 * 8 + 8 + 8 + 8
     assert ctypes.sizeof(ivr.CameraDesc) == 10 * 8 + 8
-    assert ctypes.sizeof(ivr.Stats) == 18 * 8 + 3 * 8
+    assert ctypes.sizeof(ivr.Stats) == 19 * 8 + 3 * 8
 
 
 def test_create_without_gpu_reports_device_error():

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from scenes import make_config, camera_from_angles
+from scenes import make_config, make_degenerate, camera_from_angles
 from scenes.configs import Patch, TransferFunction
 
 pytestmark = pytest.mark.gpu
@@ -130,6 +130,46 @@ def test_constant_field_closed_form(renderer):
         assert abs(depth[pix] - t0) <= DEPTH_REL_TOL * t0
     print(f"[parity] constant field closed form: max err {worst:.3e}", flush=True)
     assert worst <= RGBA_TOL
+
+
+@pytest.mark.parametrize("view", [0, 1])
+def test_degenerate_face_full_image(renderer, view):
+    """J singular on a whole boundary face (first two control layers coincide):
+    rays that enter (view 0) or leave (view 1) through it are shrunk by
+    Eq. (degeneracyfix); full 96x96 image against the oracle, no NaN."""
+    sc = make_degenerate()
+    cam = sc.cameras[view]
+    print(f"[parity] degenerate face view {view}", flush=True)
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32")
+    assert np.isfinite(img).all()
+    ref = oracle.render(sc, cam, sc.tf)
+    _compare(f"degenerate face view{view} 96x96", img, depth, ref, scale=sc.scale)
+    print(f"[parity] degenerate face view {view}: shrunk segment ends {st['degenerate']}, "
+          f"fp64 solves {st['fp64_solves']}, iteration cap {st['rk_iter_cap']}", flush=True)
+    assert st["degenerate"] > 100 and st["rk_iter_cap"] == 0
+
+
+def test_degenerate_face_constant_field_closed_form(renderer):
+    """Constant rho on the degenerate-face cube: alpha = 1 - exp(-kappa L) with L
+    the ray-box chord of the unit cube, for both views."""
+    sc = make_degenerate(constant_field=True, width=40, height=40)
+    E = np.array([np.interp(0.5, sc.tf.x, sc.tf.rgba[:, c]) for c in range(4)])
+    kappa = 4.0 * E[3]
+    for view, cam in enumerate(sc.cameras):
+        img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32")
+        worst, hits = 0.0, 0
+        for pix in range(40 * 40):
+            o, d = oracle.camera_ray(cam, pix % 40 + 0.5, pix // 40 + 0.5)
+            t0, t1 = _box_chord(o, d)
+            if t0 is None:
+                continue
+            hits += 1
+            a = 1.0 - math.exp(-kappa * (t1 - t0))
+            worst = max(worst, abs(img[pix, 3] - a), np.abs(img[pix, :3] - E[:3] * a).max())
+            assert abs(depth[pix] - t0) <= DEPTH_REL_TOL * t0
+        print(f"[parity] degenerate constant field view {view}: max err {worst:.3e} "
+              f"({hits} rays, {st['degenerate']} shrunk)", flush=True)
+        assert worst <= RGBA_TOL and hits > 200
 
 
 @pytest.mark.parametrize("view", [0, 1, 2])
