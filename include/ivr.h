@@ -154,6 +154,16 @@ void ivr_default_opts(ivr_render_opts *o);
  * model invalidates a trained MLP. */
 ivr_status ivr_upload_patches(ivr_ctx *ctx, const ivr_patch_desc *patches, int32_t n);
 
+/* Uploads several models into one context (replacing the current ones): model m
+ * is the model_sizes[m] consecutive blocks that follow model m-1's in patches[].
+ * Views of a batch name the model they look at; blocks of different models never
+ * see each other (faces shared between blocks are only matched within a model).
+ * ivr_upload_patches(ctx, p, n) is ivr_upload_models with one model of n blocks.
+ * At most 2^20-1 blocks in all.  Same validation and failure behaviour as
+ * ivr_upload_patches. */
+ivr_status ivr_upload_models(ivr_ctx *ctx, const ivr_patch_desc *patches, int32_t n,
+                             const int32_t *model_sizes, int32_t n_models);
+
 /* Renders one view.  rgba_dev: width*height*4 floats (premultiplied RGBA over
  * transparent black, row-major, row 0 at the top); depth_dev: width*height
  * floats (ray parameter of the first entry, +inf where the ray misses) or NULL.
@@ -163,6 +173,55 @@ ivr_status ivr_upload_patches(ivr_ctx *ctx, const ivr_patch_desc *patches, int32
 ivr_status ivr_render(ivr_ctx *ctx, const ivr_camera *cam, const ivr_transfer_fn *tf,
                       const ivr_render_opts *opts, float *rgba_dev, float *depth_dev,
                       ivr_stats *stats);
+
+/* One view of a batch: camera, transfer function (NULL: the batch's), the model
+ * it looks at (index into the models of the last upload) and its caller-owned
+ * device outputs, laid out as for ivr_render. */
+typedef struct {
+    ivr_camera cam;
+    const ivr_transfer_fn *tf;
+    int32_t model;
+    float *rgba_dev;
+    float *depth_dev;
+} ivr_view;
+
+/* Renders 1..64 views of possibly different sizes and models with the same
+ * options in one pass of the hot path: one fragment launch over the tiles of all
+ * views, one persistent integrator launch per degree class over all their
+ * segments (a lane's segment may come from any view) and one merge.  Without
+ * stats and timing the launches are captured once per batch shape (view sizes
+ * and models, options, launch shapes) in a HIP graph and replayed; the cameras,
+ * transfer functions and output pointers travel in a device view table written
+ * before each replay, so a replay may change them.  With stats (or
+ * opts->timing) the kernels are launched directly and the counters and phase
+ * times cover the whole batch.  IVR_EINVAL for an empty or oversized batch, a
+ * missing rgba buffer or transfer function, or an unknown model. */
+ivr_status ivr_render_batch(ivr_ctx *ctx, const ivr_view *views, int32_t n_views,
+                            const ivr_transfer_fn *tf, const ivr_render_opts *opts, ivr_stats *stats);
+
+/* Launch shapes picked by ivr_autotune. */
+typedef struct {
+    int32_t tile_w, tile_h;     /* fragment-kernel tile (one 64-lane wave)            */
+    int32_t xcd_chunk;          /* > 0: runs of this many consecutive tiles per XCD   */
+    int32_t int_block;          /* integrator workgroup size                          */
+    int32_t int_waves_cu;       /* integrator waves per CU (0: as many as fit)        */
+    int32_t n_tried;
+    double tried_ms[32];        /* phase time of every shape tried, in order           */
+    double ms_before, ms_after; /* fragment + integrator time before and after         */
+} ivr_tune_report;
+
+/* Times the batch (three runs per shape, best kept) under every fragment tile
+ * shape (8x8, 16x4, 32x2) and XCD chunk (0, 4, 16), then every integrator workgroup size
+ * (64, 128, 256) and residency (all that fit, 16 or 8 waves per CU), keeps the
+ * fastest of each for this context (ivr_render and ivr_render_batch use them)
+ * and drops captured graphs.  Writes the views' outputs as a side effect. */
+ivr_status ivr_autotune(ivr_ctx *ctx, const ivr_view *views, int32_t n_views, const ivr_transfer_fn *tf,
+                        const ivr_render_opts *opts, ivr_tune_report *report);
+
+/* Sets the launch shapes by hand (tile_w 8, 16 or 32; xcd_chunk 0..4096; int_block
+ * 64, 128 or 256; int_waves_cu 0..64).  Results do not depend on them. */
+ivr_status ivr_set_launch(ivr_ctx *ctx, int32_t tile_w, int32_t xcd_chunk, int32_t int_block,
+                          int32_t int_waves_cu);
 
 /* ---- learned initialiser: one 3 -> 64 -> 64 -> 3 tanh MLP per block that maps a
  * world point (normalised by the block's box to [-1,1]^3) to its parameter point;

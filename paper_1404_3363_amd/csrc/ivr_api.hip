@@ -37,8 +37,25 @@ struct ivr_ctx {
     int npatch = 0, nelem = 0;
     double scale = 1.0;
     uint32_t class_mask = 0;
+    struct ModelRange {
+        int begin, end;          // patches [begin, end)
+        double scale;            // bounding-box diagonal of its control points
+        uint32_t class_mask;     // degree classes present
+    };
+    std::vector<ModelRange> models;
+    // batch view table: device copy and pinned host staging (grow-only)
+    ViewRec *d_views = nullptr;
+    ViewRec *h_views = nullptr;
+    int view_cap = 0;
+    hipEvent_t views_copied = nullptr;   // the staging buffer may be rewritten after it
+    hipStream_t capture = nullptr;       // private stream the batch graphs are captured on
+    // launch shapes (autotuned) and captured batch graphs keyed by their shape
+    LaunchCfg lc = {8, 0, 256, 0};
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    unsigned long long generation = 0;   // bumps when buffers move (graphs hold pointers)
     // frame buffers
     size_t pix_cap = 0, seg_cap = 0, seg_bytes_cap = 0;
+    int queue_slabs = 0;
     void *d_segs = nullptr;
     float4 *d_results = nullptr;
     uint2 *d_pixseg = nullptr;
@@ -341,6 +358,11 @@ ivr_status ivr_create(ivr_ctx **out, int32_t device, void *hip_stream) {
             ivr_destroy(c);
             return IVR_EDEVICE;
         }
+    if (hipEventCreateWithFlags(&c->views_copied, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
+        ivr_destroy(c);
+        return IVR_EDEVICE;
+    }
     *out = c;
     return IVR_OK;
 }
@@ -358,9 +380,17 @@ static void free_mlp(ivr_ctx *c) {
     c->mlp_trained = false;
 }
 
+static void drop_graphs(ivr_ctx *c) {
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    ++c->generation;
+}
+
 static void free_frame(ivr_ctx *c) {
+    drop_graphs(c);
     dfree(c->d_segs); dfree(c->d_results); dfree(c->d_pixseg); dfree(c->d_queues);
     c->pix_cap = c->seg_cap = c->seg_bytes_cap = 0;
+    c->queue_slabs = 0;
 }
 
 void ivr_destroy(ivr_ctx *c) {
@@ -372,6 +402,10 @@ void ivr_destroy(ivr_ctx *c) {
     free_mlp(c);
     dfree(c->d_qs);
     dfree(c->d_ctr);
+    dfree(c->d_views);
+    if (c->h_views) (void)hipHostFree(c->h_views);
+    if (c->views_copied) (void)hipEventDestroy(c->views_copied);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->tev)
@@ -380,24 +414,50 @@ void ivr_destroy(ivr_ctx *c) {
 }
 
 ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t n) {
+    return ivr_upload_models(c, patches, n, &n, 1);
+}
+
+ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t n,
+                             const int32_t *model_sizes, int32_t n_models) {
     if (!c) return IVR_EINVAL;
     if (!patches || n < 1) return fail(c, IVR_EINVAL, "need at least one patch");
+    if (n > (int32_t)kPatchMask) return fail(c, IVR_EINVAL, "more than 2^20-1 patches");
+    if (!model_sizes || n_models < 1) return fail(c, IVR_EINVAL, "need at least one model");
+    std::vector<ivr_ctx::ModelRange> models(n_models);
+    std::vector<int> model_of(n);
+    {
+        long long at = 0;
+        for (int mi = 0; mi < n_models; ++mi) {
+            if (model_sizes[mi] < 1) return fail(c, IVR_EINVAL, "every model needs at least one patch");
+            models[mi].begin = (int)at;
+            at += model_sizes[mi];
+            if (at > n) return fail(c, IVR_EINVAL, "model sizes exceed the number of patches");
+            models[mi].end = (int)at;
+            for (int i = models[mi].begin; i < models[mi].end; ++i) model_of[i] = mi;
+        }
+        if (at != n) return fail(c, IVR_EINVAL, "model sizes must add up to the number of patches");
+    }
     for (int i = 0; i < n; ++i) {
         std::string e = validate_patch(patches[i], i);
         if (!e.empty()) return fail(c, IVR_EINVAL, e);
     }
     IVR_HIP(c, hipSetDevice(c->device));
-    // scale: diagonal of the box of all (projected) control points
-    Box all;
-    for (int i = 0; i < n; ++i) {
-        const auto &P = patches[i];
-        const size_t N = (size_t)P.ncp[0] * P.ncp[1] * P.ncp[2];
-        for (size_t q = 0; q < N; ++q) all.add(P.cp + 4 * q);
+    // scale of each model: diagonal of the box of its (projected) control points
+    for (auto &M : models) {
+        Box all;
+        for (int i = M.begin; i < M.end; ++i) {
+            const auto &P = patches[i];
+            const size_t N = (size_t)P.ncp[0] * P.ncp[1] * P.ncp[2];
+            for (size_t q = 0; q < N; ++q) all.add(P.cp + 4 * q);
+        }
+        double diag = 0;
+        for (int q = 0; q < 3; ++q) diag += (all.hi[q] - all.lo[q]) * (all.hi[q] - all.lo[q]);
+        M.scale = std::max(std::sqrt(diag), 1e-30);
+        M.class_mask = 0;
+        for (int i = M.begin; i < M.end; ++i)
+            M.class_mask |= 1u << (2 * (patches[i].degree[0] - 1) + (patches[i].rational ? 1 : 0));
     }
-    double diag = 0;
-    for (int q = 0; q < 3; ++q) diag += (all.hi[q] - all.lo[q]) * (all.hi[q] - all.lo[q]);
-    const double scale = std::max(std::sqrt(diag), 1e-30);
-    const double pad = 1e-5 * scale;
+    const double scale = models[0].scale;
 
     std::vector<DevPatch> hp(n);
     std::vector<float4> cp32;
@@ -411,6 +471,7 @@ ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t
         const auto &P = patches[pi];
         DevPatch &D = hp[pi];
         std::memset(&D, 0, sizeof D);
+        const double pad = 1e-5 * models[model_of[pi]].scale;
         const int p = P.degree[0];
         D.deg = p;
         D.rational = P.rational ? 1 : 0;
@@ -537,7 +598,8 @@ ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t
             for (int f = 0; f < 6; ++f) {
                 const int dn = f >> 1, da = dn == 0 ? 1 : 0, db = dn == 2 ? 1 : 2;
                 const int fix = (f & 1) ? P.ncp[dn] - 1 : 0;
-                std::vector<double> key = {(double)p, (double)P.rational, (double)P.ncp[da], (double)P.ncp[db]};
+                std::vector<double> key = {(double)model_of[pi], (double)p, (double)P.rational,
+                                           (double)P.ncp[da], (double)P.ncp[db]};
                 for (int d : {da, db}) {
                     const double *t = P.knots[d];
                     const double t0 = t[p], t1 = t[P.ncp[d]];
@@ -584,17 +646,19 @@ ivr_status ivr_upload_patches(ivr_ctx *c, const ivr_patch_desc *patches, int32_t
     tmp.d_tiles = nullptr;
     tmp.d_patches = nullptr; tmp.d_cp32 = nullptr; tmp.d_rho32 = nullptr; tmp.d_cp64 = nullptr;
     tmp.d_rho64 = nullptr; tmp.d_knots32 = nullptr; tmp.d_knots64 = nullptr; tmp.d_elems = nullptr;
+    drop_graphs(c);
     c->npatch = n;
     c->nelem = (int)elems.size();
     c->scale = scale;
     c->class_mask = class_mask;
+    c->models = models;
     c->has_model = true;
     c->err.clear();
     return IVR_OK;
 }
 
 static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *tf,
-                             const ivr_render_opts &o, FrameParams &fp) {
+                             const ivr_render_opts &o, double scale, FrameParams &fp) {
     std::memset(&fp, 0, sizeof fp);
     if (!cam || !tf) return fail(c, IVR_EINVAL, "camera and transfer function are required");
     if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384)
@@ -707,8 +771,8 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
     fp.tf_step = (float)o.tf_step;
     if (o.max_newton_iter < 1 || o.max_newton_iter > 100)
         return fail(c, IVR_EINVAL, "max_newton_iter outside 1..100");
-    const double hmax = o.h_max > 0 ? o.h_max : c->scale / 64.0;
-    const double hmin = std::max(1e-7 * c->scale, 1e-4 * hmax);
+    const double hmax = o.h_max > 0 ? o.h_max : scale / 64.0;
+    const double hmin = std::max(1e-7 * scale, 1e-4 * hmax);
     double tol = o.rk_tol;
     if (o.precision == IVR_PRECISION_FP32) tol = std::max(tol, 32.0 * 1.1920929e-7);
     fp.rk_told = tol; fp.rk_tol = (float)tol;
@@ -721,19 +785,20 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
     fp.max_frag = o.max_fragments;
     fp.hermite = o.rho_interp == IVR_RHO_HERMITE ? 1 : 0;
     fp.max_newton = o.max_newton_iter;
-    fp.scaled = c->scale;
-    fp.scale = (float)c->scale;
+    fp.scaled = scale;
+    fp.scale = (float)scale;
     return IVR_OK;
 }
 
 static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
     const size_t seg_cap = pixels * kSegCap;
     const size_t seg_bytes = seg_cap * (fp64 ? sizeof(Seg<double>) : sizeof(Seg<float>));
-    if (pixels <= c->pix_cap && seg_bytes <= c->seg_bytes_cap) return IVR_OK;
+    // one queue slab per degree class present in the uploaded models (a batch
+    // numbers its classes in class order, so it needs at most this many)
+    const int ncls = std::max(1, __builtin_popcount(c->class_mask));
+    if (pixels <= c->pix_cap && seg_bytes <= c->seg_bytes_cap && ncls <= c->queue_slabs) return IVR_OK;
     IVR_HIP(c, hipStreamSynchronize(c->stream));
     free_frame(c);
-    int ncls = 0;
-    for (int k = 0; k < kClasses; ++k) ncls += 1;  // one slab per class (indexed by class)
     if (hipMalloc(&c->d_segs, seg_bytes) != hipSuccess ||
         hipMalloc((void **)&c->d_results, sizeof(float4) * seg_cap) != hipSuccess ||
         hipMalloc((void **)&c->d_pixseg, sizeof(uint2) * pixels) != hipSuccess ||
@@ -744,27 +809,30 @@ static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
     c->pix_cap = pixels;
     c->seg_cap = seg_cap;
     c->seg_bytes_cap = seg_bytes;
+    c->queue_slabs = ncls;
     return IVR_OK;
 }
 
-ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *tf,
-                      const ivr_render_opts *opts, float *rgba_dev, float *depth_dev, ivr_stats *stats) {
-    if (!c) return IVR_EINVAL;
-    if (!c->has_model) return fail(c, IVR_ESTATE, "no model uploaded");
-    if (!rgba_dev) return fail(c, IVR_EINVAL, "rgba_dev is NULL");
-    ivr_render_opts o;
-    ivr_default_opts(&o);
-    if (opts) o = *opts;
-    FrameParams fp;
-    ivr_status st = make_frame(c, cam, tf, o, fp);
-    if (st != IVR_OK) return st;
-    fp.collect = stats ? 1 : 0;
-    const bool fp64 = o.precision == IVR_PRECISION_FP64;
-    IVR_HIP(c, hipSetDevice(c->device));
-    const size_t pixels = (size_t)cam->width * cam->height;
-    if (pixels * kSegCap > 0xFFFFFFFFull) return fail(c, IVR_EOVERFLOW, "image too large for 32-bit segment indices");
-    st = ensure_frame(c, pixels, fp64);
-    if (st != IVR_OK) return st;
+static ivr_status ensure_views(ivr_ctx *c, int n) {
+    if (n <= c->view_cap) return IVR_OK;
+    IVR_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    dfree(c->d_views);
+    if (c->h_views) (void)hipHostFree(c->h_views);
+    c->h_views = nullptr;
+    c->view_cap = 0;
+    const int cap = std::max(n, 8);
+    if (hipMalloc((void **)&c->d_views, sizeof(ViewRec) * cap) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_views, sizeof(ViewRec) * cap) != hipSuccess) {
+        dfree(c->d_views);
+        c->h_views = nullptr;
+        return fail(c, IVR_ENOMEM, "view table allocation failed");
+    }
+    c->view_cap = cap;
+    return IVR_OK;
+}
+
+static Model device_model(ivr_ctx *c) {
     Model m;
     m.patches = c->d_patches; m.cp32 = c->d_cp32; m.rho32 = c->d_rho32; m.cp64 = c->d_cp64;
     m.rho64 = c->d_rho64; m.knots32 = c->d_knots32; m.knots64 = c->d_knots64; m.elems = c->d_elems;
@@ -772,11 +840,122 @@ ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *
     m.mlp_wb = c->mlp.wb;
     m.mlp_norm = c->mlp.norm;
     m.npatch = c->npatch; m.scale = (float)c->scale; m.scaled = c->scale;
-    // events for this render: the stats set, or the next timing slot
-    hipEvent_t *ev = nullptr;
+    return m;
+}
+
+namespace {
+struct HostView {
+    const ivr_camera *cam;
+    const ivr_transfer_fn *tf;
+    int model;
+    float *rgba, *depth;
+};
+struct Batch {
+    int n = 0;
+    uint32_t n_tiles = 0, n_pixels = 0, class_mask = 0;
+    bool fp64 = false, mlp = false, collect = false;
+};
+}  // namespace
+
+// Validates the views, fills the pinned view table and sizes the frame buffers.
+static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr_render_opts &o,
+                                bool collect, const LaunchCfg &lc, Batch &b) {
+    if (!c->has_model) return fail(c, IVR_ESTATE, "no model uploaded");
+    if (n < 1 || n > 64) return fail(c, IVR_EINVAL, "a batch holds 1..64 views");
+    IVR_HIP(c, hipSetDevice(c->device));
+    ivr_status st = ensure_views(c, n);
+    if (st != IVR_OK) return st;
+    // the staging buffer is still being read by the previous batch's copy
+    IVR_HIP(c, hipEventSynchronize(c->views_copied));
+    b = Batch();
+    b.n = n;
+    b.fp64 = o.precision == IVR_PRECISION_FP64;
+    b.mlp = o.seed_mode == IVR_SEED_MLP;
+    b.collect = collect;
+    const int th = 64 / lc.tile_w;
+    uint64_t tiles = 0, pixels = 0;
+    for (int v = 0; v < n; ++v) {
+        if (!hv[v].rgba) return fail(c, IVR_EINVAL, "a view has no rgba buffer");
+        if (hv[v].model < 0 || hv[v].model >= (int)c->models.size())
+            return fail(c, IVR_EINVAL, "a view names a model that was not uploaded");
+        const auto &M = c->models[hv[v].model];
+        ViewRec &r = c->h_views[v];
+        std::memset(&r, 0, sizeof r);
+        st = make_frame(c, hv[v].cam, hv[v].tf, o, M.scale, r.fp);
+        if (st != IVR_OK) return st;
+        r.fp.collect = collect ? 1 : 0;
+        r.patch_begin = M.begin;
+        r.patch_end = M.end;
+        r.tiles_x = (uint32_t)((hv[v].cam->width + lc.tile_w - 1) / lc.tile_w);
+        r.tile_begin = (uint32_t)tiles;
+        r.pix_begin = (uint32_t)pixels;
+        r.rgba = hv[v].rgba;
+        r.depth = hv[v].depth;
+        tiles += (uint64_t)r.tiles_x * ((hv[v].cam->height + th - 1) / th);
+        pixels += (uint64_t)hv[v].cam->width * hv[v].cam->height;
+        b.class_mask |= M.class_mask;
+    }
+    if (pixels * kSegCap > 0xFFFFFFFFull || tiles > 0x7FFFFFFFull)
+        return fail(c, IVR_EOVERFLOW, "batch too large for 32-bit segment indices");
+    b.n_tiles = (uint32_t)tiles;
+    b.n_pixels = (uint32_t)pixels;
+    return ensure_frame(c, pixels, b.fp64);
+}
+
+// The launches of one batch: clear, fragments, one integrator per degree class, merge.
+static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const LaunchCfg &lc, hipEvent_t *ev,
+                               hipStream_t s) {
+    const Model m = device_model(c);
+    IVR_HIP(c, launch_clear(c->d_qs, c->d_ctr, b.collect, s));
+    if (ev) IVR_HIP(c, hipEventRecord(ev[0], s));
+    IVR_HIP(c, launch_fragments(b.fp64, b.mlp, m, c->d_views, b.n, b.n_tiles, lc, c->d_segs,
+                                (uint32_t)c->seg_cap, c->d_queues, (uint32_t)c->seg_cap, b.class_mask,
+                                c->d_qs, c->d_pixseg, c->d_ctr, s));
+    if (ev) IVR_HIP(c, hipEventRecord(ev[1], s));
+    for (int k = 0; k < kClasses; ++k) {
+        if (!((b.class_mask >> k) & 1)) continue;
+        IVR_HIP(c, launch_integrate(b.fp64, k, m, c->d_views, b.n, c->d_segs,
+                                    c->d_queues + (size_t)__builtin_popcount(b.class_mask & ((1u << k) - 1u)) *
+                                                      c->seg_cap,
+                                    c->d_qs, &c->d_qs->qnext[k],
+                                    c->d_results, c->d_ctr, c->n_cu, lc, s));
+    }
+    if (ev) IVR_HIP(c, hipEventRecord(ev[2], s));
+    IVR_HIP(c, launch_merge(c->d_views, b.n, b.n_pixels, c->d_pixseg, c->d_results, s));
+    if (ev) IVR_HIP(c, hipEventRecord(ev[3], s));
+    return IVR_OK;
+}
+
+static ivr_status copy_views(ivr_ctx *c, int n) {
+    IVR_HIP(c, hipMemcpyAsync(c->d_views, c->h_views, sizeof(ViewRec) * n, hipMemcpyHostToDevice,
+                              c->stream));
+    IVR_HIP(c, hipEventRecord(c->views_copied, c->stream));
+    return IVR_OK;
+}
+
+static ivr_status read_stats(ivr_ctx *c, ivr_stats *stats) {
+    unsigned long long h[C_COUNT];
+    IVR_HIP(c, hipMemcpyAsync(h, c->d_ctr, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    IVR_HIP(c, hipStreamSynchronize(c->stream));
+    std::memset(stats, 0, sizeof *stats);
+    uint64_t *dst = &stats->rays;
+    for (int k = 0; k < C_COUNT; ++k) dst[k] = h[k];
+    float ms;
+    IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    stats->ms_fragments = ms;
+    IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+    stats->ms_integrate = ms;
+    IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+    stats->ms_merge = ms;
+    return IVR_OK;
+}
+
+// Events of this render: the stats set, or the next timing slot, or none.
+static ivr_status pick_events(ivr_ctx *c, bool stats, bool timing, hipEvent_t *&ev) {
+    ev = nullptr;
     if (stats) {
         ev = c->ev;
-    } else if (o.timing) {
+    } else if (timing) {
         if (c->n_timed >= 4096) return fail(c, IVR_EOVERFLOW, "more than 4096 timed renders pending");
         while ((int)c->tev.size() < 4 * (c->n_timed + 1)) {
             hipEvent_t e;
@@ -786,37 +965,190 @@ ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *
         ev = &c->tev[4 * c->n_timed];
         ++c->n_timed;
     }
-    IVR_HIP(c, hipMemsetAsync(c->d_qs, 0, sizeof(QueueState), c->stream));
-    if (stats) IVR_HIP(c, hipMemsetAsync(c->d_ctr, 0, sizeof(unsigned long long) * C_COUNT, c->stream));
-    if (ev) IVR_HIP(c, hipEventRecord(ev[0], c->stream));
-    IVR_HIP(c, launch_fragments(fp64, m, fp, c->d_segs, (uint32_t)c->seg_cap, c->d_queues,
-                                (uint32_t)c->seg_cap, c->class_mask, c->d_qs, c->d_pixseg, depth_dev,
-                                c->d_ctr, c->stream));
-    if (ev) IVR_HIP(c, hipEventRecord(ev[1], c->stream));
-    for (int k = 0; k < kClasses; ++k) {
-        if (!((c->class_mask >> k) & 1)) continue;
-        IVR_HIP(c, launch_integrate(fp64, k, m, fp, c->d_segs, c->d_queues + (size_t)k * c->seg_cap,
-                                    c->d_qs, &c->d_qs->qnext[k], c->d_results, c->d_ctr, c->n_cu,
-                                    c->stream));
+    return IVR_OK;
+}
+
+// Direct launches (no graph) of a batch of host views.
+static ivr_status render_direct(ivr_ctx *c, const HostView *hv, int n, const ivr_render_opts &o,
+                                ivr_stats *stats, const LaunchCfg &lc) {
+    Batch b;
+    ivr_status st = prepare_batch(c, hv, n, o, stats != nullptr, lc, b);
+    if (st != IVR_OK) return st;
+    hipEvent_t *ev;
+    st = pick_events(c, stats != nullptr, o.timing != 0, ev);
+    if (st != IVR_OK) return st;
+    st = copy_views(c, n);
+    if (st != IVR_OK) return st;
+    st = launch_batch(c, b, lc, ev, c->stream);
+    if (st != IVR_OK) return st;
+    if (stats) return read_stats(c, stats);
+    return IVR_OK;
+}
+
+ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *tf,
+                      const ivr_render_opts *opts, float *rgba_dev, float *depth_dev, ivr_stats *stats) {
+    if (!c) return IVR_EINVAL;
+    if (!rgba_dev) return fail(c, IVR_EINVAL, "rgba_dev is NULL");
+    ivr_render_opts o;
+    ivr_default_opts(&o);
+    if (opts) o = *opts;
+    const HostView hv = {cam, tf, 0, rgba_dev, depth_dev};
+    ivr_status st = render_direct(c, &hv, 1, o, stats, c->lc);
+    if (st == IVR_OK) c->err.clear();
+    return st;
+}
+
+ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
+                            const ivr_transfer_fn *tf, const ivr_render_opts *opts, ivr_stats *stats) {
+    if (!c) return IVR_EINVAL;
+    if (!views || n_views < 1 || n_views > 64) return fail(c, IVR_EINVAL, "a batch holds 1..64 views");
+    ivr_render_opts o;
+    ivr_default_opts(&o);
+    if (opts) o = *opts;
+    std::vector<HostView> hv(n_views);
+    for (int v = 0; v < n_views; ++v) {
+        hv[v] = {&views[v].cam, views[v].tf ? views[v].tf : tf, views[v].model, views[v].rgba_dev,
+                 views[v].depth_dev};
+        if (!hv[v].tf) return fail(c, IVR_EINVAL, "a view has no transfer function");
     }
-    if (ev) IVR_HIP(c, hipEventRecord(ev[2], c->stream));
-    IVR_HIP(c, launch_merge(fp, c->d_pixseg, c->d_results, rgba_dev, c->stream));
-    if (ev) IVR_HIP(c, hipEventRecord(ev[3], c->stream));
-    if (stats) {
-        unsigned long long h[C_COUNT];
-        IVR_HIP(c, hipMemcpyAsync(h, c->d_ctr, sizeof h, hipMemcpyDeviceToHost, c->stream));
-        IVR_HIP(c, hipStreamSynchronize(c->stream));
-        std::memset(stats, 0, sizeof *stats);
-        uint64_t *dst = &stats->rays;
-        for (int k = 0; k < C_COUNT; ++k) dst[k] = h[k];
-        float ms;
-        IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-        stats->ms_fragments = ms;
-        IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
-        stats->ms_integrate = ms;
-        IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
-        stats->ms_merge = ms;
+    ivr_status st;
+    if (stats || o.timing) {
+        // counters and phase events need the launches one by one
+        st = render_direct(c, hv.data(), n_views, o, stats, c->lc);
+        if (st == IVR_OK) c->err.clear();
+        return st;
     }
+    Batch b;
+    st = prepare_batch(c, hv.data(), n_views, o, false, c->lc, b);
+    if (st != IVR_OK) return st;
+    // the graph holds every kernel argument except what the view table carries
+    // (cameras, transfer functions, output pointers): key it by the rest
+    std::vector<int64_t> key = {(int64_t)c->generation, b.n, b.fp64, b.mlp, (int64_t)b.class_mask,
+                                c->lc.tile_w, c->lc.xcd_chunk, c->lc.int_block, c->lc.int_waves_cu};
+    for (int v = 0; v < n_views; ++v) {
+        key.push_back(hv[v].cam->width);
+        key.push_back(hv[v].cam->height);
+        key.push_back(hv[v].model);
+    }
+    st = copy_views(c, n_views);
+    if (st != IVR_OK) return st;
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        // captured on the context's private stream (the render stream may be the
+        // null stream, which cannot capture), replayed on the render stream
+        hipGraph_t g = nullptr;
+        IVR_HIP(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+        st = launch_batch(c, b, c->lc, nullptr, c->capture);
+        hipError_t e = hipStreamEndCapture(c->capture, &g);
+        if (st != IVR_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(c, IVR_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t ge = nullptr;
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(c, IVR_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        it = c->graphs.emplace(key, ge).first;
+    }
+    IVR_HIP(c, hipGraphLaunch(it->second, c->stream));
+    c->err.clear();
+    return IVR_OK;
+}
+
+ivr_status ivr_autotune(ivr_ctx *c, const ivr_view *views, int32_t n_views, const ivr_transfer_fn *tf,
+                        const ivr_render_opts *opts, ivr_tune_report *report) {
+    if (!c) return IVR_EINVAL;
+    if (!views || n_views < 1 || n_views > 64) return fail(c, IVR_EINVAL, "a batch holds 1..64 views");
+    ivr_render_opts o;
+    ivr_default_opts(&o);
+    if (opts) o = *opts;
+    o.timing = 0;
+    std::vector<HostView> hv(n_views);
+    for (int v = 0; v < n_views; ++v) {
+        hv[v] = {&views[v].cam, views[v].tf ? views[v].tf : tf, views[v].model, views[v].rgba_dev,
+                 views[v].depth_dev};
+        if (!hv[v].tf) return fail(c, IVR_EINVAL, "a view has no transfer function");
+    }
+    // time a shape: best of `reps` batches, per phase, from the stats events
+    auto measure = [&](const LaunchCfg &lc, double &ms_frag, double &ms_int) -> ivr_status {
+        ms_frag = ms_int = INFINITY;
+        for (int r = 0; r < 3; ++r) {
+            ivr_stats s;
+            ivr_status st = render_direct(c, hv.data(), n_views, o, &s, lc);
+            if (st != IVR_OK) return st;
+            ms_frag = std::min(ms_frag, s.ms_fragments);
+            ms_int = std::min(ms_int, s.ms_integrate);
+        }
+        return IVR_OK;
+    };
+    ivr_tune_report rep;
+    std::memset(&rep, 0, sizeof rep);
+    LaunchCfg best = c->lc;
+    double f0, i0;
+    ivr_status st = measure(best, f0, i0);   // also warms up
+    if (st != IVR_OK) return st;
+    st = measure(best, f0, i0);
+    if (st != IVR_OK) return st;
+    rep.ms_before = f0 + i0;
+    // fragment kernel: tile shape and tile order (its time does not depend on the
+    // integrator's shape, nor the integrator's on these)
+    double bf = f0;
+    for (int tw : {8, 16, 32})
+        for (int xo : {0, 4, 16}) {
+            LaunchCfg lc = best;
+            lc.tile_w = tw;
+            lc.xcd_chunk = xo;
+            double f, i;
+            st = measure(lc, f, i);
+            if (st != IVR_OK) return st;
+            if (rep.n_tried < 32) rep.tried_ms[rep.n_tried++] = f;
+            if (f < bf) {
+                bf = f;
+                best.tile_w = tw;
+                best.xcd_chunk = xo;
+            }
+        }
+    // integrator: workgroup size and resident waves per CU (the queue consumers)
+    double bi = INFINITY;
+    for (int blk : {64, 128, 256})
+        for (int wpc : {0, 16, 8}) {
+            LaunchCfg lc = best;
+            lc.int_block = blk;
+            lc.int_waves_cu = wpc;
+            double f, i;
+            st = measure(lc, f, i);
+            if (st != IVR_OK) return st;
+            if (rep.n_tried < 32) rep.tried_ms[rep.n_tried++] = i;
+            if (i < bi) {
+                bi = i;
+                best.int_block = blk;
+                best.int_waves_cu = wpc;
+            }
+        }
+    c->lc = best;
+    drop_graphs(c);
+    rep.tile_w = best.tile_w;
+    rep.tile_h = 64 / best.tile_w;
+    rep.xcd_chunk = best.xcd_chunk;
+    rep.int_block = best.int_block;
+    rep.int_waves_cu = best.int_waves_cu;
+    rep.ms_after = bf + bi;
+    if (report) *report = rep;
+    c->err.clear();
+    return IVR_OK;
+}
+
+ivr_status ivr_set_launch(ivr_ctx *c, int32_t tile_w, int32_t xcd_chunk, int32_t int_block,
+                          int32_t int_waves_cu) {
+    if (!c) return IVR_EINVAL;
+    if (tile_w != 8 && tile_w != 16 && tile_w != 32) return fail(c, IVR_EINVAL, "tile_w must be 8, 16 or 32");
+    if (int_block != 64 && int_block != 128 && int_block != 256)
+        return fail(c, IVR_EINVAL, "int_block must be 64, 128 or 256");
+    if (int_waves_cu < 0 || int_waves_cu > 64) return fail(c, IVR_EINVAL, "int_waves_cu outside 0..64");
+    if (xcd_chunk < 0 || xcd_chunk > 4096) return fail(c, IVR_EINVAL, "xcd_chunk outside 0..4096");
+    c->lc = {tile_w, xcd_chunk, int_block, int_waves_cu};
+    drop_graphs(c);
     c->err.clear();
     return IVR_OK;
 }
@@ -945,6 +1277,7 @@ ivr_status ivr_train_inverse_mlp(ivr_ctx *c, const ivr_mlp_opts *opts, ivr_mlp_r
     cleanup();
     c->mlp_trained = true;
     c->err.clear();
+    drop_graphs(c);   // the graphs hold the MLP weight pointers
     return IVR_OK;
 }
 

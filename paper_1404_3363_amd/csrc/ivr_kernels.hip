@@ -19,6 +19,8 @@
 //   k_merge      per pixel: over-composites its segments front to back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ivr.h"
 #include "ivr_internal.h"
 #include "ivr_mlp_dev.h"
@@ -318,15 +320,45 @@ __device__ __forceinline__ u32 wave_incl_scan(u32 v, int lane) {
     return v;
 }
 
+// The view that owns batch tile g (views sorted by tile_begin; uniform per wave).
+__device__ __forceinline__ int view_of_tile(const ViewRec *views, int n_views, u32 g) {
+    int lo = 0, hi = n_views;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (__builtin_amdgcn_readfirstlane(views[mid].tile_begin) <= g) lo = mid;
+        else hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
 template <typename R, bool MLP>
-__global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R> *segs, u32 seg_cap,
+__global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views, int n_views,
+                                                  u32 n_tiles, LaunchCfg lc, Seg<R> *segs, u32 seg_cap,
                                                   u32 *queues, u32 queue_stride, u32 class_mask,
-                                                  QueueState *qs, uint2 *pixseg, float *depth,
-                                                  u64 *ctr) {
+                                                  QueueState *qs, uint2 *pixseg, u64 *ctr) {
     const int lane = threadIdx.x;
-    const int tiles_x = (fp.width + 7) >> 3;
-    const int px = (blockIdx.x % tiles_x) * 8 + (lane & 7);
-    const int py = (blockIdx.x / tiles_x) * 8 + (lane >> 3);
+    // Consecutive blocks are dealt round-robin to the 8 XCDs.  With xcd_chunk = C
+    // > 0, XCD x's j-th block takes tile j mod C of chunk (j / C) * 8 + x: runs of C
+    // neighbouring tiles (which test the same blocks and elements) share one XCD's
+    // L2, while the chunks still interleave over the image across XCDs (balance).
+    // Tiles past the last whole round of 8 C keep the plain order.
+    u32 g = blockIdx.x;
+    if (lc.xcd_chunk > 0) {
+        const u32 C = (u32)lc.xcd_chunk, full = (n_tiles / (8u * C)) * (8u * C);
+        if (g < full) {
+            const u32 x = g & 7u, j = g >> 3;
+            g = ((j / C) * 8u + x) * C + (j % C);
+        }
+    }
+    // the view is uniform over the wave: its record is read once through the
+    // scalar cache into a private copy (no reloads after the kernel's stores)
+    const int v = view_of_tile(views, n_views, g);
+    const ViewRec vr = views[v];
+    const FrameParams &fp = vr.fp;
+    const u32 tl = g - vr.tile_begin;
+    const int th = 64 / lc.tile_w;
+    const int px = (int)(tl % vr.tiles_x) * lc.tile_w + (lane % lc.tile_w);
+    const int py = (int)(tl / vr.tiles_x) * th + (lane / lc.tile_w);
     const bool valid = px < fp.width && py < fp.height;
     const u32 pixel = valid ? (u32)(py * fp.width + px) : 0u;
 
@@ -379,7 +411,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
         }
         ncand = 0;
     };
-    for (int pi = 0; pi < m.npatch; ++pi) {
+    for (int pi = vr.patch_begin; pi < vr.patch_end; ++pi) {
         const DevPatch &Pd = m.patches[pi];
         ++c_box;
         const bool hp = valid && slab(of, inv, Pd.box, Pd.box + 3);
@@ -464,7 +496,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
         if (!(fabs(det_out) >= (sizeof(R) == 4 ? R(fp.det_thr) : R(fp.det_thrd))))
             s.drho_out = R(NAN);
         s.pixel = pixel;
-        s.patch = (u32)fo.patch;
+        s.patch = (u32)fo.patch | ((u32)v << kViewShift);
         segs[first + k] = s;
     }
     // one queue per degree class
@@ -478,13 +510,14 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, FrameParams fp, Seg<R
         if (lane == 63 && ctot) cb = atomicAdd(&qs->qcount[c], ctot);
         cb = __shfl(cb, 63);
         u32 w = cb + ci - cnt;
-        u32 *qc = queues + (size_t)c * queue_stride;
+        // one queue slab per class present in the batch, in class order
+        u32 *qc = queues + (size_t)__popc(class_mask & ((1u << c) - 1u)) * queue_stride;
         for (int k = 0; k < nseg; ++k)
             if ((u32)m.patches[fr[pout[k]].patch].klass == (u32)c) qc[w++] = first + (u32)k;
     }
     if (valid) {
-        pixseg[pixel] = make_uint2(first, (u32)nseg);
-        if (depth) depth[pixel] = nseg ? float(fr[pin[0]].t) : INFINITY;
+        pixseg[vr.pix_begin + pixel] = make_uint2(first, (u32)nseg);
+        if (vr.depth) vr.depth[pixel] = nseg ? float(fr[pin[0]].t) : INFINITY;
     }
     if (fp.collect) {
         flush_counter(ctr, C_RAYS, valid ? 1 : 0);
@@ -521,24 +554,30 @@ struct RKF {
                        e5 = R(1) / R(50), e6 = R(2) / R(55);
 };
 
+// Three waves per SIMD: the FP32 kernels fit in 168 VGPRs without spilling.
 template <int P, bool RAT, typename R>
-__global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, const Seg<R> *segs,
-                                                   const u32 *queue, const QueueState *qs, int klass,
-                                                   u32 *qnext, float4 *results, u64 *ctr) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_integrate(Model m, const ViewRec *views, int n_views,
+                                                   const Seg<R> *segs, const u32 *queue,
+                                                   const QueueState *qs, int klass, u32 *qnext,
+                                                   float4 *results, u64 *ctr) {
     using K = RKF<R>;
-    __shared__ TfLds tfl;
-    tf_stage(fp, tfl);
+    // per-view transfer functions and step bounds in LDS (a lane's segment may
+    // belong to any view of the batch); the integrator options are the batch's
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    ViewLds *vls = reinterpret_cast<ViewLds *>(smem_raw);
+    view_stage(views, n_views, vls);
+    const FrameParams fp = views[0].fp;   // the batch's options (uniform)
     const u32 qcount = qs->qcount[klass];
     const Arrays<R> ar = arrays_of(m, R(0));
     const R tol = sizeof(R) == 4 ? R(fp.rk_tol) : R(fp.rk_told);
-    const R hmax = sizeof(R) == 4 ? R(fp.h_max) : R(fp.h_maxd);
-    const R hmin = sizeof(R) == 4 ? R(fp.h_min) : R(fp.h_mind);
     const R cperp = sizeof(R) == 4 ? R(fp.c_perp) : R(fp.c_perpd);
     const R early = sizeof(R) == 4 ? R(fp.early_term) : R(fp.early_termd);
     const R dthr = sizeof(R) == 4 ? R(fp.det_thr) : R(fp.det_thrd);
 
     bool active = false, queue_empty = false;
     u32 sid = 0;
+    int vid = 0;                  // view of the lane's segment
+    R hmax = 0, hmin = 0, vscale = 0;
     PatchView<R> pv;
     R p[3] = {0, 0, 0}, gin[3] = {0, 0, 0}, d[3] = {0, 0, 0};
     R s = 0, L = 0, Lend = 0, h = 0, h_prev = 0, rho_prev = 0, m_prev = 0, rho_out = 0, m_out = 0;
@@ -566,16 +605,21 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
                 if (qi < qcount) {
                     sid = queue[qi];
                     const Seg<R> sg = segs[sid];
-                    pv = view_of<R>(m.patches[sg.patch]);
-                    const int pxl = (int)(sg.pixel % (u32)fp.width), pyl = (int)(sg.pixel / (u32)fp.width);
+                    vid = (int)(sg.patch >> kViewShift);
+                    pv = view_of<R>(m.patches[sg.patch & kPatchMask]);
+                    const FrameParams &fv = views[vid].fp;
+                    const int pxl = (int)(sg.pixel % (u32)fv.width), pyl = (int)(sg.pixel / (u32)fv.width);
                     double dd[3];
-                    ray_dir(fp, pxl, pyl, dd);
+                    ray_dir(fv, pxl, pyl, dd);
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         d[q] = R(dd[q]);
-                        gin[q] = R(fp.eye[q] + double(sg.t_in) * dd[q]);
+                        gin[q] = R(fv.eye[q] + double(sg.t_in) * dd[q]);
                         p[q] = sg.p_in[q];
                     }
+                    hmax = sizeof(R) == 4 ? R(vls[vid].h_max) : R(fv.h_maxd);
+                    hmin = sizeof(R) == 4 ? R(vls[vid].h_min) : R(fv.h_mind);
+                    vscale = sizeof(R) == 4 ? R(vls[vid].scale) : R(fv.scaled);
                     L = sg.t_out - sg.t_in;
                     s = R(0);
                     h = L < hmax ? L : hmax;
@@ -608,11 +652,11 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
         const R m_cur = dot3(grho, k1);
         if (shrinking) {
             // Eq. (degeneracyfix): Newton on phi(p) = gin, iterates clamped to P
-            const R tolx = (sizeof(R) == 4 ? R(2e-6) : R(1e-12)) * R(fp.scaled);
+            const R tolx = (sizeof(R) == 4 ? R(2e-6) : R(1e-12)) * vscale;
             if (res2 <= tolx * tolx && fabs(det1) >= dthr) {
                 // the sliver [0, delta]: rho linear from the entry to the new entry
                 const R sl = (rho_cur - rho_in) / delta;
-                composite(fp, tfl, rho_in, sl, rho_cur, sl, delta, C, A, c_sub);
+                composite(fp, views[vid].fp, vls[vid], rho_in, sl, rho_cur, sl, delta, C, A, c_sub);
                 ++c_samp;
                 s = delta;
                 shrink = 0;
@@ -639,13 +683,13 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
             } else {
                 // no regular point near the entry: rho linear over the whole chord
                 const R sl = (rho_out - rho_in) / L;
-                composite(fp, tfl, rho_in, sl, rho_out, sl, L, C, A, c_sub);
+                composite(fp, views[vid].fp, vls[vid], rho_in, sl, rho_out, sl, L, C, A, c_sub);
                 ++c_samp;
                 done = true;
             }
         } else if (fresh) {
             fresh = false;
-            if (!(L > R(1e-7) * R(fp.scaled))) {
+            if (!(L > R(1e-7) * vscale)) {
                 done = true;   // empty chord
             } else if (s == R(0) && !(fabs(det1) >= dthr)) {
                 // Eq. (degeneracyfix): J_phi singular at the entry.  Move the entry
@@ -674,7 +718,7 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
             rho_prev = rho_cur;
             m_prev = m_cur;
         } else if (pending) {
-            composite(fp, tfl, rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A, c_sub);
+            composite(fp, views[vid].fp, vls[vid], rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A, c_sub);
             ++c_samp;
             rho_prev = rho_cur;
             m_prev = m_cur;
@@ -683,10 +727,11 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
         }
         if (!done && !shrinking && !shrink) {
             // the transfer function's frequencies bound the step where rho changes
-            const R dn_ds = fabs(m_cur) * R(fp.tf_inv_ranged);
+            const R dn_ds = fabs(m_cur) * R(sizeof(R) == 4 ? double(vls[vid].inv_ranged)
+                                                            : views[vid].fp.tf_inv_ranged);
             R slope;
-            if constexpr (sizeof(R) == 4) slope = tf_slope_near(fp, tfl, rho_cur);
-            else slope = tf_slope_near(fp, rho_cur);
+            if constexpr (sizeof(R) == 4) slope = tf_slope_near(vls[vid], rho_cur);
+            else slope = tf_slope_near(views[vid].fp, rho_cur);
             const R hf = R(fp.tf_step) / (dn_ds * slope + R(1e-30));
             h = h < hf ? h : (hf > hmin ? hf : hmin);
             const R hh = (h < Lend - s) ? h : (Lend - s);
@@ -725,7 +770,7 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
                     // 1e-4 of the chord short of it): close with the exit's rho
                     const R hl = hh + (L - Lend);
                     const R mo = isfinite(m_out) ? m_out : (rho_out - rho_prev) / hl;
-                    composite(fp, tfl, rho_prev, m_prev, rho_out, mo, hl, C, A, c_sub);
+                    composite(fp, views[vid].fp, vls[vid], rho_prev, m_prev, rho_out, mo, hl, C, A, c_sub);
                     ++c_samp;
                     done = true;
                 } else {
@@ -770,14 +815,27 @@ __global__ __launch_bounds__(256) void k_integrate(Model m, FrameParams fp, cons
     }
 }
 
-__global__ __launch_bounds__(256) void k_merge(FrameParams fp, const uint2 *pixseg,
-                                               const float4 *results, float4 *rgba) {
-    const u32 pixel = blockIdx.x * 256u + threadIdx.x;
-    if (pixel >= (u32)(fp.width * fp.height)) return;
-    const uint2 ps = pixseg[pixel];
+// The view that owns batch pixel g (views sorted by pix_begin).
+__device__ __forceinline__ int view_of_pixel(const ViewRec *views, int n_views, u32 g) {
+    int lo = 0, hi = n_views;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (views[mid].pix_begin <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_merge(const ViewRec *views, int n_views, u32 n_pixels,
+                                               const uint2 *pixseg, const float4 *results) {
+    const u32 g = blockIdx.x * 256u + threadIdx.x;
+    if (g >= n_pixels) return;
+    const ViewRec &vr = views[view_of_pixel(views, n_views, g)];
+    const float early = views[0].fp.early_term;
+    const uint2 ps = pixseg[g];
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
     for (u32 k = 0; k < ps.y; ++k) {
-        if (A >= 1.0f - fp.early_term) break;
+        if (A >= 1.0f - early) break;
         const float4 r = results[ps.x + k];
         const float w = 1.0f - A;
         C0 += w * r.x;
@@ -785,64 +843,74 @@ __global__ __launch_bounds__(256) void k_merge(FrameParams fp, const uint2 *pixs
         C2 += w * r.z;
         A += w * r.w;
     }
-    rgba[pixel] = make_float4(C0, C1, C2, A);
+    reinterpret_cast<float4 *>(vr.rgba)[g - vr.pix_begin] = make_float4(C0, C1, C2, A);
+}
+
+// Clears the queue bookkeeping and (collect) the counters: a kernel rather than a
+// memset so that the whole render can be captured in a graph.
+__global__ void k_clear(QueueState *qs, u64 *ctr, int collect) {
+    const int t = threadIdx.x;
+    uint32_t *q = reinterpret_cast<uint32_t *>(qs);
+    if (t < (int)(sizeof(QueueState) / 4)) q[t] = 0u;
+    if (collect && t < C_COUNT) ctr[t] = 0ull;
 }
 
 // ------------------------------------------------------------------ launchers
 
 template <typename R>
-static hipError_t launch_fragments_t(const Model &m, const FrameParams &fp, void *segs,
-                                     uint32_t seg_cap, uint32_t *queues, uint32_t queue_stride,
-                                     uint32_t class_mask, QueueState *qs, uint2 *pixseg, float *depth,
-                                     unsigned long long *ctr, hipStream_t st) {
-    const int tiles = ((fp.width + 7) / 8) * ((fp.height + 7) / 8);
-    if (fp.seed_mode == IVR_SEED_MLP)
-        hipLaunchKernelGGL((k_fragments<R, true>), dim3(tiles), dim3(64), 0, st, m, fp, (Seg<R> *)segs,
-                           seg_cap, queues, queue_stride, class_mask, qs, pixseg, depth, ctr);
+static hipError_t launch_fragments_t(const Model &m, const ViewRec *views, int n_views, uint32_t n_tiles,
+                                     const LaunchCfg &lc, bool mlp, void *segs, uint32_t seg_cap,
+                                     uint32_t *queues, uint32_t queue_stride, uint32_t class_mask,
+                                     QueueState *qs, uint2 *pixseg, unsigned long long *ctr,
+                                     hipStream_t st) {
+    if (mlp)
+        hipLaunchKernelGGL((k_fragments<R, true>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views,
+                           n_tiles, lc, (Seg<R> *)segs, seg_cap, queues, queue_stride, class_mask, qs,
+                           pixseg, ctr);
     else
-        hipLaunchKernelGGL((k_fragments<R, false>), dim3(tiles), dim3(64), 0, st, m, fp, (Seg<R> *)segs,
-                           seg_cap, queues, queue_stride, class_mask, qs, pixseg, depth, ctr);
+        hipLaunchKernelGGL((k_fragments<R, false>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views,
+                           n_tiles, lc, (Seg<R> *)segs, seg_cap, queues, queue_stride, class_mask, qs,
+                           pixseg, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_fragments(bool fp64, const Model &m, const FrameParams &fp, void *segs,
-                            uint32_t seg_cap, uint32_t *queues, uint32_t queue_stride,
-                            uint32_t class_mask, QueueState *qs, uint2 *pixseg, float *depth,
-                            unsigned long long *ctr, hipStream_t st) {
-    return fp64 ? launch_fragments_t<double>(m, fp, segs, seg_cap, queues, queue_stride, class_mask,
-                                             qs, pixseg, depth, ctr, st)
-                : launch_fragments_t<float>(m, fp, segs, seg_cap, queues, queue_stride, class_mask,
-                                            qs, pixseg, depth, ctr, st);
+hipError_t launch_fragments(bool fp64, bool mlp, const Model &m, const ViewRec *views, int n_views,
+                            uint32_t n_tiles, const LaunchCfg &lc, void *segs, uint32_t seg_cap,
+                            uint32_t *queues, uint32_t queue_stride, uint32_t class_mask, QueueState *qs,
+                            uint2 *pixseg, unsigned long long *ctr, hipStream_t st) {
+    return fp64 ? launch_fragments_t<double>(m, views, n_views, n_tiles, lc, mlp, segs, seg_cap, queues,
+                                             queue_stride, class_mask, qs, pixseg, ctr, st)
+                : launch_fragments_t<float>(m, views, n_views, n_tiles, lc, mlp, segs, seg_cap, queues,
+                                            queue_stride, class_mask, qs, pixseg, ctr, st);
 }
 
 template <int P, bool RAT, typename R>
-static hipError_t launch_integrate_t(const Model &m, const FrameParams &fp, const void *segs,
+static hipError_t launch_integrate_t(const Model &m, const ViewRec *views, int n_views, const void *segs,
                                      const uint32_t *queue, const QueueState *qs, int klass,
                                      uint32_t *qnext, float4 *results, unsigned long long *ctr,
-                                     int n_cu, hipStream_t st) {
-    static int blocks_per_cu = -1;
-    if (blocks_per_cu < 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<P, RAT, R>, 256, 0) !=
-                hipSuccess || nb < 1)
-            nb = 1;
-        blocks_per_cu = nb;
-    }
-    hipLaunchKernelGGL((k_integrate<P, RAT, R>), dim3(n_cu * blocks_per_cu), dim3(256), 0, st, m, fp,
+                                     int n_cu, const LaunchCfg &lc, hipStream_t st) {
+    const size_t lds = sizeof(ViewLds) * (size_t)n_views;
+    const int block = lc.int_block;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<P, RAT, R>, block, lds) !=
+            hipSuccess || nb < 1)
+        nb = 1;
+    if (lc.int_waves_cu > 0) nb = std::min(nb, std::max(1, lc.int_waves_cu / (block / 64)));
+    hipLaunchKernelGGL((k_integrate<P, RAT, R>), dim3(n_cu * nb), dim3(block), lds, st, m, views, n_views,
                        (const Seg<R> *)segs, queue, qs, klass, qnext, results, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_integrate(bool fp64, int klass, const Model &m, const FrameParams &fp,
+hipError_t launch_integrate(bool fp64, int klass, const Model &m, const ViewRec *views, int n_views,
                             const void *segs, const uint32_t *queue, const QueueState *qs,
                             uint32_t *qnext, float4 *results, unsigned long long *ctr, int n_cu,
-                            hipStream_t st) {
-#define IVR_CASE(K, P, RAT)                                                                     \
-    case K:                                                                                     \
-        return fp64 ? launch_integrate_t<P, RAT, double>(m, fp, segs, queue, qs, klass, qnext,  \
-                                                         results, ctr, n_cu, st)                \
-                    : launch_integrate_t<P, RAT, float>(m, fp, segs, queue, qs, klass, qnext,   \
-                                                        results, ctr, n_cu, st);
+                            const LaunchCfg &lc, hipStream_t st) {
+#define IVR_CASE(K, P, RAT)                                                                      \
+    case K:                                                                                      \
+        return fp64 ? launch_integrate_t<P, RAT, double>(m, views, n_views, segs, queue, qs, klass, \
+                                                         qnext, results, ctr, n_cu, lc, st)       \
+                    : launch_integrate_t<P, RAT, float>(m, views, n_views, segs, queue, qs, klass,  \
+                                                        qnext, results, ctr, n_cu, lc, st);
     switch (klass) {
         IVR_CASE(0, 1, false)
         IVR_CASE(1, 1, true)
@@ -855,11 +923,15 @@ hipError_t launch_integrate(bool fp64, int klass, const Model &m, const FramePar
 #undef IVR_CASE
 }
 
-hipError_t launch_merge(const FrameParams &fp, const uint2 *pixseg, const float4 *results, float *rgba,
-                        hipStream_t st) {
-    const int n = fp.width * fp.height;
-    hipLaunchKernelGGL(k_merge, dim3((n + 255) / 256), dim3(256), 0, st, fp, pixseg, results,
-                       (float4 *)rgba);
+hipError_t launch_merge(const ViewRec *views, int n_views, uint32_t n_pixels, const uint2 *pixseg,
+                        const float4 *results, hipStream_t st) {
+    hipLaunchKernelGGL(k_merge, dim3((n_pixels + 255) / 256), dim3(256), 0, st, views, n_views, n_pixels,
+                       pixseg, results);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear(QueueState *qs, unsigned long long *ctr, bool collect, hipStream_t st) {
+    hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, st, qs, ctr, collect ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -433,53 +433,52 @@ __device__ __forceinline__ void tf_eval(const FrameParams &fp, double rho, doubl
     for (int c = 0; c < 4; ++c) out[c] = v[c] + s[c] * dn;
 }
 
-// The transfer function as the integrator's workgroup keeps it in LDS: on
-// interval k (x_k <= n < x_{k+1}) channel c is a[k].c + b[k].c * n; smax[k] bounds
-// the slope on intervals k-1..k+1.
-struct TfLds {
-    float4 a[kMaxTfKnots];
-    float4 b[kMaxTfKnots];
-    float smax[kMaxTfKnots];
-};
-
-// One lane fills the table (static indices keep the kernel argument in SGPRs).
-__device__ __forceinline__ void tf_stage(const FrameParams &fp, TfLds &t) {
-    if (threadIdx.x == 0) {
+// The integrator stages every view's transfer function and step bounds in LDS
+// (ViewLds); one thread per view fills a record.
+__device__ __forceinline__ void view_stage(const ViewRec *views, int n_views, ViewLds *vls) {
+    for (int v = threadIdx.x; v < n_views; v += blockDim.x) {
+        const FrameParams &f = views[v].fp;
+        ViewLds &w = vls[v];
 #pragma unroll
         for (int k = 0; k < kMaxTfKnots; ++k) {
-            const float x = fp.tf_x[k];
-            t.b[k] = make_float4(fp.tf_s[k][0], fp.tf_s[k][1], fp.tf_s[k][2], fp.tf_s[k][3]);
-            t.a[k] = make_float4(fp.tf_v[k][0] - fp.tf_s[k][0] * x, fp.tf_v[k][1] - fp.tf_s[k][1] * x,
-                                 fp.tf_v[k][2] - fp.tf_s[k][2] * x, fp.tf_v[k][3] - fp.tf_s[k][3] * x);
-            t.smax[k] = fp.tf_smax[k];
+            const float x = f.tf_x[k];
+            w.b[k] = make_float4(f.tf_s[k][0], f.tf_s[k][1], f.tf_s[k][2], f.tf_s[k][3]);
+            w.a[k] = make_float4(f.tf_v[k][0] - f.tf_s[k][0] * x, f.tf_v[k][1] - f.tf_s[k][1] * x,
+                                 f.tf_v[k][2] - f.tf_s[k][2] * x, f.tf_v[k][3] - f.tf_s[k][3] * x);
+            w.x[k] = (k >= 1 && k < f.tf_n - 1) ? x : INFINITY;
+            w.smax[k] = f.tf_smax[k];
         }
+        w.lo = f.tf_lo;
+        w.inv_range = f.tf_inv_range;
+        w.dn = f.tf_dn;
+        w.h_max = f.h_max;
+        w.h_min = f.h_min;
+        w.scale = f.scale;
+        w.inv_ranged = f.tf_inv_ranged;
     }
     __syncthreads();
 }
 
 // Interval of n: the number of interior knots at or below it.
-__device__ __forceinline__ int tf_interval(const FrameParams &fp, float n) {
+__device__ __forceinline__ int tf_interval(const ViewLds &w, float n) {
     int k = 0;
 #pragma unroll
-    for (int m = 1; m < kMaxTfKnots - 1; ++m) k += (m < fp.tf_n - 1 && n >= fp.tf_x[m]) ? 1 : 0;
+    for (int m = 1; m < kMaxTfKnots - 1; ++m) k += n >= w.x[m] ? 1 : 0;
     return k;
 }
 
-__device__ __forceinline__ void tf_eval(const FrameParams &fp, const TfLds &t, float rho, float (&out)[4]) {
-    const float n = clamp01((rho - fp.tf_lo) * fp.tf_inv_range);
-    const int k = tf_interval(fp, n);
-    const float4 a = t.a[k], b = t.b[k];
+__device__ __forceinline__ void tf_eval(const ViewLds &w, float rho, float (&out)[4]) {
+    const float n = clamp01((rho - w.lo) * w.inv_range);
+    const int k = tf_interval(w, n);
+    const float4 a = w.a[k], b = w.b[k];
     out[0] = a.x + b.x * n;
     out[1] = a.y + b.y * n;
     out[2] = a.z + b.z * n;
     out[3] = a.w + b.w * n;
 }
-__device__ __forceinline__ void tf_eval(const FrameParams &fp, const TfLds &, double rho, double (&out)[4]) {
-    tf_eval(fp, rho, out);
-}
 
-__device__ __forceinline__ float tf_slope_near(const FrameParams &fp, const TfLds &t, float rho) {
-    return t.smax[tf_interval(fp, clamp01((rho - fp.tf_lo) * fp.tf_inv_range))];
+__device__ __forceinline__ float tf_slope_near(const ViewLds &w, float rho) {
+    return w.smax[tf_interval(w, clamp01((rho - w.lo) * w.inv_range))];
 }
 
 // Slope bound of the transfer function around rho (per unit of n).
@@ -506,12 +505,18 @@ __device__ __forceinline__ double fast_exp(double x) { return exp(x); }
 // The number of sub-steps is at least n_super and grows with the change of the
 // normalised value n over the step (the transfer function's frequencies set the
 // sampling rate, not the spline), up to 64.
+// fb: the batch's options (n_super, hermite); fv / w: the view's transfer function
+// (FP64 from fv, FP32 from its LDS copy w).
 template <typename R>
-__device__ __forceinline__ void composite(const FrameParams &fp, const TfLds &tl, R ra, R ma, R rb,
-                                          R mb, R len, R (&C)[3], R &A, uint32_t &n_sub) {
+__device__ __forceinline__ void composite(const FrameParams &fb, const FrameParams &fv, const ViewLds &w,
+                                          R ra, R ma, R rb, R mb, R len, R (&C)[3], R &A,
+                                          uint32_t &n_sub) {
+    const FrameParams &fp = fb;
     const R sa = fp.hermite ? ma * len : (rb - ra), sb = fp.hermite ? mb * len : (rb - ra);
-    const R span = fmax(fabs(rb - ra), R(0.5) * (fabs(sa) + fabs(sb))) * R(fp.tf_inv_range);
-    int ns = (int)ceil(span / R(fp.tf_dn));
+    const R inv_range = sizeof(R) == 4 ? R(w.inv_range) : R(fv.tf_inv_ranged);
+    const R tdn = sizeof(R) == 4 ? R(w.dn) : R(fv.tf_dn);
+    const R span = fmax(fabs(rb - ra), R(0.5) * (fabs(sa) + fabs(sb))) * inv_range;
+    int ns = (int)ceil(span / tdn);
     ns = ns < fp.n_super ? fp.n_super : (ns > 64 ? 64 : ns);
     n_sub += (uint32_t)ns;
     const R inv = R(1) / R(ns);
@@ -522,7 +527,8 @@ __device__ __forceinline__ void composite(const FrameParams &fp, const TfLds &tl
         const R rho = (R(2) * t3 - R(3) * t2 + R(1)) * ra + (t3 - R(2) * t2 + tau) * sa +
                       (R(3) * t2 - R(2) * t3) * rb + (t3 - t2) * sb;
         R e[4];
-        tf_eval(fp, tl, rho, e);
+        if constexpr (sizeof(R) == 4) tf_eval(w, rho, e);
+        else tf_eval(fv, rho, e);
         const R T = fast_exp(-e[3] * dl);
         const R w = (R(1) - T) * (R(1) - A);
         C[0] += w * e[0];

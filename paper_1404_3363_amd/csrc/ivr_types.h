@@ -140,4 +140,41 @@ struct FrameParams {
     double scaled;
 };
 
+
+// One view of a batch (device array).  Views may look at different models (patch
+// ranges), have their own camera and transfer function; the integrator options
+// of the batch are the same in every record.
+constexpr int kViewShift = 20;          // Seg::patch = block | view << kViewShift
+constexpr uint32_t kPatchMask = (1u << kViewShift) - 1;
+constexpr int kMaxViews = 1 << (32 - kViewShift);
+
+struct alignas(16) ViewRec {
+    FrameParams fp;
+    int32_t patch_begin, patch_end;     // the view's model
+    uint32_t tile_begin;                // first fragment-kernel tile of the view
+    uint32_t tiles_x;                   // tiles per image row
+    uint32_t pix_begin;                 // first pixel of the view in the batch
+    uint32_t pad;
+    float *rgba;                        // width*height*4, caller-owned
+    float *depth;                       // width*height or null
+};
+
+// What the integrator keeps per view in LDS: on interval k (x[k] <= n < x[k+1])
+// channel c of the transfer function is a[k].c + b[k].c * n; x[m] = +inf past the
+// last interior knot; smax[k] bounds the slope on intervals k-1..k+1.
+struct alignas(16) ViewLds {
+    float4 a[kMaxTfKnots], b[kMaxTfKnots];
+    float x[kMaxTfKnots], smax[kMaxTfKnots];
+    float lo, inv_range, dn, h_max, h_min, scale;
+    double inv_ranged;
+};
+
+// Launch shapes chosen by the autotuner.
+struct LaunchCfg {
+    int32_t tile_w;          // fragment tile width in pixels (tile_w * tile_h = 64)
+    int32_t xcd_chunk;       // > 0: runs of this many consecutive tiles per XCD
+    int32_t int_block;       // integrator workgroup size (64, 128 or 256)
+    int32_t int_waves_cu;    // integrator waves per CU (0: as many as fit)
+};
+
 }  // namespace ivr

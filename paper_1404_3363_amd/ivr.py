@@ -20,7 +20,8 @@ PRECISION = {"fp32": 0, "fp64": 1}
 SEED = {"plain": 0, "mlp": 1, "box": 2}
 RHO_INTERP = {"linear": 0, "hermite": 1}
 
-EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_render",
+EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_upload_models",
+           "ivr_render", "ivr_render_batch", "ivr_autotune", "ivr_set_launch",
            "ivr_phase_times", "ivr_last_error", "ivr_destroy", "ivr_default_mlp_opts",
            "ivr_train_inverse_mlp", "ivr_mlp_forward_backward", "ivr_mlp_get_weights",
            "ivr_mlp_infer"]
@@ -51,6 +52,17 @@ class RenderOpts(C.Structure):
                 ("seed_mode", C.c_int32), ("early_term", C.c_double),
                 ("max_newton_iter", C.c_int32), ("rho_interp", C.c_int32),
                 ("timing", C.c_int32), ("tf_step", C.c_double)]
+
+
+class ViewDesc(C.Structure):
+    _fields_ = [("cam", CameraDesc), ("tf", C.c_void_p), ("model", C.c_int32),
+                ("rgba_dev", C.c_void_p), ("depth_dev", C.c_void_p)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("xcd_chunk", C.c_int32),
+                ("int_block", C.c_int32), ("int_waves_cu", C.c_int32), ("n_tried", C.c_int32),
+                ("tried_ms", C.c_double * 32), ("ms_before", C.c_double), ("ms_after", C.c_double)]
 
 
 STAT_FIELDS = ["rays", "segments", "fragments", "anomalies", "fragment_overflow",
@@ -93,6 +105,17 @@ def load_library() -> C.CDLL:
     L.ivr_default_opts.restype = None
     L.ivr_upload_patches.argtypes = [vp, C.POINTER(PatchDesc), C.c_int32]
     L.ivr_upload_patches.restype = C.c_int32
+    L.ivr_upload_models.argtypes = [vp, C.POINTER(PatchDesc), C.c_int32, C.POINTER(C.c_int32),
+                                    C.c_int32]
+    L.ivr_upload_models.restype = C.c_int32
+    L.ivr_render_batch.argtypes = [vp, C.POINTER(ViewDesc), C.c_int32, C.POINTER(TransferDesc),
+                                   C.POINTER(RenderOpts), C.POINTER(Stats)]
+    L.ivr_render_batch.restype = C.c_int32
+    L.ivr_autotune.argtypes = [vp, C.POINTER(ViewDesc), C.c_int32, C.POINTER(TransferDesc),
+                               C.POINTER(RenderOpts), C.POINTER(TuneReport)]
+    L.ivr_autotune.restype = C.c_int32
+    L.ivr_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    L.ivr_set_launch.restype = C.c_int32
     L.ivr_render.argtypes = [vp, C.POINTER(CameraDesc), C.POINTER(TransferDesc),
                              C.POINTER(RenderOpts), vp, vp, C.POINTER(Stats)]
     L.ivr_render.restype = C.c_int32
@@ -205,6 +228,12 @@ class Renderer:
             raise IvrError(rc, self.lib.ivr_last_error(self.ctx).decode())
 
     def upload(self, patches: Sequence) -> None:
+        self.upload_models([patches])
+
+    def upload_models(self, models: Sequence[Sequence]) -> None:
+        """Several models in one context; views name them by index."""
+        patches = [p for m in models for p in m]
+        sizes = (C.c_int32 * len(models))(*[len(m) for m in models])
         keep = []
         arr = (PatchDesc * len(patches))()
         for i, p in enumerate(patches):
@@ -220,7 +249,7 @@ class Renderer:
             d.cp = _dp(cp)
             d.scalar = _dp(sc)
             d.rational = 1 if p.rational else 0
-        self._check(self.lib.ivr_upload_patches(self.ctx, arr, len(patches)))
+        self._check(self.lib.ivr_upload_models(self.ctx, arr, len(patches), sizes, len(models)))
 
     # ---- learned initialiser
     def train_mlp(self, **kw) -> dict:
@@ -272,6 +301,72 @@ class Renderer:
                                              cap, C.byref(n)))
         return buf[:3 * min(n.value, cap)].reshape(-1, 3)
 
+    def _outputs(self, cam, rgba, depth):
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+        if rgba is None:
+            rgba = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=dev)
+        if depth is None:
+            depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device=dev)
+        for t, n in ((rgba, cam.width * cam.height * 4), (depth, cam.width * cam.height)):
+            if not (t.is_contiguous() and t.dtype == torch.float32 and t.device == dev
+                    and t.numel() >= n):
+                raise ValueError("outputs must be contiguous float32 tensors of the view's size "
+                                 "on the renderer's device")
+        return rgba, depth
+
+    def _batch_args(self, views, tf, opts, kw, outputs):
+        if opts is None:
+            opts = default_opts(**kw)
+        elif kw:
+            raise ValueError("pass either opts or keyword options")
+        keep, descs, outs = [], (ViewDesc * len(views))(), []
+        for i, v in enumerate(views):
+            cam, vtf, model = v[0], v[1] if len(v) > 1 else None, v[2] if len(v) > 2 else 0
+            rgba, depth = self._outputs(cam, *(outputs[i] if outputs else (None, None)))
+            outs.append((rgba, depth))
+            d = descs[i]
+            d.cam = camera_desc(cam)
+            if vtf is not None:
+                t = _TF(vtf)
+                keep.append(t)
+                d.tf = C.cast(C.pointer(t.desc), C.c_void_p)
+            d.model = int(model)
+            d.rgba_dev = rgba.data_ptr()
+            d.depth_dev = depth.data_ptr()
+        btf = _TF(tf) if tf is not None else None
+        return opts, descs, outs, btf, keep
+
+    def render_batch(self, views, tf=None, opts: Optional[RenderOpts] = None, outputs=None,
+                     stats: bool = False, **kw):
+        """views: sequence of (camera, transfer_function or None, model index).
+        Returns [(rgba, depth)] per view (and the batch counters with stats)."""
+        opts, descs, outs, btf, keep = self._batch_args(views, tf, opts, kw, outputs)
+        st = Stats() if stats else None
+        rc = self.lib.ivr_render_batch(self.ctx, descs, len(views),
+                                       C.byref(btf.desc) if btf is not None else None,
+                                       C.byref(opts), C.byref(st) if st is not None else None)
+        self._check(rc)
+        if st is None:
+            return outs
+        out = {f: int(getattr(st, f)) for f in STAT_FIELDS}
+        out.update(ms_fragments=st.ms_fragments, ms_integrate=st.ms_integrate, ms_merge=st.ms_merge)
+        return outs, out
+
+    def autotune(self, views, tf=None, opts: Optional[RenderOpts] = None, outputs=None, **kw) -> dict:
+        opts, descs, outs, btf, keep = self._batch_args(views, tf, opts, kw, outputs)
+        rep = TuneReport()
+        self._check(self.lib.ivr_autotune(self.ctx, descs, len(views),
+                                          C.byref(btf.desc) if btf is not None else None,
+                                          C.byref(opts), C.byref(rep)))
+        return {"tile_w": rep.tile_w, "tile_h": rep.tile_h, "xcd_chunk": rep.xcd_chunk,
+                "int_block": rep.int_block, "int_waves_cu": rep.int_waves_cu,
+                "tried_ms": list(rep.tried_ms[:rep.n_tried]), "ms_before": rep.ms_before,
+                "ms_after": rep.ms_after}
+
+    def set_launch(self, tile_w=8, xcd_chunk=0, int_block=256, int_waves_cu=0) -> None:
+        self._check(self.lib.ivr_set_launch(self.ctx, tile_w, xcd_chunk, int_block, int_waves_cu))
+
     def render(self, cam, tf, opts: Optional[RenderOpts] = None, rgba=None, depth=None,
                stats: bool = False, **kw):
         torch = self.torch
@@ -279,13 +374,7 @@ class Renderer:
             opts = default_opts(**kw)
         elif kw:
             raise ValueError("pass either opts or keyword options")
-        dev = torch.device("cuda", self.device)
-        if rgba is None:
-            rgba = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=dev)
-        if depth is None:
-            depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device=dev)
-        assert rgba.is_contiguous() and rgba.numel() >= cam.width * cam.height * 4
-        assert depth.is_contiguous() and depth.numel() >= cam.width * cam.height
+        rgba, depth = self._outputs(cam, rgba, depth)
         cd = camera_desc(cam)
         td = _TF(tf)
         st = Stats() if stats else None

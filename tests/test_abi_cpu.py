@@ -38,6 +38,10 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(ivr.PatchDesc) == 6 * 4 + 3 * 8 + 8 + 8 + 8
     assert ctypes.sizeof(ivr.CameraDesc) == 10 * 8 + 8
     assert ctypes.sizeof(ivr.Stats) == 19 * 8 + 3 * 8
+    # ivr_view: camera, tf pointer, model (padded), two device pointers
+    assert ctypes.sizeof(ivr.ViewDesc) == 88 + 8 + 8 + 8 + 8
+    assert ivr.ViewDesc.model.offset == 96 and ivr.ViewDesc.rgba_dev.offset == 104
+    assert ctypes.sizeof(ivr.TuneReport) == 6 * 4 + 32 * 8 + 2 * 8
 
 
 def test_create_without_gpu_reports_device_error():

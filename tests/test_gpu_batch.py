@@ -1,0 +1,163 @@
+"""GPU tests of the batched path: many views of different sizes and models in one
+fragment launch, one persistent integrator launch per degree class and one merge,
+replayed from a captured HIP graph; the autotuner's launch shapes.
+
+* A batch gives, bit for bit, the images of the same views rendered one at a time
+  (each lane's work does not depend on which other rays share its wave).
+* Graph replays with cameras changed in between match direct launches every time,
+  with eager renders and synchronisations between the replays.
+* The batched-views workload (two models, 32 views) at reduced resolution matches
+  the oracle on sampled pixels of every view.
+* Autotuned launch shapes leave the images unchanged.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from scenes import make_config, camera_from_angles
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def renderer():
+    from paper_1404_3363_amd import Renderer
+    r = Renderer(0)
+    yield r
+    r.close()
+
+
+def _np(t):
+    return t.cpu().numpy().astype(np.float64)
+
+
+def _small_models():
+    c1 = make_config(1)
+    c3 = make_config(3, 160, 90)
+    return c1, c3
+
+
+def _views(c1, c3):
+    tf2 = dataclasses.replace(c1.tf, extinction=2.0)
+    cams = [c1.cameras[0],
+            camera_from_angles([0.5, 0.5, 0.5], 3.0, 120.0, -15.0, 33, 17),
+            c3.cameras[0],
+            dataclasses.replace(c3.cameras[0], width=97, height=55)]
+    return [(cams[0], c1.tf, 0), (cams[1], tf2, 0), (cams[2], c3.tf, 1), (cams[3], c3.tf, 1)]
+
+
+def test_batch_equals_views_rendered_alone(renderer):
+    import torch
+    c1, c3 = _small_models()
+    renderer.upload_models([c1.patches, c3.patches])
+    views = _views(c1, c3)
+    print("[batch] 4 views, 2 models, graph replay", flush=True)
+    outs = renderer.render_batch(views)
+    torch.cuda.synchronize()
+    for i, v in enumerate(views):
+        alone, st = renderer.render_batch([v], stats=True)
+        torch.cuda.synchronize()
+        a_rgba, a_depth = _np(alone[0][0]), _np(alone[0][1])
+        b_rgba, b_depth = _np(outs[i][0]), _np(outs[i][1])
+        print(f"[batch] view {i} {v[0].width}x{v[0].height}: segments {st['segments']}, "
+              f"max|diff| {np.abs(a_rgba - b_rgba).max():.1e}", flush=True)
+        assert np.array_equal(a_rgba, b_rgba)
+        assert np.array_equal(a_depth, b_depth)
+        assert st["segments"] > 0 and st["anomalies"] <= 2
+
+
+def test_graph_replays_follow_the_view_table(renderer):
+    """Three replays of one captured batch with the cameras moved between them and
+    eager work (a single-view render, a synchronisation) in between; every replay
+    equals direct launches of the same views."""
+    import torch
+    c1, c3 = _small_models()
+    renderer.upload_models([c1.patches, c3.patches])
+    base = _views(c1, c3)
+    outs = None
+    for rep, az in enumerate((10.0, 75.0, 200.0)):
+        moved = [(camera_from_angles([0.5, 0.5, 0.5], 3.0, az + 15 * i, 20.0, v[0].width,
+                                     v[0].height) if v[2] == 0 else v[0], v[1], v[2])
+                 for i, v in enumerate(base)]
+        outs = renderer.render_batch(moved, outputs=[(o[0], o[1]) for o in outs] if outs else None)
+        torch.cuda.synchronize()
+        got = [(_np(o[0]), _np(o[1])) for o in outs]
+        renderer.render(c1.cameras[0], c1.tf)          # eager work between replays
+        torch.cuda.synchronize()
+        ref, _ = renderer.render_batch(moved, stats=True)
+        torch.cuda.synchronize()
+        for i in range(len(moved)):
+            assert np.array_equal(got[i][0], _np(ref[i][0])), (rep, i)
+            assert np.array_equal(got[i][1], _np(ref[i][1])), (rep, i)
+        print(f"[batch] replay {rep} matches direct launches", flush=True)
+
+
+def test_batched_views_workload_matches_oracle(renderer):
+    """Two models (the 256-block NURBS channel and the 512-block mixed-degree
+    lattice), 32 views of the batched-views workload at 1/8 resolution in one
+    batch; seeded covered and random pixels of every view against the oracle."""
+    import torch
+    a, b, views = make_config(5)
+    renderer.upload_models([a.patches, b.patches])
+    small = [(dataclasses.replace(cam, width=max(cam.width // 8, 1), height=max(cam.height // 8, 1)),
+              (a, b)[mi].tf, mi) for mi, cam in views]
+    print(f"[batch] config5: {len(small)} views, {sum(c.width * c.height for c, _, _ in small)} rays",
+          flush=True)
+    outs, st = renderer.render_batch(small, stats=True)
+    torch.cuda.synchronize()
+    print(f"[batch] config5 stats: segments {st['segments']} anomalies {st['anomalies']} "
+          f"overflow {st['fragment_overflow']}/{st['segment_overflow']}", flush=True)
+    assert st["fragment_overflow"] == 0 and st["segment_overflow"] == 0
+    graph_outs = renderer.render_batch(small)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(55)
+    worst = 0.0
+    for i, (cam, tf, mi) in enumerate(small):
+        img = _np(outs[i][0]).reshape(-1, 4)
+        assert np.array_equal(img, _np(graph_outs[i][0]).reshape(-1, 4))
+        cov = np.flatnonzero(img[:, 3] > 0)
+        pix = np.unique(np.concatenate([rng.choice(cov, min(12, len(cov)), replace=False),
+                                        rng.choice(cam.width * cam.height, 4, replace=False)]))
+        ref = oracle.render((a, b)[mi], cam, tf, pixels=pix)
+        err = float(np.abs(img[pix] - ref.rgba).max())
+        worst = max(worst, err)
+        assert err <= 1e-3, (i, err)
+    print(f"[batch] config5 worst |rgba - oracle| over all views: {worst:.2e}", flush=True)
+
+
+def test_autotuned_shapes_keep_the_images(renderer):
+    import torch
+    c1, c3 = _small_models()
+    renderer.upload_models([c1.patches, c3.patches])
+    views = _views(c1, c3)
+    before = [(_np(o[0]), _np(o[1])) for o in renderer.render_batch(views)]
+    torch.cuda.synchronize()
+    rep = renderer.autotune(views)
+    print(f"[batch] autotune: {rep}", flush=True)
+    assert rep["tile_w"] * rep["tile_h"] == 64 and rep["int_block"] in (64, 128, 256)
+    after = renderer.render_batch(views)
+    torch.cuda.synchronize()
+    for i in range(len(views)):
+        assert np.array_equal(before[i][0], _np(after[i][0]))
+        assert np.array_equal(before[i][1], _np(after[i][1]))
+    for tw, xo, blk, wpc in ((16, 0, 64, 8), (32, 1, 128, 16)):
+        renderer.set_launch(tw, xo, blk, wpc)
+        other = renderer.render_batch(views)
+        torch.cuda.synchronize()
+        for i in range(len(views)):
+            assert np.array_equal(before[i][0], _np(other[i][0])), (tw, xo, blk, wpc, i)
+    renderer.set_launch()
+
+
+def test_batch_errors(renderer):
+    from paper_1404_3363_amd import IvrError
+    c1, c3 = _small_models()
+    renderer.upload_models([c1.patches, c3.patches])
+    with pytest.raises(IvrError):
+        renderer.render_batch([(c1.cameras[0], c1.tf, 2)])      # no model 2
+    with pytest.raises(IvrError):
+        renderer.render_batch([(c1.cameras[0], c1.tf, 0)] * 65)  # too many views
+    with pytest.raises(IvrError):
+        renderer.render_batch([(c1.cameras[0], None, 0)])       # no transfer function
