@@ -137,6 +137,54 @@ def mlp_vs_plain(r, steps, warmup):
             "max_abs_rgba_mlp_vs_plain": float(np.abs(imgs["mlp"] - imgs["plain"]).max())}
 
 
+def batch_views(r, steps, warmup, seed=9):
+    """The batched-views workload: the 256-block NURBS channel and the 512-block
+    mixed-degree lattice, 32 views with resolutions from {256^2, 512^2, 1024^2,
+    1920x1080, 2048^2}, all rendered by one graph replay of the batch (fragment
+    launch over all views' tiles, persistent integrator per degree class, merge),
+    launch shapes from the autotuner.  Mrays/s over the whole batch, plus the
+    oracle on a few covered pixels of every view."""
+    import torch
+    import oracle
+    from scenes import make_config
+    a, b, views = make_config(5)
+    r.upload_models([a.patches, b.patches])
+    vs = [(cam, (a, b)[mi].tf, mi) for mi, cam in views]
+    dev = torch.device("cuda", 0)
+    outs = [(torch.empty((c.height, c.width, 4), dtype=torch.float32, device=dev),
+             torch.empty((c.height, c.width), dtype=torch.float32, device=dev)) for c, _, _ in vs]
+    tune = r.autotune(vs, outputs=outs)
+    for _ in range(warmup):
+        r.render_batch(vs, outputs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.render_batch(vs, outputs=outs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rays = sum(c.width * c.height for c, _, _ in vs)
+    _, st = r.render_batch(vs, outputs=outs, stats=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    worst, npx = 0.0, 0
+    for i, (cam, tf, mi) in enumerate(vs):
+        img = outs[i][0].cpu().numpy().reshape(-1, 4).astype(np.float64)
+        cov = np.flatnonzero(img[:, 3] > 0)
+        pix = rng.choice(cov, min(4, len(cov)), replace=False)
+        ref = oracle.render((a, b)[mi], cam, tf, pixels=pix, nthreads=min(16, os.cpu_count() or 1))
+        worst = max(worst, float(np.abs(img[pix] - ref.rgba).max()))
+        npx += len(pix)
+    return {"workload": "batched views: config4 channel (256 cubic NURBS blocks) and a 512-block "
+                        "mixed degree-2/3 lattice, 32 views of 256^2..2048^2 in one graph replay",
+            "unit": "Mrays/s", "rays_per_batch": rays, "value": round(rays * steps / el / 1e6, 3),
+            "ms_per_batch": round(1e3 * el / steps, 3), "steps": steps, "warmup": warmup,
+            "segments": st["segments"], "ms_fragments": round(st["ms_fragments"], 3),
+            "ms_integrate": round(st["ms_integrate"], 3), "ms_merge": round(st["ms_merge"], 3),
+            "autotune": {k: tune[k] for k in ("tile_w", "tile_h", "xcd_chunk", "int_block",
+                                              "int_waves_cu", "ms_before", "ms_after")},
+            "parity_sample": {"pixels": npx, "max_abs_rgba_vs_oracle": worst}}
+
+
 def copy_calibration(nbytes=256 << 20, reps=5):
     """A plain copy of known size: under a counter profile, its FETCH_SIZE and
     WRITE_SIZE per dispatch against nbytes/1024 KiB give the counters' scale."""
@@ -158,6 +206,7 @@ def main():
     ap.add_argument("--view", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 5 times (reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -233,6 +282,8 @@ def main():
         out["parity_sample"] = parity
     if not args.no_mlp:
         out["mlp_vs_plain"] = mlp_vs_plain(r, args.steps, args.warmup)
+    if not args.no_batch:
+        out["batch_views"] = batch_views(r, max(args.steps // 4, 3), 2)
     print(json.dumps(out))
 
 
