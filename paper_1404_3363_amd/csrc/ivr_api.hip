@@ -55,12 +55,17 @@ struct ivr_ctx {
     unsigned long long generation = 0;   // bumps when buffers move (graphs hold pointers)
     // frame buffers
     size_t pix_cap = 0, seg_cap = 0, seg_bytes_cap = 0;
-    int queue_slabs = 0;
+
     void *d_segs = nullptr;
     float4 *d_results = nullptr;
     uint2 *d_pixseg = nullptr;
-    uint32_t *d_queues = nullptr;
+    uint2 *d_seg_kr = nullptr;           // (block, rank among the block's segments)
+    uint32_t *d_order = nullptr;         // segment indices sorted by block
     QueueState *d_qs = nullptr;
+    // blocks grouped by degree class (the integrators take their segments block by block)
+    uint32_t *d_pperm = nullptr, *d_pcount = nullptr, *d_pbase = nullptr, *d_pcur = nullptr;
+    int cls_q[kClasses + 1] = {0};       // class k's blocks are pperm[cls_q[k] .. cls_q[k+1])
+    int cls_max_cp[kClasses] = {0};      // largest control net of the class
     unsigned long long *d_ctr = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // phase events of renders recorded with opts.timing (4 per render)
@@ -372,6 +377,7 @@ const char *ivr_last_error(const ivr_ctx *ctx) { return ctx ? ctx->err.c_str() :
 static void free_model(ivr_ctx *c) {
     dfree(c->d_patches); dfree(c->d_cp32); dfree(c->d_rho32); dfree(c->d_cp64); dfree(c->d_rho64);
     dfree(c->d_knots32); dfree(c->d_knots64); dfree(c->d_elems); dfree(c->d_tiles);
+    dfree(c->d_pperm); dfree(c->d_pcount); dfree(c->d_pbase); dfree(c->d_pcur);
     c->has_model = false;
 }
 
@@ -388,9 +394,8 @@ static void drop_graphs(ivr_ctx *c) {
 
 static void free_frame(ivr_ctx *c) {
     drop_graphs(c);
-    dfree(c->d_segs); dfree(c->d_results); dfree(c->d_pixseg); dfree(c->d_queues);
+    dfree(c->d_segs); dfree(c->d_results); dfree(c->d_pixseg); dfree(c->d_seg_kr); dfree(c->d_order);
     c->pix_cap = c->seg_cap = c->seg_bytes_cap = 0;
-    c->queue_slabs = 0;
 }
 
 void ivr_destroy(ivr_ctx *c) {
@@ -622,6 +627,19 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
             }
         }
     }
+    // blocks grouped by degree class (stable), with each class's range and largest net
+    std::vector<uint32_t> pperm;
+    int cls_q[kClasses + 1] = {0}, cls_max_cp[kClasses] = {0};
+    for (int k = 0; k < kClasses; ++k) {
+        cls_q[k] = (int)pperm.size();
+        for (int pi = 0; pi < n; ++pi)
+            if (hp[pi].klass == k) {
+                pperm.push_back((uint32_t)pi);
+                cls_max_cp[k] = std::max(cls_max_cp[k], hp[pi].n[0] * hp[pi].n[1] * hp[pi].n[2]);
+            }
+    }
+    cls_q[kClasses] = (int)pperm.size();
+    const std::vector<uint32_t> zeros(n, 0u);
     // allocate and copy, then swap in
     ivr_ctx tmp;
     auto up = [&](auto *&dst, const auto &vec) -> bool {
@@ -631,7 +649,9 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     };
     bool ok = up(tmp.d_patches, hp) && up(tmp.d_cp32, cp32) && up(tmp.d_rho32, rho32) &&
               up(tmp.d_cp64, cp64) && up(tmp.d_rho64, rho64) && up(tmp.d_knots32, knots32) &&
-              up(tmp.d_knots64, knots64) && up(tmp.d_elems, elems) && up(tmp.d_tiles, tiles);
+              up(tmp.d_knots64, knots64) && up(tmp.d_elems, elems) && up(tmp.d_tiles, tiles) &&
+              up(tmp.d_pperm, pperm) && up(tmp.d_pcount, zeros) && up(tmp.d_pbase, zeros) &&
+              up(tmp.d_pcur, zeros);
     if (!ok) {
         free_model(&tmp);
         return fail(c, IVR_ENOMEM, "device allocation for the model failed");
@@ -643,6 +663,10 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     c->d_patches = tmp.d_patches; c->d_cp32 = tmp.d_cp32; c->d_rho32 = tmp.d_rho32;
     c->d_cp64 = tmp.d_cp64; c->d_rho64 = tmp.d_rho64; c->d_knots32 = tmp.d_knots32;
     c->d_knots64 = tmp.d_knots64; c->d_elems = tmp.d_elems; c->d_tiles = tmp.d_tiles;
+    c->d_pperm = tmp.d_pperm; c->d_pcount = tmp.d_pcount; c->d_pbase = tmp.d_pbase; c->d_pcur = tmp.d_pcur;
+    tmp.d_pperm = tmp.d_pcount = tmp.d_pbase = tmp.d_pcur = nullptr;
+    std::copy(cls_q, cls_q + kClasses + 1, c->cls_q);
+    std::copy(cls_max_cp, cls_max_cp + kClasses, c->cls_max_cp);
     tmp.d_tiles = nullptr;
     tmp.d_patches = nullptr; tmp.d_cp32 = nullptr; tmp.d_rho32 = nullptr; tmp.d_cp64 = nullptr;
     tmp.d_rho64 = nullptr; tmp.d_knots32 = nullptr; tmp.d_knots64 = nullptr; tmp.d_elems = nullptr;
@@ -793,23 +817,20 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
 static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
     const size_t seg_cap = pixels * kSegCap;
     const size_t seg_bytes = seg_cap * (fp64 ? sizeof(Seg<double>) : sizeof(Seg<float>));
-    // one queue slab per degree class present in the uploaded models (a batch
-    // numbers its classes in class order, so it needs at most this many)
-    const int ncls = std::max(1, __builtin_popcount(c->class_mask));
-    if (pixels <= c->pix_cap && seg_bytes <= c->seg_bytes_cap && ncls <= c->queue_slabs) return IVR_OK;
+    if (pixels <= c->pix_cap && seg_bytes <= c->seg_bytes_cap) return IVR_OK;
     IVR_HIP(c, hipStreamSynchronize(c->stream));
     free_frame(c);
     if (hipMalloc(&c->d_segs, seg_bytes) != hipSuccess ||
         hipMalloc((void **)&c->d_results, sizeof(float4) * seg_cap) != hipSuccess ||
         hipMalloc((void **)&c->d_pixseg, sizeof(uint2) * pixels) != hipSuccess ||
-        hipMalloc((void **)&c->d_queues, sizeof(uint32_t) * seg_cap * ncls) != hipSuccess) {
+        hipMalloc((void **)&c->d_seg_kr, sizeof(uint2) * seg_cap) != hipSuccess ||
+        hipMalloc((void **)&c->d_order, sizeof(uint32_t) * seg_cap) != hipSuccess) {
         free_frame(c);
         return fail(c, IVR_ENOMEM, "frame buffer allocation failed");
     }
     c->pix_cap = pixels;
     c->seg_cap = seg_cap;
     c->seg_bytes_cap = seg_bytes;
-    c->queue_slabs = ncls;
     return IVR_OK;
 }
 
@@ -906,19 +927,27 @@ static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr
 static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const LaunchCfg &lc, hipEvent_t *ev,
                                hipStream_t s) {
     const Model m = device_model(c);
-    IVR_HIP(c, launch_clear(c->d_qs, c->d_ctr, b.collect, s));
+    IVR_HIP(c, launch_clear(c->d_qs, c->d_ctr, b.collect, c->d_pcount, c->npatch, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[0], s));
     IVR_HIP(c, launch_fragments(b.fp64, b.mlp, m, c->d_views, b.n, b.n_tiles, lc, c->d_segs,
-                                (uint32_t)c->seg_cap, c->d_queues, (uint32_t)c->seg_cap, b.class_mask,
-                                c->d_qs, c->d_pixseg, c->d_ctr, s));
+                                (uint32_t)c->seg_cap, c->d_seg_kr, c->d_pcount, c->d_qs, c->d_pixseg,
+                                c->d_ctr, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[1], s));
+    IVR_HIP(c, launch_block_sort(c->d_qs, (uint32_t)c->seg_cap, c->d_seg_kr, c->d_pperm, c->npatch,
+                                 c->d_pcount, c->d_pbase, c->d_pcur, c->d_order, c->n_cu, s));
     for (int k = 0; k < kClasses; ++k) {
         if (!((b.class_mask >> k) & 1)) continue;
-        IVR_HIP(c, launch_integrate(b.fp64, k, m, c->d_views, b.n, c->d_segs,
-                                    c->d_queues + (size_t)__builtin_popcount(b.class_mask & ((1u << k) - 1u)) *
-                                                      c->seg_cap,
-                                    c->d_qs, &c->d_qs->qnext[k],
-                                    c->d_results, c->d_ctr, c->n_cu, lc, s));
+        IntegrateArgs ia;
+        ia.order = c->d_order;
+        ia.pperm = c->d_pperm;
+        ia.q_begin = c->cls_q[k];
+        ia.q_end = c->cls_q[k + 1];
+        ia.pbase = c->d_pbase;
+        ia.pcount = c->d_pcount;
+        ia.pcur = c->d_pcur;
+        ia.max_cp = c->cls_max_cp[k];
+        IVR_HIP(c, launch_integrate(b.fp64, k, m, c->d_views, b.n, c->d_segs, ia, c->d_results, c->d_ctr,
+                                    c->n_cu, lc, s));
     }
     if (ev) IVR_HIP(c, hipEventRecord(ev[2], s));
     IVR_HIP(c, launch_merge(c->d_views, b.n, b.n_pixels, c->d_pixseg, c->d_results, s));

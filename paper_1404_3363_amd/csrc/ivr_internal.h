@@ -9,18 +9,22 @@ namespace ivr {
 
 hipError_t launch_fragments(bool fp64, bool mlp, const Model &m, const ViewRec *views, int n_views,
                             uint32_t n_tiles, const LaunchCfg &lc, void *segs, uint32_t seg_cap,
-                            uint32_t *queues, uint32_t queue_stride, uint32_t class_mask, QueueState *qs,
-                            uint2 *pixseg, unsigned long long *ctr, hipStream_t st);
+                            uint2 *seg_kr, uint32_t *pcount, QueueState *qs, uint2 *pixseg,
+                            unsigned long long *ctr, hipStream_t st);
+
+hipError_t launch_block_sort(const QueueState *qs, uint32_t seg_cap, const uint2 *seg_kr,
+                             const uint32_t *pperm, int nperm, const uint32_t *pcount, uint32_t *pbase,
+                             uint32_t *pcur, uint32_t *order, int n_cu, hipStream_t st);
 
 hipError_t launch_integrate(bool fp64, int klass, const Model &m, const ViewRec *views, int n_views,
-                            const void *segs, const uint32_t *queue, const QueueState *qs,
-                            uint32_t *qnext, float4 *results, unsigned long long *ctr, int n_cu,
-                            const LaunchCfg &lc, hipStream_t st);
+                            const void *segs, const IntegrateArgs &a, float4 *results,
+                            unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st);
 
 hipError_t launch_merge(const ViewRec *views, int n_views, uint32_t n_pixels, const uint2 *pixseg,
                         const float4 *results, hipStream_t st);
 
-hipError_t launch_clear(QueueState *qs, unsigned long long *ctr, bool collect, hipStream_t st);
+hipError_t launch_clear(QueueState *qs, unsigned long long *ctr, bool collect, uint32_t *pcount, int npatch,
+                        hipStream_t st);
 
 hipError_t launch_mlp_samples(const Model &m, const MlpState &st, int npatch, int n, uint32_t seed,
                               float4 *xs, float4 *ps, hipStream_t s);

@@ -334,8 +334,8 @@ __device__ __forceinline__ int view_of_tile(const ViewRec *views, int n_views, u
 template <typename R, bool MLP>
 __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views, int n_views,
                                                   u32 n_tiles, LaunchCfg lc, Seg<R> *segs, u32 seg_cap,
-                                                  u32 *queues, u32 queue_stride, u32 class_mask,
-                                                  QueueState *qs, uint2 *pixseg, u64 *ctr) {
+                                                  uint2 *seg_kr, u32 *pcount, QueueState *qs,
+                                                  uint2 *pixseg, u64 *ctr) {
     const int lane = threadIdx.x;
     // Consecutive blocks are dealt round-robin to the 8 XCDs.  With xcd_chunk = C
     // > 0, XCD x's j-th block takes tile j mod C of chunk (j / C) * 8 + x: runs of C
@@ -474,6 +474,9 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     base = __shfl(base, 63);
     u32 first = base + incl - (u32)nseg;
     if (base + total > seg_cap) {  // capacity exhausted: drop this wave's segments
+        // (their slots below the capacity are marked empty for the block sort)
+        for (int k = 0; k < nseg; ++k)
+            if (first + k < seg_cap) seg_kr[first + k] = make_uint2(0xFFFFFFFFu, 0u);
         c_sovf += nseg;
         nseg = 0;
         first = 0;
@@ -499,21 +502,33 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         s.patch = (u32)fo.patch | ((u32)v << kViewShift);
         segs[first + k] = s;
     }
-    // one queue per degree class
-    for (int c = 0; c < kClasses; ++c) {
-        if (!((class_mask >> c) & 1)) continue;
-        u32 cnt = 0;
-        for (int k = 0; k < nseg; ++k) cnt += (u32)m.patches[fr[pout[k]].patch].klass == (u32)c;
-        const u32 ci = wave_incl_scan(cnt, lane);
-        const u32 ctot = __shfl(ci, 63);
-        u32 cb = 0;
-        if (lane == 63 && ctot) cb = atomicAdd(&qs->qcount[c], ctot);
-        cb = __shfl(cb, 63);
-        u32 w = cb + ci - cnt;
-        // one queue slab per class present in the batch, in class order
-        u32 *qc = queues + (size_t)__popc(class_mask & ((1u << c) - 1u)) * queue_stride;
-        for (int k = 0; k < nseg; ++k)
-            if ((u32)m.patches[fr[pout[k]].patch].klass == (u32)c) qc[w++] = first + (u32)k;
+    // 5. the rank of every segment among the segments of its block (one atomic per
+    //    block and wave): the integrator takes the segments block by block
+    {
+        u32 ranked = 0;   // bit k: segment k has its rank
+        for (;;) {
+            int kk = -1;
+            for (int k = 0; k < nseg; ++k)
+                if (!((ranked >> k) & 1u)) { kk = k; break; }
+            const int myp = kk >= 0 ? fr[pout[kk]].patch : -1;
+            const u64 any = __ballot(myp >= 0);
+            if (any == 0) break;
+            const int leader = __ffsll((long long)any) - 1;
+            const int p = __shfl(myp, leader);
+            u32 cnt = 0;
+            for (int k = 0; k < nseg; ++k) cnt += (!((ranked >> k) & 1u) && fr[pout[k]].patch == p) ? 1u : 0u;
+            const u32 ci = wave_incl_scan(cnt, lane);
+            const u32 ctot = __shfl(ci, 63);
+            u32 b = 0;
+            if (lane == leader) b = atomicAdd(&pcount[p], ctot);
+            b = __shfl(b, leader);
+            u32 r = b + ci - cnt;
+            for (int k = 0; k < nseg; ++k)
+                if (!((ranked >> k) & 1u) && fr[pout[k]].patch == p) {
+                    seg_kr[first + k] = make_uint2((u32)p, r++);
+                    ranked |= 1u << k;
+                }
+        }
     }
     if (valid) {
         pixseg[vr.pix_begin + pixel] = make_uint2(first, (u32)nseg);
@@ -554,35 +569,104 @@ struct RKF {
                        e5 = R(1) / R(50), e6 = R(2) / R(55);
 };
 
+// Segments are taken block by block.  The fragment kernel gave every segment its
+// rank among the segments of its block; one workgroup scans the block counts in
+// class order (bases, cursors), and the scatter writes the block-sorted order.
+__global__ __launch_bounds__(1024) void k_block_scan(const u32 *pperm, int nperm, const u32 *pcount,
+                                                     u32 *pbase, u32 *pcur) {
+    __shared__ u32 part[1024];
+    __shared__ u32 run;
+    const int t = threadIdx.x;
+    if (t == 0) run = 0;
+    __syncthreads();
+    for (int q0 = 0; q0 < nperm; q0 += 1024) {
+        const int q = q0 + t;
+        const u32 v = q < nperm ? pcount[pperm[q]] : 0u;
+        part[t] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan (Hillis-Steele)
+            const u32 x = t >= off ? part[t - off] : 0u;
+            __syncthreads();
+            part[t] += x;
+            __syncthreads();
+        }
+        const u32 base = run + part[t] - v;
+        if (q < nperm) {
+            pbase[pperm[q]] = base;
+            pcur[pperm[q]] = base;
+        }
+        __syncthreads();
+        if (t == 1023) run += part[1023];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_block_scatter(const QueueState *qs, u32 seg_cap, const uint2 *seg_kr,
+                                                       const u32 *pbase, u32 *order) {
+    const u32 n = min(qs->seg_total, seg_cap);
+    for (u32 i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+        const uint2 kr = seg_kr[i];
+        if (kr.x != 0xFFFFFFFFu) order[pbase[kr.x] + kr.y] = i;
+    }
+}
+
 // Three waves per SIMD: the FP32 kernels fit in 168 VGPRs without spilling.
-template <int P, bool RAT, typename R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_integrate(Model m, const ViewRec *views, int n_views,
-                                                   const Seg<R> *segs, const u32 *queue,
-                                                   const QueueState *qs, int klass, u32 *qnext,
-                                                   float4 *results, u64 *ctr) {
+//
+// Each workgroup works on one block at a time: with LDS, the block's control
+// points (and w*rho for NURBS) are staged in LDS, so every evaluation reads its
+// (p+1)^3 points from there instead of gathering them through the vector L1.
+// The workgroup starts at the block holding its share of the class's segments,
+// its waves refill their lanes from that block's cursor (one atomic per wave),
+// and when the block has no segments left it drains and moves on to the next
+// block with work, cyclically in class order.
+template <int P, bool RAT, typename R, bool LDS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_integrate(
+    Model m, const ViewRec *views, int n_views, const Seg<R> *segs, const u32 *order, const u32 *pperm,
+    int q_begin, int q_end, const u32 *pbase, const u32 *pcount, u32 *pcur, int max_cp, float4 *results,
+    u64 *ctr) {
     using K = RKF<R>;
-    // per-view transfer functions and step bounds in LDS (a lane's segment may
-    // belong to any view of the batch); the integrator options are the batch's
+    // LDS: per-view transfer functions and step bounds (a lane's segment may
+    // belong to any view of the batch), then the staged block
     extern __shared__ __align__(16) unsigned char smem_raw[];
     ViewLds *vls = reinterpret_cast<ViewLds *>(smem_raw);
+    float4 *lds_cp = reinterpret_cast<float4 *>(smem_raw + sizeof(ViewLds) * n_views);
+    float *lds_rho = reinterpret_cast<float *>(lds_cp + max_cp);
+    __shared__ int s_q;
     view_stage(views, n_views, vls);
     const FrameParams fp = views[0].fp;   // the batch's options (uniform)
-    const u32 qcount = qs->qcount[klass];
-    const Arrays<R> ar = arrays_of(m, R(0));
     const R tol = sizeof(R) == 4 ? R(fp.rk_tol) : R(fp.rk_told);
     const R cperp = sizeof(R) == 4 ? R(fp.c_perp) : R(fp.c_perpd);
     const R early = sizeof(R) == 4 ? R(fp.early_term) : R(fp.early_termd);
     const R dthr = sizeof(R) == 4 ? R(fp.det_thr) : R(fp.det_thrd);
+    const int nq = q_end - q_begin;
+    if (threadIdx.x == 0) {
+        // the block that holds segment S0 + (S1 - S0) * blockIdx / gridDim
+        const u32 S0 = pbase[pperm[q_begin]];
+        const u32 S1 = pbase[pperm[q_end - 1]] + pcount[pperm[q_end - 1]];
+        int q = -1;
+        if (S1 > S0) {
+            const u32 target = S0 + (u32)(((unsigned long long)(S1 - S0) * blockIdx.x) / gridDim.x);
+            int lo = q_begin, hi = q_end;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pbase[pperm[mid]] <= target) lo = mid;
+                else hi = mid;
+            }
+            q = lo;
+        }
+        s_q = q;
+    }
+    __syncthreads();
+    int q = s_q;
 
-    bool active = false, queue_empty = false;
+    bool active = false;
     u32 sid = 0;
     int vid = 0;                  // view of the lane's segment
     R hmax = 0, hmin = 0, vscale = 0;
-    PatchView<R> pv;
     R p[3] = {0, 0, 0}, gin[3] = {0, 0, 0}, d[3] = {0, 0, 0};
     R s = 0, L = 0, Lend = 0, h = 0, h_prev = 0, rho_prev = 0, m_prev = 0, rho_out = 0, m_out = 0;
     R C[3] = {0, 0, 0}, A = 0;
-    bool pending = false, fresh = false;
+    bool pending = false, fresh = false, rejected = false;
     int iters = 0;
     // Eq. (degeneracyfix) state: shrink > 0 (the attempt) while Newton seeks the
     // preimage of the entry moved delta along the ray; gin is then that point (it
@@ -591,22 +675,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     R delta = 0, rho_in = 0;
     u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_cap = 0, c_sub = 0, c_deg = 0;
 
-    for (;;) {
-        // refill idle lanes from the queue (one atomic per wave)
+    for (;;) {   // blocks
+        if (threadIdx.x == 0) {
+            // from q on, cyclically in class order, the first block with segments left
+            int found = -1;
+            if (q >= 0)
+                for (int t = 0; t < nq; ++t) {
+                    const int qq = q_begin + (q - q_begin + t) % nq;
+                    const u32 pp = pperm[qq];
+                    if (__hip_atomic_load(&pcur[pp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                        pbase[pp] + pcount[pp]) {
+                        found = qq;
+                        break;
+                    }
+                }
+            s_q = found;
+        }
+        __syncthreads();
+        q = s_q;
+        if (q < 0) break;
+        const u32 blk = pperm[q];
+        const u32 pend = pbase[blk] + pcount[blk];
+        PatchView<R> pv = view_of<R>(m.patches[blk]);
+        Arrays<R> ar = arrays_of(m, R(0));
+        if constexpr (LDS) {
+            const int ncp = pv.n[0] * pv.n[1] * pv.n[2];
+            for (int i = threadIdx.x; i < ncp; i += blockDim.x) {
+                lds_cp[i] = m.cp32[pv.cp_off + i];
+                if (RAT) lds_rho[i] = m.rho32[pv.cp_off + i];
+            }
+            pv.cp_off = 0;
+            ar.cp = reinterpret_cast<const typename CpType<R>::T *>(lds_cp);
+            ar.rho = reinterpret_cast<const R *>(lds_rho);
+        }
+        __syncthreads();
+        bool queue_empty = false;
+        for (;;) {   // segments of the block
+        // refill idle lanes from the block's cursor (one atomic per wave)
         const u64 need = __ballot(!active);
         if (need && !queue_empty) {
             const int leader = __ffsll((long long)need) - 1;
             u32 b = 0;
-            if (lane_id() == leader) b = atomicAdd(qnext, (u32)__popcll(need));
+            if (lane_id() == leader) b = atomicAdd(&pcur[blk], (u32)__popcll(need));
             b = __shfl(b, leader);
-            if (b + (u32)__popcll(need) >= qcount) queue_empty = true;
+            if (b + (u32)__popcll(need) >= pend) queue_empty = true;
             if (!active) {
                 const u32 qi = b + (u32)rank_in(need);
-                if (qi < qcount) {
-                    sid = queue[qi];
+                if (qi < pend) {
+                    sid = order[qi];
                     const Seg<R> sg = segs[sid];
                     vid = (int)(sg.patch >> kViewShift);
-                    pv = view_of<R>(m.patches[sg.patch & kPatchMask]);
                     const FrameParams &fv = views[vid].fp;
                     const int pxl = (int)(sg.pixel % (u32)fv.width), pyl = (int)(sg.pixel / (u32)fv.width);
                     double dd[3];
@@ -632,6 +750,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     C[0] = C[1] = C[2] = A = R(0);
                     pending = false;
                     fresh = true;
+                    rejected = false;
                     iters = 0;
                     shrink = 0;
                     active = true;
@@ -782,7 +901,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             } else {
                 ++c_rej;
             }
-            // step-size control for a 4(5) pair
+            // step-size control for a 4(5) pair; no growth on the attempt after a
+            // rejection (the error estimate just proved the step too long)
             R fac = R(2.5);
             if (!finite) {
                 fac = R(0.2);
@@ -790,6 +910,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 fac = R(0.9) * pow_fifth(tol / err);
                 fac = fac < R(0.2) ? R(0.2) : (fac > R(2.5) ? R(2.5) : fac);
             }
+            if (accept && rejected && fac > R(1)) fac = R(1);
+            rejected = !accept;
             h = hh * fac;
             h = h > hmax ? hmax : h;
             h = h < hmin ? hmin : h;
@@ -802,6 +924,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             results[sid] = make_float4(float(C[0]), float(C[1]), float(C[2]), float(A));
             active = false;
         }
+        }
+        __syncthreads();   // every wave is done with this block's LDS copy
     }
     if (fp.collect) {
         flush_counter(ctr, C_RK_STEPS, c_steps);
@@ -848,11 +972,12 @@ __global__ __launch_bounds__(256) void k_merge(const ViewRec *views, int n_views
 
 // Clears the queue bookkeeping and (collect) the counters: a kernel rather than a
 // memset so that the whole render can be captured in a graph.
-__global__ void k_clear(QueueState *qs, u64 *ctr, int collect) {
-    const int t = threadIdx.x;
+__global__ void k_clear(QueueState *qs, u64 *ctr, int collect, u32 *pcount, int npatch) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t *q = reinterpret_cast<uint32_t *>(qs);
     if (t < (int)(sizeof(QueueState) / 4)) q[t] = 0u;
     if (collect && t < C_COUNT) ctr[t] = 0ull;
+    for (int i = t; i < npatch; i += gridDim.x * blockDim.x) pcount[i] = 0u;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -860,67 +985,81 @@ __global__ void k_clear(QueueState *qs, u64 *ctr, int collect) {
 template <typename R>
 static hipError_t launch_fragments_t(const Model &m, const ViewRec *views, int n_views, uint32_t n_tiles,
                                      const LaunchCfg &lc, bool mlp, void *segs, uint32_t seg_cap,
-                                     uint32_t *queues, uint32_t queue_stride, uint32_t class_mask,
-                                     QueueState *qs, uint2 *pixseg, unsigned long long *ctr,
-                                     hipStream_t st) {
+                                     uint2 *seg_kr, uint32_t *pcount, QueueState *qs, uint2 *pixseg,
+                                     unsigned long long *ctr, hipStream_t st) {
     if (mlp)
         hipLaunchKernelGGL((k_fragments<R, true>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views,
-                           n_tiles, lc, (Seg<R> *)segs, seg_cap, queues, queue_stride, class_mask, qs,
-                           pixseg, ctr);
+                           n_tiles, lc, (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, ctr);
     else
         hipLaunchKernelGGL((k_fragments<R, false>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views,
-                           n_tiles, lc, (Seg<R> *)segs, seg_cap, queues, queue_stride, class_mask, qs,
-                           pixseg, ctr);
+                           n_tiles, lc, (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, ctr);
     return hipGetLastError();
 }
 
 hipError_t launch_fragments(bool fp64, bool mlp, const Model &m, const ViewRec *views, int n_views,
                             uint32_t n_tiles, const LaunchCfg &lc, void *segs, uint32_t seg_cap,
-                            uint32_t *queues, uint32_t queue_stride, uint32_t class_mask, QueueState *qs,
-                            uint2 *pixseg, unsigned long long *ctr, hipStream_t st) {
-    return fp64 ? launch_fragments_t<double>(m, views, n_views, n_tiles, lc, mlp, segs, seg_cap, queues,
-                                             queue_stride, class_mask, qs, pixseg, ctr, st)
-                : launch_fragments_t<float>(m, views, n_views, n_tiles, lc, mlp, segs, seg_cap, queues,
-                                            queue_stride, class_mask, qs, pixseg, ctr, st);
+                            uint2 *seg_kr, uint32_t *pcount, QueueState *qs, uint2 *pixseg,
+                            unsigned long long *ctr, hipStream_t st) {
+    return fp64 ? launch_fragments_t<double>(m, views, n_views, n_tiles, lc, mlp, segs, seg_cap, seg_kr,
+                                             pcount, qs, pixseg, ctr, st)
+                : launch_fragments_t<float>(m, views, n_views, n_tiles, lc, mlp, segs, seg_cap, seg_kr,
+                                            pcount, qs, pixseg, ctr, st);
 }
 
-template <int P, bool RAT, typename R>
-static hipError_t launch_integrate_t(const Model &m, const ViewRec *views, int n_views, const void *segs,
-                                     const uint32_t *queue, const QueueState *qs, int klass,
-                                     uint32_t *qnext, float4 *results, unsigned long long *ctr,
-                                     int n_cu, const LaunchCfg &lc, hipStream_t st) {
-    const size_t lds = sizeof(ViewLds) * (size_t)n_views;
-    const int block = lc.int_block;
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<P, RAT, R>, block, lds) !=
-            hipSuccess || nb < 1)
-        nb = 1;
-    if (lc.int_waves_cu > 0) nb = std::min(nb, std::max(1, lc.int_waves_cu / (block / 64)));
-    hipLaunchKernelGGL((k_integrate<P, RAT, R>), dim3(n_cu * nb), dim3(block), lds, st, m, views, n_views,
-                       (const Seg<R> *)segs, queue, qs, klass, qnext, results, ctr);
+hipError_t launch_block_sort(const QueueState *qs, uint32_t seg_cap, const uint2 *seg_kr,
+                             const uint32_t *pperm, int nperm, const uint32_t *pcount, uint32_t *pbase,
+                             uint32_t *pcur, uint32_t *order, int n_cu, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(1024), 0, st, pperm, nperm, pcount, pbase, pcur);
+    hipLaunchKernelGGL(k_block_scatter, dim3(n_cu * 4), dim3(256), 0, st, qs, seg_cap, seg_kr, pbase, order);
     return hipGetLastError();
 }
 
+// LDS budget of the staged block per integrator workgroup.
+constexpr size_t kLdsBlockBytes = 48 * 1024;
+
+template <int P, bool RAT, typename R, bool LDS>
+static hipError_t launch_integrate_t(const Model &m, const ViewRec *views, int n_views, const void *segs,
+                                     const IntegrateArgs &a, float4 *results, unsigned long long *ctr,
+                                     int n_cu, const LaunchCfg &lc, hipStream_t st) {
+    const size_t lds = sizeof(ViewLds) * (size_t)n_views +
+                       (LDS ? (size_t)a.max_cp * (sizeof(float4) + (RAT ? sizeof(float) : 0)) : 0);
+    const int block = lc.int_block;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<P, RAT, R, LDS>, block, lds) !=
+            hipSuccess || nb < 1)
+        nb = 1;
+    if (lc.int_waves_cu > 0) nb = std::min(nb, std::max(1, lc.int_waves_cu / (block / 64)));
+    hipLaunchKernelGGL((k_integrate<P, RAT, R, LDS>), dim3(n_cu * nb), dim3(block), lds, st, m, views,
+                       n_views, (const Seg<R> *)segs, a.order, a.pperm, a.q_begin, a.q_end, a.pbase,
+                       a.pcount, a.pcur, LDS ? a.max_cp : 0, results, ctr);
+    return hipGetLastError();
+}
+
+template <int P, bool RAT>
+static hipError_t launch_integrate_pr(bool fp64, const Model &m, const ViewRec *views, int n_views,
+                                      const void *segs, const IntegrateArgs &a, float4 *results,
+                                      unsigned long long *ctr, int n_cu, const LaunchCfg &lc,
+                                      hipStream_t st) {
+    if (fp64)
+        return launch_integrate_t<P, RAT, double, false>(m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+    const size_t bytes = (size_t)a.max_cp * (sizeof(float4) + (RAT ? sizeof(float) : 0));
+    if (bytes <= kLdsBlockBytes)
+        return launch_integrate_t<P, RAT, float, true>(m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+    return launch_integrate_t<P, RAT, float, false>(m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+}
+
 hipError_t launch_integrate(bool fp64, int klass, const Model &m, const ViewRec *views, int n_views,
-                            const void *segs, const uint32_t *queue, const QueueState *qs,
-                            uint32_t *qnext, float4 *results, unsigned long long *ctr, int n_cu,
-                            const LaunchCfg &lc, hipStream_t st) {
-#define IVR_CASE(K, P, RAT)                                                                      \
-    case K:                                                                                      \
-        return fp64 ? launch_integrate_t<P, RAT, double>(m, views, n_views, segs, queue, qs, klass, \
-                                                         qnext, results, ctr, n_cu, lc, st)       \
-                    : launch_integrate_t<P, RAT, float>(m, views, n_views, segs, queue, qs, klass,  \
-                                                        qnext, results, ctr, n_cu, lc, st);
+                            const void *segs, const IntegrateArgs &a, float4 *results,
+                            unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st) {
     switch (klass) {
-        IVR_CASE(0, 1, false)
-        IVR_CASE(1, 1, true)
-        IVR_CASE(2, 2, false)
-        IVR_CASE(3, 2, true)
-        IVR_CASE(4, 3, false)
-        IVR_CASE(5, 3, true)
+    case 0: return launch_integrate_pr<1, false>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+    case 1: return launch_integrate_pr<1, true>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+    case 2: return launch_integrate_pr<2, false>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+    case 3: return launch_integrate_pr<2, true>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+    case 4: return launch_integrate_pr<3, false>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+    case 5: return launch_integrate_pr<3, true>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
     default: return hipErrorInvalidValue;
     }
-#undef IVR_CASE
 }
 
 hipError_t launch_merge(const ViewRec *views, int n_views, uint32_t n_pixels, const uint2 *pixseg,
@@ -930,8 +1069,10 @@ hipError_t launch_merge(const ViewRec *views, int n_views, uint32_t n_pixels, co
     return hipGetLastError();
 }
 
-hipError_t launch_clear(QueueState *qs, unsigned long long *ctr, bool collect, hipStream_t st) {
-    hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, st, qs, ctr, collect ? 1 : 0);
+hipError_t launch_clear(QueueState *qs, unsigned long long *ctr, bool collect, uint32_t *pcount, int npatch,
+                        hipStream_t st) {
+    const int blocks = std::max(1, std::min(64, (npatch + 255) / 256));
+    hipLaunchKernelGGL(k_clear, dim3(blocks), dim3(256), 0, st, qs, ctr, collect ? 1 : 0, pcount, npatch);
     return hipGetLastError();
 }
 

@@ -104,12 +104,23 @@ enum Counter : int {
     C_W_EVALS, C_FP64_SOLVES, C_RK_ITER_CAP, C_MLP_QUERIES, C_SUBSAMPLES, C_DEGENERATE, C_COUNT
 };
 
-// Queue bookkeeping written by the fragment kernel and read by the integrator.
+// Bookkeeping written by the fragment kernel.
 struct QueueState {
-    uint32_t seg_total;             // segments written
-    uint32_t qcount[kClasses];      // segments per class
-    uint32_t qnext[kClasses];       // next queue slot to hand out (integrator)
-    uint32_t pad;
+    uint32_t seg_total;             // segments requested (may exceed the capacity)
+    uint32_t pad[3];
+};
+
+// What the integrator of one degree class needs to take its segments block by
+// block: the block-sorted segment order, the blocks of the class as positions
+// [q_begin, q_end) of pperm (blocks grouped by class), per-block base, count and
+// cursor into the order, and the largest control net of the class (LDS size).
+struct IntegrateArgs {
+    const uint32_t *order;
+    const uint32_t *pperm;
+    int32_t q_begin, q_end;
+    const uint32_t *pbase, *pcount;
+    uint32_t *pcur;
+    int32_t max_cp;
 };
 
 struct FrameParams {
