@@ -79,10 +79,20 @@ __device__ __forceinline__ bool slab(const float (&o)[3], const float (&inv)[3],
 
 template <typename R>
 struct Frag {
-    double t;
-    R p[3];
-    int patch;
-    int entering;
+    // a boundary crossing: ray parameter, face parameters (a, b), and the block,
+    // face and facing packed as block << 4 | face << 1 | entering (16 B in FP32)
+    R t, a, b;
+    uint32_t info;
+    __device__ int patch() const { return (int)(info >> 4); }
+    __device__ int entering() const { return (int)(info & 1u); }
+    __device__ void param(R (&p)[3]) const {
+        const int face = (int)((info >> 1) & 7u);
+        int dn, da, db;
+        face_dirs(face, dn, da, db);
+        p[dn] = (face & 1) ? R(1) : R(0);
+        p[da] = a;
+        p[db] = b;
+    }
 };
 
 // Ray (t >= 0) against an oriented box; [tmin, tmax] is the ray's interval inside.
@@ -115,7 +125,7 @@ __device__ __forceinline__ bool is_dup(const Frag<R> *fr, int nfr, int patch, in
                                        double tol) {
     bool dup = false;
     for (int q = 0; q < nfr; ++q)
-        dup |= fr[q].patch == patch && fr[q].entering == entering && fabs(fr[q].t - t) <= tol;
+        dup |= fr[q].patch() == patch && fr[q].entering() == entering && fabs(double(fr[q].t) - t) <= tol;
     return dup;
 }
 
@@ -143,19 +153,15 @@ __device__ __forceinline__ void insert_frag(Frag<RN> *fr, int &nfr, const FrameP
         ++n_ovf;
         return;
     }
-    int dn, da, db;
-    face_dirs(face, dn, da, db);
     Frag<RN> f;
-    f.t = T;
-    f.patch = patch;
-    f.entering = ent;
-    RN pp[3];
-    pp[dn] = (face & 1) ? RN(1) : RN(0);
-    pp[da] = RN(clamp01(A));
-    pp[db] = RN(clamp01(B));
-    f.p[0] = pp[0]; f.p[1] = pp[1]; f.p[2] = pp[2];
+    f.t = RN(T);
+    f.a = RN(clamp01(A));
+    f.b = RN(clamp01(B));
+    f.info = ((uint32_t)patch << 4) | ((uint32_t)face << 1) | (uint32_t)(ent & 1);
+    // depth order; at equal depth (the FP32 depths of a crossing through an edge)
+    // an entry goes before an exit, so the pairing finds the entry in front
     int q = nfr++;
-    while (q > 0 && fr[q - 1].t > T) {
+    while (q > 0 && (fr[q - 1].t > f.t || (fr[q - 1].t == f.t && ent && !fr[q - 1].entering()))) {
         fr[q] = fr[q - 1];
         --q;
     }
@@ -386,7 +392,8 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     __shared__ uint16_t sA[64 * 72];
     __shared__ float sY[64 * 4];
     constexpr bool mlp = MLP;   // a separate instantiation keeps the MFMA path's registers out of the others
-    auto solve_candidates = [&](int block) {
+    // (always inlined: a call would see the kernel's pointers as generic and load through flat)
+    auto solve_candidates = [&](int block) __attribute__((always_inline)) {
         for (int k = 0; __ballot(k < ncand) != 0; ++k) {
             float ms[3] = {0.f, 0.f, 0.f};
             if constexpr (mlp) {
@@ -444,12 +451,12 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     for (;;) {
         int ib = -1;
         for (int q = 0; q < nfr; ++q)
-            if (!((used >> q) & 1ull) && !fr[q].entering) { ib = q; break; }
+            if (!((used >> q) & 1ull) && !fr[q].entering()) { ib = q; break; }
         if (ib < 0) break;
         used |= 1ull << ib;
         int ifr = -1;
         for (int q = 0; q < ib; ++q)
-            if (!((used >> q) & 1ull) && fr[q].entering && fr[q].patch == fr[ib].patch) { ifr = q; break; }
+            if (!((used >> q) & 1ull) && fr[q].entering() && fr[q].patch() == fr[ib].patch()) { ifr = q; break; }
         if (ifr < 0) { ++c_anom; continue; }
         used |= 1ull << ifr;
         if (npair >= kSegCap) { ++c_sovf; continue; }
@@ -488,18 +495,21 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         Seg<R> s;
         s.t_in = R(fi.t);
         s.t_out = R(fo.t);
+        R pi_[3], po_[3];
+        fi.param(pi_);
+        fo.param(po_);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            s.p_in[q] = fi.p[q];
-            s.p_out[q] = fo.p[q];
+            s.p_in[q] = pi_[q];
+            s.p_out[q] = po_[q];
         }
-        const R det_out = rho_ds_any<R>(m, m.patches[fo.patch], fo.p, dr, s.rho_out, s.drho_out);
+        const R det_out = rho_ds_any<R>(m, m.patches[fo.patch()], po_, dr, s.rho_out, s.drho_out);
         // singular J at the exit (a degenerate boundary): no slope; the
         // integrator then stops short of the exit, Eq. (degeneracyfix)
         if (!(fabs(det_out) >= (sizeof(R) == 4 ? R(fp.det_thr) : R(fp.det_thrd))))
             s.drho_out = R(NAN);
         s.pixel = pixel;
-        s.patch = (u32)fo.patch | ((u32)v << kViewShift);
+        s.patch = (u32)fo.patch() | ((u32)v << kViewShift);
         segs[first + k] = s;
     }
     // 5. the rank of every segment among the segments of its block (one atomic per
@@ -510,13 +520,13 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             int kk = -1;
             for (int k = 0; k < nseg; ++k)
                 if (!((ranked >> k) & 1u)) { kk = k; break; }
-            const int myp = kk >= 0 ? fr[pout[kk]].patch : -1;
+            const int myp = kk >= 0 ? fr[pout[kk]].patch() : -1;
             const u64 any = __ballot(myp >= 0);
             if (any == 0) break;
             const int leader = __ffsll((long long)any) - 1;
             const int p = __shfl(myp, leader);
             u32 cnt = 0;
-            for (int k = 0; k < nseg; ++k) cnt += (!((ranked >> k) & 1u) && fr[pout[k]].patch == p) ? 1u : 0u;
+            for (int k = 0; k < nseg; ++k) cnt += (!((ranked >> k) & 1u) && fr[pout[k]].patch() == p) ? 1u : 0u;
             const u32 ci = wave_incl_scan(cnt, lane);
             const u32 ctot = __shfl(ci, 63);
             u32 b = 0;
@@ -524,7 +534,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             b = __shfl(b, leader);
             u32 r = b + ci - cnt;
             for (int k = 0; k < nseg; ++k)
-                if (!((ranked >> k) & 1u) && fr[pout[k]].patch == p) {
+                if (!((ranked >> k) & 1u) && fr[pout[k]].patch() == p) {
                     seg_kr[first + k] = make_uint2((u32)p, r++);
                     ranked |= 1u << k;
                 }

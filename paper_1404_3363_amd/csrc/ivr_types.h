@@ -24,7 +24,7 @@ constexpr int kMaxTfKnots = 16;
 constexpr int kClasses = 6;          // degree class = 2*(degree-1) + rational
 constexpr int kFragCap = 64;         // boundary crossings kept per ray (hard cap)
 constexpr int kSegCap = 32;          // segments kept per pixel
-constexpr int kCandCap = 128;        // face elements whose box a ray hits (Newton seeds)
+constexpr int kCandCap = 64;         // face elements whose box a ray hits (Newton seeds)
 
 struct alignas(16) DevPatch {
     int32_t deg;           // isotropic degree 1..3
