@@ -11,6 +11,7 @@ steps) and the FP64 oracle timed on the host cores over a bounded pixel sample
 (whose parity against the GPU image is reported too).
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -24,6 +25,39 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s at 1080p, RGBA err ≤1e-3 vs FP64 oracle; MLP-seeded vs plain Newton"
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32, published (packed); 78.6 without packing
+
+
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "render_config3_1080p_counters.md")
+KERNEL_SOURCES = ["paper_1404_3363_amd/csrc/ivr_kernels.hip", "paper_1404_3363_amd/csrc/ivr_spline.h",
+                  "paper_1404_3363_amd/csrc/ivr_types.h", "paper_1404_3363_amd/csrc/ivr_mlp_dev.h"]
+
+
+def kernel_sources_sha256():
+    """Hash of the kernel sources (in this order): counter profiles record it."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter profile (FETCH_SIZE
+    and WRITE_SIZE passes, scaled by a plain copy), or None if the profile is
+    missing or was taken on other kernel sources."""
+    try:
+        with open(COUNTER_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    src = None
+    value = None
+    for line in text.splitlines():
+        if line.startswith("kernel sources sha256:"):
+            src = line.split(":", 1)[1].strip()
+        if line.startswith(f"traffic_bytes {kernel}:"):
+            value = float(line.split(":", 1)[1])
+    return value if (src == kernel_sources_sha256() and value is not None) else None
 
 
 def basis_flops(p):
@@ -257,7 +291,7 @@ def main():
     achieved = flops[dom] / (avg_ms[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(dom),
                 "avg_ms": {k: round(v, 4) for k, v in avg_ms.items()},
                 "algorithmic_gflop_per_launch": {k: round(v / 1e9, 3) for k, v in flops.items()}}
 
