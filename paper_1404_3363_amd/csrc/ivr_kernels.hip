@@ -253,24 +253,48 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
     int ent = facing(face, Pd.orient, Sa, Sb, d, grazing);
     const int patch = E.patch;
     if (!grazing && is_dup(fr, nfr, patch, ent, double(t), 2e-5 * fp.scaled)) return;
-    // FP64 refinement of the boundary root
+    // FP64 refinement of the boundary root by mixed-precision iterative
+    // refinement: the residual S(a, b) - o - t d in FP64 from the FP64 control
+    // points, the correction from the FP32 tangents of the converged FP32 root.
+    // It contracts by the FP32 tangents' relative error (~1e-7) per step, so from
+    // the FP32 stopping residual (<= 2e-6 scale) one step reaches ~1e-12 scale.
+    // A step of at most 1e-5 in (a, b) and 1e-5 scale in t leaves a residual below
+    // the 1e-9 scale acceptance bound and is taken without evaluating it again.
     const PatchView<double> pv64 = view_of<double>(Pd);
     const Arrays<double> ar64 = arrays_of(m, 0.0);
-    double A = a, B = b, T = t, S2[3], Sa2[3], Sb2[3], F2[3];
+    double A = a, B = b, T = t, S2[3], F2[3], Sa2[3], Sb2[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        Sa2[q] = double(Sa[q]);
+        Sb2[q] = double(Sb[q]);
+    }
     const double tol64 = 1e-12 * fp.scaled;
-    for (int k = 0;; ++k) {
-        eval_face<P, RAT, double>(pv64, ar64, face, A, B, S2, Sa2, Sb2);
+    bool ok = false;
+    for (int k = 0; k < 4; ++k) {
+        eval_face<P, RAT, double, false>(pv64, ar64, face, A, B, S2, Sa2, Sb2);
 #pragma unroll
         for (int q = 0; q < 3; ++q) F2[q] = S2[q] - od[q] - T * dd[q];
-        if (dot3(F2, F2) <= tol64 * tol64 || k == 3) break;
+        const double r2 = dot3(F2, F2);
+        if (r2 <= tol64 * tol64) {
+            ok = true;
+            break;
+        }
+        if (k == 3) {
+            ok = r2 <= 1e-18 * fp.scaled * fp.scaled;
+            break;
+        }
         ++n_polish;
-        double nd[3] = {-dd[0], -dd[1], -dd[2]}, rhs[3] = {-F2[0], -F2[1], -F2[2]}, st[3];
-        solve_cols(Sa2, Sb2, nd, rhs, st);
-        A += st[0];
-        B += st[1];
-        T += st[2];
+        RN nd[3] = {-d[0], -d[1], -d[2]}, rhs[3] = {RN(-F2[0]), RN(-F2[1]), RN(-F2[2])}, st[3];
+        solve_cols(Sa, Sb, nd, rhs, st);
+        A += double(st[0]);
+        B += double(st[1]);
+        T += double(st[2]);
+        if (fmax(fabs(double(st[0])), fabs(double(st[1]))) <= 1e-5 && fabs(double(st[2])) <= 1e-5 * fp.scaled) {
+            ok = true;
+            break;
+        }
     }
-    if (!(dot3(F2, F2) <= 1e-18 * fp.scaled * fp.scaled)) return;
+    if (!ok) return;
     const double mg64 = 1e-7;
     if (!(A >= -mg64 && A <= 1.0 + mg64 && B >= -mg64 && B <= 1.0 + mg64 && T > 0.0)) return;
     ent = facing(face, Pd.orient, Sa2, Sb2, dd, grazing);

@@ -60,9 +60,14 @@ __device__ __forceinline__ PatchView<R> view_of(const DevPatch &P) {
     return v;
 }
 
-// a / b: FP32 as a times the hardware reciprocal (1 ulp), FP64 exact.
+// a / b from the hardware reciprocal.  FP32: the reciprocal (1 ulp) times a.
 __device__ __forceinline__ float div_fast(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double div_fast(double a, double b) { return a / b; }
+// FP64: hardware reciprocal refined by one Newton step (relative error ~1e-16).
+__device__ __forceinline__ double div_fast(double a, double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, 1.0), r, r);
+    return a * r;
+}
 
 template <typename R> __device__ __forceinline__ R clamp01(R v) {
     return v < R(0) ? R(0) : (v > R(1) ? R(1) : v);
@@ -255,7 +260,8 @@ __device__ __forceinline__ void face_dirs(int face, int &dn, int &da, int &db) {
 // S(a,b), dS/da, dS/db on face f: the bivariate spline of the boundary layer.
 // Outside [0,1]^2 the polynomial of the nearest boundary span is continued, so
 // Newton iterates may leave the face and come back.
-template <int P, bool RAT, typename R>
+// With DERIV false only S is computed (Sa, Sb are left untouched).
+template <int P, bool RAT, typename R, bool DERIV = true>
 __device__ __forceinline__ void eval_face(const PatchView<R> &pv, const Arrays<R> &ar, int face,
                                           R a, R b, R (&S)[3], R (&Sa)[3], R (&Sb)[3]) {
     int dn, da, db;
@@ -266,8 +272,8 @@ __device__ __forceinline__ void eval_face(const PatchView<R> &pv, const Arrays<R
     const int sb = span_knots<P>(b, pv.n[db], pv.nspan[db], pv.inv_nspan[db], (pv.uniform >> db) & 1,
                                  ar.knots + pv.knot_off[db], tb);
     R Na[P + 1], dNa[P + 1], Nb[P + 1], dNb[P + 1];
-    basis_d1<P>(a, ta, Na, dNa);
-    basis_d1<P>(b, tb, Nb, dNb);
+    basis_d1<P, R, true>(a, ta, Na, dNa);
+    basis_d1<P, R, true>(b, tb, Nb, dNb);
     const int stride[3] = {1, pv.n[0], pv.n[0] * pv.n[1]};
     const int fix = (face & 1) ? pv.n[dn] - 1 : 0;
     const int base = pv.cp_off + fix * stride[dn] + (sa - P) * stride[da] + (sb - P) * stride[db];
@@ -287,14 +293,16 @@ __device__ __forceinline__ void eval_face(const PatchView<R> &pv, const Arrays<R
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 A0[c] += Na[ia] * v[c];
-                A1[c] += dNa[ia] * v[c];
+                if (DERIV) A1[c] += dNa[ia] * v[c];
             }
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             H[c] += Nb[jb] * A0[c];
-            Hb[c] += dNb[jb] * A0[c];
-            Ha[c] += Nb[jb] * A1[c];
+            if (DERIV) {
+                Hb[c] += dNb[jb] * A0[c];
+                Ha[c] += Nb[jb] * A1[c];
+            }
         }
     }
     if (RAT) {
@@ -302,15 +310,19 @@ __device__ __forceinline__ void eval_face(const PatchView<R> &pv, const Arrays<R
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             S[r] = H[r] * iw;
-            Sa[r] = (Ha[r] - S[r] * Ha[NC - 1]) * iw;
-            Sb[r] = (Hb[r] - S[r] * Hb[NC - 1]) * iw;
+            if (DERIV) {
+                Sa[r] = (Ha[r] - S[r] * Ha[NC - 1]) * iw;
+                Sb[r] = (Hb[r] - S[r] * Hb[NC - 1]) * iw;
+            }
         }
     } else {
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             S[r] = H[r];
-            Sa[r] = Ha[r];
-            Sb[r] = Hb[r];
+            if (DERIV) {
+                Sa[r] = Ha[r];
+                Sb[r] = Hb[r];
+            }
         }
     }
 }
