@@ -220,6 +220,94 @@ float orientation(const ivr_patch_desc &P) {
 // argument args[r-1] at level r.  Q holds the p+1 homogeneous control points
 // s-p..s.  The Bezier points of the span [t_s, t_{s+1}] are the blossoms at
 // (t_s^(p-j), t_{s+1}^j), j = 0..p.
+// Host evaluation of a block's face surface (projected), for matching shared
+// faces at upload.  Basis on the normalised knots by the triangular recurrence.
+static void host_basis(const double *t, int n, int p, double u, int &span, double *N) {
+    const double t0 = t[p], t1 = t[n];
+    auto tn = [&](int i) { return (t[i] - t0) / (t1 - t0); };
+    int s = p;
+    while (s < n - 1 && tn(s + 1) <= u) ++s;
+    span = s;
+    double left[4], right[4];
+    N[0] = 1.0;
+    for (int j = 1; j <= p; ++j) {
+        left[j] = u - tn(s + 1 - j);
+        right[j] = tn(s + j) - u;
+        double saved = 0.0;
+        for (int r = 0; r < j; ++r) {
+            const double tmp = N[r] / (right[r + 1] + left[j - r]);
+            N[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        N[j] = saved;
+    }
+}
+
+static void face_surface(const ivr_patch_desc &P, int face, double a, double b, double x[3]) {
+    const int dn = face >> 1, da = dn == 0 ? 1 : 0, db = dn == 2 ? 1 : 2, p = P.degree[0];
+    const int fix = (face & 1) ? P.ncp[dn] - 1 : 0;
+    int sa, sb;
+    double Na[4], Nb[4];
+    host_basis(P.knots[da], P.ncp[da], p, a, sa, Na);
+    host_basis(P.knots[db], P.ncp[db], p, b, sb, Nb);
+    double h[4] = {0, 0, 0, 0};
+    for (int jb = 0; jb <= p; ++jb)
+        for (int ia = 0; ia <= p; ++ia) {
+            int ijk[3];
+            ijk[dn] = fix; ijk[da] = sa - p + ia; ijk[db] = sb - p + jb;
+            const double *cc = P.cp + 4 * ((size_t)ijk[0] + (size_t)P.ncp[0] * (ijk[1] + (size_t)P.ncp[1] * ijk[2]));
+            const double w = P.rational ? cc[3] : 1.0, k = Na[ia] * Nb[jb] * w;
+            for (int c = 0; c < 3; ++c) h[c] += k * cc[c];
+            h[3] += k;
+        }
+    for (int c = 0; c < 3; ++c) x[c] = h[c] / h[3];
+}
+
+// Corner (ca, cb) of a face: its corner control point (clamped knots).
+static void face_point(const ivr_patch_desc &P, int face, int ca, int cb, double x[3]) {
+    face_surface(P, face, (double)ca, (double)cb, x);
+}
+
+// The distinct normalised breakpoints of a knot vector.
+static std::vector<double> breakpoints(const ivr_patch_desc &P, int d) {
+    const int p = P.degree[0], n = P.ncp[d];
+    const double *t = P.knots[d];
+    std::vector<double> u;
+    for (int i = p; i <= n; ++i) {
+        const double v = (t[i] - t[p]) / (t[n] - t[p]);
+        if (u.empty() || v > u.back()) u.push_back(v);
+    }
+    return u;
+}
+
+static bool same_surface(const ivr_patch_desc &P1, int f1, const ivr_patch_desc &P2, int f2, double tol) {
+    const int dn1 = f1 >> 1, dn2 = f2 >> 1;
+    const int da1 = dn1 == 0 ? 1 : 0, db1 = dn1 == 2 ? 1 : 2, da2 = dn2 == 0 ? 1 : 0, db2 = dn2 == 2 ? 1 : 2;
+    auto grid = [](std::vector<double> u, const std::vector<double> &v) {
+        u.insert(u.end(), v.begin(), v.end());
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end(), [](double x, double y) { return std::fabs(x - y) < 1e-14; }),
+                u.end());
+        return u;
+    };
+    const std::vector<double> ga = grid(breakpoints(P1, da1), breakpoints(P2, da2));
+    const std::vector<double> gb = grid(breakpoints(P1, db1), breakpoints(P2, db2));
+    const int m = std::max(P1.degree[0], P2.degree[0]) + 2;
+    for (size_t i = 0; i + 1 < ga.size(); ++i)
+        for (size_t j = 0; j + 1 < gb.size(); ++j)
+            for (int s = 0; s < m; ++s)
+                for (int r = 0; r < m; ++r) {
+                    const double a = ga[i] + (ga[i + 1] - ga[i]) * s / (m - 1);
+                    const double b = gb[j] + (gb[j + 1] - gb[j]) * r / (m - 1);
+                    double x1[3], x2[3];
+                    face_surface(P1, f1, a, b, x1);
+                    face_surface(P2, f2, a, b, x2);
+                    for (int c = 0; c < 3; ++c)
+                        if (!(std::fabs(x1[c] - x2[c]) <= tol)) return false;
+                }
+    return true;
+}
+
 static void blossom(const double *t, int s, int p, const double (*Q)[4], const double *args,
                     double out[4]) {
     double d[kMaxDegree + 1][4];
@@ -588,41 +676,44 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
         D.elem_off[6] = (int)elems.size();
         D.tile_off[6] = (int)tiles.size();
     }
-    // Faces shared by two blocks (identical boundary nets and knot vectors, as at
-    // conforming interfaces): test them from the first block only and emit the
-    // second block's crossing from the same root.
+    // Faces shared by two blocks of a model: the same parametric surface S(a, b)
+    // (as at conforming interfaces, also between blocks of different degree or
+    // knots): test them from the first block only and emit the second block's
+    // crossing from the same root.  Candidates share their four corners; the
+    // surfaces are then compared at (p+2)^2 points of every span of the union of
+    // both knot grids, which decides equality of the piecewise polynomials.
     {
-        std::map<std::vector<double>, int> seen;
         for (int pi = 0; pi < n; ++pi) {
             for (int f = 0; f < 6; ++f) hp[pi].twin[f] = -1;
             hp[pi].face_skip = 0;
         }
+        std::map<std::vector<long long>, std::vector<int>> by_corners;
         for (int pi = 0; pi < n; ++pi) {
-            const auto &P = patches[pi];
-            const int p = P.degree[0], n0 = P.ncp[0], n1 = P.ncp[1];
+            const double q = 1e-9 * models[model_of[pi]].scale;
             for (int f = 0; f < 6; ++f) {
-                const int dn = f >> 1, da = dn == 0 ? 1 : 0, db = dn == 2 ? 1 : 2;
-                const int fix = (f & 1) ? P.ncp[dn] - 1 : 0;
-                std::vector<double> key = {(double)model_of[pi], (double)p, (double)P.rational,
-                                           (double)P.ncp[da], (double)P.ncp[db]};
-                for (int d : {da, db}) {
-                    const double *t = P.knots[d];
-                    const double t0 = t[p], t1 = t[P.ncp[d]];
-                    for (int i = 0; i < P.ncp[d] + p + 1; ++i) key.push_back((t[i] - t0) / (t1 - t0));
-                }
-                for (int jb = 0; jb < P.ncp[db]; ++jb)
-                    for (int ia = 0; ia < P.ncp[da]; ++ia) {
-                        int ijk[3];
-                        ijk[dn] = fix; ijk[da] = ia; ijk[db] = jb;
-                        const double *cc = P.cp + 4 * ((size_t)ijk[0] + (size_t)n0 * (ijk[1] + (size_t)n1 * ijk[2]));
-                        key.insert(key.end(), {cc[0], cc[1], cc[2], P.rational ? cc[3] : 1.0});
+                std::vector<long long> key = {model_of[pi]};
+                for (int cb = 0; cb < 2; ++cb)
+                    for (int ca = 0; ca < 2; ++ca) {
+                        double x[3];
+                        face_point(patches[pi], f, ca, cb, x);
+                        for (int c = 0; c < 3; ++c) key.push_back(std::llround(x[c] / q));
                     }
-                auto it = seen.find(key);
-                if (it == seen.end()) {
-                    seen.emplace(std::move(key), 8 * pi + f);
-                } else if ((it->second >> 3) != pi && hp[it->second >> 3].twin[it->second & 7] < 0) {
-                    hp[it->second >> 3].twin[it->second & 7] = 8 * pi + f;
-                    hp[pi].face_skip |= 1 << f;
+                by_corners[key].push_back(8 * pi + f);
+            }
+        }
+        for (auto &kv : by_corners) {
+            const auto &fl = kv.second;
+            for (size_t i = 0; i < fl.size(); ++i) {
+                const int p1 = fl[i] >> 3, f1 = fl[i] & 7;
+                if (hp[p1].twin[f1] >= 0 || ((hp[p1].face_skip >> f1) & 1)) continue;
+                for (size_t j = i + 1; j < fl.size(); ++j) {
+                    const int p2 = fl[j] >> 3, f2 = fl[j] & 7;
+                    if (p2 == p1 || hp[p2].twin[f2] >= 0 || ((hp[p2].face_skip >> f2) & 1)) continue;
+                    if (!same_surface(patches[p1], f1, patches[p2], f2, 1e-10 * models[model_of[p1]].scale))
+                        continue;
+                    hp[p1].twin[f1] = 8 * p2 + f2;
+                    hp[p2].face_skip |= 1 << f2;
+                    break;
                 }
             }
         }
