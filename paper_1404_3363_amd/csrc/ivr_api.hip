@@ -33,6 +33,7 @@ struct ivr_ctx {
     float *d_knots32 = nullptr;
     double *d_knots64 = nullptr;
     FaceElem *d_elems = nullptr;
+    float *d_btab = nullptr;
     FaceTile *d_tiles = nullptr;
     int npatch = 0, nelem = 0;
     double scale = 1.0;
@@ -66,6 +67,7 @@ struct ivr_ctx {
     uint32_t *d_pperm = nullptr, *d_pcount = nullptr, *d_pbase = nullptr, *d_pcur = nullptr;
     int cls_q[kClasses + 1] = {0};       // class k's blocks are pperm[cls_q[k] .. cls_q[k+1])
     int cls_max_cp[kClasses] = {0};      // largest control net of the class
+    int cls_max_tab[kClasses] = {0};     // largest basis tables of the class (floats)
     unsigned long long *d_ctr = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // phase events of renders recorded with opts.timing (4 per render)
@@ -308,6 +310,56 @@ static bool same_surface(const ivr_patch_desc &P1, int f1, const ivr_patch_desc 
     return true;
 }
 
+// Basis tables: on knot span e of direction d, the p+1 non-zero basis functions
+// as polynomials in x = (u - t_e) / (t_{e+1} - t_e); coefficients from their
+// values at p+1 points of the span (Vandermonde solve in FP64).
+static void basis_tables(const ivr_patch_desc &P, int d, std::vector<float> &out) {
+    const int p = P.degree[0], n = P.ncp[d];
+    const double *t = P.knots[d];
+    const double t0 = t[p], t1 = t[n];
+    for (int e = p; e < n; ++e) {
+        const double a = (t[e] - t0) / (t1 - t0), b = (t[e + 1] - t0) / (t1 - t0);
+        double V[4][4], rhs[4][4];
+        for (int j = 0; j <= p; ++j) {
+            const double x = p ? (double)j / p : 0.0;
+            double pw = 1.0;
+            for (int k = 0; k <= p; ++k, pw *= x) V[j][k] = pw;
+            // evaluate inside the span (the right end belongs to it here)
+            const double u = std::min(a + x * (b - a), b - 1e-13 * (b - a));
+            int span;
+            double N[4];
+            host_basis(P.knots[d], n, p, std::max(u, a), span, N);
+            // host_basis may land on an earlier span only for empty spans
+            for (int i = 0; i <= p; ++i) rhs[j][i] = (span == e) ? N[i] : 0.0;
+        }
+        // solve V c_i = rhs[:, i] for every function i (Gaussian elimination)
+        for (int i = 0; i <= p; ++i) {
+            double M[4][5];
+            for (int r = 0; r <= p; ++r) {
+                for (int k = 0; k <= p; ++k) M[r][k] = V[r][k];
+                M[r][p + 1] = rhs[r][i];
+            }
+            for (int c = 0; c <= p; ++c) {
+                int piv = c;
+                for (int r = c + 1; r <= p; ++r)
+                    if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+                for (int k = 0; k <= p + 1; ++k) std::swap(M[c][k], M[piv][k]);
+                for (int r = c + 1; r <= p; ++r) {
+                    const double f = M[r][c] / M[c][c];
+                    for (int k = c; k <= p + 1; ++k) M[r][k] -= f * M[c][k];
+                }
+            }
+            double cf[4];
+            for (int r = p; r >= 0; --r) {
+                double s = M[r][p + 1];
+                for (int k = r + 1; k <= p; ++k) s -= M[r][k] * cf[k];
+                cf[r] = s / M[r][r];
+            }
+            for (int k = 0; k <= p; ++k) out.push_back((float)cf[k]);
+        }
+    }
+}
+
 static void blossom(const double *t, int s, int p, const double (*Q)[4], const double *args,
                     double out[4]) {
     double d[kMaxDegree + 1][4];
@@ -464,7 +516,7 @@ const char *ivr_last_error(const ivr_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 static void free_model(ivr_ctx *c) {
     dfree(c->d_patches); dfree(c->d_cp32); dfree(c->d_rho32); dfree(c->d_cp64); dfree(c->d_rho64);
-    dfree(c->d_knots32); dfree(c->d_knots64); dfree(c->d_elems); dfree(c->d_tiles);
+    dfree(c->d_knots32); dfree(c->d_knots64); dfree(c->d_elems); dfree(c->d_tiles); dfree(c->d_btab);
     dfree(c->d_pperm); dfree(c->d_pcount); dfree(c->d_pbase); dfree(c->d_pcur);
     c->has_model = false;
 }
@@ -559,6 +611,7 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     std::vector<double> rho64, knots64;
     std::vector<FaceElem> elems;
     std::vector<FaceTile> tiles;
+    std::vector<float> btab;
     uint32_t class_mask = 0;
     for (int pi = 0; pi < n; ++pi) {
         const auto &P = patches[pi];
@@ -592,6 +645,9 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
                 knots64.push_back(tn[d][i]);
             }
         }
+        D.btab_off = (int)btab.size();
+        for (int d = 0; d < 3; ++d) basis_tables(P, d, btab);
+        D.btab_len = (int)btab.size() - D.btab_off;
         const int n0 = P.ncp[0], n1 = P.ncp[1], n2 = P.ncp[2];
         const size_t N = (size_t)n0 * n1 * n2;
         Box pb;
@@ -720,13 +776,14 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     }
     // blocks grouped by degree class (stable), with each class's range and largest net
     std::vector<uint32_t> pperm;
-    int cls_q[kClasses + 1] = {0}, cls_max_cp[kClasses] = {0};
+    int cls_q[kClasses + 1] = {0}, cls_max_cp[kClasses] = {0}, cls_max_tab[kClasses] = {0};
     for (int k = 0; k < kClasses; ++k) {
         cls_q[k] = (int)pperm.size();
         for (int pi = 0; pi < n; ++pi)
             if (hp[pi].klass == k) {
                 pperm.push_back((uint32_t)pi);
                 cls_max_cp[k] = std::max(cls_max_cp[k], hp[pi].n[0] * hp[pi].n[1] * hp[pi].n[2]);
+                cls_max_tab[k] = std::max(cls_max_tab[k], hp[pi].btab_len);
             }
     }
     cls_q[kClasses] = (int)pperm.size();
@@ -741,6 +798,7 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     bool ok = up(tmp.d_patches, hp) && up(tmp.d_cp32, cp32) && up(tmp.d_rho32, rho32) &&
               up(tmp.d_cp64, cp64) && up(tmp.d_rho64, rho64) && up(tmp.d_knots32, knots32) &&
               up(tmp.d_knots64, knots64) && up(tmp.d_elems, elems) && up(tmp.d_tiles, tiles) &&
+              up(tmp.d_btab, btab) &&
               up(tmp.d_pperm, pperm) && up(tmp.d_pcount, zeros) && up(tmp.d_pbase, zeros) &&
               up(tmp.d_pcur, zeros);
     if (!ok) {
@@ -754,10 +812,13 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     c->d_patches = tmp.d_patches; c->d_cp32 = tmp.d_cp32; c->d_rho32 = tmp.d_rho32;
     c->d_cp64 = tmp.d_cp64; c->d_rho64 = tmp.d_rho64; c->d_knots32 = tmp.d_knots32;
     c->d_knots64 = tmp.d_knots64; c->d_elems = tmp.d_elems; c->d_tiles = tmp.d_tiles;
+    c->d_btab = tmp.d_btab;
+    tmp.d_btab = nullptr;
     c->d_pperm = tmp.d_pperm; c->d_pcount = tmp.d_pcount; c->d_pbase = tmp.d_pbase; c->d_pcur = tmp.d_pcur;
     tmp.d_pperm = tmp.d_pcount = tmp.d_pbase = tmp.d_pcur = nullptr;
     std::copy(cls_q, cls_q + kClasses + 1, c->cls_q);
     std::copy(cls_max_cp, cls_max_cp + kClasses, c->cls_max_cp);
+    std::copy(cls_max_tab, cls_max_tab + kClasses, c->cls_max_tab);
     tmp.d_tiles = nullptr;
     tmp.d_patches = nullptr; tmp.d_cp32 = nullptr; tmp.d_rho32 = nullptr; tmp.d_cp64 = nullptr;
     tmp.d_rho64 = nullptr; tmp.d_knots32 = nullptr; tmp.d_knots64 = nullptr; tmp.d_elems = nullptr;
@@ -949,6 +1010,7 @@ static Model device_model(ivr_ctx *c) {
     m.patches = c->d_patches; m.cp32 = c->d_cp32; m.rho32 = c->d_rho32; m.cp64 = c->d_cp64;
     m.rho64 = c->d_rho64; m.knots32 = c->d_knots32; m.knots64 = c->d_knots64; m.elems = c->d_elems;
     m.tiles = c->d_tiles;
+    m.btab = c->d_btab;
     m.mlp_wb = c->mlp.wb;
     m.mlp_norm = c->mlp.norm;
     m.npatch = c->npatch; m.scale = (float)c->scale; m.scaled = c->scale;
@@ -1037,6 +1099,7 @@ static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const LaunchCfg &lc, 
         ia.pcount = c->d_pcount;
         ia.pcur = c->d_pcur;
         ia.max_cp = c->cls_max_cp[k];
+        ia.max_tab = c->cls_max_tab[k];
         IVR_HIP(c, launch_integrate(b.fp64, k, m, c->d_views, b.n, c->d_segs, ia, c->d_results, c->d_ctr,
                                     c->n_cu, lc, s));
     }
@@ -1295,7 +1358,7 @@ static Model model_of(ivr_ctx *c) {
     std::memset(&m, 0, sizeof m);
     m.patches = c->d_patches; m.cp32 = c->d_cp32; m.rho32 = c->d_rho32; m.cp64 = c->d_cp64;
     m.rho64 = c->d_rho64; m.knots32 = c->d_knots32; m.knots64 = c->d_knots64; m.elems = c->d_elems;
-    m.tiles = c->d_tiles; m.mlp_wb = c->mlp.wb; m.mlp_norm = c->mlp.norm;
+    m.tiles = c->d_tiles; m.btab = c->d_btab; m.mlp_wb = c->mlp.wb; m.mlp_norm = c->mlp.norm;
     m.npatch = c->npatch; m.scale = (float)c->scale; m.scaled = c->scale;
     return m;
 }

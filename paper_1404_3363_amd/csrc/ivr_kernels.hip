@@ -665,6 +665,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     ViewLds *vls = reinterpret_cast<ViewLds *>(smem_raw);
     float4 *lds_cp = reinterpret_cast<float4 *>(smem_raw + sizeof(ViewLds) * n_views);
     float *lds_rho = reinterpret_cast<float *>(lds_cp + max_cp);
+    float *lds_tab = lds_rho + (RAT ? (max_cp + 3) / 4 * 4 : 0);   // 16-byte aligned
     __shared__ int s_q;
     view_stage(views, n_views, vls);
     const FrameParams fp = views[0].fp;   // the batch's options (uniform)
@@ -738,9 +739,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 lds_cp[i] = m.cp32[pv.cp_off + i];
                 if (RAT) lds_rho[i] = m.rho32[pv.cp_off + i];
             }
+            const DevPatch &Pb = m.patches[blk];
+            for (int i = threadIdx.x; i < Pb.btab_len; i += blockDim.x) lds_tab[i] = m.btab[Pb.btab_off + i];
             pv.cp_off = 0;
             ar.cp = reinterpret_cast<const typename CpType<R>::T *>(lds_cp);
             ar.rho = reinterpret_cast<const R *>(lds_rho);
+            ar.tab = lds_tab;
         }
         __syncthreads();
         bool queue_empty = false;
@@ -799,7 +803,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         // shrinking, the same evaluation gives the Newton step J^-1 (gin - phi(p)).
         R k1[3], k2[3], k3[3], k4[3], k5[3], k6[3], rho_cur = R(0), grho[3], res2 = R(0);
         const bool shrinking = shrink != 0;
-        const R det1 = eval_W<P, RAT, 2>(pv, ar, p, gin, d, cperp, dthr, k1, rho_cur,
+        const R det1 = eval_W<P, RAT, 2, R, LDS>(pv, ar, p, gin, d, cperp, dthr, k1, rho_cur,
                                          grho, c_fp64, shrinking, res2);
         ++c_w;
         const R m_cur = dot3(grho, k1);
@@ -891,7 +895,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             R q[3], dummy, dg[3], dr2;
 #define IVR_STAGE(KOUT, EXPR)                                                              \
     _Pragma("unroll") for (int c = 0; c < 3; ++c) q[c] = clamp01(p[c] + hh * (EXPR));      \
-    eval_W<P, RAT, 0>(pv, ar, q, gin, d, cperp, dthr, KOUT, dummy, dg, c_fp64, false, dr2); \
+    eval_W<P, RAT, 0, R, LDS>(pv, ar, q, gin, d, cperp, dthr, KOUT, dummy, dg, c_fp64, false, dr2); \
     ++c_w;
             IVR_STAGE(k2, K::a21 * k1[c])
             IVR_STAGE(k3, K::a31 * k1[c] + K::a32 * k2[c])
@@ -1056,7 +1060,10 @@ static hipError_t launch_integrate_t(const Model &m, const ViewRec *views, int n
                                      const IntegrateArgs &a, float4 *results, unsigned long long *ctr,
                                      int n_cu, const LaunchCfg &lc, hipStream_t st) {
     const size_t lds = sizeof(ViewLds) * (size_t)n_views +
-                       (LDS ? (size_t)a.max_cp * (sizeof(float4) + (RAT ? sizeof(float) : 0)) : 0);
+                       (LDS ? (size_t)a.max_cp * sizeof(float4) +
+                                  (RAT ? (size_t)(a.max_cp + 3) / 4 * 4 * sizeof(float) : 0) +
+                                  (size_t)a.max_tab * sizeof(float)
+                            : 0);
     const int block = lc.int_block;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<P, RAT, R, LDS>, block, lds) !=
@@ -1076,7 +1083,9 @@ static hipError_t launch_integrate_pr(bool fp64, const Model &m, const ViewRec *
                                       hipStream_t st) {
     if (fp64)
         return launch_integrate_t<P, RAT, double, false>(m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
-    const size_t bytes = (size_t)a.max_cp * (sizeof(float4) + (RAT ? sizeof(float) : 0));
+    const size_t bytes = (size_t)a.max_cp * sizeof(float4) +
+                         (RAT ? (size_t)(a.max_cp + 3) / 4 * 4 * sizeof(float) : 0) +
+                         (size_t)a.max_tab * sizeof(float);
     if (bytes <= kLdsBlockBytes)
         return launch_integrate_t<P, RAT, float, true>(m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
     return launch_integrate_t<P, RAT, float, false>(m, views, n_views, segs, a, results, ctr, n_cu, lc, st);

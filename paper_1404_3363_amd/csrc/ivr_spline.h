@@ -25,13 +25,14 @@ struct Arrays {
     const typename CpType<R>::T *cp;
     const R *rho;
     const R *knots;
+    const float *tab;   // the block's basis tables (evaluators with TAB only)
 };
 
 __device__ __forceinline__ Arrays<float> arrays_of(const Model &m, float) {
-    return {m.cp32, m.rho32, m.knots32};
+    return {m.cp32, m.rho32, m.knots32, nullptr};
 }
 __device__ __forceinline__ Arrays<double> arrays_of(const Model &m, double) {
-    return {m.cp64, m.rho64, m.knots64};
+    return {m.cp64, m.rho64, m.knots64, nullptr};
 }
 
 // Per-block quantities the evaluators need.
@@ -134,6 +135,48 @@ __device__ __forceinline__ void basis_d1(R u, const R (&t)[2 * P], R (&N)[P + 1]
     }
 }
 
+// The P+1 non-zero basis functions of direction d at u and their derivatives,
+// from the block's per-span polynomial tables (Horner in the local coordinate
+// x = (u - t_e) / (t_{e+1} - t_e)).  Returns the span index s (t_s <= u < t_{s+1}).
+template <int P, typename R>
+__device__ __forceinline__ int basis_tab(const float *tab_d, R u_in, int n, int nspan, bool uniform,
+                                         const R *__restrict__ kn, R (&N)[P + 1], R (&dN)[P + 1]) {
+    const R u = clamp01(u_in);
+    int e;
+    R x, dxdu;
+    if (uniform) {
+        const R un = u * R(nspan);
+        e = (int)un;
+        e = e > nspan - 1 ? nspan - 1 : e;
+        x = un - R(e);
+        dxdu = R(nspan);
+    } else {
+        int lo = P, hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (kn[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        e = lo - P;
+        const R t0 = kn[lo], dt = kn[lo + 1] - t0;
+        dxdu = div_fast(R(1), dt);
+        x = (u - t0) * dxdu;
+    }
+    const float *c = tab_d + e * (P + 1) * (P + 1);
+#pragma unroll
+    for (int i = 0; i <= P; ++i) {
+        R v = R(c[i * (P + 1) + P]), dv = R(P) * R(c[i * (P + 1) + P]);
+#pragma unroll
+        for (int k = P - 1; k >= 0; --k) {
+            v = v * x + R(c[i * (P + 1) + k]);
+            if (k > 0) dv = dv * x + R(k) * R(c[i * (P + 1) + k]);
+        }
+        N[i] = v;
+        dN[i] = dv * dxdu;
+    }
+    return e + P;
+}
+
 template <typename R>
 __device__ __forceinline__ void load_cp(const typename CpType<R>::T &c, R (&v)[4]) {
     v[0] = c.x; v[1] = c.y; v[2] = c.z; v[3] = c.w;
@@ -141,22 +184,34 @@ __device__ __forceinline__ void load_cp(const typename CpType<R>::T &c, R (&v)[4
 
 // phi(p), J[r][c] = d phi_r / d p_c and rho(p): RHO = 0 no rho, 1 value,
 // 2 value and parameter gradient g[c] = d rho / d p_c.
-template <int P, bool RAT, int RHO, typename R>
+// With TAB the basis comes from the block's polynomial tables (ar.tab).
+template <int P, bool RAT, int RHO, typename R, bool TAB = false>
 __device__ __forceinline__ void eval_volume(const PatchView<R> &pv, const Arrays<R> &ar,
                                             const R (&p)[3], R (&x)[3], R (&J)[3][3], R &rho,
                                             R (&g)[3]) {
     const R pc[3] = {clamp01(p[0]), clamp01(p[1]), clamp01(p[2])};
-    R tu[2 * P], tv[2 * P], tw[2 * P];
-    const int su = span_knots<P>(pc[0], pv.n[0], pv.nspan[0], pv.inv_nspan[0], pv.uniform & 1,
-                                 ar.knots + pv.knot_off[0], tu);
-    const int sv = span_knots<P>(pc[1], pv.n[1], pv.nspan[1], pv.inv_nspan[1], pv.uniform & 2,
-                                 ar.knots + pv.knot_off[1], tv);
-    const int sw = span_knots<P>(pc[2], pv.n[2], pv.nspan[2], pv.inv_nspan[2], pv.uniform & 4,
-                                 ar.knots + pv.knot_off[2], tw);
     R Nu[P + 1], dNu[P + 1], Nv[P + 1], dNv[P + 1], Nw[P + 1], dNw[P + 1];
-    basis_d1<P, R, true>(pc[0], tu, Nu, dNu);
-    basis_d1<P, R, true>(pc[1], tv, Nv, dNv);
-    basis_d1<P, R, true>(pc[2], tw, Nw, dNw);
+    int su, sv, sw;
+    if constexpr (TAB) {
+        constexpr int Q2 = (P + 1) * (P + 1);
+        su = basis_tab<P>(ar.tab, pc[0], pv.n[0], pv.nspan[0], pv.uniform & 1, ar.knots + pv.knot_off[0],
+                          Nu, dNu);
+        sv = basis_tab<P>(ar.tab + pv.nspan[0] * Q2, pc[1], pv.n[1], pv.nspan[1], pv.uniform & 2,
+                          ar.knots + pv.knot_off[1], Nv, dNv);
+        sw = basis_tab<P>(ar.tab + (pv.nspan[0] + pv.nspan[1]) * Q2, pc[2], pv.n[2], pv.nspan[2],
+                          pv.uniform & 4, ar.knots + pv.knot_off[2], Nw, dNw);
+    } else {
+        R tu[2 * P], tv[2 * P], tw[2 * P];
+        su = span_knots<P>(pc[0], pv.n[0], pv.nspan[0], pv.inv_nspan[0], pv.uniform & 1,
+                           ar.knots + pv.knot_off[0], tu);
+        sv = span_knots<P>(pc[1], pv.n[1], pv.nspan[1], pv.inv_nspan[1], pv.uniform & 2,
+                           ar.knots + pv.knot_off[1], tv);
+        sw = span_knots<P>(pc[2], pv.n[2], pv.nspan[2], pv.inv_nspan[2], pv.uniform & 4,
+                           ar.knots + pv.knot_off[2], tw);
+        basis_d1<P, R, true>(pc[0], tu, Nu, dNu);
+        basis_d1<P, R, true>(pc[1], tv, Nv, dNv);
+        basis_d1<P, R, true>(pc[2], tw, Nw, dNw);
+    }
     constexpr int NC = RAT ? 4 : 3;
     const int n0 = pv.n[0], n01 = pv.n[0] * pv.n[1];
     const int base = pv.cp_off + (su - P) + n0 * (sv - P) + n01 * (sw - P);
@@ -374,12 +429,12 @@ __device__ __forceinline__ R eval_rho_ds(const PatchView<R> &pv, const Arrays<R>
 // near-singular systems are solved again in FP64.
 // With newton set, the right-hand side is r = gin - phi(p) instead, so W is the
 // Newton step of phi(p) = gin (Eq. (newtonsmethod)); res2 = |r|^2.
-template <int P, bool RAT, int RHO, typename R>
+template <int P, bool RAT, int RHO, typename R, bool TAB = false>
 __device__ __forceinline__ R eval_W(const PatchView<R> &pv, const Arrays<R> &ar, const R (&p)[3],
                                     const R (&gin)[3], const R (&d)[3], R c, R det_thr, R (&W)[3],
                                     R &rho, R (&grho)[3], uint32_t &n_fp64, bool newton, R &res2) {
     R x[3], J[3][3];
-    eval_volume<P, RAT, RHO>(pv, ar, p, x, J, rho, grho);
+    eval_volume<P, RAT, RHO, R, TAB>(pv, ar, p, x, J, rho, grho);
     R r[3] = {gin[0] - x[0], gin[1] - x[1], gin[2] - x[2]};
     const R rd = dot3(r, d);
     res2 = dot3(r, r);

@@ -44,7 +44,9 @@ struct alignas(16) DevPatch {
     float pad0;
     int32_t twin[6];       // face shared with another block: 8*block + face, or -1
     int32_t face_skip;     // bit f: face f is the twin of a face tested from the other block
-    int32_t pad1;
+    int32_t btab_off;      // first float of the block's basis tables (see Model::btab)
+    int32_t btab_len;      // floats of the block's basis tables
+    int32_t pad2[3];
 };
 
 // Face element: oriented box around the element's control points (axes from the
@@ -90,6 +92,11 @@ struct Model {
     const double *knots64;
     const FaceElem *elems;
     const FaceTile *tiles;
+    // Per block, direction d (0..2) and knot span e: the deg+1 non-zero basis
+    // functions on the span as polynomials in the local coordinate x in [0,1],
+    // (deg+1)^2 coefficients (function i, power k at [i*(deg+1)+k]); directions
+    // follow each other, spans in order.
+    const float *btab;
     const uint16_t *mlp_wb;    // BF16 MLP weights per block (seed_mode MLP)
     const float *mlp_norm;     // per block: (unused[3], 1/half extent[3], centre[3], pad[3])
     int32_t npatch;
@@ -121,6 +128,7 @@ struct IntegrateArgs {
     const uint32_t *pbase, *pcount;
     uint32_t *pcur;
     int32_t max_cp;
+    int32_t max_tab;
 };
 
 struct FrameParams {
