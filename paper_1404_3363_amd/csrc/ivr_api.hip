@@ -63,6 +63,9 @@ struct ivr_ctx {
     uint2 *d_seg_kr = nullptr;           // (block, rank among the block's segments)
     uint32_t *d_order = nullptr;         // segment indices sorted by block
     QueueState *d_qs = nullptr;
+    // two-pass fragment kernel with MLP seeds (grow-only)
+    MlpQueries mq = {nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0};
+    size_t mq_tiles = 0;
     // blocks grouped by degree class (the integrators take their segments block by block)
     uint32_t *d_pperm = nullptr, *d_pcount = nullptr, *d_pbase = nullptr, *d_pcur = nullptr;
     int cls_q[kClasses + 1] = {0};       // class k's blocks are pperm[cls_q[k] .. cls_q[k+1])
@@ -532,8 +535,15 @@ static void drop_graphs(ivr_ctx *c) {
     ++c->generation;
 }
 
+static void free_mlp_queries(ivr_ctx *c) {
+    dfree(c->mq.query); dfree(c->mq.seed); dfree(c->mq.chunks); dfree(c->mq.clist); dfree(c->mq.crange);
+    c->mq.q_cap = c->mq.chunk_cap = c->mq.c_cap = 0;
+    c->mq_tiles = 0;
+}
+
 static void free_frame(ivr_ctx *c) {
     drop_graphs(c);
+    free_mlp_queries(c);
     dfree(c->d_segs); dfree(c->d_results); dfree(c->d_pixseg); dfree(c->d_seg_kr); dfree(c->d_order);
     c->pix_cap = c->seg_cap = c->seg_bytes_cap = 0;
 }
@@ -986,6 +996,31 @@ static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
     return IVR_OK;
 }
 
+// Buffers of the MLP-seeded fragment passes: 8 candidates per pixel on average
+// (a lane keeps at most 64), 16 chunks per tile.
+static ivr_status ensure_mlp_queries(ivr_ctx *c, size_t pixels, size_t tiles) {
+    const size_t cap = std::max<size_t>(pixels * 8, 1024);
+    if (tiles <= c->mq_tiles && cap <= c->mq.q_cap) return IVR_OK;
+    IVR_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    free_mlp_queries(c);
+    if (cap > 0xFFFFFFFEull || tiles * 64 > 0xFFFFFFFFull)
+        return fail(c, IVR_EOVERFLOW, "batch too large for the MLP seed buffers");
+    if (hipMalloc((void **)&c->mq.query, sizeof(float4) * cap) != hipSuccess ||
+        hipMalloc((void **)&c->mq.seed, sizeof(float4) * cap) != hipSuccess ||
+        hipMalloc((void **)&c->mq.chunks, sizeof(uint4) * tiles * 16) != hipSuccess ||
+        hipMalloc((void **)&c->mq.clist, sizeof(uint2) * cap) != hipSuccess ||
+        hipMalloc((void **)&c->mq.crange, sizeof(uint2) * tiles * 64) != hipSuccess) {
+        free_mlp_queries(c);
+        return fail(c, IVR_ENOMEM, "MLP seed buffer allocation failed");
+    }
+    c->mq.q_cap = (uint32_t)cap;
+    c->mq.c_cap = (uint32_t)cap;
+    c->mq.chunk_cap = (uint32_t)(tiles * 16);
+    c->mq_tiles = tiles;
+    return IVR_OK;
+}
+
 static ivr_status ensure_views(ivr_ctx *c, int n) {
     if (n <= c->view_cap) return IVR_OK;
     IVR_HIP(c, hipStreamSynchronize(c->stream));
@@ -1073,7 +1108,9 @@ static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr
         return fail(c, IVR_EOVERFLOW, "batch too large for 32-bit segment indices");
     b.n_tiles = (uint32_t)tiles;
     b.n_pixels = (uint32_t)pixels;
-    return ensure_frame(c, pixels, b.fp64);
+    st = ensure_frame(c, pixels, b.fp64);
+    if (st != IVR_OK) return st;
+    return b.mlp ? ensure_mlp_queries(c, pixels, tiles) : IVR_OK;
 }
 
 // The launches of one batch: clear, fragments, one integrator per degree class, merge.
@@ -1084,7 +1121,7 @@ static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const LaunchCfg &lc, 
     if (ev) IVR_HIP(c, hipEventRecord(ev[0], s));
     IVR_HIP(c, launch_fragments(b.fp64, b.mlp, m, c->d_views, b.n, b.n_tiles, lc, c->d_segs,
                                 (uint32_t)c->seg_cap, c->d_seg_kr, c->d_pcount, c->d_qs, c->d_pixseg,
-                                c->d_ctr, s));
+                                c->mq, c->d_ctr, c->n_cu, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[1], s));
     IVR_HIP(c, launch_block_sort(c->d_qs, (uint32_t)c->seg_cap, c->d_seg_kr, c->d_pperm, c->npatch,
                                  c->d_pcount, c->d_pbase, c->d_pcur, c->d_order, c->n_cu, s));

@@ -227,7 +227,7 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
             float x[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) x[q] = of[q] + tm * df[q];
-            if (fp.seed_mode == IVR_SEED_MLP) {
+            if (fp.seed_mode == IVR_SEED_MLP && isfinite(mseed[0])) {
                 a = RN(clamp01(mseed[da]));
                 b = RN(clamp01(mseed[db]));
             } else {
@@ -361,11 +361,15 @@ __device__ __forceinline__ int view_of_tile(const ViewRec *views, int n_views, u
     return __builtin_amdgcn_readfirstlane(lo);
 }
 
-template <typename R, bool MLP>
+// MODE 0: the whole fragment pass (box or plain seeds).  With MLP seeds it runs
+// in two passes around k_mlp_seeds: MODE 1 traverses and records the candidates
+// with one network query each (grouped per block and wave), MODE 2 reads the
+// candidates and their seeds back and does the rest.
+template <typename R, int MODE>
 __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views, int n_views,
                                                   u32 n_tiles, LaunchCfg lc, Seg<R> *segs, u32 seg_cap,
                                                   uint2 *seg_kr, u32 *pcount, QueueState *qs,
-                                                  uint2 *pixseg, u64 *ctr) {
+                                                  uint2 *pixseg, MlpQueries mq, u64 *ctr) {
     const int lane = threadIdx.x;
     // Consecutive blocks are dealt round-robin to the 8 XCDs.  With xcd_chunk = C
     // > 0, XCD x's j-th block takes tile j mod C of chunk (j / C) * 8 + x: runs of C
@@ -408,33 +412,16 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     //    first) become Newton seeds; 2. the seeds are solved with all lanes in
     //    step, whenever a lane's list is full and at the end.
     u32 cand[kCandCap];
+    u32 qidx[MODE == 1 ? kCandCap : 1];
     int ncand = 0;
-    Frag<R> fr[kFragCap];
+    Frag<R> fr[MODE == 1 ? 1 : kFragCap];
     int nfr = 0;
-    // seed_mode MLP: candidates are solved per block (flushed after each block), so
-    // the wave evaluates one block's MLP for all its lanes at once on MFMA
-    __shared__ uint16_t sA[64 * 72];
-    __shared__ float sY[64 * 4];
-    constexpr bool mlp = MLP;   // a separate instantiation keeps the MFMA path's registers out of the others
     // (always inlined: a call would see the kernel's pointers as generic and load through flat)
-    auto solve_candidates = [&](int block) __attribute__((always_inline)) {
+    auto solve_candidates = [&]() __attribute__((always_inline)) {
         for (int k = 0; __ballot(k < ncand) != 0; ++k) {
-            float ms[3] = {0.f, 0.f, 0.f};
-            if constexpr (mlp) {
-                float x[3] = {of[0], of[1], of[2]};
-                if (k < ncand) {
-                    const FaceElem &E = m.elems[cand[k]];
-                    float t0, t1;
-                    obb_hit(E, of, df, t0, t1);
-                    const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) x[q] = of[q] + tm * df[q];
-                    ++c_mlp;
-                }
-                mlp_infer_wave(m.mlp_wb, m.mlp_norm, block, x, ms, sA, sY);
-            }
             if (k < ncand) {
                 const FaceElem E = m.elems[cand[k]];
+                const float ms[3] = {NAN, NAN, NAN};
                 ++c_newton;
                 face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, fr, nfr, c_iter, c_pol,
                                  c_fovf);
@@ -442,31 +429,113 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         }
         ncand = 0;
     };
-    for (int pi = vr.patch_begin; pi < vr.patch_end; ++pi) {
-        const DevPatch &Pd = m.patches[pi];
-        ++c_box;
-        const bool hp = valid && slab(of, inv, Pd.box, Pd.box + 3);
-        if (__ballot(hp) == 0) continue;
-        for (int f = 0; f < 6; ++f) {
-            if ((Pd.face_skip >> f) & 1) continue;   // tested from the neighbouring block
-            c_box += hp;
-            const bool hf = hp && slab(of, inv, Pd.fbox[f], Pd.fbox[f] + 3);
-            if (__ballot(hf) == 0) continue;
-            for (int ti = Pd.tile_off[f]; ti < Pd.tile_off[f + 1]; ++ti) {
-                const FaceTile &T = m.tiles[ti];
-                c_box += hf;
-                const bool ht = hf && obb_hit(T, of, df);
-                if (__ballot(ht) == 0) continue;
-                for (int e = T.elem_begin; e < T.elem_end; ++e) {
-                    c_box += ht;
-                    if (ht && obb_hit(m.elems[e], of, df)) cand[ncand++] = (u32)e;
-                    if (__ballot(ncand == kCandCap) != 0) solve_candidates(pi);
+    if constexpr (MODE == 0 || MODE == 1) {
+        for (int pi = vr.patch_begin; pi < vr.patch_end; ++pi) {
+            const DevPatch &Pd = m.patches[pi];
+            ++c_box;
+            const bool hp = valid && slab(of, inv, Pd.box, Pd.box + 3);
+            if (__ballot(hp) == 0) continue;
+            const int nc0 = ncand;
+            for (int f = 0; f < 6; ++f) {
+                if ((Pd.face_skip >> f) & 1) continue;   // tested from the neighbouring block
+                c_box += hp;
+                const bool hf = hp && slab(of, inv, Pd.fbox[f], Pd.fbox[f] + 3);
+                if (__ballot(hf) == 0) continue;
+                for (int ti = Pd.tile_off[f]; ti < Pd.tile_off[f + 1]; ++ti) {
+                    const FaceTile &T = m.tiles[ti];
+                    c_box += hf;
+                    const bool ht = hf && obb_hit(T, of, df);
+                    if (__ballot(ht) == 0) continue;
+                    for (int e = T.elem_begin; e < T.elem_end; ++e) {
+                        c_box += ht;
+                        const bool he = ht && obb_hit(m.elems[e], of, df);
+                        if constexpr (MODE == 0) {
+                            if (he) cand[ncand++] = (u32)e;
+                            if (__ballot(ncand == kCandCap) != 0) solve_candidates();
+                        } else {
+                            if (he) {
+                                if (ncand < kCandCap) cand[ncand++] = (u32)e;
+                                else ++c_fovf;
+                            }
+                        }
+                    }
+                }
+            }
+            if constexpr (MODE == 1) {
+                // one network query per new candidate of this block: the ray's
+                // midpoint in the element's box; the block's queries of this wave
+                // are contiguous and recorded as one chunk
+                const u32 nb = (u32)(ncand - nc0);
+                if (__ballot(nb > 0) != 0) {
+                    const u32 incl = wave_incl_scan(nb, lane);
+                    const u32 total = __shfl(incl, 63);
+                    u32 qb = 0, cb = 0;
+                    if (lane == 63) {
+                        qb = atomicAdd(&qs->n_queries, total);
+                        cb = atomicAdd(&qs->n_chunks, 1u);
+                    }
+                    qb = __shfl(qb, 63);
+                    cb = __shfl(cb, 63);
+                    const bool fits = cb < mq.chunk_cap && qb + total <= mq.q_cap;
+                    if (fits && lane == 63) mq.chunks[cb] = make_uint4((u32)pi, qb, total, 0u);
+                    u32 q = qb + incl - nb;
+                    for (int k = nc0; k < ncand; ++k, ++q) {
+                        if (fits) {
+                            const FaceElem &E = m.elems[cand[k]];
+                            float t0, t1;
+                            obb_hit(E, of, df, t0, t1);
+                            const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
+                            mq.query[q] = make_float4(of[0] + tm * df[0], of[1] + tm * df[1],
+                                                      of[2] + tm * df[2], 0.f);
+                            ++c_mlp;
+                        }
+                        qidx[k] = fits ? q : 0xFFFFFFFFu;
+                    }
                 }
             }
         }
-        if (mlp && __ballot(ncand > 0) != 0) solve_candidates(pi);   // one block per flush
     }
-    solve_candidates(0);
+    if constexpr (MODE == 1) {
+        // the lane's candidates, contiguous per wave, for the solve pass
+        const u32 incl = wave_incl_scan((u32)ncand, lane);
+        const u32 total = __shfl(incl, 63);
+        u32 base = 0;
+        if (lane == 63 && total) base = atomicAdd(&qs->n_cands, total);
+        base = __shfl(base, 63);
+        u32 first = base + incl - (u32)ncand;
+        if (base + total > mq.c_cap) {
+            c_fovf += (u32)ncand;
+            ncand = 0;
+            first = 0;
+        }
+        for (int k = 0; k < ncand; ++k) mq.clist[first + k] = make_uint2(cand[k], qidx[k]);
+        mq.crange[g * 64u + (u32)lane] = make_uint2(first, (u32)ncand);
+        if (fp.collect) {
+            flush_counter(ctr, C_FRAG_OVF, c_fovf);
+            flush_counter(ctr, C_BOX_TESTS, c_box);
+            flush_counter(ctr, C_MLP_QUERIES, c_mlp);
+        }
+        return;
+    } else if constexpr (MODE == 2) {
+        // candidates and their network seeds from the first pass
+        const uint2 cr = mq.crange[g * 64u + (u32)lane];
+        for (int k = 0; __ballot(k < (int)cr.y) != 0; ++k) {
+            if (k < (int)cr.y) {
+                const uint2 c = mq.clist[cr.x + k];
+                const FaceElem E = m.elems[c.x];
+                float ms[3] = {NAN, NAN, NAN};
+                if (c.y != 0xFFFFFFFFu) {
+                    const float4 s = mq.seed[c.y];
+                    ms[0] = s.x; ms[1] = s.y; ms[2] = s.z;
+                }
+                ++c_newton;
+                face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, fr, nfr, c_iter, c_pol,
+                                 c_fovf);
+            }
+        }
+    } else {
+        solve_candidates();
+    }
     // 3. Algorithm "Blockwise depth-sorting": the nearest unused exit, then the
     //    nearest unused entry of the same block in front of it.
     unsigned char pin[kSegCap], pout[kSegCap];
@@ -602,6 +671,36 @@ struct RKF {
     static constexpr R e1 = R(1) / R(360), e3 = R(-128) / R(4275), e4 = R(-2197) / R(75240),
                        e5 = R(1) / R(50), e6 = R(2) / R(55);
 };
+
+// The network seeds of the recorded queries: one wave per chunk (one block, up
+// to 64 queries per call of the wave-wide BF16 MFMA inference), persistent.
+__global__ __launch_bounds__(64) void k_mlp_seeds(const uint16_t *wb, const float *norm, QueueState *qs,
+                                                  MlpQueries mq) {
+    __shared__ uint16_t sA[64 * 72];
+    __shared__ float sY[64 * 4];
+    __shared__ u32 s_chunk;
+    const int lane = threadIdx.x;
+    const u32 nch = min(qs->n_chunks, mq.chunk_cap);
+    for (;;) {
+        if (lane == 0) s_chunk = atomicAdd(&qs->next_chunk, 1u);
+        __syncthreads();
+        const u32 ci = s_chunk;
+        __syncthreads();
+        if (ci >= nch) break;
+        const uint4 ch = mq.chunks[ci];
+        for (u32 r0 = 0; r0 < ch.z; r0 += 64) {
+            const u32 row = r0 + (u32)lane;
+            const bool ok = row < ch.z;
+            float x[3] = {0.f, 0.f, 0.f}, p[3];
+            if (ok) {
+                const float4 q = mq.query[ch.y + row];
+                x[0] = q.x; x[1] = q.y; x[2] = q.z;
+            }
+            mlp_infer_wave(wb, norm, (int)ch.x, x, p, sA, sY);
+            if (ok) mq.seed[ch.y + row] = make_float4(p[0], p[1], p[2], 0.f);
+        }
+    }
+}
 
 // Segments are taken block by block.  The fragment kernel gave every segment its
 // rank among the segments of its block; one workgroup scans the block counts in
@@ -1024,24 +1123,29 @@ template <typename R>
 static hipError_t launch_fragments_t(const Model &m, const ViewRec *views, int n_views, uint32_t n_tiles,
                                      const LaunchCfg &lc, bool mlp, void *segs, uint32_t seg_cap,
                                      uint2 *seg_kr, uint32_t *pcount, QueueState *qs, uint2 *pixseg,
-                                     unsigned long long *ctr, hipStream_t st) {
-    if (mlp)
-        hipLaunchKernelGGL((k_fragments<R, true>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views,
-                           n_tiles, lc, (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, ctr);
-    else
-        hipLaunchKernelGGL((k_fragments<R, false>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views,
-                           n_tiles, lc, (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, ctr);
+                                     const MlpQueries &mq, unsigned long long *ctr, int n_cu,
+                                     hipStream_t st) {
+    if (mlp) {
+        hipLaunchKernelGGL((k_fragments<R, 1>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views, n_tiles,
+                           lc, (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, mq, ctr);
+        hipLaunchKernelGGL(k_mlp_seeds, dim3(n_cu * 8), dim3(64), 0, st, m.mlp_wb, m.mlp_norm, qs, mq);
+        hipLaunchKernelGGL((k_fragments<R, 2>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views, n_tiles,
+                           lc, (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, mq, ctr);
+    } else {
+        hipLaunchKernelGGL((k_fragments<R, 0>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views, n_tiles,
+                           lc, (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, mq, ctr);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_fragments(bool fp64, bool mlp, const Model &m, const ViewRec *views, int n_views,
                             uint32_t n_tiles, const LaunchCfg &lc, void *segs, uint32_t seg_cap,
                             uint2 *seg_kr, uint32_t *pcount, QueueState *qs, uint2 *pixseg,
-                            unsigned long long *ctr, hipStream_t st) {
+                            const MlpQueries &mq, unsigned long long *ctr, int n_cu, hipStream_t st) {
     return fp64 ? launch_fragments_t<double>(m, views, n_views, n_tiles, lc, mlp, segs, seg_cap, seg_kr,
-                                             pcount, qs, pixseg, ctr, st)
+                                             pcount, qs, pixseg, mq, ctr, n_cu, st)
                 : launch_fragments_t<float>(m, views, n_views, n_tiles, lc, mlp, segs, seg_cap, seg_kr,
-                                            pcount, qs, pixseg, ctr, st);
+                                            pcount, qs, pixseg, mq, ctr, n_cu, st);
 }
 
 hipError_t launch_block_sort(const QueueState *qs, uint32_t seg_cap, const uint2 *seg_kr,

@@ -114,7 +114,23 @@ enum Counter : int {
 // Bookkeeping written by the fragment kernel.
 struct QueueState {
     uint32_t seg_total;             // segments requested (may exceed the capacity)
+    uint32_t n_queries;             // MLP seeds: queries, chunks and candidates recorded
+    uint32_t n_chunks;
+    uint32_t n_cands;
+    uint32_t next_chunk;            // next chunk for the seed kernel
     uint32_t pad[3];
+};
+
+// Buffers of the two-pass fragment kernel with MLP seeds: queries (world points)
+// and their seeds, chunks (block, first query, count) of one block's queries from
+// one wave, each lane's candidates (element, query) and its range in that list.
+struct MlpQueries {
+    float4 *query;
+    float4 *seed;
+    uint4 *chunks;
+    uint2 *clist;
+    uint2 *crange;            // per lane of a fragment tile (tile * 64 + lane)
+    uint32_t q_cap, chunk_cap, c_cap;
 };
 
 // What the integrator of one degree class needs to take its segments block by
