@@ -997,7 +997,8 @@ static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
 }
 
 // Buffers of the MLP-seeded fragment passes: 8 candidates per pixel on average
-// (a lane keeps at most 64), 16 chunks per tile.
+// (a lane keeps at most 64), 64 chunks (blocks with candidates) per tile.  Past
+// these capacities candidates keep the box seed.
 static ivr_status ensure_mlp_queries(ivr_ctx *c, size_t pixels, size_t tiles) {
     const size_t cap = std::max<size_t>(pixels * 8, 1024);
     if (tiles <= c->mq_tiles && cap <= c->mq.q_cap) return IVR_OK;
@@ -1008,7 +1009,7 @@ static ivr_status ensure_mlp_queries(ivr_ctx *c, size_t pixels, size_t tiles) {
         return fail(c, IVR_EOVERFLOW, "batch too large for the MLP seed buffers");
     if (hipMalloc((void **)&c->mq.query, sizeof(float4) * cap) != hipSuccess ||
         hipMalloc((void **)&c->mq.seed, sizeof(float4) * cap) != hipSuccess ||
-        hipMalloc((void **)&c->mq.chunks, sizeof(uint4) * tiles * 16) != hipSuccess ||
+        hipMalloc((void **)&c->mq.chunks, sizeof(uint4) * tiles * 64) != hipSuccess ||
         hipMalloc((void **)&c->mq.clist, sizeof(uint2) * cap) != hipSuccess ||
         hipMalloc((void **)&c->mq.crange, sizeof(uint2) * tiles * 64) != hipSuccess) {
         free_mlp_queries(c);
@@ -1016,7 +1017,7 @@ static ivr_status ensure_mlp_queries(ivr_ctx *c, size_t pixels, size_t tiles) {
     }
     c->mq.q_cap = (uint32_t)cap;
     c->mq.c_cap = (uint32_t)cap;
-    c->mq.chunk_cap = (uint32_t)(tiles * 16);
+    c->mq.chunk_cap = (uint32_t)(tiles * 64);
     c->mq_tiles = tiles;
     return IVR_OK;
 }
