@@ -64,7 +64,7 @@ struct ivr_ctx {
     uint32_t *d_order = nullptr;         // segment indices sorted by block
     QueueState *d_qs = nullptr;
     // two-pass fragment kernel with MLP seeds (grow-only)
-    MlpQueries mq = {nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0};
+    CandLists mq = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0};
     size_t mq_tiles = 0;
     // blocks grouped by degree class (the integrators take their segments block by block)
     uint32_t *d_pperm = nullptr, *d_pcount = nullptr, *d_pbase = nullptr, *d_pcur = nullptr;
@@ -535,15 +535,15 @@ static void drop_graphs(ivr_ctx *c) {
     ++c->generation;
 }
 
-static void free_mlp_queries(ivr_ctx *c) {
-    dfree(c->mq.query); dfree(c->mq.seed); dfree(c->mq.chunks); dfree(c->mq.clist); dfree(c->mq.crange);
+static void free_cand_lists(ivr_ctx *c) {
+    dfree(c->mq.query); dfree(c->mq.seed); dfree(c->mq.chunks); dfree(c->mq.clist); dfree(c->mq.plist); dfree(c->mq.crange);
     c->mq.q_cap = c->mq.chunk_cap = c->mq.c_cap = 0;
     c->mq_tiles = 0;
 }
 
 static void free_frame(ivr_ctx *c) {
     drop_graphs(c);
-    free_mlp_queries(c);
+    free_cand_lists(c);
     dfree(c->d_segs); dfree(c->d_results); dfree(c->d_pixseg); dfree(c->d_seg_kr); dfree(c->d_order);
     c->pix_cap = c->seg_cap = c->seg_bytes_cap = 0;
 }
@@ -742,6 +742,8 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
         D.elem_off[6] = (int)elems.size();
         D.tile_off[6] = (int)tiles.size();
     }
+    if (elems.size() > kCandElemMask)
+        return fail(c, IVR_EOVERFLOW, "more than 2^26 face elements");
     // Faces shared by two blocks of a model: the same parametric surface S(a, b)
     // (as at conforming interfaces, also between blocks of different degree or
     // knots): test them from the first block only and emit the second block's
@@ -996,24 +998,26 @@ static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
     return IVR_OK;
 }
 
-// Buffers of the MLP-seeded fragment passes: 8 candidates per pixel on average
-// (a lane keeps at most 64), 64 chunks (blocks with candidates) per tile.  Past
-// these capacities candidates keep the box seed.
-static ivr_status ensure_mlp_queries(ivr_ctx *c, size_t pixels, size_t tiles) {
+// Buffers of the two-pass fragment kernel: 8 candidates per pixel on average (a
+// lane keeps at most 64), 64 chunks (blocks with candidates) per tile.  Past the
+// chunk and query capacities candidates keep the box seed; rays whose candidates
+// do not fit are traversed again by the solve pass.
+static ivr_status ensure_cand_lists(ivr_ctx *c, size_t pixels, size_t tiles) {
     const size_t cap = std::max<size_t>(pixels * 8, 1024);
     if (tiles <= c->mq_tiles && cap <= c->mq.q_cap) return IVR_OK;
     IVR_HIP(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
-    free_mlp_queries(c);
+    free_cand_lists(c);
     if (cap > 0xFFFFFFFEull || tiles * 64 > 0xFFFFFFFFull)
-        return fail(c, IVR_EOVERFLOW, "batch too large for the MLP seed buffers");
+        return fail(c, IVR_EOVERFLOW, "batch too large for the candidate buffers");
     if (hipMalloc((void **)&c->mq.query, sizeof(float4) * cap) != hipSuccess ||
         hipMalloc((void **)&c->mq.seed, sizeof(float4) * cap) != hipSuccess ||
         hipMalloc((void **)&c->mq.chunks, sizeof(uint4) * tiles * 64) != hipSuccess ||
         hipMalloc((void **)&c->mq.clist, sizeof(uint2) * cap) != hipSuccess ||
+        hipMalloc((void **)&c->mq.plist, sizeof(uint32_t) * cap) != hipSuccess ||
         hipMalloc((void **)&c->mq.crange, sizeof(uint2) * tiles * 64) != hipSuccess) {
-        free_mlp_queries(c);
-        return fail(c, IVR_ENOMEM, "MLP seed buffer allocation failed");
+        free_cand_lists(c);
+        return fail(c, IVR_ENOMEM, "candidate buffer allocation failed");
     }
     c->mq.q_cap = (uint32_t)cap;
     c->mq.c_cap = (uint32_t)cap;
@@ -1111,7 +1115,7 @@ static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr
     b.n_pixels = (uint32_t)pixels;
     st = ensure_frame(c, pixels, b.fp64);
     if (st != IVR_OK) return st;
-    return b.mlp ? ensure_mlp_queries(c, pixels, tiles) : IVR_OK;
+    return ensure_cand_lists(c, pixels, tiles);
 }
 
 // The launches of one batch: clear, fragments, one integrator per degree class, merge.

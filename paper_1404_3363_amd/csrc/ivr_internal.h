@@ -10,7 +10,7 @@ namespace ivr {
 hipError_t launch_fragments(bool fp64, bool mlp, const Model &m, const ViewRec *views, int n_views,
                             uint32_t n_tiles, const LaunchCfg &lc, void *segs, uint32_t seg_cap,
                             uint2 *seg_kr, uint32_t *pcount, QueueState *qs, uint2 *pixseg,
-                            const MlpQueries &mq, unsigned long long *ctr, int n_cu, hipStream_t st);
+                            const CandLists &mq, unsigned long long *ctr, int n_cu, hipStream_t st);
 
 hipError_t launch_block_sort(const QueueState *qs, uint32_t seg_cap, const uint2 *seg_kr,
                              const uint32_t *pperm, int nperm, const uint32_t *pcount, uint32_t *pbase,

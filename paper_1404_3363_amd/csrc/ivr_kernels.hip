@@ -31,6 +31,8 @@ namespace ivr {
 using u32 = uint32_t;
 using u64 = unsigned long long;
 
+constexpr int kFlat = 256;   // candidates solved per pass of the flattened solve
+
 __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
@@ -93,6 +95,15 @@ struct Frag {
         p[da] = a;
         p[db] = b;
     }
+};
+
+// A root of one candidate, handed from the lane that solved it to the lane that
+// owns the ray: the crossing (t, a, b, info as in Frag; info ~0 when there is
+// none) and the info of the shared face's crossing at the same root (or ~0).
+template <typename R>
+struct RootRec {
+    R t, a, b;
+    uint32_t info, tinfo;
 };
 
 // Ray (t >= 0) against an oriented box; [tmin, tmax] is the ray's interval inside.
@@ -203,11 +214,13 @@ __device__ __forceinline__ bool face_newton(const PatchView<RN> &pv, const Array
 // If Newton does not converge from it: the element centre and its four quarter
 // points.  A root that converges anywhere on the face and is new for
 // this ray is refined in FP64 and inserted into the depth-sorted fragment list.
-template <int P, bool RAT, typename RN>
+// With OUT the root goes to *out instead of the ray's own fragment list (fr,
+// nfr then only serve the early duplicate test; nfr may be 0).
+template <int P, bool RAT, typename RN, bool OUT>
 __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E, const double (&od)[3],
                           const double (&dd)[3], const float (&of)[3], const float (&df)[3],
                           const FrameParams &fp, const float (&mseed)[3], Frag<RN> *fr, int &nfr,
-                          u32 &n_iter, u32 &n_polish, u32 &n_ovf) {
+                          RootRec<RN> *out, u32 &n_iter, u32 &n_polish, u32 &n_ovf) {
     const int face = E.face;
     const PatchView<RN> pv = view_of<RN>(Pd);
     const Arrays<RN> ar = arrays_of(m, RN(0));
@@ -299,29 +312,36 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
     if (!(A >= -mg64 && A <= 1.0 + mg64 && B >= -mg64 && B <= 1.0 + mg64 && T > 0.0)) return;
     ent = facing(face, Pd.orient, Sa2, Sb2, dd, grazing);
     if (grazing) return;
-    insert_frag(fr, nfr, fp, patch, face, ent, A, B, T, n_ovf);
     // the same root is the crossing of the block on the other side of a shared face
     const int tw = Pd.twin[face];
-    if (tw >= 0) {
-        const int tp = tw >> 3, tf = tw & 7;
-        const int tent = facing(tf, m.patches[tp].orient, Sa2, Sb2, dd, grazing);
-        insert_frag(fr, nfr, fp, tp, tf, tent, A, B, T, n_ovf);
+    int tent = 0;
+    if (tw >= 0) tent = facing(tw & 7, m.patches[tw >> 3].orient, Sa2, Sb2, dd, grazing);
+    if constexpr (OUT) {
+        out->t = RN(T);
+        out->a = RN(clamp01(A));
+        out->b = RN(clamp01(B));
+        out->info = ((uint32_t)patch << 4) | ((uint32_t)face << 1) | (uint32_t)(ent & 1);
+        out->tinfo = tw >= 0 ? (((uint32_t)(tw >> 3) << 4) | ((uint32_t)(tw & 7) << 1) | (uint32_t)(tent & 1))
+                             : 0xFFFFFFFFu;
+    } else {
+        insert_frag(fr, nfr, fp, patch, face, ent, A, B, T, n_ovf);
+        if (tw >= 0) insert_frag(fr, nfr, fp, tw >> 3, tw & 7, tent, A, B, T, n_ovf);
     }
 }
 
-template <typename R>
+template <typename R, bool OUT>
 __device__ __forceinline__ void face_root_any(const Model &m, const DevPatch &Pd, const FaceElem &E,
                                               const double (&od)[3], const double (&dd)[3],
                                               const float (&of)[3], const float (&df)[3],
                                               const FrameParams &fp, const float (&ms)[3], Frag<R> *fr,
-                                              int &nfr, u32 &ni, u32 &np, u32 &no) {
+                                              int &nfr, RootRec<R> *out, u32 &ni, u32 &np, u32 &no) {
     switch (Pd.deg * 2 + Pd.rational) {
-    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
-    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
-    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
-    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
-    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
-    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, ni, np, no); break;
+    case 2: face_root<1, false, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
+    case 3: face_root<1, true, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
+    case 4: face_root<2, false, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
+    case 5: face_root<2, true, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
+    case 6: face_root<3, false, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
+    default: face_root<3, true, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
     }
 }
 
@@ -361,15 +381,16 @@ __device__ __forceinline__ int view_of_tile(const ViewRec *views, int n_views, u
     return __builtin_amdgcn_readfirstlane(lo);
 }
 
-// MODE 0: the whole fragment pass (box or plain seeds).  With MLP seeds it runs
-// in two passes around k_mlp_seeds: MODE 1 traverses and records the candidates
-// with one network query each (grouped per block and wave), MODE 2 reads the
-// candidates and their seeds back and does the rest.
+// The fragment pass in two launches.  MODE 1 traverses the block, face, tile
+// and element boxes and records each wave's candidates (elements whose box the
+// ray hits), with MLP seeds one network query each (grouped per block and wave,
+// evaluated by k_mlp_seeds in between).  MODE 2 solves the candidates, pairs the
+// roots into segments and writes them.
 template <typename R, int MODE>
 __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views, int n_views,
                                                   u32 n_tiles, LaunchCfg lc, Seg<R> *segs, u32 seg_cap,
                                                   uint2 *seg_kr, u32 *pcount, QueueState *qs,
-                                                  uint2 *pixseg, MlpQueries mq, u64 *ctr) {
+                                                  uint2 *pixseg, CandLists mq, u64 *ctr) {
     const int lane = threadIdx.x;
     // Consecutive blocks are dealt round-robin to the 8 XCDs.  With xcd_chunk = C
     // > 0, XCD x's j-th block takes tile j mod C of chunk (j / C) * 8 + x: runs of C
@@ -409,31 +430,37 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     u32 c_anom = 0, c_fovf = 0, c_sovf = 0, c_box = 0, c_newton = 0, c_iter = 0, c_pol = 0, c_mlp = 0;
 
     // 1. face elements whose oriented box the ray hits (block and face boxes
-    //    first) become Newton seeds; 2. the seeds are solved with all lanes in
-    //    step, whenever a lane's list is full and at the end.
+    //    first) become Newton seeds; 2. the seeds are solved (a wave's 64 at a
+    //    time whatever their rays, in the second launch).
     u32 cand[kCandCap];
     u32 qidx[MODE == 1 ? kCandCap : 1];
+    u32 cpos[MODE == 1 ? kCandCap : 1];   // position in the wave's block-major list
     int ncand = 0;
     Frag<R> fr[MODE == 1 ? 1 : kFragCap];
     int nfr = 0;
-    // (always inlined: a call would see the kernel's pointers as generic and load through flat)
+    // The lane's listed candidates, all lanes in step (only for rays whose
+    // candidates the first launch could not record).  Always inlined: a call
+    // would see the kernel's pointers as generic and load through flat.
     auto solve_candidates = [&]() __attribute__((always_inline)) {
         for (int k = 0; __ballot(k < ncand) != 0; ++k) {
             if (k < ncand) {
                 const FaceElem E = m.elems[cand[k]];
                 const float ms[3] = {NAN, NAN, NAN};
                 ++c_newton;
-                face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, fr, nfr, c_iter, c_pol,
-                                 c_fovf);
+                face_root_any<R, false>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, fr, nfr, nullptr,
+                                        c_iter, c_pol, c_fovf);
             }
         }
         ncand = 0;
     };
-    if constexpr (MODE == 0 || MODE == 1) {
+    // The traversal: on_hit(e, he) for every face element e of a tile the wave
+    // tests (he: the lane's ray hits its box), after_block(pi, nc0) after each
+    // block the wave's rays may hit, with nc0 the lane's candidate count before it.
+    auto traverse = [&](bool act, auto &&on_hit, auto &&after_block) __attribute__((always_inline)) {
         for (int pi = vr.patch_begin; pi < vr.patch_end; ++pi) {
             const DevPatch &Pd = m.patches[pi];
             ++c_box;
-            const bool hp = valid && slab(of, inv, Pd.box, Pd.box + 3);
+            const bool hp = act && slab(of, inv, Pd.box, Pd.box + 3);
             if (__ballot(hp) == 0) continue;
             const int nc0 = ncand;
             for (int f = 0; f < 6; ++f) {
@@ -448,93 +475,154 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                     if (__ballot(ht) == 0) continue;
                     for (int e = T.elem_begin; e < T.elem_end; ++e) {
                         c_box += ht;
-                        const bool he = ht && obb_hit(m.elems[e], of, df);
-                        if constexpr (MODE == 0) {
-                            if (he) cand[ncand++] = (u32)e;
-                            if (__ballot(ncand == kCandCap) != 0) solve_candidates();
-                        } else {
-                            if (he) {
-                                if (ncand < kCandCap) cand[ncand++] = (u32)e;
-                                else ++c_fovf;
-                            }
-                        }
+                        on_hit((u32)e, ht && obb_hit(m.elems[e], of, df));
                     }
                 }
             }
-            if constexpr (MODE == 1) {
-                // one network query per new candidate of this block: the ray's
-                // midpoint in the element's box; the block's queries of this wave
-                // are contiguous and recorded as one chunk
-                const u32 nb = (u32)(ncand - nc0);
-                if (__ballot(nb > 0) != 0) {
-                    const u32 incl = wave_incl_scan(nb, lane);
-                    const u32 total = __shfl(incl, 63);
-                    u32 qb = 0, cb = 0;
-                    if (lane == 63) {
-                        qb = atomicAdd(&qs->n_queries, total);
-                        cb = atomicAdd(&qs->n_chunks, 1u);
-                    }
-                    qb = __shfl(qb, 63);
-                    cb = __shfl(cb, 63);
-                    const bool fits = cb < mq.chunk_cap && qb + total <= mq.q_cap;
-                    if (fits && lane == 63) mq.chunks[cb] = make_uint4((u32)pi, qb, total, 0u);
-                    u32 q = qb + incl - nb;
-                    for (int k = nc0; k < ncand; ++k, ++q) {
-                        if (fits) {
-                            const FaceElem &E = m.elems[cand[k]];
-                            float t0, t1;
-                            obb_hit(E, of, df, t0, t1);
-                            const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
-                            mq.query[q] = make_float4(of[0] + tm * df[0], of[1] + tm * df[1],
-                                                      of[2] + tm * df[2], 0.f);
-                            ++c_mlp;
-                        }
-                        qidx[k] = fits ? q : 0xFFFFFFFFu;
-                    }
-                }
-            }
+            after_block(pi, nc0);
         }
-    }
+    };
+    auto no_block = [&](int, int) __attribute__((always_inline)) {};
+    bool c_more = false;   // the lane found more candidates than its list holds
     if constexpr (MODE == 1) {
-        // the lane's candidates, contiguous per wave, for the solve pass
-        const u32 incl = wave_incl_scan((u32)ncand, lane);
-        const u32 total = __shfl(incl, 63);
+        auto hit = [&](u32 e, bool he) __attribute__((always_inline)) {
+            if (he) {
+                if (ncand < kCandCap) cand[ncand++] = e;
+                else c_more = true;
+            }
+        };
+        // The wave's list holds the candidates block after block (lane after lane
+        // within a block): a solve round then meets one or two blocks, of one
+        // degree, instead of the blocks of a few rays.
+        u32 wrun = 0;
+        auto block = [&](int pi, int nc0) __attribute__((always_inline)) {
+            const u32 nb = (u32)(ncand - nc0);
+            if (__ballot(nb > 0) == 0) return;
+            const u32 incl = wave_incl_scan(nb, lane);
+            const u32 total = __shfl(incl, 63);
+            for (int k = nc0; k < ncand; ++k) cpos[k] = wrun + incl - nb + (u32)(k - nc0);
+            wrun += total;
+            if (fp.seed_mode != IVR_SEED_MLP) return;
+            // one network query per new candidate of this block: the ray's
+            // midpoint in the element's box; the block's queries of this wave
+            // are contiguous and recorded as one chunk
+            u32 qb = 0, cb = 0;
+            if (lane == 63) {
+                qb = atomicAdd(&qs->n_queries, total);
+                cb = atomicAdd(&qs->n_chunks, 1u);
+            }
+            qb = __shfl(qb, 63);
+            cb = __shfl(cb, 63);
+            const bool fits = cb < mq.chunk_cap && qb + total <= mq.q_cap;
+            if (fits && lane == 63) mq.chunks[cb] = make_uint4((u32)pi, qb, total, 0u);
+            u32 q = qb + incl - nb;
+            for (int k = nc0; k < ncand; ++k, ++q) {
+                if (fits) {
+                    const FaceElem &E = m.elems[cand[k]];
+                    float t0, t1;
+                    obb_hit(E, of, df, t0, t1);
+                    const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
+                    mq.query[q] = make_float4(of[0] + tm * df[0], of[1] + tm * df[1], of[2] + tm * df[2], 0.f);
+                    ++c_mlp;
+                }
+                qidx[k] = fits ? q : 0xFFFFFFFFu;
+            }
+        };
+        traverse(valid, hit, block);
+        // the candidates for the solve pass
         u32 base = 0;
-        if (lane == 63 && total) base = atomicAdd(&qs->n_cands, total);
-        base = __shfl(base, 63);
-        u32 first = base + incl - (u32)ncand;
-        if (base + total > mq.c_cap) {
-            c_fovf += (u32)ncand;
+        if (lane == 0 && wrun) base = atomicAdd(&qs->n_cands, wrun);
+        base = __shfl(base, 0);
+        if (base + wrun > mq.c_cap) {   // the list is full: the solve pass traverses again
+            c_more = ncand > 0 || c_more;
             ncand = 0;
-            first = 0;
         }
-        for (int k = 0; k < ncand; ++k) mq.clist[first + k] = make_uint2(cand[k], qidx[k]);
-        mq.crange[g * 64u + (u32)lane] = make_uint2(first, (u32)ncand);
+        const u32 excl = wave_incl_scan((u32)ncand, lane) - (u32)ncand;
+        const bool mlp = fp.seed_mode == IVR_SEED_MLP;
+        for (int k = 0; k < ncand; ++k) {
+            mq.clist[base + cpos[k]] = make_uint2(cand[k] | ((u32)lane << kCandLaneShift), mlp ? qidx[k] : 0xFFFFFFFFu);
+            mq.plist[base + excl + (u32)k] = cpos[k];
+        }
+        // the wave's base and the lane's count; the top bit asks the solve pass for the rest
+        mq.crange[g * 64u + (u32)lane] = make_uint2(base, (u32)ncand | (c_more ? 0x80000000u : 0u));
         if (fp.collect) {
-            flush_counter(ctr, C_FRAG_OVF, c_fovf);
             flush_counter(ctr, C_BOX_TESTS, c_box);
             flush_counter(ctr, C_MLP_QUERIES, c_mlp);
         }
         return;
-    } else if constexpr (MODE == 2) {
-        // candidates and their network seeds from the first pass
+    }
+    if constexpr (MODE == 2) {
+        // The wave's candidates (block after block from the first pass) are solved
+        // 64 at a time whatever lane owns them; the roots go through LDS back to
+        // the owning lanes, which find them by their positions in the list and
+        // keep their fragment lists.
+        __shared__ double s_dd[64 * 3];
+        __shared__ RootRec<R> s_res[kFlat];
         const uint2 cr = mq.crange[g * 64u + (u32)lane];
-        for (int k = 0; __ballot(k < (int)cr.y) != 0; ++k) {
-            if (k < (int)cr.y) {
-                const uint2 c = mq.clist[cr.x + k];
-                const FaceElem E = m.elems[c.x];
-                float ms[3] = {NAN, NAN, NAN};
-                if (c.y != 0xFFFFFFFFu) {
-                    const float4 s = mq.seed[c.y];
-                    ms[0] = s.x; ms[1] = s.y; ms[2] = s.z;
+        const u32 nrec = cr.y & 0x7FFFFFFFu;
+        const u32 incl = wave_incl_scan(nrec, lane);
+        const u32 total = __shfl(incl, 63);
+        const u32 wbase = __builtin_amdgcn_readfirstlane(cr.x);
+        const u32 *own = mq.plist + wbase + (incl - nrec);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s_dd[lane * 3 + q] = dd[q];
+        __syncthreads();
+        u32 kk = 0, mypos = nrec ? own[0] : 0xFFFFFFFFu;
+        for (u32 b0 = 0; b0 < total; b0 += kFlat) {
+            const u32 nb = min((u32)kFlat, total - b0);
+            for (u32 r = 0; r < nb; r += 64) {
+                const u32 j = r + (u32)lane;
+                if (j < nb) {
+                    const uint2 c = mq.clist[wbase + b0 + j];
+                    const u32 ol = c.x >> kCandLaneShift;
+                    const double odd[3] = {s_dd[ol * 3], s_dd[ol * 3 + 1], s_dd[ol * 3 + 2]};
+                    const float odf[3] = {float(odd[0]), float(odd[1]), float(odd[2])};
+                    const FaceElem E = m.elems[c.x & kCandElemMask];
+                    float ms[3] = {NAN, NAN, NAN};
+                    if (c.y != 0xFFFFFFFFu) {
+                        const float4 s = mq.seed[c.y];
+                        ms[0] = s.x; ms[1] = s.y; ms[2] = s.z;
+                    }
+                    RootRec<R> out;
+                    out.info = out.tinfo = 0xFFFFFFFFu;
+                    int nz = 0;
+                    ++c_newton;
+                    face_root_any<R, true>(m, m.patches[E.patch], E, od, odd, of, odf, fp, ms, fr, nz, &out,
+                                           c_iter, c_pol, c_fovf);
+                    s_res[j] = out;
                 }
-                ++c_newton;
-                face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, fr, nfr, c_iter, c_pol,
-                                 c_fovf);
             }
+            __syncthreads();
+            // the lane's own roots of this pass, in the order of its candidates
+            while (mypos < b0 + nb) {
+                const RootRec<R> rr = s_res[mypos - b0];
+                // a root that an earlier candidate of the ray already gave is dropped
+                // (the test the fused pass makes before refining)
+                if (rr.info != 0xFFFFFFFFu &&
+                    !is_dup(fr, nfr, (int)(rr.info >> 4), (int)(rr.info & 1u), double(rr.t), 2e-5 * fp.scaled)) {
+                    insert_frag(fr, nfr, fp, (int)(rr.info >> 4), (int)((rr.info >> 1) & 7u), (int)(rr.info & 1u),
+                                double(rr.a), double(rr.b), double(rr.t), c_fovf);
+                    if (rr.tinfo != 0xFFFFFFFFu)
+                        insert_frag(fr, nfr, fp, (int)(rr.tinfo >> 4), (int)((rr.tinfo >> 1) & 7u),
+                                    (int)(rr.tinfo & 1u), double(rr.a), double(rr.b), double(rr.t), c_fovf);
+                }
+                mypos = ++kk < nrec ? own[kk] : 0xFFFFFFFFu;
+            }
+            __syncthreads();
         }
-    } else {
-        solve_candidates();
+        // Rays with more candidates than were recorded traverse again and solve
+        // the rest (box or element-centre seeds) with all lanes in step,
+        // whenever a lane's list is full and at the end.
+        const bool more = (cr.y >> 31) != 0;
+        if (__ballot(more) != 0) {
+            u32 seen = 0;
+            auto hit_rest = [&](u32 e, bool he) __attribute__((always_inline)) {
+                if (he && seen++ >= nrec) cand[ncand++] = e;
+                if (__ballot(ncand == kCandCap) != 0) solve_candidates();
+            };
+            traverse(valid && more, hit_rest, no_block);
+            solve_candidates();
+        }
     }
     // 3. Algorithm "Blockwise depth-sorting": the nearest unused exit, then the
     //    nearest unused entry of the same block in front of it.
@@ -675,7 +763,7 @@ struct RKF {
 // The network seeds of the recorded queries: one wave per chunk (one block, up
 // to 64 queries per call of the wave-wide BF16 MFMA inference), persistent.
 __global__ __launch_bounds__(64) void k_mlp_seeds(const uint16_t *wb, const float *norm, QueueState *qs,
-                                                  MlpQueries mq) {
+                                                  CandLists mq) {
     __shared__ uint16_t sA[64 * 72];
     __shared__ float sY[64 * 4];
     __shared__ u32 s_chunk;
@@ -1123,25 +1211,20 @@ template <typename R>
 static hipError_t launch_fragments_t(const Model &m, const ViewRec *views, int n_views, uint32_t n_tiles,
                                      const LaunchCfg &lc, bool mlp, void *segs, uint32_t seg_cap,
                                      uint2 *seg_kr, uint32_t *pcount, QueueState *qs, uint2 *pixseg,
-                                     const MlpQueries &mq, unsigned long long *ctr, int n_cu,
+                                     const CandLists &mq, unsigned long long *ctr, int n_cu,
                                      hipStream_t st) {
-    if (mlp) {
-        hipLaunchKernelGGL((k_fragments<R, 1>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views, n_tiles,
-                           lc, (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, mq, ctr);
-        hipLaunchKernelGGL(k_mlp_seeds, dim3(n_cu * 8), dim3(64), 0, st, m.mlp_wb, m.mlp_norm, qs, mq);
-        hipLaunchKernelGGL((k_fragments<R, 2>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views, n_tiles,
-                           lc, (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, mq, ctr);
-    } else {
-        hipLaunchKernelGGL((k_fragments<R, 0>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views, n_tiles,
-                           lc, (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, mq, ctr);
-    }
+    hipLaunchKernelGGL((k_fragments<R, 1>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views, n_tiles, lc,
+                       (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, mq, ctr);
+    if (mlp) hipLaunchKernelGGL(k_mlp_seeds, dim3(n_cu * 8), dim3(64), 0, st, m.mlp_wb, m.mlp_norm, qs, mq);
+    hipLaunchKernelGGL((k_fragments<R, 2>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views, n_tiles, lc,
+                       (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, mq, ctr);
     return hipGetLastError();
 }
 
 hipError_t launch_fragments(bool fp64, bool mlp, const Model &m, const ViewRec *views, int n_views,
                             uint32_t n_tiles, const LaunchCfg &lc, void *segs, uint32_t seg_cap,
                             uint2 *seg_kr, uint32_t *pcount, QueueState *qs, uint2 *pixseg,
-                            const MlpQueries &mq, unsigned long long *ctr, int n_cu, hipStream_t st) {
+                            const CandLists &mq, unsigned long long *ctr, int n_cu, hipStream_t st) {
     return fp64 ? launch_fragments_t<double>(m, views, n_views, n_tiles, lc, mlp, segs, seg_cap, seg_kr,
                                              pcount, qs, pixseg, mq, ctr, n_cu, st)
                 : launch_fragments_t<float>(m, views, n_views, n_tiles, lc, mlp, segs, seg_cap, seg_kr,

@@ -121,14 +121,19 @@ struct QueueState {
     uint32_t pad[3];
 };
 
-// Buffers of the two-pass fragment kernel with MLP seeds: queries (world points)
-// and their seeds, chunks (block, first query, count) of one block's queries from
-// one wave, each lane's candidates (element, query) and its range in that list.
-struct MlpQueries {
+// Buffers of the two-pass fragment kernel: network queries (world points) and
+// their seeds with MLP seeds, chunks (block, first query, count) of one block's
+// queries from one wave; every wave's candidates block after block (element |
+// owning lane << kCandLaneShift, query), per lane the positions of its own
+// candidates in that list, and per lane the wave's base and its count.
+constexpr int kCandLaneShift = 26;
+constexpr uint32_t kCandElemMask = (1u << kCandLaneShift) - 1;
+struct CandLists {
     float4 *query;
     float4 *seed;
     uint4 *chunks;
     uint2 *clist;
+    uint32_t *plist;
     uint2 *crange;            // per lane of a fragment tile (tile * 64 + lane)
     uint32_t q_cap, chunk_cap, c_cap;
 };
