@@ -31,7 +31,8 @@ namespace ivr {
 using u32 = uint32_t;
 using u64 = unsigned long long;
 
-constexpr int kFlat = 256;   // candidates solved per pass of the flattened solve
+constexpr int kFlat = 256;    // candidates solved per pass of the flattened solve
+constexpr int kFragLds = 16;  // crossings per ray kept in LDS (the rest in scratch)
 
 __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -85,17 +86,18 @@ struct Frag {
     // face and facing packed as block << 4 | face << 1 | entering (16 B in FP32)
     R t, a, b;
     uint32_t info;
-    __device__ int patch() const { return (int)(info >> 4); }
-    __device__ int entering() const { return (int)(info & 1u); }
-    __device__ void param(R (&p)[3]) const {
-        const int face = (int)((info >> 1) & 7u);
-        int dn, da, db;
-        face_dirs(face, dn, da, db);
-        p[dn] = (face & 1) ? R(1) : R(0);
-        p[da] = a;
-        p[db] = b;
-    }
 };
+
+// The parameter point of a crossing: face parameters (a, b) on the face of info.
+template <typename R>
+__device__ __forceinline__ void face_point(uint32_t info, R a, R b, R (&p)[3]) {
+    const int face = (int)((info >> 1) & 7u);
+    int dn, da, db;
+    face_dirs(face, dn, da, db);
+    p[dn] = (face & 1) ? R(1) : R(0);
+    p[da] = a;
+    p[db] = b;
+}
 
 // A root of one candidate, handed from the lane that solved it to the lane that
 // owns the ray: the crossing (t, a, b, info as in Frag; info ~0 when there is
@@ -131,15 +133,6 @@ __device__ __forceinline__ bool obb_hit(const Box3 &E, const float (&o)[3], cons
     return obb_hit(E, o, d, t0, t1);
 }
 
-template <typename R>
-__device__ __forceinline__ bool is_dup(const Frag<R> *fr, int nfr, int patch, int entering, double t,
-                                       double tol) {
-    bool dup = false;
-    for (int q = 0; q < nfr; ++q)
-        dup |= fr[q].patch() == patch && fr[q].entering() == entering && fabs(double(fr[q].t) - t) <= tol;
-    return dup;
-}
-
 // Front facing: the sign of (J^-1 d) along the face's inward normal.  By
 // Cramer's rule it equals the sign of d . (S_a x S_b) times the face's side,
 // the orientation of (a, b, n) and the block's orientation (sign of det J).
@@ -152,31 +145,6 @@ __device__ __forceinline__ int facing(int face, float orient, const R (&Sa)[3], 
     grazing = !(fabs(g) > R(1e-10) * sqrt(dot3(nrm, nrm)));
     const R sigma = ((face >> 1) == 1) ? R(-1) : R(1), side = (face & 1) ? R(-1) : R(1);
     return (side * sigma * g * R(orient)) > R(0);
-}
-
-// Adds a crossing of `patch` through `face` at face parameters (A, B), ray
-// parameter T, to the depth-sorted list unless it duplicates one already there.
-template <typename RN>
-__device__ __forceinline__ void insert_frag(Frag<RN> *fr, int &nfr, const FrameParams &fp, int patch,
-                                            int face, int ent, double A, double B, double T, u32 &n_ovf) {
-    if (is_dup(fr, nfr, patch, ent, T, 1e-6 * fp.scaled)) return;
-    if (nfr >= fp.max_frag) {
-        ++n_ovf;
-        return;
-    }
-    Frag<RN> f;
-    f.t = RN(T);
-    f.a = RN(clamp01(A));
-    f.b = RN(clamp01(B));
-    f.info = ((uint32_t)patch << 4) | ((uint32_t)face << 1) | (uint32_t)(ent & 1);
-    // depth order; at equal depth (the FP32 depths of a crossing through an edge)
-    // an entry goes before an exit, so the pairing finds the entry in front
-    int q = nfr++;
-    while (q > 0 && (fr[q - 1].t > f.t || (fr[q - 1].t == f.t && ent && !fr[q - 1].entering()))) {
-        fr[q] = fr[q - 1];
-        --q;
-    }
-    fr[q] = f;
 }
 
 // Newton on S_f(a,b) - (o + t d) = 0 (Eqs. (F), (newtonsmethod) restricted to
@@ -214,13 +182,11 @@ __device__ __forceinline__ bool face_newton(const PatchView<RN> &pv, const Array
 // If Newton does not converge from it: the element centre and its four quarter
 // points.  A root that converges anywhere on the face and is new for
 // this ray is refined in FP64 and inserted into the depth-sorted fragment list.
-// With OUT the root goes to *out instead of the ray's own fragment list (fr,
-// nfr then only serve the early duplicate test; nfr may be 0).
-template <int P, bool RAT, typename RN, bool OUT>
+template <int P, bool RAT, typename RN>
 __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E, const double (&od)[3],
                           const double (&dd)[3], const float (&of)[3], const float (&df)[3],
-                          const FrameParams &fp, const float (&mseed)[3], Frag<RN> *fr, int &nfr,
-                          RootRec<RN> *out, u32 &n_iter, u32 &n_polish, u32 &n_ovf) {
+                          const FrameParams &fp, const float (&mseed)[3], RootRec<RN> &out, u32 &n_iter,
+                          u32 &n_polish) {
     const int face = E.face;
     const PatchView<RN> pv = view_of<RN>(Pd);
     const Arrays<RN> ar = arrays_of(m, RN(0));
@@ -262,10 +228,7 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
     }
     const RN mg = RN(1e-4);
     if (!conv || !(a >= -mg && a <= RN(1) + mg && b >= -mg && b <= RN(1) + mg && t > RN(0))) return;
-    bool grazing;
-    int ent = facing(face, Pd.orient, Sa, Sb, d, grazing);
     const int patch = E.patch;
-    if (!grazing && is_dup(fr, nfr, patch, ent, double(t), 2e-5 * fp.scaled)) return;
     // FP64 refinement of the boundary root by mixed-precision iterative
     // refinement: the residual S(a, b) - o - t d in FP64 from the FP64 control
     // points, the correction from the FP32 tangents of the converged FP32 root.
@@ -310,38 +273,36 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
     if (!ok) return;
     const double mg64 = 1e-7;
     if (!(A >= -mg64 && A <= 1.0 + mg64 && B >= -mg64 && B <= 1.0 + mg64 && T > 0.0)) return;
-    ent = facing(face, Pd.orient, Sa2, Sb2, dd, grazing);
+    bool grazing;
+    const int ent = facing(face, Pd.orient, Sa2, Sb2, dd, grazing);
     if (grazing) return;
     // the same root is the crossing of the block on the other side of a shared face
     const int tw = Pd.twin[face];
     int tent = 0;
     if (tw >= 0) tent = facing(tw & 7, m.patches[tw >> 3].orient, Sa2, Sb2, dd, grazing);
-    if constexpr (OUT) {
-        out->t = RN(T);
-        out->a = RN(clamp01(A));
-        out->b = RN(clamp01(B));
-        out->info = ((uint32_t)patch << 4) | ((uint32_t)face << 1) | (uint32_t)(ent & 1);
-        out->tinfo = tw >= 0 ? (((uint32_t)(tw >> 3) << 4) | ((uint32_t)(tw & 7) << 1) | (uint32_t)(tent & 1))
-                             : 0xFFFFFFFFu;
-    } else {
-        insert_frag(fr, nfr, fp, patch, face, ent, A, B, T, n_ovf);
-        if (tw >= 0) insert_frag(fr, nfr, fp, tw >> 3, tw & 7, tent, A, B, T, n_ovf);
-    }
+    out.t = RN(T);
+    out.a = RN(clamp01(A));
+    out.b = RN(clamp01(B));
+    out.info = ((uint32_t)patch << 4) | ((uint32_t)face << 1) | (uint32_t)(ent & 1);
+    out.tinfo = tw >= 0 ? (((uint32_t)(tw >> 3) << 4) | ((uint32_t)(tw & 7) << 1) | (uint32_t)(tent & 1))
+                        : 0xFFFFFFFFu;
 }
 
-template <typename R, bool OUT>
+// The root of one candidate in out (out.info stays ~0 when there is none).
+template <typename R>
 __device__ __forceinline__ void face_root_any(const Model &m, const DevPatch &Pd, const FaceElem &E,
                                               const double (&od)[3], const double (&dd)[3],
                                               const float (&of)[3], const float (&df)[3],
-                                              const FrameParams &fp, const float (&ms)[3], Frag<R> *fr,
-                                              int &nfr, RootRec<R> *out, u32 &ni, u32 &np, u32 &no) {
+                                              const FrameParams &fp, const float (&ms)[3], RootRec<R> &out,
+                                              u32 &ni, u32 &np) {
+    out.info = out.tinfo = 0xFFFFFFFFu;
     switch (Pd.deg * 2 + Pd.rational) {
-    case 2: face_root<1, false, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
-    case 3: face_root<1, true, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
-    case 4: face_root<2, false, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
-    case 5: face_root<2, true, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
-    case 6: face_root<3, false, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
-    default: face_root<3, true, R, OUT>(m, Pd, E, od, dd, of, df, fp, ms, fr, nfr, out, ni, np, no); break;
+    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
+    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
+    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
+    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
+    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
+    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
     }
 }
 
@@ -436,8 +397,51 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     u32 qidx[MODE == 1 ? kCandCap : 1];
     u32 cpos[MODE == 1 ? kCandCap : 1];   // position in the wave's block-major list
     int ncand = 0;
+    // The ray's boundary crossings, unsorted in the order they were found: depth
+    // and info (Frag) of the first kFragLds in LDS (slot-major, so a wave's
+    // accesses to one slot are consecutive), of the rest in the lane's scratch
+    // array, which also keeps every crossing's face parameters (a, b).
+    __shared__ R s_ft[MODE == 2 ? kFragLds * 64 : 1];
+    __shared__ u32 s_fi[MODE == 2 ? kFragLds * 64 : 1];
     Frag<R> fr[MODE == 1 ? 1 : kFragCap];
     int nfr = 0;
+    auto ft = [&](int q) __attribute__((always_inline)) -> R {
+        return q < kFragLds ? s_ft[q * 64 + lane] : fr[q].t;
+    };
+    auto fi = [&](int q) __attribute__((always_inline)) -> u32 {
+        return q < kFragLds ? s_fi[q * 64 + lane] : fr[q].info;
+    };
+    // a crossing of the same block and facing within tol of depth t is there already
+    auto known = [&](u32 info, R t, R tol) __attribute__((always_inline)) -> bool {
+        bool dup = false;
+        for (int q = 0; q < nfr; ++q) dup |= ((fi(q) ^ info) & ~0xEu) == 0u && fabs(ft(q) - t) <= tol;
+        return dup;
+    };
+    auto push = [&](u32 info, R t, R a, R b) __attribute__((always_inline)) {
+        if (nfr >= fp.max_frag) {
+            ++c_fovf;
+            return;
+        }
+        const int q = nfr++;
+        fr[q].a = a;
+        fr[q].b = b;
+        if (q < kFragLds) {
+            s_ft[q * 64 + lane] = t;
+            s_fi[q * 64 + lane] = info;
+        } else {
+            fr[q].t = t;
+            fr[q].info = info;
+        }
+    };
+    // A root of one of the ray's candidates.  A root an earlier candidate already
+    // gave (the same crossing through an edge or corner shared by elements or
+    // faces) is dropped; so is a second copy of the shared face's crossing.
+    auto add_root = [&](const RootRec<R> &rr) __attribute__((always_inline)) {
+        if (rr.info == 0xFFFFFFFFu || known(rr.info, rr.t, R(2e-5 * fp.scaled))) return;
+        push(rr.info, rr.t, rr.a, rr.b);
+        if (rr.tinfo != 0xFFFFFFFFu && !known(rr.tinfo, rr.t, R(1e-6 * fp.scaled)))
+            push(rr.tinfo, rr.t, rr.a, rr.b);
+    };
     // The lane's listed candidates, all lanes in step (only for rays whose
     // candidates the first launch could not record).  Always inlined: a call
     // would see the kernel's pointers as generic and load through flat.
@@ -446,9 +450,10 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             if (k < ncand) {
                 const FaceElem E = m.elems[cand[k]];
                 const float ms[3] = {NAN, NAN, NAN};
+                RootRec<R> rr;
                 ++c_newton;
-                face_root_any<R, false>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, fr, nfr, nullptr,
-                                        c_iter, c_pol, c_fovf);
+                face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, rr, c_iter, c_pol);
+                add_root(rr);
             }
         }
         ncand = 0;
@@ -584,28 +589,15 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                         ms[0] = s.x; ms[1] = s.y; ms[2] = s.z;
                     }
                     RootRec<R> out;
-                    out.info = out.tinfo = 0xFFFFFFFFu;
-                    int nz = 0;
                     ++c_newton;
-                    face_root_any<R, true>(m, m.patches[E.patch], E, od, odd, of, odf, fp, ms, fr, nz, &out,
-                                           c_iter, c_pol, c_fovf);
+                    face_root_any<R>(m, m.patches[E.patch], E, od, odd, of, odf, fp, ms, out, c_iter, c_pol);
                     s_res[j] = out;
                 }
             }
             __syncthreads();
             // the lane's own roots of this pass, in the order of its candidates
             while (mypos < b0 + nb) {
-                const RootRec<R> rr = s_res[mypos - b0];
-                // a root that an earlier candidate of the ray already gave is dropped
-                // (the test the fused pass makes before refining)
-                if (rr.info != 0xFFFFFFFFu &&
-                    !is_dup(fr, nfr, (int)(rr.info >> 4), (int)(rr.info & 1u), double(rr.t), 2e-5 * fp.scaled)) {
-                    insert_frag(fr, nfr, fp, (int)(rr.info >> 4), (int)((rr.info >> 1) & 7u), (int)(rr.info & 1u),
-                                double(rr.a), double(rr.b), double(rr.t), c_fovf);
-                    if (rr.tinfo != 0xFFFFFFFFu)
-                        insert_frag(fr, nfr, fp, (int)(rr.tinfo >> 4), (int)((rr.tinfo >> 1) & 7u),
-                                    (int)(rr.tinfo & 1u), double(rr.a), double(rr.b), double(rr.t), c_fovf);
-                }
+                add_root(s_res[mypos - b0]);
                 mypos = ++kk < nrec ? own[kk] : 0xFFFFFFFFu;
             }
             __syncthreads();
@@ -625,25 +617,42 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         }
     }
     // 3. Algorithm "Blockwise depth-sorting": the nearest unused exit, then the
-    //    nearest unused entry of the same block in front of it.
+    //    nearest unused entry of the same block in front of it.  Depth order is
+    //    (depth, entries before exits at equal depth, order found): at equal
+    //    depth (the FP32 depths of a crossing through an edge) the pairing then
+    //    finds the entry in front.
     unsigned char pin[kSegCap], pout[kSegCap];
     int npair = 0;
     u64 used = 0;
     for (;;) {
         int ib = -1;
-        for (int q = 0; q < nfr; ++q)
-            if (!((used >> q) & 1ull) && !fr[q].entering()) { ib = q; break; }
+        R tb = R(0);
+        for (int q = 0; q < nfr; ++q) {
+            const R tq = ft(q);
+            if (!((used >> q) & 1ull) && !(fi(q) & 1u) && (ib < 0 || tq < tb)) {
+                ib = q;
+                tb = tq;
+            }
+        }
         if (ib < 0) break;
         used |= 1ull << ib;
+        const u32 pb = fi(ib) >> 4;
         int ifr = -1;
-        for (int q = 0; q < ib; ++q)
-            if (!((used >> q) & 1ull) && fr[q].entering() && fr[q].patch() == fr[ib].patch()) { ifr = q; break; }
+        R tf = R(0);
+        for (int q = 0; q < nfr; ++q) {
+            const u32 iq = fi(q);
+            const R tq = ft(q);
+            if (!((used >> q) & 1ull) && (iq & 1u) && (iq >> 4) == pb && tq <= tb && (ifr < 0 || tq < tf)) {
+                ifr = q;
+                tf = tq;
+            }
+        }
         if (ifr < 0) { ++c_anom; continue; }
         used |= 1ull << ifr;
         if (npair >= kSegCap) { ++c_sovf; continue; }
         // keep the pairs ordered by entry depth
         int q = npair++;
-        while (q > 0 && fr[pin[q - 1]].t > fr[ifr].t) {
+        while (q > 0 && ft(pin[q - 1]) > tf) {
             pin[q] = pin[q - 1];
             pout[q] = pout[q - 1];
             --q;
@@ -671,26 +680,26 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     }
     const R dr[3] = {R(dd[0]), R(dd[1]), R(dd[2])};
     for (int k = 0; k < nseg; ++k) {
-        const Frag<R> &fi = fr[pin[k]];
-        const Frag<R> &fo = fr[pout[k]];
+        const int qi = pin[k], qo = pout[k];
+        const u32 info_o = fi(qo);
         Seg<R> s;
-        s.t_in = R(fi.t);
-        s.t_out = R(fo.t);
+        s.t_in = ft(qi);
+        s.t_out = ft(qo);
         R pi_[3], po_[3];
-        fi.param(pi_);
-        fo.param(po_);
+        face_point(fi(qi), fr[qi].a, fr[qi].b, pi_);
+        face_point(info_o, fr[qo].a, fr[qo].b, po_);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             s.p_in[q] = pi_[q];
             s.p_out[q] = po_[q];
         }
-        const R det_out = rho_ds_any<R>(m, m.patches[fo.patch()], po_, dr, s.rho_out, s.drho_out);
+        const R det_out = rho_ds_any<R>(m, m.patches[info_o >> 4], po_, dr, s.rho_out, s.drho_out);
         // singular J at the exit (a degenerate boundary): no slope; the
         // integrator then stops short of the exit, Eq. (degeneracyfix)
         if (!(fabs(det_out) >= (sizeof(R) == 4 ? R(fp.det_thr) : R(fp.det_thrd))))
             s.drho_out = R(NAN);
         s.pixel = pixel;
-        s.patch = (u32)fo.patch() | ((u32)v << kViewShift);
+        s.patch = (info_o >> 4) | ((u32)v << kViewShift);
         segs[first + k] = s;
     }
     // 5. the rank of every segment among the segments of its block (one atomic per
@@ -701,13 +710,13 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             int kk = -1;
             for (int k = 0; k < nseg; ++k)
                 if (!((ranked >> k) & 1u)) { kk = k; break; }
-            const int myp = kk >= 0 ? fr[pout[kk]].patch() : -1;
+            const int myp = kk >= 0 ? (int)(fi(pout[kk]) >> 4) : -1;
             const u64 any = __ballot(myp >= 0);
             if (any == 0) break;
             const int leader = __ffsll((long long)any) - 1;
             const int p = __shfl(myp, leader);
             u32 cnt = 0;
-            for (int k = 0; k < nseg; ++k) cnt += (!((ranked >> k) & 1u) && fr[pout[k]].patch() == p) ? 1u : 0u;
+            for (int k = 0; k < nseg; ++k) cnt += (!((ranked >> k) & 1u) && (int)(fi(pout[k]) >> 4) == p) ? 1u : 0u;
             const u32 ci = wave_incl_scan(cnt, lane);
             const u32 ctot = __shfl(ci, 63);
             u32 b = 0;
@@ -715,7 +724,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             b = __shfl(b, leader);
             u32 r = b + ci - cnt;
             for (int k = 0; k < nseg; ++k)
-                if (!((ranked >> k) & 1u) && fr[pout[k]].patch() == p) {
+                if (!((ranked >> k) & 1u) && (int)(fi(pout[k]) >> 4) == p) {
                     seg_kr[first + k] = make_uint2((u32)p, r++);
                     ranked |= 1u << k;
                 }
@@ -723,7 +732,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     }
     if (valid) {
         pixseg[vr.pix_begin + pixel] = make_uint2(first, (u32)nseg);
-        if (vr.depth) vr.depth[pixel] = nseg ? float(fr[pin[0]].t) : INFINITY;
+        if (vr.depth) vr.depth[pixel] = nseg ? float(ft(pin[0])) : INFINITY;
     }
     if (fp.collect) {
         flush_counter(ctr, C_RAYS, valid ? 1 : 0);
