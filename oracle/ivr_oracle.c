@@ -685,8 +685,12 @@ int32_t orc_ray_fragments(const orc_scene *s, const double o[3], const double d[
 /* ------------------------------------------------------------------ pairing
  * Algorithm "Blockwise depth-sorting": repeatedly take the unused exit nearest
  * to the screen, then the unused entry nearest to the screen of the same
- * block (read here with t_in <= t_out); stop when no exit is left.          */
-static int pair_fragments(const orc_fragment *fr, int n, int (*segs)[2], int *anomalies)
+ * block (read here with t_in <= t_out + teq); stop when no exit is left.  teq
+ * is the tolerance within which two crossings are one (the duplicate merge
+ * above): where a ray passes through an edge or corner of a block, its entry
+ * and exit there come from roots on different faces, which agree only to
+ * rounding, so either may come first.                                       */
+static int pair_fragments(const orc_fragment *fr, int n, double teq, int (*segs)[2], int *anomalies)
 {
     int used[FRAG_CAP] = {0};
     int nseg = 0;
@@ -698,7 +702,7 @@ static int pair_fragments(const orc_fragment *fr, int n, int (*segs)[2], int *an
         if (ib < 0) break;
         int ifr = -1;
         for (int i = 0; i < n; ++i)
-            if (!used[i] && fr[i].entering && fr[i].patch == fr[ib].patch && fr[i].t <= fr[ib].t &&
+            if (!used[i] && fr[i].entering && fr[i].patch == fr[ib].patch && fr[i].t <= fr[ib].t + teq &&
                 (ifr < 0 || fr[i].t < fr[ifr].t))
                 ifr = i;
         used[ib] = 1;
@@ -756,7 +760,7 @@ static void render_one(const orc_scene *s, const orc_camera *cam, const orc_tf *
     static const int SEGCAP = FRAG_CAP;
     int (*segs)[2] = malloc(sizeof(int[2]) * SEGCAP);
     int anomalies = 0;
-    int nseg = pair_fragments(fr, n, segs, &anomalies);
+    int nseg = pair_fragments(fr, n, 1e-9 * s->scale, segs, &anomalies);
     dg->n_segments = nseg;
     dg->n_anomalies = anomalies;
     /* order segments front to back by entry depth */

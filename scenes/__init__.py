@@ -7,10 +7,10 @@ evaluation of its own, no inversion, no quadrature); the one place that needs
 a spline's Jacobian (the twisted bar's det-J field) calls scipy's B-spline
 routines.
 """
-from .configs import (Patch, Scene, Camera, TransferFunction, make_config, make_degenerate,
+from .configs import (Patch, Scene, Camera, TransferFunction, make_config, make_degenerate, make_edge_lattice,
                       open_uniform_knots, greville, affine_patch,
                       camera_from_angles, random_tf)
 
-__all__ = ["Patch", "Scene", "Camera", "TransferFunction", "make_config", "make_degenerate",
+__all__ = ["Patch", "Scene", "Camera", "TransferFunction", "make_config", "make_degenerate, make_edge_lattice",
            "open_uniform_knots", "greville", "affine_patch",
            "camera_from_angles", "random_tf"]

@@ -484,6 +484,30 @@ def make_degenerate(constant_field: bool = False, width: int = 96, height: int =
                  dict(precision="fp32", rk_tol=1e-5))
 
 
+def make_edge_lattice(width: int = 65, height: int = 65) -> Scene:
+    """Eight affine degree-2 blocks (4^3 control points each) tiling [0, 2]^3, rho
+    sampled from one smooth function at every block's Greville points (C0 across
+    the interfaces).  With odd image sizes the centre pixel's ray goes exactly
+    at the camera target: camera 0 through the edge x = y = 1 that four blocks
+    share, camera 1 through the corner (1, 1, 1) of all eight, camera 2 through
+    the boundary edge x = 1, y = 0 of two blocks (leaving the model there)."""
+    def field(x):
+        return 0.5 + 0.25 * np.sin(1.3 * x[:, 0] + 0.4) * np.cos(0.9 * x[:, 1] - 0.2) + 0.1 * x[:, 2]
+    patches = []
+    for k in range(2):
+        for j in range(2):
+            for i in range(2):
+                off = np.array([i, j, k], dtype=np.float64)
+                patches.append(affine_patch(np.eye(3), off, scalar=lambda g, off=off: field(g + off)))
+    tf = random_tf(np.random.default_rng(np.random.PCG64(6101)), 3.0, scalar_domain(patches))
+    up = np.array([0.0, 0.0, 1.0])
+    cams = [Camera(np.array([-1.5, 3.5, 0.73]), np.array([1.0, 1.0, 0.73]), up, 30.0, width, height),
+            Camera(np.array([-0.6, 2.9, -0.35]), np.array([1.0, 1.0, 1.0]), up, 30.0, width, height),
+            Camera(np.array([1.9, 2.2, 1.4]), np.array([1.0, 0.0, 0.6]), up, 30.0, width, height)]
+    return Scene("edge_lattice_2x2x2", patches, tf, cams, bbox_of(patches),
+                 dict(precision="fp32", rk_tol=1e-5))
+
+
 def make_config(k: int, width: Optional[int] = None, height: Optional[int] = None):
     """Build config k (1..4) as a Scene; config 5 returns (model_a, model_b, views)."""
     if k == 1:

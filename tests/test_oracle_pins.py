@@ -233,6 +233,37 @@ def test_fragments_of_affine_block_are_slab_roots(oracle_lib):
     assert checked == 60
 
 
+def test_rays_through_block_edges_and_corners_pair_per_block(oracle_lib):
+    """Eight unit blocks tiling [0, 2]^3; the centre rays of the edge-lattice
+    cameras go exactly through an edge of four blocks, a corner of all eight and
+    a boundary edge of two.  Every block the ray meets has as many entries as
+    exits, the first entry and last exit are the slab roots of [0, 2]^3, and the
+    crossings at the edge or corner sit at its ray parameter."""
+    from scenes import make_edge_lattice
+    sc = make_edge_lattice()
+    so = oracle.OracleScene(sc.patches, sc.scale)
+    for cam in sc.cameras:
+        o, d = oracle.camera_ray(cam, 32.5, 32.5)
+        assert np.allclose(np.cross(d, cam.target - o), 0.0, atol=1e-12)   # through the target
+        fr = so.fragments(o, d)
+        n_in, n_out = np.zeros(8, int), np.zeros(8, int)
+        for t, p, patch, face, ent in fr:
+            (n_in if ent else n_out)[patch] += 1
+            x = o + t * d
+            assert np.allclose(p, x - np.array([patch & 1, (patch >> 1) & 1, patch >> 2]), atol=1e-9)
+        assert (n_in == n_out).all(), (n_in, n_out)
+        t0, t1 = _slab(o, d, np.zeros(3), np.full(3, 2.0))
+        assert abs(fr[0][0] - t0) < 1e-9 and abs(fr[-1][0] - t1) < 1e-9
+        t_edge = float(np.dot(cam.target - o, d))
+        assert sum(abs(t - t_edge) < 1e-9 for t, *_ in fr) >= 2
+        # the pairing leaves nothing over: one segment per block met, also on the
+        # other rays of the image column, which lie in a plane through the edge
+        col = np.arange(cam.height) * cam.width + 32
+        ref = oracle.render(sc, cam, sc.tf, pixels=col)
+        assert (ref.n_anomalies == 0).all()
+        assert ref.n_segments[32] == int((n_in > 0).sum())
+
+
 # ------------------------------------------------------------------ closed-form images
 
 def _box_chord(o, d):
