@@ -460,6 +460,30 @@ static void build_obb(Box3 &E, const std::vector<std::array<double, 3>> &pts, co
     }
 }
 
+// A bound on the slope of an element's surface against its box plane: the
+// largest ratio of normal to in-plane component over the edges of its Bezier
+// net, times 3 (the surface tangents are positive combinations of the net's
+// edges, and the two parameter directions need not be orthogonal), at most 1;
+// 1 for a net with an edge that has no in-plane extent.
+static float element_graze(const FaceElem &E, const std::vector<std::array<double, 3>> &pts, int p) {
+    double g = 0.0;
+    auto edge = [&](const std::array<double, 3> &P0, const std::array<double, 3> &P1) {
+        double c[3];
+        for (int r = 0; r < 3; ++r)
+            c[r] = E.ax[r][0] * (P1[0] - P0[0]) + E.ax[r][1] * (P1[1] - P0[1]) + E.ax[r][2] * (P1[2] - P0[2]);
+        const double inpl = std::sqrt(c[0] * c[0] + c[1] * c[1]);
+        const double len = std::sqrt(inpl * inpl + c[2] * c[2]);
+        if (len == 0.0) return;                       // coincident points: no direction
+        g = std::max(g, inpl > 1e-9 * len ? std::fabs(c[2]) / inpl : 1e30);
+    };
+    for (int j = 0; j <= p; ++j)
+        for (int i = 0; i < p; ++i) {
+            edge(pts[j * (p + 1) + i], pts[j * (p + 1) + i + 1]);
+            edge(pts[i * (p + 1) + j], pts[(i + 1) * (p + 1) + j]);
+        }
+    return (float)std::min(1.0, 3.0 * g);
+}
+
 }  // namespace
 
 extern "C" {
@@ -720,6 +744,7 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
                             std::memset(&E, 0, sizeof E);
                             build_obb(E, pts, pts[0].data(), pts[p].data(), pts[p * (p + 1)].data(),
                                       pts[(p + 1) * (p + 1) - 1].data(), pad);
+                            E.graze = element_graze(E, pts, p);
                             E.a0 = (float)tn[da][sa];
                             E.a1 = (float)tn[da][sa + 1];
                             E.b0 = (float)tn[db][sb];

@@ -33,6 +33,7 @@ using u64 = unsigned long long;
 
 constexpr int kFlat = 256;    // candidates solved per pass of the flattened solve
 constexpr int kFragLds = 16;  // crossings per ray kept in LDS (the rest in scratch)
+constexpr int kExtra = 64;    // second roots of one element per pass of the flattened solve
 
 __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -173,20 +174,25 @@ __device__ __forceinline__ bool face_newton(const PatchView<RN> &pv, const Array
     return false;
 }
 
-// Boundary roots from one candidate element E.  First seed by seed_mode:
+// Boundary roots of a ray in one candidate element E (Eqs. (F), (newtonsmethod)
+// restricted to the face): FP32 Newton, then FP64 refinement.  First seed by
+// seed_mode:
 //   PLAIN  the element centre;
 //   BOX    the point of the ray in the middle of its passage through E's box,
 //          mapped to (a, b) through the box axes;
 //   MLP    the block's learned inverse map at that same point, restricted to the
 //          face's (a, b).
 // If Newton does not converge from it: the element centre and its four quarter
-// points.  A root that converges anywhere on the face and is new for
-// this ray is refined in FP64 and inserted into the depth-sorted fragment list.
+// points.  A root on the closed face becomes the crossing in out and, across a
+// shared face, the neighbouring block's crossing (out.tinfo).  A ray nearly
+// tangent to the element may cross it twice: then `again` is set, and a second
+// call with T1 = the first root's depth looks for another root by Newton from
+// points of the ray's passage through the element's box on both sides of it.
 template <int P, bool RAT, typename RN>
 __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E, const double (&od)[3],
                           const double (&dd)[3], const float (&of)[3], const float (&df)[3],
-                          const FrameParams &fp, const float (&mseed)[3], RootRec<RN> &out, u32 &n_iter,
-                          u32 &n_polish) {
+                          const FrameParams &fp, const float (&mseed)[3], float T1, RootRec<RN> &out,
+                          bool &again, u32 &n_iter, u32 &n_polish) {
     const int face = E.face;
     const PatchView<RN> pv = view_of<RN>(Pd);
     const Arrays<RN> ar = arrays_of(m, RN(0));
@@ -194,19 +200,39 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
     const RN tol = (sizeof(RN) == 4 ? RN(2e-6) : RN(1e-12)) * RN(fp.scaled);
     const RN ac = RN(0.5) * (RN(E.a0) + RN(E.a1)), bc = RN(0.5) * (RN(E.b0) + RN(E.b1));
     const RN ha = RN(0.5) * (RN(E.a1) - RN(E.a0)), hb = RN(0.5) * (RN(E.b1) - RN(E.b0));
-    RN a, b, t, Sa[3], Sb[3];
-    bool conv = false;
     int dn, da, db;
     face_dirs(face, dn, da, db);
-    for (int seed = (fp.seed_mode == IVR_SEED_PLAIN) ? 1 : 0; seed < 6 && !conv; ++seed) {
-        if (seed == 0) {
-            float t0, t1;
-            obb_hit(E, of, df, t0, t1);
-            const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
+    float t0, t1;
+    obb_hit(E, of, df, t0, t1);
+    t1 = fminf(t1, t0 + 4.0f * fp.scale);
+    // Two crossings need the ray's slope against the element's plane below the
+    // surface's largest slope there (the surface's height along the ray has a
+    // stationary point between them); E.graze bounds that slope from the net.
+    const bool tangent = fabsf(E.ax[2][0] * df[0] + E.ax[2][1] * df[1] + E.ax[2][2] * df[2]) < E.graze;
+    const bool second = T1 >= 0.f;
+    const double tsame = 2e-5 * fp.scaled;   // one crossing
+    const PatchView<double> pv64 = view_of<double>(Pd);
+    const Arrays<double> ar64 = arrays_of(m, 0.0);
+    const double tol64 = 1e-12 * fp.scaled;
+    const int s_begin = second ? 6 : (fp.seed_mode == IVR_SEED_PLAIN ? 1 : 0);
+    const int s_end = second ? 12 : 6;
+    // Seeds in turn until Newton converges; the first search ends there, with or
+    // without a crossing, the second goes on past roots off the face and the
+    // first root again.
+    for (int seed = s_begin; seed < s_end; ++seed) {
+        RN a, b, t, Sa[3], Sb[3];
+        if (seed == 0 || seed >= 6) {
+            // the ray's point in the middle of its interval in the box (for the
+            // second root: points of that interval 1 and 3 eighths of its length
+            // before and after the first root, then its ends)
+            const float h = 0.125f * (t1 - t0);
+            const float tm = seed == 0 ? 0.5f * (t0 + t1)
+                             : seed < 10 ? fminf(fmaxf(T1 + ((seed & 1) ? h : -h) * (seed < 8 ? 1.f : 3.f), t0), t1)
+                                         : (seed == 10 ? t0 : t1);
             float x[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) x[q] = of[q] + tm * df[q];
-            if (fp.seed_mode == IVR_SEED_MLP && isfinite(mseed[0])) {
+            if (seed == 0 && fp.seed_mode == IVR_SEED_MLP && isfinite(mseed[0])) {
                 a = RN(clamp01(mseed[da]));
                 b = RN(clamp01(mseed[db]));
             } else {
@@ -224,85 +250,103 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
             a = ac + ha * RN((seed & 1) ? -0.5 : 0.5);
             b = bc + hb * RN((seed & 2) ? -0.5 : 0.5);
         }
-        conv = face_newton<P, RAT, RN>(pv, ar, face, o, d, tol, fp.max_newton, a, b, t, Sa, Sb, n_iter);
-    }
-    const RN mg = RN(1e-4);
-    if (!conv || !(a >= -mg && a <= RN(1) + mg && b >= -mg && b <= RN(1) + mg && t > RN(0))) return;
-    const int patch = E.patch;
-    // FP64 refinement of the boundary root by mixed-precision iterative
-    // refinement: the residual S(a, b) - o - t d in FP64 from the FP64 control
-    // points, the correction from the FP32 tangents of the converged FP32 root.
-    // It contracts by the FP32 tangents' relative error (~1e-7) per step, so from
-    // the FP32 stopping residual (<= 2e-6 scale) one step reaches ~1e-12 scale.
-    // A step of at most 1e-5 in (a, b) and 1e-5 scale in t leaves a residual below
-    // the 1e-9 scale acceptance bound and is taken without evaluating it again.
-    const PatchView<double> pv64 = view_of<double>(Pd);
-    const Arrays<double> ar64 = arrays_of(m, 0.0);
-    double A = a, B = b, T = t, S2[3], F2[3], Sa2[3], Sb2[3];
+        if (!face_newton<P, RAT, RN>(pv, ar, face, o, d, tol, fp.max_newton, a, b, t, Sa, Sb, n_iter)) continue;
+        const RN mg = RN(1e-4);
+        if (!(a >= -mg && a <= RN(1) + mg && b >= -mg && b <= RN(1) + mg && t > RN(0))) {
+            if (second) continue;
+            return;
+        }
+        // FP64 refinement of the boundary root by mixed-precision iterative
+        // refinement: the residual S(a, b) - o - t d in FP64 from the FP64 control
+        // points, the correction from FP32 tangents.  It contracts by the FP32
+        // tangents' relative error (~1e-7) times the system's condition per step,
+        // so from the FP32 stopping residual (<= 2e-6 scale) one step reaches
+        // ~1e-12 scale.  A ray nearly tangent to the face has a large condition and
+        // an FP32 root far off along the tangent: after a step above 1e-4 in
+        // (a, b) the FP32 tangents are taken again at the new point.  A step of at
+        // most 1e-5 in (a, b) and 1e-5 scale in t leaves a residual below the 1e-9
+        // scale acceptance bound and is taken without evaluating it again.
+        double A = a, B = b, T = t, S2[3], F2[3], Sa2[3], Sb2[3];
+        bool ok = false;
+        for (int k = 0; k < 4; ++k) {
+            eval_face<P, RAT, double, false>(pv64, ar64, face, A, B, S2, Sa2, Sb2);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        Sa2[q] = double(Sa[q]);
-        Sb2[q] = double(Sb[q]);
-    }
-    const double tol64 = 1e-12 * fp.scaled;
-    bool ok = false;
-    for (int k = 0; k < 4; ++k) {
-        eval_face<P, RAT, double, false>(pv64, ar64, face, A, B, S2, Sa2, Sb2);
+            for (int q = 0; q < 3; ++q) F2[q] = S2[q] - od[q] - T * dd[q];
+            const double r2 = dot3(F2, F2);
+            if (r2 <= tol64 * tol64) {
+                ok = true;
+                break;
+            }
+            if (k == 3) {
+                ok = r2 <= 1e-18 * fp.scaled * fp.scaled;
+                break;
+            }
+            ++n_polish;
+            RN nd[3] = {-d[0], -d[1], -d[2]}, rhs[3] = {RN(-F2[0]), RN(-F2[1]), RN(-F2[2])}, st[3];
+            solve_cols(Sa, Sb, nd, rhs, st);
+            A += double(st[0]);
+            B += double(st[1]);
+            T += double(st[2]);
+            const double sab = fmax(fabs(double(st[0])), fabs(double(st[1])));
+            if (sab <= 1e-5 && fabs(double(st[2])) <= 1e-5 * fp.scaled) {
+                ok = true;
+                break;
+            }
+            if (sab > 1e-4) {
+                RN S[3];
+                eval_face<P, RAT, RN>(pv, ar, face, RN(A), RN(B), S, Sa, Sb);
+            }
+        }
+        // A crossing is a root on the closed face up to 1e-9 in (a, b): the refined
+        // root is accurate to ~1e-11, so a crossing exactly at an edge is kept, while
+        // a ray passing just outside the edge yields no crossing of this face (its
+        // crossing of the block, if any, is a root on the neighbouring face).
+        const double mg64 = 1e-9;
+        if (!ok || !(A >= -mg64 && A <= 1.0 + mg64 && B >= -mg64 && B <= 1.0 + mg64 && T > 0.0)) {
+            if (second) continue;
+            return;
+        }
+        if (second && fabs(T - double(T1)) <= tsame) continue;   // the first root again
 #pragma unroll
-        for (int q = 0; q < 3; ++q) F2[q] = S2[q] - od[q] - T * dd[q];
-        const double r2 = dot3(F2, F2);
-        if (r2 <= tol64 * tol64) {
-            ok = true;
-            break;
+        for (int q = 0; q < 3; ++q) {   // facing from the FP32 tangents at the root
+            Sa2[q] = double(Sa[q]);
+            Sb2[q] = double(Sb[q]);
         }
-        if (k == 3) {
-            ok = r2 <= 1e-18 * fp.scaled * fp.scaled;
-            break;
-        }
-        ++n_polish;
-        RN nd[3] = {-d[0], -d[1], -d[2]}, rhs[3] = {RN(-F2[0]), RN(-F2[1]), RN(-F2[2])}, st[3];
-        solve_cols(Sa, Sb, nd, rhs, st);
-        A += double(st[0]);
-        B += double(st[1]);
-        T += double(st[2]);
-        if (fmax(fabs(double(st[0])), fabs(double(st[1]))) <= 1e-5 && fabs(double(st[2])) <= 1e-5 * fp.scaled) {
-            ok = true;
-            break;
-        }
+        bool grazing;
+        const int ent = facing(face, Pd.orient, Sa2, Sb2, dd, grazing);
+        if (grazing) return;
+        // the same root is the crossing of the block on the other side of a shared face
+        const int tw = Pd.twin[face];
+        int tent = 0;
+        if (tw >= 0) tent = facing(tw & 7, m.patches[tw >> 3].orient, Sa2, Sb2, dd, grazing);
+        out.t = RN(T);
+        out.a = RN(clamp01(A));
+        out.b = RN(clamp01(B));
+        out.info = ((uint32_t)E.patch << 4) | ((uint32_t)face << 1) | (uint32_t)(ent & 1);
+        out.tinfo = tw >= 0 ? (((uint32_t)(tw >> 3) << 4) | ((uint32_t)(tw & 7) << 1) | (uint32_t)(tent & 1))
+                            : 0xFFFFFFFFu;
+        again = tangent && !second;
+        return;
     }
-    if (!ok) return;
-    const double mg64 = 1e-7;
-    if (!(A >= -mg64 && A <= 1.0 + mg64 && B >= -mg64 && B <= 1.0 + mg64 && T > 0.0)) return;
-    bool grazing;
-    const int ent = facing(face, Pd.orient, Sa2, Sb2, dd, grazing);
-    if (grazing) return;
-    // the same root is the crossing of the block on the other side of a shared face
-    const int tw = Pd.twin[face];
-    int tent = 0;
-    if (tw >= 0) tent = facing(tw & 7, m.patches[tw >> 3].orient, Sa2, Sb2, dd, grazing);
-    out.t = RN(T);
-    out.a = RN(clamp01(A));
-    out.b = RN(clamp01(B));
-    out.info = ((uint32_t)patch << 4) | ((uint32_t)face << 1) | (uint32_t)(ent & 1);
-    out.tinfo = tw >= 0 ? (((uint32_t)(tw >> 3) << 4) | ((uint32_t)(tw & 7) << 1) | (uint32_t)(tent & 1))
-                        : 0xFFFFFFFFu;
 }
 
-// The root of one candidate in out (out.info stays ~0 when there is none).
+// The root of one candidate in out (info stays ~0 when there is none); T1 < 0
+// for the first search, else the depth of the first root (see face_root).
 template <typename R>
 __device__ __forceinline__ void face_root_any(const Model &m, const DevPatch &Pd, const FaceElem &E,
                                               const double (&od)[3], const double (&dd)[3],
                                               const float (&of)[3], const float (&df)[3],
-                                              const FrameParams &fp, const float (&ms)[3], RootRec<R> &out,
-                                              u32 &ni, u32 &np) {
+                                              const FrameParams &fp, const float (&ms)[3], float T1,
+                                              RootRec<R> &out, bool &again, u32 &ni, u32 &np) {
     out.info = out.tinfo = 0xFFFFFFFFu;
+    again = false;
     switch (Pd.deg * 2 + Pd.rational) {
-    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
-    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
-    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
-    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
-    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
-    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, ms, out, ni, np); break;
+    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
     }
 }
 
@@ -433,14 +477,17 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             fr[q].info = info;
         }
     };
-    // A root of one of the ray's candidates.  A root an earlier candidate already
-    // gave (the same crossing through an edge or corner shared by elements or
-    // faces) is dropped; so is a second copy of the shared face's crossing.
+    // A root of one of the ray's candidates: the block's crossing and the
+    // neighbour's across a shared face, each dropped on its own when the list
+    // has it already (the same crossing through an edge or corner shared by
+    // elements or faces).  A ray through an edge of four blocks crosses two of
+    // them at one point: their entry and exit come from different faces'
+    // roots, whose other crossings are duplicates.
     auto add_root = [&](const RootRec<R> &rr) __attribute__((always_inline)) {
-        if (rr.info == 0xFFFFFFFFu || known(rr.info, rr.t, R(2e-5 * fp.scaled))) return;
-        push(rr.info, rr.t, rr.a, rr.b);
-        if (rr.tinfo != 0xFFFFFFFFu && !known(rr.tinfo, rr.t, R(1e-6 * fp.scaled)))
-            push(rr.tinfo, rr.t, rr.a, rr.b);
+        if (rr.info == 0xFFFFFFFFu) return;
+        const R tol = R(2e-5 * fp.scaled);
+        if (!known(rr.info, rr.t, tol)) push(rr.info, rr.t, rr.a, rr.b);
+        if (rr.tinfo != 0xFFFFFFFFu && !known(rr.tinfo, rr.t, tol)) push(rr.tinfo, rr.t, rr.a, rr.b);
     };
     // The lane's listed candidates, all lanes in step (only for rays whose
     // candidates the first launch could not record).  Always inlined: a call
@@ -450,10 +497,17 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             if (k < ncand) {
                 const FaceElem E = m.elems[cand[k]];
                 const float ms[3] = {NAN, NAN, NAN};
-                RootRec<R> rr;
-                ++c_newton;
-                face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, rr, c_iter, c_pol);
-                add_root(rr);
+                float T1 = -1.f;
+                for (int s = 0; s < 2; ++s) {   // a second search where the ray is nearly tangent
+                    RootRec<R> rr;
+                    bool again;
+                    ++c_newton;
+                    face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, T1, rr, again, c_iter,
+                                     c_pol);
+                    add_root(rr);
+                    if (!again) break;
+                    T1 = float(rr.t);
+                }
             }
         }
         ncand = 0;
@@ -563,6 +617,9 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         // keep their fragment lists.
         __shared__ double s_dd[64 * 3];
         __shared__ RootRec<R> s_res[kFlat];
+        __shared__ RootRec<R> s_x[kExtra];   // second roots of a pass and their owning lanes
+        __shared__ u32 s_xo[kExtra];
+        __shared__ u32 s_nx;
         const uint2 cr = mq.crange[g * 64u + (u32)lane];
         const u32 nrec = cr.y & 0x7FFFFFFFu;
         const u32 incl = wave_incl_scan(nrec, lane);
@@ -575,6 +632,8 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         u32 kk = 0, mypos = nrec ? own[0] : 0xFFFFFFFFu;
         for (u32 b0 = 0; b0 < total; b0 += kFlat) {
             const u32 nb = min((u32)kFlat, total - b0);
+            if (lane == 0) s_nx = 0;
+            __syncthreads();
             for (u32 r = 0; r < nb; r += 64) {
                 const u32 j = r + (u32)lane;
                 if (j < nb) {
@@ -588,10 +647,27 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                         const float4 s = mq.seed[c.y];
                         ms[0] = s.x; ms[1] = s.y; ms[2] = s.z;
                     }
-                    RootRec<R> out;
-                    ++c_newton;
-                    face_root_any<R>(m, m.patches[E.patch], E, od, odd, of, odf, fp, ms, out, c_iter, c_pol);
-                    s_res[j] = out;
+                    float T1 = -1.f;
+                    for (int s = 0; s < 2; ++s) {   // a second search where the ray is nearly tangent
+                        RootRec<R> out;
+                        bool again;
+                        ++c_newton;
+                        face_root_any<R>(m, m.patches[E.patch], E, od, odd, of, odf, fp, ms, T1, out, again,
+                                         c_iter, c_pol);
+                        if (s == 0) {
+                            s_res[j] = out;
+                        } else if (out.info != 0xFFFFFFFFu) {   // to the pass's short list of second roots
+                            const u32 x = atomicAdd(&s_nx, 1u);
+                            if (x < (u32)kExtra) {
+                                s_x[x] = out;
+                                s_xo[x] = ol;
+                            } else {
+                                ++c_fovf;
+                            }
+                        }
+                        if (!again) break;
+                        T1 = float(out.t);
+                    }
                 }
             }
             __syncthreads();
@@ -600,6 +676,9 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                 add_root(s_res[mypos - b0]);
                 mypos = ++kk < nrec ? own[kk] : 0xFFFFFFFFu;
             }
+            const u32 nx = min(s_nx, (u32)kExtra);
+            for (u32 i = 0; i < nx; ++i)
+                if (s_xo[i] == (u32)lane) add_root(s_x[i]);
             __syncthreads();
         }
         // Rays with more candidates than were recorded traverse again and solve
@@ -618,12 +697,14 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     }
     // 3. Algorithm "Blockwise depth-sorting": the nearest unused exit, then the
     //    nearest unused entry of the same block in front of it.  Depth order is
-    //    (depth, entries before exits at equal depth, order found): at equal
-    //    depth (the FP32 depths of a crossing through an edge) the pairing then
-    //    finds the entry in front.
+    //    (depth, order found); an entry counts as in front of an exit up to the
+    //    depth tolerance of one crossing (an entry and exit at one point, as
+    //    where a ray passes through an edge of the block, come from roots of
+    //    different faces and may round to neighbouring FP32 depths).
     unsigned char pin[kSegCap], pout[kSegCap];
     int npair = 0;
     u64 used = 0;
+    const R teq = R(1e-6 * fp.scaled);
     for (;;) {
         int ib = -1;
         R tb = R(0);
@@ -642,7 +723,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         for (int q = 0; q < nfr; ++q) {
             const u32 iq = fi(q);
             const R tq = ft(q);
-            if (!((used >> q) & 1ull) && (iq & 1u) && (iq >> 4) == pb && tq <= tb && (ifr < 0 || tq < tf)) {
+            if (!((used >> q) & 1ull) && (iq & 1u) && (iq >> 4) == pb && tq <= tb + teq && (ifr < 0 || tq < tf)) {
                 ifr = q;
                 tf = tq;
             }

@@ -58,7 +58,8 @@ struct alignas(16) FaceElem {
     float a0, a1, b0, b1;  // parameter rectangle in the face's (a, b) directions
     int32_t face;
     int32_t patch;
-    int32_t pad[2];
+    float graze;           // bound on the slope of the element against its box plane
+    int32_t pad;
 };
 
 // Up to kTile x kTile neighbouring elements of one face, with an oriented box

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from scenes import make_config, make_degenerate, camera_from_angles
+from scenes import make_config, make_degenerate, make_edge_lattice, camera_from_angles
 from scenes.configs import Patch, TransferFunction
 
 pytestmark = pytest.mark.gpu
@@ -149,6 +149,23 @@ def test_degenerate_face_full_image(renderer, view):
     assert st["degenerate"] > 100 and st["rk_iter_cap"] == 0
 
 
+@pytest.mark.parametrize("view", [0, 1, 2])
+def test_rays_through_block_edges_and_corners(renderer, view):
+    """Centre rays exactly through an edge of four blocks (view 0), a corner of
+    eight (view 1) and a boundary edge of two (view 2): the crossings found from
+    different faces of one point must leave every block paired (no anomaly);
+    the full 65x65 image against the oracle."""
+    sc = make_edge_lattice()
+    cam = sc.cameras[view]
+    print(f"[parity] edge lattice view {view}", flush=True)
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32")
+    ref = oracle.render(sc, cam, sc.tf)
+    _compare(f"edge lattice view{view} 65x65", img, depth, ref, scale=sc.scale)
+    assert st["anomalies"] == 0 and st["fragment_overflow"] == 0
+    centre = 32 * cam.width + 32
+    assert abs(depth[centre] - ref.depth[centre]) <= DEPTH_REL_TOL * ref.depth[centre]
+
+
 def test_degenerate_face_constant_field_closed_form(renderer):
     """Constant rho on the degenerate-face cube: alpha = 1 - exp(-kappa L) with L
     the ray-box chord of the unit cube, for both views."""
@@ -181,6 +198,25 @@ def test_config2_twisted_bar_sampled(renderer, view):
     ref = oracle.render(sc, cam, sc.tf, pixels=pix)
     _compare(f"config2 view{view} 512x512", img, depth, ref, pix, sc.scale)
     assert st["segment_overflow"] == 0
+    assert st["anomalies"] == 0
+
+
+# Rays of the twisted bar that clip a thin sliver of it, crossing one curved face
+# element twice (found as the only pairing anomalies of the 512^2 views when an
+# element gave at most one root): view, pixel x, y.
+_DOUBLE_CROSSINGS = [(0, 283, 170), (2, 224, 419), (2, 285, 254), (2, 232, 249)]
+
+
+def test_element_crossed_twice(renderer):
+    sc = make_config(2)
+    for view in sorted({v for v, _, _ in _DOUBLE_CROSSINGS}):
+        cam = sc.cameras[view]
+        img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32", rk_tol=1e-5)
+        pix = np.array([y * cam.width + x for v, x, y in _DOUBLE_CROSSINGS if v == view])
+        ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+        assert (ref.n_segments >= 1).all()
+        _compare(f"config2 view{view} double crossings", img, depth, ref, pix, sc.scale)
+        assert st["anomalies"] == 0
 
 
 def test_config3_bent_beam_1080p_sampled(renderer):
