@@ -228,6 +228,7 @@ def test_config3_bent_beam_1080p_sampled(renderer):
     _compare("config3 1920x1080", img, depth, ref, pix, sc.scale)
     print(f"[stats] config3: {st}", flush=True)
     assert st["fragment_overflow"] == 0 and st["segment_overflow"] == 0
+    assert st["anomalies"] == 0
 
 
 def test_config4_nurbs_channel_1080p_sampled(renderer):
@@ -238,6 +239,19 @@ def test_config4_nurbs_channel_1080p_sampled(renderer):
     ref = oracle.render(sc, cam, sc.tf, pixels=pix)
     _compare("config4 1920x1080", img, depth, ref, pix, sc.scale)
     print(f"[stats] config4: {st}", flush=True)
+    assert st["anomalies"] == 0
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_every_ray_pairs_cleanly_at_1080p(renderer, k):
+    """All views of the multi-block models at 1920x1080 (6.2M rays): every
+    crossing is paired (rays through block edges and corners, grazing rays)."""
+    sc = make_config(k)
+    for view, cam in enumerate(sc.cameras):
+        _, _, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32")
+        print(f"[parity] config{k} view{view}: rays {st['rays']} segments {st['segments']} "
+              f"anomalies {st['anomalies']}", flush=True)
+        assert st["anomalies"] == 0 and st["fragment_overflow"] == 0 and st["segment_overflow"] == 0
 
 
 @pytest.mark.parametrize("size", [(1, 1), (67, 35), (8, 8)])
