@@ -96,7 +96,8 @@ typedef struct {
     int32_t precision;          /* IVR_PRECISION_*                          [FP32] */
     double rk_tol;              /* RKF45 local error bound on p (inf-norm) [1e-5] */
     double h_max;               /* largest step, in world units along the ray;
-                                   <= 0: scale/64                           [0]   */
+                                   <= 0: scale/32; half of it on a segment
+                                   with a singular end                      [0]   */
     double c_perp;              /* weight c of V_perp in Eq. (vec2)         [1]   */
     int32_t n_super;            /* supersampling sub-steps per RK step      [4]   */
     double det_fp64_threshold;  /* |det J| below it: solve in FP64          [1e-6] */
@@ -108,8 +109,11 @@ typedef struct {
     int32_t timing;             /* 1: record HIP events around every phase of
                                    this render for ivr_phase_times (no sync) [0] */
     double tf_step;             /* largest change of the transfer function's
-                                   output per step: limits h where the transfer
-                                   function is steep and rho is changing   [0.1] */
+                                   output per supersampling sub-step: more
+                                   sub-steps where it is steep       [0.025] */
+    double rho_step;            /* largest change of rho per step, as a
+                                   fraction of the transfer function's domain:
+                                   limits h where rho changes fast     [0.1] */
 } ivr_render_opts;
 
 /* Counters of one render (filled when a non-NULL ivr_stats* is passed; that

@@ -502,7 +502,8 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->max_newton_iter = 16;
     o->rho_interp = IVR_RHO_HERMITE;
     o->timing = 0;
-    o->tf_step = 0.1;
+    o->tf_step = 0.025;
+    o->rho_step = 0.1;
 }
 
 ivr_status ivr_create(ivr_ctx **out, int32_t device, void *hip_stream) {
@@ -982,10 +983,12 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
     if (!(o.early_term >= 0 && o.early_term < 1)) return fail(c, IVR_EINVAL, "early_term outside [0,1)");
     if (!(o.tf_step > 0 && std::isfinite(o.tf_step))) return fail(c, IVR_EINVAL, "tf_step must be > 0");
     fp.tf_step = (float)o.tf_step;
+    if (!(o.rho_step > 0 && std::isfinite(o.rho_step))) return fail(c, IVR_EINVAL, "rho_step must be > 0");
+    fp.rho_step = (float)o.rho_step;
     if (o.max_newton_iter < 1 || o.max_newton_iter > 100)
         return fail(c, IVR_EINVAL, "max_newton_iter outside 1..100");
-    const double hmax = o.h_max > 0 ? o.h_max : scale / 64.0;
-    const double hmin = std::max(1e-7 * scale, 1e-4 * hmax);
+    const double hmax = o.h_max > 0 ? o.h_max : scale / 32.0;
+    const double hmin = std::min(hmax, 1.5625e-6 * scale);
     double tol = o.rk_tol;
     if (o.precision == IVR_PRECISION_FP32) tol = std::max(tol, 32.0 * 1.1920929e-7);
     fp.rk_told = tol; fp.rk_tol = (float)tol;

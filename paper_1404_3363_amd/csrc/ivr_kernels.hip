@@ -1062,6 +1062,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     // the chord short of it and close with the exit's rho
                     Lend = isfinite(m_out) ? L : L - R(1e-4) * L;
                     c_deg += !isfinite(m_out);
+                    // next to a singular face p' and rho vary like sqrt of the
+                    // distance: half the step bound on such a segment
+                    if (!isfinite(m_out)) hmax *= R(0.5);
                     C[0] = C[1] = C[2] = A = R(0);
                     pending = false;
                     fresh = true;
@@ -1134,6 +1137,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 // to first order at the face)
                 ++c_deg;
                 rho_in = rho_cur;
+                hmax *= R(0.5);
                 const Seg<R> &sg = segs[sid];
                 shrink = 1;
                 newton_it = 0;
@@ -1160,13 +1164,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             if (A >= R(1) - early) done = true;
         }
         if (!done && !shrinking && !shrink) {
-            // the transfer function's frequencies bound the step where rho changes
+            // rho's change per step is bounded (its interpolation between samples);
+            // the transfer function's frequencies are the supersampling's
             const R dn_ds = fabs(m_cur) * R(sizeof(R) == 4 ? double(vls[vid].inv_ranged)
                                                             : views[vid].fp.tf_inv_ranged);
-            R slope;
-            if constexpr (sizeof(R) == 4) slope = tf_slope_near(vls[vid], rho_cur);
-            else slope = tf_slope_near(views[vid].fp, rho_cur);
-            const R hf = R(fp.tf_step) / (dn_ds * slope + R(1e-30));
+            const R hf = R(fp.rho_step) / (dn_ds + R(1e-30));
             h = h < hf ? h : (hf > hmin ? hf : hmin);
             const R hh = (h < Lend - s) ? h : (Lend - s);
             R q[3], dummy, dg[3], dr2;

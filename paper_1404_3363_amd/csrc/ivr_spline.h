@@ -544,21 +544,6 @@ __device__ __forceinline__ void tf_eval(const ViewLds &w, float rho, float (&out
     out[3] = a.w + b.w * n;
 }
 
-__device__ __forceinline__ float tf_slope_near(const ViewLds &w, float rho) {
-    return w.smax[tf_interval(w, clamp01((rho - w.lo) * w.inv_range))];
-}
-
-// Slope bound of the transfer function around rho (per unit of n).
-template <typename R>
-__device__ __forceinline__ R tf_slope_near(const FrameParams &fp, R rho) {
-    const float n = clamp01(float((rho - R(fp.tf_lod)) * R(fp.tf_inv_ranged)));
-    float sm = fp.tf_smax[0];
-#pragma unroll
-    for (int k = 1; k < kMaxTfKnots - 1; ++k)
-        if (k < fp.tf_n - 1) sm = n >= fp.tf_x[k] ? fp.tf_smax[k] : sm;
-    return R(sm);
-}
-
 __device__ __forceinline__ float fast_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double fast_exp(double x) { return exp(x); }
 
@@ -570,10 +555,12 @@ __device__ __forceinline__ double fast_exp(double x) { return exp(x); }
 // midpoint and composited by Algorithm "Front-to-back compositing" with
 // (1 - alpha_src)^(ds/xi) = exp(-kappa ds).
 // The number of sub-steps is at least n_super and grows with the change of the
-// normalised value n over the step (the transfer function's frequencies set the
-// sampling rate, not the spline), up to 64.
-// fb: the batch's options (n_super, hermite); fv / w: the view's transfer function
-// (FP64 from fv, FP32 from its LDS copy w).
+// normalised value n over the step and with the transfer function's slope over
+// that range of n (the transfer function's frequencies set the sampling rate,
+// not the spline): the transfer function changes by at most tf_step per
+// sub-step, and n by at most dn; up to 128.
+// fb: the batch's options (n_super, hermite, tf_step); fv / w: the view's
+// transfer function (FP64 from fv, FP32 from its LDS copy w).
 template <typename R>
 __device__ __forceinline__ void composite(const FrameParams &fb, const FrameParams &fv, const ViewLds &w,
                                           R ra, R ma, R rb, R mb, R len, R (&C)[3], R &A,
@@ -583,8 +570,23 @@ __device__ __forceinline__ void composite(const FrameParams &fb, const FramePara
     const R inv_range = sizeof(R) == 4 ? R(w.inv_range) : R(fv.tf_inv_ranged);
     const R tdn = sizeof(R) == 4 ? R(w.dn) : R(fv.tf_dn);
     const R span = fmax(fabs(rb - ra), R(0.5) * (fabs(sa) + fabs(sb))) * inv_range;
-    int ns = (int)ceil(span / tdn);
-    ns = ns < fp.n_super ? fp.n_super : (ns > 64 ? 64 : ns);
+    // the largest slope of the transfer function over the interval's range of n
+    // (the Hermite interpolant stays within a quarter of its end slopes' sum)
+    const R lo_r = sizeof(R) == 4 ? R(w.lo) : R(fv.tf_lod);
+    const R na = (ra - lo_r) * inv_range, nb = (rb - lo_r) * inv_range;
+    const R over = R(0.25) * (fabs(sa) + fabs(sb)) * inv_range;
+    const float n_lo = float(fmin(na, nb) - over), n_hi = float(fmax(na, nb) + over);
+    float sm = 0.f;
+#pragma unroll
+    for (int m = 0; m < kMaxTfKnots - 1; ++m) {   // interval m: [x[m], x[m+1]), x[0] = -inf
+        const bool exists = sizeof(R) == 4 || m < fv.tf_n - 1;
+        const float xm = sizeof(R) == 4 ? w.x[m] : fv.tf_x[m];
+        const float xm1 = sizeof(R) == 4 ? w.x[m + 1] : (m + 1 < fv.tf_n - 1 ? fv.tf_x[m + 1] : INFINITY);
+        const float smm = sizeof(R) == 4 ? w.smax[m] : fv.tf_smax[m];
+        if (exists && (m == 0 || xm <= n_hi) && xm1 > n_lo) sm = fmaxf(sm, smm);
+    }
+    int ns = (int)ceil(fmax(span / tdn, span * R(sm) / R(fp.tf_step)));
+    ns = ns < fp.n_super ? fp.n_super : (ns > 128 ? 128 : ns);
     n_sub += (uint32_t)ns;
     const R inv = R(1) / R(ns);
     const R dl = len * inv;

@@ -168,7 +168,8 @@ struct FrameParams {
     float tf_lo, tf_inv_range;
     float tf_dn;                    // target change of n per supersampling sub-step
     float tf_smax[kMaxTfKnots];     // largest |slope| over channels on intervals k-1..k+1
-    float tf_step;                  // largest change of the transfer function per step
+    float tf_step;                  // largest change of the transfer function per sub-step
+    float rho_step;                 // largest change of n (normalised rho) per step
     double tf_xd[kMaxTfKnots];
     double tf_vd[kMaxTfKnots][4];
     double tf_sd[kMaxTfKnots][4];
