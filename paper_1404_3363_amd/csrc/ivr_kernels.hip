@@ -34,6 +34,7 @@ using u64 = unsigned long long;
 constexpr int kFlat = 256;    // candidates solved per pass of the flattened solve
 constexpr int kFragLds = 16;  // crossings per ray kept in LDS (the rest in scratch)
 constexpr int kExtra = 64;    // second roots of one element per pass of the flattened solve
+constexpr int kChunksWave = 64;   // network-query chunks (blocks with candidates) per wave
 
 __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -438,7 +439,6 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     //    first) become Newton seeds; 2. the seeds are solved (a wave's 64 at a
     //    time whatever their rays, in the second launch).
     u32 cand[kCandCap];
-    u32 qidx[MODE == 1 ? kCandCap : 1];
     u32 cpos[MODE == 1 ? kCandCap : 1];   // position in the wave's block-major list
     int ncand = 0;
     // The ray's boundary crossings, unsorted in the order they were found: depth
@@ -498,10 +498,10 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                 const FaceElem E = m.elems[cand[k]];
                 const float ms[3] = {NAN, NAN, NAN};
                 float T1 = -1.f;
+                ++c_newton;
                 for (int s = 0; s < 2; ++s) {   // a second search where the ray is nearly tangent
                     RootRec<R> rr;
                     bool again;
-                    ++c_newton;
                     face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, T1, rr, again, c_iter,
                                      c_pol);
                     add_root(rr);
@@ -553,6 +553,29 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         // The wave's list holds the candidates block after block (lane after lane
         // within a block): a solve round then meets one or two blocks, of one
         // degree, instead of the blocks of a few rays.
+        // With MLP seeds every candidate has one network query, stored at its
+        // position in the list; a block's candidates of the wave form one chunk
+        // (block, tile, first position relative to the wave's base, count) for
+        // the seed kernel.  Chunks gather in LDS and go out kChunksWave at a time
+        // with one atomic (the seed kernel adds the wave's base).  Candidates
+        // whose chunk finds no room keep the box seed (top bit of cpos).
+        __shared__ uint4 s_ch[kChunksWave];
+        u32 nch = 0;
+        bool ch_full = false;
+        const bool mlp = fp.seed_mode == IVR_SEED_MLP;
+        auto flush_chunks = [&]() __attribute__((always_inline)) {
+            u32 cb = 0;
+            if (lane == 0) cb = atomicAdd(&qs->n_chunks, nch);
+            cb = __shfl(cb, 0);
+            __syncthreads();
+            if (cb + nch <= mq.chunk_cap) {
+                for (u32 i = (u32)lane; i < nch; i += 64) mq.chunks[cb + i] = s_ch[i];
+            } else {
+                ch_full = true;   // these and later candidates keep the box seed
+            }
+            __syncthreads();
+            nch = 0;
+        };
         u32 wrun = 0;
         auto block = [&](int pi, int nc0) __attribute__((always_inline)) {
             const u32 nb = (u32)(ncand - nc0);
@@ -560,34 +583,14 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             const u32 incl = wave_incl_scan(nb, lane);
             const u32 total = __shfl(incl, 63);
             for (int k = nc0; k < ncand; ++k) cpos[k] = wrun + incl - nb + (u32)(k - nc0);
+            if (mlp) {
+                if (lane == 0) s_ch[nch] = make_uint4((u32)pi, g, wrun, total);
+                if (++nch == (u32)kChunksWave) flush_chunks();
+            }
             wrun += total;
-            if (fp.seed_mode != IVR_SEED_MLP) return;
-            // one network query per new candidate of this block: the ray's
-            // midpoint in the element's box; the block's queries of this wave
-            // are contiguous and recorded as one chunk
-            u32 qb = 0, cb = 0;
-            if (lane == 63) {
-                qb = atomicAdd(&qs->n_queries, total);
-                cb = atomicAdd(&qs->n_chunks, 1u);
-            }
-            qb = __shfl(qb, 63);
-            cb = __shfl(cb, 63);
-            const bool fits = cb < mq.chunk_cap && qb + total <= mq.q_cap;
-            if (fits && lane == 63) mq.chunks[cb] = make_uint4((u32)pi, qb, total, 0u);
-            u32 q = qb + incl - nb;
-            for (int k = nc0; k < ncand; ++k, ++q) {
-                if (fits) {
-                    const FaceElem &E = m.elems[cand[k]];
-                    float t0, t1;
-                    obb_hit(E, of, df, t0, t1);
-                    const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
-                    mq.query[q] = make_float4(of[0] + tm * df[0], of[1] + tm * df[1], of[2] + tm * df[2], 0.f);
-                    ++c_mlp;
-                }
-                qidx[k] = fits ? q : 0xFFFFFFFFu;
-            }
         };
         traverse(valid, hit, block);
+        if (mlp && nch > 0) flush_chunks();
         // the candidates for the solve pass
         u32 base = 0;
         if (lane == 0 && wrun) base = atomicAdd(&qs->n_cands, wrun);
@@ -597,10 +600,20 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             ncand = 0;
         }
         const u32 excl = wave_incl_scan((u32)ncand, lane) - (u32)ncand;
-        const bool mlp = fp.seed_mode == IVR_SEED_MLP;
+        const bool seeds = mlp && !ch_full;
         for (int k = 0; k < ncand; ++k) {
-            mq.clist[base + cpos[k]] = make_uint2(cand[k] | ((u32)lane << kCandLaneShift), mlp ? qidx[k] : 0xFFFFFFFFu);
-            mq.plist[base + excl + (u32)k] = cpos[k];
+            const u32 pos = cpos[k];
+            const bool q = seeds;
+            if (q) {   // the network's input: the ray's midpoint in the element's box
+                const FaceElem &E = m.elems[cand[k]];
+                float t0, t1;
+                obb_hit(E, of, df, t0, t1);
+                const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
+                mq.query[base + pos] = make_float4(of[0] + tm * df[0], of[1] + tm * df[1], of[2] + tm * df[2], 0.f);
+                ++c_mlp;
+            }
+            mq.clist[base + pos] = make_uint2(cand[k] | ((u32)lane << kCandLaneShift), q ? base + pos : 0xFFFFFFFFu);
+            mq.plist[base + excl + (u32)k] = pos;
         }
         // the wave's base and the lane's count; the top bit asks the solve pass for the rest
         mq.crange[g * 64u + (u32)lane] = make_uint2(base, (u32)ncand | (c_more ? 0x80000000u : 0u));
@@ -648,10 +661,10 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                         ms[0] = s.x; ms[1] = s.y; ms[2] = s.z;
                     }
                     float T1 = -1.f;
+                    ++c_newton;
                     for (int s = 0; s < 2; ++s) {   // a second search where the ray is nearly tangent
                         RootRec<R> out;
                         bool again;
-                        ++c_newton;
                         face_root_any<R>(m, m.patches[E.patch], E, od, odd, of, odf, fp, ms, T1, out, again,
                                          c_iter, c_pol);
                         if (s == 0) {
@@ -856,26 +869,26 @@ __global__ __launch_bounds__(64) void k_mlp_seeds(const uint16_t *wb, const floa
                                                   CandLists mq) {
     __shared__ uint16_t sA[64 * 72];
     __shared__ float sY[64 * 4];
-    __shared__ u32 s_chunk;
     const int lane = threadIdx.x;
     const u32 nch = min(qs->n_chunks, mq.chunk_cap);
-    for (;;) {
-        if (lane == 0) s_chunk = atomicAdd(&qs->next_chunk, 1u);
-        __syncthreads();
-        const u32 ci = s_chunk;
-        __syncthreads();
-        if (ci >= nch) break;
+    // chunks (block, tile, first position relative to the tile's base, count)
+    // dealt round-robin to the waves (no shared cursor to contend on); a wave
+    // whose list did not fit has no queries
+    for (u32 ci = blockIdx.x; ci < nch; ci += gridDim.x) {
         const uint4 ch = mq.chunks[ci];
-        for (u32 r0 = 0; r0 < ch.z; r0 += 64) {
+        const uint2 cr = mq.crange[ch.y * 64u];
+        const u32 first = cr.x + ch.z;
+        if (first + ch.w > mq.c_cap) continue;
+        for (u32 r0 = 0; r0 < ch.w; r0 += 64) {
             const u32 row = r0 + (u32)lane;
-            const bool ok = row < ch.z;
+            const bool ok = row < ch.w;
             float x[3] = {0.f, 0.f, 0.f}, p[3];
             if (ok) {
-                const float4 q = mq.query[ch.y + row];
+                const float4 q = mq.query[first + row];
                 x[0] = q.x; x[1] = q.y; x[2] = q.z;
             }
             mlp_infer_wave(wb, norm, (int)ch.x, x, p, sA, sY);
-            if (ok) mq.seed[ch.y + row] = make_float4(p[0], p[1], p[2], 0.f);
+            if (ok) mq.seed[first + row] = make_float4(p[0], p[1], p[2], 0.f);
         }
     }
 }

@@ -115,18 +115,17 @@ enum Counter : int {
 // Bookkeeping written by the fragment kernel.
 struct QueueState {
     uint32_t seg_total;             // segments requested (may exceed the capacity)
-    uint32_t n_queries;             // MLP seeds: queries, chunks and candidates recorded
-    uint32_t n_chunks;
-    uint32_t n_cands;
-    uint32_t next_chunk;            // next chunk for the seed kernel
-    uint32_t pad[3];
+    uint32_t n_chunks;              // network-query chunks recorded (MLP seeds)
+    uint32_t n_cands;               // candidates recorded
+    uint32_t pad[5];
 };
 
-// Buffers of the two-pass fragment kernel: network queries (world points) and
-// their seeds with MLP seeds, chunks (block, first query, count) of one block's
-// queries from one wave; every wave's candidates block after block (element |
-// owning lane << kCandLaneShift, query), per lane the positions of its own
-// candidates in that list, and per lane the wave's base and its count.
+// Buffers of the two-pass fragment kernel: every wave's candidates block after
+// block (element | owning lane << kCandLaneShift, seed index or ~0), per lane
+// the positions of its own candidates in that list, and per lane the wave's
+// base and its count.  With MLP seeds, a candidate's network query (world
+// point) and seed sit at its position in the list, and chunks (block, first
+// position, count) group one block's queries from one wave.
 constexpr int kCandLaneShift = 26;
 constexpr uint32_t kCandElemMask = (1u << kCandLaneShift) - 1;
 struct CandLists {
