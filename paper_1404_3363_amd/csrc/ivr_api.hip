@@ -64,7 +64,7 @@ struct ivr_ctx {
     uint32_t *d_order = nullptr;         // segment indices sorted by block
     QueueState *d_qs = nullptr;
     // two-pass fragment kernel with MLP seeds (grow-only)
-    CandLists mq = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0};
+    CandLists mq = {nullptr, nullptr, nullptr, nullptr, nullptr, 0};
     size_t mq_tiles = 0;
     // blocks grouped by degree class (the integrators take their segments block by block)
     uint32_t *d_pperm = nullptr, *d_pcount = nullptr, *d_pbase = nullptr, *d_pcur = nullptr;
@@ -561,8 +561,8 @@ static void drop_graphs(ivr_ctx *c) {
 }
 
 static void free_cand_lists(ivr_ctx *c) {
-    dfree(c->mq.query); dfree(c->mq.seed); dfree(c->mq.chunks); dfree(c->mq.clist); dfree(c->mq.plist); dfree(c->mq.crange);
-    c->mq.q_cap = c->mq.chunk_cap = c->mq.c_cap = 0;
+    dfree(c->mq.query); dfree(c->mq.seed); dfree(c->mq.clist); dfree(c->mq.plist); dfree(c->mq.crange);
+    c->mq.c_cap = 0;
     c->mq_tiles = 0;
 }
 
@@ -1027,12 +1027,11 @@ static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
 }
 
 // Buffers of the two-pass fragment kernel: 8 candidates per pixel on average (a
-// lane keeps at most 64), 64 chunks (blocks with candidates) per tile.  Past the
-// chunk and query capacities candidates keep the box seed; rays whose candidates
-// do not fit are traversed again by the solve pass.
+// lane keeps at most 64), with their network queries and seeds.  Rays whose
+// candidates do not fit are traversed again by the solve pass (box seeds).
 static ivr_status ensure_cand_lists(ivr_ctx *c, size_t pixels, size_t tiles) {
     const size_t cap = std::max<size_t>(pixels * 8, 1024);
-    if (tiles <= c->mq_tiles && cap <= c->mq.q_cap) return IVR_OK;
+    if (tiles <= c->mq_tiles && cap <= c->mq.c_cap) return IVR_OK;
     IVR_HIP(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
     free_cand_lists(c);
@@ -1040,16 +1039,13 @@ static ivr_status ensure_cand_lists(ivr_ctx *c, size_t pixels, size_t tiles) {
         return fail(c, IVR_EOVERFLOW, "batch too large for the candidate buffers");
     if (hipMalloc((void **)&c->mq.query, sizeof(float4) * cap) != hipSuccess ||
         hipMalloc((void **)&c->mq.seed, sizeof(float4) * cap) != hipSuccess ||
-        hipMalloc((void **)&c->mq.chunks, sizeof(uint4) * tiles * 64) != hipSuccess ||
         hipMalloc((void **)&c->mq.clist, sizeof(uint2) * cap) != hipSuccess ||
         hipMalloc((void **)&c->mq.plist, sizeof(uint32_t) * cap) != hipSuccess ||
         hipMalloc((void **)&c->mq.crange, sizeof(uint2) * tiles * 64) != hipSuccess) {
         free_cand_lists(c);
         return fail(c, IVR_ENOMEM, "candidate buffer allocation failed");
     }
-    c->mq.q_cap = (uint32_t)cap;
     c->mq.c_cap = (uint32_t)cap;
-    c->mq.chunk_cap = (uint32_t)(tiles * 64);
     c->mq_tiles = tiles;
     return IVR_OK;
 }

@@ -34,7 +34,6 @@ using u64 = unsigned long long;
 constexpr int kFlat = 256;    // candidates solved per pass of the flattened solve
 constexpr int kFragLds = 16;  // crossings per ray kept in LDS (the rest in scratch)
 constexpr int kExtra = 64;    // second roots of one element per pass of the flattened solve
-constexpr int kChunksWave = 64;   // network-query chunks (blocks with candidates) per wave
 
 __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -389,8 +388,8 @@ __device__ __forceinline__ int view_of_tile(const ViewRec *views, int n_views, u
 
 // The fragment pass in two launches.  MODE 1 traverses the block, face, tile
 // and element boxes and records each wave's candidates (elements whose box the
-// ray hits), with MLP seeds one network query each (grouped per block and wave,
-// evaluated by k_mlp_seeds in between).  MODE 2 solves the candidates, pairs the
+// ray hits), with MLP seeds one network query each (evaluated by k_mlp_seeds in
+// between).  MODE 2 solves the candidates, pairs the
 // roots into segments and writes them.
 template <typename R, int MODE>
 __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views, int n_views,
@@ -553,29 +552,10 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         // The wave's list holds the candidates block after block (lane after lane
         // within a block): a solve round then meets one or two blocks, of one
         // degree, instead of the blocks of a few rays.
-        // With MLP seeds every candidate has one network query, stored at its
-        // position in the list; a block's candidates of the wave form one chunk
-        // (block, tile, first position relative to the wave's base, count) for
-        // the seed kernel.  Chunks gather in LDS and go out kChunksWave at a time
-        // with one atomic (the seed kernel adds the wave's base).  Candidates
-        // whose chunk finds no room keep the box seed (top bit of cpos).
-        __shared__ uint4 s_ch[kChunksWave];
-        u32 nch = 0;
-        bool ch_full = false;
+        // With MLP seeds every candidate has one network query (the ray's
+        // midpoint in the element's box, and the element's block), stored at its
+        // position in the list, where the seed kernel leaves its seed.
         const bool mlp = fp.seed_mode == IVR_SEED_MLP;
-        auto flush_chunks = [&]() __attribute__((always_inline)) {
-            u32 cb = 0;
-            if (lane == 0) cb = atomicAdd(&qs->n_chunks, nch);
-            cb = __shfl(cb, 0);
-            __syncthreads();
-            if (cb + nch <= mq.chunk_cap) {
-                for (u32 i = (u32)lane; i < nch; i += 64) mq.chunks[cb + i] = s_ch[i];
-            } else {
-                ch_full = true;   // these and later candidates keep the box seed
-            }
-            __syncthreads();
-            nch = 0;
-        };
         u32 wrun = 0;
         auto block = [&](int pi, int nc0) __attribute__((always_inline)) {
             const u32 nb = (u32)(ncand - nc0);
@@ -583,14 +563,9 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             const u32 incl = wave_incl_scan(nb, lane);
             const u32 total = __shfl(incl, 63);
             for (int k = nc0; k < ncand; ++k) cpos[k] = wrun + incl - nb + (u32)(k - nc0);
-            if (mlp) {
-                if (lane == 0) s_ch[nch] = make_uint4((u32)pi, g, wrun, total);
-                if (++nch == (u32)kChunksWave) flush_chunks();
-            }
             wrun += total;
         };
         traverse(valid, hit, block);
-        if (mlp && nch > 0) flush_chunks();
         // the candidates for the solve pass
         u32 base = 0;
         if (lane == 0 && wrun) base = atomicAdd(&qs->n_cands, wrun);
@@ -600,19 +575,18 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             ncand = 0;
         }
         const u32 excl = wave_incl_scan((u32)ncand, lane) - (u32)ncand;
-        const bool seeds = mlp && !ch_full;
         for (int k = 0; k < ncand; ++k) {
             const u32 pos = cpos[k];
-            const bool q = seeds;
-            if (q) {   // the network's input: the ray's midpoint in the element's box
+            if (mlp) {
                 const FaceElem &E = m.elems[cand[k]];
                 float t0, t1;
                 obb_hit(E, of, df, t0, t1);
                 const float tm = 0.5f * (t0 + fminf(t1, t0 + 4.0f * fp.scale));
-                mq.query[base + pos] = make_float4(of[0] + tm * df[0], of[1] + tm * df[1], of[2] + tm * df[2], 0.f);
+                mq.query[base + pos] = make_float4(of[0] + tm * df[0], of[1] + tm * df[1], of[2] + tm * df[2],
+                                                   __int_as_float(E.patch));
                 ++c_mlp;
             }
-            mq.clist[base + pos] = make_uint2(cand[k] | ((u32)lane << kCandLaneShift), q ? base + pos : 0xFFFFFFFFu);
+            mq.clist[base + pos] = make_uint2(cand[k] | ((u32)lane << kCandLaneShift), mlp ? base + pos : 0xFFFFFFFFu);
             mq.plist[base + excl + (u32)k] = pos;
         }
         // the wave's base and the lane's count; the top bit asks the solve pass for the rest
@@ -863,33 +837,29 @@ struct RKF {
                        e5 = R(1) / R(50), e6 = R(2) / R(55);
 };
 
-// The network seeds of the recorded queries: one wave per chunk (one block, up
-// to 64 queries per call of the wave-wide BF16 MFMA inference), persistent.
-__global__ __launch_bounds__(64) void k_mlp_seeds(const uint16_t *wb, const float *norm, QueueState *qs,
-                                                  CandLists mq) {
+// Network seeds of a frame's candidates: the recorded queries, 64 rows per wave
+// and call in list order (rows of different blocks share a call), the seed
+// written where the query is.  Rows of waves whose lists did not fit carry no
+// query; a block index outside the model marks them.
+__global__ __launch_bounds__(64) void k_mlp_seeds(const uint16_t *wb, const float *norm, int npatch,
+                                                  const QueueState *qs, CandLists mq) {
     __shared__ uint16_t sA[64 * 72];
-    __shared__ float sY[64 * 4];
+    __shared__ float sZ[64 * 65];
+    __shared__ int sQ[64];
     const int lane = threadIdx.x;
-    const u32 nch = min(qs->n_chunks, mq.chunk_cap);
-    // chunks (block, tile, first position relative to the tile's base, count)
-    // dealt round-robin to the waves (no shared cursor to contend on); a wave
-    // whose list did not fit has no queries
-    for (u32 ci = blockIdx.x; ci < nch; ci += gridDim.x) {
-        const uint4 ch = mq.chunks[ci];
-        const uint2 cr = mq.crange[ch.y * 64u];
-        const u32 first = cr.x + ch.z;
-        if (first + ch.w > mq.c_cap) continue;
-        for (u32 r0 = 0; r0 < ch.w; r0 += 64) {
-            const u32 row = r0 + (u32)lane;
-            const bool ok = row < ch.w;
-            float x[3] = {0.f, 0.f, 0.f}, p[3];
-            if (ok) {
-                const float4 q = mq.query[first + row];
-                x[0] = q.x; x[1] = q.y; x[2] = q.z;
-            }
-            mlp_infer_wave(wb, norm, (int)ch.x, x, p, sA, sY);
-            if (ok) mq.seed[first + row] = make_float4(p[0], p[1], p[2], 0.f);
+    const u32 nq = min(qs->n_cands, mq.c_cap);
+    for (u32 r0 = blockIdx.x * 64u; r0 < nq; r0 += gridDim.x * 64u) {
+        const u32 row = r0 + (u32)lane;
+        float x[3] = {0.f, 0.f, 0.f}, p[3];
+        int q = 0;
+        if (row < nq) {
+            const float4 v = mq.query[row];
+            x[0] = v.x; x[1] = v.y; x[2] = v.z;
+            q = __float_as_int(v.w);
         }
+        const bool ok = row < nq && q >= 0 && q < npatch && isfinite(x[0] + x[1] + x[2]);
+        mlp_infer_rows(wb, norm, q, ok, x, p, sA, sZ, sQ);
+        if (ok) mq.seed[row] = make_float4(p[0], p[1], p[2], 0.f);
     }
 }
 
@@ -1320,7 +1290,7 @@ static hipError_t launch_fragments_t(const Model &m, const ViewRec *views, int n
                                      hipStream_t st) {
     hipLaunchKernelGGL((k_fragments<R, 1>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views, n_tiles, lc,
                        (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, mq, ctr);
-    if (mlp) hipLaunchKernelGGL(k_mlp_seeds, dim3(n_cu * 8), dim3(64), 0, st, m.mlp_wb, m.mlp_norm, qs, mq);
+    if (mlp) hipLaunchKernelGGL(k_mlp_seeds, dim3(n_cu * 8), dim3(64), 0, st, m.mlp_wb, m.mlp_norm, m.npatch, qs, mq);
     hipLaunchKernelGGL((k_fragments<R, 2>), dim3(n_tiles), dim3(64), 0, st, m, views, n_views, n_tiles, lc,
                        (Seg<R> *)segs, seg_cap, seg_kr, pcount, qs, pixseg, mq, ctr);
     return hipGetLastError();

@@ -49,78 +49,103 @@ __device__ __forceinline__ void mlp_infer(const uint16_t *wball, const float *no
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// MLP of one block (wave-uniform q) for the 64 points of a wave: layer 1 and 3
-// per lane on the VALU, the 64x64 layer as a 64-row GEMM on
-// v_mfma_f32_16x16x16_bf16 (lane l holds A[l%16][4(l/16)+j], B[4(l/16)+j][l%16],
-// D[4(l/16)+j][l%16]).  sA: 64*72 BF16 and sY: 64*4 floats of LDS owned by the
-// wave.  Every lane of the wave must execute this.
-__device__ __forceinline__ void mlp_infer_wave(const uint16_t *wball, const float *normall, int q,
-                                               const float (&x)[3], float (&p)[3], uint16_t *sA,
-                                               float *sY) {
+// The MLP for the 64 rows of a wave, each row (lane) with its own block q (ok:
+// the row is a query).  Layers 1 and 3 run per lane on the VALU with the row's
+// own weights (16-byte loads); the 64x64 layer runs on v_mfma_f32_16x16x16_bf16
+// once per distinct block among the rows, each row keeping its block's result.
+// LDS owned by the wave: sA 64*72 BF16 (layer-1 activations), sZ 64*65 floats
+// (layer-2 pre-activations), sQ 64 ints.  Every lane of the wave must execute it.
+__device__ __forceinline__ void mlp_infer_rows(const uint16_t *wball, const float *normall, int q, bool ok,
+                                               const float (&x)[3], float (&p)[3], uint16_t *sA, float *sZ,
+                                               int *sQ) {
     const int l = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const int lr16 = l & 15, lg = l >> 4;
-    const uint16_t *wb = wball + (size_t)q * kMlpWbStride;
-    const float *nm = normall + 12 * q;
+    const int qq = ok ? q : 0;
+    const uint16_t *wq = wball + (size_t)qq * kMlpWbStride;
+    const float *nm = normall + 12 * qq;
     const float xh[3] = {(x[0] - nm[6]) * nm[3], (x[1] - nm[7]) * nm[4], (x[2] - nm[8]) * nm[5]};
+    sQ[l] = ok ? q : -1;
     uint32_t *row = reinterpret_cast<uint32_t *>(sA + l * 72);
+#pragma unroll 1
+    for (int n0 = 0; n0 < kMlpH; n0 += 8) {
+        const uint4 w0 = *reinterpret_cast<const uint4 *>(wq + kOffW1 + n0);
+        const uint4 w1 = *reinterpret_cast<const uint4 *>(wq + kOffW1 + 64 + n0);
+        const uint4 w2 = *reinterpret_cast<const uint4 *>(wq + kOffW1 + 128 + n0);
+        const uint4 b1 = *reinterpret_cast<const uint4 *>(wq + kOffB1 + n0);
+        const uint32_t a0[4] = {w0.x, w0.y, w0.z, w0.w}, a1[4] = {w1.x, w1.y, w1.z, w1.w};
+        const uint32_t a2[4] = {w2.x, w2.y, w2.z, w2.w}, bb[4] = {b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
-    for (int n = 0; n < kMlpH; n += 2) {
-        const float h0 = tanh_fast(bf2f(wb[kOffB1 + n]) + xh[0] * bf2f(wb[kOffW1 + n]) +
-                                   xh[1] * bf2f(wb[kOffW1 + 64 + n]) + xh[2] * bf2f(wb[kOffW1 + 128 + n]));
-        const float h1 = tanh_fast(bf2f(wb[kOffB1 + n + 1]) + xh[0] * bf2f(wb[kOffW1 + n + 1]) +
-                                   xh[1] * bf2f(wb[kOffW1 + 64 + n + 1]) + xh[2] * bf2f(wb[kOffW1 + 128 + n + 1]));
-        row[n >> 1] = (uint32_t)f2bf(h0) | ((uint32_t)f2bf(h1) << 16);
+        for (int h = 0; h < 4; ++h) {
+            float v[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int sh = 16 * s;
+                v[s] = tanh_fast(bf2f((uint16_t)(bb[h] >> sh)) + xh[0] * bf2f((uint16_t)(a0[h] >> sh)) +
+                                 xh[1] * bf2f((uint16_t)(a1[h] >> sh)) + xh[2] * bf2f((uint16_t)(a2[h] >> sh)));
+            }
+            row[(n0 >> 1) + h] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+        }
     }
     __syncthreads();
-    f32x4 acc[4][4];
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[rb][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-        bf16x4 a[4], b[4];
+    unsigned long long todo = __ballot(ok);
+    while (todo) {
+        const int b = __builtin_amdgcn_readfirstlane(__shfl(qq, __builtin_ctzll(todo)));
+        const uint16_t *wb = wball + (size_t)b * kMlpWbStride;
+        f32x4 acc[4][4];
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
-            a[rb] = *reinterpret_cast<const bf16x4 *>(sA + (rb * 16 + lr16) * 72 + ks * 16 + 4 * lg);
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-            b[ct] = *reinterpret_cast<const bf16x4 *>(wb + kOffW2T + (ct * 16 + lr16) * 64 + ks * 16 + 4 * lg);
+            for (int ct = 0; ct < 4; ++ct) acc[rb][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int ks = 0; ks < 4; ++ks) {
+            bf16x4 a[4], bm[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+                a[rb] = *reinterpret_cast<const bf16x4 *>(sA + (rb * 16 + lr16) * 72 + ks * 16 + 4 * lg);
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct)
-                acc[rb][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[rb], b[ct], acc[rb][ct], 0, 0, 0);
-    }
+                bm[ct] = *reinterpret_cast<const bf16x4 *>(wb + kOffW2T + (ct * 16 + lr16) * 64 + ks * 16 + 4 * lg);
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+            for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float y[3] = {0.f, 0.f, 0.f};
+                for (int ct = 0; ct < 4; ++ct)
+                    acc[rb][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[rb], bm[ct], acc[rb][ct], 0, 0, 0);
+        }
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                const int n = ct * 16 + lr16;
-                const float h2 = tanh_fast(acc[rb][ct][j] + bf2f(wb[kOffB2 + n]));
+        for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) y[c] += h2 * bf2f(wb[kOffW3 + n * 3 + c]);
+            for (int j = 0; j < 4; ++j) {
+                const int r = rb * 16 + 4 * lg + j;
+                if (sQ[r] == b) {
+#pragma unroll
+                    for (int ct = 0; ct < 4; ++ct) sZ[r * 65 + ct * 16 + lr16] = acc[rb][ct][j];
+                }
             }
+        todo &= ~__ballot(ok && q == b);
+    }
+    __syncthreads();
+    float y[3] = {bf2f(wq[kOffB3]), bf2f(wq[kOffB3 + 1]), bf2f(wq[kOffB3 + 2])};
+#pragma unroll 1
+    for (int n0 = 0; n0 < kMlpH; n0 += 8) {
+        const uint4 b2 = *reinterpret_cast<const uint4 *>(wq + kOffB2 + n0);
+        const uint32_t bb[4] = {b2.x, b2.y, b2.z, b2.w};
+        uint32_t w3[12];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const uint4 t = *reinterpret_cast<const uint4 *>(wq + kOffW3 + 3 * n0 + 8 * v);
+            w3[4 * v] = t.x; w3[4 * v + 1] = t.y; w3[4 * v + 2] = t.z; w3[4 * v + 3] = t.w;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float h2 = tanh_fast(sZ[l * 65 + n0 + i] + bf2f((uint16_t)(bb[i >> 1] >> (16 * (i & 1)))));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                float v = y[c];
-                v += __shfl_xor(v, 1);
-                v += __shfl_xor(v, 2);
-                v += __shfl_xor(v, 4);
-                v += __shfl_xor(v, 8);
-                y[c] = v;
-            }
-            if (lr16 == 0) {
-                const int r = rb * 16 + 4 * lg + j;
-                sY[r * 4] = y[0]; sY[r * 4 + 1] = y[1]; sY[r * 4 + 2] = y[2];
+                const int e = 3 * i + c;   // element of the 24 BF16 of W3 rows n0..n0+7
+                y[c] += h2 * bf2f((uint16_t)(w3[e >> 1] >> (16 * (e & 1))));
             }
         }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 3; ++c) p[c] = sY[l * 4 + c] + bf2f(wb[kOffB3 + c]);
+    }
+    p[0] = y[0]; p[1] = y[1]; p[2] = y[2];
     __syncthreads();
 }
 

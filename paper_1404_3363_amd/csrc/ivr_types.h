@@ -115,27 +115,24 @@ enum Counter : int {
 // Bookkeeping written by the fragment kernel.
 struct QueueState {
     uint32_t seg_total;             // segments requested (may exceed the capacity)
-    uint32_t n_chunks;              // network-query chunks recorded (MLP seeds)
     uint32_t n_cands;               // candidates recorded
-    uint32_t pad[5];
+    uint32_t pad[6];
 };
 
 // Buffers of the two-pass fragment kernel: every wave's candidates block after
 // block (element | owning lane << kCandLaneShift, seed index or ~0), per lane
 // the positions of its own candidates in that list, and per lane the wave's
 // base and its count.  With MLP seeds, a candidate's network query (world
-// point) and seed sit at its position in the list, and chunks (block, first
-// position, count) group one block's queries from one wave.
+// point, block) and seed sit at its position in the list.
 constexpr int kCandLaneShift = 26;
 constexpr uint32_t kCandElemMask = (1u << kCandLaneShift) - 1;
 struct CandLists {
-    float4 *query;
+    float4 *query;            // x, y, z, block (as int bits)
     float4 *seed;
-    uint4 *chunks;
     uint2 *clist;
     uint32_t *plist;
     uint2 *crange;            // per lane of a fragment tile (tile * 64 + lane)
-    uint32_t q_cap, chunk_cap, c_cap;
+    uint32_t c_cap;
 };
 
 // What the integrator of one degree class needs to take its segments block by
