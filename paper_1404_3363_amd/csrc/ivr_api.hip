@@ -645,7 +645,7 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     std::vector<double4> cp64;
     std::vector<double> rho64, knots64;
     std::vector<FaceElem> elems;
-    std::vector<FaceTile> tiles;
+    std::vector<FaceTile> tiles, subs;
     std::vector<float> btab;
     uint32_t class_mask = 0;
     for (int pi = 0; pi < n; ++pi) {
@@ -730,11 +730,20 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
                     FaceTile T;
                     std::memset(&T, 0, sizeof T);
                     T.elem_begin = (int)elems.size();
+                    T.sub_begin = (int)subs.size();
                     std::vector<std::array<double, 3>> tpts;
                     double corner[4][3];
                     const size_t ea1 = std::min(spa.size(), ta + kTile), eb1 = std::min(spb.size(), tb + kTile);
-                    for (size_t ib = tb; ib < eb1; ++ib)
-                        for (size_t ia = ta; ia < ea1; ++ia) {
+                    for (size_t sb0 = tb; sb0 < eb1; sb0 += 2)
+                    for (size_t sa0 = ta; sa0 < ea1; sa0 += 2) {
+                    FaceTile S;
+                    std::memset(&S, 0, sizeof S);
+                    S.elem_begin = (int)elems.size();
+                    std::vector<std::array<double, 3>> spts;
+                    double scorner[4][3];
+                    const size_t sa1 = std::min(ea1, sa0 + 2), sb1 = std::min(eb1, sb0 + 2);
+                    for (size_t ib = sb0; ib < sb1; ++ib)
+                        for (size_t ia = sa0; ia < sa1; ++ia) {
                             const int sa = spa[ia], sb = spb[ib];
                             double net[(kMaxDegree + 1) * (kMaxDegree + 1)][4];
                             bezier_net(tn[da].data(), tn[db].data(), sa, sb, p, hq, net);
@@ -754,19 +763,42 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
                             E.patch = pi;
                             elems.push_back(E);
                             tpts.insert(tpts.end(), pts.begin(), pts.end());
+                            spts.insert(spts.end(), pts.begin(), pts.end());
                             if (ia == ta && ib == tb) std::memcpy(corner[0], pts[0].data(), sizeof corner[0]);
                             if (ia + 1 == ea1 && ib == tb) std::memcpy(corner[1], pts[p].data(), sizeof corner[1]);
                             if (ia == ta && ib + 1 == eb1) std::memcpy(corner[2], pts[p * (p + 1)].data(), sizeof corner[2]);
                             if (ia + 1 == ea1 && ib + 1 == eb1)
                                 std::memcpy(corner[3], pts[(p + 1) * (p + 1) - 1].data(), sizeof corner[3]);
+                            if (ia == sa0 && ib == sb0) std::memcpy(scorner[0], pts[0].data(), sizeof scorner[0]);
+                            if (ia + 1 == sa1 && ib == sb0) std::memcpy(scorner[1], pts[p].data(), sizeof scorner[1]);
+                            if (ia == sa0 && ib + 1 == sb1) std::memcpy(scorner[2], pts[p * (p + 1)].data(), sizeof scorner[2]);
+                            if (ia + 1 == sa1 && ib + 1 == sb1)
+                                std::memcpy(scorner[3], pts[(p + 1) * (p + 1) - 1].data(), sizeof scorner[3]);
                         }
+                    S.elem_end = (int)elems.size();
+                    build_obb(S, spts, scorner[0], scorner[1], scorner[2], scorner[3], pad);
+                    subs.push_back(S);
+                    }
                     T.elem_end = (int)elems.size();
+                    T.sub_end = (int)subs.size();
+                    if (T.sub_end - T.sub_begin <= 1) {   // one sub-tile: the tile itself
+                        subs.resize(T.sub_begin);
+                        T.sub_end = T.sub_begin;
+                    }
                     build_obb(T, tpts, corner[0], corner[1], corner[2], corner[3], pad);
                     tiles.push_back(T);
                 }
         }
         D.elem_off[6] = (int)elems.size();
         D.tile_off[6] = (int)tiles.size();
+    }
+    {   // sub-tiles after all tiles
+        const int off = (int)tiles.size();
+        for (auto &T : tiles) {
+            T.sub_begin += off;
+            T.sub_end += off;
+        }
+        tiles.insert(tiles.end(), subs.begin(), subs.end());
     }
     if (elems.size() > kCandElemMask)
         return fail(c, IVR_EOVERFLOW, "more than 2^26 face elements");

@@ -531,9 +531,19 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                     c_box += hf;
                     const bool ht = hf && obb_hit(T, of, df);
                     if (__ballot(ht) == 0) continue;
-                    for (int e = T.elem_begin; e < T.elem_end; ++e) {
-                        c_box += ht;
-                        on_hit((u32)e, ht && obb_hit(m.elems[e], of, df));
+                    const bool split = T.sub_end > T.sub_begin;
+                    for (int si = split ? T.sub_begin : ti; si < (split ? T.sub_end : ti + 1); ++si) {
+                        const FaceTile &S = m.tiles[si];
+                        bool hs = ht;
+                        if (split) {
+                            c_box += ht;
+                            hs = ht && obb_hit(S, of, df);
+                            if (__ballot(hs) == 0) continue;
+                        }
+                        for (int e = S.elem_begin; e < S.elem_end; ++e) {
+                            c_box += hs;
+                            on_hit((u32)e, hs && obb_hit(m.elems[e], of, df));
+                        }
                     }
                 }
             }

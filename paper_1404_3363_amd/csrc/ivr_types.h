@@ -63,14 +63,18 @@ struct alignas(16) FaceElem {
 };
 
 // Up to kTile x kTile neighbouring elements of one face, with an oriented box
-// around all their Bezier points; its elements are contiguous.
+// around all their Bezier points; its elements are contiguous.  A tile of more
+// than 2 x 2 elements is split into sub-tiles of up to 2 x 2 (records of the
+// same kind, [sub_begin, sub_end) of the tile array, their elements contiguous
+// in the tile's order); otherwise sub_begin == sub_end.
 constexpr int kTile = 4;
 struct alignas(16) FaceTile {
     float c[3];
     float ax[3][3];
     float ext[3];
     int32_t elem_begin, elem_end;
-    int32_t pad[3];
+    int32_t sub_begin, sub_end;
+    int32_t pad;
 };
 
 template <typename R>
