@@ -296,3 +296,29 @@ def test_error_codes(renderer):
     with pytest.raises(IvrError) as e:
         renderer.render(sc.cameras[0], bad_tf)
     assert e.value.code == -1
+    for opt in ({"rho_step": 0.0}, {"tf_step": -1.0}, {"rho_step": float("nan")}, {"h_max": float("inf")}):
+        with pytest.raises(IvrError) as e:
+            renderer.render(sc.cameras[0], sc.tf, **opt)
+        assert e.value.code == -1, opt
+
+
+def test_sampling_options_follow_their_definitions(renderer):
+    """h_max and rho_step bound the RK steps, tf_step the supersampling sub-steps:
+    tighter bounds take more steps / sub-steps and the image stays within the bar."""
+    sc = make_config(3, 160, 90)
+    cam = sc.cameras[0]
+    ref_pix = np.arange(0, 160 * 90, 37)
+    ref = oracle.render(sc, cam, sc.tf, pixels=ref_pix)
+    runs = {}
+    for name, kw in (("default", {}), ("h_max/4", {"h_max": sc.scale / 128}),
+                     ("rho_step/4", {"rho_step": 0.025}), ("tf_step/4", {"tf_step": 0.00625})):
+        img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32", **kw)
+        err = float(np.abs(img[ref_pix] - ref.rgba).max())
+        print(f"[parity] sampling {name}: rk steps {st['rk_steps']} sub-steps {st['subsamples']} "
+              f"max err {err:.2e}", flush=True)
+        assert err <= RGBA_TOL
+        runs[name] = st
+    assert runs["h_max/4"]["rk_steps"] > 1.5 * runs["default"]["rk_steps"]
+    assert runs["rho_step/4"]["rk_steps"] >= runs["default"]["rk_steps"]
+    assert runs["tf_step/4"]["rk_steps"] == runs["default"]["rk_steps"]
+    assert runs["tf_step/4"]["subsamples"] > 1.5 * runs["default"]["subsamples"]
