@@ -123,10 +123,11 @@ typedef struct {
     uint64_t segments;          /* entry/exit pairs integrated                   */
     uint64_t fragments;         /* boundary crossings kept                       */
     uint64_t anomalies;         /* crossings left unpaired by the pairing        */
-    uint64_t fragment_overflow; /* crossings or seeds dropped (fixed capacities)  */
+    uint64_t fragment_overflow; /* crossings dropped (fixed capacities)           */
     uint64_t segment_overflow;  /* segments dropped (per-pixel capacity)         */
     uint64_t box_tests;         /* ray/box slab tests                            */
-    uint64_t face_newton;       /* face Newton solves started                    */
+    uint64_t face_newton;       /* candidates solved (face Newton started; a
+                                   second search on one element counts once)    */
     uint64_t face_newton_iter;  /* FP32 face Newton iterations                   */
     uint64_t fp64_polish_iter;  /* FP64 refinement iterations                    */
     uint64_t rk_steps;          /* RKF45 attempts (6 evaluations of W each)      */
