@@ -14,6 +14,10 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ __forceinline__ float tanh_fast(float x) { return 1.0f - 2.0f / (__expf(2.0f * x) + 1.0f); }
+// for inference: the hardware reciprocal (about 1 ulp) instead of a division
+__device__ __forceinline__ float tanh_infer(float x) {
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * x) + 1.0f);
+}
 
 // PCG hash (Jarzynski & Olano, "Hash Functions for GPU Rendering", JCGT 2020).
 __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
@@ -80,7 +84,7 @@ __device__ __forceinline__ void mlp_infer_rows(const uint16_t *wball, const floa
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int sh = 16 * s;
-                v[s] = tanh_fast(bf2f((uint16_t)(bb[h] >> sh)) + xh[0] * bf2f((uint16_t)(a0[h] >> sh)) +
+                v[s] = tanh_infer(bf2f((uint16_t)(bb[h] >> sh)) + xh[0] * bf2f((uint16_t)(a0[h] >> sh)) +
                                  xh[1] * bf2f((uint16_t)(a1[h] >> sh)) + xh[2] * bf2f((uint16_t)(a2[h] >> sh)));
             }
             row[(n0 >> 1) + h] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
@@ -137,7 +141,7 @@ __device__ __forceinline__ void mlp_infer_rows(const uint16_t *wball, const floa
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const float h2 = tanh_fast(sZ[l * 65 + n0 + i] + bf2f((uint16_t)(bb[i >> 1] >> (16 * (i & 1)))));
+            const float h2 = tanh_infer(sZ[l * 65 + n0 + i] + bf2f((uint16_t)(bb[i >> 1] >> (16 * (i & 1)))));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int e = 3 * i + c;   // element of the 24 BF16 of W3 rows n0..n0+7
