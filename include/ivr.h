@@ -140,6 +140,7 @@ typedef struct {
     uint64_t subsamples;        /* supersampling sub-steps (transfer function)   */
     uint64_t degenerate;        /* segment ends with singular J (|det J| below
                                    det_fp64_threshold), shrunk by Eq. (degeneracyfix) */
+    uint64_t mlp_restarts;      /* shrunk entries whose Newton the network seeded */
     double ms_fragments, ms_integrate, ms_merge;  /* event times per phase      */
 } ivr_stats;
 

@@ -978,7 +978,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     // stays on the ray, so V keeps its meaning)
     int shrink = 0, newton_it = 0;
     R delta = 0, rho_in = 0;
-    u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_cap = 0, c_sub = 0, c_deg = 0;
+    u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_cap = 0, c_sub = 0, c_deg = 0, c_mlp = 0;
 
     for (;;) {   // blocks
         if (threadIdx.x == 0) {
@@ -1145,6 +1145,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     gin[c] += delta * d[c];
                     p[c] = clamp01(sg.p_in[c] + eps * (nrm > R(0) ? dp[c] : R(0.5) - sg.p_in[c]));
                 }
+                // with MLP seeds the first Newton of the restart starts from the
+                // block's network at the new entry (the offset above if that fails)
+                if (fp.seed_mode == IVR_SEED_MLP) {
+                    float pm[3];
+                    mlp_seed_at(m.mlp_wb, m.mlp_norm, blk, float(gin[0]), float(gin[1]), float(gin[2]), pm);
+                    if (isfinite(pm[0] + pm[1] + pm[2])) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) p[c] = clamp01(R(pm[c]));
+                        ++c_mlp;
+                    }
+                }
             }
             rho_prev = rho_cur;
             m_prev = m_cur;
@@ -1246,6 +1257,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         flush_counter(ctr, C_RK_ITER_CAP, c_cap);
         flush_counter(ctr, C_SUBSAMPLES, c_sub);
         flush_counter(ctr, C_DEGENERATE, c_deg);
+        flush_counter(ctr, C_MLP_RESTARTS, c_mlp);
     }
 }
 

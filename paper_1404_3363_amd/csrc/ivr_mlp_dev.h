@@ -50,6 +50,16 @@ __device__ __forceinline__ void mlp_infer(const uint16_t *wball, const float *no
     p[0] = y[0]; p[1] = y[1]; p[2] = y[2];
 }
 
+// The network's guess of the parameter point of world point x in block q, out
+// of line: the integrator calls it only to seed a rare Newton restart.
+__device__ __attribute__((noinline)) void mlp_seed_at(const uint16_t *wball, const float *normall, int q,
+                                                      float x0, float x1, float x2, float *p) {
+    const float x[3] = {x0, x1, x2};
+    float r[3];
+    mlp_infer(wball, normall, q, x, r);
+    p[0] = r[0]; p[1] = r[1]; p[2] = r[2];
+}
+
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 

@@ -113,7 +113,8 @@ struct Model {
 enum Counter : int {
     C_RAYS = 0, C_SEGMENTS, C_FRAGMENTS, C_ANOMALIES, C_FRAG_OVF, C_SEG_OVF, C_BOX_TESTS,
     C_FACE_NEWTON, C_FACE_NEWTON_ITER, C_FP64_POLISH, C_RK_STEPS, C_RK_REJECTED, C_SAMPLES,
-    C_W_EVALS, C_FP64_SOLVES, C_RK_ITER_CAP, C_MLP_QUERIES, C_SUBSAMPLES, C_DEGENERATE, C_COUNT
+    C_W_EVALS, C_FP64_SOLVES, C_RK_ITER_CAP, C_MLP_QUERIES, C_SUBSAMPLES, C_DEGENERATE,
+    C_MLP_RESTARTS, C_COUNT
 };
 
 // Bookkeeping written by the fragment kernel.

@@ -68,7 +68,8 @@ class TuneReport(C.Structure):
 STAT_FIELDS = ["rays", "segments", "fragments", "anomalies", "fragment_overflow",
                "segment_overflow", "box_tests", "face_newton", "face_newton_iter",
                "fp64_polish_iter", "rk_steps", "rk_rejected", "samples", "w_evals",
-               "fp64_solves", "rk_iter_cap", "mlp_queries", "subsamples", "degenerate"]
+               "fp64_solves", "rk_iter_cap", "mlp_queries", "subsamples", "degenerate",
+               "mlp_restarts"]
 
 
 class MlpOpts(C.Structure):

@@ -38,7 +38,7 @@ def test_struct_layouts_match_header():
     from paper_1404_3363_amd import ivr
     assert ctypes.sizeof(ivr.PatchDesc) == 6 * 4 + 3 * 8 + 8 + 8 + 8
     assert ctypes.sizeof(ivr.CameraDesc) == 10 * 8 + 8
-    assert ctypes.sizeof(ivr.Stats) == 19 * 8 + 3 * 8
+    assert ctypes.sizeof(ivr.Stats) == 20 * 8 + 3 * 8
     # ivr_view: camera, tf pointer, model (padded), two device pointers
     assert ctypes.sizeof(ivr.ViewDesc) == 88 + 8 + 8 + 8 + 8
     assert ivr.ViewDesc.model.offset == 96 and ivr.ViewDesc.rgba_dev.offset == 104

@@ -119,3 +119,31 @@ def test_mlp_seeded_render_matches_oracle(renderer, trained_c4):
         assert st["anomalies"] == 0
     it = {m: out[m][1]["face_newton_iter"] / max(out[m][1]["face_newton"], 1) for m in out}
     assert it["mlp"] < it["plain"]
+
+
+def test_mlp_seeds_the_restart_at_degenerate_entries(renderer):
+    """With MLP seeds the network also seeds the Newton restart at a shrunk
+    degenerate entry (Eq. (degeneracyfix)); the image still matches the oracle."""
+    import torch
+    from scenes import make_degenerate
+    sc = make_degenerate()
+    cam = sc.cameras[0]
+    renderer.upload(sc.patches)
+    renderer.train_mlp()
+    out = {}
+    for mode in ("box", "mlp"):
+        rgba, depth, st = renderer.render(cam, sc.tf, stats=True, seed_mode=mode)
+        torch.cuda.synchronize()
+        out[mode] = (rgba.cpu().numpy().reshape(-1, 4).astype(np.float64), st)
+        print(f"[mlp] degenerate entries, seed {mode}: shrunk {st['degenerate']}, "
+              f"network restarts {st['mlp_restarts']}", flush=True)
+    assert out["box"][1]["mlp_restarts"] == 0
+    assert out["mlp"][1]["mlp_restarts"] > 100
+    rng = np.random.default_rng(53)
+    cov = np.flatnonzero(out["box"][0][:, 3] > 0)
+    pix = np.unique(rng.choice(cov, 300, replace=False))
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    for mode, (img, st) in out.items():
+        err = np.abs(img[pix] - ref.rgba).max()
+        print(f"[mlp] degenerate entries, seed {mode}: max |rgba - oracle| = {err:.2e}", flush=True)
+        assert err <= 1e-3
