@@ -92,12 +92,12 @@ struct Frag {
 // The parameter point of a crossing: face parameters (a, b) on the face of info.
 template <typename R>
 __device__ __forceinline__ void face_point(uint32_t info, R a, R b, R (&p)[3]) {
-    const int face = (int)((info >> 1) & 7u);
-    int dn, da, db;
-    face_dirs(face, dn, da, db);
-    p[dn] = (face & 1) ? R(1) : R(0);
-    p[da] = a;
-    p[db] = b;
+    const int face = (int)((info >> 1) & 7u), dn = face >> 1;
+    const R pn = (face & 1) ? R(1) : R(0);
+    // (a, b) are the two other directions in increasing order
+    p[0] = dn == 0 ? pn : a;
+    p[1] = dn == 0 ? a : (dn == 1 ? pn : b);
+    p[2] = dn == 2 ? pn : b;
 }
 
 // A root of one candidate, handed from the lane that solved it to the lane that
@@ -151,11 +151,11 @@ __device__ __forceinline__ int facing(int face, float orient, const R (&Sa)[3], 
 // Newton on S_f(a,b) - (o + t d) = 0 (Eqs. (F), (newtonsmethod) restricted to
 // the face) in precision RN from (a, b); true when it converges.
 template <int P, bool RAT, typename RN>
-__device__ __forceinline__ bool face_newton(const PatchView<RN> &pv, const Arrays<RN> &ar, int face,
+__device__ __forceinline__ bool face_newton(const FaceView<RN> &fv, const Arrays<RN> &ar,
                                             const RN (&o)[3], const RN (&d)[3], RN tol, int max_it,
                                             RN &a, RN &b, RN &t, RN (&Sa)[3], RN (&Sb)[3], u32 &n_iter) {
     RN S[3];
-    eval_face<P, RAT, RN>(pv, ar, face, a, b, S, Sa, Sb);
+    eval_face<P, RAT, RN>(fv, ar, a, b, S, Sa, Sb);
     t = (S[0] - o[0]) * d[0] + (S[1] - o[1]) * d[1] + (S[2] - o[2]) * d[2];
     for (int it = 0; it < max_it; ++it) {
         ++n_iter;
@@ -169,7 +169,7 @@ __device__ __forceinline__ bool face_newton(const PatchView<RN> &pv, const Array
         b += st[1];
         t += st[2];
         if (!(a >= RN(-1) && a <= RN(2) && b >= RN(-1) && b <= RN(2))) return false;
-        eval_face<P, RAT, RN>(pv, ar, face, a, b, S, Sa, Sb);
+        eval_face<P, RAT, RN>(fv, ar, a, b, S, Sa, Sb);
     }
     return false;
 }
@@ -194,7 +194,7 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
                           const FrameParams &fp, const float (&mseed)[3], float T1, RootRec<RN> &out,
                           bool &again, u32 &n_iter, u32 &n_polish) {
     const int face = E.face;
-    const PatchView<RN> pv = view_of<RN>(Pd);
+    const FaceView<RN> fv = face_view<RN>(Pd, face);
     const Arrays<RN> ar = arrays_of(m, RN(0));
     const RN o[3] = {RN(od[0]), RN(od[1]), RN(od[2])}, d[3] = {RN(dd[0]), RN(dd[1]), RN(dd[2])};
     const RN tol = (sizeof(RN) == 4 ? RN(2e-6) : RN(1e-12)) * RN(fp.scaled);
@@ -211,7 +211,7 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
     const bool tangent = fabsf(E.ax[2][0] * df[0] + E.ax[2][1] * df[1] + E.ax[2][2] * df[2]) < E.graze;
     const bool second = T1 >= 0.f;
     const double tsame = 2e-5 * fp.scaled;   // one crossing
-    const PatchView<double> pv64 = view_of<double>(Pd);
+    const FaceView<double> fv64 = face_view<double>(Pd, face);
     const Arrays<double> ar64 = arrays_of(m, 0.0);
     const double tol64 = 1e-12 * fp.scaled;
     const int s_begin = second ? 6 : (fp.seed_mode == IVR_SEED_PLAIN ? 1 : 0);
@@ -233,8 +233,8 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
 #pragma unroll
             for (int q = 0; q < 3; ++q) x[q] = of[q] + tm * df[q];
             if (seed == 0 && fp.seed_mode == IVR_SEED_MLP && isfinite(mseed[0])) {
-                a = RN(clamp01(mseed[da]));
-                b = RN(clamp01(mseed[db]));
+                a = RN(clamp01(da == 0 ? mseed[0] : mseed[1]));
+                b = RN(clamp01(db == 1 ? mseed[1] : mseed[2]));
             } else {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) x[q] -= E.c[q];
@@ -250,7 +250,7 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
             a = ac + ha * RN((seed & 1) ? -0.5 : 0.5);
             b = bc + hb * RN((seed & 2) ? -0.5 : 0.5);
         }
-        if (!face_newton<P, RAT, RN>(pv, ar, face, o, d, tol, fp.max_newton, a, b, t, Sa, Sb, n_iter)) continue;
+        if (!face_newton<P, RAT, RN>(fv, ar, o, d, tol, fp.max_newton, a, b, t, Sa, Sb, n_iter)) continue;
         const RN mg = RN(1e-4);
         if (!(a >= -mg && a <= RN(1) + mg && b >= -mg && b <= RN(1) + mg && t > RN(0))) {
             if (second) continue;
@@ -269,7 +269,7 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
         double A = a, B = b, T = t, S2[3], F2[3], Sa2[3], Sb2[3];
         bool ok = false;
         for (int k = 0; k < 4; ++k) {
-            eval_face<P, RAT, double, false>(pv64, ar64, face, A, B, S2, Sa2, Sb2);
+            eval_face<P, RAT, double, false>(fv64, ar64, A, B, S2, Sa2, Sb2);
 #pragma unroll
             for (int q = 0; q < 3; ++q) F2[q] = S2[q] - od[q] - T * dd[q];
             const double r2 = dot3(F2, F2);
@@ -294,7 +294,7 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
             }
             if (sab > 1e-4) {
                 RN S[3];
-                eval_face<P, RAT, RN>(pv, ar, face, RN(A), RN(B), S, Sa, Sb);
+                eval_face<P, RAT, RN>(fv, ar, RN(A), RN(B), S, Sa, Sb);
             }
         }
         // A crossing is a root on the closed face up to 1e-9 in (a, b): the refined

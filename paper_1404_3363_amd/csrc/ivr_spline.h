@@ -312,26 +312,59 @@ __device__ __forceinline__ void face_dirs(int face, int &dn, int &da, int &db) {
     db = dn == 2 ? 1 : 2;
 }
 
+// Face f of a block as the face evaluator needs it: along the in-face directions
+// (a, b) the control-point counts, spans, open-uniform flags, knot offsets and
+// control-point strides, and the index of the face layer's first control point.
+// Taken once per face from the block record in global memory: a private copy of
+// the block's per-direction arrays, indexed by the face's runtime directions,
+// would live in scratch memory.
+template <typename R>
+struct FaceView {
+    int na, nb, nsa, nsb;
+    bool ua, ub;
+    R inva, invb;
+    int koa, kob;
+    int stra, strb;
+    int base;
+};
+
+template <typename R>
+__device__ __forceinline__ FaceView<R> face_view(const DevPatch &P, int face) {
+    int dn, da, db;
+    face_dirs(face, dn, da, db);
+    FaceView<R> f;
+    f.na = P.n[da];
+    f.nb = P.n[db];
+    f.nsa = P.nspan[da];
+    f.nsb = P.nspan[db];
+    f.ua = (P.uniform >> da) & 1;
+    f.ub = (P.uniform >> db) & 1;
+    f.inva = R(1) / R(f.nsa);
+    f.invb = R(1) / R(f.nsb);
+    f.koa = P.knot_off[da];
+    f.kob = P.knot_off[db];
+    const int n0 = P.n[0], n01 = P.n[0] * P.n[1];
+    f.stra = da == 0 ? 1 : n0;     // da is 0 or 1
+    f.strb = db == 1 ? n0 : n01;   // db is 1 or 2
+    const int strn = dn == 0 ? 1 : (dn == 1 ? n0 : n01);
+    f.base = P.cp_off + ((face & 1) ? (P.n[dn] - 1) * strn : 0);
+    return f;
+}
+
 // S(a,b), dS/da, dS/db on face f: the bivariate spline of the boundary layer.
 // Outside [0,1]^2 the polynomial of the nearest boundary span is continued, so
 // Newton iterates may leave the face and come back.
 // With DERIV false only S is computed (Sa, Sb are left untouched).
 template <int P, bool RAT, typename R, bool DERIV = true>
-__device__ __forceinline__ void eval_face(const PatchView<R> &pv, const Arrays<R> &ar, int face,
-                                          R a, R b, R (&S)[3], R (&Sa)[3], R (&Sb)[3]) {
-    int dn, da, db;
-    face_dirs(face, dn, da, db);
+__device__ __forceinline__ void eval_face(const FaceView<R> &fv, const Arrays<R> &ar, R a, R b,
+                                          R (&S)[3], R (&Sa)[3], R (&Sb)[3]) {
     R ta[2 * P], tb[2 * P];
-    const int sa = span_knots<P>(a, pv.n[da], pv.nspan[da], pv.inv_nspan[da], (pv.uniform >> da) & 1,
-                                 ar.knots + pv.knot_off[da], ta);
-    const int sb = span_knots<P>(b, pv.n[db], pv.nspan[db], pv.inv_nspan[db], (pv.uniform >> db) & 1,
-                                 ar.knots + pv.knot_off[db], tb);
+    const int sa = span_knots<P>(a, fv.na, fv.nsa, fv.inva, fv.ua, ar.knots + fv.koa, ta);
+    const int sb = span_knots<P>(b, fv.nb, fv.nsb, fv.invb, fv.ub, ar.knots + fv.kob, tb);
     R Na[P + 1], dNa[P + 1], Nb[P + 1], dNb[P + 1];
     basis_d1<P, R, true>(a, ta, Na, dNa);
     basis_d1<P, R, true>(b, tb, Nb, dNb);
-    const int stride[3] = {1, pv.n[0], pv.n[0] * pv.n[1]};
-    const int fix = (face & 1) ? pv.n[dn] - 1 : 0;
-    const int base = pv.cp_off + fix * stride[dn] + (sa - P) * stride[da] + (sb - P) * stride[db];
+    const int base = fv.base + (sa - P) * fv.stra + (sb - P) * fv.strb;
     constexpr int NC = RAT ? 4 : 3;
     R H[NC], Ha[NC], Hb[NC];
 #pragma unroll
@@ -344,7 +377,7 @@ __device__ __forceinline__ void eval_face(const PatchView<R> &pv, const Arrays<R
 #pragma unroll
         for (int ia = 0; ia <= P; ++ia) {
             R v[4];
-            load_cp<R>(ar.cp[base + ia * stride[da] + jb * stride[db]], v);
+            load_cp<R>(ar.cp[base + ia * fv.stra + jb * fv.strb], v);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 A0[c] += Na[ia] * v[c];
