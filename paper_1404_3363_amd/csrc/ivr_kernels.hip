@@ -120,7 +120,7 @@ __device__ __forceinline__ bool obb_hit(const Box3 &E, const float (&o)[3], cons
     for (int r = 0; r < 3; ++r) {
         const float po = E.ax[r][0] * oc[0] + E.ax[r][1] * oc[1] + E.ax[r][2] * oc[2];
         const float pd = E.ax[r][0] * d[0] + E.ax[r][1] * d[1] + E.ax[r][2] * d[2];
-        const float inv = __fdividef(1.0f, pd);
+        const float inv = __builtin_amdgcn_rcpf(pd);
         const float t0 = (-E.ext[r] - po) * inv, t1 = (E.ext[r] - po) * inv;
         tmin = fmaxf(tmin, fminf(t0, t1));
         tmax = fminf(tmax, fmaxf(t0, t1));
@@ -128,10 +128,23 @@ __device__ __forceinline__ bool obb_hit(const Box3 &E, const float (&o)[3], cons
     return tmin <= tmax;
 }
 
+// The test alone: per axis the slab's interval is -po/pd -+ ext/|pd| (ext >= 0),
+// one product and two FMAs with the reciprocal's absolute value.  Boxes are
+// padded well beyond the FP32 rounding of either form.
 template <typename Box3>
 __device__ __forceinline__ bool obb_hit(const Box3 &E, const float (&o)[3], const float (&d)[3]) {
-    float t0, t1;
-    return obb_hit(E, o, d, t0, t1);
+    const float oc[3] = {o[0] - E.c[0], o[1] - E.c[1], o[2] - E.c[2]};
+    float tmin = 0.f, tmax = INFINITY;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const float po = E.ax[r][0] * oc[0] + E.ax[r][1] * oc[1] + E.ax[r][2] * oc[2];
+        const float pd = E.ax[r][0] * d[0] + E.ax[r][1] * d[1] + E.ax[r][2] * d[2];
+        const float inv = __builtin_amdgcn_rcpf(pd);
+        const float mid = -po * inv, ai = fabsf(inv);
+        tmin = fmaxf(tmin, fmaf(-E.ext[r], ai, mid));
+        tmax = fminf(tmax, fmaf(E.ext[r], ai, mid));
+    }
+    return tmin <= tmax;
 }
 
 // Front facing: the sign of (J^-1 d) along the face's inward normal.  By

@@ -61,6 +61,11 @@ __device__ __forceinline__ PatchView<R> view_of(const DevPatch &P) {
     return v;
 }
 
+// 1 / w of a rational point: in FP32 the hardware reciprocal (1 ulp), in FP64
+// the correctly rounded quotient.
+__device__ __forceinline__ float inv_weight(float w) { return __builtin_amdgcn_rcpf(w); }
+__device__ __forceinline__ double inv_weight(double w) { return 1.0 / w; }
+
 // a / b from the hardware reciprocal.  FP32: the reciprocal (1 ulp) times a.
 __device__ __forceinline__ float div_fast(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 // FP64: hardware reciprocal refined by one Newton step (relative error ~1e-16).
@@ -272,7 +277,7 @@ __device__ __forceinline__ void eval_volume(const PatchView<R> &pv, const Arrays
         }
     }
     if (RAT) {
-        const R iw = R(1) / X[NC - 1];
+        const R iw = inv_weight(X[NC - 1]);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             x[r] = X[r] * iw;
@@ -394,7 +399,7 @@ __device__ __forceinline__ void eval_face(const FaceView<R> &fv, const Arrays<R>
         }
     }
     if (RAT) {
-        const R iw = R(1) / H[NC - 1];
+        const R iw = inv_weight(H[NC - 1]);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             S[r] = H[r] * iw;
