@@ -685,6 +685,9 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
         D.btab_len = (int)btab.size() - D.btab_off;
         const int n0 = P.ncp[0], n1 = P.ncp[1], n2 = P.ncp[2];
         const size_t N = (size_t)n0 * n1 * n2;
+        // the face evaluator addresses the nets by 32-bit byte offsets (32 B per FP64 point)
+        if (cp32.size() + N > ((size_t)1 << 27))
+            return fail(c, IVR_EOVERFLOW, "more than 2^27 control points");
         Box pb;
         for (size_t q = 0; q < N; ++q) {
             const double *cc = P.cp + 4 * q;

@@ -182,6 +182,13 @@ __device__ __forceinline__ int basis_tab(const float *tab_d, R u_in, int n, int 
     return e + P;
 }
 
+// Element i of an array under 4 GiB, addressed by a 32-bit byte offset from the
+// array's base: one offset computation per load instead of a 64-bit one.
+template <typename T>
+__device__ __forceinline__ const T &at_off32(const T *base, uint32_t i) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (uint32_t)sizeof(T));
+}
+
 template <typename R>
 __device__ __forceinline__ void load_cp(const typename CpType<R>::T &c, R (&v)[4]) {
     v[0] = c.x; v[1] = c.y; v[2] = c.z; v[3] = c.w;
@@ -344,8 +351,13 @@ __device__ __forceinline__ FaceView<R> face_view(const DevPatch &P, int face) {
     f.nsb = P.nspan[db];
     f.ua = (P.uniform >> da) & 1;
     f.ub = (P.uniform >> db) & 1;
-    f.inva = R(1) / R(f.nsa);
-    f.invb = R(1) / R(f.nsb);
+    if constexpr (sizeof(R) == 4) {   // the block record holds 1 / spans in FP32
+        f.inva = P.inv_nspan[da];
+        f.invb = P.inv_nspan[db];
+    } else {
+        f.inva = R(1) / R(f.nsa);
+        f.invb = R(1) / R(f.nsb);
+    }
     f.koa = P.knot_off[da];
     f.kob = P.knot_off[db];
     const int n0 = P.n[0], n01 = P.n[0] * P.n[1];
@@ -382,7 +394,7 @@ __device__ __forceinline__ void eval_face(const FaceView<R> &fv, const Arrays<R>
 #pragma unroll
         for (int ia = 0; ia <= P; ++ia) {
             R v[4];
-            load_cp<R>(ar.cp[base + ia * fv.stra + jb * fv.strb], v);
+            load_cp<R>(at_off32(ar.cp, (uint32_t)(base + ia * fv.stra + jb * fv.strb)), v);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 A0[c] += Na[ia] * v[c];
