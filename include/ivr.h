@@ -114,6 +114,12 @@ typedef struct {
     double rho_step;            /* largest change of rho per step, as a
                                    fraction of the transfer function's domain:
                                    limits h where rho changes fast     [0.1] */
+    int32_t cand_per_pixel;     /* capacity of the candidate list (element
+                                   boxes a ray hits, solved 64 at a time across
+                                   rays) per pixel on average, 0..64: the rays
+                                   of a 64-pixel tile whose candidates do not
+                                   fit are traversed again and solved ray by
+                                   ray (0: every ray); same image       [8]   */
 } ivr_render_opts;
 
 /* Counters of one render (filled when a non-NULL ivr_stats* is passed; that

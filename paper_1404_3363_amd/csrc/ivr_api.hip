@@ -504,6 +504,7 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->timing = 0;
     o->tf_step = 0.025;
     o->rho_step = 0.1;
+    o->cand_per_pixel = 8;
 }
 
 ivr_status ivr_create(ivr_ctx **out, int32_t device, void *hip_stream) {
@@ -1061,11 +1062,11 @@ static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
     return IVR_OK;
 }
 
-// Buffers of the two-pass fragment kernel: 8 candidates per pixel on average (a
-// lane keeps at most 64), with their network queries and seeds.  Rays whose
+// Buffers of the two-pass fragment kernel: `want` candidates (a lane keeps at
+// most 64), with their network queries and seeds; at least 1024.  Rays whose
 // candidates do not fit are traversed again by the solve pass (box seeds).
-static ivr_status ensure_cand_lists(ivr_ctx *c, size_t pixels, size_t tiles) {
-    const size_t cap = std::max<size_t>(pixels * 8, 1024);
+static ivr_status ensure_cand_lists(ivr_ctx *c, size_t want, size_t tiles) {
+    const size_t cap = std::max<size_t>(want, 1024);
     if (tiles <= c->mq_tiles && cap <= c->mq.c_cap) return IVR_OK;
     IVR_HIP(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
@@ -1127,6 +1128,7 @@ struct Batch {
     int n = 0;
     uint32_t n_tiles = 0, n_pixels = 0, class_mask = 0;
     bool fp64 = false, mlp = false, collect = false;
+    uint32_t c_cap = 0;   // candidates the fragment launches may record
 };
 }  // namespace
 
@@ -1174,7 +1176,13 @@ static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr
     b.n_pixels = (uint32_t)pixels;
     st = ensure_frame(c, pixels, b.fp64);
     if (st != IVR_OK) return st;
-    return ensure_cand_lists(c, pixels, tiles);
+    if (o.cand_per_pixel < 0 || o.cand_per_pixel > kCandCap)
+        return fail(c, IVR_EINVAL, "cand_per_pixel outside 0..64");
+    const size_t want = (size_t)pixels * (size_t)o.cand_per_pixel;
+    st = ensure_cand_lists(c, want, tiles);
+    if (st != IVR_OK) return st;
+    b.c_cap = (uint32_t)want;   // <= the allocation
+    return IVR_OK;
 }
 
 // The launches of one batch: clear, fragments, one integrator per degree class, merge.
@@ -1183,9 +1191,11 @@ static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const LaunchCfg &lc, 
     const Model m = device_model(c);
     IVR_HIP(c, launch_clear(c->d_qs, c->d_ctr, b.collect, c->d_pcount, c->npatch, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[0], s));
+    CandLists mq = c->mq;
+    mq.c_cap = b.c_cap;
     IVR_HIP(c, launch_fragments(b.fp64, b.mlp, m, c->d_views, b.n, b.n_tiles, lc, c->d_segs,
                                 (uint32_t)c->seg_cap, c->d_seg_kr, c->d_pcount, c->d_qs, c->d_pixseg,
-                                c->mq, c->d_ctr, c->n_cu, s));
+                                mq, c->d_ctr, c->n_cu, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[1], s));
     IVR_HIP(c, launch_block_sort(c->d_qs, (uint32_t)c->seg_cap, c->d_seg_kr, c->d_pperm, c->npatch,
                                  c->d_pcount, c->d_pbase, c->d_pcur, c->d_order, c->n_cu, s));

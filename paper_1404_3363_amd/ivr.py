@@ -51,7 +51,8 @@ class RenderOpts(C.Structure):
                 ("det_fp64_threshold", C.c_double), ("max_fragments", C.c_int32),
                 ("seed_mode", C.c_int32), ("early_term", C.c_double),
                 ("max_newton_iter", C.c_int32), ("rho_interp", C.c_int32),
-                ("timing", C.c_int32), ("tf_step", C.c_double), ("rho_step", C.c_double)]
+                ("timing", C.c_int32), ("tf_step", C.c_double), ("rho_step", C.c_double),
+                ("cand_per_pixel", C.c_int32)]
 
 
 class ViewDesc(C.Structure):

@@ -254,6 +254,33 @@ def test_every_ray_pairs_cleanly_at_1080p(renderer, k):
         assert st["anomalies"] == 0 and st["fragment_overflow"] == 0 and st["segment_overflow"] == 0
 
 
+@pytest.mark.parametrize("k,cpp", [(2, 0), (3, 0), (3, 1), (4, 0)])
+def test_rays_past_the_candidate_list_traverse_again(renderer, k, cpp):
+    """Rays whose candidates do not fit the candidate list are traversed again
+    by the solve launch and solved ray by ray (cand_per_pixel 0: every ray; 1:
+    the tiles recorded after the list fills).  The same candidates give the same
+    roots: crossings, segments and image agree with the list path, and a sample
+    agrees with the oracle."""
+    sc = make_config(k)
+    cam = sc.cameras[0]
+    img0, d0, st0 = _render(renderer, sc.patches, cam, sc.tf, precision="fp32")
+    img1, d1, st1 = _render(renderer, sc.patches, cam, sc.tf, precision="fp32", cand_per_pixel=cpp)
+    print(f"[parity] config{k} cand_per_pixel={cpp}: candidates {st1['face_newton']} "
+          f"(list path {st0['face_newton']}), box tests {st1['box_tests']} ({st0['box_tests']}), "
+          f"max|rgba - list path| {np.abs(img1 - img0).max():.3e}", flush=True)
+    for key in ("face_newton", "fragments", "segments"):
+        assert st1[key] == st0[key], key
+    assert st1["box_tests"] > st0["box_tests"]   # the second traversal ran
+    assert st1["anomalies"] == 0 and st1["fragment_overflow"] == 0 and st1["segment_overflow"] == 0
+    assert np.abs(img1 - img0).max() <= 1e-5
+    hit = np.isfinite(d0)
+    assert (np.isfinite(d1) == hit).all()
+    assert (np.abs(d1[hit] - d0[hit]) <= 1e-6 * d0[hit]).all()
+    pix = _sample(cam, d1, 256, 128, 50 + k)
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    _compare(f"config{k} cand_per_pixel={cpp}", img1, d1, ref, pix, sc.scale)
+
+
 @pytest.mark.parametrize("size", [(1, 1), (67, 35), (8, 8)])
 def test_ragged_and_tiny_images(renderer, size):
     sc = make_config(1)
@@ -296,7 +323,8 @@ def test_error_codes(renderer):
     with pytest.raises(IvrError) as e:
         renderer.render(sc.cameras[0], bad_tf)
     assert e.value.code == -1
-    for opt in ({"rho_step": 0.0}, {"tf_step": -1.0}, {"rho_step": float("nan")}, {"h_max": float("inf")}):
+    for opt in ({"rho_step": 0.0}, {"tf_step": -1.0}, {"rho_step": float("nan")}, {"h_max": float("inf")},
+                {"cand_per_pixel": -1}, {"cand_per_pixel": 65}):
         with pytest.raises(IvrError) as e:
             renderer.render(sc.cameras[0], sc.tf, **opt)
         assert e.value.code == -1, opt
