@@ -1172,6 +1172,9 @@ static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr
     }
     if (pixels * kSegCap > 0xFFFFFFFFull || tiles > 0x7FFFFFFFull)
         return fail(c, IVR_EOVERFLOW, "batch too large for 32-bit segment indices");
+    int nint = 0;
+    for (int v = 0; v < n; ++v) nint = std::max(nint, c->h_views[v].fp.tf_n - 2);
+    for (int v = 0; v < n; ++v) c->h_views[v].fp.tf_nint_max = nint;
     b.n_tiles = (uint32_t)tiles;
     b.n_pixels = (uint32_t)pixels;
     st = ensure_frame(c, pixels, b.fp64);

@@ -576,17 +576,27 @@ __device__ __forceinline__ void view_stage(const ViewRec *views, int n_views, Vi
     __syncthreads();
 }
 
-// Interval of n: the number of interior knots at or below it.
-__device__ __forceinline__ int tf_interval(const ViewLds &w, float n) {
-    int k = 0;
-#pragma unroll
-    for (int m = 1; m < kMaxTfKnots - 1; ++m) k += n >= w.x[m] ? 1 : 0;
-    return k;
+// Interval of n: the number of interior knots at or below it, from the sign
+// bits of n - x (n - x >= +0 exactly when n >= x; a +inf slot gives -inf), with
+// no compares.  nint (uniform): the most interior knots of any view of the
+// batch; the slots past a view's own knots hold +inf.
+__device__ __forceinline__ int tf_interval(const ViewLds &w, float n, int nint) {
+    static_assert(kMaxTfKnots == 16, "interior knot slots 1..14");
+    auto below = [&](int m) __attribute__((always_inline)) -> uint32_t {
+        return __float_as_uint(n - w.x[m]) >> 31;
+    };
+    uint32_t lt = below(1) + below(2) + below(3) + below(4) + below(5) + below(6);
+    int slots = 6;
+    if (nint > 6) {
+        lt += below(7) + below(8) + below(9) + below(10) + below(11) + below(12) + below(13) + below(14);
+        slots = 14;
+    }
+    return slots - (int)lt;
 }
 
-__device__ __forceinline__ void tf_eval(const ViewLds &w, float rho, float (&out)[4]) {
+__device__ __forceinline__ void tf_eval(const ViewLds &w, float rho, float (&out)[4], int nint) {
     const float n = clamp01((rho - w.lo) * w.inv_range);
-    const int k = tf_interval(w, n);
+    const int k = tf_interval(w, n, nint);
     const float4 a = w.a[k], b = w.b[k];
     out[0] = a.x + b.x * n;
     out[1] = a.y + b.y * n;
@@ -646,7 +656,7 @@ __device__ __forceinline__ void composite(const FrameParams &fb, const FramePara
         const R rho = (R(2) * t3 - R(3) * t2 + R(1)) * ra + (t3 - R(2) * t2 + tau) * sa +
                       (R(3) * t2 - R(2) * t3) * rb + (t3 - t2) * sb;
         R e[4];
-        if constexpr (sizeof(R) == 4) tf_eval(w, rho, e);
+        if constexpr (sizeof(R) == 4) tf_eval(w, rho, e, fb.tf_nint_max);
         else tf_eval(fv, rho, e);
         const R T = fast_exp(-e[3] * dl);
         const R w = (R(1) - T) * (R(1) - A);

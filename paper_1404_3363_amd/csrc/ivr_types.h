@@ -163,6 +163,7 @@ struct FrameParams {
     int32_t width, height;
     // transfer function: knots x[k] and per-interval value/slope
     int32_t tf_n;
+    int32_t tf_nint_max;            // most interior knots of any view of the batch
     float tf_x[kMaxTfKnots];
     float tf_v[kMaxTfKnots][4];     // value at knot k (RGB, kappa = extinction*A)
     float tf_s[kMaxTfKnots][4];     // slope on [x_k, x_{k+1}]
