@@ -1321,7 +1321,8 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
     // the graph holds every kernel argument except what the view table carries
     // (cameras, transfer functions, output pointers): key it by the rest
     std::vector<int64_t> key = {(int64_t)c->generation, b.n, b.fp64, b.mlp, (int64_t)b.class_mask,
-                                c->lc.tile_w, c->lc.xcd_chunk, c->lc.int_block, c->lc.int_waves_cu};
+                                c->lc.tile_w, c->lc.xcd_chunk, c->lc.int_block, c->lc.int_waves_cu,
+                                (int64_t)b.c_cap};
     for (int v = 0; v < n_views; ++v) {
         key.push_back(hv[v].cam->width);
         key.push_back(hv[v].cam->height);
