@@ -127,6 +127,33 @@ def test_batched_views_workload_matches_oracle(renderer):
     print(f"[batch] config5 worst |rgba - oracle| over all views: {worst:.2e}", flush=True)
 
 
+def test_transfer_functions_with_many_knots(renderer):
+    """A 16-knot transfer function (14 interior knots, the most a view holds),
+    alone against the oracle, and in one batch with an 8-knot view: the batch
+    counts every sample's interval over the knot slots its views use, and each
+    view's image equals its render alone."""
+    import torch
+    from scenes import random_tf
+    c1 = make_config(1)
+    cam = c1.cameras[0]
+    tf16 = random_tf(np.random.default_rng(7101), c1.tf.extinction, c1.tf.domain, n_knots=16)
+    renderer.upload_models([c1.patches])
+    (alone16,), st = renderer.render_batch([(cam, tf16, 0)], stats=True)
+    (alone8,) = renderer.render_batch([(cam, c1.tf, 0)])
+    both = renderer.render_batch([(cam, c1.tf, 0), (cam, tf16, 0)])
+    torch.cuda.synchronize()
+    img = _np(alone16[0]).reshape(-1, 4)
+    ref = oracle.render(c1, cam, tf16)
+    err = float(np.abs(img - ref.rgba).max())
+    print(f"[batch] 16-knot transfer function {cam.width}x{cam.height}: segments {st['segments']}, "
+          f"max|rgba - oracle| {err:.3e}", flush=True)
+    assert (ref.n_anomalies == 0).all() and st["anomalies"] == 0
+    assert err <= 1e-3
+    for (a_rgba, a_depth), (b_rgba, b_depth) in ((alone8, both[0]), (alone16, both[1])):
+        assert np.array_equal(_np(a_rgba), _np(b_rgba))
+        assert np.array_equal(_np(a_depth), _np(b_depth))
+
+
 def test_mlp_seeded_batch_matches_oracle(renderer):
     """The batched-views workload at 1/16 resolution with MLP seeds (networks
     trained for all 768 blocks of both models): the two-pass fragment kernel with
