@@ -121,6 +121,26 @@ def test_mlp_seeded_render_matches_oracle(renderer, trained_c4):
     assert it["mlp"] < it["plain"]
 
 
+def test_mlp_rays_past_the_candidate_list_use_box_seeds(renderer, trained_c4):
+    """With MLP seeds, rays whose candidates do not fit the list are solved ray
+    by ray from box seeds (no network query): with an empty list no query is
+    made, and the same crossings give the MLP-seeded render's image."""
+    import torch
+    sc, _ = trained_c4
+    cam = sc.cameras[0]
+    a, da, sa = renderer.render(cam, sc.tf, stats=True, seed_mode="mlp")
+    b, db, sb = renderer.render(cam, sc.tf, stats=True, seed_mode="mlp", cand_per_pixel=0)
+    torch.cuda.synchronize()
+    a, b = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+    print(f"[mlp] cand_per_pixel=0: mlp queries {sb['mlp_queries']} (list path {sa['mlp_queries']}), "
+          f"max|rgba - list path| {np.abs(a - b).max():.3e}", flush=True)
+    assert sa["mlp_queries"] > 0 and sb["mlp_queries"] == 0
+    for key in ("face_newton", "fragments", "segments"):
+        assert sb[key] == sa[key], key
+    assert sb["anomalies"] == 0
+    assert np.abs(a - b).max() <= 1e-5
+
+
 def test_mlp_seeds_the_restart_at_degenerate_entries(renderer):
     """With MLP seeds the network also seeds the Newton restart at a shrunk
     degenerate entry (Eq. (degeneracyfix)); the image still matches the oracle."""
