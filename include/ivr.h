@@ -186,6 +186,27 @@ ivr_status ivr_render(ivr_ctx *ctx, const ivr_camera *cam, const ivr_transfer_fn
                       const ivr_render_opts *opts, float *rgba_dev, float *depth_dev,
                       ivr_stats *stats);
 
+/* ivr_render for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same image, but every frame buffer (segments, candidate
+ * list, block order, per-segment results, counters, the view record) is carved
+ * out of one fixed 256 MiB device array per GPU, set up by ivr_create and held
+ * until the process ends.  The call allocates nothing, host or device (a
+ * non-NULL stats uses the context's pinned staging and events).
+ *   - At most 1048576 pixels per call and 65536 blocks in the model, else
+ *     IVR_EOVERFLOW with nothing launched; opts->timing must be 0 (IVR_EINVAL).
+ *   - Segment slots are what the array holds after the fixed parts (about 2.3
+ *     per pixel at 1024x1024, more for smaller views): segments beyond them are
+ *     dropped and counted in stats->segment_overflow.  Candidate-list capacity
+ *     is capped likewise (rays past it are traversed again; same image).
+ *   - Every call on one GPU, from any context, uses that GPU's one array: calls
+ *     whose work overlaps on the device (different streams, no ordering) race
+ *     and must be serialised by the caller.  Calls on one stream are ordered.
+ * Arguments, outputs and errors otherwise as ivr_render. */
+ivr_status ivr_render_noalloc(ivr_ctx *ctx, const ivr_camera *cam, const ivr_transfer_fn *tf,
+                              const ivr_render_opts *opts, float *rgba_dev, float *depth_dev,
+                              ivr_stats *stats);
+
 /* One view of a batch: camera, transfer function (NULL: the batch's), the model
  * it looks at (index into the models of the last upload) and its caller-owned
  * device outputs, laid out as for ivr_render. */

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -72,6 +73,8 @@ struct ivr_ctx {
     int cls_max_cp[kClasses] = {0};      // largest control net of the class
     int cls_max_tab[kClasses] = {0};     // largest basis tables of the class (floats)
     unsigned long long *d_ctr = nullptr;
+    unsigned long long *h_ctr = nullptr;  // pinned staging of the counters (stats)
+    unsigned char *scratch = nullptr;     // this device's scratch array (ivr_render_noalloc)
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // phase events of renders recorded with opts.timing (4 per render)
     std::vector<hipEvent_t> tev;
@@ -81,6 +84,18 @@ struct ivr_ctx {
     MlpState mlp = {nullptr, nullptr, nullptr, nullptr, nullptr};
     bool mlp_trained = false;
 };
+
+// Scratch memory of ivr_render_noalloc: one fixed array per GPU, held until the
+// process ends.  In host code the array's name is not a device address; the
+// address comes from hipGetSymbolAddress on each device (at ivr_create, with the
+// device current) and is kept per device.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr uint32_t kNoAllocMaxPixels = 1u << 20;
+constexpr int kNoAllocMaxBlocks = 1 << 16;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kMaxDevices];
 
 namespace {
 
@@ -507,6 +522,8 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->cand_per_pixel = 8;
 }
 
+static ivr_status ensure_views(ivr_ctx *c, int n);
+
 ivr_status ivr_create(ivr_ctx **out, int32_t device, void *hip_stream) {
     if (!out) return IVR_EINVAL;
     *out = nullptr;
@@ -536,6 +553,25 @@ ivr_status ivr_create(ivr_ctx **out, int32_t device, void *hip_stream) {
         hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
         ivr_destroy(c);
         return IVR_EDEVICE;
+    }
+    // the view table and the pinned counter staging exist from the start, so that
+    // ivr_render_noalloc allocates nothing
+    if (hipHostMalloc((void **)&c->h_ctr, sizeof(unsigned long long) * C_COUNT) != hipSuccess ||
+        ensure_views(c, 8) != IVR_OK) {
+        ivr_destroy(c);
+        return IVR_ENOMEM;
+    }
+    if (device < kMaxDevices) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+                ivr_destroy(c);
+                return IVR_EDEVICE;
+            }
+            g_scratch_ptr[device] = static_cast<unsigned char *>(p);
+        }
+        c->scratch = g_scratch_ptr[device];
     }
     *out = c;
     return IVR_OK;
@@ -585,6 +621,7 @@ void ivr_destroy(ivr_ctx *c) {
     dfree(c->d_ctr);
     dfree(c->d_views);
     if (c->h_views) (void)hipHostFree(c->h_views);
+    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->views_copied) (void)hipEventDestroy(c->views_copied);
     if (c->capture) (void)hipStreamDestroy(c->capture);
     for (auto &e : c->ev)
@@ -1132,14 +1169,29 @@ struct Batch {
 };
 }  // namespace
 
-// Validates the views, fills the pinned view table and sizes the frame buffers.
-static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr_render_opts &o,
-                                bool collect, const LaunchCfg &lc, Batch &b) {
+// Device buffers of one frame: the context's grow-only buffers, or the carve-up of
+// the scratch array used by ivr_render_noalloc.
+struct FrameBufs {
+    void *segs = nullptr;
+    size_t seg_cap = 0;
+    float4 *results = nullptr;
+    uint2 *pixseg = nullptr, *seg_kr = nullptr;
+    uint32_t *order = nullptr;
+    QueueState *qs = nullptr;
+    unsigned long long *ctr = nullptr;
+    uint32_t *pcount = nullptr, *pbase = nullptr, *pcur = nullptr;
+    CandLists mq = {nullptr, nullptr, nullptr, nullptr, nullptr, 0};   // c_cap: what may be recorded
+    ViewRec *views = nullptr;
+};
+
+// Validates the views and fills the pinned view table (at most view_cap views);
+// sizes of the batch in b.  Allocates nothing.
+static ivr_status fill_views(ivr_ctx *c, const HostView *hv, int n, const ivr_render_opts &o,
+                             bool collect, const LaunchCfg &lc, Batch &b) {
     if (!c->has_model) return fail(c, IVR_ESTATE, "no model uploaded");
     if (n < 1 || n > 64) return fail(c, IVR_EINVAL, "a batch holds 1..64 views");
+    if (n > c->view_cap) return fail(c, IVR_EINVAL, "more views than the view table holds");
     IVR_HIP(c, hipSetDevice(c->device));
-    ivr_status st = ensure_views(c, n);
-    if (st != IVR_OK) return st;
     // the staging buffer is still being read by the previous batch's copy
     IVR_HIP(c, hipEventSynchronize(c->views_copied));
     b = Batch();
@@ -1156,7 +1208,7 @@ static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr
         const auto &M = c->models[hv[v].model];
         ViewRec &r = c->h_views[v];
         std::memset(&r, 0, sizeof r);
-        st = make_frame(c, hv[v].cam, hv[v].tf, o, M.scale, r.fp);
+        ivr_status st = make_frame(c, hv[v].cam, hv[v].tf, o, M.scale, r.fp);
         if (st != IVR_OK) return st;
         r.fp.collect = collect ? 1 : 0;
         r.patch_begin = M.begin;
@@ -1170,73 +1222,98 @@ static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr
         pixels += (uint64_t)hv[v].cam->width * hv[v].cam->height;
         b.class_mask |= M.class_mask;
     }
-    if (pixels * kSegCap > 0xFFFFFFFFull || tiles > 0x7FFFFFFFull)
-        return fail(c, IVR_EOVERFLOW, "batch too large for 32-bit segment indices");
+    if (pixels > 0xFFFFFFFFull || tiles > 0x3FFFFFFull)
+        return fail(c, IVR_EOVERFLOW, "batch too large for 32-bit pixel and lane indices");
+    if (o.cand_per_pixel < 0 || o.cand_per_pixel > kCandCap)
+        return fail(c, IVR_EINVAL, "cand_per_pixel outside 0..64");
     int nint = 0;
     for (int v = 0; v < n; ++v) nint = std::max(nint, c->h_views[v].fp.tf_n - 2);
     for (int v = 0; v < n; ++v) c->h_views[v].fp.tf_nint_max = nint;
     b.n_tiles = (uint32_t)tiles;
     b.n_pixels = (uint32_t)pixels;
-    st = ensure_frame(c, pixels, b.fp64);
+    return IVR_OK;
+}
+
+// The context's own frame buffers for batch b (grown as needed).
+static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr_render_opts &o,
+                                bool collect, const LaunchCfg &lc, Batch &b, FrameBufs &fb) {
+    if (n < 1 || n > 64) return fail(c, IVR_EINVAL, "a batch holds 1..64 views");
+    ivr_status st = ensure_views(c, n);
     if (st != IVR_OK) return st;
-    if (o.cand_per_pixel < 0 || o.cand_per_pixel > kCandCap)
-        return fail(c, IVR_EINVAL, "cand_per_pixel outside 0..64");
-    const size_t want = (size_t)pixels * (size_t)o.cand_per_pixel;
-    st = ensure_cand_lists(c, want, tiles);
+    st = fill_views(c, hv, n, o, collect, lc, b);
+    if (st != IVR_OK) return st;
+    if ((uint64_t)b.n_pixels * kSegCap > 0xFFFFFFFFull)
+        return fail(c, IVR_EOVERFLOW, "batch too large for 32-bit segment indices");
+    st = ensure_frame(c, b.n_pixels, b.fp64);
+    if (st != IVR_OK) return st;
+    const size_t want = (size_t)b.n_pixels * (size_t)o.cand_per_pixel;
+    st = ensure_cand_lists(c, want, b.n_tiles);
     if (st != IVR_OK) return st;
     b.c_cap = (uint32_t)want;   // <= the allocation
+    fb = FrameBufs();
+    fb.segs = c->d_segs;
+    fb.seg_cap = c->seg_cap;
+    fb.results = c->d_results;
+    fb.pixseg = c->d_pixseg;
+    fb.seg_kr = c->d_seg_kr;
+    fb.order = c->d_order;
+    fb.qs = c->d_qs;
+    fb.ctr = c->d_ctr;
+    fb.pcount = c->d_pcount;
+    fb.pbase = c->d_pbase;
+    fb.pcur = c->d_pcur;
+    fb.mq = c->mq;
+    fb.mq.c_cap = b.c_cap;
+    fb.views = c->d_views;
     return IVR_OK;
 }
 
 // The launches of one batch: clear, fragments, one integrator per degree class, merge.
-static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const LaunchCfg &lc, hipEvent_t *ev,
-                               hipStream_t s) {
+static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const FrameBufs &fb, const LaunchCfg &lc,
+                               hipEvent_t *ev, hipStream_t s) {
     const Model m = device_model(c);
-    IVR_HIP(c, launch_clear(c->d_qs, c->d_ctr, b.collect, c->d_pcount, c->npatch, s));
+    IVR_HIP(c, launch_clear(fb.qs, fb.ctr, b.collect, fb.pcount, c->npatch, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[0], s));
-    CandLists mq = c->mq;
-    mq.c_cap = b.c_cap;
-    IVR_HIP(c, launch_fragments(b.fp64, b.mlp, m, c->d_views, b.n, b.n_tiles, lc, c->d_segs,
-                                (uint32_t)c->seg_cap, c->d_seg_kr, c->d_pcount, c->d_qs, c->d_pixseg,
-                                mq, c->d_ctr, c->n_cu, s));
+    IVR_HIP(c, launch_fragments(b.fp64, b.mlp, m, fb.views, b.n, b.n_tiles, lc, fb.segs, (uint32_t)fb.seg_cap,
+                                fb.seg_kr, fb.pcount, fb.qs, fb.pixseg, fb.mq, fb.ctr, c->n_cu, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[1], s));
-    IVR_HIP(c, launch_block_sort(c->d_qs, (uint32_t)c->seg_cap, c->d_seg_kr, c->d_pperm, c->npatch,
-                                 c->d_pcount, c->d_pbase, c->d_pcur, c->d_order, c->n_cu, s));
+    IVR_HIP(c, launch_block_sort(fb.qs, (uint32_t)fb.seg_cap, fb.seg_kr, c->d_pperm, c->npatch, fb.pcount,
+                                 fb.pbase, fb.pcur, fb.order, c->n_cu, s));
     for (int k = 0; k < kClasses; ++k) {
         if (!((b.class_mask >> k) & 1)) continue;
         IntegrateArgs ia;
-        ia.order = c->d_order;
+        ia.order = fb.order;
         ia.pperm = c->d_pperm;
         ia.q_begin = c->cls_q[k];
         ia.q_end = c->cls_q[k + 1];
-        ia.pbase = c->d_pbase;
-        ia.pcount = c->d_pcount;
-        ia.pcur = c->d_pcur;
+        ia.pbase = fb.pbase;
+        ia.pcount = fb.pcount;
+        ia.pcur = fb.pcur;
         ia.max_cp = c->cls_max_cp[k];
         ia.max_tab = c->cls_max_tab[k];
-        IVR_HIP(c, launch_integrate(b.fp64, k, m, c->d_views, b.n, c->d_segs, ia, c->d_results, c->d_ctr,
-                                    c->n_cu, lc, s));
+        IVR_HIP(c, launch_integrate(b.fp64, k, m, fb.views, b.n, fb.segs, ia, fb.results, fb.ctr, c->n_cu, lc, s));
     }
     if (ev) IVR_HIP(c, hipEventRecord(ev[2], s));
-    IVR_HIP(c, launch_merge(c->d_views, b.n, b.n_pixels, c->d_pixseg, c->d_results, s));
+    IVR_HIP(c, launch_merge(fb.views, b.n, b.n_pixels, fb.pixseg, fb.results, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[3], s));
     return IVR_OK;
 }
 
-static ivr_status copy_views(ivr_ctx *c, int n) {
-    IVR_HIP(c, hipMemcpyAsync(c->d_views, c->h_views, sizeof(ViewRec) * n, hipMemcpyHostToDevice,
-                              c->stream));
+static ivr_status copy_views(ivr_ctx *c, int n, ViewRec *dst) {
+    IVR_HIP(c, hipMemcpyAsync(dst, c->h_views, sizeof(ViewRec) * n, hipMemcpyHostToDevice, c->stream));
     IVR_HIP(c, hipEventRecord(c->views_copied, c->stream));
     return IVR_OK;
 }
 
-static ivr_status read_stats(ivr_ctx *c, ivr_stats *stats) {
-    unsigned long long h[C_COUNT];
-    IVR_HIP(c, hipMemcpyAsync(h, c->d_ctr, sizeof h, hipMemcpyDeviceToHost, c->stream));
+// Counters of the last render (fb.ctr) into *stats through the pinned staging
+// buffer, and the phase times from the stats events.  Waits for the stream.
+static ivr_status read_stats(ivr_ctx *c, const unsigned long long *ctr, ivr_stats *stats) {
+    IVR_HIP(c, hipMemcpyAsync(c->h_ctr, ctr, sizeof(unsigned long long) * C_COUNT, hipMemcpyDeviceToHost,
+                              c->stream));
     IVR_HIP(c, hipStreamSynchronize(c->stream));
     std::memset(stats, 0, sizeof *stats);
     uint64_t *dst = &stats->rays;
-    for (int k = 0; k < C_COUNT; ++k) dst[k] = h[k];
+    for (int k = 0; k < C_COUNT; ++k) dst[k] = c->h_ctr[k];
     float ms;
     IVR_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
     stats->ms_fragments = ms;
@@ -1269,16 +1346,17 @@ static ivr_status pick_events(ivr_ctx *c, bool stats, bool timing, hipEvent_t *&
 static ivr_status render_direct(ivr_ctx *c, const HostView *hv, int n, const ivr_render_opts &o,
                                 ivr_stats *stats, const LaunchCfg &lc) {
     Batch b;
-    ivr_status st = prepare_batch(c, hv, n, o, stats != nullptr, lc, b);
+    FrameBufs fb;
+    ivr_status st = prepare_batch(c, hv, n, o, stats != nullptr, lc, b, fb);
     if (st != IVR_OK) return st;
     hipEvent_t *ev;
     st = pick_events(c, stats != nullptr, o.timing != 0, ev);
     if (st != IVR_OK) return st;
-    st = copy_views(c, n);
+    st = copy_views(c, n, fb.views);
     if (st != IVR_OK) return st;
-    st = launch_batch(c, b, lc, ev, c->stream);
+    st = launch_batch(c, b, fb, lc, ev, c->stream);
     if (st != IVR_OK) return st;
-    if (stats) return read_stats(c, stats);
+    if (stats) return read_stats(c, fb.ctr, stats);
     return IVR_OK;
 }
 
@@ -1293,6 +1371,80 @@ ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *
     ivr_status st = render_direct(c, &hv, 1, o, stats, c->lc);
     if (st == IVR_OK) c->err.clear();
     return st;
+}
+
+// ivr_render without allocation: the frame buffers are carved out of this
+// device's scratch array.  Every call on the device shares the array.
+ivr_status ivr_render_noalloc(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *tf,
+                              const ivr_render_opts *opts, float *rgba_dev, float *depth_dev,
+                              ivr_stats *stats) {
+    if (!c) return IVR_EINVAL;
+    if (!rgba_dev) return fail(c, IVR_EINVAL, "rgba_dev is NULL");
+    if (!c->scratch) return fail(c, IVR_EDEVICE, "no scratch array on this device");
+    ivr_render_opts o;
+    ivr_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.timing) return fail(c, IVR_EINVAL, "timing events are not available without allocation");
+    if (cam && (uint64_t)cam->width * (uint64_t)cam->height > kNoAllocMaxPixels)
+        return fail(c, IVR_EOVERFLOW, "more than 1048576 pixels for the scratch array");
+    if (c->has_model && c->npatch > kNoAllocMaxBlocks)
+        return fail(c, IVR_EOVERFLOW, "more than 65536 blocks for the scratch array");
+    const HostView hv = {cam, tf, 0, rgba_dev, depth_dev};
+    Batch b;
+    ivr_status st = fill_views(c, &hv, 1, o, stats != nullptr, c->lc, b);
+    if (st != IVR_OK) return st;
+    // carve the array: fixed parts first, then a quarter of the rest for the
+    // candidate list and the remainder for segment slots
+    unsigned char *const base = c->scratch;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> unsigned char * {
+        off = (off + 255) & ~size_t(255);
+        unsigned char *p = base + off;
+        off += bytes;
+        return p;
+    };
+    FrameBufs fb;
+    fb.views = reinterpret_cast<ViewRec *>(take(sizeof(ViewRec)));
+    fb.qs = reinterpret_cast<QueueState *>(take(sizeof(QueueState)));
+    fb.ctr = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * C_COUNT));
+    fb.pcount = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * c->npatch));
+    fb.pbase = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * c->npatch));
+    fb.pcur = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * c->npatch));
+    fb.pixseg = reinterpret_cast<uint2 *>(take(sizeof(uint2) * b.n_pixels));
+    fb.mq.crange = reinterpret_cast<uint2 *>(take(sizeof(uint2) * 64 * (size_t)b.n_tiles));
+    const size_t slack = 8 * 256;   // alignment of the arrays still to come
+    if (off + slack >= kScratchBytes) return fail(c, IVR_EOVERFLOW, "view too large for the scratch array");
+    const size_t rest = kScratchBytes - off - slack;
+    const size_t cand_bytes = sizeof(uint2) + sizeof(uint32_t) + (b.mlp ? 2 * sizeof(float4) : 0);
+    const size_t c_cap = std::min<size_t>((size_t)b.n_pixels * (size_t)o.cand_per_pixel, rest / 4 / cand_bytes);
+    fb.mq.clist = reinterpret_cast<uint2 *>(take(sizeof(uint2) * c_cap));
+    fb.mq.plist = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * c_cap));
+    if (b.mlp) {
+        fb.mq.query = reinterpret_cast<float4 *>(take(sizeof(float4) * c_cap));
+        fb.mq.seed = reinterpret_cast<float4 *>(take(sizeof(float4) * c_cap));
+    }
+    fb.mq.c_cap = (uint32_t)c_cap;
+    const size_t seg_bytes = b.fp64 ? sizeof(Seg<double>) : sizeof(Seg<float>);
+    const size_t slot = seg_bytes + sizeof(float4) + sizeof(uint2) + sizeof(uint32_t);
+    const size_t left = kScratchBytes - std::min(kScratchBytes, off + slack);
+    fb.seg_cap = std::min<size_t>((size_t)b.n_pixels * kSegCap, left / slot);
+    fb.segs = take(seg_bytes * fb.seg_cap);
+    fb.results = reinterpret_cast<float4 *>(take(sizeof(float4) * fb.seg_cap));
+    fb.seg_kr = reinterpret_cast<uint2 *>(take(sizeof(uint2) * fb.seg_cap));
+    fb.order = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * fb.seg_cap));
+    if (off > kScratchBytes || fb.seg_cap == 0)
+        return fail(c, IVR_EOVERFLOW, "view too large for the scratch array");
+    b.c_cap = (uint32_t)c_cap;
+    st = copy_views(c, 1, fb.views);
+    if (st != IVR_OK) return st;
+    st = launch_batch(c, b, fb, c->lc, stats ? c->ev : nullptr, c->stream);
+    if (st != IVR_OK) return st;
+    if (stats) {
+        st = read_stats(c, fb.ctr, stats);
+        if (st != IVR_OK) return st;
+    }
+    c->err.clear();
+    return IVR_OK;
 }
 
 ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
@@ -1316,7 +1468,8 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
         return st;
     }
     Batch b;
-    st = prepare_batch(c, hv.data(), n_views, o, false, c->lc, b);
+    FrameBufs fb;
+    st = prepare_batch(c, hv.data(), n_views, o, false, c->lc, b, fb);
     if (st != IVR_OK) return st;
     // the graph holds every kernel argument except what the view table carries
     // (cameras, transfer functions, output pointers): key it by the rest
@@ -1328,7 +1481,7 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
         key.push_back(hv[v].cam->height);
         key.push_back(hv[v].model);
     }
-    st = copy_views(c, n_views);
+    st = copy_views(c, n_views, fb.views);
     if (st != IVR_OK) return st;
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
@@ -1336,7 +1489,7 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
         // null stream, which cannot capture), replayed on the render stream
         hipGraph_t g = nullptr;
         IVR_HIP(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-        st = launch_batch(c, b, c->lc, nullptr, c->capture);
+        st = launch_batch(c, b, fb, c->lc, nullptr, c->capture);
         hipError_t e = hipStreamEndCapture(c->capture, &g);
         if (st != IVR_OK) {
             if (g) (void)hipGraphDestroy(g);

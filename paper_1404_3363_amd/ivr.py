@@ -21,7 +21,7 @@ SEED = {"plain": 0, "mlp": 1, "box": 2}
 RHO_INTERP = {"linear": 0, "hermite": 1}
 
 EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_upload_models",
-           "ivr_render", "ivr_render_batch", "ivr_autotune", "ivr_set_launch",
+           "ivr_render", "ivr_render_noalloc", "ivr_render_batch", "ivr_autotune", "ivr_set_launch",
            "ivr_phase_times", "ivr_last_error", "ivr_destroy", "ivr_default_mlp_opts",
            "ivr_train_inverse_mlp", "ivr_mlp_forward_backward", "ivr_mlp_get_weights",
            "ivr_mlp_infer"]
@@ -121,6 +121,8 @@ def load_library() -> C.CDLL:
     L.ivr_render.argtypes = [vp, C.POINTER(CameraDesc), C.POINTER(TransferDesc),
                              C.POINTER(RenderOpts), vp, vp, C.POINTER(Stats)]
     L.ivr_render.restype = C.c_int32
+    L.ivr_render_noalloc.argtypes = L.ivr_render.argtypes
+    L.ivr_render_noalloc.restype = C.c_int32
     fp = C.POINTER(C.c_float)
     L.ivr_default_mlp_opts.argtypes = [C.POINTER(MlpOpts)]
     L.ivr_default_mlp_opts.restype = None
@@ -370,8 +372,9 @@ class Renderer:
         self._check(self.lib.ivr_set_launch(self.ctx, tile_w, xcd_chunk, int_block, int_waves_cu))
 
     def render(self, cam, tf, opts: Optional[RenderOpts] = None, rgba=None, depth=None,
-               stats: bool = False, **kw):
-        torch = self.torch
+               stats: bool = False, noalloc: bool = False, **kw):
+        """One view.  noalloc: through ivr_render_noalloc (frame buffers in the
+        device's fixed scratch array, no allocation by the library)."""
         if opts is None:
             opts = default_opts(**kw)
         elif kw:
@@ -380,9 +383,10 @@ class Renderer:
         cd = camera_desc(cam)
         td = _TF(tf)
         st = Stats() if stats else None
-        rc = self.lib.ivr_render(self.ctx, C.byref(cd), C.byref(td.desc), C.byref(opts),
-                                 C.c_void_p(rgba.data_ptr()), C.c_void_p(depth.data_ptr()),
-                                 C.byref(st) if st is not None else None)
+        fn = self.lib.ivr_render_noalloc if noalloc else self.lib.ivr_render
+        rc = fn(self.ctx, C.byref(cd), C.byref(td.desc), C.byref(opts),
+                C.c_void_p(rgba.data_ptr()), C.c_void_p(depth.data_ptr()),
+                C.byref(st) if st is not None else None)
         self._check(rc)
         out = None
         if st is not None:
