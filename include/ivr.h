@@ -100,7 +100,8 @@ typedef struct {
                                    with a singular end                      [0]   */
     double c_perp;              /* weight c of V_perp in Eq. (vec2)         [1]   */
     int32_t n_super;            /* supersampling sub-steps per RK step      [4]   */
-    double det_fp64_threshold;  /* |det J| below it: solve in FP64          [1e-6] */
+    double det_fp64_threshold;  /* |det J| below it: the 3x3 solve of W (and of
+                                   a Newton step) in FP64               [1e-6] */
     int32_t max_fragments;      /* boundary crossings kept per ray, 2..64   [64]  */
     int32_t seed_mode;          /* IVR_SEED_*: first Newton seed of a face root [BOX]*/
     double early_term;          /* stop a segment once alpha >= 1-early_term [1e-4]*/
@@ -120,6 +121,11 @@ typedef struct {
                                    of a 64-pixel tile whose candidates do not
                                    fit are traversed again and solved ray by
                                    ray (0: every ray); same image       [8]   */
+    double det_singular;        /* |det J_phi| below it at a segment end makes
+                                   the end singular, Eq. (degeneracyfix): a
+                                   singular entry is moved along the ray and
+                                   found again by Newton, the integration stops
+                                   short of a singular exit            [1e-6] */
 } ivr_render_opts;
 
 /* Counters of one render (filled when a non-NULL ivr_stats* is passed; that
@@ -145,8 +151,10 @@ typedef struct {
     uint64_t mlp_queries;       /* MLP seed evaluations                          */
     uint64_t subsamples;        /* supersampling sub-steps (transfer function)   */
     uint64_t degenerate;        /* segment ends with singular J (|det J| below
-                                   det_fp64_threshold), shrunk by Eq. (degeneracyfix) */
+                                   det_singular), shrunk by Eq. (degeneracyfix) */
     uint64_t mlp_restarts;      /* shrunk entries whose Newton the network seeded */
+    uint64_t face_newton_fail;  /* candidates from whose every seed the face
+                                   Newton failed to converge (no crossing taken) */
     double ms_fragments, ms_integrate, ms_merge;  /* event times per phase      */
 } ivr_stats;
 

@@ -88,6 +88,8 @@ def lib():
                                         C.POINTER(_Opts), C.POINTER(C.c_int64), C.c_int64, dp, dp,
                                         C.POINTER(_Diag)]
         L.orc_render_pixels.restype = C.c_int32
+        L.orc_locate.argtypes = [C.c_void_p, dp, C.c_int64, C.POINTER(C.c_int32), dp, dp]
+        L.orc_locate.restype = C.c_int32
         L.orc_table1.argtypes = [C.c_int32, C.c_double, C.c_double]
         L.orc_table1.restype = C.c_double
         _lib = L
@@ -158,6 +160,22 @@ class OracleScene:
                 lib().orc_free(self.handle)
         except Exception:
             pass
+
+    def locate(self, g, hint_block=None, hint_p=None, chain=False):
+        """Brute-force point location (Newton inversion from a hint and nine seeds):
+        per point the block that holds it (-1: none), its parameters and rho.
+        chain: each point after the first is seeded with its predecessor's result."""
+        g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(-1, 3))
+        n = len(g)
+        blk = np.full(n, -1, dtype=np.int32) if hint_block is None else \
+            np.ascontiguousarray(np.broadcast_to(hint_block, (n,)), dtype=np.int32).copy()
+        p = np.full((n, 3), 0.5) if hint_p is None else \
+            np.ascontiguousarray(np.broadcast_to(hint_p, (n, 3)), dtype=np.float64).copy()
+        if chain and n > 1:
+            blk[1:] = -2
+        rho = np.zeros(n)
+        lib().orc_locate(self.handle, _dp(g), n, blk.ctypes.data_as(C.POINTER(C.c_int32)), _dp(p), _dp(rho))
+        return blk, p, rho
 
     def fragments(self, o, d, cap=1024):
         o = np.ascontiguousarray(o, dtype=np.float64)

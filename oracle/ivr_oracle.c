@@ -438,6 +438,60 @@ void orc_free(orc_scene *s)
     free(s->patches); free(s->elems); free(s->pbox); free(s->elem_begin); free(s);
 }
 
+/* ------------------------------------------------------------------ point location
+ * For brute-force tests of the fragment finder: is g inside block alpha, i.e.
+ * does F_g of Eq. (F) have a root in P_alpha?  By the argument of Sec. "Root
+ * Finding Based Algorithm" (|F_g(p)| is the distance to the preimage, so
+ * Newton with line search converges from interior seeds when a preimage
+ * exists), Newton with clamping and line search (orc_invert) is run from the
+ * hint (the previous point's parameters, when *block >= 0 on entry) and then
+ * from nine interior seeds, over every block whose control-point box holds g.
+ * block[i] = -2 on entry takes point i-1's result as the hint (points along a
+ * ray).  Uses no part of the boundary-face machinery.  On return block[i] is the
+ * first block that holds g[i] (-1: none), p[3i..] its parameters and rho[i]
+ * the scalar there.                                                          */
+int32_t orc_locate(const orc_scene *s, const double *g, int64_t n, int32_t *block, double *p,
+                   double *rho)
+{
+    static const double seeds[9][3] = {{0.5, 0.5, 0.5}, {0.25, 0.25, 0.25}, {0.75, 0.25, 0.25},
+                                       {0.25, 0.75, 0.25}, {0.75, 0.75, 0.25}, {0.25, 0.25, 0.75},
+                                       {0.75, 0.25, 0.75}, {0.25, 0.75, 0.75}, {0.75, 0.75, 0.75}};
+    for (int64_t i = 0; i < n; ++i) {
+        const double *gi = g + 3 * i;
+        const int chain = block[i] == -2 && i > 0;
+        const int hint = chain ? block[i - 1] : block[i];
+        const double *hsrc = chain ? p + 3 * (i - 1) : p + 3 * i;
+        double hp[3] = {hsrc[0], hsrc[1], hsrc[2]};
+        int found = -1;
+        double q[3];
+        for (int pi = 0; pi < s->npatch && found < 0; ++pi) {
+            const double *bx = s->pbox[pi];
+            const double pad = 1e-9 * s->scale;
+            if (gi[0] < bx[0] - pad || gi[1] < bx[1] - pad || gi[2] < bx[2] - pad || gi[0] > bx[3] + pad ||
+                gi[1] > bx[4] + pad || gi[2] > bx[5] + pad)
+                continue;
+            const orc_patch *P = &s->patches[pi];
+            if (pi == hint && orc_invert(P, gi, hp, s->scale, q, NULL) == 0) {
+                found = pi;
+                break;
+            }
+            for (int k = 0; k < 9; ++k)
+                if (orc_invert(P, gi, seeds[k], s->scale, q, NULL) == 0) {
+                    found = pi;
+                    break;
+                }
+        }
+        block[i] = found;
+        if (found >= 0) {
+            double x[3], J[9], r;
+            orc_eval(&s->patches[found], q, x, J, &r);
+            p[3 * i] = q[0]; p[3 * i + 1] = q[1]; p[3 * i + 2] = q[2];
+            if (rho) rho[i] = r;
+        }
+    }
+    return 0;
+}
+
 /* slab test of the ray (t >= 0) against a padded box */
 static int ray_box(const double o[3], const double d[3], const double lo[3], const double hi[3],
                    double pad)

@@ -88,6 +88,12 @@ int32_t orc_eval(const orc_patch *P, const double p[3], double x[3], double J[9]
 /* Newton preimage of g with line search and clamping to [0,1]^3. */
 int32_t orc_invert(const orc_patch *P, const double g[3], const double seed[3], double scale,
                    double p_out[3], int32_t *iterations);
+/* Brute-force point location (tests only): for each of n points g[3i..], the
+   first block whose map reaches it by Newton inversion (hint: block[i] >= 0 and
+   p[3i..] on entry; block[i] = -2: point i-1's result), -1 if none; its
+   parameters p[3i..] and rho[i] (rho may be NULL). */
+int32_t orc_locate(const orc_scene *s, const double *g, int64_t n, int32_t *block, double *p,
+                   double *rho);
 /* Pinhole ray through pixel position (px, py) (pixel centres at i+0.5). */
 void orc_camera_ray(const orc_camera *c, double px, double py, double o[3], double d[3]);
 /* Transfer function at rho: (R,G,B,kappa). */

@@ -520,6 +520,7 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->tf_step = 0.025;
     o->rho_step = 0.1;
     o->cand_per_pixel = 8;
+    o->det_singular = 1e-6;
 }
 
 static ivr_status ensure_views(ivr_ctx *c, int n);
@@ -1044,6 +1045,8 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
     if (!(o.c_perp >= 0 && std::isfinite(o.c_perp))) return fail(c, IVR_EINVAL, "c_perp must be >= 0");
     if (o.n_super < 1 || o.n_super > 64) return fail(c, IVR_EINVAL, "n_super outside 1..64");
     if (!(o.det_fp64_threshold >= 0)) return fail(c, IVR_EINVAL, "det_fp64_threshold must be >= 0");
+    if (!(o.det_singular >= 0 && std::isfinite(o.det_singular)))
+        return fail(c, IVR_EINVAL, "det_singular must be finite and >= 0");
     if (o.max_fragments < 2 || o.max_fragments > kFragCap)
         return fail(c, IVR_EINVAL, "max_fragments outside 2..64");
     if (o.rho_interp != IVR_RHO_LINEAR && o.rho_interp != IVR_RHO_HERMITE)
@@ -1070,6 +1073,7 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
     fp.c_perpd = o.c_perp; fp.c_perp = (float)o.c_perp;
     fp.early_termd = o.early_term; fp.early_term = (float)o.early_term;
     fp.det_thrd = o.det_fp64_threshold; fp.det_thr = (float)o.det_fp64_threshold;
+    fp.det_singd = o.det_singular; fp.det_sing = (float)o.det_singular;
     fp.n_super = o.n_super;
     fp.max_frag = o.max_fragments;
     fp.hermite = o.rho_interp == IVR_RHO_HERMITE ? 1 : 0;

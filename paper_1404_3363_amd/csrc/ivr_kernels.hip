@@ -205,7 +205,7 @@ template <int P, bool RAT, typename RN>
 __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E, const double (&od)[3],
                           const double (&dd)[3], const float (&of)[3], const float (&df)[3],
                           const FrameParams &fp, const float (&mseed)[3], float T1, RootRec<RN> &out,
-                          bool &again, u32 &n_iter, u32 &n_polish) {
+                          bool &again, u32 &n_iter, u32 &n_polish, u32 &n_fail) {
     const int face = E.face;
     const FaceView<RN> fv = face_view<RN>(Pd, face);
     const Arrays<RN> ar = arrays_of(m, RN(0));
@@ -341,6 +341,7 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
         again = tangent && !second;
         return;
     }
+    if (!second) ++n_fail;   // Newton converged from no seed
 }
 
 // The root of one candidate in out (info stays ~0 when there is none); T1 < 0
@@ -350,16 +351,16 @@ __device__ __forceinline__ void face_root_any(const Model &m, const DevPatch &Pd
                                               const double (&od)[3], const double (&dd)[3],
                                               const float (&of)[3], const float (&df)[3],
                                               const FrameParams &fp, const float (&ms)[3], float T1,
-                                              RootRec<R> &out, bool &again, u32 &ni, u32 &np) {
+                                              RootRec<R> &out, bool &again, u32 &ni, u32 &np, u32 &nf) {
     out.info = out.tinfo = 0xFFFFFFFFu;
     again = false;
     switch (Pd.deg * 2 + Pd.rational) {
-    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
-    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
-    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
-    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
-    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
-    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
+    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
+    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
+    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
+    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
+    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
     }
 }
 
@@ -445,7 +446,8 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         df[q] = float(dd[q]);
         inv[q] = 1.0f / df[q];
     }
-    u32 c_anom = 0, c_fovf = 0, c_sovf = 0, c_box = 0, c_newton = 0, c_iter = 0, c_pol = 0, c_mlp = 0;
+    u32 c_anom = 0, c_fovf = 0, c_sovf = 0, c_box = 0, c_newton = 0, c_iter = 0, c_pol = 0, c_mlp = 0,
+        c_nfail = 0;
 
     // 1. face elements whose oriented box the ray hits (block and face boxes
     //    first) become Newton seeds; 2. the seeds are solved (a wave's 64 at a
@@ -515,7 +517,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                     RootRec<R> rr;
                     bool again;
                     face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, T1, rr, again, c_iter,
-                                     c_pol);
+                                     c_pol, c_nfail);
                     add_root(rr);
                     if (!again) break;
                     T1 = float(rr.t);
@@ -663,7 +665,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                         RootRec<R> out;
                         bool again;
                         face_root_any<R>(m, m.patches[E.patch], E, od, odd, of, odf, fp, ms, T1, out, again,
-                                         c_iter, c_pol);
+                                         c_iter, c_pol, c_nfail);
                         if (s == 0) {
                             s_res[j] = out;
                         } else if (out.info != 0xFFFFFFFFu) {   // to the pass's short list of second roots
@@ -787,7 +789,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         const R det_out = rho_ds_any<R>(m, m.patches[info_o >> 4], po_, dr, s.rho_out, s.drho_out);
         // singular J at the exit (a degenerate boundary): no slope; the
         // integrator then stops short of the exit, Eq. (degeneracyfix)
-        if (!(fabs(det_out) >= (sizeof(R) == 4 ? R(fp.det_thr) : R(fp.det_thrd))))
+        if (!(fabs(det_out) >= (sizeof(R) == 4 ? R(fp.det_sing) : R(fp.det_singd))))
             s.drho_out = R(NAN);
         s.pixel = pixel;
         s.patch = (info_o >> 4) | ((u32)v << kViewShift);
@@ -837,6 +839,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         flush_counter(ctr, C_FACE_NEWTON_ITER, c_iter);
         flush_counter(ctr, C_FP64_POLISH, c_pol);
         flush_counter(ctr, C_MLP_QUERIES, c_mlp);
+        flush_counter(ctr, C_FACE_FAIL, c_nfail);
     }
 }
 
@@ -955,7 +958,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const R tol = sizeof(R) == 4 ? R(fp.rk_tol) : R(fp.rk_told);
     const R cperp = sizeof(R) == 4 ? R(fp.c_perp) : R(fp.c_perpd);
     const R early = sizeof(R) == 4 ? R(fp.early_term) : R(fp.early_termd);
-    const R dthr = sizeof(R) == 4 ? R(fp.det_thr) : R(fp.det_thrd);
+    const R dthr = sizeof(R) == 4 ? R(fp.det_thr) : R(fp.det_thrd);     // FP64 solves below it
+    const R dsing = sizeof(R) == 4 ? R(fp.det_sing) : R(fp.det_singd);  // singular J below it
     const int nq = q_end - q_begin;
     if (threadIdx.x == 0) {
         // the block that holds segment S0 + (S1 - S0) * blockIdx / gridDim
@@ -1096,7 +1100,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         if (shrinking) {
             // Eq. (degeneracyfix): Newton on phi(p) = gin, iterates clamped to P
             const R tolx = (sizeof(R) == 4 ? R(2e-6) : R(1e-12)) * vscale;
-            if (res2 <= tolx * tolx && fabs(det1) >= dthr) {
+            if (res2 <= tolx * tolx && fabs(det1) >= dsing) {
                 // the sliver [0, delta]: rho linear from the entry to the new entry
                 const R sl = (rho_cur - rho_in) / delta;
                 composite(fp, views[vid].fp, vls[vid], rho_in, sl, rho_cur, sl, delta, C, A, c_sub);
@@ -1134,7 +1138,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             fresh = false;
             if (!(L > R(1e-7) * vscale)) {
                 done = true;   // empty chord
-            } else if (s == R(0) && !(fabs(det1) >= dthr)) {
+            } else if (s == R(0) && !(fabs(det1) >= dsing)) {
                 // Eq. (degeneracyfix): J_phi singular at the entry.  Move the entry
                 // delta = 1e-4 L along the ray (tenfold more, up to twice, if Newton
                 // fails) and find its preimage by Newton from

@@ -52,7 +52,7 @@ class RenderOpts(C.Structure):
                 ("seed_mode", C.c_int32), ("early_term", C.c_double),
                 ("max_newton_iter", C.c_int32), ("rho_interp", C.c_int32),
                 ("timing", C.c_int32), ("tf_step", C.c_double), ("rho_step", C.c_double),
-                ("cand_per_pixel", C.c_int32)]
+                ("cand_per_pixel", C.c_int32), ("det_singular", C.c_double)]
 
 
 class ViewDesc(C.Structure):
@@ -70,7 +70,7 @@ STAT_FIELDS = ["rays", "segments", "fragments", "anomalies", "fragment_overflow"
                "segment_overflow", "box_tests", "face_newton", "face_newton_iter",
                "fp64_polish_iter", "rk_steps", "rk_rejected", "samples", "w_evals",
                "fp64_solves", "rk_iter_cap", "mlp_queries", "subsamples", "degenerate",
-               "mlp_restarts"]
+               "mlp_restarts", "face_newton_fail"]
 
 
 class MlpOpts(C.Structure):

@@ -508,6 +508,68 @@ def make_edge_lattice(width: int = 65, height: int = 65) -> Scene:
                  dict(precision="fp32", rk_tol=1e-5))
 
 
+def _insert_knot_homogeneous(t, H, p, u):
+    """Boehm insertion of u into a rational curve given by homogeneous points H
+    (rows (w x, w y, w)), via scipy's B-spline knot insertion per coordinate."""
+    from scipy.interpolate import insert
+    cols, tt = [], None
+    for c in range(H.shape[1]):
+        tt, cc, _ = insert(u, (t, np.concatenate([H[:, c], np.zeros(p + 1)]), p))
+        cols.append(cc[:len(tt) - p - 1])
+    return np.asarray(tt), np.stack(cols, axis=1)
+
+
+def make_annulus(constant_field: bool = False, width: int = 48, height: int = 48,
+                 r_in: float = 1.0, r_out: float = 2.0, height_z: float = 1.5) -> Scene:
+    """Quarter annulus r_in <= r <= r_out, 0 <= theta <= pi/2, 0 <= z <= height_z as
+    one quadratic NURBS block (degree 2 in every direction):
+      u (arc): the unit quarter circle with weights (1, sqrt(2)/2, 1), then the knot
+               0.35 inserted (homogeneous Boehm insertion): knots (0,0,0,.35,1,1,1);
+      v (radial): radii (r_in, mid, r_out), knots (0,0,0,1,1,1) (linear);
+      w (height): knots (0,0,0,.3,1,1,1), control points at the Greville points.
+    Weights depend on u only, so the map is r(v) (cos theta(u), sin theta(u)), z(w):
+    the faces v = 0, 1 are exactly the cylinders r = r_in, r_out, the faces u = 0, 1
+    the half planes y = 0, x = 0, and w = 0, 1 the planes z = 0, height_z.
+    Field: constant 0.5, or 0.5 + 0.3 sin(2x) cos(1.5y) + 0.2 z quasi-interpolated.
+    Three views (seeds 6201..6203)."""
+    p = 2
+    arc = np.array([[1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
+    w0 = np.array([1.0, math.sqrt(0.5), 1.0])
+    H0 = np.concatenate([arc * w0[:, None], w0[:, None]], axis=1)
+    tu, Hu = _insert_knot_homogeneous(np.array([0, 0, 0, 1, 1, 1.0]), H0, p, 0.35)
+    wu = Hu[:, 2]
+    au = Hu[:, :2] / wu[:, None]
+    tv = np.array([0, 0, 0, 1, 1, 1.0])
+    radii = np.array([r_in, 0.5 * (r_in + r_out), r_out])
+    tw = np.array([0, 0, 0, 0.3, 1, 1, 1.0])
+    zs = height_z * greville(tw, p)
+    nu, nv, nw = len(wu), len(radii), len(zs)
+    xyz = np.empty((nw, nv, nu, 3))
+    wt = np.empty((nw, nv, nu))
+    for k in range(nw):
+        for j in range(nv):
+            for i in range(nu):
+                xyz[k, j, i] = (radii[j] * au[i, 0], radii[j] * au[i, 1], zs[k])
+                wt[k, j, i] = wu[i]
+    if constant_field:
+        sc = np.full((nw, nv, nu), 0.5)
+    else:
+        sc = 0.5 + 0.3 * np.sin(2.0 * xyz[..., 0]) * np.cos(1.5 * xyz[..., 1]) + 0.2 * xyz[..., 2]
+    patch = _make_patch((p, p, p), (nu, nv, nw), [tu, tv, tw], xyz, sc, w=wt, rational=True)
+    bbox = np.array([[0.0, 0.0, 0.0], [r_out, r_out, height_z]])
+    rng = np.random.Generator(np.random.PCG64(6200))
+    tf = random_tf(rng, extinction_for(bbox), (0.0, 1.0) if constant_field else scalar_domain([patch]))
+    target = 0.5 * (bbox[0] + bbox[1])
+    cams = []
+    for s in range(3):
+        r = np.random.Generator(np.random.PCG64(6201 + s))
+        az, el = r.uniform(0.0, 360.0), r.uniform(-45.0, 45.0)
+        cams.append(camera_from_angles(target, 3.2 * float(np.linalg.norm(bbox[1] - bbox[0])) / 2.0,
+                                       az, el, width, height))
+    return Scene("quarter_annulus_nurbs", [patch], tf, cams, bbox,
+                 dict(r_in=r_in, r_out=r_out, height=height_z))
+
+
 def make_config(k: int, width: Optional[int] = None, height: Optional[int] = None):
     """Build config k (1..4) as a Scene; config 5 returns (model_a, model_b, views)."""
     if k == 1:

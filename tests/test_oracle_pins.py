@@ -593,3 +593,201 @@ def test_mlp_reference_gradient_matches_finite_differences():
         tm[i] -= h
         fd = (mlp.loss(tp, x, p) - mlp.loss(tm, x, p)) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-9, (i, fd, g[i])
+
+
+# ------------------------------------------------------------------ curved faces by brute force
+
+def _inside_intervals(prep, o, d, t0, t1, ds, eps):
+    """Inside/outside of the ray's points by brute-force point location (Newton
+    inversion of the volume map, no face machinery): a scan at step ds, then every
+    change located by bisection to eps.  Returns the transitions [(t, entering)]."""
+    n = int(math.ceil((t1 - t0) / ds))
+    ts = t0 + np.arange(n + 1) * (t1 - t0) / n
+    inside = prep.locate(o + ts[:, None] * d, chain=True)[0] >= 0
+    trans = []
+    for i in np.flatnonzero(inside[1:] != inside[:-1]):
+        a, b = ts[i], ts[i + 1]
+        while b - a > eps:
+            m = 0.5 * (a + b)
+            if (prep.locate(o + m * d)[0][0] >= 0) == inside[i]:
+                a = m
+            else:
+                b = m
+        trans.append((0.5 * (a + b), bool(inside[i + 1])))
+    return trans
+
+
+def _check_fragments_by_brute_force(scene_patches, scale, cam, tf, min_crossings):
+    prep = oracle.OracleScene(scene_patches, scale)
+    ref = oracle.render(scene_patches, cam, tf, scale=scale)
+    ds, eps = scale / 1024.0, 1e-11 * scale
+    pts = np.concatenate([p.cp[:, :3] for p in scene_patches])
+    lo, hi = pts.min(0) - 0.01 * scale, pts.max(0) + 0.01 * scale
+    crossings = 0
+    for pix in range(cam.width * cam.height):
+        o, d = oracle.camera_ray(cam, pix % cam.width + 0.5, pix // cam.width + 0.5)
+        t0, t1 = _slab(o, d, lo, hi)
+        fr = prep.fragments(o, d)
+        if not t1 > max(t0, 0):
+            assert not fr
+            continue
+        trans = _inside_intervals(prep, o, d, max(t0, 0.0), t1, ds, eps)
+        # every crossing the scan finds is an oracle fragment of the same facing ...
+        for tb, entb in trans:
+            assert any(abs(t - tb) <= 1e-9 * scale and ent == entb for t, *_, ent in fr), (pix, tb, fr)
+        # ... every oracle fragment is a change of inside/outside right at it ...
+        for t, *_, ent in fr:
+            b_before = prep.locate(o + (t - 1e-8 * scale) * d)[0][0]
+            b_after = prep.locate(o + (t + 1e-8 * scale) * d)[0][0]
+            assert (b_before < 0) == ent and (b_after >= 0) == ent, (pix, t)
+        # ... and those the scan stepped over are slivers thinner than its step
+        extra = [f for f in fr if not any(abs(f[0] - tb) <= 1e-9 * scale for tb, _ in trans)]
+        assert len(extra) % 2 == 0, (pix, extra)
+        for f_in, f_out in zip(extra[0::2], extra[1::2]):
+            assert f_in[4] and not f_out[4] and f_out[0] - f_in[0] < ds, (pix, extra)
+        trans = [(f[0], f[4]) for f in fr]
+        crossings += len(fr)
+        # dense midpoint quadrature over the brute-force intervals (65536 panels per
+        # scale: the transfer function's kinks make coarser midpoint sums wander by
+        # 1e-5), composited front to back
+        C, A = np.zeros(3), 0.0
+        for (ta, _), (tb, _) in zip(trans[0::2], trans[1::2]):
+            m = max(int(math.ceil((tb - ta) / (scale / 65536.0))), 8)
+            h = (tb - ta) / m
+            g = o + (ta + (np.arange(m) + 0.5) * h)[:, None] * d
+            blk, _, rho = prep.locate(g, chain=True)
+            assert (blk >= 0).all()
+            n = np.clip((rho - tf.domain[0]) / (tf.domain[1] - tf.domain[0]), 0.0, 1.0)
+            e = np.stack([np.interp(n, tf.x, tf.rgba[:, c]) for c in range(4)], axis=1)
+            T = np.exp(-tf.extinction * e[:, 3] * h)
+            before = np.concatenate([[1.0], np.cumprod(T)[:-1]]) * (1.0 - A)
+            C += ((1.0 - T) * before) @ e[:, :3]
+            A += float(((1.0 - T) * before).sum())
+        assert abs(ref.rgba[pix, 3] - A) < 5e-6 and np.abs(ref.rgba[pix, :3] - C).max() < 5e-6, pix
+        if trans:
+            assert abs(ref.depth[pix] - trans[0][0]) <= 1e-9 * scale
+    assert crossings >= min_crossings
+
+
+def test_brute_force_twisted_bar_along_its_length(oracle_lib):
+    """Curved faces (config 2, cubic, twisted 180 degrees): 8x8 rays down the bar's
+    length cross its side faces up to four times.  Every crossing that a brute-force
+    scan of the volume map finds (Newton inversion at every point, step 1/1024 of the
+    scale, bisection to 1e-11 of it) is an oracle fragment to 1e-9 of the scale, with
+    the same facing; every oracle fragment is an inside/outside change within 1e-8
+    of the scale (those the scan stepped over pair up as slivers thinner than its
+    step); dense quadrature over the intervals matches the image."""
+    sc = make_config(2)
+    cam = camera_from_angles([0.0, 0.0, 4.0], 9.0, 30.0, 84.0, 8, 8, fov_y_deg=10.0)
+    _check_fragments_by_brute_force(sc.patches, sc.scale, cam, sc.tf, min_crossings=60)
+
+
+def test_brute_force_bent_beam_block(oracle_lib):
+    """One curved block of config 3 (cubic, 10^3 control points, bent about z) seen
+    obliquely: the same brute-force checks as for the twisted bar."""
+    sc = make_config(3, 96, 54)
+    P = sc.patches[63]
+    pts = P.cp[:, :3]
+    c = 0.5 * (pts.min(0) + pts.max(0))
+    size = float(np.linalg.norm(pts.max(0) - pts.min(0)))
+    cam = camera_from_angles(c, 3.0 * size, 20.0, 30.0, 10, 10, fov_y_deg=22.0)
+    _check_fragments_by_brute_force([P], sc.scale, cam, sc.tf, min_crossings=40)
+
+
+# ------------------------------------------------------------------ NURBS faces in closed form
+
+def _annulus_transitions(o, d, r_in, r_out, hz):
+    """Exact crossings of the ray o + t d (t > 0) with the boundary of the quarter
+    annulus r_in <= r <= r_out, x >= 0, y >= 0, 0 <= z <= hz: the roots of the two
+    cylinders and four planes, kept where the inside test changes between roots."""
+    roots = []
+    a = d[0] ** 2 + d[1] ** 2
+    b = 2.0 * (o[0] * d[0] + o[1] * d[1])
+    for R in (r_in, r_out):
+        c = o[0] ** 2 + o[1] ** 2 - R * R
+        disc = b * b - 4.0 * a * c
+        if a > 0.0 and disc > 0.0:
+            q = -0.5 * (b + math.copysign(math.sqrt(disc), b))
+            roots += [q / a, c / q]
+    for ax, val in ((0, 0.0), (1, 0.0), (2, 0.0), (2, hz)):
+        if d[ax] != 0.0:
+            roots.append((val - o[ax]) / d[ax])
+    roots = sorted(t for t in roots if t > 0.0)
+
+    def inside(t):
+        x = o + t * d
+        r = math.hypot(x[0], x[1])
+        return r_in <= r <= r_out and x[0] >= 0.0 and x[1] >= 0.0 and 0.0 <= x[2] <= hz
+    out, prev = [], inside(0.0)
+    ends = roots + [roots[-1] + 100.0] if roots else []
+    for i, t in enumerate(roots):
+        now = inside(0.5 * (t + ends[i + 1]))
+        if now != prev:
+            out.append((t, now))
+        prev = now
+    return out
+
+
+def _annulus_rays(n, seed):
+    rng = np.random.default_rng(seed)
+    centre = np.array([1.0, 1.0, 0.75])
+    for _ in range(n):
+        v = rng.normal(size=3)
+        eye = centre + 5.0 * v / np.linalg.norm(v)
+        aim = rng.uniform([-0.2, -0.2, -0.2], [2.2, 2.2, 1.7])
+        d = aim - eye
+        yield eye, d / np.linalg.norm(d)
+
+
+def test_nurbs_annulus_fragments_are_cylinder_and_plane_roots(oracle_lib):
+    """Rational faces with non-uniform knots (quadratic NURBS quarter annulus, weights
+    (1, sqrt(2)/2, 1) on the arc with an inserted knot): the oracle's fragments are
+    the closed-form ray-cylinder and ray-plane roots to 1e-9 of the scale, with the
+    right facing, on the right face, and map back onto the ray."""
+    from scenes import make_annulus
+    sc = make_annulus()
+    prm = sc.params
+    prep = oracle.OracleScene(sc.patches, sc.scale)
+    op = oracle.OraclePatch(sc.patches[0])
+    n_rays = n_cross = n_four = 0
+    for o, d in _annulus_rays(120, 611):
+        exact = _annulus_transitions(o, d, prm["r_in"], prm["r_out"], prm["height"])
+        fr = prep.fragments(o, d)
+        assert len(fr) == len(exact), ([f[0] for f in fr], exact)
+        for (t, p, _, face, ent), (te, ente) in zip(fr, exact):
+            assert abs(t - te) <= 1e-9 * sc.scale and ent == ente, (t, te)
+            x, _, _ = oracle.evaluate(op, p)
+            assert np.abs(x - (o + t * d)).max() <= 1e-9 * sc.scale
+            r = math.hypot(x[0], x[1])
+            on = {0: abs(x[1]), 1: abs(x[0]), 2: abs(r - prm["r_in"]), 3: abs(r - prm["r_out"]),
+                  4: abs(x[2]), 5: abs(x[2] - prm["height"])}[face]
+            assert on <= 1e-9 * sc.scale, (face, x)
+        n_rays += 1
+        n_cross += len(fr)
+        n_four += len(fr) >= 4
+    assert n_rays >= 60 and n_cross >= 120 and n_four >= 3, (n_rays, n_cross, n_four)
+
+
+def test_nurbs_annulus_constant_field_closed_form(oracle_lib):
+    """Constant rho on the NURBS annulus: alpha = 1 - exp(-kappa L) and RGB = E alpha
+    with L the total closed-form chord, and the depth the first closed-form entry."""
+    from scenes import make_annulus
+    sc = make_annulus(constant_field=True, width=20, height=20)
+    prm = sc.params
+    E = oracle.transfer(sc.tf, 0.5)
+    for cam in sc.cameras:
+        res = oracle.render(sc, cam, sc.tf)
+        hits = 0
+        for pix in range(cam.width * cam.height):
+            o, d = oracle.camera_ray(cam, pix % cam.width + 0.5, pix // cam.width + 0.5)
+            tr = _annulus_transitions(o, d, prm["r_in"], prm["r_out"], prm["height"])
+            L = sum(b[0] - a[0] for a, b in zip(tr[0::2], tr[1::2]))
+            alpha = 1.0 - math.exp(-E[3] * L)
+            assert abs(res.rgba[pix, 3] - alpha) < 1e-7, pix
+            assert np.abs(res.rgba[pix, :3] - E[:3] * alpha).max() < 1e-7, pix
+            if tr:
+                hits += 1
+                assert abs(res.depth[pix] - tr[0][0]) <= 1e-9 * sc.scale
+            else:
+                assert np.isinf(res.depth[pix])
+        assert hits > 60
