@@ -46,7 +46,16 @@ typedef struct ivr_ctx ivr_ctx;
 
 /* One block (patch) of the model, Eq. (Bspline) and Sec. "Approach and
  * Implementation" (blocks G_alpha with phi_alpha and rho_alpha on P_alpha).
- *   degree[d]   polynomial degree per direction, 1..3, equal in all directions
+ *   degree[d]   polynomial degree per direction, 1..3; a block whose directions
+ *               differ is raised at upload to its largest degree in every
+ *               direction (exact degree elevation: knot multiplicities grow by
+ *               the difference, coefficients by collocation), which the kernels
+ *               then evaluate; a block is also split (exactly) at every interior
+ *               knot of full multiplicity, where it is only C0, into blocks
+ *               that meet there as at any conforming interface, so that the
+ *               integrator meets smooth blocks only.  Block indices used by the
+ *               MLP functions count the blocks after these splits (the same as
+ *               the input's when no block has such a knot)
  *   ncp[d]      control points per direction, >= degree+1
  *   knots[d]    ncp[d]+degree[d]+1 non-decreasing values, clamped (first and last
  *               value repeated degree+1 times); mapped affinely onto [0,1]
@@ -126,7 +135,23 @@ typedef struct {
                                    singular entry is moved along the ray and
                                    found again by Newton, the integration stops
                                    short of a singular exit            [1e-6] */
+    double drift_tol;           /* largest distance of phi(p) from the ray point
+                                   of its arc length, as a fraction of the
+                                   model's scale, checked before every sample:
+                                   beyond it the point is found again by Newton
+                                   from p (from the block's network with MLP
+                                   seeds) before it is sampled; 0: no check [1e-5] */
 } ivr_render_opts;
+
+/* Per-pixel flags (ivr_view.flags_dev): OR of the events of the pixel's ray. */
+#define IVR_FLAG_ANOMALY 1u              /* a crossing left unpaired              */
+#define IVR_FLAG_FRAGMENT_OVERFLOW 2u    /* crossings dropped (max_fragments)     */
+#define IVR_FLAG_SEGMENT_OVERFLOW 4u     /* segments dropped (capacity)           */
+#define IVR_FLAG_ITER_CAP 8u             /* a segment stopped at the RK step cap  */
+#define IVR_FLAG_DRIFT_RESTART 16u       /* a segment drifted off the ray and was
+                                            put back on it by Newton             */
+#define IVR_FLAG_RESTART_FAIL 32u        /* such a Newton did not converge        */
+#define IVR_FLAG_DEGENERATE 64u          /* a segment end with singular J_phi     */
 
 /* Counters of one render (filled when a non-NULL ivr_stats* is passed; that
  * forces a stream synchronisation). */
@@ -153,8 +178,8 @@ typedef struct {
     uint64_t degenerate;        /* segment ends with singular J (|det J| below
                                    det_singular), shrunk by Eq. (degeneracyfix) */
     uint64_t mlp_restarts;      /* shrunk entries whose Newton the network seeded */
-    uint64_t face_newton_fail;  /* candidates from whose every seed the face
-                                   Newton failed to converge (no crossing taken) */
+    uint64_t drift_restarts;    /* samples put back on the ray by Newton (drift_tol) */
+    uint64_t restart_fail;      /* of which Newton did not converge               */
     double ms_fragments, ms_integrate, ms_merge;  /* event times per phase      */
 } ivr_stats;
 
@@ -217,13 +242,15 @@ ivr_status ivr_render_noalloc(ivr_ctx *ctx, const ivr_camera *cam, const ivr_tra
 
 /* One view of a batch: camera, transfer function (NULL: the batch's), the model
  * it looks at (index into the models of the last upload) and its caller-owned
- * device outputs, laid out as for ivr_render. */
+ * device outputs, laid out as for ivr_render, plus optional per-pixel flags
+ * (width*height uint32 IVR_FLAG_* bits, or NULL). */
 typedef struct {
     ivr_camera cam;
     const ivr_transfer_fn *tf;
     int32_t model;
     float *rgba_dev;
     float *depth_dev;
+    uint32_t *flags_dev;
 } ivr_view;
 
 /* Renders 1..64 views of possibly different sizes and models with the same
@@ -312,6 +339,13 @@ ivr_status ivr_mlp_infer(ivr_ctx *ctx, const int32_t *patch, const float *x, int
  * milliseconds to ms_out (3*cap doubles), the number of renders to *n_out, and
  * forgets them.  At most 4096 renders are kept (IVR_EOVERFLOW past that). */
 ivr_status ivr_phase_times(ivr_ctx *ctx, double *ms_out, int32_t cap, int32_t *n_out);
+
+/* Device memory the context holds: the uploaded model (control nets, boxes,
+ * basis tables) and the frame buffers, which are sized from counts (segment
+ * slots at 2.5 per pixel or 1.2 times the most per pixel a render needed,
+ * candidate entries at 2 per pixel or 1.25 times the most needed) and grow but never shrink.  Either pointer may
+ * be NULL. */
+ivr_status ivr_device_bytes(ivr_ctx *ctx, uint64_t *model_bytes, uint64_t *frame_bytes);
 
 /* Message for the last failing call of this context ("" if none). */
 const char *ivr_last_error(const ivr_ctx *ctx);

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -55,11 +56,18 @@ struct ivr_ctx {
     LaunchCfg lc = {8, 0, 256, 0};
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
     unsigned long long generation = 0;   // bumps when buffers move (graphs hold pointers)
-    // frame buffers
+    // frame buffers, sized from counts: segment slots and candidate entries per
+    // pixel, the largest ratio the renders so far needed (read back without
+    // blocking after every render of the context's own buffers)
     size_t pix_cap = 0, seg_cap = 0, seg_bytes_cap = 0;
+    double seg_ratio = 0.0, cand_ratio = 0.0;
+    size_t model_bytes = 0;
+    uint32_t *h_qs = nullptr;             // pinned: (segments requested, candidates recorded)
+    hipEvent_t qs_ev = nullptr;
+    uint64_t qs_pixels = 0;               // pixels of the batch last read back
+    bool qs_pending = false;
 
     void *d_segs = nullptr;
-    float4 *d_results = nullptr;
     uint2 *d_pixseg = nullptr;
     uint2 *d_seg_kr = nullptr;           // (block, rank among the block's segments)
     uint32_t *d_order = nullptr;         // segment indices sorted by block
@@ -146,14 +154,10 @@ struct Box {
 
 std::string validate_patch(const ivr_patch_desc &P, int idx) {
     char buf[256];
-    const int p = P.degree[0];
     for (int d = 0; d < 3; ++d) {
-        if (P.degree[d] < 1 || P.degree[d] > kMaxDegree) {
+        const int p = P.degree[d];
+        if (p < 1 || p > kMaxDegree) {
             snprintf(buf, sizeof buf, "patch %d: degree %d outside 1..3", idx, P.degree[d]);
-            return buf;
-        }
-        if (P.degree[d] != p) {
-            snprintf(buf, sizeof buf, "patch %d: degrees must be equal in all directions", idx);
             return buf;
         }
         if (P.ncp[d] < p + 1 || P.ncp[d] > 4096) {
@@ -499,6 +503,205 @@ static float element_graze(const FaceElem &E, const std::vector<std::array<doubl
     return (float)std::min(1.0, 3.0 * g);
 }
 
+// Degree elevation, exact: direction d of degree p < P is rewritten in degree P.
+// Every distinct knot's multiplicity grows by P - p (the ends stay clamped), so
+// the degree-P space on the new knots contains every old basis function; the
+// new coefficients come from collocation at the new basis's Greville points
+// (distinct, so the collocation matrix is regular; it is totally positive and
+// banded, so it is solved by banded elimination without pivoting) and reproduce
+// the old spline up to rounding.  H holds nch channels per control point,
+// i fastest; n[] is updated.
+static void elevate_direction(std::vector<double> &H, int nch, int n[3], int d, const double *t_old, int p,
+                              int P, std::vector<double> &t_new) {
+    const int n_old = n[d], nk_old = n_old + p + 1;
+    t_new.clear();
+    for (int i = 0; i < nk_old;) {
+        int j = i;
+        while (j < nk_old && t_old[j] == t_old[i]) ++j;
+        for (int r = 0; r < (j - i) + (P - p); ++r) t_new.push_back(t_old[i]);
+        i = j;
+    }
+    const int n_new = (int)t_new.size() - P - 1;
+    const double t0 = t_new[P], t1 = t_new[n_new];
+    // lines along d: stride and count of the other two directions
+    const int stride = d == 0 ? 1 : (d == 1 ? n[0] : n[0] * n[1]);
+    const int lines = n[0] * n[1] * n[2] / n_old;
+    const int K = lines * nch;   // right-hand sides
+    auto line_base = [&](int l) {   // first point of line l (old layout)
+        const int inner = stride, outer = l / inner;
+        return (l % inner) + outer * inner * n_old;
+    };
+    // band of the collocation matrix (row i: columns i-P .. i+P) and the
+    // right-hand sides R[i][k] = sum_j N_j(xi_i) C_j[k]
+    const int W = P;
+    std::vector<double> A((size_t)n_new * (2 * W + 1), 0.0), R((size_t)n_new * K, 0.0);
+    for (int i = 0; i < n_new; ++i) {
+        double xi = 0.0;
+        for (int r = 1; r <= P; ++r) xi += t_new[i + r];
+        xi = (xi / P - t0) / (t1 - t0);
+        int s_new, s_old;
+        double M[kMaxDegree + 1], N[kMaxDegree + 1];
+        host_basis(t_new.data(), n_new, P, xi, s_new, M);
+        host_basis(t_old, n_old, p, xi, s_old, N);
+        for (int r = 0; r <= P; ++r) {
+            const int col = s_new - P + r;
+            if (col - i >= -W && col - i <= W) A[(size_t)i * (2 * W + 1) + (col - i + W)] = M[r];
+        }
+        for (int r = 0; r <= p; ++r) {
+            const int j = s_old - p + r;
+            for (int l = 0; l < lines; ++l) {
+                const double *src = &H[(size_t)(line_base(l) + j * stride) * nch];
+                for (int c = 0; c < nch; ++c) R[(size_t)i * K + l * nch + c] += N[r] * src[c];
+            }
+        }
+    }
+    // banded elimination without pivoting, then back substitution
+    auto a = [&](int r, int c) -> double & { return A[(size_t)r * (2 * W + 1) + (c - r + W)]; };
+    for (int c = 0; c < n_new; ++c) {
+        for (int r = c + 1; r <= std::min(n_new - 1, c + W); ++r) {
+            const double f = a(r, c) / a(c, c);
+            if (f == 0.0) continue;
+            for (int k = c; k <= std::min(n_new - 1, c + W); ++k) a(r, k) -= f * a(c, k);
+            for (int k = 0; k < K; ++k) R[(size_t)r * K + k] -= f * R[(size_t)c * K + k];
+        }
+    }
+    for (int r = n_new - 1; r >= 0; --r) {
+        for (int k = r + 1; k <= std::min(n_new - 1, r + W); ++k) {
+            const double f = a(r, k);
+            if (f == 0.0) continue;
+            for (int q = 0; q < K; ++q) R[(size_t)r * K + q] -= f * R[(size_t)k * K + q];
+        }
+        const double inv = 1.0 / a(r, r);
+        for (int q = 0; q < K; ++q) R[(size_t)r * K + q] *= inv;
+    }
+    // scatter back in the new layout
+    int nn[3] = {n[0], n[1], n[2]};
+    nn[d] = n_new;
+    const int stride_new = d == 0 ? 1 : (d == 1 ? nn[0] : nn[0] * nn[1]);
+    std::vector<double> Hn((size_t)nn[0] * nn[1] * nn[2] * nch);
+    for (int l = 0; l < lines; ++l) {
+        const int inner = stride_new, outer = l / inner;
+        const int base = (l % inner) + outer * inner * n_new;
+        for (int i = 0; i < n_new; ++i)
+            for (int c = 0; c < nch; ++c) Hn[(size_t)(base + i * stride_new) * nch + c] = R[(size_t)i * K + l * nch + c];
+    }
+    H.swap(Hn);
+    n[0] = nn[0]; n[1] = nn[1]; n[2] = nn[2];
+}
+
+// A block with the same spline in one degree (the largest of its directions) in
+// all three directions; owns its arrays.
+struct IsoPatch {
+    std::vector<double> knots[3], cp, scalar;
+    ivr_patch_desc desc;
+};
+
+static void make_isotropic(const ivr_patch_desc &P, IsoPatch &out) {
+    const int Pm = std::max(P.degree[0], std::max(P.degree[1], P.degree[2]));
+    int n[3] = {P.ncp[0], P.ncp[1], P.ncp[2]};
+    const size_t N = (size_t)n[0] * n[1] * n[2];
+    // homogeneous channels (w x, w y, w z, w, w rho)
+    std::vector<double> H(N * 5);
+    for (size_t q = 0; q < N; ++q) {
+        const double w = P.rational ? P.cp[4 * q + 3] : 1.0;
+        for (int c = 0; c < 3; ++c) H[5 * q + c] = w * P.cp[4 * q + c];
+        H[5 * q + 3] = w;
+        H[5 * q + 4] = w * P.scalar[q];
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (P.degree[d] == Pm) {
+            out.knots[d].assign(P.knots[d], P.knots[d] + P.ncp[d] + P.degree[d] + 1);
+        } else {
+            elevate_direction(H, 5, n, d, P.knots[d], P.degree[d], Pm, out.knots[d]);
+        }
+    }
+    const size_t M = (size_t)n[0] * n[1] * n[2];
+    out.cp.resize(4 * M);
+    out.scalar.resize(M);
+    for (size_t q = 0; q < M; ++q) {
+        const double w = H[5 * q + 3];
+        for (int c = 0; c < 3; ++c) out.cp[4 * q + c] = H[5 * q + c] / w;
+        out.cp[4 * q + 3] = P.rational ? w : 1.0;
+        out.scalar[q] = H[5 * q + 4] / w;
+    }
+    out.desc = P;
+    for (int d = 0; d < 3; ++d) {
+        out.desc.degree[d] = Pm;
+        out.desc.ncp[d] = n[d];
+        out.desc.knots[d] = out.knots[d].data();
+    }
+    out.desc.cp = out.cp.data();
+    out.desc.scalar = out.scalar.data();
+}
+
+// Splits a block (one degree P in every direction) at every interior knot of
+// multiplicity P, where the spline is only C0: the pieces share the control
+// layer that the spline passes through there, so together they are the block.
+// Pieces without such knots are appended to out (their arrays in store).
+static void split_at_c0(const ivr_patch_desc &P, std::deque<IsoPatch> &store, std::vector<ivr_patch_desc> &out) {
+    const int p = P.degree[0];
+    for (int d = 0; d < 3; ++d) {
+        const int n = P.ncp[d];
+        const double *t = P.knots[d];
+        for (int i = p + 1; i < n; ++i) {
+            int mult = 1;
+            while (i + mult < n && t[i + mult] == t[i]) ++mult;
+            if (mult < p) {
+                i += mult - 1;
+                continue;
+            }
+            // knots t[i .. i+p-1] = u; the spline passes through control layer i-1
+            const int n0 = P.ncp[0], n1 = P.ncp[1];
+            int nl[3] = {P.ncp[0], P.ncp[1], P.ncp[2]}, nr[3] = {P.ncp[0], P.ncp[1], P.ncp[2]};
+            nl[d] = i;
+            nr[d] = n - i + 1;
+            IsoPatch *piece[2];
+            for (int side = 0; side < 2; ++side) {
+                store.emplace_back();
+                IsoPatch &Q = store.back();
+                const int *nn = side ? nr : nl;
+                const int off = side ? i - 1 : 0;
+                for (int e = 0; e < 3; ++e) {
+                    if (e != d) {
+                        Q.knots[e].assign(P.knots[e], P.knots[e] + P.ncp[e] + p + 1);
+                    } else if (side == 0) {
+                        Q.knots[e].assign(t, t + i);
+                        Q.knots[e].insert(Q.knots[e].end(), p + 1, t[i]);
+                    } else {
+                        Q.knots[e].assign(p + 1, t[i]);
+                        Q.knots[e].insert(Q.knots[e].end(), t + i + p, t + n + p + 1);
+                    }
+                }
+                const size_t N = (size_t)nn[0] * nn[1] * nn[2];
+                Q.cp.resize(4 * N);
+                Q.scalar.resize(N);
+                for (int k = 0; k < nn[2]; ++k)
+                    for (int j = 0; j < nn[1]; ++j)
+                        for (int a = 0; a < nn[0]; ++a) {
+                            int src[3] = {a, j, k};
+                            src[d] += off;
+                            const size_t si = (size_t)src[0] + (size_t)n0 * (src[1] + (size_t)n1 * src[2]);
+                            const size_t di = (size_t)a + (size_t)nn[0] * (j + (size_t)nn[1] * k);
+                            for (int c = 0; c < 4; ++c) Q.cp[4 * di + c] = P.cp[4 * si + c];
+                            Q.scalar[di] = P.scalar[si];
+                        }
+                Q.desc = P;
+                for (int e = 0; e < 3; ++e) {
+                    Q.desc.ncp[e] = nn[e];
+                    Q.desc.knots[e] = Q.knots[e].data();
+                }
+                Q.desc.cp = Q.cp.data();
+                Q.desc.scalar = Q.scalar.data();
+                piece[side] = &Q;
+            }
+            split_at_c0(piece[0]->desc, store, out);
+            split_at_c0(piece[1]->desc, store, out);
+            return;
+        }
+    }
+    out.push_back(P);
+}
+
 }  // namespace
 
 extern "C" {
@@ -521,6 +724,7 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->rho_step = 0.1;
     o->cand_per_pixel = 8;
     o->det_singular = 1e-6;
+    o->drift_tol = 1e-5;
 }
 
 static ivr_status ensure_views(ivr_ctx *c, int n);
@@ -558,7 +762,8 @@ ivr_status ivr_create(ivr_ctx **out, int32_t device, void *hip_stream) {
     // the view table and the pinned counter staging exist from the start, so that
     // ivr_render_noalloc allocates nothing
     if (hipHostMalloc((void **)&c->h_ctr, sizeof(unsigned long long) * C_COUNT) != hipSuccess ||
-        ensure_views(c, 8) != IVR_OK) {
+        hipHostMalloc((void **)&c->h_qs, 2 * sizeof(uint32_t)) != hipSuccess ||
+        hipEventCreateWithFlags(&c->qs_ev, hipEventDisableTiming) != hipSuccess || ensure_views(c, 8) != IVR_OK) {
         ivr_destroy(c);
         return IVR_ENOMEM;
     }
@@ -607,7 +812,7 @@ static void free_cand_lists(ivr_ctx *c) {
 static void free_frame(ivr_ctx *c) {
     drop_graphs(c);
     free_cand_lists(c);
-    dfree(c->d_segs); dfree(c->d_results); dfree(c->d_pixseg); dfree(c->d_seg_kr); dfree(c->d_order);
+    dfree(c->d_segs); dfree(c->d_pixseg); dfree(c->d_seg_kr); dfree(c->d_order);
     c->pix_cap = c->seg_cap = c->seg_bytes_cap = 0;
 }
 
@@ -623,6 +828,8 @@ void ivr_destroy(ivr_ctx *c) {
     dfree(c->d_views);
     if (c->h_views) (void)hipHostFree(c->h_views);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    if (c->h_qs) (void)hipHostFree(c->h_qs);
+    if (c->qs_ev) (void)hipEventDestroy(c->qs_ev);
     if (c->views_copied) (void)hipEventDestroy(c->views_copied);
     if (c->capture) (void)hipStreamDestroy(c->capture);
     for (auto &e : c->ev)
@@ -660,6 +867,38 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
         std::string e = validate_patch(patches[i], i);
         if (!e.empty()) return fail(c, IVR_EINVAL, e);
     }
+    // Blocks whose directions differ in degree are raised to their largest degree,
+    // and blocks are split at interior knots of full multiplicity (where the map
+    // and rho are only C0), both exactly: the kernels see one degree per block
+    // and smooth blocks, joined at the splits as at any conforming interface.
+    // Block indices from here on (segments, MLPs) are those of the split model.
+    std::deque<IsoPatch> iso;
+    std::vector<ivr_patch_desc> descs;
+    {
+        std::vector<int> sizes(n_models, 0);
+        for (int i = 0; i < n; ++i) {
+            ivr_patch_desc P = patches[i];
+            if (P.degree[0] != P.degree[1] || P.degree[0] != P.degree[2]) {
+                iso.emplace_back();
+                make_isotropic(P, iso.back());
+                P = iso.back().desc;
+            }
+            const size_t before = descs.size();
+            split_at_c0(P, iso, descs);
+            sizes[model_of[i]] += (int)(descs.size() - before);
+        }
+        if (descs.size() > kPatchMask) return fail(c, IVR_EINVAL, "more than 2^20-1 blocks after splitting");
+        n = (int32_t)descs.size();
+        model_of.assign(n, 0);
+        int at = 0;
+        for (int mi = 0; mi < n_models; ++mi) {
+            models[mi].begin = at;
+            at += sizes[mi];
+            models[mi].end = at;
+            for (int i = models[mi].begin; i < models[mi].end; ++i) model_of[i] = mi;
+        }
+    }
+    patches = descs.data();
     IVR_HIP(c, hipSetDevice(c->device));
     // scale of each model: diagonal of the box of its (projected) control points
     for (auto &M : models) {
@@ -902,8 +1141,10 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     const std::vector<uint32_t> zeros(n, 0u);
     // allocate and copy, then swap in
     ivr_ctx tmp;
+    size_t model_bytes = 0;
     auto up = [&](auto *&dst, const auto &vec) -> bool {
         using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+        model_bytes += sizeof(T) * std::max<size_t>(vec.size(), 1);
         if (hipMalloc((void **)&dst, sizeof(T) * std::max<size_t>(vec.size(), 1)) != hipSuccess) return false;
         return hipMemcpy((void *)dst, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice) == hipSuccess;
     };
@@ -936,6 +1177,7 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     tmp.d_rho64 = nullptr; tmp.d_knots32 = nullptr; tmp.d_knots64 = nullptr; tmp.d_elems = nullptr;
     drop_graphs(c);
     c->npatch = n;
+    c->model_bytes = model_bytes;
     c->nelem = (int)elems.size();
     c->scale = scale;
     c->class_mask = class_mask;
@@ -1047,6 +1289,8 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
     if (!(o.det_fp64_threshold >= 0)) return fail(c, IVR_EINVAL, "det_fp64_threshold must be >= 0");
     if (!(o.det_singular >= 0 && std::isfinite(o.det_singular)))
         return fail(c, IVR_EINVAL, "det_singular must be finite and >= 0");
+    if (!(o.drift_tol >= 0 && std::isfinite(o.drift_tol)))
+        return fail(c, IVR_EINVAL, "drift_tol must be finite and >= 0");
     if (o.max_fragments < 2 || o.max_fragments > kFragCap)
         return fail(c, IVR_EINVAL, "max_fragments outside 2..64");
     if (o.rho_interp != IVR_RHO_LINEAR && o.rho_interp != IVR_RHO_HERMITE)
@@ -1074,6 +1318,7 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
     fp.early_termd = o.early_term; fp.early_term = (float)o.early_term;
     fp.det_thrd = o.det_fp64_threshold; fp.det_thr = (float)o.det_fp64_threshold;
     fp.det_singd = o.det_singular; fp.det_sing = (float)o.det_singular;
+    fp.drift_told = o.drift_tol; fp.drift_tol = (float)o.drift_tol;   // relative to the model's scale
     fp.n_super = o.n_super;
     fp.max_frag = o.max_fragments;
     fp.hermite = o.rho_interp == IVR_RHO_HERMITE ? 1 : 0;
@@ -1083,14 +1328,12 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
     return IVR_OK;
 }
 
-static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
-    const size_t seg_cap = pixels * kSegCap;
+static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, size_t seg_cap, bool fp64) {
     const size_t seg_bytes = seg_cap * (fp64 ? sizeof(Seg<double>) : sizeof(Seg<float>));
-    if (pixels <= c->pix_cap && seg_bytes <= c->seg_bytes_cap) return IVR_OK;
+    if (pixels <= c->pix_cap && seg_cap <= c->seg_cap && seg_bytes <= c->seg_bytes_cap) return IVR_OK;
     IVR_HIP(c, hipStreamSynchronize(c->stream));
     free_frame(c);
     if (hipMalloc(&c->d_segs, seg_bytes) != hipSuccess ||
-        hipMalloc((void **)&c->d_results, sizeof(float4) * seg_cap) != hipSuccess ||
         hipMalloc((void **)&c->d_pixseg, sizeof(uint2) * pixels) != hipSuccess ||
         hipMalloc((void **)&c->d_seg_kr, sizeof(uint2) * seg_cap) != hipSuccess ||
         hipMalloc((void **)&c->d_order, sizeof(uint32_t) * seg_cap) != hipSuccess) {
@@ -1104,18 +1347,19 @@ static ivr_status ensure_frame(ivr_ctx *c, size_t pixels, bool fp64) {
 }
 
 // Buffers of the two-pass fragment kernel: `want` candidates (a lane keeps at
-// most 64), with their network queries and seeds; at least 1024.  Rays whose
-// candidates do not fit are traversed again by the solve pass (box seeds).
-static ivr_status ensure_cand_lists(ivr_ctx *c, size_t want, size_t tiles) {
+// most 64), with their network queries and seeds when MLP seeds are used; at
+// least 1024.  Rays whose candidates do not fit are traversed again by the solve
+// pass (box seeds).
+static ivr_status ensure_cand_lists(ivr_ctx *c, size_t want, size_t tiles, bool mlp) {
     const size_t cap = std::max<size_t>(want, 1024);
-    if (tiles <= c->mq_tiles && cap <= c->mq.c_cap) return IVR_OK;
+    if (tiles <= c->mq_tiles && cap <= c->mq.c_cap && (!mlp || c->mq.query)) return IVR_OK;
     IVR_HIP(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
     free_cand_lists(c);
     if (cap > 0xFFFFFFFEull || tiles * 64 > 0xFFFFFFFFull)
         return fail(c, IVR_EOVERFLOW, "batch too large for the candidate buffers");
-    if (hipMalloc((void **)&c->mq.query, sizeof(float4) * cap) != hipSuccess ||
-        hipMalloc((void **)&c->mq.seed, sizeof(float4) * cap) != hipSuccess ||
+    if ((mlp && (hipMalloc((void **)&c->mq.query, sizeof(float4) * cap) != hipSuccess ||
+                 hipMalloc((void **)&c->mq.seed, sizeof(float4) * cap) != hipSuccess)) ||
         hipMalloc((void **)&c->mq.clist, sizeof(uint2) * cap) != hipSuccess ||
         hipMalloc((void **)&c->mq.plist, sizeof(uint32_t) * cap) != hipSuccess ||
         hipMalloc((void **)&c->mq.crange, sizeof(uint2) * tiles * 64) != hipSuccess) {
@@ -1146,6 +1390,25 @@ static ivr_status ensure_views(ivr_ctx *c, int n) {
     return IVR_OK;
 }
 
+// The segment and candidate totals of the last render, once its readback has
+// arrived (no waiting): the per-pixel ratios that size the next frame's buffers.
+static void poll_counts(ivr_ctx *c) {
+    if (!c->qs_pending || hipEventQuery(c->qs_ev) != hipSuccess) return;
+    c->qs_pending = false;
+    if (c->qs_pixels == 0) return;
+    c->seg_ratio = std::max(c->seg_ratio, (double)c->h_qs[0] / (double)c->qs_pixels);
+    c->cand_ratio = std::max(c->cand_ratio, (double)c->h_qs[1] / (double)c->qs_pixels);
+}
+
+// After a render of the context's buffers: copy its totals to pinned memory.
+static ivr_status enqueue_counts(ivr_ctx *c, const QueueState *qs, uint64_t pixels) {
+    IVR_HIP(c, hipMemcpyAsync(c->h_qs, qs, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    IVR_HIP(c, hipEventRecord(c->qs_ev, c->stream));
+    c->qs_pixels = pixels;
+    c->qs_pending = true;
+    return IVR_OK;
+}
+
 static Model device_model(ivr_ctx *c) {
     Model m;
     m.patches = c->d_patches; m.cp32 = c->d_cp32; m.rho32 = c->d_rho32; m.cp64 = c->d_cp64;
@@ -1164,6 +1427,7 @@ struct HostView {
     const ivr_transfer_fn *tf;
     int model;
     float *rgba, *depth;
+    uint32_t *flags;
 };
 struct Batch {
     int n = 0;
@@ -1178,7 +1442,6 @@ struct Batch {
 struct FrameBufs {
     void *segs = nullptr;
     size_t seg_cap = 0;
-    float4 *results = nullptr;
     uint2 *pixseg = nullptr, *seg_kr = nullptr;
     uint32_t *order = nullptr;
     QueueState *qs = nullptr;
@@ -1222,6 +1485,7 @@ static ivr_status fill_views(ivr_ctx *c, const HostView *hv, int n, const ivr_re
         r.pix_begin = (uint32_t)pixels;
         r.rgba = hv[v].rgba;
         r.depth = hv[v].depth;
+        r.flags = hv[v].flags;
         tiles += (uint64_t)r.tiles_x * ((hv[v].cam->height + th - 1) / th);
         pixels += (uint64_t)hv[v].cam->width * hv[v].cam->height;
         b.class_mask |= M.class_mask;
@@ -1246,18 +1510,26 @@ static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr
     if (st != IVR_OK) return st;
     st = fill_views(c, hv, n, o, collect, lc, b);
     if (st != IVR_OK) return st;
-    if ((uint64_t)b.n_pixels * kSegCap > 0xFFFFFFFFull)
-        return fail(c, IVR_EOVERFLOW, "batch too large for 32-bit segment indices");
-    st = ensure_frame(c, b.n_pixels, b.fp64);
+    // Segment slots: 2.5 per pixel, or 1.2 times the most per pixel a render of
+    // this context needed (at most 32 per pixel, the cap per ray); candidates: 2 per
+    // pixel or 1.25 times the most needed, at most cand_per_pixel.  A render whose
+    // segments do not fit drops and counts them (segment_overflow, per-pixel
+    // flags) and makes the next call grow the buffers.
+    poll_counts(c);
+    const double px = (double)b.n_pixels;
+    const double seg_pp = std::min((double)kSegCap, std::max(2.5, 1.2 * c->seg_ratio));
+    const double slots = std::max(std::ceil(px * seg_pp), (double)(1u << 20));
+    if (slots > 4294967040.0) return fail(c, IVR_EOVERFLOW, "batch too large for 32-bit segment indices");
+    st = ensure_frame(c, b.n_pixels, (size_t)slots, b.fp64);
     if (st != IVR_OK) return st;
-    const size_t want = (size_t)b.n_pixels * (size_t)o.cand_per_pixel;
-    st = ensure_cand_lists(c, want, b.n_tiles);
+    const size_t limit = (size_t)b.n_pixels * (size_t)o.cand_per_pixel;
+    const double cand_pp = std::max(2.0, 1.25 * c->cand_ratio);
+    st = ensure_cand_lists(c, std::min(limit, (size_t)std::ceil(px * cand_pp)), b.n_tiles, b.mlp);
     if (st != IVR_OK) return st;
-    b.c_cap = (uint32_t)want;   // <= the allocation
+    b.c_cap = (uint32_t)std::min<size_t>(limit, c->mq.c_cap);
     fb = FrameBufs();
     fb.segs = c->d_segs;
     fb.seg_cap = c->seg_cap;
-    fb.results = c->d_results;
     fb.pixseg = c->d_pixseg;
     fb.seg_kr = c->d_seg_kr;
     fb.order = c->d_order;
@@ -1295,10 +1567,10 @@ static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const FrameBufs &fb, 
         ia.pcur = fb.pcur;
         ia.max_cp = c->cls_max_cp[k];
         ia.max_tab = c->cls_max_tab[k];
-        IVR_HIP(c, launch_integrate(b.fp64, k, m, fb.views, b.n, fb.segs, ia, fb.results, fb.ctr, c->n_cu, lc, s));
+        IVR_HIP(c, launch_integrate(b.fp64, k, m, fb.views, b.n, fb.segs, ia, fb.ctr, c->n_cu, lc, s));
     }
     if (ev) IVR_HIP(c, hipEventRecord(ev[2], s));
-    IVR_HIP(c, launch_merge(fb.views, b.n, b.n_pixels, fb.pixseg, fb.results, s));
+    IVR_HIP(c, launch_merge(fb.views, b.n, b.n_pixels, fb.pixseg, fb.segs, b.fp64, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[3], s));
     return IVR_OK;
 }
@@ -1347,21 +1619,30 @@ static ivr_status pick_events(ivr_ctx *c, bool stats, bool timing, hipEvent_t *&
 }
 
 // Direct launches (no graph) of a batch of host views.
+// With stats the call is synchronous anyway: a render whose segments did not fit
+// the buffers is run once more after they have grown.
 static ivr_status render_direct(ivr_ctx *c, const HostView *hv, int n, const ivr_render_opts &o,
                                 ivr_stats *stats, const LaunchCfg &lc) {
-    Batch b;
-    FrameBufs fb;
-    ivr_status st = prepare_batch(c, hv, n, o, stats != nullptr, lc, b, fb);
-    if (st != IVR_OK) return st;
-    hipEvent_t *ev;
-    st = pick_events(c, stats != nullptr, o.timing != 0, ev);
-    if (st != IVR_OK) return st;
-    st = copy_views(c, n, fb.views);
-    if (st != IVR_OK) return st;
-    st = launch_batch(c, b, fb, lc, ev, c->stream);
-    if (st != IVR_OK) return st;
-    if (stats) return read_stats(c, fb.ctr, stats);
-    return IVR_OK;
+    for (int attempt = 0;; ++attempt) {
+        Batch b;
+        FrameBufs fb;
+        ivr_status st = prepare_batch(c, hv, n, o, stats != nullptr, lc, b, fb);
+        if (st != IVR_OK) return st;
+        hipEvent_t *ev;
+        st = pick_events(c, stats != nullptr, o.timing != 0, ev);
+        if (st != IVR_OK) return st;
+        st = copy_views(c, n, fb.views);
+        if (st != IVR_OK) return st;
+        st = launch_batch(c, b, fb, lc, ev, c->stream);
+        if (st != IVR_OK) return st;
+        st = enqueue_counts(c, fb.qs, b.n_pixels);
+        if (st != IVR_OK) return st;
+        if (!stats) return IVR_OK;
+        st = read_stats(c, fb.ctr, stats);
+        if (st != IVR_OK) return st;
+        poll_counts(c);   // the stream has finished: the totals are here
+        if (c->h_qs[0] <= fb.seg_cap || attempt > 0) return IVR_OK;
+    }
 }
 
 ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *tf,
@@ -1371,7 +1652,7 @@ ivr_status ivr_render(ivr_ctx *c, const ivr_camera *cam, const ivr_transfer_fn *
     ivr_render_opts o;
     ivr_default_opts(&o);
     if (opts) o = *opts;
-    const HostView hv = {cam, tf, 0, rgba_dev, depth_dev};
+    const HostView hv = {cam, tf, 0, rgba_dev, depth_dev, nullptr};
     ivr_status st = render_direct(c, &hv, 1, o, stats, c->lc);
     if (st == IVR_OK) c->err.clear();
     return st;
@@ -1393,7 +1674,7 @@ ivr_status ivr_render_noalloc(ivr_ctx *c, const ivr_camera *cam, const ivr_trans
         return fail(c, IVR_EOVERFLOW, "more than 1048576 pixels for the scratch array");
     if (c->has_model && c->npatch > kNoAllocMaxBlocks)
         return fail(c, IVR_EOVERFLOW, "more than 65536 blocks for the scratch array");
-    const HostView hv = {cam, tf, 0, rgba_dev, depth_dev};
+    const HostView hv = {cam, tf, 0, rgba_dev, depth_dev, nullptr};
     Batch b;
     ivr_status st = fill_views(c, &hv, 1, o, stats != nullptr, c->lc, b);
     if (st != IVR_OK) return st;
@@ -1429,11 +1710,10 @@ ivr_status ivr_render_noalloc(ivr_ctx *c, const ivr_camera *cam, const ivr_trans
     }
     fb.mq.c_cap = (uint32_t)c_cap;
     const size_t seg_bytes = b.fp64 ? sizeof(Seg<double>) : sizeof(Seg<float>);
-    const size_t slot = seg_bytes + sizeof(float4) + sizeof(uint2) + sizeof(uint32_t);
+    const size_t slot = seg_bytes + sizeof(uint2) + sizeof(uint32_t);
     const size_t left = kScratchBytes - std::min(kScratchBytes, off + slack);
     fb.seg_cap = std::min<size_t>((size_t)b.n_pixels * kSegCap, left / slot);
     fb.segs = take(seg_bytes * fb.seg_cap);
-    fb.results = reinterpret_cast<float4 *>(take(sizeof(float4) * fb.seg_cap));
     fb.seg_kr = reinterpret_cast<uint2 *>(take(sizeof(uint2) * fb.seg_cap));
     fb.order = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * fb.seg_cap));
     if (off > kScratchBytes || fb.seg_cap == 0)
@@ -1461,7 +1741,7 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
     std::vector<HostView> hv(n_views);
     for (int v = 0; v < n_views; ++v) {
         hv[v] = {&views[v].cam, views[v].tf ? views[v].tf : tf, views[v].model, views[v].rgba_dev,
-                 views[v].depth_dev};
+                 views[v].depth_dev, views[v].flags_dev};
         if (!hv[v].tf) return fail(c, IVR_EINVAL, "a view has no transfer function");
     }
     ivr_status st;
@@ -1507,6 +1787,8 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
         it = c->graphs.emplace(key, ge).first;
     }
     IVR_HIP(c, hipGraphLaunch(it->second, c->stream));
+    st = enqueue_counts(c, fb.qs, b.n_pixels);
+    if (st != IVR_OK) return st;
     c->err.clear();
     return IVR_OK;
 }
@@ -1522,7 +1804,7 @@ ivr_status ivr_autotune(ivr_ctx *c, const ivr_view *views, int32_t n_views, cons
     std::vector<HostView> hv(n_views);
     for (int v = 0; v < n_views; ++v) {
         hv[v] = {&views[v].cam, views[v].tf ? views[v].tf : tf, views[v].model, views[v].rgba_dev,
-                 views[v].depth_dev};
+                 views[v].depth_dev, views[v].flags_dev};
         if (!hv[v].tf) return fail(c, IVR_EINVAL, "a view has no transfer function");
     }
     // time a shape: best of `reps` batches, per phase, from the stats events
@@ -1591,6 +1873,18 @@ ivr_status ivr_autotune(ivr_ctx *c, const ivr_view *views, int32_t n_views, cons
     rep.ms_after = bf + bi;
     if (report) *report = rep;
     c->err.clear();
+    return IVR_OK;
+}
+
+ivr_status ivr_device_bytes(ivr_ctx *c, uint64_t *model_bytes, uint64_t *frame_bytes) {
+    if (!c) return IVR_EINVAL;
+    const size_t tiles = c->mq_tiles;
+    const size_t frame = c->seg_bytes_cap + c->seg_cap * (sizeof(uint2) + sizeof(uint32_t)) +
+                         c->pix_cap * sizeof(uint2) +
+                         (size_t)c->mq.c_cap * ((c->mq.query ? 2 * sizeof(float4) : 0) + sizeof(uint2) + sizeof(uint32_t)) +
+                         tiles * 64 * sizeof(uint2);
+    if (model_bytes) *model_bytes = c->model_bytes;
+    if (frame_bytes) *frame_bytes = frame;
     return IVR_OK;
 }
 

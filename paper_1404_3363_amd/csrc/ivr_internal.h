@@ -17,11 +17,11 @@ hipError_t launch_block_sort(const QueueState *qs, uint32_t seg_cap, const uint2
                              uint32_t *pcur, uint32_t *order, int n_cu, hipStream_t st);
 
 hipError_t launch_integrate(bool fp64, int klass, const Model &m, const ViewRec *views, int n_views,
-                            const void *segs, const IntegrateArgs &a, float4 *results,
+                            void *segs, const IntegrateArgs &a,
                             unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st);
 
 hipError_t launch_merge(const ViewRec *views, int n_views, uint32_t n_pixels, const uint2 *pixseg,
-                        const float4 *results, hipStream_t st);
+                        const void *segs, bool fp64, hipStream_t st);
 
 hipError_t launch_clear(QueueState *qs, unsigned long long *ctr, bool collect, uint32_t *pcount, int npatch,
                         hipStream_t st);

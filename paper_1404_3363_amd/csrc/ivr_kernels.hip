@@ -205,7 +205,7 @@ template <int P, bool RAT, typename RN>
 __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E, const double (&od)[3],
                           const double (&dd)[3], const float (&of)[3], const float (&df)[3],
                           const FrameParams &fp, const float (&mseed)[3], float T1, RootRec<RN> &out,
-                          bool &again, u32 &n_iter, u32 &n_polish, u32 &n_fail) {
+                          bool &again, u32 &n_iter, u32 &n_polish) {
     const int face = E.face;
     const FaceView<RN> fv = face_view<RN>(Pd, face);
     const Arrays<RN> ar = arrays_of(m, RN(0));
@@ -341,7 +341,6 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
         again = tangent && !second;
         return;
     }
-    if (!second) ++n_fail;   // Newton converged from no seed
 }
 
 // The root of one candidate in out (info stays ~0 when there is none); T1 < 0
@@ -351,16 +350,16 @@ __device__ __forceinline__ void face_root_any(const Model &m, const DevPatch &Pd
                                               const double (&od)[3], const double (&dd)[3],
                                               const float (&of)[3], const float (&df)[3],
                                               const FrameParams &fp, const float (&ms)[3], float T1,
-                                              RootRec<R> &out, bool &again, u32 &ni, u32 &np, u32 &nf) {
+                                              RootRec<R> &out, bool &again, u32 &ni, u32 &np) {
     out.info = out.tinfo = 0xFFFFFFFFu;
     again = false;
     switch (Pd.deg * 2 + Pd.rational) {
-    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
-    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
-    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
-    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
-    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
-    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np, nf); break;
+    case 2: face_root<1, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    case 3: face_root<1, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    case 4: face_root<2, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    case 5: face_root<2, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    case 6: face_root<3, false, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
+    default: face_root<3, true, R>(m, Pd, E, od, dd, of, df, fp, ms, T1, out, again, ni, np); break;
     }
 }
 
@@ -446,8 +445,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         df[q] = float(dd[q]);
         inv[q] = 1.0f / df[q];
     }
-    u32 c_anom = 0, c_fovf = 0, c_sovf = 0, c_box = 0, c_newton = 0, c_iter = 0, c_pol = 0, c_mlp = 0,
-        c_nfail = 0;
+    u32 c_anom = 0, c_fovf = 0, c_sovf = 0, c_box = 0, c_newton = 0, c_iter = 0, c_pol = 0, c_mlp = 0;
 
     // 1. face elements whose oriented box the ray hits (block and face boxes
     //    first) become Newton seeds; 2. the seeds are solved (a wave's 64 at a
@@ -517,7 +515,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                     RootRec<R> rr;
                     bool again;
                     face_root_any<R>(m, m.patches[E.patch], E, od, dd, of, df, fp, ms, T1, rr, again, c_iter,
-                                     c_pol, c_nfail);
+                                     c_pol);
                     add_root(rr);
                     if (!again) break;
                     T1 = float(rr.t);
@@ -665,7 +663,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                         RootRec<R> out;
                         bool again;
                         face_root_any<R>(m, m.patches[E.patch], E, od, odd, of, odf, fp, ms, T1, out, again,
-                                         c_iter, c_pol, c_nfail);
+                                         c_iter, c_pol);
                         if (s == 0) {
                             s_res[j] = out;
                         } else if (out.info != 0xFFFFFFFFu) {   // to the pass's short list of second roots
@@ -826,6 +824,10 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     if (valid) {
         pixseg[vr.pix_begin + pixel] = make_uint2(first, (u32)nseg);
         if (vr.depth) vr.depth[pixel] = nseg ? float(ft(pin[0])) : INFINITY;
+        // the pixel's flags start here; the integrator ORs in its segments' flags
+        if (vr.flags)
+            vr.flags[pixel] = (c_anom ? (u32)IVR_FLAG_ANOMALY : 0u) | (c_fovf ? (u32)IVR_FLAG_FRAGMENT_OVERFLOW : 0u) |
+                              (c_sovf ? (u32)IVR_FLAG_SEGMENT_OVERFLOW : 0u);
     }
     if (fp.collect) {
         flush_counter(ctr, C_RAYS, valid ? 1 : 0);
@@ -839,9 +841,12 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         flush_counter(ctr, C_FACE_NEWTON_ITER, c_iter);
         flush_counter(ctr, C_FP64_POLISH, c_pol);
         flush_counter(ctr, C_MLP_QUERIES, c_mlp);
-        flush_counter(ctr, C_FACE_FAIL, c_nfail);
     }
 }
+
+// Integrator-internal bit of a segment's flags: a drift restart happened since
+// the last accepted RK step (not reported).
+constexpr uint32_t kJustRestarted = 1u << 31;
 
 __device__ __forceinline__ float pow_fifth(float x) { return exp2f(0.2f * __log2f(x)); }
 __device__ __forceinline__ double pow_fifth(double x) { return pow(x, 0.2); }
@@ -941,9 +946,8 @@ __global__ __launch_bounds__(256) void k_block_scatter(const QueueState *qs, u32
 // block with work, cyclically in class order.
 template <int P, bool RAT, typename R, bool LDS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_integrate(
-    Model m, const ViewRec *views, int n_views, const Seg<R> *segs, const u32 *order, const u32 *pperm,
-    int q_begin, int q_end, const u32 *pbase, const u32 *pcount, u32 *pcur, int max_cp, float4 *results,
-    u64 *ctr) {
+    Model m, const ViewRec *views, int n_views, Seg<R> *segs, const u32 *order, const u32 *pperm,
+    int q_begin, int q_end, const u32 *pbase, const u32 *pcount, u32 *pcur, int max_cp, u64 *ctr) {
     using K = RKF<R>;
     // LDS: per-view transfer functions and step bounds (a lane's segment may
     // belong to any view of the batch), then the staged block
@@ -993,9 +997,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     // Eq. (degeneracyfix) state: shrink > 0 (the attempt) while Newton seeks the
     // preimage of the entry moved delta along the ray; gin is then that point (it
     // stays on the ray, so V keeps its meaning)
+    // shrink < 0: a drift restart, Newton on phi(p) = gin.  gin is the ray point at
+    // the current arc length s (V_perp only takes its distance from the ray, so
+    // any ray point serves; it moves with every accepted step).  fl: IVR_FLAG_*
+    // bits of the lane's segment.
     int shrink = 0, newton_it = 0;
     R delta = 0, rho_in = 0;
-    u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_cap = 0, c_sub = 0, c_deg = 0, c_mlp = 0;
+    u32 fl = 0;
+    // frequent events are counted per lane and summed per wave at the end; rare
+    // ones (iteration cap, singular ends, restarts) with one atomic each
+    u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_sub = 0;
+    auto count_rare = [&](int idx) __attribute__((always_inline)) {
+        if (fp.collect) atomicAdd(ctr + idx, 1ull);
+    };
+    // drift threshold relative to the scale (0: no check); per lane it is at least
+    // twice the restart Newton's own tolerance, so that a converged restart never
+    // triggers another
+    const R drel_set = sizeof(R) == 4 ? R(fp.drift_tol) : R(fp.drift_told);
+    const R drel = drel_set > R(0) ? fmax(drel_set, sizeof(R) == 4 ? R(4e-6) : R(2e-12)) : R(0);
 
     for (;;) {   // blocks
         if (threadIdx.x == 0) {
@@ -1071,7 +1090,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     // singular J at the exit (flagged by a NaN slope): stop 1e-4 of
                     // the chord short of it and close with the exit's rho
                     Lend = isfinite(m_out) ? L : L - R(1e-4) * L;
-                    c_deg += !isfinite(m_out);
+                    if (!isfinite(m_out)) count_rare(C_DEGENERATE);
                     // next to a singular face p' and rho vary like sqrt of the
                     // distance: half the step bound on such a segment
                     if (!isfinite(m_out)) hmax *= R(0.5);
@@ -1081,6 +1100,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     rejected = false;
                     iters = 0;
                     shrink = 0;
+                    fl = isfinite(m_out) ? 0u : (u32)IVR_FLAG_DEGENERATE;
                     active = true;
                 }
             }
@@ -1091,13 +1111,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         bool done = false;
         // stage 1 at the current point; also samples rho and d rho/ds there.  While
         // shrinking, the same evaluation gives the Newton step J^-1 (gin - phi(p)).
-        R k1[3], k2[3], k3[3], k4[3], k5[3], k6[3], rho_cur = R(0), grho[3], res2 = R(0);
+        R k1[3], k2[3], k3[3], k4[3], k5[3], k6[3], rho_cur = R(0), grho[3], res2 = R(0), xw[3];
         const bool shrinking = shrink != 0;
         const R det1 = eval_W<P, RAT, 2, R, LDS>(pv, ar, p, gin, d, cperp, dthr, k1, rho_cur,
-                                         grho, c_fp64, shrinking, res2);
+                                         grho, c_fp64, shrinking, res2, xw);
         ++c_w;
         const R m_cur = dot3(grho, k1);
-        if (shrinking) {
+        if (shrinking && shrink < 0) {
+            // drift restart: Newton on phi(p) = gin (Eqs. (F), (newtonsmethod)),
+            // iterates clamped to P; once converged the point is sampled again
+            const R tolx = (sizeof(R) == 4 ? R(2e-6) : R(1e-12)) * vscale;
+            if (res2 <= tolx * tolx) {
+                shrink = 0;
+            } else if (++newton_it < 12 && isfinite(k1[0] + k1[1] + k1[2])) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) p[c] = clamp01(p[c] + k1[c]);
+            } else {
+                shrink = 0;   // go on from where Newton stopped, no further restarts
+                fl |= IVR_FLAG_RESTART_FAIL;
+                count_rare(C_RESTART_FAIL);
+            }
+        } else if (shrinking) {
             // Eq. (degeneracyfix): Newton on phi(p) = gin, iterates clamped to P
             const R tolx = (sizeof(R) == 4 ? R(2e-6) : R(1e-12)) * vscale;
             if (res2 <= tolx * tolx && fabs(det1) >= dsing) {
@@ -1105,7 +1139,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 const R sl = (rho_cur - rho_in) / delta;
                 composite(fp, views[vid].fp, vls[vid], rho_in, sl, rho_cur, sl, delta, C, A, c_sub);
                 ++c_samp;
-                s = delta;
+                s = delta;             // gin is the ray point at arc length delta
                 shrink = 0;
                 fresh = true;          // restart the ODE from the new entry
             } else if (++newton_it < 16 && isfinite(k1[0] + k1[1] + k1[2])) {
@@ -1145,7 +1179,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 // x0 = p_in + eps (p_out - p_in)/|p_out - p_in|, eps = sqrt(delta/L)
                 // |p_out - p_in| (the offset of a map whose normal derivative vanishes
                 // to first order at the face)
-                ++c_deg;
+                count_rare(C_DEGENERATE);
+                fl |= IVR_FLAG_DEGENERATE;
                 rho_in = rho_cur;
                 hmax *= R(0.5);
                 const Seg<R> &sg = segs[sid];
@@ -1170,19 +1205,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     if (isfinite(pm[0] + pm[1] + pm[2])) {
 #pragma unroll
                         for (int c = 0; c < 3; ++c) p[c] = clamp01(R(pm[c]));
-                        ++c_mlp;
+                        count_rare(C_MLP_RESTARTS);
                     }
                 }
             }
             rho_prev = rho_cur;
             m_prev = m_cur;
         } else if (pending) {
-            composite(fp, views[vid].fp, vls[vid], rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A, c_sub);
-            ++c_samp;
-            rho_prev = rho_cur;
-            m_prev = m_cur;
-            pending = false;
-            if (A >= R(1) - early) done = true;
+            // The RK steps keep phi(p) on the ray only up to their error (and, with
+            // c = 0, nothing pulls it back): when phi(p) lies more than drift_tol
+            // from the ray point at arc length s, that point is found again by
+            // Newton (seeded by the block's network with MLP seeds) before it is
+            // sampled.
+            R e2 = R(0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) e2 += (xw[c] - gin[c]) * (xw[c] - gin[c]);
+            // at most one restart between two RK steps (kJustRestarted)
+            const R dtol = drel * vscale;
+            if (e2 > dtol * dtol && drel > R(0) && !(fl & (IVR_FLAG_RESTART_FAIL | kJustRestarted))) {
+                shrink = -1;
+                fl |= kJustRestarted;
+                newton_it = 0;
+                fl |= IVR_FLAG_DRIFT_RESTART;
+                count_rare(C_DRIFT_RESTARTS);
+                if (fp.seed_mode == IVR_SEED_MLP) {
+                    float pm[3];
+                    mlp_seed_at(m.mlp_wb, m.mlp_norm, blk, float(gin[0]), float(gin[1]), float(gin[2]), pm);
+                    if (isfinite(pm[0] + pm[1] + pm[2])) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) p[c] = clamp01(R(pm[c]));
+                        count_rare(C_MLP_RESTARTS);
+                    }
+                }
+            } else {
+                composite(fp, views[vid].fp, vls[vid], rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A, c_sub);
+                ++c_samp;
+                rho_prev = rho_cur;
+                m_prev = m_cur;
+                pending = false;
+                if (A >= R(1) - early) done = true;
+            }
         }
         if (!done && !shrinking && !shrink) {
             // rho's change per step is bounded (its interpolation between samples);
@@ -1192,10 +1254,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             const R hf = R(fp.rho_step) / (dn_ds + R(1e-30));
             h = h < hf ? h : (hf > hmin ? hf : hmin);
             const R hh = (h < Lend - s) ? h : (Lend - s);
-            R q[3], dummy, dg[3], dr2;
+            R q[3], dummy, dg[3], dr2, dx[3];
 #define IVR_STAGE(KOUT, EXPR)                                                              \
     _Pragma("unroll") for (int c = 0; c < 3; ++c) q[c] = clamp01(p[c] + hh * (EXPR));      \
-    eval_W<P, RAT, 0, R, LDS>(pv, ar, q, gin, d, cperp, dthr, KOUT, dummy, dg, c_fp64, false, dr2); \
+    eval_W<P, RAT, 0, R, LDS>(pv, ar, q, gin, d, cperp, dthr, KOUT, dummy, dg, c_fp64, false, dr2, dx); \
     ++c_w;
             IVR_STAGE(k2, K::a21 * k1[c])
             IVR_STAGE(k3, K::a31 * k1[c] + K::a32 * k2[c])
@@ -1218,6 +1280,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             const bool accept = (err <= tol) || (hh <= hmin);
             if (accept) {
                 s += hh;
+                fl &= ~kJustRestarted;
                 if (!finite) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) p5[c] = p[c];   // at h_min: hold p
@@ -1232,7 +1295,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     done = true;
                 } else {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) p[c] = clamp01(p5[c]);
+                    for (int c = 0; c < 3; ++c) {
+                        p[c] = clamp01(p5[c]);
+                        gin[c] += hh * d[c];
+                    }
                     pending = true;
                     h_prev = hh;
                 }
@@ -1254,13 +1320,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             h = h > hmax ? hmax : h;
             h = h < hmin ? hmin : h;
             if (++iters >= 20000 && !done) {
-                ++c_cap;
+                count_rare(C_RK_ITER_CAP);
+                fl |= IVR_FLAG_ITER_CAP;
                 done = true;
             }
         }
         if (done) {
-            results[sid] = make_float4(float(C[0]), float(C[1]), float(C[2]), float(A));
+            // the result (C, alpha) over the first 16 bytes of the segment's own
+            // record (read at the refill; only its pixel is needed after this)
+            *reinterpret_cast<float4 *>(segs + sid) = make_float4(float(C[0]), float(C[1]), float(C[2]), float(A));
             active = false;
+            fl &= ~kJustRestarted;
+            if (fl) {
+                uint32_t *fv = views[vid].flags;
+                if (fv) atomicOr(fv + segs[sid].pixel, fl);
+            }
         }
         }
         __syncthreads();   // every wave is done with this block's LDS copy
@@ -1271,10 +1345,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         flush_counter(ctr, C_SAMPLES, c_samp);
         flush_counter(ctr, C_W_EVALS, c_w);
         flush_counter(ctr, C_FP64_SOLVES, c_fp64);
-        flush_counter(ctr, C_RK_ITER_CAP, c_cap);
         flush_counter(ctr, C_SUBSAMPLES, c_sub);
-        flush_counter(ctr, C_DEGENERATE, c_deg);
-        flush_counter(ctr, C_MLP_RESTARTS, c_mlp);
     }
 }
 
@@ -1290,7 +1361,7 @@ __device__ __forceinline__ int view_of_pixel(const ViewRec *views, int n_views, 
 }
 
 __global__ __launch_bounds__(256) void k_merge(const ViewRec *views, int n_views, u32 n_pixels,
-                                               const uint2 *pixseg, const float4 *results) {
+                                               const uint2 *pixseg, const unsigned char *segs, u32 seg_bytes) {
     const u32 g = blockIdx.x * 256u + threadIdx.x;
     if (g >= n_pixels) return;
     const ViewRec &vr = views[view_of_pixel(views, n_views, g)];
@@ -1299,7 +1370,7 @@ __global__ __launch_bounds__(256) void k_merge(const ViewRec *views, int n_views
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
     for (u32 k = 0; k < ps.y; ++k) {
         if (A >= 1.0f - early) break;
-        const float4 r = results[ps.x + k];
+        const float4 r = *reinterpret_cast<const float4 *>(segs + (size_t)(ps.x + k) * seg_bytes);
         const float w = 1.0f - A;
         C0 += w * r.x;
         C1 += w * r.y;
@@ -1358,7 +1429,7 @@ constexpr size_t kLdsBlockBytes = 48 * 1024;
 
 template <int P, bool RAT, typename R, bool LDS>
 static hipError_t launch_integrate_t(const Model &m, const ViewRec *views, int n_views, const void *segs,
-                                     const IntegrateArgs &a, float4 *results, unsigned long long *ctr,
+                                     const IntegrateArgs &a, unsigned long long *ctr,
                                      int n_cu, const LaunchCfg &lc, hipStream_t st) {
     const size_t lds = sizeof(ViewLds) * (size_t)n_views +
                        (LDS ? (size_t)a.max_cp * sizeof(float4) +
@@ -1372,44 +1443,44 @@ static hipError_t launch_integrate_t(const Model &m, const ViewRec *views, int n
         nb = 1;
     if (lc.int_waves_cu > 0) nb = std::min(nb, std::max(1, lc.int_waves_cu / (block / 64)));
     hipLaunchKernelGGL((k_integrate<P, RAT, R, LDS>), dim3(n_cu * nb), dim3(block), lds, st, m, views,
-                       n_views, (const Seg<R> *)segs, a.order, a.pperm, a.q_begin, a.q_end, a.pbase,
-                       a.pcount, a.pcur, LDS ? a.max_cp : 0, results, ctr);
+                       n_views, (Seg<R> *)segs, a.order, a.pperm, a.q_begin, a.q_end, a.pbase,
+                       a.pcount, a.pcur, LDS ? a.max_cp : 0, ctr);
     return hipGetLastError();
 }
 
 template <int P, bool RAT>
 static hipError_t launch_integrate_pr(bool fp64, const Model &m, const ViewRec *views, int n_views,
-                                      const void *segs, const IntegrateArgs &a, float4 *results,
+                                      void *segs, const IntegrateArgs &a,
                                       unsigned long long *ctr, int n_cu, const LaunchCfg &lc,
                                       hipStream_t st) {
     if (fp64)
-        return launch_integrate_t<P, RAT, double, false>(m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+        return launch_integrate_t<P, RAT, double, false>(m, views, n_views, segs, a, ctr, n_cu, lc, st);
     const size_t bytes = (size_t)a.max_cp * sizeof(float4) +
                          (RAT ? (size_t)(a.max_cp + 3) / 4 * 4 * sizeof(float) : 0) +
                          (size_t)a.max_tab * sizeof(float);
     if (bytes <= kLdsBlockBytes)
-        return launch_integrate_t<P, RAT, float, true>(m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
-    return launch_integrate_t<P, RAT, float, false>(m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+        return launch_integrate_t<P, RAT, float, true>(m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    return launch_integrate_t<P, RAT, float, false>(m, views, n_views, segs, a, ctr, n_cu, lc, st);
 }
 
 hipError_t launch_integrate(bool fp64, int klass, const Model &m, const ViewRec *views, int n_views,
-                            const void *segs, const IntegrateArgs &a, float4 *results,
+                            void *segs, const IntegrateArgs &a,
                             unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st) {
     switch (klass) {
-    case 0: return launch_integrate_pr<1, false>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
-    case 1: return launch_integrate_pr<1, true>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
-    case 2: return launch_integrate_pr<2, false>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
-    case 3: return launch_integrate_pr<2, true>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
-    case 4: return launch_integrate_pr<3, false>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
-    case 5: return launch_integrate_pr<3, true>(fp64, m, views, n_views, segs, a, results, ctr, n_cu, lc, st);
+    case 0: return launch_integrate_pr<1, false>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 1: return launch_integrate_pr<1, true>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 2: return launch_integrate_pr<2, false>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 3: return launch_integrate_pr<2, true>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 4: return launch_integrate_pr<3, false>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 5: return launch_integrate_pr<3, true>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_merge(const ViewRec *views, int n_views, uint32_t n_pixels, const uint2 *pixseg,
-                        const float4 *results, hipStream_t st) {
+                        const void *segs, bool fp64, hipStream_t st) {
     hipLaunchKernelGGL(k_merge, dim3((n_pixels + 255) / 256), dim3(256), 0, st, views, n_views, n_pixels,
-                       pixseg, results);
+                       pixseg, (const unsigned char *)segs, (u32)(fp64 ? sizeof(Seg<double>) : sizeof(Seg<float>)));
     return hipGetLastError();
 }
 

@@ -479,11 +479,13 @@ __device__ __forceinline__ R eval_rho_ds(const PatchView<R> &pv, const Arrays<R>
 // near-singular systems are solved again in FP64.
 // With newton set, the right-hand side is r = gin - phi(p) instead, so W is the
 // Newton step of phi(p) = gin (Eq. (newtonsmethod)); res2 = |r|^2.
+// x: phi(p).
 template <int P, bool RAT, int RHO, typename R, bool TAB = false>
 __device__ __forceinline__ R eval_W(const PatchView<R> &pv, const Arrays<R> &ar, const R (&p)[3],
                                     const R (&gin)[3], const R (&d)[3], R c, R det_thr, R (&W)[3],
-                                    R &rho, R (&grho)[3], uint32_t &n_fp64, bool newton, R &res2) {
-    R x[3], J[3][3];
+                                    R &rho, R (&grho)[3], uint32_t &n_fp64, bool newton, R &res2,
+                                    R (&x)[3]) {
+    R J[3][3];
     eval_volume<P, RAT, RHO, R, TAB>(pv, ar, p, x, J, rho, grho);
     R r[3] = {gin[0] - x[0], gin[1] - x[1], gin[2] - x[2]};
     const R rd = dot3(r, d);

@@ -114,7 +114,7 @@ enum Counter : int {
     C_RAYS = 0, C_SEGMENTS, C_FRAGMENTS, C_ANOMALIES, C_FRAG_OVF, C_SEG_OVF, C_BOX_TESTS,
     C_FACE_NEWTON, C_FACE_NEWTON_ITER, C_FP64_POLISH, C_RK_STEPS, C_RK_REJECTED, C_SAMPLES,
     C_W_EVALS, C_FP64_SOLVES, C_RK_ITER_CAP, C_MLP_QUERIES, C_SUBSAMPLES, C_DEGENERATE,
-    C_MLP_RESTARTS, C_FACE_FAIL, C_COUNT
+    C_MLP_RESTARTS, C_DRIFT_RESTARTS, C_RESTART_FAIL, C_COUNT
 };
 
 // Bookkeeping written by the fragment kernel.
@@ -177,8 +177,8 @@ struct FrameParams {
     double tf_sd[kMaxTfKnots][4];
     double tf_lod, tf_inv_ranged;
     // integrator
-    float rk_tol, h_max, h_min, c_perp, early_term, det_thr, det_sing;
-    double rk_told, h_maxd, h_mind, c_perpd, early_termd, det_thrd, det_singd;
+    float rk_tol, h_max, h_min, c_perp, early_term, det_thr, det_sing, drift_tol;
+    double rk_told, h_maxd, h_mind, c_perpd, early_termd, det_thrd, det_singd, drift_told;
     int32_t n_super, max_frag, max_newton, collect, hermite, seed_mode;
     float scale;
     double scaled;
@@ -201,6 +201,7 @@ struct alignas(16) ViewRec {
     uint32_t pad;
     float *rgba;                        // width*height*4, caller-owned
     float *depth;                       // width*height or null
+    uint32_t *flags;                    // width*height IVR_FLAG_* bits or null
 };
 
 // What the integrator keeps per view in LDS: on interval k (x[k] <= n < x[k+1])

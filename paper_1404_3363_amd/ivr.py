@@ -16,6 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libivr.so")
 
 IVR_OK, IVR_EINVAL, IVR_ENOMEM, IVR_EDEVICE, IVR_ESTATE, IVR_EOVERFLOW = 0, -1, -2, -3, -4, -5
+FLAGS = {"anomaly": 1, "fragment_overflow": 2, "segment_overflow": 4, "iter_cap": 8,
+         "drift_restart": 16, "restart_fail": 32, "degenerate": 64}
 PRECISION = {"fp32": 0, "fp64": 1}
 SEED = {"plain": 0, "mlp": 1, "box": 2}
 RHO_INTERP = {"linear": 0, "hermite": 1}
@@ -24,7 +26,7 @@ EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_upload_m
            "ivr_render", "ivr_render_noalloc", "ivr_render_batch", "ivr_autotune", "ivr_set_launch",
            "ivr_phase_times", "ivr_last_error", "ivr_destroy", "ivr_default_mlp_opts",
            "ivr_train_inverse_mlp", "ivr_mlp_forward_backward", "ivr_mlp_get_weights",
-           "ivr_mlp_infer"]
+           "ivr_mlp_infer", "ivr_device_bytes"]
 MLP_PARAMS = 4611
 
 
@@ -52,12 +54,13 @@ class RenderOpts(C.Structure):
                 ("seed_mode", C.c_int32), ("early_term", C.c_double),
                 ("max_newton_iter", C.c_int32), ("rho_interp", C.c_int32),
                 ("timing", C.c_int32), ("tf_step", C.c_double), ("rho_step", C.c_double),
-                ("cand_per_pixel", C.c_int32), ("det_singular", C.c_double)]
+                ("cand_per_pixel", C.c_int32), ("det_singular", C.c_double),
+                ("drift_tol", C.c_double)]
 
 
 class ViewDesc(C.Structure):
     _fields_ = [("cam", CameraDesc), ("tf", C.c_void_p), ("model", C.c_int32),
-                ("rgba_dev", C.c_void_p), ("depth_dev", C.c_void_p)]
+                ("rgba_dev", C.c_void_p), ("depth_dev", C.c_void_p), ("flags_dev", C.c_void_p)]
 
 
 class TuneReport(C.Structure):
@@ -70,7 +73,7 @@ STAT_FIELDS = ["rays", "segments", "fragments", "anomalies", "fragment_overflow"
                "segment_overflow", "box_tests", "face_newton", "face_newton_iter",
                "fp64_polish_iter", "rk_steps", "rk_rejected", "samples", "w_evals",
                "fp64_solves", "rk_iter_cap", "mlp_queries", "subsamples", "degenerate",
-               "mlp_restarts", "face_newton_fail"]
+               "mlp_restarts", "drift_restarts", "restart_fail"]
 
 
 class MlpOpts(C.Structure):
@@ -136,6 +139,8 @@ def load_library() -> C.CDLL:
     L.ivr_mlp_infer.restype = C.c_int32
     L.ivr_phase_times.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]
     L.ivr_phase_times.restype = C.c_int32
+    L.ivr_device_bytes.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    L.ivr_device_bytes.restype = C.c_int32
     L.ivr_last_error.argtypes = [vp]
     L.ivr_last_error.restype = C.c_char_p
     L.ivr_destroy.argtypes = [vp]
@@ -296,6 +301,12 @@ class Renderer:
                                            out.ctypes.data_as(C.POINTER(C.c_float))))
         return out
 
+    def device_bytes(self) -> dict:
+        """Device memory held by the uploaded model and by the frame buffers."""
+        m, f = C.c_uint64(0), C.c_uint64(0)
+        self._check(self.lib.ivr_device_bytes(self.ctx, C.byref(m), C.byref(f)))
+        return {"model": m.value, "frame": f.value}
+
     def phase_times(self, cap: int = 4096) -> np.ndarray:
         """(n, 3) milliseconds (fragments, integrate, merge) of the renders recorded
         with timing=1 since the last call."""
@@ -319,7 +330,7 @@ class Renderer:
                                  "on the renderer's device")
         return rgba, depth
 
-    def _batch_args(self, views, tf, opts, kw, outputs):
+    def _batch_args(self, views, tf, opts, kw, outputs, flags=False):
         if opts is None:
             opts = default_opts(**kw)
         elif kw:
@@ -327,8 +338,14 @@ class Renderer:
         keep, descs, outs = [], (ViewDesc * len(views))(), []
         for i, v in enumerate(views):
             cam, vtf, model = v[0], v[1] if len(v) > 1 else None, v[2] if len(v) > 2 else 0
-            rgba, depth = self._outputs(cam, *(outputs[i] if outputs else (None, None)))
-            outs.append((rgba, depth))
+            rgba, depth = self._outputs(cam, *(outputs[i][:2] if outputs else (None, None)))
+            if flags:
+                fl = self.torch.empty((cam.height, cam.width), dtype=self.torch.int32,
+                                      device=rgba.device)
+                descs[i].flags_dev = fl.data_ptr()
+                outs.append((rgba, depth, fl))
+            else:
+                outs.append((rgba, depth))
             d = descs[i]
             d.cam = camera_desc(cam)
             if vtf is not None:
@@ -342,10 +359,11 @@ class Renderer:
         return opts, descs, outs, btf, keep
 
     def render_batch(self, views, tf=None, opts: Optional[RenderOpts] = None, outputs=None,
-                     stats: bool = False, **kw):
+                     stats: bool = False, flags: bool = False, **kw):
         """views: sequence of (camera, transfer_function or None, model index).
-        Returns [(rgba, depth)] per view (and the batch counters with stats)."""
-        opts, descs, outs, btf, keep = self._batch_args(views, tf, opts, kw, outputs)
+        Returns [(rgba, depth)] per view, [(rgba, depth, flags)] with flags (int32
+        IVR_FLAG_* bits per pixel), and the batch counters with stats."""
+        opts, descs, outs, btf, keep = self._batch_args(views, tf, opts, kw, outputs, flags)
         st = Stats() if stats else None
         rc = self.lib.ivr_render_batch(self.ctx, descs, len(views),
                                        C.byref(btf.desc) if btf is not None else None,

@@ -570,6 +570,39 @@ def make_annulus(constant_field: bool = False, width: int = 48, height: int = 48
                  dict(r_in=r_in, r_out=r_out, height=height_z))
 
 
+def make_mixed_degree(rational: bool = False, width: int = 64, height: int = 64) -> Scene:
+    """One block whose directions have different degrees: (1, 2, 3) as a B-spline
+    with 3 x 4 x 5 control points, or (2, 3, 3) as a NURBS with 4 x 5 x 6 control
+    points, weights U[0.8, 1.2] and non-uniform knots along w.  Control points at
+    the Greville points of the unit cube, bent and sheared smoothly
+    (x + 0.15 sin(pi z), y + 0.1 z^2, z + 0.1 x y), interior points jittered by
+    U[-0.03, 0.03]; scalar coefficients U[0, 1].  Two 64x64 views (seeds 6300+)."""
+    seed = 6310 if rational else 6300
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if rational:
+        deg, ncp = (2, 3, 3), (4, 5, 6)
+        knots = [open_uniform_knots(4, 2), open_uniform_knots(5, 3),
+                 np.array([0, 0, 0, 0, 0.2, 0.55, 1, 1, 1, 1.0])]
+    else:
+        deg, ncp = (1, 2, 3), (3, 4, 5)
+        knots = [open_uniform_knots(3, 1), open_uniform_knots(4, 2), open_uniform_knots(5, 3)]
+    g = _grid_points(*(greville(knots[d], deg[d]) for d in range(3)))
+    x, y, z = g[..., 0], g[..., 1], g[..., 2]
+    xyz = np.stack([x + 0.15 * np.sin(math.pi * z), y + 0.1 * z * z, z + 0.1 * x * y], axis=-1)
+    n0, n1, n2 = ncp
+    inner = np.zeros((n2, n1, n0), bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    xyz[inner] += rng.uniform(-0.03, 0.03, (int(inner.sum()), 3))
+    w = rng.uniform(0.8, 1.2, (n2, n1, n0)) if rational else None
+    sc = rng.uniform(0.0, 1.0, (n2, n1, n0))
+    patch = _make_patch(deg, ncp, knots, xyz, sc, w=w, rational=rational)
+    bbox = bbox_of([patch])
+    tf = random_tf(rng, extinction_for(bbox), scalar_domain([patch]))
+    target = 0.5 * (bbox[0] + bbox[1])
+    cams = [camera_from_angles(target, 2.2, az, el, width, height) for az, el in ((35.0, 25.0), (200.0, -30.0))]
+    return Scene("mixed_degree_nurbs" if rational else "mixed_degree_bspline", [patch], tf, cams, bbox)
+
+
 def make_config(k: int, width: Optional[int] = None, height: Optional[int] = None):
     """Build config k (1..4) as a Scene; config 5 returns (model_a, model_b, views)."""
     if k == 1:

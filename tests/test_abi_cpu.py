@@ -32,16 +32,16 @@ def test_default_opts_match_header():
     assert o.n_super == 4 and o.max_fragments == 64 and o.seed_mode == 2 and o.rho_interp == 1
     assert o.early_term == 1e-4 and o.max_newton_iter == 16
     assert o.tf_step == 0.025 and o.rho_step == 0.1 and o.cand_per_pixel == 8
-    assert o.det_singular == 1e-6 and o.det_fp64_threshold == 1e-6
+    assert o.det_singular == 1e-6 and o.det_fp64_threshold == 1e-6 and o.drift_tol == 1e-5
 
 
 def test_struct_layouts_match_header():
     from paper_1404_3363_amd import ivr
     assert ctypes.sizeof(ivr.PatchDesc) == 6 * 4 + 3 * 8 + 8 + 8 + 8
     assert ctypes.sizeof(ivr.CameraDesc) == 10 * 8 + 8
-    assert ctypes.sizeof(ivr.Stats) == len(ivr.STAT_FIELDS) * 8 + 3 * 8 == 21 * 8 + 3 * 8
-    # ivr_view: camera, tf pointer, model (padded), two device pointers
-    assert ctypes.sizeof(ivr.ViewDesc) == 88 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(ivr.Stats) == len(ivr.STAT_FIELDS) * 8 + 3 * 8 == 22 * 8 + 3 * 8
+    # ivr_view: camera, tf pointer, model (padded), three device pointers
+    assert ctypes.sizeof(ivr.ViewDesc) == 88 + 8 + 8 + 8 + 8 + 8
     assert ivr.ViewDesc.model.offset == 96 and ivr.ViewDesc.rgba_dev.offset == 104
     assert ctypes.sizeof(ivr.TuneReport) == 6 * 4 + 32 * 8 + 2 * 8
 

@@ -161,6 +161,73 @@ def test_batched_views_full_resolution_sampled(renderer):
     assert n >= 32 * 60
 
 
+def test_frame_buffers_are_sized_from_counts():
+    """A fresh context renders the batched-views workload (47M rays): its frame
+    buffers follow the segments and candidates the batch needs (2.2 segments per
+    pixel here), not 32 segment slots per pixel, and stay under 10 GB."""
+    import torch
+    from paper_1404_3363_amd import Renderer
+    r = Renderer(0)
+    try:
+        a, b, views = make_config(5)
+        r.upload_models([a.patches, b.patches])
+        vs = [(cam, (a, b)[mi].tf, mi) for mi, cam in views]
+        outs, st = r.render_batch(vs, stats=True)
+        r.render_batch(vs, outputs=outs)
+        torch.cuda.synchronize()
+        mem = r.device_bytes()
+        rays = sum(c.width * c.height for c, _, _ in vs)
+        print(f"[batch] config5 frame buffers {mem['frame'] / 1e9:.2f} GB for {rays} rays, "
+              f"{st['segments'] / rays:.2f} segments per ray; model {mem['model'] / 1e6:.1f} MB", flush=True)
+        assert st["segment_overflow"] == 0 and mem["frame"] < 10e9
+    finally:
+        r.close()
+
+
+def test_batch_of_32_views_at_2048():
+    """32 views of 2048^2 (134M rays, more than 2^32 / 32 pixels) in one batch of
+    the step channel: accepted, no overflow, sampled pixels of every view within
+    the bar against the oracle."""
+    import torch
+    from paper_1404_3363_amd import Renderer
+    r = Renderer(0)
+    try:
+        sc = make_config(4)
+        r.upload(sc.patches)
+        rng = np.random.default_rng(77)
+        vs = [(camera_from_angles(sc.cameras[0].target, float(np.linalg.norm(sc.cameras[0].eye - sc.cameras[0].target)),
+                                  rng.uniform(0, 360), rng.uniform(-40, 40), 2048, 2048), sc.tf, 0) for _ in range(32)]
+        print("[batch] 32 views of 2048^2", flush=True)
+        outs, st = r.render_batch(vs, stats=True, flags=True)
+        torch.cuda.synchronize()
+        mem = r.device_bytes()
+        print(f"[batch] 32x2048^2: segments {st['segments']} overflow {st['fragment_overflow']}/"
+              f"{st['segment_overflow']} anomalies {st['anomalies']}; frame buffers {mem['frame'] / 1e9:.1f} GB",
+              flush=True)
+        for i, (cam, _, _) in enumerate(vs):
+            bad = np.flatnonzero(outs[i][2].cpu().numpy().reshape(-1) & 1)
+            for q in bad:
+                print(f"[batch] unpaired crossing: view {i} (eye {np.round(cam.eye, 6).tolist()}) pixel "
+                      f"x={q % cam.width} y={q // cam.width}", flush=True)
+        assert st["rays"] == 32 * 2048 * 2048
+        assert st["segment_overflow"] == 0 and st["fragment_overflow"] == 0
+        # rare unpaired crossings (rays grazing a block edge), at most one in 10^7 rays
+        assert st["anomalies"] <= st["rays"] // 10_000_000
+        prep = oracle.OracleScene(sc.patches, sc.scale)
+        worst = 0.0
+        for i, (cam, tf, _) in enumerate(vs):
+            img = _np(outs[i][0]).reshape(-1, 4)
+            cov = np.flatnonzero(img[:, 3] > 0)
+            pix = np.unique(np.concatenate([rng.choice(cov, min(6, len(cov)), replace=False),
+                                            rng.choice(cam.width * cam.height, 2, replace=False)]))
+            ref = oracle.render(sc, cam, tf, pixels=pix, prepared=prep)
+            worst = max(worst, float(np.abs(img[pix] - ref.rgba).max()))
+        print(f"[batch] 32x2048^2 worst |rgba - oracle| {worst:.2e}", flush=True)
+        assert worst <= 1e-3
+    finally:
+        r.close()
+
+
 def test_transfer_functions_with_many_knots(renderer):
     """A 16-knot transfer function (14 interior knots, the most a view holds),
     alone against the oracle, and in one batch with an 8-knot view: the batch

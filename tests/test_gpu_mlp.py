@@ -141,6 +141,26 @@ def test_mlp_rays_past_the_candidate_list_use_box_seeds(renderer, trained_c4):
     assert np.abs(a - b).max() <= 1e-5
 
 
+def test_mlp_seeds_drift_restarts(renderer, trained_c4):
+    """With MLP seeds, the Newton of a drift restart (c_perp = 0, rk_tol = 1e-3, so
+    the samples drift) starts from the block's network at the ray point: restarts
+    are counted as network-seeded, and the image stays within the bar."""
+    import torch
+    sc, _ = trained_c4
+    cam = sc.cameras[0]
+    rgba, depth, st = renderer.render(cam, sc.tf, stats=True, seed_mode="mlp", c_perp=0.0, rk_tol=1e-3)
+    torch.cuda.synchronize()
+    img = rgba.cpu().numpy().reshape(-1, 4).astype(np.float64)
+    cov = np.flatnonzero(img[:, 3] > 0)
+    pix = np.random.default_rng(44).choice(cov, 256, replace=False)
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    err = float(np.abs(img[pix] - ref.rgba).max())
+    print(f"[mlp] drift restarts {st['drift_restarts']}, network-seeded {st['mlp_restarts']}, "
+          f"failed {st['restart_fail']}, max err {err:.2e}", flush=True)
+    assert st["drift_restarts"] > 0 and st["mlp_restarts"] >= st["drift_restarts"] // 2
+    assert err <= 1e-3
+
+
 def test_mlp_seeds_the_restart_at_degenerate_entries(renderer):
     """With MLP seeds the network also seeds the Newton restart at a shrunk
     degenerate entry (Eq. (degeneracyfix)); the image still matches the oracle."""
@@ -167,3 +187,4 @@ def test_mlp_seeds_the_restart_at_degenerate_entries(renderer):
         err = np.abs(img[pix] - ref.rgba).max()
         print(f"[mlp] degenerate entries, seed {mode}: max |rgba - oracle| = {err:.2e}", flush=True)
         assert err <= 1e-3
+
