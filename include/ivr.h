@@ -99,6 +99,11 @@ typedef struct {
 #define IVR_SEED_BOX 2         /* from the ray's passage through the element box   */
 #define IVR_RHO_LINEAR 0       /* rho linear between samples (as in the paper)  */
 #define IVR_RHO_HERMITE 1      /* cubic Hermite from rho and d rho/ds           */
+#define IVR_INTERIOR_ODE 0     /* the ray preimage ODE by adaptive RKF45 (Sec. "ODE
+                                  Based Algorithm")                               */
+#define IVR_INTERIOR_RF 1      /* every sample's preimage by Newton, seeded from the
+                                  previous sample (Sec. "Root Finding Based
+                                  Algorithm"); steps bounded as for the ODE        */
 
 /* Render options (ivr_default_opts fills the defaults given in brackets). */
 typedef struct {
@@ -141,6 +146,21 @@ typedef struct {
                                    beyond it the point is found again by Newton
                                    from p (from the block's network with MLP
                                    seeds) before it is sampled; 0: no check [1e-5] */
+    int32_t interior;           /* IVR_INTERIOR_*: how a segment's samples find
+                                   their parameter points                 [ODE] */
+    int32_t cut;                /* 1: a cutting plane (Sec. "Cutting and Near Clip
+                                   Planes"): only points g with
+                                   cut_normal . (g - cut_point) >= 0 are
+                                   rendered; a segment cut by it starts or ends
+                                   on it, that end's parameter point found by
+                                   Newton (from the block centre, or the block's
+                                   network with MLP seeds)                  [0] */
+    double cut_point[3], cut_normal[3];
+    double near_clip;           /* > 0: the near plane, this far in front of the
+                                   eye along the view direction; only points
+                                   beyond it are rendered, and a block it cuts is
+                                   entered there (an exit without an entry in
+                                   front); 0: none                          [0] */
 } ivr_render_opts;
 
 /* Per-pixel flags (ivr_view.flags_dev): OR of the events of the pixel's ray. */

@@ -47,7 +47,8 @@ class _Camera(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("panels_per_scale", C.c_double), ("richardson", C.c_int32),
-                ("nthreads", C.c_int32), ("self_tol", C.c_double)]
+                ("nthreads", C.c_int32), ("self_tol", C.c_double), ("cut", C.c_int32),
+                ("cut_point", C.c_double * 3), ("cut_normal", C.c_double * 3), ("near_clip", C.c_double)]
 
 
 class Fragment(C.Structure):
@@ -252,9 +253,11 @@ class RenderResult:
 def render(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None,
            panels_per_scale: float = 2048.0, richardson: bool = True, nthreads: int = 0,
            scale: Optional[float] = None, prepared: Optional[OracleScene] = None,
-           self_tol: float = 1e-5) -> RenderResult:
+           self_tol: float = 1e-5, cut_plane=None, near_clip: float = 0.0) -> RenderResult:
     """Reference image (premultiplied RGBA, first-entry depth) for the listed pixels
-    (linear index row*width+col), or for the whole image when pixels is None."""
+    (linear index row*width+col), or for the whole image when pixels is None.
+    cut_plane: (point, normal), keeping normal . (g - point) >= 0; near_clip: the
+    near plane's distance from the eye along the view direction (0: none)."""
     if prepared is None:
         patches = getattr(scene_or_patches, "patches", scene_or_patches)
         if scale is None:
@@ -263,6 +266,12 @@ def render(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None,
     cam_s = _camera(cam)
     tf_s = OracleTF(tf)
     opts = _Opts(float(panels_per_scale), 1 if richardson else 0, int(nthreads), float(self_tol))
+    if cut_plane is not None:
+        opts.cut = 1
+        for q in range(3):
+            opts.cut_point[q] = float(cut_plane[0][q])
+            opts.cut_normal[q] = float(cut_plane[1][q])
+    opts.near_clip = float(near_clip)
     if pixels is None:
         npix = cam.width * cam.height
         pix_ptr = None

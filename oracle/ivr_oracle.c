@@ -744,7 +744,7 @@ int32_t orc_ray_fragments(const orc_scene *s, const double o[3], const double d[
  * above): where a ray passes through an edge or corner of a block, its entry
  * and exit there come from roots on different faces, which agree only to
  * rounding, so either may come first.                                       */
-static int pair_fragments(const orc_fragment *fr, int n, double teq, int (*segs)[2], int *anomalies)
+static int pair_fragments(const orc_fragment *fr, int n, double teq, int near, int (*segs)[2], int *anomalies)
 {
     int used[FRAG_CAP] = {0};
     int nseg = 0;
@@ -760,7 +760,19 @@ static int pair_fragments(const orc_fragment *fr, int n, double teq, int (*segs)
                 (ifr < 0 || fr[i].t < fr[ifr].t))
                 ifr = i;
         used[ib] = 1;
-        if (ifr < 0) { ++*anomalies; continue; }
+        if (ifr < 0) {
+            /* Sec. "Cutting and Near Clip Planes": with a near plane, an exit of a
+               block without an entry in front of it means the near plane lies
+               inside that block: the segment starts there (entry index -1) */
+            if (near) {
+                segs[nseg][0] = -1;
+                segs[nseg][1] = ib;
+                ++nseg;
+            } else {
+                ++*anomalies;
+            }
+            continue;
+        }
         used[ifr] = 1;
         segs[nseg][0] = ifr;
         segs[nseg][1] = ib;
@@ -798,6 +810,18 @@ static int segment_integral(const orc_patch *P, const orc_tf *tf, const double o
     return 0;
 }
 
+typedef struct {
+    double t0, t1;             /* ray parameters of the segment's ends            */
+    const double *p0;          /* parameter point of the entry, NULL if unknown   */
+    int patch;
+} seg_t;
+
+static int cmp_seg(const void *x, const void *y)
+{
+    double a = ((const seg_t *)x)->t0, b = ((const seg_t *)y)->t0;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
 static void render_one(const orc_scene *s, const orc_camera *cam, const orc_tf *tf,
                        const orc_opts *opts, int64_t pix, double rgba[4], double *depth,
                        orc_pixel_diag *dg, orc_fragment *fr)
@@ -810,40 +834,93 @@ static void render_one(const orc_scene *s, const orc_camera *cam, const orc_tf *
     *depth = INFINITY;
     int n = orc_ray_fragments(s, o, d, fr, FRAG_CAP);
     if (n < 0) { dg->n_anomalies = -1; return; }
+    /* Sec. "Cutting and Near Clip Planes": the near plane lies near_clip in front
+       of the eye along the view direction; crossings in front of it are dropped */
+    const int near = opts->near_clip > 0.0;
+    double t_near = 0.0;
+    if (near) {
+        double f[3], nf = 0.0, fd = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            f[c] = cam->target[c] - cam->eye[c];
+            nf += f[c] * f[c];
+        }
+        for (int c = 0; c < 3; ++c) fd += d[c] * f[c] / sqrt(nf);
+        t_near = opts->near_clip / fd;
+        int m = 0;
+        for (int i = 0; i < n; ++i)
+            if (fr[i].t >= t_near) fr[m++] = fr[i];
+        n = m;
+    }
     dg->n_fragments = n;
     static const int SEGCAP = FRAG_CAP;
-    int (*segs)[2] = malloc(sizeof(int[2]) * SEGCAP);
+    int (*pairs)[2] = malloc(sizeof(int[2]) * SEGCAP);
+    seg_t *segs = malloc(sizeof(seg_t) * SEGCAP);
     int anomalies = 0;
-    int nseg = pair_fragments(fr, n, 1e-9 * s->scale, segs, &anomalies);
-    dg->n_segments = nseg;
+    int npair = pair_fragments(fr, n, 1e-9 * s->scale, near, pairs, &anomalies);
     dg->n_anomalies = anomalies;
-    /* order segments front to back by entry depth */
-    for (int i = 1; i < nseg; ++i)
-        for (int j = i; j > 0 && fr[segs[j][0]].t < fr[segs[j - 1][0]].t; --j) {
-            int a = segs[j][0], b = segs[j][1];
-            segs[j][0] = segs[j - 1][0]; segs[j][1] = segs[j - 1][1];
-            segs[j - 1][0] = a; segs[j - 1][1] = b;
+    /* the segments, clipped to the cutting plane's kept half-space
+       n . (g - g0) >= 0; an end moved to the plane has no known parameter point */
+    int nseg = 0;
+    for (int k = 0; k < npair; ++k) {
+        seg_t sg;
+        sg.t0 = pairs[k][0] < 0 ? t_near : fr[pairs[k][0]].t;
+        sg.p0 = pairs[k][0] < 0 ? NULL : fr[pairs[k][0]].p;
+        sg.t1 = fr[pairs[k][1]].t;
+        sg.patch = fr[pairs[k][1]].patch;
+        if (opts->cut) {
+            double s0 = 0.0, sd = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                s0 += opts->cut_normal[c] * (o[c] - opts->cut_point[c]);
+                sd += opts->cut_normal[c] * d[c];
+            }
+            if (sd == 0.0) {
+                if (s0 < 0.0) continue;
+            } else {
+                const double ts = -s0 / sd;
+                if (sd > 0.0 && ts > sg.t0) {       /* kept beyond the plane */
+                    sg.t0 = ts;
+                    sg.p0 = NULL;
+                } else if (sd < 0.0 && ts < sg.t1) { /* kept in front of it */
+                    sg.t1 = ts;
+                }
+            }
+            if (!(sg.t1 > sg.t0)) continue;
         }
+        segs[nseg++] = sg;
+    }
+    dg->n_segments = nseg;
+    /* front to back by entry depth */
+    qsort(segs, nseg, sizeof(seg_t), cmp_seg);
     double C[3] = {0, 0, 0}, A = 0.0;
     for (int k = 0; k < nseg; ++k) {
-        const orc_fragment *fi = &fr[segs[k][0]], *fo = &fr[segs[k][1]];
+        const seg_t *sg = &segs[k];
+        const orc_patch *P = &s->patches[sg->patch];
         if (k == 0) {
-            *depth = fi->t;
-            dg->first_chord = fo->t - fi->t;
+            *depth = sg->t0;
+            dg->first_chord = sg->t1 - sg->t0;
         }
-        double L = fo->t - fi->t;
+        double p0[3] = {0.5, 0.5, 0.5};
+        if (sg->p0) {
+            memcpy(p0, sg->p0, sizeof p0);
+        } else {
+            /* an entry on a clip plane: its preimage by Newton (Eq. (F)) from the
+               block centre, as the seed of the quadrature's continuation */
+            double g[3], q[3];
+            for (int c = 0; c < 3; ++c) g[c] = o[c] + sg->t0 * d[c];
+            if (invert_with_restarts(P, g, p0, s->scale, q) != 0) ++dg->n_newton_fail;
+            memcpy(p0, q, sizeof p0);
+        }
+        double L = sg->t1 - sg->t0;
         int npan = (int)ceil(L * opts->panels_per_scale / s->scale);
         if (npan < 1) npan = 1;
         double I1[4], res[4];
         int fails = 0;
-        segment_integral(&s->patches[fi->patch], tf, o, d, fi->t, fo->t, fi->p, s->scale, npan, I1,
-                         &fails);
+        segment_integral(P, tf, o, d, sg->t0, sg->t1, p0, s->scale, npan, I1, &fails);
         if (opts->richardson) {
             /* halve the panels until |I_h - I_{h/2}| <= self_tol (at most 4 times) */
             double I2[4], err = 0.0;
             for (int refine = 0;; ++refine) {
-                segment_integral(&s->patches[fi->patch], tf, o, d, fi->t, fo->t, fi->p, s->scale,
-                                 2 * npan, I2, &fails);
+                segment_integral(P, tf, o, d, sg->t0, sg->t1, p0, s->scale, 2 * npan, I2, &fails);
                 err = 0.0;
                 for (int c = 0; c < 4; ++c)
                     if (fabs(I1[c] - I2[c]) > err) err = fabs(I1[c] - I2[c]);
@@ -861,6 +938,7 @@ static void render_one(const orc_scene *s, const orc_camera *cam, const orc_tf *
         for (int c = 0; c < 3; ++c) C[c] += (1.0 - A) * res[c];
         A += (1.0 - A) * res[3];
     }
+    free(pairs);
     free(segs);
     rgba[0] = C[0]; rgba[1] = C[1]; rgba[2] = C[2]; rgba[3] = A;
 }

@@ -58,6 +58,14 @@ typedef struct {
     int32_t richardson;       /* 1: combine h and h/2 as (4 I_{h/2} - I_h)/3 */
     int32_t nthreads;         /* 0: all online cores                         */
     double self_tol;          /* halve the panels while |I_h - I_{h/2}| > this */
+    /* Sec. "Cutting and Near Clip Planes".  Cutting plane (cut != 0): only
+       points g with cut_normal . (g - cut_point) >= 0 are rendered.  Near clip
+       plane (near_clip > 0): only points at least near_clip in front of the eye
+       along the view direction; a block that the near plane cuts is entered
+       there.                                                                   */
+    int32_t cut;
+    double cut_point[3], cut_normal[3];
+    double near_clip;
 } orc_opts;
 
 typedef struct orc_scene orc_scene;

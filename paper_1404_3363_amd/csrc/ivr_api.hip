@@ -725,6 +725,10 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->cand_per_pixel = 8;
     o->det_singular = 1e-6;
     o->drift_tol = 1e-5;
+    o->interior = IVR_INTERIOR_ODE;
+    o->cut = 0;
+    for (int q = 0; q < 3; ++q) o->cut_point[q] = o->cut_normal[q] = 0.0;
+    o->near_clip = 0.0;
 }
 
 static ivr_status ensure_views(ivr_ctx *c, int n);
@@ -1291,6 +1295,22 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
         return fail(c, IVR_EINVAL, "det_singular must be finite and >= 0");
     if (!(o.drift_tol >= 0 && std::isfinite(o.drift_tol)))
         return fail(c, IVR_EINVAL, "drift_tol must be finite and >= 0");
+    if (o.interior != IVR_INTERIOR_ODE && o.interior != IVR_INTERIOR_RF)
+        return fail(c, IVR_EINVAL, "unknown interior method");
+    if (!(o.near_clip >= 0 && std::isfinite(o.near_clip))) return fail(c, IVR_EINVAL, "near_clip must be >= 0");
+    fp.near_clip = o.near_clip;
+    fp.cut = o.cut ? 1 : 0;
+    if (o.cut) {
+        if (!finite3(o.cut_point) || !finite3(o.cut_normal)) return fail(c, IVR_EINVAL, "cutting plane not finite");
+        const double nn = std::sqrt(o.cut_normal[0] * o.cut_normal[0] + o.cut_normal[1] * o.cut_normal[1] +
+                                    o.cut_normal[2] * o.cut_normal[2]);
+        if (!(nn > 0)) return fail(c, IVR_EINVAL, "cutting plane normal is zero");
+        fp.cut_s0 = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            fp.cut_n[q] = o.cut_normal[q] / nn;
+            fp.cut_s0 += fp.cut_n[q] * (cam->eye[q] - o.cut_point[q]);
+        }
+    }
     if (o.max_fragments < 2 || o.max_fragments > kFragCap)
         return fail(c, IVR_EINVAL, "max_fragments outside 2..64");
     if (o.rho_interp != IVR_RHO_LINEAR && o.rho_interp != IVR_RHO_HERMITE)
@@ -1431,6 +1451,7 @@ struct HostView {
 };
 struct Batch {
     int n = 0;
+    int method = IVR_INTERIOR_ODE;
     uint32_t n_tiles = 0, n_pixels = 0, class_mask = 0;
     bool fp64 = false, mlp = false, collect = false;
     uint32_t c_cap = 0;   // candidates the fragment launches may record
@@ -1465,6 +1486,7 @@ static ivr_status fill_views(ivr_ctx *c, const HostView *hv, int n, const ivr_re
     b.n = n;
     b.fp64 = o.precision == IVR_PRECISION_FP64;
     b.mlp = o.seed_mode == IVR_SEED_MLP;
+    b.method = o.interior;
     b.collect = collect;
     const int th = 64 / lc.tile_w;
     uint64_t tiles = 0, pixels = 0;
@@ -1567,7 +1589,7 @@ static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const FrameBufs &fb, 
         ia.pcur = fb.pcur;
         ia.max_cp = c->cls_max_cp[k];
         ia.max_tab = c->cls_max_tab[k];
-        IVR_HIP(c, launch_integrate(b.fp64, k, m, fb.views, b.n, fb.segs, ia, fb.ctr, c->n_cu, lc, s));
+        IVR_HIP(c, launch_integrate(b.fp64, b.method, k, m, fb.views, b.n, fb.segs, ia, fb.ctr, c->n_cu, lc, s));
     }
     if (ev) IVR_HIP(c, hipEventRecord(ev[2], s));
     IVR_HIP(c, launch_merge(fb.views, b.n, b.n_pixels, fb.pixseg, fb.segs, b.fp64, s));
@@ -1757,7 +1779,7 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
     if (st != IVR_OK) return st;
     // the graph holds every kernel argument except what the view table carries
     // (cameras, transfer functions, output pointers): key it by the rest
-    std::vector<int64_t> key = {(int64_t)c->generation, b.n, b.fp64, b.mlp, (int64_t)b.class_mask,
+    std::vector<int64_t> key = {(int64_t)c->generation, b.n, b.fp64, b.mlp, b.method, (int64_t)b.class_mask,
                                 c->lc.tile_w, c->lc.xcd_chunk, c->lc.int_block, c->lc.int_waves_cu,
                                 (int64_t)b.c_cap};
     for (int v = 0; v < n_views; ++v) {

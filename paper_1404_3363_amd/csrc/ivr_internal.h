@@ -16,7 +16,7 @@ hipError_t launch_block_sort(const QueueState *qs, uint32_t seg_cap, const uint2
                              const uint32_t *pperm, int nperm, const uint32_t *pcount, uint32_t *pbase,
                              uint32_t *pcur, uint32_t *order, int n_cu, hipStream_t st);
 
-hipError_t launch_integrate(bool fp64, int klass, const Model &m, const ViewRec *views, int n_views,
+hipError_t launch_integrate(bool fp64, int method, int klass, const Model &m, const ViewRec *views, int n_views,
                             void *segs, const IntegrateArgs &a,
                             unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st);
 

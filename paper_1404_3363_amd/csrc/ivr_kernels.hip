@@ -32,6 +32,7 @@ using u32 = uint32_t;
 using u64 = unsigned long long;
 
 constexpr int kFlat = 256;    // candidates solved per pass of the flattened solve
+constexpr int kRayStart = 255;  // entry index of a segment that starts on the near plane
 constexpr int kFragLds = 16;  // crossings per ray kept in LDS (the rest in scratch)
 constexpr int kExtra = 64;    // second roots of one element per pass of the flattened solve
 
@@ -711,6 +712,23 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     //    depth tolerance of one crossing (an entry and exit at one point, as
     //    where a ray passes through an edge of the block, come from roots of
     //    different faces and may round to neighbouring FP32 depths).
+    //    Sec. "Cutting and Near Clip Planes": segments are clipped to the kept
+    //    interval [klo, khi] of the ray (beyond the near plane, on the kept side of
+    //    the cutting plane); with a near plane an exit without an entry in front
+    //    starts where the ray starts (entry index kRayStart), the near plane
+    //    lying inside that block.  An end moved to a plane has no parameter point.
+    R klo = -INFINITY, khi = INFINITY;
+    if (fp.near_clip > 0.0)
+        klo = R(fp.near_clip / (dd[0] * fp.fwd[0] + dd[1] * fp.fwd[1] + dd[2] * fp.fwd[2]));
+    if (fp.cut) {
+        const double sd = fp.cut_n[0] * dd[0] + fp.cut_n[1] * dd[1] + fp.cut_n[2] * dd[2];
+        if (sd > 0.0) klo = fmax(klo, R(-fp.cut_s0 / sd));
+        else if (sd < 0.0) khi = R(-fp.cut_s0 / sd);
+        else if (fp.cut_s0 < 0.0) khi = -INFINITY;
+    }
+    auto t_in_of = [&](int q) __attribute__((always_inline)) -> R {
+        return q == kRayStart ? klo : fmax(ft(q), klo);
+    };
     unsigned char pin[kSegCap], pout[kSegCap];
     int npair = 0;
     u64 used = 0;
@@ -738,12 +756,21 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                 tf = tq;
             }
         }
-        if (ifr < 0) { ++c_anom; continue; }
-        used |= 1ull << ifr;
+        if (ifr < 0) {
+            if (!(fp.near_clip > 0.0)) {
+                ++c_anom;
+                continue;
+            }
+            ifr = kRayStart;
+        } else {
+            used |= 1ull << ifr;
+        }
+        const R t_in = t_in_of(ifr);
+        if (!(fmin(tb, khi) > t_in)) continue;   // nothing of it is kept
         if (npair >= kSegCap) { ++c_sovf; continue; }
-        // keep the pairs ordered by entry depth
+        // keep the pairs ordered by (kept) entry depth
         int q = npair++;
-        while (q > 0 && ft(pin[q - 1]) > tf) {
+        while (q > 0 && t_in_of(pin[q - 1]) > t_in) {
             pin[q] = pin[q - 1];
             pout[q] = pout[q - 1];
             --q;
@@ -774,21 +801,32 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         const int qi = pin[k], qo = pout[k];
         const u32 info_o = fi(qo);
         Seg<R> s;
-        s.t_in = ft(qi);
-        s.t_out = ft(qo);
+        s.t_in = t_in_of(qi);
+        s.t_out = fmin(ft(qo), khi);
         R pi_[3], po_[3];
-        face_point(fi(qi), fr[qi].a, fr[qi].b, pi_);
+        if (qi != kRayStart && ft(qi) >= klo) {
+            face_point(fi(qi), fr[qi].a, fr[qi].b, pi_);
+        } else {
+            pi_[0] = pi_[1] = pi_[2] = R(NAN);   // entry on a plane: found by the integrator
+        }
         face_point(info_o, fr[qo].a, fr[qo].b, po_);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             s.p_in[q] = pi_[q];
             s.p_out[q] = po_[q];
         }
-        const R det_out = rho_ds_any<R>(m, m.patches[info_o >> 4], po_, dr, s.rho_out, s.drho_out);
-        // singular J at the exit (a degenerate boundary): no slope; the
-        // integrator then stops short of the exit, Eq. (degeneracyfix)
-        if (!(fabs(det_out) >= (sizeof(R) == 4 ? R(fp.det_sing) : R(fp.det_singd))))
-            s.drho_out = R(NAN);
+        if (ft(qo) <= khi) {
+            const R det_out = rho_ds_any<R>(m, m.patches[info_o >> 4], po_, dr, s.rho_out, s.drho_out);
+            // singular J at the exit (a degenerate boundary): no slope; the
+            // integrator then stops short of the exit, Eq. (degeneracyfix)
+            if (!(fabs(det_out) >= (sizeof(R) == 4 ? R(fp.det_sing) : R(fp.det_singd))))
+                s.drho_out = R(NAN);
+        } else {
+            // exit on the cutting plane: no parameter point, the integrator samples it
+            s.p_out[0] = R(NAN);
+            s.rho_out = R(0);
+            s.drho_out = R(0);
+        }
         s.pixel = pixel;
         s.patch = (info_o >> 4) | ((u32)v << kViewShift);
         segs[first + k] = s;
@@ -823,7 +861,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     }
     if (valid) {
         pixseg[vr.pix_begin + pixel] = make_uint2(first, (u32)nseg);
-        if (vr.depth) vr.depth[pixel] = nseg ? float(ft(pin[0])) : INFINITY;
+        if (vr.depth) vr.depth[pixel] = nseg ? float(t_in_of(pin[0])) : INFINITY;
         // the pixel's flags start here; the integrator ORs in its segments' flags
         if (vr.flags)
             vr.flags[pixel] = (c_anom ? (u32)IVR_FLAG_ANOMALY : 0u) | (c_fovf ? (u32)IVR_FLAG_FRAGMENT_OVERFLOW : 0u) |
@@ -844,9 +882,13 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     }
 }
 
-// Integrator-internal bit of a segment's flags: a drift restart happened since
-// the last accepted RK step (not reported).
+// Integrator-internal bits of a segment's flags (not reported): a drift restart
+// happened since the last accepted RK step; the exit lies on the cutting plane
+// (no parameter point: the last step's end is sampled); that end sample is due.
 constexpr uint32_t kJustRestarted = 1u << 31;
+constexpr uint32_t kExitOnPlane = 1u << 30;
+constexpr uint32_t kEndSample = 1u << 29;
+constexpr uint32_t kPublicFlags = 0xFFFFu;
 
 __device__ __forceinline__ float pow_fifth(float x) { return exp2f(0.2f * __log2f(x)); }
 __device__ __forceinline__ double pow_fifth(double x) { return pow(x, 0.2); }
@@ -944,7 +986,12 @@ __global__ __launch_bounds__(256) void k_block_scatter(const QueueState *qs, u32
 // its waves refill their lanes from that block's cursor (one atomic per wave),
 // and when the block has no segments left it drains and moves on to the next
 // block with work, cyclically in class order.
-template <int P, bool RAT, typename R, bool LDS>
+// METHOD kOde: the ray preimage ODE by adaptive RKF45 (Sec. "ODE Based
+// Algorithm"); kRootFinding: every sample's preimage by Newton (Sec. "Root
+// Finding Based Algorithm"), seeded from the previous sample along J^-1 d.
+constexpr int kOde = 0, kRootFinding = 1;
+
+template <int P, bool RAT, typename R, bool LDS, int METHOD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_integrate(
     Model m, const ViewRec *views, int n_views, Seg<R> *segs, const u32 *order, const u32 *pperm,
     int q_begin, int q_end, const u32 *pbase, const u32 *pcount, u32 *pcur, int max_cp, u64 *ctr) {
@@ -1101,6 +1148,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     iters = 0;
                     shrink = 0;
                     fl = isfinite(m_out) ? 0u : (u32)IVR_FLAG_DEGENERATE;
+                    if (!isfinite(sg.p_out[0])) fl |= kExitOnPlane;
+                    // an entry on a clip plane has no parameter point: Newton finds
+                    // it (Sec. "Cutting and Near Clip Planes", Eq. (F)) from the block
+                    // centre, or from the block's network with MLP seeds, before the
+                    // ODE starts
+                    if (!isfinite(sg.p_in[0])) {
+                        p[0] = p[1] = p[2] = R(0.5);
+                        shrink = -2;
+                        newton_it = 0;
+                        if (fv.seed_mode == IVR_SEED_MLP) {
+                            float pm[3];
+                            mlp_seed_at(m.mlp_wb, m.mlp_norm, blk, float(gin[0]), float(gin[1]), float(gin[2]), pm);
+                            if (isfinite(pm[0] + pm[1] + pm[2])) {
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) p[c] = clamp01(R(pm[c]));
+                                count_rare(C_MLP_RESTARTS);
+                            }
+                        }
+                    }
                     active = true;
                 }
             }
@@ -1111,23 +1177,83 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         bool done = false;
         // stage 1 at the current point; also samples rho and d rho/ds there.  While
         // shrinking, the same evaluation gives the Newton step J^-1 (gin - phi(p)).
-        R k1[3], k2[3], k3[3], k4[3], k5[3], k6[3], rho_cur = R(0), grho[3], res2 = R(0), xw[3];
+        R k1[3], k2[3], k3[3], k4[3], k5[3], k6[3], rho_cur = R(0), grho[3], res2 = R(0), xw[3], wt[3];
         const bool shrinking = shrink != 0;
-        const R det1 = eval_W<P, RAT, 2, R, LDS>(pv, ar, p, gin, d, cperp, dthr, k1, rho_cur,
-                                         grho, c_fp64, shrinking, res2, xw);
+        const R det1 = eval_W<P, RAT, 2, R, LDS, METHOD == kRootFinding>(pv, ar, p, gin, d, cperp, dthr, k1,
+                                                                         rho_cur, grho, c_fp64, shrinking, res2,
+                                                                         xw, wt);
         ++c_w;
         const R m_cur = dot3(grho, k1);
+        // Root finding: the next sample.  Its step follows the same bounds as the
+        // ODE's (h_max, rho's change); its preimage is predicted along W = J^-1 d
+        // and found by Newton (shrink -3); the last interval closes with the exit.
+        auto rf_advance = [&](const R (&Wd)[3], R m_here) __attribute__((always_inline)) {
+            const R dn_ds = fabs(m_here) * R(sizeof(R) == 4 ? double(vls[vid].inv_ranged)
+                                                             : views[vid].fp.tf_inv_ranged);
+            const R hf = R(fp.rho_step) / (dn_ds + R(1e-30));
+            R hh = hmax < hf ? hmax : (hf > hmin ? hf : hmin);
+            hh = hh < Lend - s ? hh : Lend - s;
+            ++c_steps;
+            if (Lend - s - hh <= R(1e-6) * L && !(fl & kExitOnPlane)) {
+                const R hl = hh + (L - Lend);
+                const R mo = isfinite(m_out) ? m_out : (rho_out - rho_prev) / hl;
+                composite(fp, views[vid].fp, vls[vid], rho_prev, m_prev, rho_out, mo, hl, C, A, c_sub);
+                ++c_samp;
+                done = true;
+                return;
+            }
+            if (Lend - s - hh <= R(1e-6) * L) fl |= kEndSample;   // the exit lies on the cutting plane
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                p[c] = clamp01(p[c] + hh * Wd[c]);
+                gin[c] += hh * d[c];
+            }
+            s += hh;
+            h_prev = hh;
+            shrink = -3;
+            newton_it = 0;
+            if (++iters >= 20000) {
+                count_rare(C_RK_ITER_CAP);
+                fl |= IVR_FLAG_ITER_CAP;
+                done = true;
+            }
+        };
         if (shrinking && shrink < 0) {
-            // drift restart: Newton on phi(p) = gin (Eqs. (F), (newtonsmethod)),
-            // iterates clamped to P; once converged the point is sampled again
+            // drift restart (-1) or entry on a clip plane (-2): Newton on
+            // phi(p) = gin (Eqs. (F), (newtonsmethod)), iterates clamped to P; once
+            // converged the point is sampled (again)
             const R tolx = (sizeof(R) == 4 ? R(2e-6) : R(1e-12)) * vscale;
-            if (res2 <= tolx * tolx) {
+            if (METHOD == kRootFinding && shrink == -3) {
+                if (res2 <= tolx * tolx || newton_it >= 12 || !isfinite(k1[0] + k1[1] + k1[2])) {
+                    // the sample: rho and d rho/ds = grad rho . J^-1 d at the preimage
+                    // (where Newton stopped if it did not converge: counted, flagged)
+                    if (!(res2 <= tolx * tolx)) {
+                        fl |= IVR_FLAG_RESTART_FAIL;
+                        count_rare(C_RESTART_FAIL);
+                    }
+                    shrink = 0;
+                    const R m_t = dot3(grho, wt);
+                    composite(fp, views[vid].fp, vls[vid], rho_prev, m_prev, rho_cur, m_t, h_prev, C, A, c_sub);
+                    ++c_samp;
+                    rho_prev = rho_cur;
+                    m_prev = m_t;
+                    if (A >= R(1) - early || (fl & kEndSample)) done = true;
+                    else rf_advance(wt, m_t);
+                } else {
+                    ++newton_it;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) p[c] = clamp01(p[c] + k1[c]);
+                }
+            } else if (res2 <= tolx * tolx) {
                 shrink = 0;
-            } else if (++newton_it < 12 && isfinite(k1[0] + k1[1] + k1[2])) {
+            } else if (++newton_it < (shrink == -2 ? 24 : 12) && isfinite(k1[0] + k1[1] + k1[2])) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) p[c] = clamp01(p[c] + k1[c]);
             } else {
-                shrink = 0;   // go on from where Newton stopped, no further restarts
+                // a drift restart goes on from where Newton stopped (no further
+                // restarts); an entry that Newton cannot find leaves the segment empty
+                done = shrink == -2;
+                shrink = 0;
                 fl |= IVR_FLAG_RESTART_FAIL;
                 count_rare(C_RESTART_FAIL);
             }
@@ -1243,10 +1369,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 rho_prev = rho_cur;
                 m_prev = m_cur;
                 pending = false;
-                if (A >= R(1) - early) done = true;
+                if (A >= R(1) - early || (fl & kEndSample)) done = true;
             }
         }
-        if (!done && !shrinking && !shrink) {
+        if (METHOD == kRootFinding && !done && !shrinking && !shrink) {
+            rf_advance(k1, m_cur);   // from the entry (or a shrunk entry): W = J^-1 d there
+        } else if (METHOD == kOde && !done && !shrinking && !shrink) {
             // rho's change per step is bounded (its interpolation between samples);
             // the transfer function's frequencies are the supersampling's
             const R dn_ds = fabs(m_cur) * R(sizeof(R) == 4 ? double(vls[vid].inv_ranged)
@@ -1257,7 +1385,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             R q[3], dummy, dg[3], dr2, dx[3];
 #define IVR_STAGE(KOUT, EXPR)                                                              \
     _Pragma("unroll") for (int c = 0; c < 3; ++c) q[c] = clamp01(p[c] + hh * (EXPR));      \
-    eval_W<P, RAT, 0, R, LDS>(pv, ar, q, gin, d, cperp, dthr, KOUT, dummy, dg, c_fp64, false, dr2, dx); \
+    eval_W<P, RAT, 0, R, LDS>(pv, ar, q, gin, d, cperp, dthr, KOUT, dummy, dg, c_fp64, false, dr2, dx, dx); \
     ++c_w;
             IVR_STAGE(k2, K::a21 * k1[c])
             IVR_STAGE(k3, K::a31 * k1[c] + K::a32 * k2[c])
@@ -1285,7 +1413,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
                     for (int c = 0; c < 3; ++c) p5[c] = p[c];   // at h_min: hold p
                 }
-                if (Lend - s <= R(1e-6) * L) {
+                if (Lend - s <= R(1e-6) * L && (fl & kExitOnPlane)) {
+                    // last step ends on the cutting plane: its end is sampled
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        p[c] = clamp01(isfinite(err) ? p5[c] : p[c]);
+                        gin[c] += hh * d[c];
+                    }
+                    pending = true;
+                    h_prev = hh;
+                    fl |= kEndSample;
+                } else if (Lend - s <= R(1e-6) * L) {
                     // last step ends on the exit fragment (or, at a singular exit,
                     // 1e-4 of the chord short of it): close with the exit's rho
                     const R hl = hh + (L - Lend);
@@ -1330,7 +1468,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             // record (read at the refill; only its pixel is needed after this)
             *reinterpret_cast<float4 *>(segs + sid) = make_float4(float(C[0]), float(C[1]), float(C[2]), float(A));
             active = false;
-            fl &= ~kJustRestarted;
+            fl &= kPublicFlags;
             if (fl) {
                 uint32_t *fv = views[vid].flags;
                 if (fv) atomicOr(fv + segs[sid].pixel, fl);
@@ -1427,7 +1565,7 @@ hipError_t launch_block_sort(const QueueState *qs, uint32_t seg_cap, const uint2
 // LDS budget of the staged block per integrator workgroup.
 constexpr size_t kLdsBlockBytes = 48 * 1024;
 
-template <int P, bool RAT, typename R, bool LDS>
+template <int P, bool RAT, typename R, bool LDS, int METHOD>
 static hipError_t launch_integrate_t(const Model &m, const ViewRec *views, int n_views, const void *segs,
                                      const IntegrateArgs &a, unsigned long long *ctr,
                                      int n_cu, const LaunchCfg &lc, hipStream_t st) {
@@ -1438,41 +1576,49 @@ static hipError_t launch_integrate_t(const Model &m, const ViewRec *views, int n
                             : 0);
     const int block = lc.int_block;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<P, RAT, R, LDS>, block, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<P, RAT, R, LDS, METHOD>, block, lds) !=
             hipSuccess || nb < 1)
         nb = 1;
     if (lc.int_waves_cu > 0) nb = std::min(nb, std::max(1, lc.int_waves_cu / (block / 64)));
-    hipLaunchKernelGGL((k_integrate<P, RAT, R, LDS>), dim3(n_cu * nb), dim3(block), lds, st, m, views,
+    hipLaunchKernelGGL((k_integrate<P, RAT, R, LDS, METHOD>), dim3(n_cu * nb), dim3(block), lds, st, m, views,
                        n_views, (Seg<R> *)segs, a.order, a.pperm, a.q_begin, a.q_end, a.pbase,
                        a.pcount, a.pcur, LDS ? a.max_cp : 0, ctr);
     return hipGetLastError();
 }
 
-template <int P, bool RAT>
-static hipError_t launch_integrate_pr(bool fp64, const Model &m, const ViewRec *views, int n_views,
-                                      void *segs, const IntegrateArgs &a,
-                                      unsigned long long *ctr, int n_cu, const LaunchCfg &lc,
-                                      hipStream_t st) {
+template <int P, bool RAT, int METHOD>
+static hipError_t launch_integrate_m(bool fp64, const Model &m, const ViewRec *views, int n_views,
+                                     void *segs, const IntegrateArgs &a, unsigned long long *ctr, int n_cu,
+                                     const LaunchCfg &lc, hipStream_t st) {
     if (fp64)
-        return launch_integrate_t<P, RAT, double, false>(m, views, n_views, segs, a, ctr, n_cu, lc, st);
+        return launch_integrate_t<P, RAT, double, false, METHOD>(m, views, n_views, segs, a, ctr, n_cu, lc, st);
     const size_t bytes = (size_t)a.max_cp * sizeof(float4) +
                          (RAT ? (size_t)(a.max_cp + 3) / 4 * 4 * sizeof(float) : 0) +
                          (size_t)a.max_tab * sizeof(float);
     if (bytes <= kLdsBlockBytes)
-        return launch_integrate_t<P, RAT, float, true>(m, views, n_views, segs, a, ctr, n_cu, lc, st);
-    return launch_integrate_t<P, RAT, float, false>(m, views, n_views, segs, a, ctr, n_cu, lc, st);
+        return launch_integrate_t<P, RAT, float, true, METHOD>(m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    return launch_integrate_t<P, RAT, float, false, METHOD>(m, views, n_views, segs, a, ctr, n_cu, lc, st);
 }
 
-hipError_t launch_integrate(bool fp64, int klass, const Model &m, const ViewRec *views, int n_views,
+template <int P, bool RAT>
+static hipError_t launch_integrate_pr(bool fp64, int method, const Model &m, const ViewRec *views, int n_views,
+                                      void *segs, const IntegrateArgs &a, unsigned long long *ctr, int n_cu,
+                                      const LaunchCfg &lc, hipStream_t st) {
+    if (method == IVR_INTERIOR_RF)
+        return launch_integrate_m<P, RAT, kRootFinding>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    return launch_integrate_m<P, RAT, kOde>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+}
+
+hipError_t launch_integrate(bool fp64, int method, int klass, const Model &m, const ViewRec *views, int n_views,
                             void *segs, const IntegrateArgs &a,
                             unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st) {
     switch (klass) {
-    case 0: return launch_integrate_pr<1, false>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
-    case 1: return launch_integrate_pr<1, true>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
-    case 2: return launch_integrate_pr<2, false>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
-    case 3: return launch_integrate_pr<2, true>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
-    case 4: return launch_integrate_pr<3, false>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
-    case 5: return launch_integrate_pr<3, true>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 0: return launch_integrate_pr<1, false>(fp64, method, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 1: return launch_integrate_pr<1, true>(fp64, method, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 2: return launch_integrate_pr<2, false>(fp64, method, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 3: return launch_integrate_pr<2, true>(fp64, method, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 4: return launch_integrate_pr<3, false>(fp64, method, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    case 5: return launch_integrate_pr<3, true>(fp64, method, m, views, n_views, segs, a, ctr, n_cu, lc, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -479,12 +479,13 @@ __device__ __forceinline__ R eval_rho_ds(const PatchView<R> &pv, const Arrays<R>
 // near-singular systems are solved again in FP64.
 // With newton set, the right-hand side is r = gin - phi(p) instead, so W is the
 // Newton step of phi(p) = gin (Eq. (newtonsmethod)); res2 = |r|^2.
-// x: phi(p).
-template <int P, bool RAT, int RHO, typename R, bool TAB = false>
+// x: phi(p).  With TAN, Wt = J^-1 d as well (the ray's tangent in P, from the
+// same factors).
+template <int P, bool RAT, int RHO, typename R, bool TAB = false, bool TAN = false>
 __device__ __forceinline__ R eval_W(const PatchView<R> &pv, const Arrays<R> &ar, const R (&p)[3],
                                     const R (&gin)[3], const R (&d)[3], R c, R det_thr, R (&W)[3],
                                     R &rho, R (&grho)[3], uint32_t &n_fp64, bool newton, R &res2,
-                                    R (&x)[3]) {
+                                    R (&x)[3], R (&Wt)[3]) {
     R J[3][3];
     eval_volume<P, RAT, RHO, R, TAB>(pv, ar, p, x, J, rho, grho);
     R r[3] = {gin[0] - x[0], gin[1] - x[1], gin[2] - x[2]};
@@ -495,12 +496,33 @@ __device__ __forceinline__ R eval_W(const PatchView<R> &pv, const Arrays<R> &ar,
     for (int q = 0; q < 3; ++q) V[q] = newton ? r[q] : d[q] + c * (r[q] - rd * d[q]);
     R ju[3] = {J[0][0], J[1][0], J[2][0]}, jv[3] = {J[0][1], J[1][1], J[2][1]},
       jw[3] = {J[0][2], J[1][2], J[2][2]};
-    const R det = solve_cols(ju, jv, jw, V, W);
+    R det;
+    if constexpr (TAN) {
+        R k12[3], k20[3], k01[3];
+        cross3(jv, jw, k12);
+        cross3(jw, ju, k20);
+        cross3(ju, jv, k01);
+        det = dot3(ju, k12);
+        const R inv = div_fast(R(1), det);
+        W[0] = dot3(V, k12) * inv;
+        W[1] = dot3(V, k20) * inv;
+        W[2] = dot3(V, k01) * inv;
+        Wt[0] = dot3(d, k12) * inv;
+        Wt[1] = dot3(d, k20) * inv;
+        Wt[2] = dot3(d, k01) * inv;
+    } else {
+        det = solve_cols(ju, jv, jw, V, W);
+    }
     if (!(fabs(det) >= det_thr)) {
         double du[3] = {ju[0], ju[1], ju[2]}, dv[3] = {jv[0], jv[1], jv[2]},
                dw[3] = {jw[0], jw[1], jw[2]}, dV[3] = {V[0], V[1], V[2]}, dW[3];
         solve_cols(du, dv, dw, dV, dW);
         W[0] = R(dW[0]); W[1] = R(dW[1]); W[2] = R(dW[2]);
+        if constexpr (TAN) {
+            double dd[3] = {d[0], d[1], d[2]};
+            solve_cols(du, dv, dw, dd, dW);
+            Wt[0] = R(dW[0]); Wt[1] = R(dW[1]); Wt[2] = R(dW[2]);
+        }
         ++n_fp64;
     }
     return det;

@@ -21,6 +21,7 @@ FLAGS = {"anomaly": 1, "fragment_overflow": 2, "segment_overflow": 4, "iter_cap"
 PRECISION = {"fp32": 0, "fp64": 1}
 SEED = {"plain": 0, "mlp": 1, "box": 2}
 RHO_INTERP = {"linear": 0, "hermite": 1}
+INTERIOR = {"ode": 0, "rf": 1}
 
 EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_upload_models",
            "ivr_render", "ivr_render_noalloc", "ivr_render_batch", "ivr_autotune", "ivr_set_launch",
@@ -55,7 +56,8 @@ class RenderOpts(C.Structure):
                 ("max_newton_iter", C.c_int32), ("rho_interp", C.c_int32),
                 ("timing", C.c_int32), ("tf_step", C.c_double), ("rho_step", C.c_double),
                 ("cand_per_pixel", C.c_int32), ("det_singular", C.c_double),
-                ("drift_tol", C.c_double)]
+                ("drift_tol", C.c_double), ("interior", C.c_int32), ("cut", C.c_int32),
+                ("cut_point", C.c_double * 3), ("cut_normal", C.c_double * 3), ("near_clip", C.c_double)]
 
 
 class ViewDesc(C.Structure):
@@ -169,6 +171,15 @@ def default_opts(**kw) -> RenderOpts:
             v = SEED[v]
         if k == "rho_interp" and isinstance(v, str):
             v = RHO_INTERP[v]
+        if k == "interior" and isinstance(v, str):
+            v = INTERIOR[v]
+        if k == "cut_plane":   # (point, normal) or None
+            o.cut = 0 if v is None else 1
+            if v is not None:
+                for q in range(3):
+                    o.cut_point[q] = float(v[0][q])
+                    o.cut_normal[q] = float(v[1][q])
+            continue
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)

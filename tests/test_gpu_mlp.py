@@ -161,6 +161,33 @@ def test_mlp_seeds_drift_restarts(renderer, trained_c4):
     assert err <= 1e-3
 
 
+def test_mlp_seeds_entries_on_a_cutting_plane(renderer, trained_c4):
+    """An entry on a cutting plane has no parameter point: its Newton is a cold
+    start, from the block centre (box seeds) or from the block's network (MLP
+    seeds).  Both images match the oracle, and the network-seeded solves are
+    counted; the evaluations each seed takes are reported."""
+    import torch
+    sc, _ = trained_c4
+    cam = sc.cameras[0]
+    centre = 0.5 * (sc.bbox[0] + sc.bbox[1])
+    cut = (centre, np.array([0.8, -0.2, 0.55]))
+    out = {}
+    for mode in ("box", "mlp"):
+        rgba, depth, st = renderer.render(cam, sc.tf, stats=True, seed_mode=mode, cut_plane=cut)
+        torch.cuda.synchronize()
+        out[mode] = (rgba.cpu().numpy().reshape(-1, 4).astype(np.float64), st)
+        print(f"[mlp] cutting plane, seed {mode}: segments {st['segments']}, network-seeded entries "
+              f"{st['mlp_restarts']}, evaluations {st['w_evals']}, failed {st['restart_fail']}", flush=True)
+    assert out["box"][1]["mlp_restarts"] == 0 and out["mlp"][1]["mlp_restarts"] > 100
+    cov = np.flatnonzero(out["box"][0][:, 3] > 0)
+    pix = np.random.default_rng(58).choice(cov, 300, replace=False)
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix, cut_plane=cut)
+    for mode, (img, st) in out.items():
+        err = float(np.abs(img[pix] - ref.rgba).max())
+        print(f"[mlp] cutting plane, seed {mode}: max |rgba - oracle| = {err:.2e}", flush=True)
+        assert err <= 1e-3 and st["restart_fail"] == 0
+
+
 def test_mlp_seeds_the_restart_at_degenerate_entries(renderer):
     """With MLP seeds the network also seeds the Newton restart at a shrunk
     degenerate entry (Eq. (degeneracyfix)); the image still matches the oracle."""

@@ -791,3 +791,62 @@ def test_nurbs_annulus_constant_field_closed_form(oracle_lib):
             else:
                 assert np.isinf(res.depth[pix])
         assert hits > 60
+
+
+# ------------------------------------------------------------------ cutting and near clip planes
+
+def _kept_chord(o, d, fwd, cut=None, near=0.0):
+    """Closed form: the part of the ray inside the unit cube, in front of nothing
+    nearer than the near plane, and in the cutting plane's kept half-space
+    n . (g - g0) >= 0.  Returns (t_start, length) or (None, 0)."""
+    t0, t1 = _slab(o, d, np.zeros(3), np.ones(3))
+    t0 = max(t0, 0.0)
+    if near > 0.0:
+        t0 = max(t0, near / float(d @ fwd))
+    if cut is not None:
+        g0, n = (np.asarray(v, float) for v in cut)
+        s0, sd = float(n @ (o - g0)), float(n @ d)
+        if sd > 0:
+            t0 = max(t0, -s0 / sd)
+        elif sd < 0:
+            t1 = min(t1, -s0 / sd)
+        elif s0 < 0:
+            return None, 0.0
+    return (t0, t1 - t0) if t1 > t0 else (None, 0.0)
+
+
+@pytest.mark.parametrize("case", ["cut", "near", "eye_inside", "cut_and_near"])
+def test_cutting_and_near_planes_constant_field(oracle_lib, case):
+    """Sec. "Cutting and Near Clip Planes" on the unit cube with constant rho:
+    alpha = 1 - exp(-kappa L) and RGB = E alpha with L the closed-form kept chord
+    (inside the cube, beyond the near plane, in the cutting plane's kept
+    half-space), and the depth is where that chord starts.  With the eye inside
+    the cube every ray starts on the near plane, from an exit without entry."""
+    sc = make_config(1)
+    P = sc.patches[0]
+    Pc = Patch(P.degree, P.ncp, P.knots, P.cp, np.full_like(P.scalar, 0.37), False)
+    tf = TransferFunction(sc.tf.x, sc.tf.rgba, 4.0, (0.0, 1.0))
+    cut = ((0.5, 0.45, 0.55), np.array([0.3, -0.5, 0.8]) / np.linalg.norm([0.3, -0.5, 0.8]))
+    if case == "eye_inside":
+        cam = camera_from_angles([0.9, 0.5, 0.5], 0.5, 200.0, 10.0, 20, 20, fov_y_deg=60.0)
+    else:
+        cam = camera_from_angles([0.5, 0.5, 0.5], 3.0, 30.0, 20.0, 20, 20)
+    kw = {"cut": {"cut_plane": cut}, "near": {"near_clip": 2.75}, "eye_inside": {"near_clip": 0.05},
+          "cut_and_near": {"cut_plane": cut, "near_clip": 2.75}}[case]
+    res = oracle.render([Pc], cam, tf, scale=math.sqrt(3.0), **kw)
+    E = oracle.transfer(tf, 0.37)
+    fwd = (cam.target - cam.eye) / np.linalg.norm(cam.target - cam.eye)
+    clipped = 0
+    for pix in range(cam.width * cam.height):
+        o, d = oracle.camera_ray(cam, pix % cam.width + 0.5, pix // cam.width + 0.5)
+        t_start, L = _kept_chord(o, d, fwd, kw.get("cut_plane"), kw.get("near_clip", 0.0))
+        full, Lf = _kept_chord(o, d, fwd)
+        clipped += (L < Lf - 1e-9)
+        a = 1.0 - math.exp(-E[3] * L)
+        assert abs(res.rgba[pix, 3] - a) < 1e-7 and np.abs(res.rgba[pix, :3] - E[:3] * a).max() < 1e-7, pix
+        if t_start is None:
+            assert np.isinf(res.depth[pix]), pix
+        else:
+            assert abs(res.depth[pix] - t_start) < 1e-9, pix
+    assert (res.n_anomalies == 0).all() and (res.n_newton_fail == 0).all()
+    assert clipped > 50
