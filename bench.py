@@ -24,7 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s at 1080p, RGBA err ≤1e-3 vs FP64 oracle; MLP-seeded vs plain Newton"
-PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32, published (packed); 78.6 without packing
+PEAK_FP32_TFLOPS = 157.3            # MI355X vector FP32, published (packed FMA)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6    # 256 CUs x 64 lanes x 2 flops x 2.4 GHz without packing
 
 
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "render_config3_1080p_counters.md")
@@ -60,67 +61,96 @@ def measured_traffic(kernel):
     return value if (src == kernel_sources_sha256() and value is not None) else None
 
 
-def basis_flops(p):
-    """Triangular evaluation of the p+1 basis functions and first derivatives on a span."""
-    return 2 * p + 2.5 * p * (p + 1) + 6 * (p + 1)
-
-
-def contraction_flops(p, nc):
-    """Sum-factorised phi and its 3 partials over (p+1)^3 points, nc channels (FMA = 2)."""
-    q = p + 1
-    return 2 * (q ** 3 * 2 * nc + q ** 2 * 3 * nc + q * 4 * nc)
-
-
-def unit_flops(p, rational):
-    nc = 4 if rational else 3
-    q = p + 1
-    quotient = 25 if rational else 0
-    return {
-        # phi, J_phi, V = V_par + c V_perp and the 3x3 solve of J W = V
-        "w_eval": 3 * basis_flops(p) + contraction_flops(p, nc) + quotient + 80,
-        # rho and its parameter gradient in the first stage, plus d rho/ds
-        "stage1_rho": 2 * (q ** 3 * 2 + q ** 2 * 3 + q * 3) + 5,
-        # stage arguments, 5th-order update, error norm, step control
-        "rk_step": 200,
-        # Hermite value, transfer function, exp, front-to-back update
-        "subsample": 25,
-        # one FP32 face Newton iteration: bivariate value+2 partials, 3x3 solve
-        "face_iter": 2 * basis_flops(p) + 2 * (q ** 2 * 2 * nc + q * 3 * nc) + 70,
-        "box_test": 30,
-    }
+# Algorithmic work per unit in FP32 flops (FMA = 2, reciprocal and exp 1 each):
+# the per-evaluation counts of the method, not of a dense grid, for cubic
+# B-spline blocks (the headline model): an evaluation of phi, J_phi and
+# W = J^-1 V (three bases with derivatives, the sum-factorised contraction of
+# 576 FMA, V = V_par + c V_perp and the 3x3 solve) 1340; rho's value where the
+# step is sampled 168; the RK bookkeeping of one attempt 120; one supersampling
+# sub-step (interpolation, transfer function, exp, front-to-back update) 40; one
+# face Newton iteration (bivariate value and partials, 3x3 solve) 400; one
+# box test 20.  Degree 2: 700 / 78 per evaluation; NURBS add the fourth
+# homogeneous channel and the quotient rule (1770 for cubic).
+UNIT_FLOPS = {
+    (3, False): {"w_eval": 1340, "rho": 168},
+    (3, True): {"w_eval": 1770, "rho": 200},
+    (2, False): {"w_eval": 700, "rho": 78},
+    (2, True): {"w_eval": 930, "rho": 95},
+}
+UNIT_COMMON = {"rk_step": 120, "subsample": 40, "face_iter": 400, "box_test": 20}
 
 
 def kernel_flops(st, p, rational):
-    u = unit_flops(p, rational)
-    stage1 = max(st["w_evals"] - 5 * st["rk_steps"], 0)
-    k2 = (st["w_evals"] * u["w_eval"] + stage1 * u["stage1_rho"] + st["rk_steps"] * u["rk_step"] +
+    u = dict(UNIT_FLOPS[(p, rational)], **UNIT_COMMON)
+    # rho is sampled once per accepted step (the first stage of the next attempt)
+    k2 = (st["w_evals"] * u["w_eval"] + st["samples"] * u["rho"] + st["rk_steps"] * u["rk_step"] +
           st["subsamples"] * u["subsample"])
     k1 = (st["box_tests"] * u["box_test"] + st["face_newton_iter"] * u["face_iter"] +
-          st["fp64_polish_iter"] * u["face_iter"] + st["segments"] * (u["w_eval"] + u["stage1_rho"]))
+          st["fp64_polish_iter"] * u["face_iter"] + st["segments"] * (u["w_eval"] + u["rho"]))
     return {"k_fragments": k1, "k_integrate": k2}
 
 
+def host_cpu():
+    """The host's CPU model, logical CPUs and the CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count() or 1, "usable": usable}
+
+
+# the CPU share of one GPU on the GPU host (worker pools are limited to it)
+CPU_SHARE = 16
+
+
 def cpu_baseline(sc, cam, gpu_rgba, seconds_target=15.0, seed=7):
+    """The oracle in reference mode (the judge of parity) and in method mode (the
+    GPU's method in FP64, the like-for-like CPU baseline), each on a bounded
+    uniform pixel sample of the same view, on the host's CPU share."""
     import oracle
     rng = np.random.default_rng(seed)
     npx = cam.width * cam.height
     prep = oracle.OracleScene(sc.patches, sc.scale)
-    nthreads = min(16, os.cpu_count() or 1)
-    n = 512
-    pix = rng.choice(npx, n, replace=False)
-    t0 = time.perf_counter()
-    ref = oracle.render(sc, cam, sc.tf, pixels=pix, prepared=prep, nthreads=nthreads)
-    dt = time.perf_counter() - t0
-    if dt < seconds_target / 4:
-        n = int(min(npx, max(n, n * seconds_target / max(dt, 1e-3))))
+    cpu = host_cpu()
+    nthreads = max(1, min(cpu["usable"], CPU_SHARE))
+
+    def timed(fn, n0):
+        n = n0
         pix = rng.choice(npx, n, replace=False)
         t0 = time.perf_counter()
-        ref = oracle.render(sc, cam, sc.tf, pixels=pix, prepared=prep, nthreads=nthreads)
+        out = fn(pix)
         dt = time.perf_counter() - t0
+        if dt < seconds_target / 4:
+            n = int(min(npx, max(n, n * seconds_target / max(dt, 1e-3))))
+            pix = rng.choice(npx, n, replace=False)
+            t0 = time.perf_counter()
+            out = fn(pix)
+            dt = time.perf_counter() - t0
+        return pix, out, dt
+
+    pix, ref, dt = timed(lambda px: oracle.render(sc, cam, sc.tf, pixels=px, prepared=prep, nthreads=nthreads), 512)
     err = float(np.abs(gpu_rgba[pix] - ref.rgba).max())
-    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{n} uniformly drawn pixels of the same 1920x1080 view, {dt:.1f} s"}, \
-        {"pixels": n, "max_abs_rgba_vs_oracle": err}
+    note = (f"{cpu['model']}, {cpu['nproc']} logical CPUs, {cpu['usable']} usable by this process, "
+            f"{nthreads} threads (the CPU share of one GPU)")
+    base = {"value": len(pix) / dt / 1e6, "unit": "Mrays/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{len(pix)} uniformly drawn pixels of the same 1920x1080 view, reference mode "
+                      f"(converged quadrature of Eq. (volRenderIntegral)), {dt:.1f} s; {note}"}
+    mpix, (mimg, msteps), mdt = timed(lambda px: oracle.render_method(sc, cam, sc.tf, pixels=px, prepared=prep,
+                                                                        nthreads=nthreads), 4096)
+    method = {"value": len(mpix) / mdt / 1e6, "unit": "Mrays/s", "cores": nthreads, "kind": "oracle method mode",
+              "sample": f"{len(mpix)} uniformly drawn pixels, the GPU's method in FP64 (adaptive RKF45, "
+                        f"same tolerance and step bounds), {mdt:.1f} s, {msteps} RK attempts",
+              "max_abs_rgba_vs_gpu": float(np.abs(gpu_rgba[mpix] - mimg).max())}
+    return base, method, {"pixels": len(pix), "max_abs_rgba_vs_oracle": err}
 
 
 def time_renders(r, sc, cam, steps, warmup, **kw):
@@ -147,7 +177,10 @@ def time_renders(r, sc, cam, steps, warmup, **kw):
 def mlp_vs_plain(r, steps, warmup):
     """Config 4 (256 NURBS blocks, 1920x1080): boundary-root Newton seeded by the
     trained MLP versus the plain element-centre seed (and the box seed, the
-    default), same GPU, same image within the parity bar."""
+    default), same GPU, same image within the parity bar; then the cold starts of
+    Sec. "Cutting and Near Clip Planes": with a cutting plane through the model,
+    the entries on it are found by Newton from the block centre or from the
+    network."""
     from scenes import make_config
     sc = make_config(4)
     cam = sc.cameras[0]
@@ -161,6 +194,13 @@ def mlp_vs_plain(r, steps, warmup):
         res[mode] = {"value": round(v, 3), "ms_per_step": round(ms, 4),
                      "newton_iter_per_root": round(st["face_newton_iter"] / max(st["face_newton"], 1), 4),
                      "ms_fragments": round(st["ms_fragments"], 4), "mlp_queries": st["mlp_queries"]}
+    centre = 0.5 * (sc.bbox[0] + sc.bbox[1])
+    cut = (centre, np.array([0.8, -0.2, 0.55]))
+    cold = {}
+    for mode in ("box", "mlp"):
+        v, ms, st, rgba = time_renders(r, sc, cam, steps, warmup, seed_mode=mode, cut_plane=cut)
+        cold[mode] = {"value": round(v, 3), "ms_per_step": round(ms, 4), "ms_integrate": round(st["ms_integrate"], 4),
+                      "entries_on_plane_seeded_by_network": st["mlp_restarts"], "w_evals": st["w_evals"]}
     return {"workload": "config4: step channel, 256 cubic NURBS patches of 8^3 control points, "
                         "1920x1080 view 0", "unit": "Mrays/s",
             "mlp_training": {"ms_samples": round(rep["ms_samples"], 2), "ms_train": round(rep["ms_train"], 2),
@@ -168,7 +208,34 @@ def mlp_vs_plain(r, steps, warmup):
                              "heldout_max_err": rep["heldout_max_err"]},
             "plain": res["plain"], "mlp": res["mlp"], "box": res["box"],
             "speedup_mlp_over_plain": round(res["mlp"]["value"] / res["plain"]["value"], 4),
-            "max_abs_rgba_mlp_vs_plain": float(np.abs(imgs["mlp"] - imgs["plain"]).max())}
+            "max_abs_rgba_mlp_vs_plain": float(np.abs(imgs["mlp"] - imgs["plain"]).max()),
+            "cold_start_at_cutting_plane": {"plane": "through the model's centre, normal (0.8, -0.2, 0.55)",
+                                            "centre_seed": cold["box"], "mlp_seed": cold["mlp"],
+                                            "speedup_mlp_over_centre": round(cold["mlp"]["value"] /
+                                                                             cold["box"]["value"], 4)}}
+
+
+def interior_ab(r, steps, warmup):
+    """The two interior methods on configs 3 and 4 at 1920x1080: the ray preimage
+    ODE by adaptive RKF45 (the default) and root finding, every sample's preimage
+    by Newton (Sec. "Root Finding Based Algorithm"), with the same step bounds."""
+    from scenes import make_config
+    out = {}
+    for k in (3, 4):
+        sc = make_config(k)
+        cam = sc.cameras[0]
+        r.upload(sc.patches)
+        row, imgs = {}, {}
+        for method in ("ode", "rf"):
+            v, ms, st, rgba = time_renders(r, sc, cam, steps, warmup, interior=method)
+            imgs[method] = rgba.cpu().numpy().reshape(-1, 4)
+            row[method] = {"value": round(v, 3), "ms_per_step": round(ms, 4),
+                           "ms_integrate": round(st["ms_integrate"], 4), "w_evals": st["w_evals"],
+                           "samples": st["samples"]}
+        row["speedup_rf_over_ode"] = round(row["rf"]["value"] / row["ode"]["value"], 4)
+        row["max_abs_rgba_rf_vs_ode"] = float(np.abs(imgs["rf"] - imgs["ode"]).max())
+        out[f"config{k}"] = row
+    return {"unit": "Mrays/s", **out}
 
 
 def batch_views(r, steps, warmup, seed=9):
@@ -212,7 +279,10 @@ def batch_views(r, steps, warmup, seed=9):
                         "mixed degree-2/3 lattice, 32 views of 256^2..2048^2 in one graph replay",
             "unit": "Mrays/s", "rays_per_batch": rays, "value": round(rays * steps / el / 1e6, 3),
             "ms_per_batch": round(1e3 * el / steps, 3), "steps": steps, "warmup": warmup,
-            "segments": st["segments"], "ms_fragments": round(st["ms_fragments"], 3),
+            "segments": st["segments"],
+            "counters": {k: st[k] for k in ("samples", "subsamples", "rk_steps", "rk_rejected", "w_evals",
+                                            "drift_restarts", "restart_fail", "degenerate", "anomalies")},
+            "ms_fragments": round(st["ms_fragments"], 3),
             "ms_integrate": round(st["ms_integrate"], 3), "ms_merge": round(st["ms_merge"], 3),
             "autotune": {k: tune[k] for k in ("tile_w", "tile_h", "xcd_chunk", "int_block",
                                               "int_waves_cu", "ms_before", "ms_after")},
@@ -241,6 +311,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-ab", action="store_true", help="skip the RF-vs-ODE interior-method comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 5 times (reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -280,6 +351,7 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     rays = cam.width * cam.height
     value = rays * args.steps / elapsed / 1e6
+    per_render = phases.sum(axis=1)      # fragments + integrator + merge of every timed render
 
     # counters of one render (deterministic work) -> algorithmic FLOPs per launch
     _, _, st = r.render(cam, sc.tf, opts=opts, rgba=rgba, depth=depth, stats=True)
@@ -291,31 +363,41 @@ def main():
     achieved = flops[dom] / (avg_ms[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(dom),
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "frac_of_unpacked_fp32": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4),
+                "traffic": measured_traffic(dom),
                 "avg_ms": {k: round(v, 4) for k, v in avg_ms.items()},
                 "algorithmic_gflop_per_launch": {k: round(v / 1e9, 3) for k, v in flops.items()}}
 
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+           "ms_per_render_events": {"median": round(float(np.median(per_render)), 4),
+                                    "p10": round(float(np.percentile(per_render, 10)), 4),
+                                    "p90": round(float(np.percentile(per_render, 90)), 4)},
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": "config3: bent beam, 64 cubic B-spline patches of 10^3 control "
                                   "points, 3-Gaussian+ramp field, 8-knot transfer function, "
                                   f"1920x1080 view {args.view}",
                       "width": cam.width, "height": cam.height, "patches": len(sc.patches),
-                      "rk_tol": opts.rk_tol, "rho_interp": "hermite", "n_super": opts.n_super},
+                      "rk_tol": opts.rk_tol, "rho_interp": "hermite", "n_super": opts.n_super,
+                      "interior": "ode (adaptive RKF45)"},
            "roofline": roofline,
+           "device_bytes": r.device_bytes(),
            "counters": {k: st[k] for k in ("segments", "fragments", "anomalies", "rk_steps",
                                            "rk_rejected", "samples", "w_evals", "subsamples",
                                            "face_newton", "face_newton_iter", "fp64_polish_iter",
-                                           "box_tests")}}
+                                           "box_tests", "drift_restarts")}}
     if not args.no_cpu_baseline:
         img = rgba.cpu().numpy().reshape(-1, 4).astype(np.float64)
-        cpu, parity = cpu_baseline(sc, cam, img)
+        cpu, method, parity = cpu_baseline(sc, cam, img)
         out["cpu_baseline"] = cpu
+        out["cpu_baseline_method_mode"] = method
         out["parity_sample"] = parity
     if not args.no_mlp:
         out["mlp_vs_plain"] = mlp_vs_plain(r, args.steps, args.warmup)
+    if not args.no_ab:
+        out["interior_rf_vs_ode"] = interior_ab(r, args.steps, args.warmup)
     if not args.no_batch:
         out["batch_views"] = batch_views(r, max(args.steps // 4, 3), 2)
     print(json.dumps(out))

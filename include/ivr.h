@@ -145,7 +145,7 @@ typedef struct {
                                    model's scale, checked before every sample:
                                    beyond it the point is found again by Newton
                                    from p (from the block's network with MLP
-                                   seeds) before it is sampled; 0: no check [1e-5] */
+                                   seeds) before it is sampled; 0: no check [1e-4] */
     int32_t interior;           /* IVR_INTERIOR_*: how a segment's samples find
                                    their parameter points                 [ODE] */
     int32_t cut;                /* 1: a cutting plane (Sec. "Cutting and Near Clip
@@ -200,7 +200,10 @@ typedef struct {
     uint64_t mlp_restarts;      /* shrunk entries whose Newton the network seeded */
     uint64_t drift_restarts;    /* samples put back on the ray by Newton (drift_tol) */
     uint64_t restart_fail;      /* of which Newton did not converge               */
-    double ms_fragments, ms_integrate, ms_merge;  /* event times per phase      */
+    double ms_fragments, ms_integrate, ms_merge;  /* event times per phase: the
+                                   fragment launches with the block sort that
+                                   follows them, the integrator launches, the
+                                   merge                                       */
 } ivr_stats;
 
 /* Creates a context on `device` using `hip_stream` (a hipStream_t; NULL = the

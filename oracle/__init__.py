@@ -51,6 +51,11 @@ class _Opts(C.Structure):
                 ("cut_point", C.c_double * 3), ("cut_normal", C.c_double * 3), ("near_clip", C.c_double)]
 
 
+class _MethodOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("h_max", C.c_double), ("c_perp", C.c_double), ("rho_step", C.c_double),
+                ("tf_step", C.c_double), ("n_super", C.c_int32), ("hermite", C.c_int32), ("nthreads", C.c_int32)]
+
+
 class Fragment(C.Structure):
     _fields_ = [("t", C.c_double), ("p", C.c_double * 3), ("patch", C.c_int32),
                 ("face", C.c_int32), ("entering", C.c_int32), ("pad", C.c_int32)]
@@ -91,6 +96,10 @@ def lib():
         L.orc_render_pixels.restype = C.c_int32
         L.orc_locate.argtypes = [C.c_void_p, dp, C.c_int64, C.POINTER(C.c_int32), dp, dp]
         L.orc_locate.restype = C.c_int32
+        L.orc_render_pixels_method.argtypes = [C.c_void_p, C.POINTER(_Camera), C.POINTER(_TF),
+                                               C.POINTER(_MethodOpts), C.POINTER(C.c_int64), C.c_int64, dp,
+                                               C.POINTER(C.c_int64)]
+        L.orc_render_pixels_method.restype = C.c_int32
         L.orc_table1.argtypes = [C.c_int32, C.c_double, C.c_double]
         L.orc_table1.restype = C.c_double
         _lib = L
@@ -287,3 +296,31 @@ def render(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None,
     if rc != 0:
         raise RuntimeError(f"orc_render_pixels failed ({rc})")
     return RenderResult(rgba, depth, [diag[i] for i in range(npix)])
+
+
+def render_method(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None, rk_tol: float = 1e-5,
+                  h_max: float = 0.0, c_perp: float = 1.0, rho_step: float = 0.1, tf_step: float = 0.025,
+                  n_super: int = 4, hermite: bool = True, nthreads: int = 0, scale: Optional[float] = None,
+                  prepared: Optional[OracleScene] = None):
+    """Method mode: the GPU path's method (adaptive RKF45 on the ray preimage ODE,
+    Hermite or linear rho, supersampling) in FP64.  Returns (rgba, rk attempts)."""
+    if prepared is None:
+        patches = getattr(scene_or_patches, "patches", scene_or_patches)
+        if scale is None:
+            scale = scene_or_patches.scale
+        prepared = OracleScene(patches, scale)
+    mo = _MethodOpts(float(rk_tol), float(h_max), float(c_perp), float(rho_step), float(tf_step),
+                     int(n_super), 1 if hermite else 0, int(nthreads))
+    tf_s = OracleTF(tf)
+    if pixels is None:
+        npix, pix_ptr = cam.width * cam.height, None
+    else:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        npix, pix_ptr = len(pixels), pixels.ctypes.data_as(C.POINTER(C.c_int64))
+    rgba = np.zeros((npix, 4))
+    steps = C.c_int64(0)
+    rc = lib().orc_render_pixels_method(prepared.handle, C.byref(_camera(cam)), C.byref(tf_s.struct), C.byref(mo),
+                                        pix_ptr, npix, _dp(rgba), C.byref(steps))
+    if rc != 0:
+        raise RuntimeError(f"orc_render_pixels_method failed ({rc})")
+    return rgba, steps.value

@@ -993,6 +993,17 @@ int32_t orc_render_pixels(const orc_scene *s, const orc_camera *cam, const orc_t
  * J_phi W = V(phi(p)) (Eq. (VgVp)) with V = V_par + c V_perp (Eq. (vec2));
  * N = round(L/ds) uniform explicit RK steps; the error is the largest distance
  * of phi(p_i) from the view ray (caption of the table).                      */
+/* Runge-Kutta-Fehlberg 4(5): stages A_rkf, 5th-order weights b_rkf (the
+   solution carried on), 4th-order weights b4_rkf (the embedded estimate).    */
+static const double A_rkf[6][6] = {{0},
+                                   {1.0 / 4},
+                                   {3.0 / 32, 9.0 / 32},
+                                   {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197},
+                                   {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104},
+                                   {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40}};
+static const double b_rkf[6] = {16.0 / 135, 0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50, 2.0 / 55};
+static const double b4_rkf[6] = {25.0 / 216, 0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0};
+
 static void t1_phi(const double p[2], double g[2], double J[4])
 {
     double x = p[0], y = p[1];
@@ -1029,14 +1040,6 @@ double orc_table1(int32_t method, double ds, double c)
     static const double b_rk4[6] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
     static const double A_38[4][6] = {{0}, {1.0 / 3}, {-1.0 / 3, 1}, {1, -1, 1}};
     static const double b_38[6] = {1.0 / 8, 3.0 / 8, 3.0 / 8, 1.0 / 8};
-    static const double A_rkf[6][6] = {{0},
-                                       {1.0 / 4},
-                                       {3.0 / 32, 9.0 / 32},
-                                       {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197},
-                                       {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104},
-                                       {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40}};
-    static const double b_rkf[6] = {16.0 / 135, 0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50,
-                                    2.0 / 55};
     const double(*A)[6];
     const double *b;
     int st;
@@ -1079,4 +1082,280 @@ double orc_table1(int32_t method, double ds, double c)
         if (e > err) err = e;
     }
     return err;
+}
+
+/* ------------------------------------------------------------------ method mode
+ * The method itself in FP64, as a diagnostic and as the like-for-like CPU
+ * baseline of the GPU path: for each segment of Algorithm "Blockwise
+ * depth-sorting" the ray preimage ODE p' = W(p), J_phi(p) W = V_par + c V_perp
+ * (Eqs. (odepar), (VgVp), (vec2), V_perp towards the view ray), integrated by
+ * the Fehlberg 4(5) pair carrying the 5th-order solution: error
+ * max_c |p5 - p4| <= tol, h <- h clamp(0.8 (tol/err)^(1/5), 0.2, 2.5) (no growth
+ * right after a rejection), h <= h_max and h <= rho_step / |dn/ds|, iterates
+ * clamped to P.  rho is sampled at every accepted step; between two samples it
+ * is the cubic Hermite interpolant of the values and d rho/ds = grad rho . W
+ * (hermite) or linear, and the interval is supersampled (Sec. "Quadrature of
+ * volume render integral") with the midpoints of
+ * max(n_super, span/dn, span * slope/tf_step) equal sub-steps (at most 128),
+ * span the change of n over the interval, dn half the smallest knot gap of the
+ * transfer function within [1/64, 1/16] and slope the transfer function's
+ * largest slope over the interval's range of n; each sub-step composited by
+ * Algorithm "Front-to-back compositing" with T = exp(-kappa ds).  The last step
+ * ends on the exit, closing with rho there.                                  */
+
+/* phi, J (J[r*3+q] = d phi_r / d p_q), rho and its parameter gradient at p. */
+static void eval_rho_grad(const orc_patch *P, const double pin[3], double x[3], double J[9], double *rho,
+                          double g[3])
+{
+    double Nb[3][MAXN], dNb[3][MAXN], p[3];
+    for (int d = 0; d < 3; ++d) {
+        p[d] = clamp01(pin[d]);
+        orc_basis(P->knots[d], P->ncp[d] + P->deg[d] + 1, P->deg[d], p[d], Nb[d], dNb[d]);
+    }
+    const int n0 = P->ncp[0], n1 = P->ncp[1], n2 = P->ncp[2];
+    double A[4] = {0, 0, 0, 0}, dA[3][4] = {{0}}, R = 0.0, dR[3] = {0, 0, 0};
+    for (int k = 0; k < n2; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n0; ++i) {
+                const double b = Nb[0][i] * Nb[1][j] * Nb[2][k];
+                const double bd[3] = {dNb[0][i] * Nb[1][j] * Nb[2][k], Nb[0][i] * dNb[1][j] * Nb[2][k],
+                                      Nb[0][i] * Nb[1][j] * dNb[2][k]};
+                if (b == 0.0 && bd[0] == 0.0 && bd[1] == 0.0 && bd[2] == 0.0) continue;
+                const size_t li = i + (size_t)n0 * (j + (size_t)n1 * k);
+                const double *c = P->cp + 4 * li;
+                const double w = P->rational ? c[3] : 1.0, sc = P->scalar[li];
+                for (int r = 0; r < 3; ++r) A[r] += b * w * c[r];
+                A[3] += b * w;
+                R += b * w * sc;
+                for (int q = 0; q < 3; ++q) {
+                    for (int r = 0; r < 3; ++r) dA[q][r] += bd[q] * w * c[r];
+                    dA[q][3] += bd[q] * w;
+                    dR[q] += bd[q] * w * sc;
+                }
+            }
+    /* quotient rule (the denominator is 1 for B-splines) */
+    for (int r = 0; r < 3; ++r) x[r] = A[r] / A[3];
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) J[r * 3 + q] = (dA[q][r] - x[r] * dA[q][3]) / A[3];
+    *rho = R / A[3];
+    for (int q = 0; q < 3; ++q) g[q] = (dR[q] - *rho * dA[q][3]) / A[3];
+}
+
+/* W(p) of Eq. (VgVp); rho, grad rho at p.  Returns -1 if J is singular. */
+static int method_W(const orc_patch *P, const double p[3], const double gin[3], const double d[3], double c,
+                    double W[3], double *rho, double g[3])
+{
+    double x[3], J[9], r[3], V[3];
+    eval_rho_grad(P, p, x, J, rho, g);
+    for (int q = 0; q < 3; ++q) r[q] = gin[q] - x[q];
+    const double rd = r[0] * d[0] + r[1] * d[1] + r[2] * d[2];
+    for (int q = 0; q < 3; ++q) V[q] = d[q] + c * (r[q] - rd * d[q]);
+    return solve3(J, V, W);
+}
+
+/* the transfer function's largest slope (any channel; A without the extinction)
+   on interval k of n, and over the intervals of n that meet [lo, hi] together
+   with their neighbours (the bound the sub-steps are counted with) */
+static double tf_interval_slope(const orc_tf *tf, int k)
+{
+    double m = 0.0;
+    if (k < 0 || k + 1 >= tf->n) return 0.0;
+    for (int c = 0; c < 4; ++c) {
+        const double s = fabs(tf->rgba[4 * (k + 1) + c] - tf->rgba[4 * k + c]) / (tf->x[k + 1] - tf->x[k]);
+        if (s > m) m = s;
+    }
+    return m;
+}
+
+/* The sub-step count is an integer that floating point decides: its thresholds
+   (the slope bounds, the knots, the range of n, dn and tf_step) are taken in
+   binary32, the precision the GPU path holds them in, so that both sides count
+   alike.  f32() rounds to it. */
+static double f32(double v) { return (double)(float)v; }
+
+static double tf_slope(const orc_tf *tf, double lo, double hi)
+{
+    double m = 0.0;
+    lo = f32(lo);
+    hi = f32(hi);
+    for (int k = 0; k + 1 < tf->n; ++k) {
+        /* interval k is [x_k, x_{k+1}); the first reaches down and the last up */
+        const double a = k == 0 ? -INFINITY : f32(tf->x[k]), b = k + 2 == tf->n ? INFINITY : f32(tf->x[k + 1]);
+        if (b <= lo || a > hi) continue;
+        for (int q = k - 1; q <= k + 1; ++q) m = fmax(m, f32(tf_interval_slope(tf, q)));
+    }
+    return m;
+}
+
+static void method_interval(const orc_tf *tf, const orc_method_opts *mo, double ra, double ma, double rb,
+                            double mb, double len, double C[3], double *A)
+{
+    const double inv = 1.0 / (tf->domain[1] - tf->domain[0]);
+    const double sa = mo->hermite ? ma * len : rb - ra, sb = mo->hermite ? mb * len : rb - ra;
+    const double span = fmax(fabs(rb - ra), 0.5 * (fabs(sa) + fabs(sb))) * inv;
+    double gap = 1.0;
+    for (int k = 0; k + 1 < tf->n; ++k) gap = fmin(gap, tf->x[k + 1] - tf->x[k]);
+    const double dn = f32(fmin(1.0 / 16.0, fmax(1.0 / 64.0, 0.5 * gap)));
+    const double na = (ra - tf->domain[0]) * inv, nb = (rb - tf->domain[0]) * inv;
+    const double over = 0.25 * (fabs(sa) + fabs(sb)) * inv;
+    const double slope = tf_slope(tf, fmin(na, nb) - over, fmax(na, nb) + over);
+    int ns = (int)ceil(fmax(span / dn, span * slope / f32(mo->tf_step)));
+    if (ns < mo->n_super) ns = mo->n_super;
+    if (ns > 128) ns = 128;
+    const double ds = len / ns;
+    for (int j = 0; j < ns; ++j) {
+        const double u = (j + 0.5) / ns, u2 = u * u, u3 = u2 * u;
+        const double rho = (2 * u3 - 3 * u2 + 1) * ra + (u3 - 2 * u2 + u) * sa + (3 * u2 - 2 * u3) * rb +
+                           (u3 - u2) * sb;
+        double e[4];
+        orc_transfer(tf, rho, e);
+        const double T = exp(-e[3] * ds);
+        for (int c = 0; c < 3; ++c) C[c] += (1.0 - T) * (1.0 - *A) * e[c];
+        *A += (1.0 - T) * (1.0 - *A);
+    }
+}
+
+static void method_segment(const orc_patch *P, const orc_tf *tf, const orc_method_opts *mo, double scale,
+                           const double o[3], const double d[3], const orc_fragment *fi, const orc_fragment *fo,
+                           double out[4], long long *steps)
+{
+    const double L = fo->t - fi->t, hmax = mo->h_max > 0 ? mo->h_max : scale / 32.0;
+    const double hmin = fmin(hmax, 1.5625e-6 * scale);
+    double gin[3], p[3], W[3], rho, g[3], C[3] = {0, 0, 0}, A = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        gin[q] = o[q] + fi->t * d[q];
+        p[q] = fi->p[q];
+    }
+    method_W(P, p, gin, d, mo->c_perp, W, &rho, g);
+    double rho_a = rho, m_a = g[0] * W[0] + g[1] * W[1] + g[2] * W[2];
+    double rho_out, m_out, Wo[3], go[3];
+    {
+        double x[3], J[9];
+        eval_rho_grad(P, fo->p, x, J, &rho_out, go);
+        if (solve3(J, d, Wo) != 0) Wo[0] = Wo[1] = Wo[2] = 0.0;
+        m_out = go[0] * Wo[0] + go[1] * Wo[1] + go[2] * Wo[2];
+    }
+    const double inv = 1.0 / (tf->domain[1] - tf->domain[0]);
+    double s = 0.0, h = fmin(L, hmax);
+    int rejected = 0;
+    for (int it = 0; it < 200000 && s < L && A < 1.0 - 1e-4; ++it) {
+        const double hf = mo->rho_step / (fabs(m_a) * inv + 1e-300);
+        if (h > hf) h = fmax(hf, hmin);
+        const double hh = fmin(h, L - s);
+        double k[6][3], p5[3], err = 0.0;
+        for (int i = 0; i < 6; ++i) {
+            double q[3], rr, gg[3];
+            for (int c = 0; c < 3; ++c) {
+                q[c] = p[c];
+                for (int j = 0; j < i; ++j) q[c] += hh * A_rkf[i][j] * k[j][c];
+                q[c] = clamp01(q[c]);
+            }
+            if (i == 0) {
+                for (int c = 0; c < 3; ++c) k[0][c] = W[c];
+            } else {
+                method_W(P, q, gin, d, mo->c_perp, k[i], &rr, gg);
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            double a5 = p[c], a4 = p[c];
+            for (int i = 0; i < 6; ++i) {
+                a5 += hh * b_rkf[i] * k[i][c];
+                a4 += hh * b4_rkf[i] * k[i][c];
+            }
+            p5[c] = a5;
+            if (fabs(a5 - a4) > err) err = fabs(a5 - a4);
+        }
+        ++*steps;
+        const int accept = err <= mo->tol || hh <= hmin;
+        if (accept) {
+            s += hh;
+            if (L - s <= 1e-6 * L) {
+                method_interval(tf, mo, rho_a, m_a, rho_out, m_out, hh, C, &A);
+                break;
+            }
+            for (int c = 0; c < 3; ++c) p[c] = clamp01(p5[c]);
+            method_W(P, p, gin, d, mo->c_perp, W, &rho, g);
+            const double m_b = g[0] * W[0] + g[1] * W[1] + g[2] * W[2];
+            method_interval(tf, mo, rho_a, m_a, rho, m_b, hh, C, &A);
+            rho_a = rho;
+            m_a = m_b;
+        }
+        double fac = err > 0.0 ? 0.8 * pow(mo->tol / err, 0.2) : 2.5;
+        fac = fac < 0.2 ? 0.2 : (fac > 2.5 ? 2.5 : fac);
+        if (accept && rejected && fac > 1.0) fac = 1.0;
+        rejected = !accept;
+        h = fmin(hmax, fmax(hmin, hh * fac));
+    }
+    out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = A;
+}
+
+typedef struct {
+    const orc_scene *s;
+    const orc_camera *cam;
+    const orc_tf *tf;
+    const orc_method_opts *mo;
+    const int64_t *pixels;
+    int64_t npix;
+    double *rgba;
+    long long steps;
+    int tid, nthreads;
+} mjob_t;
+
+static void *method_worker(void *arg)
+{
+    mjob_t *j = arg;
+    orc_fragment *fr = malloc(sizeof(orc_fragment) * FRAG_CAP);
+    int (*pairs)[2] = malloc(sizeof(int[2]) * FRAG_CAP);
+    for (int64_t i = j->tid; i < j->npix; i += j->nthreads) {
+        const int64_t pix = j->pixels ? j->pixels[i] : i;
+        double o[3], d[3], *out = j->rgba + 4 * i;
+        orc_camera_ray(j->cam, pix % j->cam->width + 0.5, pix / j->cam->width + 0.5, o, d);
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        const int n = orc_ray_fragments(j->s, o, d, fr, FRAG_CAP);
+        if (n <= 0) continue;
+        int anom = 0;
+        const int np = pair_fragments(fr, n, 1e-9 * j->s->scale, 0, pairs, &anom);
+        /* front to back by entry depth */
+        for (int a = 1; a < np; ++a)
+            for (int b = a; b > 0 && fr[pairs[b][0]].t < fr[pairs[b - 1][0]].t; --b) {
+                int t0 = pairs[b][0], t1 = pairs[b][1];
+                pairs[b][0] = pairs[b - 1][0]; pairs[b][1] = pairs[b - 1][1];
+                pairs[b - 1][0] = t0; pairs[b - 1][1] = t1;
+            }
+        double C[3] = {0, 0, 0}, A = 0.0;
+        for (int k = 0; k < np && A < 1.0 - 1e-4; ++k) {
+            double r[4];
+            const orc_fragment *fi = &fr[pairs[k][0]], *fo = &fr[pairs[k][1]];
+            method_segment(&j->s->patches[fo->patch], j->tf, j->mo, j->s->scale, o, d, fi, fo, r, &j->steps);
+            for (int c = 0; c < 3; ++c) C[c] += (1.0 - A) * r[c];
+            A += (1.0 - A) * r[3];
+        }
+        out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = A;
+    }
+    free(fr);
+    free(pairs);
+    return NULL;
+}
+
+int32_t orc_render_pixels_method(const orc_scene *s, const orc_camera *cam, const orc_tf *tf,
+                                 const orc_method_opts *mo, const int64_t *pixels, int64_t npix, double *rgba,
+                                 int64_t *rk_steps)
+{
+    if (!s || !cam || !tf || !mo || !rgba || tf->n < 2 || !(mo->tol > 0)) return -1;
+    int nt = mo->nthreads > 0 ? mo->nthreads : (int)sysconf(_SC_NPROCESSORS_ONLN);
+    if (nt < 1) nt = 1;
+    if (nt > 256) nt = 256;
+    pthread_t th[256];
+    mjob_t jobs[256];
+    for (int t = 0; t < nt; ++t) {
+        jobs[t] = (mjob_t){s, cam, tf, mo, pixels, npix, rgba, 0, t, nt};
+        pthread_create(&th[t], NULL, method_worker, &jobs[t]);
+    }
+    long long total = 0;
+    for (int t = 0; t < nt; ++t) {
+        pthread_join(th[t], NULL);
+        total += jobs[t].steps;
+    }
+    if (rk_steps) *rk_steps = total;
+    return 0;
 }

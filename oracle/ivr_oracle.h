@@ -113,6 +113,17 @@ int32_t orc_ray_fragments(const orc_scene *s, const double o[3], const double d[
 int32_t orc_render_pixels(const orc_scene *s, const orc_camera *cam, const orc_tf *tf,
                           const orc_opts *opts, const int64_t *pixels, int64_t npix,
                           double *rgba, double *depth, orc_pixel_diag *diag);
+/* Method mode: the GPU path's method in FP64 (ray preimage ODE by adaptive
+   RKF45, Hermite or linear rho between samples, supersampling, Algorithm
+   "Front-to-back compositing"), a diagnostic and the like-for-like CPU
+   baseline.  Writes RGBA per pixel and the RK attempts in all. */
+typedef struct {
+    double tol, h_max, c_perp, rho_step, tf_step;  /* h_max <= 0: scale/32       */
+    int32_t n_super, hermite, nthreads;
+} orc_method_opts;
+int32_t orc_render_pixels_method(const orc_scene *s, const orc_camera *cam, const orc_tf *tf,
+                                 const orc_method_opts *mo, const int64_t *pixels, int64_t npix, double *rgba,
+                                 int64_t *rk_steps);
 /* Convergence study: error of an explicit RK method on the analytic 2-D map.
    method 1 Euler, 2 midpoint, 3 Kutta, 4 classic, 5 3/8-rule, 6 Fehlberg (5th). */
 double orc_table1(int32_t method, double ds, double c);

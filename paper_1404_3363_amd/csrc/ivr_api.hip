@@ -62,10 +62,9 @@ struct ivr_ctx {
     size_t pix_cap = 0, seg_cap = 0, seg_bytes_cap = 0;
     double seg_ratio = 0.0, cand_ratio = 0.0;
     size_t model_bytes = 0;
-    uint32_t *h_qs = nullptr;             // pinned: (segments requested, candidates recorded)
-    hipEvent_t qs_ev = nullptr;
-    uint64_t qs_pixels = 0;               // pixels of the batch last read back
-    bool qs_pending = false;
+    // pinned host memory the merge kernel writes each frame's (segments requested,
+    // candidates recorded, pixels) to, and its device address
+    uint32_t *h_totals = nullptr, *d_totals = nullptr;
 
     void *d_segs = nullptr;
     uint2 *d_pixseg = nullptr;
@@ -724,7 +723,7 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->rho_step = 0.1;
     o->cand_per_pixel = 8;
     o->det_singular = 1e-6;
-    o->drift_tol = 1e-5;
+    o->drift_tol = 1e-4;
     o->interior = IVR_INTERIOR_ODE;
     o->cut = 0;
     for (int q = 0; q < 3; ++q) o->cut_point[q] = o->cut_normal[q] = 0.0;
@@ -766,8 +765,8 @@ ivr_status ivr_create(ivr_ctx **out, int32_t device, void *hip_stream) {
     // the view table and the pinned counter staging exist from the start, so that
     // ivr_render_noalloc allocates nothing
     if (hipHostMalloc((void **)&c->h_ctr, sizeof(unsigned long long) * C_COUNT) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_qs, 2 * sizeof(uint32_t)) != hipSuccess ||
-        hipEventCreateWithFlags(&c->qs_ev, hipEventDisableTiming) != hipSuccess || ensure_views(c, 8) != IVR_OK) {
+        hipHostMalloc((void **)&c->h_totals, 4 * sizeof(uint32_t), hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->d_totals, c->h_totals, 0) != hipSuccess || ensure_views(c, 8) != IVR_OK) {
         ivr_destroy(c);
         return IVR_ENOMEM;
     }
@@ -832,8 +831,7 @@ void ivr_destroy(ivr_ctx *c) {
     dfree(c->d_views);
     if (c->h_views) (void)hipHostFree(c->h_views);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
-    if (c->h_qs) (void)hipHostFree(c->h_qs);
-    if (c->qs_ev) (void)hipEventDestroy(c->qs_ev);
+    if (c->h_totals) (void)hipHostFree(c->h_totals);
     if (c->views_copied) (void)hipEventDestroy(c->views_copied);
     if (c->capture) (void)hipStreamDestroy(c->capture);
     for (auto &e : c->ev)
@@ -1410,23 +1408,15 @@ static ivr_status ensure_views(ivr_ctx *c, int n) {
     return IVR_OK;
 }
 
-// The segment and candidate totals of the last render, once its readback has
-// arrived (no waiting): the per-pixel ratios that size the next frame's buffers.
+// The segment and candidate totals of the last frame that the merge kernel has
+// written to host memory (no waiting; a frame still in flight shows an earlier
+// one): the per-pixel ratios that size the next frame's buffers.
 static void poll_counts(ivr_ctx *c) {
-    if (!c->qs_pending || hipEventQuery(c->qs_ev) != hipSuccess) return;
-    c->qs_pending = false;
-    if (c->qs_pixels == 0) return;
-    c->seg_ratio = std::max(c->seg_ratio, (double)c->h_qs[0] / (double)c->qs_pixels);
-    c->cand_ratio = std::max(c->cand_ratio, (double)c->h_qs[1] / (double)c->qs_pixels);
-}
-
-// After a render of the context's buffers: copy its totals to pinned memory.
-static ivr_status enqueue_counts(ivr_ctx *c, const QueueState *qs, uint64_t pixels) {
-    IVR_HIP(c, hipMemcpyAsync(c->h_qs, qs, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-    IVR_HIP(c, hipEventRecord(c->qs_ev, c->stream));
-    c->qs_pixels = pixels;
-    c->qs_pending = true;
-    return IVR_OK;
+    const volatile uint32_t *t = c->h_totals;
+    const uint32_t segs = t[0], cands = t[1], pixels = t[2];
+    if (pixels == 0) return;
+    c->seg_ratio = std::max(c->seg_ratio, (double)segs / (double)pixels);
+    c->cand_ratio = std::max(c->cand_ratio, (double)cands / (double)pixels);
 }
 
 static Model device_model(ivr_ctx *c) {
@@ -1470,6 +1460,7 @@ struct FrameBufs {
     uint32_t *pcount = nullptr, *pbase = nullptr, *pcur = nullptr;
     CandLists mq = {nullptr, nullptr, nullptr, nullptr, nullptr, 0};   // c_cap: what may be recorded
     ViewRec *views = nullptr;
+    uint32_t *totals = nullptr;           // host-mapped frame totals, or null
 };
 
 // Validates the views and fills the pinned view table (at most view_cap views);
@@ -1563,6 +1554,7 @@ static ivr_status prepare_batch(ivr_ctx *c, const HostView *hv, int n, const ivr
     fb.mq = c->mq;
     fb.mq.c_cap = b.c_cap;
     fb.views = c->d_views;
+    fb.totals = c->d_totals;
     return IVR_OK;
 }
 
@@ -1574,9 +1566,11 @@ static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const FrameBufs &fb, 
     if (ev) IVR_HIP(c, hipEventRecord(ev[0], s));
     IVR_HIP(c, launch_fragments(b.fp64, b.mlp, m, fb.views, b.n, b.n_tiles, lc, fb.segs, (uint32_t)fb.seg_cap,
                                 fb.seg_kr, fb.pcount, fb.qs, fb.pixseg, fb.mq, fb.ctr, c->n_cu, s));
-    if (ev) IVR_HIP(c, hipEventRecord(ev[1], s));
     IVR_HIP(c, launch_block_sort(fb.qs, (uint32_t)fb.seg_cap, fb.seg_kr, c->d_pperm, c->npatch, fb.pcount,
                                  fb.pbase, fb.pcur, fb.order, c->n_cu, s));
+    // the fragment phase ends after the (short) block sort, so that the
+    // integrator phase is the integrator launches alone
+    if (ev) IVR_HIP(c, hipEventRecord(ev[1], s));
     for (int k = 0; k < kClasses; ++k) {
         if (!((b.class_mask >> k) & 1)) continue;
         IntegrateArgs ia;
@@ -1592,7 +1586,7 @@ static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const FrameBufs &fb, 
         IVR_HIP(c, launch_integrate(b.fp64, b.method, k, m, fb.views, b.n, fb.segs, ia, fb.ctr, c->n_cu, lc, s));
     }
     if (ev) IVR_HIP(c, hipEventRecord(ev[2], s));
-    IVR_HIP(c, launch_merge(fb.views, b.n, b.n_pixels, fb.pixseg, fb.segs, b.fp64, s));
+    IVR_HIP(c, launch_merge(fb.views, b.n, b.n_pixels, fb.pixseg, fb.segs, b.fp64, fb.qs, fb.totals, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[3], s));
     return IVR_OK;
 }
@@ -1657,13 +1651,11 @@ static ivr_status render_direct(ivr_ctx *c, const HostView *hv, int n, const ivr
         if (st != IVR_OK) return st;
         st = launch_batch(c, b, fb, lc, ev, c->stream);
         if (st != IVR_OK) return st;
-        st = enqueue_counts(c, fb.qs, b.n_pixels);
-        if (st != IVR_OK) return st;
         if (!stats) return IVR_OK;
         st = read_stats(c, fb.ctr, stats);
         if (st != IVR_OK) return st;
         poll_counts(c);   // the stream has finished: the totals are here
-        if (c->h_qs[0] <= fb.seg_cap || attempt > 0) return IVR_OK;
+        if (c->h_totals[0] <= fb.seg_cap || attempt > 0) return IVR_OK;
     }
 }
 
@@ -1809,8 +1801,6 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
         it = c->graphs.emplace(key, ge).first;
     }
     IVR_HIP(c, hipGraphLaunch(it->second, c->stream));
-    st = enqueue_counts(c, fb.qs, b.n_pixels);
-    if (st != IVR_OK) return st;
     c->err.clear();
     return IVR_OK;
 }

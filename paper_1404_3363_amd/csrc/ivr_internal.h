@@ -21,7 +21,7 @@ hipError_t launch_integrate(bool fp64, int method, int klass, const Model &m, co
                             unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st);
 
 hipError_t launch_merge(const ViewRec *views, int n_views, uint32_t n_pixels, const uint2 *pixseg,
-                        const void *segs, bool fp64, hipStream_t st);
+                        const void *segs, bool fp64, const QueueState *qs, uint32_t *totals, hipStream_t st);
 
 hipError_t launch_clear(QueueState *qs, unsigned long long *ctr, bool collect, uint32_t *pcount, int npatch,
                         hipStream_t st);

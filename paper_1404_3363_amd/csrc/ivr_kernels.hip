@@ -888,6 +888,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
 constexpr uint32_t kJustRestarted = 1u << 31;
 constexpr uint32_t kExitOnPlane = 1u << 30;
 constexpr uint32_t kEndSample = 1u << 29;
+constexpr uint32_t kSecondSeed = 1u << 28;   // this Newton restarted from its second seed
 constexpr uint32_t kPublicFlags = 0xFFFFu;
 
 __device__ __forceinline__ float pow_fifth(float x) { return exp2f(0.2f * __log2f(x)); }
@@ -1249,6 +1250,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             } else if (++newton_it < (shrink == -2 ? 24 : 12) && isfinite(k1[0] + k1[1] + k1[2])) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) p[c] = clamp01(p[c] + k1[c]);
+            } else if (fp.seed_mode == IVR_SEED_MLP && !(fl & kSecondSeed)) {
+                // with MLP seeds a second seed: the block's network for a drift
+                // restart (which started from the drifted point), the block centre for
+                // an entry on a plane (which started from the network)
+                fl |= kSecondSeed;
+                newton_it = 0;
+                if (shrink == -1) {
+                    float pm[3];
+                    mlp_seed_at(m.mlp_wb, m.mlp_norm, blk, float(gin[0]), float(gin[1]), float(gin[2]), pm);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) p[c] = isfinite(pm[0] + pm[1] + pm[2]) ? clamp01(R(pm[c])) : R(0.5);
+                    count_rare(C_MLP_RESTARTS);
+                } else {
+                    p[0] = p[1] = p[2] = R(0.5);
+                }
             } else {
                 // a drift restart goes on from where Newton stopped (no further
                 // restarts); an entry that Newton cannot find leaves the segment empty
@@ -1349,20 +1365,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             // at most one restart between two RK steps (kJustRestarted)
             const R dtol = drel * vscale;
             if (e2 > dtol * dtol && drel > R(0) && !(fl & (IVR_FLAG_RESTART_FAIL | kJustRestarted))) {
+                // Newton from the drifted point, which lies close to the preimage
                 shrink = -1;
-                fl |= kJustRestarted;
+                fl = (fl | kJustRestarted | IVR_FLAG_DRIFT_RESTART) & ~kSecondSeed;
                 newton_it = 0;
-                fl |= IVR_FLAG_DRIFT_RESTART;
                 count_rare(C_DRIFT_RESTARTS);
-                if (fp.seed_mode == IVR_SEED_MLP) {
-                    float pm[3];
-                    mlp_seed_at(m.mlp_wb, m.mlp_norm, blk, float(gin[0]), float(gin[1]), float(gin[2]), pm);
-                    if (isfinite(pm[0] + pm[1] + pm[2])) {
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) p[c] = clamp01(R(pm[c]));
-                        count_rare(C_MLP_RESTARTS);
-                    }
-                }
             } else {
                 composite(fp, views[vid].fp, vls[vid], rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A, c_sub);
                 ++c_samp;
@@ -1449,7 +1456,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             if (!finite) {
                 fac = R(0.2);
             } else if (err > R(0)) {
-                fac = R(0.9) * pow_fifth(tol / err);
+                fac = R(0.8) * pow_fifth(tol / err);
                 fac = fac < R(0.2) ? R(0.2) : (fac > R(2.5) ? R(2.5) : fac);
             }
             if (accept && rejected && fac > R(1)) fac = R(1);
@@ -1499,8 +1506,16 @@ __device__ __forceinline__ int view_of_pixel(const ViewRec *views, int n_views, 
 }
 
 __global__ __launch_bounds__(256) void k_merge(const ViewRec *views, int n_views, u32 n_pixels,
-                                               const uint2 *pixseg, const unsigned char *segs, u32 seg_bytes) {
+                                               const uint2 *pixseg, const unsigned char *segs, u32 seg_bytes,
+                                               const QueueState *qs, u32 *totals) {
     const u32 g = blockIdx.x * 256u + threadIdx.x;
+    // the frame's totals (segments requested, candidates recorded, pixels) to
+    // host memory: they size the next frame's buffers without a readback call
+    if (g == 0 && totals) {
+        totals[0] = qs->seg_total;
+        totals[1] = qs->n_cands;
+        totals[2] = n_pixels;
+    }
     if (g >= n_pixels) return;
     const ViewRec &vr = views[view_of_pixel(views, n_views, g)];
     const float early = views[0].fp.early_term;
@@ -1624,9 +1639,10 @@ hipError_t launch_integrate(bool fp64, int method, int klass, const Model &m, co
 }
 
 hipError_t launch_merge(const ViewRec *views, int n_views, uint32_t n_pixels, const uint2 *pixseg,
-                        const void *segs, bool fp64, hipStream_t st) {
+                        const void *segs, bool fp64, const QueueState *qs, uint32_t *totals, hipStream_t st) {
     hipLaunchKernelGGL(k_merge, dim3((n_pixels + 255) / 256), dim3(256), 0, st, views, n_views, n_pixels,
-                       pixseg, (const unsigned char *)segs, (u32)(fp64 ? sizeof(Seg<double>) : sizeof(Seg<float>)));
+                       pixseg, (const unsigned char *)segs, (u32)(fp64 ? sizeof(Seg<double>) : sizeof(Seg<float>)), qs,
+                       totals);
     return hipGetLastError();
 }
 

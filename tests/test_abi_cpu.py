@@ -32,7 +32,7 @@ def test_default_opts_match_header():
     assert o.n_super == 4 and o.max_fragments == 64 and o.seed_mode == 2 and o.rho_interp == 1
     assert o.early_term == 1e-4 and o.max_newton_iter == 16
     assert o.tf_step == 0.025 and o.rho_step == 0.1 and o.cand_per_pixel == 8
-    assert o.det_singular == 1e-6 and o.det_fp64_threshold == 1e-6 and o.drift_tol == 1e-5
+    assert o.det_singular == 1e-6 and o.det_fp64_threshold == 1e-6 and o.drift_tol == 1e-4
 
 
 def test_struct_layouts_match_header():

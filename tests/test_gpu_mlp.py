@@ -142,23 +142,33 @@ def test_mlp_rays_past_the_candidate_list_use_box_seeds(renderer, trained_c4):
 
 
 def test_mlp_seeds_drift_restarts(renderer, trained_c4):
-    """With MLP seeds, the Newton of a drift restart (c_perp = 0, rk_tol = 1e-3, so
-    the samples drift) starts from the block's network at the ray point: restarts
-    are counted as network-seeded, and the image stays within the bar."""
+    """With MLP seeds, the Newton of a drift restart (c_perp = 0, rk_tol = 1e-3,
+    drift_tol = 1e-5, so the samples drift) starts from the drifted point like the other seed modes,
+    and from the block's network at the ray point only when that fails: the
+    restarts happen, those that take the network are counted, and the image
+    stays within the bar."""
     import torch
     sc, _ = trained_c4
     cam = sc.cameras[0]
-    rgba, depth, st = renderer.render(cam, sc.tf, stats=True, seed_mode="mlp", c_perp=0.0, rk_tol=1e-3)
-    torch.cuda.synchronize()
-    img = rgba.cpu().numpy().reshape(-1, 4).astype(np.float64)
+    out = {}
+    for mode in ("box", "mlp"):
+        rgba, depth, st = renderer.render(cam, sc.tf, stats=True, seed_mode=mode, c_perp=0.0, rk_tol=1e-3,
+                                         drift_tol=1e-5)
+        torch.cuda.synchronize()
+        out[mode] = (rgba.cpu().numpy().reshape(-1, 4).astype(np.float64), st)
+        print(f"[mlp] drift, seed {mode}: restarts {st['drift_restarts']}, network-seeded {st['mlp_restarts']}, "
+              f"failed {st['restart_fail']}", flush=True)
+    img, st = out["mlp"]
+    assert st["drift_restarts"] > 0
+    assert out["box"][1]["mlp_restarts"] == 0 and st["mlp_restarts"] <= st["drift_restarts"]
+    assert st["restart_fail"] <= out["box"][1]["restart_fail"]
     cov = np.flatnonzero(img[:, 3] > 0)
     pix = np.random.default_rng(44).choice(cov, 256, replace=False)
     ref = oracle.render(sc, cam, sc.tf, pixels=pix)
-    err = float(np.abs(img[pix] - ref.rgba).max())
-    print(f"[mlp] drift restarts {st['drift_restarts']}, network-seeded {st['mlp_restarts']}, "
-          f"failed {st['restart_fail']}, max err {err:.2e}", flush=True)
-    assert st["drift_restarts"] > 0 and st["mlp_restarts"] >= st["drift_restarts"] // 2
-    assert err <= 1e-3
+    for mode, (im, _) in out.items():
+        err = float(np.abs(im[pix] - ref.rgba).max())
+        print(f"[mlp] drift, seed {mode}: max err {err:.2e}", flush=True)
+        assert err <= 1e-3
 
 
 def test_mlp_seeds_entries_on_a_cutting_plane(renderer, trained_c4):
@@ -170,7 +180,11 @@ def test_mlp_seeds_entries_on_a_cutting_plane(renderer, trained_c4):
     sc, _ = trained_c4
     cam = sc.cameras[0]
     centre = 0.5 * (sc.bbox[0] + sc.bbox[1])
-    cut = (centre, np.array([0.8, -0.2, 0.55]))
+    # the eye on the cut-away side: the rays enter the kept half through the plane
+    away = centre - np.asarray(cam.eye, dtype=np.float64)
+    normal = away / np.linalg.norm(away) + np.array([0.2, -0.1, 0.15])
+    cut = (centre, normal)
+    assert float(normal @ (np.asarray(cam.eye) - centre)) < 0
     out = {}
     for mode in ("box", "mlp"):
         rgba, depth, st = renderer.render(cam, sc.tf, stats=True, seed_mode=mode, cut_plane=cut)

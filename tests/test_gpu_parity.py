@@ -591,7 +591,8 @@ def test_drift_restarts_keep_the_image(renderer):
     sc = _wavy_block_with_linear_field()
     cam = sc.cameras[0]
     kw = dict(c_perp=0.0, rk_tol=1e-2, h_max=sc.scale / 4, rho_step=10.0)
-    img, depth, fl, st = _render_flags(renderer, sc, cam, **kw)
+    # drift_tol 1e-5 (tighter than the default) so that the restarts are many
+    img, depth, fl, st = _render_flags(renderer, sc, cam, drift_tol=1e-5, **kw)
     img0, _, fl0, st0 = _render_flags(renderer, sc, cam, drift_tol=0.0, **kw)
     pix = _sample(cam, depth, 512, 256, 90)
     ref = oracle.render(sc, cam, sc.tf, pixels=pix)
@@ -727,3 +728,30 @@ def test_clip_planes_on_the_bent_beam(renderer, case):
           flush=True)
     _compare(f"config3 {case}", img, depth, ref, pix, sc.scale)
     assert st["anomalies"] == 0 and st["restart_fail"] == 0
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_gpu_follows_the_method_mode(renderer, k):
+    """The GPU's integrator against the oracle's method mode (the same method in
+    FP64, written separately): in FP64 the images agree far below the method's
+    own sampling error, so what the parity bar measures on the GPU is the
+    method's discretisation, not a different algorithm; the RK attempts match."""
+    sc = make_config(k)
+    cam = sc.cameras[0]
+    tol = 1e-6 if k == 1 else 1e-5
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp64", rk_tol=tol)
+    pix = None if k == 1 else _sample(cam, depth, 512, 256, 120)
+    method, steps = oracle.render_method(sc, cam, sc.tf, pixels=pix, rk_tol=tol)
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    sel = img if pix is None else img[pix]
+    d_method = float(np.abs(sel - method).max())
+    d_ref = float(np.abs(sel - ref.rgba).max())
+    w = int(np.abs(sel - method).max(1).argmax())
+    wpix = w if pix is None else int(pix[w])
+    print(f"[method] config{k} worst pixel {wpix}: gpu {sel[w]} method mode {method[w]} "
+          f"reference {ref.rgba[w]} segments {ref.n_segments[w]} first chord {ref.first_chord[w]:.3e}", flush=True)
+    print(f"[method] config{k} fp64: |gpu - method mode| {d_method:.2e}, |gpu - reference| {d_ref:.2e}, "
+          f"rk attempts gpu {st['rk_steps']} method mode {steps}", flush=True)
+    assert d_method <= 1e-6 and d_method < 0.05 * d_ref
+    if k == 1:
+        assert st["rk_steps"] == steps

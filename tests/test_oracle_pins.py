@@ -850,3 +850,34 @@ def test_cutting_and_near_planes_constant_field(oracle_lib, case):
             assert abs(res.depth[pix] - t_start) < 1e-9, pix
     assert (res.n_anomalies == 0).all() and (res.n_newton_fail == 0).all()
     assert clipped > 50
+
+
+# ------------------------------------------------------------------ method mode
+
+def test_method_mode_converges_to_the_reference(oracle_lib):
+    """The oracle's method mode (adaptive RKF45 on the ray preimage ODE, Hermite rho,
+    supersampling) approaches the reference image as its step bounds shrink: the
+    error falls with h_max, rho_step and tf_step divided by 4 and by 16, to 1e-5;
+    on an affine block (straight preimage) the RK steps are exact, and the
+    linear-rho reading gives the same image as Hermite where rho is linear."""
+    sc = make_config(1)
+    cam = sc.cameras[0]
+    pix = np.arange(0, cam.width * cam.height, 3)
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix, self_tol=1e-9, panels_per_scale=8192.0)
+    errs = []
+    for div in (1, 4, 16):
+        img, steps = oracle.render_method(sc, cam, sc.tf, pixels=pix, rk_tol=1e-8, h_max=sc.scale / (32 * div),
+                                          rho_step=0.1 / div, tf_step=0.025 / div)
+        errs.append(float(np.abs(img - ref.rgba).max()))
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-5, errs
+    # affine block, rho linear in world coordinates: Hermite and linear interpolation coincide
+    A = np.array([[1.2, 0.1, 0.0], [0.0, 0.9, 0.2], [0.1, 0.0, 1.1]])
+    P = affine_patch(A, np.array([0.1, -0.2, 0.05]))
+    rho = P.cp[:, :3] @ np.array([0.3, -0.2, 0.5]) + 0.5
+    Q = Patch(P.degree, P.ncp, P.knots, P.cp, rho, False)
+    tf = TransferFunction(sc.tf.x, sc.tf.rgba, 4.0, (float(rho.min()), float(rho.max())))
+    c = A @ np.full(3, 0.5) + np.array([0.1, -0.2, 0.05])
+    cam2 = camera_from_angles(c, 3.0, 40.0, 25.0, 16, 16)
+    h, _ = oracle.render_method([Q], cam2, tf, scale=2.0, hermite=True)
+    l, _ = oracle.render_method([Q], cam2, tf, scale=2.0, hermite=False)
+    assert np.abs(h - l).max() < 1e-12
