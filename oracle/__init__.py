@@ -53,7 +53,12 @@ class _Opts(C.Structure):
 
 class _MethodOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("h_max", C.c_double), ("c_perp", C.c_double), ("rho_step", C.c_double),
-                ("tf_step", C.c_double), ("n_super", C.c_int32), ("hermite", C.c_int32), ("nthreads", C.c_int32)]
+                ("tf_step", C.c_double), ("n_super", C.c_int32), ("hermite", C.c_int32), ("nthreads", C.c_int32),
+                ("method", C.c_int32)]
+
+
+# interior methods of the method mode (orc_method_opts.method)
+METHODS = {"rkf45": 0, "rk1": 1, "rk2": 2, "rk3": 3, "rk4": 4, "rk4_38": 5, "rkf5": 6, "irk1": 7, "rf": 8}
 
 
 class Fragment(C.Structure):
@@ -102,6 +107,13 @@ def lib():
         L.orc_render_pixels_method.restype = C.c_int32
         L.orc_table1.argtypes = [C.c_int32, C.c_double, C.c_double]
         L.orc_table1.restype = C.c_double
+        L.orc_table1_newton.argtypes = [C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_int32)]
+        L.orc_table1_newton.restype = C.c_double
+        L.orc_path_error.argtypes = [C.POINTER(_Patch), dp, dp, C.c_int32, C.c_double, C.c_double,
+                                     C.POINTER(C.c_int32)]
+        L.orc_path_error.restype = C.c_double
+        L.orc_eval_hessian.argtypes = [C.POINTER(_Patch), dp, dp, dp, dp]
+        L.orc_eval_hessian.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -244,7 +256,39 @@ def transfer(tf, rho):
 
 
 def table1(method: int, ds: float, c: float = 1.0) -> float:
+    """Error of the convergence study (methods 1..6 explicit RK, 7 implicit Euler)."""
     return float(lib().orc_table1(int(method), float(ds), float(c)))
+
+
+def table1_newton(method: int, ds: float, c: float = 1.0):
+    """(error, most Newton iterations of an implicit Euler step; -1: one failed)."""
+    it = C.c_int32(0)
+    e = float(lib().orc_table1_newton(int(method), float(ds), float(c), C.byref(it)))
+    return e, it.value
+
+
+def path_error(patch, p_in, p_out, method: int, ds: float, c: float = 1.0):
+    """Convergence study on a block: (largest distance of phi(p_i) from the ray
+    phi(p_in) -> phi(p_out) after uniform steps ds of method 1..7, most Newton
+    iterations of an implicit Euler step)."""
+    op = patch if isinstance(patch, OraclePatch) else OraclePatch(patch)
+    a = np.ascontiguousarray(p_in, dtype=np.float64)
+    b = np.ascontiguousarray(p_out, dtype=np.float64)
+    it = C.c_int32(0)
+    e = float(lib().orc_path_error(C.byref(op.struct), _dp(a), _dp(b), int(method), float(ds), float(c),
+                                   C.byref(it)))
+    return e, it.value
+
+
+def evaluate_hessian(patch, p):
+    """phi(p), J(p) and H (3x3x3, H[r, a, b] = d^2 phi_r / dp_a dp_b)."""
+    op = patch if isinstance(patch, OraclePatch) else OraclePatch(patch)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    x, J, H = np.zeros(3), np.zeros(9), np.zeros(27)
+    rc = lib().orc_eval_hessian(C.byref(op.struct), _dp(p), _dp(x), _dp(J), _dp(H))
+    if rc != 0:
+        raise ValueError("orc_eval_hessian failed")
+    return x, J.reshape(3, 3), H.reshape(3, 3, 3)
 
 
 class RenderResult:
@@ -301,16 +345,17 @@ def render(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None,
 def render_method(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None, rk_tol: float = 1e-5,
                   h_max: float = 0.0, c_perp: float = 1.0, rho_step: float = 0.1, tf_step: float = 0.025,
                   n_super: int = 4, hermite: bool = True, nthreads: int = 0, scale: Optional[float] = None,
-                  prepared: Optional[OracleScene] = None):
+                  prepared: Optional[OracleScene] = None, method: str = "rkf45"):
     """Method mode: the GPU path's method (adaptive RKF45 on the ray preimage ODE,
-    Hermite or linear rho, supersampling) in FP64.  Returns (rgba, rk attempts)."""
+    or a fixed-step method of METHODS; Hermite or linear rho, supersampling) in
+    FP64.  Returns (rgba, steps)."""
     if prepared is None:
         patches = getattr(scene_or_patches, "patches", scene_or_patches)
         if scale is None:
             scale = scene_or_patches.scale
         prepared = OracleScene(patches, scale)
     mo = _MethodOpts(float(rk_tol), float(h_max), float(c_perp), float(rho_step), float(tf_step),
-                     int(n_super), 1 if hermite else 0, int(nthreads))
+                     int(n_super), 1 if hermite else 0, int(nthreads), METHODS[method])
     tf_s = OracleTF(tf)
     if pixels is None:
         npix, pix_ptr = cam.width * cam.height, None

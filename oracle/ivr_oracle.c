@@ -51,6 +51,19 @@ static double cox_de_boor_deriv(const double *t, int nk, int i, int p, double u)
     return r;
 }
 
+/* Second derivative, the same rule applied to the first derivatives:
+   N''_{i,p} = p/(t_{i+p}-t_i) N'_{i,p-1} - p/(t_{i+p+1}-t_{i+1}) N'_{i+1,p-1}. */
+static double cox_de_boor_deriv2(const double *t, int nk, int i, int p, double u)
+{
+    if (p <= 1) return 0.0;
+    if (u < t[i] || u > t[i + p + 1]) return 0.0;
+    double r = 0.0;
+    double d1 = t[i + p] - t[i], d2 = t[i + p + 1] - t[i + 1];
+    if (d1 > 0.0) r += p / d1 * cox_de_boor_deriv(t, nk, i, p - 1, u);
+    if (d2 > 0.0) r -= p / d2 * cox_de_boor_deriv(t, nk, i + 1, p - 1, u);
+    return r;
+}
+
 static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
 
 int32_t orc_basis(const double *t, int32_t nk, int32_t p, double u, double *N, double *dN)
@@ -116,6 +129,70 @@ int32_t orc_eval(const orc_patch *P, const double pin[3], double x[3], double J[
             for (int q = 0; q < 3; ++q) J[r * 3 + q] = dA[q][r];
         if (rho) *rho = R;
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ Hessian
+ * H_phi of Sec. "ODE Based Algorithm" (the order-3 tensor in the Jacobian of
+ * the implicit Euler step): H[r*9 + a*3 + b] = d^2 phi_r / dp_a dp_b, with phi
+ * and J.  Tensor-product sums of the basis and its first and second
+ * derivatives; for NURBS, phi = A/w differentiated twice:
+ *   phi_ab = (A_ab - phi_a w_b - phi_b w_a - phi w_ab) / w.                  */
+int32_t orc_eval_hessian(const orc_patch *P, const double pin[3], double x[3], double J[9], double H[27])
+{
+    static __thread double Nb[3][MAXN], dNb[3][MAXN], ddNb[3][MAXN];
+    double p[3];
+    for (int d = 0; d < 3; ++d) {
+        if (P->ncp[d] > MAXN || P->deg[d] > MAXP) return -1;
+        p[d] = clamp01(pin[d]);
+        const int nk = P->ncp[d] + P->deg[d] + 1;
+        for (int i = 0; i < P->ncp[d]; ++i) {
+            Nb[d][i] = cox_de_boor(P->knots[d], nk, i, P->deg[d], p[d]);
+            dNb[d][i] = cox_de_boor_deriv(P->knots[d], nk, i, P->deg[d], p[d]);
+            ddNb[d][i] = cox_de_boor_deriv2(P->knots[d], nk, i, P->deg[d], p[d]);
+        }
+    }
+    const int n0 = P->ncp[0], n1 = P->ncp[1], n2 = P->ncp[2];
+    /* A[c], dA[a][c], ddA[a][b][c]: homogeneous sums (c = 3 the weight) */
+    double A[4] = {0}, dA[3][4] = {{0}}, ddA[3][3][4] = {{{0}}};
+    for (int k = 0; k < n2; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n0; ++i) {
+                const double f[3] = {Nb[0][i], Nb[1][j], Nb[2][k]};
+                const double df[3] = {dNb[0][i], dNb[1][j], dNb[2][k]};
+                const double ddf[3] = {ddNb[0][i], ddNb[1][j], ddNb[2][k]};
+                if (f[0] == 0 && df[0] == 0 && ddf[0] == 0) continue;
+                if (f[1] == 0 && df[1] == 0 && ddf[1] == 0) continue;
+                if (f[2] == 0 && df[2] == 0 && ddf[2] == 0) continue;
+                const double *c = P->cp + 4 * ((size_t)i + (size_t)n0 * (j + (size_t)n1 * k));
+                const double w = P->rational ? c[3] : 1.0;
+                const double hv[4] = {w * c[0], w * c[1], w * c[2], w};
+                /* basis products: direction a differentiated once (and b once more) */
+                for (int a = 0; a < 3; ++a) {
+                    double ba = 1.0;
+                    for (int e = 0; e < 3; ++e) ba *= e == a ? df[e] : f[e];
+                    for (int q = 0; q < 4; ++q) dA[a][q] += ba * hv[q];
+                    for (int b = 0; b < 3; ++b) {
+                        double bab = 1.0;
+                        for (int e = 0; e < 3; ++e) {
+                            const int order = (e == a) + (e == b);
+                            bab *= order == 0 ? f[e] : (order == 1 ? df[e] : ddf[e]);
+                        }
+                        for (int q = 0; q < 4; ++q) ddA[a][b][q] += bab * hv[q];
+                    }
+                }
+                const double b0 = f[0] * f[1] * f[2];
+                for (int q = 0; q < 4; ++q) A[q] += b0 * hv[q];
+            }
+    const double w = A[3];
+    for (int r = 0; r < 3; ++r) x[r] = A[r] / w;
+    for (int r = 0; r < 3; ++r)
+        for (int a = 0; a < 3; ++a) J[r * 3 + a] = (dA[a][r] - x[r] * dA[a][3]) / w;
+    for (int r = 0; r < 3; ++r)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                H[r * 9 + a * 3 + b] = (ddA[a][b][r] - J[r * 3 + a] * dA[b][3] - J[r * 3 + b] * dA[a][3] -
+                                        x[r] * ddA[a][b][3]) / w;
     return 0;
 }
 
@@ -1004,6 +1081,26 @@ static const double A_rkf[6][6] = {{0},
 static const double b_rkf[6] = {16.0 / 135, 0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50, 2.0 / 55};
 static const double b4_rkf[6] = {25.0 / 216, 0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0};
 
+/* The explicit family of the study, by its Butcher tableaux (stages, a in the
+   lower triangle, b): 1 explicit Euler, 2 midpoint, 3 Kutta's third order,
+   4 the classic fourth order, 5 the 3/8 rule, 6 Fehlberg's fifth order. */
+static const double A_rk1[1][6] = {{0}};
+static const double b_rk1[6] = {1};
+static const double A_rk2[2][6] = {{0}, {0.5}};
+static const double b_rk2[6] = {0, 1};
+static const double A_rk3[3][6] = {{0}, {0.5}, {-1, 2}};
+static const double b_rk3[6] = {1.0 / 6, 2.0 / 3, 1.0 / 6};
+static const double A_rk4[4][6] = {{0}, {0.5}, {0, 0.5}, {0, 0, 1}};
+static const double b_rk4[6] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+static const double A_38[4][6] = {{0}, {1.0 / 3}, {-1.0 / 3, 1}, {1, -1, 1}};
+static const double b_38[6] = {1.0 / 8, 3.0 / 8, 3.0 / 8, 1.0 / 8};
+static const struct {
+    int stages;
+    const double (*A)[6];
+    const double *b;
+} rk_family[7] = {{0, NULL, NULL},   {1, A_rk1, b_rk1}, {2, A_rk2, b_rk2}, {3, A_rk3, b_rk3},
+                  {4, A_rk4, b_rk4}, {4, A_38, b_38},   {6, A_rkf, b_rkf}};
+
 static void t1_phi(const double p[2], double g[2], double J[4])
 {
     double x = p[0], y = p[1];
@@ -1027,31 +1124,85 @@ static void t1_W(const double p[2], const double gin[2], const double vpar[2], d
     w[1] = (-J[2] * V[0] + J[0] * V[1]) / det;
 }
 
+/* d^2 phi_2 / dx^2 of the test map (the only non-zero second derivative) */
+static double t1_phi2_xx(double x)
+{
+    const double k = 10.0 * M_PI;
+    return 0.3 * (-2.0 * k * cos(k * x) - (1.0 - x) * k * k * sin(k * x));
+}
+
+/* One implicit Euler step (Eq. (implicitEuler)) on the 2-D map: Newton on
+   G(z) = z - h W(p + z) (Eq. (newtonimpliciteuler)) from the explicit Euler
+   predictor, with the exact Jacobian of Eq. (JacG):
+     J_phi J_G = H_phi (z - G) + (I - h J_V) J_phi,  J_V = c (v v^T - I),
+   so that each Newton update solves (J_phi J_G) dz = -J_phi G, where
+   J_phi G = J_phi z - h V(phi(p + z)) (Eq. (newtonimpliciteulerReformulated)).
+   Returns the Newton iterations taken (-1: no convergence in 50). */
+static int t1_irk1_step(double p[2], double h, const double gin[2], const double v[2], double c)
+{
+    double z[2], w0[2];
+    t1_W(p, gin, v, c, w0);
+    z[0] = h * w0[0];
+    z[1] = h * w0[1];
+    for (int it = 1; it <= 50; ++it) {
+        const double q[2] = {p[0] + z[0], p[1] + z[1]};
+        double g[2], J[4], w[2];
+        t1_phi(q, g, J);
+        t1_W(q, gin, v, c, w);
+        const double r[2] = {gin[0] - g[0], gin[1] - g[1]};
+        const double rv = r[0] * v[0] + r[1] * v[1];
+        const double V[2] = {v[0] + c * (r[0] - rv * v[0]), v[1] + c * (r[1] - rv * v[1])};
+        /* z - G(z) = h W(q); H_phi applied to it: column a of the matrix is
+           sum_b d^2 phi / dp_a dp_b (h W)_b; only phi_2,xx is non-zero */
+        const double hw[2] = {h * w[0], h * w[1]};
+        double M[4];
+        const double hxx = t1_phi2_xx(q[0]);
+        /* (I - h J_V) = (1 + h c) I - h c v v^T */
+        for (int i = 0; i < 2; ++i)
+            for (int a = 0; a < 2; ++a) {
+                double s = (1.0 + h * c) * J[i * 2 + a];
+                for (int m = 0; m < 2; ++m) s -= h * c * v[i] * v[m] * J[m * 2 + a];
+                M[i * 2 + a] = s;
+            }
+        M[1 * 2 + 0] += hxx * hw[0];
+        const double rhs[2] = {-(J[0] * z[0] + J[1] * z[1] - h * V[0]), -(J[2] * z[0] + J[3] * z[1] - h * V[1])};
+        const double det = M[0] * M[3] - M[1] * M[2];
+        const double dz[2] = {(M[3] * rhs[0] - M[1] * rhs[1]) / det, (-M[2] * rhs[0] + M[0] * rhs[1]) / det};
+        z[0] += dz[0];
+        z[1] += dz[1];
+        if (fmax(fabs(dz[0]), fabs(dz[1])) <= 1e-15) {
+            p[0] += z[0];
+            p[1] += z[1];
+            return it;
+        }
+    }
+    p[0] += z[0];
+    p[1] += z[1];
+    return -1;
+}
+
+double orc_table1_newton(int32_t method, double ds, double c, int32_t *max_newton);
+
 double orc_table1(int32_t method, double ds, double c)
 {
-    /* Butcher tableaux (explicit): stages, a (lower triangle), b */
-    static const double A_rk1[1][6] = {{0}};
-    static const double b_rk1[6] = {1};
-    static const double A_rk2[2][6] = {{0}, {0.5}};
-    static const double b_rk2[6] = {0, 1};
-    static const double A_rk3[3][6] = {{0}, {0.5}, {-1, 2}};
-    static const double b_rk3[6] = {1.0 / 6, 2.0 / 3, 1.0 / 6};
-    static const double A_rk4[4][6] = {{0}, {0.5}, {0, 0.5}, {0, 0, 1}};
-    static const double b_rk4[6] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
-    static const double A_38[4][6] = {{0}, {1.0 / 3}, {-1.0 / 3, 1}, {1, -1, 1}};
-    static const double b_38[6] = {1.0 / 8, 3.0 / 8, 3.0 / 8, 1.0 / 8};
-    const double(*A)[6];
-    const double *b;
-    int st;
-    switch (method) {
-    case 1: A = A_rk1; b = b_rk1; st = 1; break;
-    case 2: A = A_rk2; b = b_rk2; st = 2; break;
-    case 3: A = A_rk3; b = b_rk3; st = 3; break;
-    case 4: A = A_rk4; b = b_rk4; st = 4; break;
-    case 5: A = A_38; b = b_38; st = 4; break;
-    case 6: A = A_rkf; b = b_rkf; st = 6; break;
-    default: return -1.0;
+    return orc_table1_newton(method, ds, c, NULL);
+}
+
+/* As orc_table1; method 7 is the implicit Euler method, and *max_newton (if
+   given) the most Newton iterations of any of its steps (-1: one failed). */
+double orc_table1_newton(int32_t method, double ds, double c, int32_t *max_newton)
+{
+    const double(*A)[6] = NULL;
+    const double *b = NULL;
+    int st = 0;
+    if (method >= 1 && method <= 6) {
+        A = rk_family[method].A;
+        b = rk_family[method].b;
+        st = rk_family[method].stages;
+    } else if (method != 7) {
+        return -1.0;
     }
+    if (max_newton) *max_newton = 0;
     double pin[2] = {0.0, 0.3}, pout[2] = {1.0, 0.7}, gin[2], gout[2], Jd[4];
     t1_phi(pin, gin, Jd);
     t1_phi(pout, gout, Jd);
@@ -1062,6 +1213,10 @@ double orc_table1(int32_t method, double ds, double c)
     double h = L / N, p[2] = {pin[0], pin[1]}, err = 0.0;
     for (int n = 0; n < N; ++n) {
         double k[6][2];
+        if (method == 7) {
+            const int it = t1_irk1_step(p, h, gin, vpar, c);
+            if (max_newton && (it < 0 || (*max_newton >= 0 && it > *max_newton))) *max_newton = it;
+        }
         for (int i = 0; i < st; ++i) {
             double q[2] = {p[0], p[1]};
             for (int j = 0; j < i; ++j) {
@@ -1215,6 +1370,171 @@ static void method_interval(const orc_tf *tf, const orc_method_opts *mo, double 
     }
 }
 
+/* One implicit Euler step (Eq. (implicitEuler)) from p with step h: Newton on
+   G(z) = z - h W(p + z) (Eq. (newtonimpliciteuler)) from the explicit Euler
+   predictor z = h W(p), each update solving (J_phi J_G) dz = -J_phi G with
+     J_phi J_G = H_phi (h W(q)) + (I - h J_V) J_phi,   J_V = c (d d^T - I),
+     J_phi G = J_phi z - h V(phi(q)),                   q = p + z
+   (Eqs. (newtonimpliciteulerReformulated), (JacG)); iterates clamped to P.
+   On return p is the new point; the Newton iterations are returned (-1: no
+   convergence to 1e-13 in 30). */
+static int irk1_step(const orc_patch *P, double p[3], double h, const double gin[3], const double d[3],
+                     double c, const double W0[3])
+{
+    double z[3] = {h * W0[0], h * W0[1], h * W0[2]};
+    for (int it = 1; it <= 30; ++it) {
+        double q[3], x[3], J[9], H[27], r[3], V[3], hV[3], hw[3], M[9], rhs[3], dz[3];
+        for (int e = 0; e < 3; ++e) q[e] = clamp01(p[e] + z[e]);
+        orc_eval_hessian(P, q, x, J, H);
+        for (int e = 0; e < 3; ++e) r[e] = gin[e] - x[e];
+        const double rd = r[0] * d[0] + r[1] * d[1] + r[2] * d[2];
+        for (int e = 0; e < 3; ++e) {
+            V[e] = d[e] + c * (r[e] - rd * d[e]);
+            hV[e] = h * V[e];
+        }
+        if (solve3(J, hV, hw) != 0) break;
+        for (int i = 0; i < 3; ++i)
+            for (int a = 0; a < 3; ++a) {
+                double m = (1.0 + h * c) * J[i * 3 + a];
+                for (int k = 0; k < 3; ++k) m -= h * c * d[i] * d[k] * J[k * 3 + a];
+                for (int b = 0; b < 3; ++b) m += H[i * 9 + a * 3 + b] * hw[b];
+                M[i * 3 + a] = m;
+            }
+        for (int i = 0; i < 3; ++i) rhs[i] = -(J[i * 3] * z[0] + J[i * 3 + 1] * z[1] + J[i * 3 + 2] * z[2] - hV[i]);
+        if (solve3(M, rhs, dz) != 0) break;
+        for (int e = 0; e < 3; ++e) z[e] += dz[e];
+        if (fmax(fabs(dz[0]), fmax(fabs(dz[1]), fabs(dz[2]))) <= 1e-13) {
+            for (int e = 0; e < 3; ++e) p[e] = clamp01(p[e] + z[e]);
+            return it;
+        }
+    }
+    for (int e = 0; e < 3; ++e) p[e] = clamp01(p[e] + z[e]);
+    return -1;
+}
+
+/* The fixed-step methods of Sec. "ODE Based Algorithm" (method 1..6 the
+   explicit family, 7 implicit Euler) and Sec. "Root Finding Based Algorithm"
+   (8: every sample's preimage by Newton on phi(p) = g, from the previous
+   sample's p moved along J^-1 d).  No error control: every step is h_max,
+   shortened where rho changes by more than rho_step in n (h >= h_min) and at
+   the exit; each step's end is sampled (rho, d rho/ds) and the interval
+   composited as in the adaptive mode.  Explicit stages and steps are clamped
+   to P. */
+static void method_fixed_steps(const orc_patch *P, const orc_tf *tf, const orc_method_opts *mo, double scale,
+                               double hmax, double hmin, double L, double gin[3], const double d[3], double p[3],
+                               double W[3], double rho_a, double m_a, double rho_out, double m_out, double C[3],
+                               double *A, long long *steps)
+{
+    const double inv = 1.0 / (tf->domain[1] - tf->domain[0]);
+    const int method = mo->method;
+    const double c = method == 8 ? 0.0 : mo->c_perp;
+    double s = 0.0, rho, g[3];
+    for (int it = 0; it < 200000 && *A < 1.0 - 1e-4; ++it) {
+        const double hf = mo->rho_step / (fabs(m_a) * inv + 1e-300);
+        double hh = hmax < hf ? hmax : fmax(hf, hmin);
+        hh = fmin(hh, L - s);
+        ++*steps;
+        if (L - s - hh <= 1e-6 * L) {   /* the step ends on the exit */
+            method_interval(tf, mo, rho_a, m_a, rho_out, m_out, hh, C, A);
+            return;
+        }
+        if (method >= 1 && method <= 6) {
+            const int st = rk_family[method].stages;
+            double k[6][3];
+            for (int i = 0; i < st; ++i) {
+                double q[3], rr, gg[3];
+                if (i == 0) {
+                    for (int e = 0; e < 3; ++e) k[0][e] = W[e];
+                    continue;
+                }
+                for (int e = 0; e < 3; ++e) {
+                    q[e] = p[e];
+                    for (int j = 0; j < i; ++j) q[e] += hh * rk_family[method].A[i][j] * k[j][e];
+                    q[e] = clamp01(q[e]);
+                }
+                method_W(P, q, gin, d, c, k[i], &rr, gg);
+            }
+            for (int e = 0; e < 3; ++e) {
+                double v = p[e];
+                for (int i = 0; i < st; ++i) v += hh * rk_family[method].b[i] * k[i][e];
+                p[e] = clamp01(v);
+            }
+        } else if (method == 7) {
+            irk1_step(P, p, hh, gin, d, c, W);
+        } else {
+            double x[3], J[9], Wt[3], pred[3], gn[3], pr[3];
+            eval_rho_grad(P, p, x, J, &rho, g);
+            if (solve3(J, d, Wt) != 0) Wt[0] = Wt[1] = Wt[2] = 0.0;
+            for (int e = 0; e < 3; ++e) {
+                pred[e] = clamp01(p[e] + hh * Wt[e]);
+                gn[e] = gin[e] + hh * d[e];
+            }
+            orc_invert(P, gn, pred, scale, pr, NULL);
+            for (int e = 0; e < 3; ++e) p[e] = pr[e];
+        }
+        for (int e = 0; e < 3; ++e) gin[e] += hh * d[e];
+        s += hh;
+        method_W(P, p, gin, d, c, W, &rho, g);
+        const double m_b = g[0] * W[0] + g[1] * W[1] + g[2] * W[2];
+        method_interval(tf, mo, rho_a, m_a, rho, m_b, hh, C, A);
+        rho_a = rho;
+        m_a = m_b;
+    }
+}
+
+/* The convergence study on a block of a spline model: the ray from phi(p_in) to
+   phi(p_out), N = round(L/ds) uniform steps of method 1..6 (explicit family)
+   or 7 (implicit Euler) with V = V_par + c V_perp; the error is the largest
+   distance of phi(p_i) from the ray (the measure of Table
+   "2dcomparisonefficiency").  *max_newton as in orc_table1_newton.          */
+double orc_path_error(const orc_patch *P, const double p_in[3], const double p_out[3], int32_t method, double ds,
+                      double c, int32_t *max_newton)
+{
+    if (!((method >= 1 && method <= 7) && ds > 0)) return -1.0;
+    double x0[3], x1[3], J[9], rho, g[3], d[3], gin[3], p[3], W[3];
+    eval_rho_grad(P, p_in, x0, J, &rho, g);
+    eval_rho_grad(P, p_out, x1, J, &rho, g);
+    for (int e = 0; e < 3; ++e) d[e] = x1[e] - x0[e];
+    const double L = norm3(d);
+    for (int e = 0; e < 3; ++e) {
+        d[e] /= L;
+        gin[e] = x0[e];
+        p[e] = p_in[e];
+    }
+    const int N = (int)lround(L / ds);
+    const double h = L / N;
+    double err = 0.0;
+    if (max_newton) *max_newton = 0;
+    for (int n = 0; n < N; ++n) {
+        method_W(P, p, gin, d, c, W, &rho, g);
+        if (method == 7) {
+            const int it = irk1_step(P, p, h, gin, d, c, W);
+            if (max_newton && (it < 0 || (*max_newton >= 0 && it > *max_newton))) *max_newton = it;
+        } else {
+            const int st = rk_family[method].stages;
+            double k[6][3];
+            for (int e = 0; e < 3; ++e) k[0][e] = W[e];
+            for (int i = 1; i < st; ++i) {
+                double q[3], rr, gg[3];
+                for (int e = 0; e < 3; ++e) {
+                    q[e] = p[e];
+                    for (int j = 0; j < i; ++j) q[e] += h * rk_family[method].A[i][j] * k[j][e];
+                }
+                method_W(P, q, gin, d, c, k[i], &rr, gg);
+            }
+            for (int e = 0; e < 3; ++e)
+                for (int i = 0; i < st; ++i) p[e] += h * rk_family[method].b[i] * k[i][e];
+        }
+        double x[3], r[3];
+        eval_rho_grad(P, p, x, J, &rho, g);
+        for (int e = 0; e < 3; ++e) r[e] = gin[e] - x[e];
+        const double rd = r[0] * d[0] + r[1] * d[1] + r[2] * d[2];
+        for (int e = 0; e < 3; ++e) r[e] -= rd * d[e];
+        err = fmax(err, norm3(r));
+    }
+    return err;
+}
+
 static void method_segment(const orc_patch *P, const orc_tf *tf, const orc_method_opts *mo, double scale,
                            const double o[3], const double d[3], const orc_fragment *fi, const orc_fragment *fo,
                            double out[4], long long *steps)
@@ -1236,6 +1556,11 @@ static void method_segment(const orc_patch *P, const orc_tf *tf, const orc_metho
         m_out = go[0] * Wo[0] + go[1] * Wo[1] + go[2] * Wo[2];
     }
     const double inv = 1.0 / (tf->domain[1] - tf->domain[0]);
+    if (mo->method != 0) {
+        method_fixed_steps(P, tf, mo, scale, hmax, hmin, L, gin, d, p, W, rho_a, m_a, rho_out, m_out, C, &A, steps);
+        out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = A;
+        return;
+    }
     double s = 0.0, h = fmin(L, hmax);
     int rejected = 0;
     for (int it = 0; it < 200000 && s < L && A < 1.0 - 1e-4; ++it) {

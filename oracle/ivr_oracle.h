@@ -114,19 +114,35 @@ int32_t orc_render_pixels(const orc_scene *s, const orc_camera *cam, const orc_t
                           const orc_opts *opts, const int64_t *pixels, int64_t npix,
                           double *rgba, double *depth, orc_pixel_diag *diag);
 /* Method mode: the GPU path's method in FP64 (ray preimage ODE by adaptive
-   RKF45, Hermite or linear rho between samples, supersampling, Algorithm
-   "Front-to-back compositing"), a diagnostic and the like-for-like CPU
-   baseline.  Writes RGBA per pixel and the RK attempts in all. */
+   RKF45 or a fixed-step method, Hermite or linear rho between samples,
+   supersampling, Algorithm "Front-to-back compositing"), a diagnostic and the
+   like-for-like CPU baseline.  Writes RGBA per pixel and the steps (attempts)
+   in all. */
 typedef struct {
     double tol, h_max, c_perp, rho_step, tf_step;  /* h_max <= 0: scale/32       */
     int32_t n_super, hermite, nthreads;
+    /* 0 adaptive RKF45; fixed steps: 1..6 the explicit family of the
+       convergence study (Euler, midpoint, Kutta, classic, 3/8, Fehlberg 5th),
+       7 implicit Euler, 8 root finding (Sec. "Root Finding Based Algorithm") */
+    int32_t method;
 } orc_method_opts;
 int32_t orc_render_pixels_method(const orc_scene *s, const orc_camera *cam, const orc_tf *tf,
                                  const orc_method_opts *mo, const int64_t *pixels, int64_t npix, double *rgba,
                                  int64_t *rk_steps);
-/* Convergence study: error of an explicit RK method on the analytic 2-D map.
-   method 1 Euler, 2 midpoint, 3 Kutta, 4 classic, 5 3/8-rule, 6 Fehlberg (5th). */
+/* Convergence study: error of an RK method on the analytic 2-D map.
+   method 1 Euler, 2 midpoint, 3 Kutta, 4 classic, 5 3/8-rule, 6 Fehlberg (5th),
+   7 implicit Euler. */
 double orc_table1(int32_t method, double ds, double c);
+/* method 7: implicit Euler (Eq. (implicitEuler)) by Newton with the exact J_G of
+   Eq. (JacG); *max_newton: most Newton iterations of a step (-1: one failed). */
+double orc_table1_newton(int32_t method, double ds, double c, int32_t *max_newton);
+/* The convergence study on block P: the ray from phi(p_in) to phi(p_out) by
+   N = round(L/ds) uniform steps of method 1..7; largest distance of phi(p_i)
+   from the ray.  *max_newton as in orc_table1_newton. */
+double orc_path_error(const orc_patch *P, const double p_in[3], const double p_out[3], int32_t method, double ds,
+                      double c, int32_t *max_newton);
+/* phi, J and the Hessian H[r*9 + a*3 + b] = d^2 phi_r / dp_a dp_b at p. */
+int32_t orc_eval_hessian(const orc_patch *P, const double p[3], double x[3], double J[9], double H[27]);
 
 #ifdef __cplusplus
 }
