@@ -215,10 +215,15 @@ def mlp_vs_plain(r, steps, warmup):
                                                                              cold["box"]["value"], 4)}}
 
 
-def interior_ab(r, steps, warmup):
-    """The two interior methods on configs 3 and 4 at 1920x1080: the ray preimage
-    ODE by adaptive RKF45 (the default) and root finding, every sample's preimage
-    by Newton (Sec. "Root Finding Based Algorithm"), with the same step bounds."""
+def interior_ab(r, steps, warmup, seed=11):
+    """The interior methods on configs 3 and 4 at 1920x1080 with the same step
+    bounds: the ray preimage ODE by adaptive RKF45 (the default), root finding
+    (every sample's preimage by Newton, Sec. "Root Finding Based Algorithm") and
+    the fixed-step methods of the convergence study (explicit RK family and
+    implicit Euler, Sec. "ODE Based Algorithm").  Mrays/s, evaluations, Newton
+    failures and the largest RGBA error against the oracle on 1024 covered
+    pixels."""
+    import oracle
     from scenes import make_config
     out = {}
     for k in (3, 4):
@@ -226,12 +231,18 @@ def interior_ab(r, steps, warmup):
         cam = sc.cameras[0]
         r.upload(sc.patches)
         row, imgs = {}, {}
-        for method in ("ode", "rf"):
+        pix = ref = None
+        for method in ("ode", "rf", "rk1", "rk2", "rk3", "rk4", "rk4_38", "rkf5", "irk1"):
             v, ms, st, rgba = time_renders(r, sc, cam, steps, warmup, interior=method)
-            imgs[method] = rgba.cpu().numpy().reshape(-1, 4)
+            imgs[method] = rgba.cpu().numpy().reshape(-1, 4).astype(np.float64)
+            if pix is None:
+                cov = np.flatnonzero(imgs[method][:, 3] > 0)
+                pix = np.random.default_rng(seed + k).choice(cov, min(1024, len(cov)), replace=False)
+                ref = oracle.render(sc, cam, sc.tf, pixels=pix, nthreads=CPU_SHARE).rgba
             row[method] = {"value": round(v, 3), "ms_per_step": round(ms, 4),
                            "ms_integrate": round(st["ms_integrate"], 4), "w_evals": st["w_evals"],
-                           "samples": st["samples"]}
+                           "samples": st["samples"], "newton_failures": st["restart_fail"],
+                           "max_abs_rgba_vs_oracle": float(np.abs(imgs[method][pix] - ref).max())}
         row["speedup_rf_over_ode"] = round(row["rf"]["value"] / row["ode"]["value"], 4)
         row["max_abs_rgba_rf_vs_ode"] = float(np.abs(imgs["rf"] - imgs["ode"]).max())
         out[f"config{k}"] = row
@@ -397,7 +408,7 @@ def main():
     if not args.no_mlp:
         out["mlp_vs_plain"] = mlp_vs_plain(r, args.steps, args.warmup)
     if not args.no_ab:
-        out["interior_rf_vs_ode"] = interior_ab(r, args.steps, args.warmup)
+        out["interior_methods"] = interior_ab(r, args.steps, args.warmup)
     if not args.no_batch:
         out["batch_views"] = batch_views(r, max(args.steps // 4, 3), 2)
     print(json.dumps(out))

@@ -104,6 +104,22 @@ typedef struct {
 #define IVR_INTERIOR_RF 1      /* every sample's preimage by Newton, seeded from the
                                   previous sample (Sec. "Root Finding Based
                                   Algorithm"); steps bounded as for the ODE        */
+/* The fixed-step methods of the convergence study (Sec. "ODE Based Algorithm",
+   Table "2dcomparisonefficiency") on the same ODE: no error control; every step
+   is h_max, shortened where rho changes by more than rho_step and at the exit
+   (as for IVR_INTERIOR_RF), and each step's end is a sample.                  */
+#define IVR_INTERIOR_RK1 2     /* explicit Euler, Eq. (explicitEuler)              */
+#define IVR_INTERIOR_RK2 3     /* midpoint rule (second order)                     */
+#define IVR_INTERIOR_RK3 4     /* Kutta's third-order method                       */
+#define IVR_INTERIOR_RK4 5     /* the classic fourth-order method                  */
+#define IVR_INTERIOR_RK4_38 6  /* the 3/8 rule (fourth order)                      */
+#define IVR_INTERIOR_RKF5 7    /* Fehlberg's fifth-order solution, fixed step       */
+#define IVR_INTERIOR_IRK1 8    /* implicit Euler, Eq. (implicitEuler): Newton on
+                                  G(z) = z - h W(p + z) with the exact J_G of
+                                  Eq. (JacG) (Hessian of the map), iterates
+                                  projected onto P; a step whose Newton does not
+                                  converge in 16 iterations is taken as it
+                                  stands and flagged RESTART_FAIL               */
 
 /* Render options (ivr_default_opts fills the defaults given in brackets). */
 typedef struct {
@@ -170,7 +186,9 @@ typedef struct {
 #define IVR_FLAG_ITER_CAP 8u             /* a segment stopped at the RK step cap  */
 #define IVR_FLAG_DRIFT_RESTART 16u       /* a segment drifted off the ray and was
                                             put back on it by Newton             */
-#define IVR_FLAG_RESTART_FAIL 32u        /* such a Newton did not converge        */
+#define IVR_FLAG_RESTART_FAIL 32u        /* such a Newton did not converge (also
+                                            a root-finding sample's or an
+                                            implicit Euler step's Newton)        */
 #define IVR_FLAG_DEGENERATE 64u          /* a segment end with singular J_phi     */
 
 /* Counters of one render (filled when a non-NULL ivr_stats* is passed; that

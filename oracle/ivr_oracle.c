@@ -1375,9 +1375,10 @@ static void method_interval(const orc_tf *tf, const orc_method_opts *mo, double 
    predictor z = h W(p), each update solving (J_phi J_G) dz = -J_phi G with
      J_phi J_G = H_phi (h W(q)) + (I - h J_V) J_phi,   J_V = c (d d^T - I),
      J_phi G = J_phi z - h V(phi(q)),                   q = p + z
-   (Eqs. (newtonimpliciteulerReformulated), (JacG)); iterates clamped to P.
-   On return p is the new point; the Newton iterations are returned (-1: no
-   convergence to 1e-13 in 30). */
+   (Eqs. (newtonimpliciteulerReformulated), (JacG)); every iterate p + z is
+   projected onto P, so that a step that would leave P stops on its boundary.
+   On return p is the new point; the Newton iterations are returned (-1: the
+   iterate still moved by more than 1e-13 after 30). */
 static int irk1_step(const orc_patch *P, double p[3], double h, const double gin[3], const double d[3],
                      double c, const double W0[3])
 {
@@ -1402,8 +1403,14 @@ static int irk1_step(const orc_patch *P, double p[3], double h, const double gin
             }
         for (int i = 0; i < 3; ++i) rhs[i] = -(J[i * 3] * z[0] + J[i * 3 + 1] * z[1] + J[i * 3 + 2] * z[2] - hV[i]);
         if (solve3(M, rhs, dz) != 0) break;
-        for (int e = 0; e < 3; ++e) z[e] += dz[e];
-        if (fmax(fabs(dz[0]), fmax(fabs(dz[1]), fabs(dz[2]))) <= 1e-13) {
+        /* the iterate projected onto P; converged once it moves by <= 1e-13 */
+        double mv = 0.0;
+        for (int e = 0; e < 3; ++e) {
+            const double zn = clamp01(p[e] + z[e] + dz[e]) - p[e];
+            mv = fmax(mv, fabs(zn - z[e]));
+            z[e] = zn;
+        }
+        if (mv <= 1e-13) {
             for (int e = 0; e < 3; ++e) p[e] = clamp01(p[e] + z[e]);
             return it;
         }

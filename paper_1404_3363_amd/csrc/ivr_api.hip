@@ -1293,8 +1293,9 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
         return fail(c, IVR_EINVAL, "det_singular must be finite and >= 0");
     if (!(o.drift_tol >= 0 && std::isfinite(o.drift_tol)))
         return fail(c, IVR_EINVAL, "drift_tol must be finite and >= 0");
-    if (o.interior != IVR_INTERIOR_ODE && o.interior != IVR_INTERIOR_RF)
+    if (o.interior < IVR_INTERIOR_ODE || o.interior > IVR_INTERIOR_IRK1)
         return fail(c, IVR_EINVAL, "unknown interior method");
+    fp.interior = o.interior;
     if (!(o.near_clip >= 0 && std::isfinite(o.near_clip))) return fail(c, IVR_EINVAL, "near_clip must be >= 0");
     fp.near_clip = o.near_clip;
     fp.cut = o.cut ? 1 : 0;

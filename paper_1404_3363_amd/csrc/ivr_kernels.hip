@@ -911,6 +911,28 @@ struct RKF {
                        e5 = R(1) / R(50), e6 = R(2) / R(55);
 };
 
+// The fixed-step explicit family (IVR_INTERIOR_RK1 .. RKF5, in that order):
+// stages, the lower triangle of a, and b, by Butcher tableau.
+struct RkTableau {
+    int stages;
+    double a[6][6];
+    double b[6];
+};
+__constant__ RkTableau kRkFamily[6] = {
+    {1, {{0}}, {1}},                                                            // explicit Euler
+    {2, {{0}, {0.5}}, {0, 1}},                                                  // midpoint
+    {3, {{0}, {0.5}, {-1, 2}}, {1.0 / 6, 2.0 / 3, 1.0 / 6}},                    // Kutta, third order
+    {4, {{0}, {0.5}, {0, 0.5}, {0, 0, 1}}, {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6}},  // classic fourth order
+    {4, {{0}, {1.0 / 3}, {-1.0 / 3, 1}, {1, -1, 1}}, {1.0 / 8, 3.0 / 8, 3.0 / 8, 1.0 / 8}},  // 3/8 rule
+    {6,
+     {{0},
+      {1.0 / 4},
+      {3.0 / 32, 9.0 / 32},
+      {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197},
+      {439.0 / 216, -8, 3680.0 / 513, -845.0 / 4104},
+      {-8.0 / 27, 2, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40}},
+     {16.0 / 135, 0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50, 2.0 / 55}}};  // Fehlberg, fifth order
+
 // Network seeds of a frame's candidates: the recorded queries, 64 rows per wave
 // and call in list order (rows of different blocks share a call), the seed
 // written where the query is.  Rows of waves whose lists did not fit carry no
@@ -990,7 +1012,9 @@ __global__ __launch_bounds__(256) void k_block_scatter(const QueueState *qs, u32
 // METHOD kOde: the ray preimage ODE by adaptive RKF45 (Sec. "ODE Based
 // Algorithm"); kRootFinding: every sample's preimage by Newton (Sec. "Root
 // Finding Based Algorithm"), seeded from the previous sample along J^-1 d.
-constexpr int kOde = 0, kRootFinding = 1;
+// kFixedRK: a fixed-step explicit method of the family above; kImplicitEuler:
+// implicit Euler with the exact Jacobian of its Newton (Eq. (JacG)).
+constexpr int kOde = 0, kRootFinding = 1, kFixedRK = 2, kImplicitEuler = 3;
 
 template <int P, bool RAT, typename R, bool LDS, int METHOD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_integrate(
@@ -1381,14 +1405,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         }
         if (METHOD == kRootFinding && !done && !shrinking && !shrink) {
             rf_advance(k1, m_cur);   // from the entry (or a shrunk entry): W = J^-1 d there
-        } else if (METHOD == kOde && !done && !shrinking && !shrink) {
+        } else if (METHOD != kRootFinding && !done && !shrinking && !shrink) {
             // rho's change per step is bounded (its interpolation between samples);
-            // the transfer function's frequencies are the supersampling's
+            // the transfer function's frequencies are the supersampling's.  The
+            // fixed-step methods start every step from h_max.
             const R dn_ds = fabs(m_cur) * R(sizeof(R) == 4 ? double(vls[vid].inv_ranged)
                                                             : views[vid].fp.tf_inv_ranged);
             const R hf = R(fp.rho_step) / (dn_ds + R(1e-30));
+            if constexpr (METHOD != kOde) h = hmax;
             h = h < hf ? h : (hf > hmin ? hf : hmin);
             const R hh = (h < Lend - s) ? h : (Lend - s);
+            // fixed steps: a step that ends on the exit fragment takes no stages;
+            // the exit's rho closes the segment (as for root finding)
+            bool closed = false;
+            if constexpr (METHOD != kOde) {
+                if (Lend - s - hh <= R(1e-6) * L && !(fl & kExitOnPlane)) {
+                    const R hl = hh + (L - Lend);
+                    const R mo = isfinite(m_out) ? m_out : (rho_out - rho_prev) / hl;
+                    composite(fp, views[vid].fp, vls[vid], rho_prev, m_prev, rho_out, mo, hl, C, A, c_sub);
+                    ++c_samp;
+                    ++c_steps;
+                    done = true;
+                    closed = true;
+                }
+            }
+            if (!closed) {
+            R err = R(0), p5[3];
+            if constexpr (METHOD == kOde) {
             R q[3], dummy, dg[3], dr2, dx[3];
 #define IVR_STAGE(KOUT, EXPR)                                                              \
     _Pragma("unroll") for (int c = 0; c < 3; ++c) q[c] = clamp01(p[c] + hh * (EXPR));      \
@@ -1401,8 +1444,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             IVR_STAGE(k6, K::a61 * k1[c] + K::a62 * k2[c] + K::a63 * k3[c] + K::a64 * k4[c] +
                               K::a65 * k5[c])
 #undef IVR_STAGE
-            ++c_steps;
-            R err = R(0), p5[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 p5[c] = p[c] + hh * (K::b1 * k1[c] + K::b3 * k3[c] + K::b4 * k4[c] + K::b5 * k5[c] +
@@ -1411,8 +1452,109 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                                        K::e5 * k5[c] + K::e6 * k6[c]));
                 err = (e > err || e != e) ? e : err;   // a non-finite stage rejects the step
             }
+            } else if constexpr (METHOD == kFixedRK) {
+                // the batch's tableau (uniform): stage i at p + hh sum_j a_ij k_j,
+                // clamped to P; the step's end p + hh sum_i b_i k_i
+                const RkTableau &tb = kRkFamily[fp.interior - IVR_INTERIOR_RK1];
+                const int S = tb.stages;
+                R kk[6][3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) kk[0][c] = k1[c];
+#pragma unroll
+                for (int i = 1; i < 6; ++i) {
+                    if (i < S) {
+                        R q[3], dummy, dg[3], dr2, dx[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            R acc = R(0);
+#pragma unroll
+                            for (int j = 0; j < i; ++j) acc += R(tb.a[i][j]) * kk[j][c];
+                            q[c] = clamp01(p[c] + hh * acc);
+                        }
+                        eval_W<P, RAT, 0, R, LDS>(pv, ar, q, gin, d, cperp, dthr, kk[i], dummy, dg, c_fp64, false,
+                                                  dr2, dx, dx);
+                        ++c_w;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    R acc = R(0);
+#pragma unroll
+                    for (int i = 0; i < 6; ++i)
+                        if (i < S) acc += R(tb.b[i]) * kk[i][c];
+                    p5[c] = p[c] + hh * acc;
+                }
+                err = isfinite(p5[0] + p5[1] + p5[2]) ? R(0) : R(NAN);
+            } else {
+                // Eq. (implicitEuler): Newton on G(z) = z - hh W(p + z) (Eq.
+                // (newtonimpliciteuler)) from the explicit Euler predictor; each
+                // update solves (J_phi J_G) dz = -J_phi G with, at q = p + z,
+                //   J_phi J_G = H_phi (hh W(q)) + (I - hh J_V) J_phi,  J_V = c (d d^T - I),
+                //   J_phi G   = J_phi z - hh V(phi(q))
+                // (Eqs. (newtonimpliciteulerReformulated), (JacG)); iterates projected
+                // onto P
+                // Newton converges quadratically: once an update is below tolz the
+                // point is at rounding level (FP32: updates below 1e-5 leave ~1e-10)
+                const R tolz = sizeof(R) == 4 ? R(1e-5) : R(1e-12);
+                const R hc = hh * cperp;
+                R z[3] = {hh * k1[0], hh * k1[1], hh * k1[2]};
+                bool conv = false;
+#pragma unroll 1
+                for (int it = 0; it < 16 && !conv; ++it) {
+                    R q[3], xq[3], Jq[3][3], Hq[3][6];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[c] = clamp01(p[c] + z[c]);
+                    eval_volume_h<P, RAT, R, LDS>(pv, ar, q, xq, Jq, Hq);
+                    ++c_w;
+                    R r[3] = {gin[0] - xq[0], gin[1] - xq[1], gin[2] - xq[2]}, hV[3];
+                    const R rd = dot3(r, d);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) hV[c] = hh * (d[c] + cperp * (r[c] - rd * d[c]));
+                    R ju[3] = {Jq[0][0], Jq[1][0], Jq[2][0]}, jv[3] = {Jq[0][1], Jq[1][1], Jq[2][1]},
+                      jw[3] = {Jq[0][2], Jq[1][2], Jq[2][2]}, hw[3];
+                    solve_cols(ju, jv, jw, hV, hw);
+                    // columns of J_phi J_G; (d^T J_phi) for the J_V term
+                    R dJ[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) dJ[a] = d[0] * Jq[0][a] + d[1] * Jq[1][a] + d[2] * Jq[2][a];
+                    R M[3][3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const R *Hi = Hq[i];
+                        // packed (uu, vv, ww, uv, uw, vw) applied to hw, column by column
+                        M[i][0] = (R(1) + hc) * Jq[i][0] - hc * d[i] * dJ[0] + Hi[0] * hw[0] + Hi[3] * hw[1] + Hi[4] * hw[2];
+                        M[i][1] = (R(1) + hc) * Jq[i][1] - hc * d[i] * dJ[1] + Hi[3] * hw[0] + Hi[1] * hw[1] + Hi[5] * hw[2];
+                        M[i][2] = (R(1) + hc) * Jq[i][2] - hc * d[i] * dJ[2] + Hi[4] * hw[0] + Hi[5] * hw[1] + Hi[2] * hw[2];
+                    }
+                    R rhs[3], dz[3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) rhs[i] = hV[i] - (Jq[i][0] * z[0] + Jq[i][1] * z[1] + Jq[i][2] * z[2]);
+                    const R m0[3] = {M[0][0], M[1][0], M[2][0]}, m1[3] = {M[0][1], M[1][1], M[2][1]},
+                            m2[3] = {M[0][2], M[1][2], M[2][2]};
+                    solve_cols(m0, m1, m2, rhs, dz);
+                    if (!isfinite(dz[0] + dz[1] + dz[2])) break;
+                    // the iterate projected onto P (a step that would leave P stops
+                    // on its boundary); converged once it moves by at most tolz
+                    R mv = R(0);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const R zn = clamp01(p[c] + z[c] + dz[c]) - p[c];
+                        mv = fmax(mv, fabs(zn - z[c]));
+                        z[c] = zn;
+                    }
+                    conv = mv <= tolz;
+                }
+                if (!conv) {
+                    fl |= IVR_FLAG_RESTART_FAIL;
+                    count_rare(C_RESTART_FAIL);
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) p5[c] = p[c] + z[c];
+                err = isfinite(p5[0] + p5[1] + p5[2]) ? R(0) : R(NAN);
+            }
+            ++c_steps;
             const bool finite = isfinite(err);
-            const bool accept = (err <= tol) || (hh <= hmin);
+            const bool accept = METHOD != kOde || (err <= tol) || (hh <= hmin);
             if (accept) {
                 s += hh;
                 fl &= ~kJustRestarted;
@@ -1451,7 +1593,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 ++c_rej;
             }
             // step-size control for a 4(5) pair; no growth on the attempt after a
-            // rejection (the error estimate just proved the step too long)
+            // rejection (the error estimate just proved the step too long).  The
+            // fixed-step methods take h_max again at the next step.
+            if constexpr (METHOD == kOde) {
             R fac = R(2.5);
             if (!finite) {
                 fac = R(0.2);
@@ -1464,10 +1608,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             h = hh * fac;
             h = h > hmax ? hmax : h;
             h = h < hmin ? hmin : h;
+            }
             if (++iters >= 20000 && !done) {
                 count_rare(C_RK_ITER_CAP);
                 fl |= IVR_FLAG_ITER_CAP;
                 done = true;
+            }
             }
         }
         if (done) {
@@ -1621,6 +1767,10 @@ static hipError_t launch_integrate_pr(bool fp64, int method, const Model &m, con
                                       const LaunchCfg &lc, hipStream_t st) {
     if (method == IVR_INTERIOR_RF)
         return launch_integrate_m<P, RAT, kRootFinding>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    if (method >= IVR_INTERIOR_RK1 && method <= IVR_INTERIOR_RKF5)
+        return launch_integrate_m<P, RAT, kFixedRK>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+    if (method == IVR_INTERIOR_IRK1)
+        return launch_integrate_m<P, RAT, kImplicitEuler>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
     return launch_integrate_m<P, RAT, kOde>(fp64, m, views, n_views, segs, a, ctr, n_cu, lc, st);
 }
 

@@ -316,6 +316,223 @@ __device__ __forceinline__ void eval_volume(const PatchView<R> &pv, const Arrays
 }
 
 
+// Second derivatives (the implicit Euler step's Hessian, Sec. "ODE Based
+// Algorithm").  The P+1 non-zero basis functions on the span with their first
+// and second derivatives: the rows of degree P-2, P-1 and P of the triangular
+// recurrence, then the derivative rule
+//   N'_{i,q} = q (N_{i,q-1} / (t_{i+q} - t_i) - N_{i+1,q-1} / (t_{i+q+1} - t_{i+1}))
+// applied to row P (from row P-1), to row P-1 (from row P-2), and once more to
+// the first derivatives of row P-1 for row P's second derivatives.  On a
+// non-empty span every denominator is positive.
+template <int P, typename R>
+__device__ __forceinline__ void basis_d2(R u, const R (&t)[2 * P], R (&N)[P + 1], R (&dN)[P + 1],
+                                         R (&d2N)[P + 1]) {
+    R T[P + 1][P + 1], left[P + 1], right[P + 1];
+    T[0][0] = R(1);
+#pragma unroll
+    for (int j = 1; j <= P; ++j) {
+        left[j] = u - t[P - j];
+        right[j] = t[P - 1 + j] - u;
+        R saved = R(0);
+#pragma unroll
+        for (int r = 0; r < j; ++r) {
+            const R temp = T[j - 1][r] / (right[r + 1] + left[j - r]);
+            T[j][r] = saved + right[r + 1] * temp;
+            saved = left[j - r] * temp;
+        }
+        T[j][j] = saved;
+    }
+    // derivatives of row P-1 (zero for P = 1)
+    R dM[P + 1];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        R v = R(0);
+        if (P >= 2) {
+            if (r > 0) v += T[P - 2 > 0 ? P - 2 : 0][r - 1] / (t[P - 1 + r] - t[r]);
+            if (r < P - 1) v -= T[P - 2 > 0 ? P - 2 : 0][r] / (t[P + r] - t[r + 1]);
+        }
+        dM[r] = R(P - 1) * v;
+    }
+#pragma unroll
+    for (int r = 0; r <= P; ++r) {
+        R v = R(0), w = R(0);
+        if (r > 0) {
+            const R den = t[P - 1 + r] - t[r - 1];
+            v += T[P - 1][r - 1] / den;
+            w += dM[r - 1] / den;
+        }
+        if (r < P) {
+            const R den = t[P + r] - t[r];
+            v -= T[P - 1][r] / den;
+            w -= dM[r] / den;
+        }
+        N[r] = T[P][r];
+        dN[r] = R(P) * v;
+        d2N[r] = R(P) * w;
+    }
+}
+
+// As basis_tab, with second derivatives (Horner on the span's polynomials).
+template <int P, typename R>
+__device__ __forceinline__ int basis_tab2(const float *tab_d, R u_in, int n, int nspan, bool uniform,
+                                          const R *__restrict__ kn, R (&N)[P + 1], R (&dN)[P + 1],
+                                          R (&d2N)[P + 1]) {
+    const R u = clamp01(u_in);
+    int e;
+    R x, dxdu;
+    if (uniform) {
+        const R un = u * R(nspan);
+        e = (int)un;
+        e = e > nspan - 1 ? nspan - 1 : e;
+        x = un - R(e);
+        dxdu = R(nspan);
+    } else {
+        int lo = P, hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (kn[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        e = lo - P;
+        const R t0 = kn[lo], dt = kn[lo + 1] - t0;
+        dxdu = R(1) / dt;
+        x = (u - t0) * dxdu;
+    }
+    const float *c = tab_d + e * (P + 1) * (P + 1);
+#pragma unroll
+    for (int i = 0; i <= P; ++i) {
+        R v = R(0), dv = R(0), d2v = R(0);
+#pragma unroll
+        for (int k = P; k >= 0; --k) {
+            const R ck = R(c[i * (P + 1) + k]);
+            v = v * x + ck;
+            if (k >= 1) dv = dv * x + R(k) * ck;
+            if (k >= 2) d2v = d2v * x + R(k * (k - 1)) * ck;
+        }
+        N[i] = v;
+        dN[i] = dv * dxdu;
+        d2N[i] = d2v * dxdu * dxdu;
+    }
+    return e + P;
+}
+
+// phi(p), J[r][a] = d phi_r / d p_a and the Hessian in packed symmetric form,
+// H[r][k] = d^2 phi_r / dp_a dp_b for (a, b) = (0,0), (1,1), (2,2), (0,1),
+// (0,2), (1,2) in k = 0..5.  Sum-factorised like eval_volume, carrying the
+// second derivatives along; NURBS by the quotient rule applied twice,
+//   phi_ab = (X_ab - phi_a w_b - phi_b w_a - phi w_ab) / w.
+template <int P, bool RAT, typename R, bool TAB = false>
+__device__ __forceinline__ void eval_volume_h(const PatchView<R> &pv, const Arrays<R> &ar, const R (&p)[3],
+                                              R (&x)[3], R (&J)[3][3], R (&H)[3][6]) {
+    const R pc[3] = {clamp01(p[0]), clamp01(p[1]), clamp01(p[2])};
+    R Nu[P + 1], dNu[P + 1], ddNu[P + 1], Nv[P + 1], dNv[P + 1], ddNv[P + 1], Nw[P + 1], dNw[P + 1],
+        ddNw[P + 1];
+    int su, sv, sw;
+    if constexpr (TAB) {
+        constexpr int Q2 = (P + 1) * (P + 1);
+        su = basis_tab2<P>(ar.tab, pc[0], pv.n[0], pv.nspan[0], pv.uniform & 1, ar.knots + pv.knot_off[0], Nu,
+                           dNu, ddNu);
+        sv = basis_tab2<P>(ar.tab + pv.nspan[0] * Q2, pc[1], pv.n[1], pv.nspan[1], pv.uniform & 2,
+                           ar.knots + pv.knot_off[1], Nv, dNv, ddNv);
+        sw = basis_tab2<P>(ar.tab + (pv.nspan[0] + pv.nspan[1]) * Q2, pc[2], pv.n[2], pv.nspan[2],
+                           pv.uniform & 4, ar.knots + pv.knot_off[2], Nw, dNw, ddNw);
+    } else {
+        R tu[2 * P], tv[2 * P], tw[2 * P];
+        su = span_knots<P>(pc[0], pv.n[0], pv.nspan[0], pv.inv_nspan[0], pv.uniform & 1,
+                           ar.knots + pv.knot_off[0], tu);
+        sv = span_knots<P>(pc[1], pv.n[1], pv.nspan[1], pv.inv_nspan[1], pv.uniform & 2,
+                           ar.knots + pv.knot_off[1], tv);
+        sw = span_knots<P>(pc[2], pv.n[2], pv.nspan[2], pv.inv_nspan[2], pv.uniform & 4,
+                           ar.knots + pv.knot_off[2], tw);
+        basis_d2<P, R>(pc[0], tu, Nu, dNu, ddNu);
+        basis_d2<P, R>(pc[1], tv, Nv, dNv, ddNv);
+        basis_d2<P, R>(pc[2], tw, Nw, dNw, ddNw);
+    }
+    constexpr int NC = RAT ? 4 : 3;
+    const int n0 = pv.n[0], n01 = pv.n[0] * pv.n[1];
+    const int base = pv.cp_off + (su - P) + n0 * (sv - P) + n01 * (sw - P);
+    // X: value; X1[a]: d/dp_a; X2[k]: the packed second derivatives
+    R X[NC], X1[3][NC], X2[6][NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        X[c] = R(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) X1[a][c] = R(0);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) X2[k][c] = R(0);
+    }
+#pragma unroll 1
+    for (int k = 0; k <= P; ++k) {
+        // B[.]: sums over u and v with the v-derivatives of orders 0..2 and the
+        // u-derivatives of orders 0..2 (combined order at most 2)
+        R B00[NC], B01[NC], B02[NC], B10[NC], B11[NC], B20[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) B00[c] = B01[c] = B02[c] = B10[c] = B11[c] = B20[c] = R(0);
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            const int row = base + n0 * j + n01 * k;
+            R A0[NC], A1[NC], A2[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) A0[c] = A1[c] = A2[c] = R(0);
+#pragma unroll
+            for (int i = 0; i <= P; ++i) {
+                R v[4];
+                load_cp<R>(ar.cp[row + i], v);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    A0[c] += Nu[i] * v[c];
+                    A1[c] += dNu[i] * v[c];
+                    A2[c] += ddNu[i] * v[c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                B00[c] += Nv[j] * A0[c];
+                B01[c] += dNv[j] * A0[c];
+                B02[c] += ddNv[j] * A0[c];
+                B10[c] += Nv[j] * A1[c];
+                B11[c] += dNv[j] * A1[c];
+                B20[c] += Nv[j] * A2[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            X[c] += Nw[k] * B00[c];
+            X1[0][c] += Nw[k] * B10[c];
+            X1[1][c] += Nw[k] * B01[c];
+            X1[2][c] += dNw[k] * B00[c];
+            X2[0][c] += Nw[k] * B20[c];     // uu
+            X2[1][c] += Nw[k] * B02[c];     // vv
+            X2[2][c] += ddNw[k] * B00[c];   // ww
+            X2[3][c] += Nw[k] * B11[c];     // uv
+            X2[4][c] += dNw[k] * B10[c];    // uw
+            X2[5][c] += dNw[k] * B01[c];    // vw
+        }
+    }
+    if constexpr (RAT) {
+        const R iw = R(1) / X[3];
+        constexpr int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            x[r] = X[r] * iw;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) J[r][a] = (X1[a][r] - x[r] * X1[a][3]) * iw;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                H[r][k] = (X2[k][r] - J[r][pa[k]] * X1[pb[k]][3] - J[r][pb[k]] * X1[pa[k]][3] - x[r] * X2[k][3]) * iw;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            x[r] = X[r];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) J[r][a] = X1[a][r];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) H[r][k] = X2[k][r];
+        }
+    }
+}
+
 // Boundary face f (0..5 = u0,u1,v0,v1,w0,w1): in-face directions (a, b) are the two
 // remaining parameter directions in increasing order.
 __device__ __forceinline__ void face_dirs(int face, int &dn, int &da, int &db) {

@@ -180,6 +180,7 @@ struct FrameParams {
     float rk_tol, h_max, h_min, c_perp, early_term, det_thr, det_sing, drift_tol;
     double rk_told, h_maxd, h_mind, c_perpd, early_termd, det_thrd, det_singd, drift_told;
     int32_t n_super, max_frag, max_newton, collect, hermite, seed_mode;
+    int32_t interior;               // IVR_INTERIOR_*
     // Sec. "Cutting and Near Clip Planes": cutting plane (cut != 0) keeping
     // cut_n . (g - g0) >= 0, with cut_s0 = cut_n . (eye - g0) for this view; near
     // plane near_clip in front of the eye along fwd (0: none)

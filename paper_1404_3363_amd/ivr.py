@@ -21,7 +21,7 @@ FLAGS = {"anomaly": 1, "fragment_overflow": 2, "segment_overflow": 4, "iter_cap"
 PRECISION = {"fp32": 0, "fp64": 1}
 SEED = {"plain": 0, "mlp": 1, "box": 2}
 RHO_INTERP = {"linear": 0, "hermite": 1}
-INTERIOR = {"ode": 0, "rf": 1}
+INTERIOR = {"ode": 0, "rf": 1, "rk1": 2, "rk2": 3, "rk3": 4, "rk4": 5, "rk4_38": 6, "rkf5": 7, "irk1": 8}
 
 EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_upload_models",
            "ivr_render", "ivr_render_noalloc", "ivr_render_batch", "ivr_autotune", "ivr_set_launch",
