@@ -32,7 +32,11 @@ def build(force: bool = True) -> str:
 class _Patch(C.Structure):
     _fields_ = [("deg", C.c_int32 * 3), ("ncp", C.c_int32 * 3),
                 ("knots", C.POINTER(C.c_double) * 3), ("cp", C.POINTER(C.c_double)),
-                ("scalar", C.POINTER(C.c_double)), ("rational", C.c_int32)]
+                ("scalar", C.POINTER(C.c_double)), ("rational", C.c_int32), ("disp", C.POINTER(C.c_double))]
+
+
+# fields sampled along the ray (orc_opts.field)
+FIELDS = {"scalar": 0, "param_quality": 1, "von_mises": 2}
 
 
 class _TF(C.Structure):
@@ -48,7 +52,8 @@ class _Camera(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("panels_per_scale", C.c_double), ("richardson", C.c_int32),
                 ("nthreads", C.c_int32), ("self_tol", C.c_double), ("cut", C.c_int32),
-                ("cut_point", C.c_double * 3), ("cut_normal", C.c_double * 3), ("near_clip", C.c_double)]
+                ("cut_point", C.c_double * 3), ("cut_normal", C.c_double * 3), ("near_clip", C.c_double),
+                ("field", C.c_int32)]
 
 
 class _MethodOpts(C.Structure):
@@ -112,6 +117,8 @@ def lib():
         L.orc_path_error.argtypes = [C.POINTER(_Patch), dp, dp, C.c_int32, C.c_double, C.c_double,
                                      C.POINTER(C.c_int32)]
         L.orc_path_error.restype = C.c_double
+        L.orc_field.argtypes = [C.POINTER(_Patch), dp, C.c_int32, dp]
+        L.orc_field.restype = C.c_int32
         L.orc_eval_hessian.argtypes = [C.POINTER(_Patch), dp, dp, dp, dp]
         L.orc_eval_hessian.restype = C.c_int32
         _lib = L
@@ -137,6 +144,10 @@ class OraclePatch:
         s.cp = _dp(self._cp)
         s.scalar = _dp(self._sc)
         s.rational = 1 if patch.rational else 0
+        disp = getattr(patch, "displacement", None)
+        if disp is not None:
+            self._disp = np.ascontiguousarray(disp, dtype=np.float64).reshape(-1)
+            s.disp = _dp(self._disp)
         self.struct = s
 
 
@@ -280,6 +291,16 @@ def path_error(patch, p_in, p_out, method: int, ds: float, c: float = 1.0):
     return e, it.value
 
 
+def field_value(patch, p, field: str) -> float:
+    """The value of a field of FIELDS at parameter point p of the block."""
+    op = patch if isinstance(patch, OraclePatch) else OraclePatch(patch)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    v = np.zeros(1)
+    if lib().orc_field(C.byref(op.struct), _dp(p), FIELDS[field], _dp(v)) != 0:
+        raise ValueError(f"orc_field failed ({field})")
+    return float(v[0])
+
+
 def evaluate_hessian(patch, p):
     """phi(p), J(p) and H (3x3x3, H[r, a, b] = d^2 phi_r / dp_a dp_b)."""
     op = patch if isinstance(patch, OraclePatch) else OraclePatch(patch)
@@ -306,11 +327,12 @@ class RenderResult:
 def render(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None,
            panels_per_scale: float = 2048.0, richardson: bool = True, nthreads: int = 0,
            scale: Optional[float] = None, prepared: Optional[OracleScene] = None,
-           self_tol: float = 1e-5, cut_plane=None, near_clip: float = 0.0) -> RenderResult:
+           self_tol: float = 1e-5, cut_plane=None, near_clip: float = 0.0, field: str = "scalar") -> RenderResult:
     """Reference image (premultiplied RGBA, first-entry depth) for the listed pixels
     (linear index row*width+col), or for the whole image when pixels is None.
     cut_plane: (point, normal), keeping normal . (g - point) >= 0; near_clip: the
-    near plane's distance from the eye along the view direction (0: none)."""
+    near plane's distance from the eye along the view direction (0: none);
+    field: the value sampled along the ray (FIELDS)."""
     if prepared is None:
         patches = getattr(scene_or_patches, "patches", scene_or_patches)
         if scale is None:
@@ -325,6 +347,7 @@ def render(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None,
             opts.cut_point[q] = float(cut_plane[0][q])
             opts.cut_normal[q] = float(cut_plane[1][q])
     opts.near_clip = float(near_clip)
+    opts.field = FIELDS[field]
     if pixels is None:
         npix = cam.width * cam.height
         pix_ptr = None

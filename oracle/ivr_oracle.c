@@ -196,6 +196,88 @@ int32_t orc_eval_hessian(const orc_patch *P, const double pin[3], double x[3], d
     return 0;
 }
 
+/* ------------------------------------------------------------------ derived fields
+ * Sec. "Parametrization Quality of Geometry", Eq. (paramQuality): the quality
+ * of the parametrisation is det J_phi / ||J_phi||_F.
+ * Structural analysis, Eq. (vonMises): a displacement field u on P (a spline on
+ * the basis of phi: u = sum R_i u_i with the rational basis R_i of a NURBS
+ * block).  The Jacobian X of u o phi^-1 at g = phi(p) solves
+ * J_phi(p)^T X = J_u(p)^T, column by column (that is the transpose of the
+ * chain rule's J_u J_phi^-1, which the symmetrisation below removes); the
+ * tensor e = (X + X^T)/2, and the value
+ *   sqrt(((e11-e22)^2 + (e22-e33)^2 + (e33-e11)^2 + 6 (e12^2 + e23^2 + e31^2)) / 2),
+ * the von Mises form, whose squares and root the printed formula lacks.      */
+static int solve3(const double Min[9], const double bin[3], double xout[3]);
+
+/* J_u[r*3 + a] = d u_r / dp_a of the displacement spline at p */
+static int eval_disp_jacobian(const orc_patch *P, const double pin[3], double Ju[9])
+{
+    static __thread double Nb[3][MAXN], dNb[3][MAXN];
+    double p[3];
+    if (!P->disp) return -1;
+    for (int d = 0; d < 3; ++d) {
+        p[d] = clamp01(pin[d]);
+        orc_basis(P->knots[d], P->ncp[d] + P->deg[d] + 1, P->deg[d], p[d], Nb[d], dNb[d]);
+    }
+    const int n0 = P->ncp[0], n1 = P->ncp[1], n2 = P->ncp[2];
+    double U[4] = {0, 0, 0, 0}, dU[3][4] = {{0}};   /* homogeneous (w u, w) */
+    for (int k = 0; k < n2; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n0; ++i) {
+                const double b = Nb[0][i] * Nb[1][j] * Nb[2][k];
+                const double bd[3] = {dNb[0][i] * Nb[1][j] * Nb[2][k], Nb[0][i] * dNb[1][j] * Nb[2][k],
+                                      Nb[0][i] * Nb[1][j] * dNb[2][k]};
+                if (b == 0.0 && bd[0] == 0.0 && bd[1] == 0.0 && bd[2] == 0.0) continue;
+                const size_t li = i + (size_t)n0 * (j + (size_t)n1 * k);
+                const double w = P->rational ? P->cp[4 * li + 3] : 1.0;
+                const double hv[4] = {w * P->disp[3 * li], w * P->disp[3 * li + 1], w * P->disp[3 * li + 2], w};
+                for (int q = 0; q < 4; ++q) {
+                    U[q] += b * hv[q];
+                    for (int a = 0; a < 3; ++a) dU[a][q] += bd[a] * hv[q];
+                }
+            }
+    for (int r = 0; r < 3; ++r) {
+        const double u = U[r] / U[3];
+        for (int a = 0; a < 3; ++a) Ju[r * 3 + a] = (dU[a][r] - u * dU[a][3]) / U[3];
+    }
+    return 0;
+}
+
+int32_t orc_field(const orc_patch *P, const double p[3], int32_t field, double *value)
+{
+    double x[3], J[9], rho;
+    if (orc_eval(P, p, x, J, &rho) != 0) return -1;
+    if (field == ORC_FIELD_SCALAR) {
+        *value = rho;
+        return 0;
+    }
+    if (field == ORC_FIELD_PARAM_QUALITY) {
+        const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                           J[2] * (J[3] * J[7] - J[4] * J[6]);
+        double fro = 0.0;
+        for (int i = 0; i < 9; ++i) fro += J[i] * J[i];
+        *value = det / sqrt(fro);
+        return 0;
+    }
+    if (field != ORC_FIELD_VON_MISES) return -1;
+    double Ju[9], JT[9], X[9];
+    if (eval_disp_jacobian(P, p, Ju) != 0) return -1;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) JT[r * 3 + c] = J[c * 3 + r];
+    for (int col = 0; col < 3; ++col) {
+        /* column col of J_u^T is row col of J_u */
+        double rhs[3] = {Ju[col * 3], Ju[col * 3 + 1], Ju[col * 3 + 2]}, xc[3];
+        if (solve3(JT, rhs, xc) != 0) return -1;
+        for (int r = 0; r < 3; ++r) X[r * 3 + col] = xc[r];
+    }
+    double e[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) e[r][c] = 0.5 * (X[r * 3 + c] + X[c * 3 + r]);
+    const double a = e[0][0] - e[1][1], b = e[1][1] - e[2][2], c = e[2][2] - e[0][0];
+    *value = sqrt(0.5 * (a * a + b * b + c * c + 6.0 * (e[0][1] * e[0][1] + e[1][2] * e[1][2] + e[2][0] * e[2][0])));
+    return 0;
+}
+
 /* ------------------------------------------------------------------ linear solve
  * 3x3 systems of Eq. (newtonsmethod) and Eq. (VgVp).  The paper names a QR
  * factorisation; any exact direct method solves the same system.  Gaussian
@@ -868,7 +950,7 @@ static int pair_fragments(const orc_fragment *fr, int n, double teq, int near, i
  * each midpoint is found by Newton, continued from the previous midpoint.    */
 static int segment_integral(const orc_patch *P, const orc_tf *tf, const double o[3],
                             const double d[3], double t0, double t1, const double p0[3],
-                            double scale, int npan, double out[4], int *fails)
+                            double scale, int npan, int field, double out[4], int *fails)
 {
     double h = (t1 - t0) / npan, C[3] = {0, 0, 0}, A = 0.0, p[3] = {p0[0], p0[1], p0[2]};
     for (int m = 0; m < npan; ++m) {
@@ -876,8 +958,11 @@ static int segment_integral(const orc_patch *P, const orc_tf *tf, const double o
         for (int c = 0; c < 3; ++c) g[c] = o[c] + s * d[c];
         if (invert_with_restarts(P, g, p, scale, q) != 0) ++*fails;
         memcpy(p, q, sizeof p);
-        double x[3], J[9], rho, te[4];
-        orc_eval(P, p, x, J, &rho);
+        double rho, te[4];
+        if (orc_field(P, p, field, &rho) != 0) {
+            ++*fails;
+            rho = 0.0;
+        }
         orc_transfer(tf, rho, te);
         double T = exp(-te[3] * h);
         for (int c = 0; c < 3; ++c) C[c] += (1.0 - T) * (1.0 - A) * te[c];
@@ -992,12 +1077,12 @@ static void render_one(const orc_scene *s, const orc_camera *cam, const orc_tf *
         if (npan < 1) npan = 1;
         double I1[4], res[4];
         int fails = 0;
-        segment_integral(P, tf, o, d, sg->t0, sg->t1, p0, s->scale, npan, I1, &fails);
+        segment_integral(P, tf, o, d, sg->t0, sg->t1, p0, s->scale, npan, opts->field, I1, &fails);
         if (opts->richardson) {
             /* halve the panels until |I_h - I_{h/2}| <= self_tol (at most 4 times) */
             double I2[4], err = 0.0;
             for (int refine = 0;; ++refine) {
-                segment_integral(P, tf, o, d, sg->t0, sg->t1, p0, s->scale, 2 * npan, I2, &fails);
+                segment_integral(P, tf, o, d, sg->t0, sg->t1, p0, s->scale, 2 * npan, opts->field, I2, &fails);
                 err = 0.0;
                 for (int c = 0; c < 4; ++c)
                     if (fabs(I1[c] - I2[c]) > err) err = fabs(I1[c] - I2[c]);

@@ -37,7 +37,16 @@ typedef struct {
     const double *cp;         /* ncp0*ncp1*ncp2 x (x,y,z,w), i fastest     */
     const double *scalar;     /* ncp0*ncp1*ncp2 coefficients of rho         */
     int32_t rational;         /* 1: NURBS (w used), 0: plain B-spline       */
+    const double *disp;       /* NULL, or ncp0*ncp1*ncp2 x (u_x,u_y,u_z): the
+                                 displacement spline u on the same basis      */
 } orc_patch;
+
+/* Scalar field sampled along the ray (orc_opts.field): the block's scalar
+   spline rho, or a field derived from the maps on the fly. */
+#define ORC_FIELD_SCALAR 0
+#define ORC_FIELD_PARAM_QUALITY 1   /* Eq. (paramQuality): det J_phi / |J_phi|_F */
+#define ORC_FIELD_VON_MISES 2       /* Eq. (vonMises), read with its squares and
+                                       root, of the symmetrised J_{u o phi^-1}   */
 
 typedef struct {
     int32_t n;                /* number of knots of the transfer function   */
@@ -66,6 +75,7 @@ typedef struct {
     int32_t cut;
     double cut_point[3], cut_normal[3];
     double near_clip;
+    int32_t field;            /* ORC_FIELD_*                                  */
 } orc_opts;
 
 typedef struct orc_scene orc_scene;
@@ -141,6 +151,10 @@ double orc_table1_newton(int32_t method, double ds, double c, int32_t *max_newto
    from the ray.  *max_newton as in orc_table1_newton. */
 double orc_path_error(const orc_patch *P, const double p_in[3], const double p_out[3], int32_t method, double ds,
                       double c, int32_t *max_newton);
+/* The value of field ORC_FIELD_* at parameter point p of block P (0, or -1
+   where the field needs a displacement the block does not have or J_phi is
+   singular). */
+int32_t orc_field(const orc_patch *P, const double p[3], int32_t field, double *value);
 /* phi, J and the Hessian H[r*9 + a*3 + b] = d^2 phi_r / dp_a dp_b at p. */
 int32_t orc_eval_hessian(const orc_patch *P, const double p[3], double x[3], double J[9], double H[27]);
 

@@ -37,6 +37,7 @@ class Patch:
     cp: np.ndarray            # (N, 4) x, y, z, w
     scalar: np.ndarray        # (N,)
     rational: bool = False
+    displacement: Optional[np.ndarray] = None   # (N, 3) displacement spline u, or None
 
     def grid(self) -> np.ndarray:
         """Control points as an array indexed [k, j, i, c]."""
@@ -616,3 +617,27 @@ def make_config(k: int, width: Optional[int] = None, height: Optional[int] = Non
     if k == 5:
         return _config5()
     raise ValueError(f"unknown config {k}")
+
+
+# ---------------------------------------------------------------- displacement fields
+
+def with_displacement(scene: Scene, B: Optional[np.ndarray] = None, amplitude: float = 0.0,
+                      seed: int = 7300) -> Scene:
+    """The scene with a displacement spline u on every block, on the block's own
+    basis, with coefficient u_i = f(x_i) at each control point x_i (quasi-
+    interpolation): f(g) = B g for a 3x3 matrix B (then u = B phi exactly, also
+    for NURBS blocks), plus, with amplitude > 0, a smooth seeded field
+    amplitude * (sin(a.g), cos(b.g), sin(c.g + 0.3)) with random wave vectors.
+    The transfer function and cameras are the scene's."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    waves = rng.normal(0.0, 1.0, (3, 3)) / max(float(np.linalg.norm(scene.bbox[1] - scene.bbox[0])), 1e-9) * 4.0
+    out = []
+    for P in scene.patches:
+        x = P.cp[:, :3]
+        u = np.zeros_like(x)
+        if B is not None:
+            u += x @ np.asarray(B, dtype=np.float64).T
+        if amplitude > 0.0:
+            u += amplitude * np.stack([np.sin(x @ waves[0]), np.cos(x @ waves[1]), np.sin(x @ waves[2] + 0.3)], -1)
+        out.append(Patch(P.degree, P.ncp, P.knots, P.cp, P.scalar, P.rational, u))
+    return Scene(scene.name + "_displaced", out, scene.tf, scene.cameras, scene.bbox, dict(scene.params))

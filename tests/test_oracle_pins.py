@@ -1039,3 +1039,95 @@ def test_method_mode_fixed_steps_approach_root_finding(oracle_lib):
     for m in ("rk1", "rk2", "rk3", "rk4", "rk4_38", "rkf5", "irk1", "rkf45"):
         img, _ = oracle.render_method([P], cam2, tf, scale=2.0, method=m, h_max=0.05)
         assert np.abs(img - base).max() < 1e-11, m
+
+
+# ------------------------------------------------------------------ derived fields
+
+def _von_mises(e):
+    a, b, c = e[0, 0] - e[1, 1], e[1, 1] - e[2, 2], e[2, 2] - e[0, 0]
+    return math.sqrt(0.5 * (a * a + b * b + c * c + 6.0 * (e[0, 1] ** 2 + e[1, 2] ** 2 + e[2, 0] ** 2)))
+
+
+def test_parametrisation_quality_closed_forms(oracle_lib):
+    """Eq. (paramQuality), det J / |J|_F: on an affine block it is det A / |A|_F
+    everywhere; on a uniformly scaled cube s^2/sqrt(3); on the twisted bar (config 2,
+    a rigid twist of the unit square cross-section, det J = 8 along its length) it
+    equals det J / |J|_F with J from the oracle's evaluator, and flipping the
+    parameter direction flips its sign."""
+    from scenes import affine_patch
+    A = np.array([[1.2, 0.1, 0.0], [0.0, 0.9, 0.2], [0.1, 0.0, 1.1]])
+    P = affine_patch(A, np.array([0.1, -0.2, 0.05]))
+    rng = np.random.default_rng(61)
+    for p in rng.uniform(0, 1, (10, 3)):
+        assert abs(oracle.field_value(P, p, "param_quality") - np.linalg.det(A) / np.linalg.norm(A)) < 1e-13
+    S = affine_patch(2.5 * np.eye(3), np.zeros(3))
+    assert abs(oracle.field_value(S, [0.3, 0.6, 0.2], "param_quality") - 2.5 ** 2 / math.sqrt(3.0)) < 1e-13
+    F = affine_patch(np.diag([1.0, 1.0, -1.0]), np.zeros(3))
+    assert abs(oracle.field_value(F, [0.5, 0.5, 0.5], "param_quality") + 1.0 / math.sqrt(3.0)) < 1e-13
+    bar = make_config(2).patches[0]
+    for p in rng.uniform(0.05, 0.95, (10, 3)):
+        _, J, _ = oracle.evaluate(bar, p)
+        q = oracle.field_value(bar, p, "param_quality")
+        assert abs(q - np.linalg.det(J) / np.linalg.norm(J)) < 1e-12 * abs(q)
+
+
+@pytest.mark.parametrize("which", ["bar", "channel", "annulus"])
+def test_von_mises_of_a_linear_displacement_is_exact(oracle_lib, which):
+    """Eq. (vonMises) as read (squares and root restored): for the displacement
+    u = B phi (coefficients B x_i, exact on B-spline and NURBS bases) the Jacobian of
+    u o phi^-1 is B everywhere, whatever the map's curvature, so the field is the
+    von Mises value of (B + B^T)/2 at every point of a curved block; a rotation-free
+    pure shear gives sqrt(3)*gamma.  Using J_u without J_phi^-1, or dropping the
+    transpose, fails this on the curved blocks."""
+    from scenes import make_annulus, with_displacement
+    sc = {"bar": make_config(2), "channel": make_config(4, 64, 36), "annulus": make_annulus()}[which]
+    B = np.array([[0.02, 0.013, -0.004], [0.001, -0.011, 0.007], [0.009, 0.002, 0.015]])
+    ds = with_displacement(sc, B=B)
+    e = 0.5 * (B + B.T)
+    want = _von_mises(e)
+    rng = np.random.default_rng(71)
+    for P in ds.patches[:6]:
+        for p in rng.uniform(0.02, 0.98, (6, 3)):
+            assert abs(oracle.field_value(P, p, "von_mises") - want) < 1e-11 * want + 1e-15
+    gamma = 0.01
+    shear = with_displacement(sc, B=np.array([[0.0, gamma, 0.0], [gamma, 0.0, 0.0], [0.0, 0.0, 0.0]]))
+    v = oracle.field_value(shear.patches[0], [0.4, 0.5, 0.6], "von_mises")
+    assert abs(v - math.sqrt(3.0) * gamma) < 1e-12
+
+
+def test_render_of_a_constant_derived_field_has_the_closed_form(oracle_lib):
+    """An affine block with u = B phi: both derived fields are constant, so the
+    reference render is the constant-field closed form alpha = 1 - exp(-kappa L),
+    RGB = E alpha, with L the ray's chord through the block."""
+    from scenes import affine_patch, with_displacement
+    from scenes.configs import Scene
+    A = np.array([[1.2, 0.1, 0.0], [0.0, 0.9, 0.2], [0.1, 0.0, 1.1]])
+    b0 = np.array([0.1, -0.2, 0.05])
+    P = affine_patch(A, b0)
+    B = np.array([[0.02, 0.013, -0.004], [0.001, -0.011, 0.007], [0.009, 0.002, 0.015]])
+    bbox = np.array([P.cp[:, :3].min(0), P.cp[:, :3].max(0)])
+    cam = camera_from_angles(A @ np.full(3, 0.5) + b0, 3.5, 35.0, 20.0, 12, 12)
+    sc = with_displacement(Scene("affine", [P], None, [cam], bbox), B=B)
+    for field, value in (("param_quality", np.linalg.det(A) / np.linalg.norm(A)),
+                         ("von_mises", _von_mises(0.5 * (B + B.T)))):
+        tf = TransferFunction(np.array([0.0, 0.5, 1.0]), np.array([[0.1, 0.2, 0.9, 0.1], [0.9, 0.5, 0.1, 0.6],
+                                                                    [0.3, 0.8, 0.4, 0.9]]),
+                              3.0, (value - 1.0 * abs(value), value + 0.5 * abs(value)))
+        res = oracle.render(sc, cam, tf, field=field)
+        n = (value - tf.domain[0]) / (tf.domain[1] - tf.domain[0])
+        E = np.array([np.interp(n, tf.x, tf.rgba[:, c]) for c in range(4)])
+        kappa = tf.extinction * E[3]
+        Ainv = np.linalg.inv(A)
+        for pix in range(cam.width * cam.height):
+            o, d = oracle.camera_ray(cam, pix % cam.width + 0.5, pix // cam.width + 0.5)
+            # the chord through the block: the ray in parameter space against [0,1]^3
+            po, pd = Ainv @ (o - b0), Ainv @ d
+            t0, t1 = -np.inf, np.inf
+            for c in range(3):
+                a_, b_ = (0 - po[c]) / pd[c], (1 - po[c]) / pd[c]
+                t0, t1 = max(t0, min(a_, b_)), min(t1, max(a_, b_))
+            if not (t1 > max(t0, 0.0)):
+                assert res.rgba[pix, 3] == 0.0
+                continue
+            a = 1.0 - math.exp(-kappa * (t1 - t0))
+            assert np.abs(res.rgba[pix] - np.concatenate([E[:3] * a, [a]])).max() < 1e-9, (field, pix)
