@@ -70,6 +70,9 @@ typedef struct {
     const double *cp;
     const double *scalar;
     int32_t rational;
+    const double *displacement;   /* NULL, or ncp0*ncp1*ncp2 x (u_x,u_y,u_z): a
+                                     displacement spline u on the block's own
+                                     (rational) basis, for IVR_FIELD_VON_MISES */
 } ivr_patch_desc;
 
 /* Pinhole camera: the ray of pixel (i, j), row 0 at the top, passes through the
@@ -120,6 +123,17 @@ typedef struct {
                                   projected onto P; a step whose Newton does not
                                   converge in 16 iterations is taken as it
                                   stands and flagged RESTART_FAIL               */
+
+/* The value sampled along the ray.  The derived fields are computed from the
+   maps at every sample. */
+#define IVR_FIELD_SCALAR 0         /* the blocks' scalar splines rho              */
+#define IVR_FIELD_PARAM_QUALITY 1  /* det J_phi / |J_phi|_F, Sec. "Parametrization
+                                      Quality of Geometry", Eq. (paramQuality)  */
+#define IVR_FIELD_VON_MISES 2      /* von Mises value of the symmetrised Jacobian
+                                      of u o phi^-1 for the blocks' displacement
+                                      splines u (Eq. (vonMises), with the squares
+                                      and root its print lacks); every block must
+                                      carry one                                 */
 
 /* Render options (ivr_default_opts fills the defaults given in brackets). */
 typedef struct {
@@ -177,6 +191,12 @@ typedef struct {
                                    beyond it are rendered, and a block it cuts is
                                    entered there (an exit without an entry in
                                    front); 0: none                          [0] */
+    int32_t field;              /* IVR_FIELD_*: the value sampled along the ray;
+                                   a derived field comes with its exact
+                                   gradient (from the Hessian of the maps), so
+                                   rho_interp and the step bounds work as for
+                                   the scalar field; derived fields run with
+                                   the ODE and RF interior methods   [SCALAR] */
 } ivr_render_opts;
 
 /* Per-pixel flags (ivr_view.flags_dev): OR of the events of the pixel's ray. */

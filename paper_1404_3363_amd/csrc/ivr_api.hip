@@ -32,6 +32,9 @@ struct ivr_ctx {
     float *d_rho32 = nullptr;
     double4 *d_cp64 = nullptr;
     double *d_rho64 = nullptr;
+    float4 *d_disp32 = nullptr;           // displacement (w u, w) per control point, or null
+    double4 *d_disp64 = nullptr;
+    bool all_disp = false;                // every block carries a displacement spline
     float *d_knots32 = nullptr;
     double *d_knots64 = nullptr;
     FaceElem *d_elems = nullptr;
@@ -202,6 +205,10 @@ std::string validate_patch(const ivr_patch_desc &P, int idx) {
         if (!finite3(c) || !std::isfinite(P.scalar[i]) ||
             (P.rational && !(std::isfinite(c[3]) && c[3] > 0.0))) {
             snprintf(buf, sizeof buf, "patch %d: control point %zu not finite or weight <= 0", idx, i);
+            return buf;
+        }
+        if (P.displacement && !finite3(P.displacement + 3 * i)) {
+            snprintf(buf, sizeof buf, "patch %d: displacement %zu not finite", idx, i);
             return buf;
         }
     }
@@ -591,7 +598,7 @@ static void elevate_direction(std::vector<double> &H, int nch, int n[3], int d, 
 // A block with the same spline in one degree (the largest of its directions) in
 // all three directions; owns its arrays.
 struct IsoPatch {
-    std::vector<double> knots[3], cp, scalar;
+    std::vector<double> knots[3], cp, scalar, disp;
     ivr_patch_desc desc;
 };
 
@@ -599,29 +606,35 @@ static void make_isotropic(const ivr_patch_desc &P, IsoPatch &out) {
     const int Pm = std::max(P.degree[0], std::max(P.degree[1], P.degree[2]));
     int n[3] = {P.ncp[0], P.ncp[1], P.ncp[2]};
     const size_t N = (size_t)n[0] * n[1] * n[2];
-    // homogeneous channels (w x, w y, w z, w, w rho)
-    std::vector<double> H(N * 5);
+    // homogeneous channels (w x, w y, w z, w, w rho[, w u_x, w u_y, w u_z])
+    const int NCH = P.displacement ? 8 : 5;
+    std::vector<double> H(N * NCH);
     for (size_t q = 0; q < N; ++q) {
         const double w = P.rational ? P.cp[4 * q + 3] : 1.0;
-        for (int c = 0; c < 3; ++c) H[5 * q + c] = w * P.cp[4 * q + c];
-        H[5 * q + 3] = w;
-        H[5 * q + 4] = w * P.scalar[q];
+        for (int c = 0; c < 3; ++c) H[NCH * q + c] = w * P.cp[4 * q + c];
+        H[NCH * q + 3] = w;
+        H[NCH * q + 4] = w * P.scalar[q];
+        if (P.displacement)
+            for (int c = 0; c < 3; ++c) H[NCH * q + 5 + c] = w * P.displacement[3 * q + c];
     }
     for (int d = 0; d < 3; ++d) {
         if (P.degree[d] == Pm) {
             out.knots[d].assign(P.knots[d], P.knots[d] + P.ncp[d] + P.degree[d] + 1);
         } else {
-            elevate_direction(H, 5, n, d, P.knots[d], P.degree[d], Pm, out.knots[d]);
+            elevate_direction(H, NCH, n, d, P.knots[d], P.degree[d], Pm, out.knots[d]);
         }
     }
     const size_t M = (size_t)n[0] * n[1] * n[2];
     out.cp.resize(4 * M);
     out.scalar.resize(M);
+    if (P.displacement) out.disp.resize(3 * M);
     for (size_t q = 0; q < M; ++q) {
-        const double w = H[5 * q + 3];
-        for (int c = 0; c < 3; ++c) out.cp[4 * q + c] = H[5 * q + c] / w;
+        const double w = H[NCH * q + 3];
+        for (int c = 0; c < 3; ++c) out.cp[4 * q + c] = H[NCH * q + c] / w;
         out.cp[4 * q + 3] = P.rational ? w : 1.0;
-        out.scalar[q] = H[5 * q + 4] / w;
+        out.scalar[q] = H[NCH * q + 4] / w;
+        if (P.displacement)
+            for (int c = 0; c < 3; ++c) out.disp[3 * q + c] = H[NCH * q + 5 + c] / w;
     }
     out.desc = P;
     for (int d = 0; d < 3; ++d) {
@@ -631,6 +644,7 @@ static void make_isotropic(const ivr_patch_desc &P, IsoPatch &out) {
     }
     out.desc.cp = out.cp.data();
     out.desc.scalar = out.scalar.data();
+    out.desc.displacement = P.displacement ? out.disp.data() : nullptr;
 }
 
 // Splits a block (one degree P in every direction) at every interior knot of
@@ -674,6 +688,7 @@ static void split_at_c0(const ivr_patch_desc &P, std::deque<IsoPatch> &store, st
                 const size_t N = (size_t)nn[0] * nn[1] * nn[2];
                 Q.cp.resize(4 * N);
                 Q.scalar.resize(N);
+                if (P.displacement) Q.disp.resize(3 * N);
                 for (int k = 0; k < nn[2]; ++k)
                     for (int j = 0; j < nn[1]; ++j)
                         for (int a = 0; a < nn[0]; ++a) {
@@ -683,6 +698,8 @@ static void split_at_c0(const ivr_patch_desc &P, std::deque<IsoPatch> &store, st
                             const size_t di = (size_t)a + (size_t)nn[0] * (j + (size_t)nn[1] * k);
                             for (int c = 0; c < 4; ++c) Q.cp[4 * di + c] = P.cp[4 * si + c];
                             Q.scalar[di] = P.scalar[si];
+                            if (P.displacement)
+                                for (int c = 0; c < 3; ++c) Q.disp[3 * di + c] = P.displacement[3 * si + c];
                         }
                 Q.desc = P;
                 for (int e = 0; e < 3; ++e) {
@@ -691,6 +708,7 @@ static void split_at_c0(const ivr_patch_desc &P, std::deque<IsoPatch> &store, st
                 }
                 Q.desc.cp = Q.cp.data();
                 Q.desc.scalar = Q.scalar.data();
+                Q.desc.displacement = P.displacement ? Q.disp.data() : nullptr;
                 piece[side] = &Q;
             }
             split_at_c0(piece[0]->desc, store, out);
@@ -725,6 +743,7 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->det_singular = 1e-6;
     o->drift_tol = 1e-4;
     o->interior = IVR_INTERIOR_ODE;
+    o->field = IVR_FIELD_SCALAR;
     o->cut = 0;
     for (int q = 0; q < 3; ++q) o->cut_point[q] = o->cut_normal[q] = 0.0;
     o->near_clip = 0.0;
@@ -790,6 +809,7 @@ const char *ivr_last_error(const ivr_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 static void free_model(ivr_ctx *c) {
     dfree(c->d_patches); dfree(c->d_cp32); dfree(c->d_rho32); dfree(c->d_cp64); dfree(c->d_rho64);
+    dfree(c->d_disp32); dfree(c->d_disp64);
     dfree(c->d_knots32); dfree(c->d_knots64); dfree(c->d_elems); dfree(c->d_tiles); dfree(c->d_btab);
     dfree(c->d_pperm); dfree(c->d_pcount); dfree(c->d_pbase); dfree(c->d_pcur);
     c->has_model = false;
@@ -924,6 +944,9 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     std::vector<float> rho32, knots32;
     std::vector<double4> cp64;
     std::vector<double> rho64, knots64;
+    std::vector<float4> disp32;
+    std::vector<double4> disp64;
+    size_t n_disp = 0;   // blocks with a displacement spline
     std::vector<FaceElem> elems;
     std::vector<FaceTile> tiles, subs;
     std::vector<float> btab;
@@ -978,8 +1001,14 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
             cp64.push_back(make_double4(w * cc[0], w * cc[1], w * cc[2], w4));
             rho32.push_back((float)(w * P.scalar[q]));
             rho64.push_back(w * P.scalar[q]);
+            // displacement as (w u, w); blocks without one hold zeros
+            const double *u = P.displacement ? P.displacement + 3 * q : nullptr;
+            const double du[3] = {u ? w * u[0] : 0.0, u ? w * u[1] : 0.0, u ? w * u[2] : 0.0};
+            disp32.push_back(make_float4((float)du[0], (float)du[1], (float)du[2], (float)w));
+            disp64.push_back(make_double4(du[0], du[1], du[2], w));
             pb.add(cc);
         }
+        if (P.displacement) ++n_disp;
         pb.store(D.box, pad);
         auto idx = [&](int i, int j, int k) { return (size_t)i + (size_t)n0 * (j + (size_t)n1 * k); };
         for (int f = 0; f < 6; ++f) {
@@ -1150,7 +1179,12 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
         if (hipMalloc((void **)&dst, sizeof(T) * std::max<size_t>(vec.size(), 1)) != hipSuccess) return false;
         return hipMemcpy((void *)dst, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice) == hipSuccess;
     };
+    if (n_disp == 0) {   // no displacement anywhere: nothing to store
+        disp32.clear();
+        disp64.clear();
+    }
     bool ok = up(tmp.d_patches, hp) && up(tmp.d_cp32, cp32) && up(tmp.d_rho32, rho32) &&
+              up(tmp.d_disp32, disp32) && up(tmp.d_disp64, disp64) &&
               up(tmp.d_cp64, cp64) && up(tmp.d_rho64, rho64) && up(tmp.d_knots32, knots32) &&
               up(tmp.d_knots64, knots64) && up(tmp.d_elems, elems) && up(tmp.d_tiles, tiles) &&
               up(tmp.d_btab, btab) &&
@@ -1166,6 +1200,9 @@ ivr_status ivr_upload_models(ivr_ctx *c, const ivr_patch_desc *patches, int32_t 
     c->hpatch = hp;
     c->d_patches = tmp.d_patches; c->d_cp32 = tmp.d_cp32; c->d_rho32 = tmp.d_rho32;
     c->d_cp64 = tmp.d_cp64; c->d_rho64 = tmp.d_rho64; c->d_knots32 = tmp.d_knots32;
+    c->d_disp32 = tmp.d_disp32; c->d_disp64 = tmp.d_disp64;
+    tmp.d_disp32 = nullptr; tmp.d_disp64 = nullptr;
+    c->all_disp = n_disp == (size_t)n;
     c->d_knots64 = tmp.d_knots64; c->d_elems = tmp.d_elems; c->d_tiles = tmp.d_tiles;
     c->d_btab = tmp.d_btab;
     tmp.d_btab = nullptr;
@@ -1341,6 +1378,14 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
     fp.n_super = o.n_super;
     fp.max_frag = o.max_fragments;
     fp.hermite = o.rho_interp == IVR_RHO_HERMITE ? 1 : 0;
+    if (o.field < IVR_FIELD_SCALAR || o.field > IVR_FIELD_VON_MISES) return fail(c, IVR_EINVAL, "unknown field");
+    if (o.field != IVR_FIELD_SCALAR) {
+        if (o.interior != IVR_INTERIOR_ODE && o.interior != IVR_INTERIOR_RF)
+            return fail(c, IVR_EINVAL, "derived fields need the ODE or RF interior method");
+        if (o.field == IVR_FIELD_VON_MISES && !c->all_disp)
+            return fail(c, IVR_EINVAL, "von Mises needs a displacement spline on every block");
+    }
+    fp.field = o.field;
     fp.max_newton = o.max_newton_iter;
     fp.scaled = scale;
     fp.scale = (float)scale;
@@ -1424,6 +1469,7 @@ static Model device_model(ivr_ctx *c) {
     Model m;
     m.patches = c->d_patches; m.cp32 = c->d_cp32; m.rho32 = c->d_rho32; m.cp64 = c->d_cp64;
     m.rho64 = c->d_rho64; m.knots32 = c->d_knots32; m.knots64 = c->d_knots64; m.elems = c->d_elems;
+    m.disp32 = c->d_disp32; m.disp64 = c->d_disp64;
     m.tiles = c->d_tiles;
     m.btab = c->d_btab;
     m.mlp_wb = c->mlp.wb;
@@ -1443,6 +1489,7 @@ struct HostView {
 struct Batch {
     int n = 0;
     int method = IVR_INTERIOR_ODE;
+    int field = IVR_FIELD_SCALAR;
     uint32_t n_tiles = 0, n_pixels = 0, class_mask = 0;
     bool fp64 = false, mlp = false, collect = false;
     uint32_t c_cap = 0;   // candidates the fragment launches may record
@@ -1479,6 +1526,7 @@ static ivr_status fill_views(ivr_ctx *c, const HostView *hv, int n, const ivr_re
     b.fp64 = o.precision == IVR_PRECISION_FP64;
     b.mlp = o.seed_mode == IVR_SEED_MLP;
     b.method = o.interior;
+    b.field = o.field;
     b.collect = collect;
     const int th = 64 / lc.tile_w;
     uint64_t tiles = 0, pixels = 0;
@@ -1584,7 +1632,8 @@ static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const FrameBufs &fb, 
         ia.pcur = fb.pcur;
         ia.max_cp = c->cls_max_cp[k];
         ia.max_tab = c->cls_max_tab[k];
-        IVR_HIP(c, launch_integrate(b.fp64, b.method, k, m, fb.views, b.n, fb.segs, ia, fb.ctr, c->n_cu, lc, s));
+        IVR_HIP(c, launch_integrate(b.fp64, b.method, b.field, k, m, fb.views, b.n, fb.segs, ia, fb.ctr, c->n_cu,
+                                    lc, s));
     }
     if (ev) IVR_HIP(c, hipEventRecord(ev[2], s));
     IVR_HIP(c, launch_merge(fb.views, b.n, b.n_pixels, fb.pixseg, fb.segs, b.fp64, fb.qs, fb.totals, s));
@@ -1772,7 +1821,7 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
     if (st != IVR_OK) return st;
     // the graph holds every kernel argument except what the view table carries
     // (cameras, transfer functions, output pointers): key it by the rest
-    std::vector<int64_t> key = {(int64_t)c->generation, b.n, b.fp64, b.mlp, b.method, (int64_t)b.class_mask,
+    std::vector<int64_t> key = {(int64_t)c->generation, b.n, b.fp64, b.mlp, b.method, b.field, (int64_t)b.class_mask,
                                 c->lc.tile_w, c->lc.xcd_chunk, c->lc.int_block, c->lc.int_waves_cu,
                                 (int64_t)b.c_cap};
     for (int v = 0; v < n_views; ++v) {
@@ -1938,6 +1987,7 @@ static Model model_of(ivr_ctx *c) {
     m.patches = c->d_patches; m.cp32 = c->d_cp32; m.rho32 = c->d_rho32; m.cp64 = c->d_cp64;
     m.rho64 = c->d_rho64; m.knots32 = c->d_knots32; m.knots64 = c->d_knots64; m.elems = c->d_elems;
     m.tiles = c->d_tiles; m.btab = c->d_btab; m.mlp_wb = c->mlp.wb; m.mlp_norm = c->mlp.norm;
+    m.disp32 = c->d_disp32; m.disp64 = c->d_disp64;
     m.npatch = c->npatch; m.scale = (float)c->scale; m.scaled = c->scale;
     return m;
 }

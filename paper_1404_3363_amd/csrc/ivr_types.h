@@ -103,6 +103,10 @@ struct Model {
     // follow each other, spans in order.
     const float *btab;
     const uint16_t *mlp_wb;    // BF16 MLP weights per block (seed_mode MLP)
+    // displacement spline u per control point as (w u, w) (w = 1 for B-splines),
+    // same order as cp32 / cp64; null when the model has none
+    const float4 *disp32;
+    const double4 *disp64;
     const float *mlp_norm;     // per block: (unused[3], 1/half extent[3], centre[3], pad[3])
     int32_t npatch;
     float scale;           // bounding-box diagonal of the model
@@ -181,6 +185,7 @@ struct FrameParams {
     double rk_told, h_maxd, h_mind, c_perpd, early_termd, det_thrd, det_singd, drift_told;
     int32_t n_super, max_frag, max_newton, collect, hermite, seed_mode;
     int32_t interior;               // IVR_INTERIOR_*
+    int32_t field;                  // IVR_FIELD_*
     // Sec. "Cutting and Near Clip Planes": cutting plane (cut != 0) keeping
     // cut_n . (g - g0) >= 0, with cut_s0 = cut_n . (eye - g0) for this view; near
     // plane near_clip in front of the eye along fwd (0: none)

@@ -21,6 +21,7 @@ FLAGS = {"anomaly": 1, "fragment_overflow": 2, "segment_overflow": 4, "iter_cap"
 PRECISION = {"fp32": 0, "fp64": 1}
 SEED = {"plain": 0, "mlp": 1, "box": 2}
 RHO_INTERP = {"linear": 0, "hermite": 1}
+FIELDS = {"scalar": 0, "param_quality": 1, "von_mises": 2}
 INTERIOR = {"ode": 0, "rf": 1, "rk1": 2, "rk2": 3, "rk3": 4, "rk4": 5, "rk4_38": 6, "rkf5": 7, "irk1": 8}
 
 EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_upload_models",
@@ -34,7 +35,8 @@ MLP_PARAMS = 4611
 class PatchDesc(C.Structure):
     _fields_ = [("degree", C.c_int32 * 3), ("ncp", C.c_int32 * 3),
                 ("knots", C.POINTER(C.c_double) * 3), ("cp", C.POINTER(C.c_double)),
-                ("scalar", C.POINTER(C.c_double)), ("rational", C.c_int32)]
+                ("scalar", C.POINTER(C.c_double)), ("rational", C.c_int32),
+                ("displacement", C.POINTER(C.c_double))]
 
 
 class CameraDesc(C.Structure):
@@ -57,7 +59,8 @@ class RenderOpts(C.Structure):
                 ("timing", C.c_int32), ("tf_step", C.c_double), ("rho_step", C.c_double),
                 ("cand_per_pixel", C.c_int32), ("det_singular", C.c_double),
                 ("drift_tol", C.c_double), ("interior", C.c_int32), ("cut", C.c_int32),
-                ("cut_point", C.c_double * 3), ("cut_normal", C.c_double * 3), ("near_clip", C.c_double)]
+                ("cut_point", C.c_double * 3), ("cut_normal", C.c_double * 3), ("near_clip", C.c_double),
+                ("field", C.c_int32)]
 
 
 class ViewDesc(C.Structure):
@@ -173,6 +176,8 @@ def default_opts(**kw) -> RenderOpts:
             v = RHO_INTERP[v]
         if k == "interior" and isinstance(v, str):
             v = INTERIOR[v]
+        if k == "field" and isinstance(v, str):
+            v = FIELDS[v]
         if k == "cut_plane":   # (point, normal) or None
             o.cut = 0 if v is None else 1
             if v is not None:
@@ -269,6 +274,12 @@ class Renderer:
             d.cp = _dp(cp)
             d.scalar = _dp(sc)
             d.rational = 1 if p.rational else 0
+            disp = getattr(p, "displacement", None)
+            if disp is not None:
+                u = np.ascontiguousarray(disp, dtype=np.float64).reshape(-1)
+                assert u.size == 3 * len(sc), "displacement: 3 values per control point"
+                keep.append(u)
+                d.displacement = _dp(u)
         self._check(self.lib.ivr_upload_models(self.ctx, arr, len(patches), sizes, len(models)))
 
     # ---- learned initialiser

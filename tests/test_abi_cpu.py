@@ -35,9 +35,40 @@ def test_default_opts_match_header():
     assert o.det_singular == 1e-6 and o.det_fp64_threshold == 1e-6 and o.drift_tol == 1e-4
 
 
+def test_struct_layouts_match_the_compiled_header(tmp_path):
+    """Every ctypes mirror of an include/ivr.h struct has the size and field
+    offsets the C compiler gives the header."""
+    import shutil
+    import subprocess
+    from paper_1404_3363_amd import ivr
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"ivr_patch_desc": ivr.PatchDesc, "ivr_camera": ivr.CameraDesc, "ivr_render_opts": ivr.RenderOpts,
+               "ivr_transfer_fn": ivr.TransferDesc,
+               "ivr_stats": ivr.Stats, "ivr_view": ivr.ViewDesc, "ivr_tune_report": ivr.TuneReport,
+               "ivr_mlp_opts": ivr.MlpOpts, "ivr_mlp_report": ivr.MlpReport}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ivr.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'    printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in mirrors.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
+
+
 def test_struct_layouts_match_header():
     from paper_1404_3363_amd import ivr
-    assert ctypes.sizeof(ivr.PatchDesc) == 6 * 4 + 3 * 8 + 8 + 8 + 8
+    assert ctypes.sizeof(ivr.PatchDesc) == 6 * 4 + 3 * 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(ivr.CameraDesc) == 10 * 8 + 8
     assert ctypes.sizeof(ivr.Stats) == len(ivr.STAT_FIELDS) * 8 + 3 * 8 == 22 * 8 + 3 * 8
     # ivr_view: camera, tf pointer, model (padded), three device pointers

@@ -821,3 +821,114 @@ def test_fixed_step_methods_fp32_within_the_bar(renderer, method):
             assert st["restart_fail"] <= 2e-3 * st["rk_steps"]
         else:
             assert st["restart_fail"] == 0
+
+
+# ------------------------------------------------------------------ derived fields
+
+def _field_tf(sc, field, seed=5):
+    """The scene's transfer function over the range of a derived field (its 2nd to
+    98th percentile over seeded points of every block, by the oracle)."""
+    rng = np.random.default_rng(seed)
+    vals = [oracle.field_value(P, p, field) for P in sc.patches for p in rng.uniform(0, 1, (max(2, 256 // len(sc.patches)), 3))]
+    lo, hi = np.percentile(vals, [2, 98])
+    if hi <= lo:
+        lo, hi = lo - 1.0, hi + 1.0
+    return TransferFunction(sc.tf.x, sc.tf.rgba, sc.tf.extinction, (float(lo), float(hi)))
+
+
+@pytest.mark.parametrize("interior", ["ode", "rf"])
+@pytest.mark.parametrize("k", [2, 4])
+def test_parametrisation_quality_field(renderer, k, interior):
+    """The parametrisation quality det J / |J|_F (Eq. (paramQuality)) computed at
+    every sample, with its exact gradient for the Hermite interpolation and the
+    step bound, on the twisted bar (config 2) and the NURBS channel (config 4):
+    within the bar against the oracle's reference render of the same field.  On
+    the channel the quality spans only 0.044..0.060, which the transfer function
+    stretches over its whole range: the sampling takes rho_step = 0.01 and
+    h_max = scale/512 there (at the defaults the error is that of the sampling,
+    4e-3 with the ODE, and falls with rho_step)."""
+    sc = make_config(k) if k == 2 else make_config(k, 480, 270)
+    cam = sc.cameras[0]
+    tf = _field_tf(sc, "param_quality")
+    kw = {} if k == 2 else dict(rho_step=0.01, h_max=sc.scale / 512)
+    img, depth, st = _render(renderer, sc.patches, cam, tf, field="param_quality", interior=interior, **kw)
+    pix = None if k == 2 else _sample(cam, depth, 384, 128, 400 + k)
+    ref = oracle.render(sc, cam, tf, pixels=pix, field="param_quality")
+    _compare(f"config{k} parametrisation quality ({interior})", img, depth, ref, pix, sc.scale)
+    assert st["anomalies"] == 0
+    if k == 4 and interior == "ode":
+        errs = []
+        for rs in (0.1, 0.025):
+            im, _, _ = _render(renderer, sc.patches, cam, tf, field="param_quality", rho_step=rs)
+            errs.append(float(np.abs(im[pix] - ref.rgba).max()))
+        print(f"[fields] channel quality, ODE: max err {errs[0]:.2e} at rho_step 0.1, {errs[1]:.2e} at 0.025",
+              flush=True)
+        assert errs[1] < errs[0]
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_von_mises_field(renderer, k):
+    """Von Mises of a displacement spline (Eq. (vonMises) as read) with its exact
+    gradient, on the bent beam (config 3, cubic B-spline blocks) and the NURBS
+    channel (config 4), the displacement a seeded smooth field plus a linear part:
+    within the bar against the oracle's reference render (rho_step = 0.05); FP64
+    as well on the channel."""
+    from scenes import with_displacement
+    base = make_config(k, 480, 270)
+    B = np.array([[0.01, 0.004, 0.0], [0.002, -0.006, 0.003], [0.0, 0.001, 0.008]])
+    sc = with_displacement(base, B=B, amplitude=0.02 * base.scale)
+    cam = sc.cameras[0]
+    tf = _field_tf(sc, "von_mises")
+    for precision in (("fp32", "fp64") if k == 4 else ("fp32",)):
+        img, depth, st = _render(renderer, sc.patches, cam, tf, field="von_mises", precision=precision,
+                                 rho_step=0.05)
+        pix = _sample(cam, depth, 384, 128, 410 + k)
+        ref = oracle.render(sc, cam, tf, pixels=pix, field="von_mises")
+        _compare(f"config{k} von Mises {precision}", img, depth, ref, pix, sc.scale)
+
+
+def test_derived_fields_closed_form_and_errors(renderer):
+    """On an affine block with u = B phi both derived fields are constant: the GPU
+    image is the constant-field closed form.  Von Mises on a model without
+    displacement, or a derived field with a fixed-step method, is refused."""
+    from paper_1404_3363_amd import IvrError
+    from scenes import affine_patch, with_displacement
+    from scenes.configs import Scene
+    A = np.array([[1.2, 0.1, 0.0], [0.0, 0.9, 0.2], [0.1, 0.0, 1.1]])
+    b0 = np.array([0.1, -0.2, 0.05])
+    P = affine_patch(A, b0)
+    B = np.array([[0.02, 0.013, -0.004], [0.001, -0.011, 0.007], [0.009, 0.002, 0.015]])
+    bbox = np.array([P.cp[:, :3].min(0), P.cp[:, :3].max(0)])
+    cam = camera_from_angles(A @ np.full(3, 0.5) + b0, 3.5, 35.0, 20.0, 40, 40)
+    sc = with_displacement(Scene("affine", [P], None, [cam], bbox), B=B)
+    e = 0.5 * (B + B.T)
+    vm = math.sqrt(0.5 * ((e[0, 0] - e[1, 1]) ** 2 + (e[1, 1] - e[2, 2]) ** 2 + (e[2, 2] - e[0, 0]) ** 2 +
+                          6 * (e[0, 1] ** 2 + e[1, 2] ** 2 + e[2, 0] ** 2)))
+    Ainv = np.linalg.inv(A)
+    for field, value in (("param_quality", np.linalg.det(A) / np.linalg.norm(A)), ("von_mises", vm)):
+        tf = TransferFunction(np.array([0.0, 0.5, 1.0]), np.array([[0.1, 0.2, 0.9, 0.1], [0.9, 0.5, 0.1, 0.6],
+                                                                    [0.3, 0.8, 0.4, 0.9]]),
+                              3.0, (value - abs(value), value + 0.5 * abs(value)))
+        img, depth, _ = _render(renderer, sc.patches, cam, tf, field=field)
+        n = (value - tf.domain[0]) / (tf.domain[1] - tf.domain[0])
+        E = np.array([np.interp(n, tf.x, tf.rgba[:, c]) for c in range(4)])
+        worst = 0.0
+        for pix in range(cam.width * cam.height):
+            o, d = oracle.camera_ray(cam, pix % cam.width + 0.5, pix // cam.width + 0.5)
+            po, pd = Ainv @ (o - b0), Ainv @ d
+            t0, t1 = -np.inf, np.inf
+            for c in range(3):
+                a_, b_ = (0 - po[c]) / pd[c], (1 - po[c]) / pd[c]
+                t0, t1 = max(t0, min(a_, b_)), min(t1, max(a_, b_))
+            if not (t1 > max(t0, 0.0)):
+                continue
+            a = 1.0 - math.exp(-tf.extinction * E[3] * (t1 - t0))
+            worst = max(worst, float(np.abs(img[pix] - np.concatenate([E[:3] * a, [a]])).max()))
+        print(f"[fields] affine block, {field}: max err vs closed form {worst:.2e}", flush=True)
+        assert worst <= 1e-5
+    renderer.upload([P])
+    with pytest.raises(IvrError):
+        renderer.render(cam, make_config(1).tf, field="von_mises")
+    renderer.upload(sc.patches)
+    with pytest.raises(IvrError):
+        renderer.render(cam, make_config(1).tf, field="param_quality", interior="rk2")
