@@ -108,7 +108,9 @@ def lib():
         L.orc_locate.restype = C.c_int32
         L.orc_render_pixels_method.argtypes = [C.c_void_p, C.POINTER(_Camera), C.POINTER(_TF),
                                                C.POINTER(_MethodOpts), C.POINTER(C.c_int64), C.c_int64, dp,
-                                               C.POINTER(C.c_int64)]
+                                               C.POINTER(C.c_int64), dp, C.POINTER(C.c_int32)]
+        L.orc_delta_p.argtypes = [C.POINTER(_Camera), C.c_int64, dp]
+        L.orc_delta_p.restype = C.c_double
         L.orc_render_pixels_method.restype = C.c_int32
         L.orc_table1.argtypes = [C.c_int32, C.c_double, C.c_double]
         L.orc_table1.restype = C.c_double
@@ -368,10 +370,11 @@ def render(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None,
 def render_method(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None, rk_tol: float = 1e-5,
                   h_max: float = 0.0, c_perp: float = 1.0, rho_step: float = 0.1, tf_step: float = 0.025,
                   n_super: int = 4, hermite: bool = True, nthreads: int = 0, scale: Optional[float] = None,
-                  prepared: Optional[OracleScene] = None, method: str = "rkf45"):
+                  prepared: Optional[OracleScene] = None, method: str = "rkf45", pixel_accuracy: bool = False):
     """Method mode: the GPU path's method (adaptive RKF45 on the ray preimage ODE,
     or a fixed-step method of METHODS; Hermite or linear rho, supersampling) in
-    FP64.  Returns (rgba, steps)."""
+    FP64.  Returns (rgba, steps), and with pixel_accuracy a third item: per pixel
+    the largest Delta P of the interior samples and the depth-order violations."""
     if prepared is None:
         patches = getattr(scene_or_patches, "patches", scene_or_patches)
         if scale is None:
@@ -387,8 +390,20 @@ def render_method(scene_or_patches, cam, tf, pixels: Optional[np.ndarray] = None
         npix, pix_ptr = len(pixels), pixels.ctypes.data_as(C.POINTER(C.c_int64))
     rgba = np.zeros((npix, 4))
     steps = C.c_int64(0)
+    dpv = np.zeros(npix) if pixel_accuracy else None
+    bad = np.zeros(npix, dtype=np.int32) if pixel_accuracy else None
     rc = lib().orc_render_pixels_method(prepared.handle, C.byref(_camera(cam)), C.byref(tf_s.struct), C.byref(mo),
-                                        pix_ptr, npix, _dp(rgba), C.byref(steps))
+                                        pix_ptr, npix, _dp(rgba), C.byref(steps),
+                                        _dp(dpv) if pixel_accuracy else None,
+                                        bad.ctypes.data_as(C.POINTER(C.c_int32)) if pixel_accuracy else None)
     if rc != 0:
         raise RuntimeError(f"orc_render_pixels_method failed ({rc})")
+    if pixel_accuracy:
+        return rgba, steps.value, {"delta_p": dpv, "order_violations": bad}
     return rgba, steps.value
+
+
+def delta_p(cam, pixel: int, g) -> float:
+    """Eq. (deltaP) for point g and pixel (row*width + col)."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    return float(lib().orc_delta_p(C.byref(_camera(cam)), int(pixel), _dp(g)))

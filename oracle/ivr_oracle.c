@@ -196,6 +196,59 @@ int32_t orc_eval_hessian(const orc_patch *P, const double pin[3], double x[3], d
     return 0;
 }
 
+/* ------------------------------------------------------------------ pixel accuracy
+ * Definition "Pixel-Accurate Approximation of Geometry": a sample phi(p_i)
+ * must project into the pixel of its ray, Delta P = 2 |pi_s(phi(p_i)) - c|_inf
+ * <= 1 (Eq. (deltaP)) with c the pixel centre and pi_s the projection to the
+ * screen (in pixel units), and the samples' projections onto the ray must not
+ * go back towards the eye ("covering accuracy").                             */
+static double norm3(const double v[3]);
+
+double orc_delta_p(const orc_camera *c, int64_t pixel, const double g[3])
+{
+    double f[3], r[3], u[3], v[3];
+    for (int q = 0; q < 3; ++q) f[q] = c->target[q] - c->eye[q];
+    const double nf = norm3(f);
+    for (int q = 0; q < 3; ++q) f[q] /= nf;
+    r[0] = f[1] * c->up[2] - f[2] * c->up[1];
+    r[1] = f[2] * c->up[0] - f[0] * c->up[2];
+    r[2] = f[0] * c->up[1] - f[1] * c->up[0];
+    const double nr = norm3(r);
+    for (int q = 0; q < 3; ++q) r[q] /= nr;
+    u[0] = r[1] * f[2] - r[2] * f[1];
+    u[1] = r[2] * f[0] - r[0] * f[2];
+    u[2] = r[0] * f[1] - r[1] * f[0];
+    for (int q = 0; q < 3; ++q) v[q] = g[q] - c->eye[q];
+    const double z = v[0] * f[0] + v[1] * f[1] + v[2] * f[2];
+    const double th = tan(0.5 * c->fov_y_deg * M_PI / 180.0), aspect = (double)c->width / (double)c->height;
+    const double sx = (v[0] * r[0] + v[1] * r[1] + v[2] * r[2]) / z;
+    const double sy = (v[0] * u[0] + v[1] * u[1] + v[2] * u[2]) / z;
+    const double X = (sx / (th * aspect) + 1.0) * 0.5 * c->width, Y = (1.0 - sy / th) * 0.5 * c->height;
+    const double cx = (double)(pixel % c->width) + 0.5, cy = (double)(pixel / c->width) + 0.5;
+    return 2.0 * fmax(fabs(X - cx), fabs(Y - cy));
+}
+
+/* Per-pixel pixel-accuracy record of the method mode's interior samples. */
+typedef struct {
+    const orc_camera *cam;
+    int64_t pixel;
+    const double *o, *d;
+    double dp_max, t_prev;
+    int order_bad;
+} pix_diag_t;
+
+static void diag_sample(pix_diag_t *dg, const orc_patch *P, const double p[3])
+{
+    if (!dg) return;
+    double x[3], J[9];
+    orc_eval(P, p, x, J, NULL);
+    const double dp = orc_delta_p(dg->cam, dg->pixel, x);
+    if (dp > dg->dp_max) dg->dp_max = dp;
+    const double t = (x[0] - dg->o[0]) * dg->d[0] + (x[1] - dg->o[1]) * dg->d[1] + (x[2] - dg->o[2]) * dg->d[2];
+    if (t < dg->t_prev) ++dg->order_bad;
+    dg->t_prev = t;
+}
+
 /* ------------------------------------------------------------------ derived fields
  * Sec. "Parametrization Quality of Geometry", Eq. (paramQuality): the quality
  * of the parametrisation is det J_phi / ||J_phi||_F.
@@ -1515,7 +1568,7 @@ static int irk1_step(const orc_patch *P, double p[3], double h, const double gin
 static void method_fixed_steps(const orc_patch *P, const orc_tf *tf, const orc_method_opts *mo, double scale,
                                double hmax, double hmin, double L, double gin[3], const double d[3], double p[3],
                                double W[3], double rho_a, double m_a, double rho_out, double m_out, double C[3],
-                               double *A, long long *steps)
+                               double *A, long long *steps, pix_diag_t *dg)
 {
     const double inv = 1.0 / (tf->domain[1] - tf->domain[0]);
     const int method = mo->method;
@@ -1566,6 +1619,7 @@ static void method_fixed_steps(const orc_patch *P, const orc_tf *tf, const orc_m
         }
         for (int e = 0; e < 3; ++e) gin[e] += hh * d[e];
         s += hh;
+        diag_sample(dg, P, p);
         method_W(P, p, gin, d, c, W, &rho, g);
         const double m_b = g[0] * W[0] + g[1] * W[1] + g[2] * W[2];
         method_interval(tf, mo, rho_a, m_a, rho, m_b, hh, C, A);
@@ -1629,8 +1683,9 @@ double orc_path_error(const orc_patch *P, const double p_in[3], const double p_o
 
 static void method_segment(const orc_patch *P, const orc_tf *tf, const orc_method_opts *mo, double scale,
                            const double o[3], const double d[3], const orc_fragment *fi, const orc_fragment *fo,
-                           double out[4], long long *steps)
+                           double out[4], long long *steps, pix_diag_t *dg)
 {
+    if (dg) dg->t_prev = fi->t;
     const double L = fo->t - fi->t, hmax = mo->h_max > 0 ? mo->h_max : scale / 32.0;
     const double hmin = fmin(hmax, 1.5625e-6 * scale);
     double gin[3], p[3], W[3], rho, g[3], C[3] = {0, 0, 0}, A = 0.0;
@@ -1649,7 +1704,9 @@ static void method_segment(const orc_patch *P, const orc_tf *tf, const orc_metho
     }
     const double inv = 1.0 / (tf->domain[1] - tf->domain[0]);
     if (mo->method != 0) {
-        method_fixed_steps(P, tf, mo, scale, hmax, hmin, L, gin, d, p, W, rho_a, m_a, rho_out, m_out, C, &A, steps);
+        method_fixed_steps(P, tf, mo, scale, hmax, hmin, L, gin, d, p, W, rho_a, m_a, rho_out, m_out, C, &A, steps,
+                           dg);
+        if (dg && fo->t < dg->t_prev) ++dg->order_bad;
         out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = A;
         return;
     }
@@ -1691,6 +1748,7 @@ static void method_segment(const orc_patch *P, const orc_tf *tf, const orc_metho
                 break;
             }
             for (int c = 0; c < 3; ++c) p[c] = clamp01(p5[c]);
+            diag_sample(dg, P, p);
             method_W(P, p, gin, d, mo->c_perp, W, &rho, g);
             const double m_b = g[0] * W[0] + g[1] * W[1] + g[2] * W[2];
             method_interval(tf, mo, rho_a, m_a, rho, m_b, hh, C, &A);
@@ -1703,6 +1761,7 @@ static void method_segment(const orc_patch *P, const orc_tf *tf, const orc_metho
         rejected = !accept;
         h = fmin(hmax, fmax(hmin, hh * fac));
     }
+    if (dg && fo->t < dg->t_prev) ++dg->order_bad;
     out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = A;
 }
 
@@ -1714,6 +1773,8 @@ typedef struct {
     const int64_t *pixels;
     int64_t npix;
     double *rgba;
+    double *dp;
+    int32_t *order_bad;
     long long steps;
     int tid, nthreads;
 } mjob_t;
@@ -1740,14 +1801,18 @@ static void *method_worker(void *arg)
                 pairs[b - 1][0] = t0; pairs[b - 1][1] = t1;
             }
         double C[3] = {0, 0, 0}, A = 0.0;
+        pix_diag_t dgv = {j->cam, pix, o, d, 0.0, 0.0, 0};
+        pix_diag_t *dg = (j->dp || j->order_bad) ? &dgv : NULL;
         for (int k = 0; k < np && A < 1.0 - 1e-4; ++k) {
             double r[4];
             const orc_fragment *fi = &fr[pairs[k][0]], *fo = &fr[pairs[k][1]];
-            method_segment(&j->s->patches[fo->patch], j->tf, j->mo, j->s->scale, o, d, fi, fo, r, &j->steps);
+            method_segment(&j->s->patches[fo->patch], j->tf, j->mo, j->s->scale, o, d, fi, fo, r, &j->steps, dg);
             for (int c = 0; c < 3; ++c) C[c] += (1.0 - A) * r[c];
             A += (1.0 - A) * r[3];
         }
         out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = A;
+        if (j->dp) j->dp[i] = dgv.dp_max;
+        if (j->order_bad) j->order_bad[i] = dgv.order_bad;
     }
     free(fr);
     free(pairs);
@@ -1756,7 +1821,7 @@ static void *method_worker(void *arg)
 
 int32_t orc_render_pixels_method(const orc_scene *s, const orc_camera *cam, const orc_tf *tf,
                                  const orc_method_opts *mo, const int64_t *pixels, int64_t npix, double *rgba,
-                                 int64_t *rk_steps)
+                                 int64_t *rk_steps, double *dp, int32_t *order_bad)
 {
     if (!s || !cam || !tf || !mo || !rgba || tf->n < 2 || !(mo->tol > 0)) return -1;
     int nt = mo->nthreads > 0 ? mo->nthreads : (int)sysconf(_SC_NPROCESSORS_ONLN);
@@ -1765,7 +1830,7 @@ int32_t orc_render_pixels_method(const orc_scene *s, const orc_camera *cam, cons
     pthread_t th[256];
     mjob_t jobs[256];
     for (int t = 0; t < nt; ++t) {
-        jobs[t] = (mjob_t){s, cam, tf, mo, pixels, npix, rgba, 0, t, nt};
+        jobs[t] = (mjob_t){s, cam, tf, mo, pixels, npix, rgba, dp, order_bad, 0, t, nt};
         pthread_create(&th[t], NULL, method_worker, &jobs[t]);
     }
     long long total = 0;

@@ -138,7 +138,13 @@ typedef struct {
 } orc_method_opts;
 int32_t orc_render_pixels_method(const orc_scene *s, const orc_camera *cam, const orc_tf *tf,
                                  const orc_method_opts *mo, const int64_t *pixels, int64_t npix, double *rgba,
-                                 int64_t *rk_steps);
+                                 int64_t *rk_steps, double *dp, int32_t *order_bad);
+/* Eq. (deltaP): 2 |pi_s(g) - pixel centre|_inf in pixels for point g and the
+   pixel (row*width + col) of camera c.  The method mode writes per pixel (when
+   dp / order_bad are not NULL) the largest Delta P of the interior samples and
+   the number of samples whose projection onto the ray lies before the previous
+   one's (the segment's entry and exit included as the first and last). */
+double orc_delta_p(const orc_camera *c, int64_t pixel, const double g[3]);
 /* Convergence study: error of an RK method on the analytic 2-D map.
    method 1 Euler, 2 midpoint, 3 Kutta, 4 classic, 5 3/8-rule, 6 Fehlberg (5th),
    7 implicit Euler. */

@@ -1131,3 +1131,40 @@ def test_render_of_a_constant_derived_field_has_the_closed_form(oracle_lib):
                 continue
             a = 1.0 - math.exp(-kappa * (t1 - t0))
             assert np.abs(res.rgba[pix] - np.concatenate([E[:3] * a, [a]])).max() < 1e-9, (field, pix)
+
+
+# ------------------------------------------------------------------ pixel accuracy
+
+def test_delta_p_closed_forms(oracle_lib):
+    """Eq. (deltaP): points on a pixel's own central ray have Delta P = 0 at every
+    depth; the rays through the pixel's corners give exactly 1, through the
+    neighbouring pixel's centre 2 (square pixels)."""
+    cam = camera_from_angles([0.3, -0.2, 0.1], 4.0, 37.0, 18.0, 64, 48)
+    for pix in (0, 100, 64 * 48 - 1, 23 * 64 + 31):
+        col, row = pix % 64, pix // 64
+        o, d = oracle.camera_ray(cam, col + 0.5, row + 0.5)
+        for t in (0.5, 3.0, 17.0):
+            assert oracle.delta_p(cam, pix, o + t * d) < 1e-10
+        for dx, dy in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            o, d = oracle.camera_ray(cam, col + dx, row + dy)
+            assert abs(oracle.delta_p(cam, pix, o + 2.5 * d) - 1.0) < 1e-10
+        o, d = oracle.camera_ray(cam, col + 1.5, row + 0.5)
+        assert abs(oracle.delta_p(cam, pix, o + 7.0 * d) - 2.0) < 1e-10
+
+
+def test_method_mode_pixel_accuracy(oracle_lib):
+    """The method mode's pixel-accuracy record: root finding puts every sample on
+    the ray (Delta P at rounding level), the adaptive RKF45 at its defaults keeps
+    every sample inside the pixel (Delta P <= 1) in the right depth order, and
+    explicit Euler without the pull back to the ray (c = 0) and with long steps
+    leaves the pixel."""
+    sc = make_config(2)
+    cam = sc.cameras[0]
+    pix = np.arange(0, cam.width * cam.height, 5)
+    _, _, rf = oracle.render_method(sc, cam, sc.tf, pixels=pix, method="rf", pixel_accuracy=True)
+    assert rf["delta_p"].max() < 1e-6 and rf["order_violations"].max() == 0
+    _, _, ode = oracle.render_method(sc, cam, sc.tf, pixels=pix, pixel_accuracy=True)
+    assert 0 < ode["delta_p"].max() <= 1.0 and ode["order_violations"].max() == 0
+    _, _, rk1 = oracle.render_method(sc, cam, sc.tf, pixels=pix, method="rk1", c_perp=0.0, h_max=sc.scale / 8,
+                                     rho_step=10.0, pixel_accuracy=True)
+    assert rk1["delta_p"].max() > 1.0
