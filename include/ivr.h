@@ -135,6 +135,14 @@ typedef struct {
                                       and root its print lacks); every block must
                                       carry one                                 */
 
+/* Stopping rule of the Newton iteration of a root-finding sample (Sec. "Root
+   Finding Based Algorithm"). */
+#define IVR_NEWTON_STOP_TOL 0      /* |phi(p) - g| <= 2e-6 of the scale (FP32) or
+                                      1e-12 (FP64)                              */
+#define IVR_NEWTON_STOP_FRUSTUM 1  /* the paper's pixel-accurate rule: |phi(p) - g|
+                                      at most g's distance to the boundary of the
+                                      pixel's frustum (not below the TOL rule)  */
+
 /* Render options (ivr_default_opts fills the defaults given in brackets). */
 typedef struct {
     int32_t precision;          /* IVR_PRECISION_*                          [FP32] */
@@ -191,6 +199,8 @@ typedef struct {
                                    beyond it are rendered, and a block it cuts is
                                    entered there (an exit without an entry in
                                    front); 0: none                          [0] */
+    int32_t newton_stop;        /* IVR_NEWTON_STOP_*: when a root-finding
+                                   sample's Newton stops                [TOL] */
     int32_t field;              /* IVR_FIELD_*: the value sampled along the ray;
                                    a derived field comes with its exact
                                    gradient (from the Hessian of the maps), so
@@ -210,6 +220,8 @@ typedef struct {
                                             a root-finding sample's or an
                                             implicit Euler step's Newton)        */
 #define IVR_FLAG_DEGENERATE 64u          /* a segment end with singular J_phi     */
+#define IVR_FLAG_DEPTH_ORDER 128u        /* samples out of depth order (ivr_view
+                                            dp_dev given)                        */
 
 /* Counters of one render (filled when a non-NULL ivr_stats* is passed; that
  * forces a stream synchronisation). */
@@ -238,6 +250,9 @@ typedef struct {
     uint64_t mlp_restarts;      /* shrunk entries whose Newton the network seeded */
     uint64_t drift_restarts;    /* samples put back on the ray by Newton (drift_tol) */
     uint64_t restart_fail;      /* of which Newton did not converge               */
+    uint64_t dp_over;           /* interior samples with Delta P > 1 (views with
+                                   dp_dev only)                                   */
+    uint64_t order_violations;  /* samples out of depth order (same)             */
     double ms_fragments, ms_integrate, ms_merge;  /* event times per phase: the
                                    fragment launches with the block sort that
                                    follows them, the integrator launches, the
@@ -304,7 +319,15 @@ ivr_status ivr_render_noalloc(ivr_ctx *ctx, const ivr_camera *cam, const ivr_tra
 /* One view of a batch: camera, transfer function (NULL: the batch's), the model
  * it looks at (index into the models of the last upload) and its caller-owned
  * device outputs, laid out as for ivr_render, plus optional per-pixel flags
- * (width*height uint32 IVR_FLAG_* bits, or NULL). */
+ * (width*height uint32 IVR_FLAG_* bits, or NULL) and an optional per-pixel
+ * pixel-accuracy record (Definition "Pixel-Accurate Approximation of
+ * Geometry"): dp_dev, width*height floats, receives the largest
+ * Delta P = 2 |pi_s(phi(p_i)) - pixel centre|_inf (Eq. (deltaP), in pixels) over
+ * the interior samples p_i of the pixel's segments (0 where there are none),
+ * and the flags receive IVR_FLAG_DEPTH_ORDER where a sample's projection onto
+ * the ray lies before its predecessor's (the entry and exit included).  A batch
+ * with any dp_dev runs an instrumented integrator (scalar field, ODE or RF
+ * interior method; IVR_EINVAL otherwise). */
 typedef struct {
     ivr_camera cam;
     const ivr_transfer_fn *tf;
@@ -312,6 +335,7 @@ typedef struct {
     float *rgba_dev;
     float *depth_dev;
     uint32_t *flags_dev;
+    float *dp_dev;
 } ivr_view;
 
 /* Renders 1..64 views of possibly different sizes and models with the same

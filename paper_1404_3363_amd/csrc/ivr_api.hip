@@ -744,6 +744,7 @@ void ivr_default_opts(ivr_render_opts *o) {
     o->drift_tol = 1e-4;
     o->interior = IVR_INTERIOR_ODE;
     o->field = IVR_FIELD_SCALAR;
+    o->newton_stop = IVR_NEWTON_STOP_TOL;
     o->cut = 0;
     for (int q = 0; q < 3; ++q) o->cut_point[q] = o->cut_normal[q] = 0.0;
     o->near_clip = 0.0;
@@ -1386,6 +1387,9 @@ static ivr_status make_frame(ivr_ctx *c, const ivr_camera *cam, const ivr_transf
             return fail(c, IVR_EINVAL, "von Mises needs a displacement spline on every block");
     }
     fp.field = o.field;
+    if (o.newton_stop != IVR_NEWTON_STOP_TOL && o.newton_stop != IVR_NEWTON_STOP_FRUSTUM)
+        return fail(c, IVR_EINVAL, "unknown newton_stop");
+    fp.newton_stop = o.newton_stop;
     fp.max_newton = o.max_newton_iter;
     fp.scaled = scale;
     fp.scale = (float)scale;
@@ -1485,11 +1489,13 @@ struct HostView {
     int model;
     float *rgba, *depth;
     uint32_t *flags;
+    float *dp;
 };
 struct Batch {
     int n = 0;
     int method = IVR_INTERIOR_ODE;
     int field = IVR_FIELD_SCALAR;
+    bool diag = false;    // some view records the pixel accuracy
     uint32_t n_tiles = 0, n_pixels = 0, class_mask = 0;
     bool fp64 = false, mlp = false, collect = false;
     uint32_t c_cap = 0;   // candidates the fragment launches may record
@@ -1548,10 +1554,14 @@ static ivr_status fill_views(ivr_ctx *c, const HostView *hv, int n, const ivr_re
         r.rgba = hv[v].rgba;
         r.depth = hv[v].depth;
         r.flags = hv[v].flags;
+        r.dp = hv[v].dp;
+        if (hv[v].dp) b.diag = true;
         tiles += (uint64_t)r.tiles_x * ((hv[v].cam->height + th - 1) / th);
         pixels += (uint64_t)hv[v].cam->width * hv[v].cam->height;
         b.class_mask |= M.class_mask;
     }
+    if (b.diag && (b.field != IVR_FIELD_SCALAR || (b.method != IVR_INTERIOR_ODE && b.method != IVR_INTERIOR_RF)))
+        return fail(c, IVR_EINVAL, "the pixel-accuracy record needs the scalar field and the ODE or RF method");
     if (pixels > 0xFFFFFFFFull || tiles > 0x3FFFFFFull)
         return fail(c, IVR_EOVERFLOW, "batch too large for 32-bit pixel and lane indices");
     if (o.cand_per_pixel < 0 || o.cand_per_pixel > kCandCap)
@@ -1612,6 +1622,7 @@ static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const FrameBufs &fb, 
                                hipEvent_t *ev, hipStream_t s) {
     const Model m = device_model(c);
     IVR_HIP(c, launch_clear(fb.qs, fb.ctr, b.collect, fb.pcount, c->npatch, s));
+    if (b.diag) IVR_HIP(c, launch_dp_clear(fb.views, b.n, b.n_pixels, s));
     if (ev) IVR_HIP(c, hipEventRecord(ev[0], s));
     IVR_HIP(c, launch_fragments(b.fp64, b.mlp, m, fb.views, b.n, b.n_tiles, lc, fb.segs, (uint32_t)fb.seg_cap,
                                 fb.seg_kr, fb.pcount, fb.qs, fb.pixseg, fb.mq, fb.ctr, c->n_cu, s));
@@ -1632,8 +1643,8 @@ static ivr_status launch_batch(ivr_ctx *c, const Batch &b, const FrameBufs &fb, 
         ia.pcur = fb.pcur;
         ia.max_cp = c->cls_max_cp[k];
         ia.max_tab = c->cls_max_tab[k];
-        IVR_HIP(c, launch_integrate(b.fp64, b.method, b.field, k, m, fb.views, b.n, fb.segs, ia, fb.ctr, c->n_cu,
-                                    lc, s));
+        IVR_HIP(c, launch_integrate(b.fp64, b.method, b.field, b.diag, k, m, fb.views, b.n, fb.segs, ia, fb.ctr,
+                                    c->n_cu, lc, s));
     }
     if (ev) IVR_HIP(c, hipEventRecord(ev[2], s));
     IVR_HIP(c, launch_merge(fb.views, b.n, b.n_pixels, fb.pixseg, fb.segs, b.fp64, fb.qs, fb.totals, s));
@@ -1805,7 +1816,7 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
     std::vector<HostView> hv(n_views);
     for (int v = 0; v < n_views; ++v) {
         hv[v] = {&views[v].cam, views[v].tf ? views[v].tf : tf, views[v].model, views[v].rgba_dev,
-                 views[v].depth_dev, views[v].flags_dev};
+                 views[v].depth_dev, views[v].flags_dev, views[v].dp_dev};
         if (!hv[v].tf) return fail(c, IVR_EINVAL, "a view has no transfer function");
     }
     ivr_status st;
@@ -1821,7 +1832,8 @@ ivr_status ivr_render_batch(ivr_ctx *c, const ivr_view *views, int32_t n_views,
     if (st != IVR_OK) return st;
     // the graph holds every kernel argument except what the view table carries
     // (cameras, transfer functions, output pointers): key it by the rest
-    std::vector<int64_t> key = {(int64_t)c->generation, b.n, b.fp64, b.mlp, b.method, b.field, (int64_t)b.class_mask,
+    std::vector<int64_t> key = {(int64_t)c->generation, b.n, b.fp64, b.mlp, b.method, b.field, b.diag,
+                                (int64_t)b.class_mask,
                                 c->lc.tile_w, c->lc.xcd_chunk, c->lc.int_block, c->lc.int_waves_cu,
                                 (int64_t)b.c_cap};
     for (int v = 0; v < n_views; ++v) {
@@ -1866,7 +1878,7 @@ ivr_status ivr_autotune(ivr_ctx *c, const ivr_view *views, int32_t n_views, cons
     std::vector<HostView> hv(n_views);
     for (int v = 0; v < n_views; ++v) {
         hv[v] = {&views[v].cam, views[v].tf ? views[v].tf : tf, views[v].model, views[v].rgba_dev,
-                 views[v].depth_dev, views[v].flags_dev};
+                 views[v].depth_dev, views[v].flags_dev, views[v].dp_dev};
         if (!hv[v].tf) return fail(c, IVR_EINVAL, "a view has no transfer function");
     }
     // time a shape: best of `reps` batches, per phase, from the stats events

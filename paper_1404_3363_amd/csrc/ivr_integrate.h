@@ -180,6 +180,42 @@ __device__ __forceinline__ R derived_field(const PatchView<R> &pv, const Arrays<
     }
 }
 
+// Distance of point g to the boundary of the frustum of pixel (row*width + col)
+// of view fv: the smallest distance to its four side planes through the eye
+// (Sec. "Root Finding Based Algorithm": the pixel-accurate Newton stop).
+template <typename R>
+__device__ __forceinline__ R frustum_distance(const FrameParams &fv, uint32_t pixel, const R (&g)[3]) {
+    const int px = (int)(pixel % (uint32_t)fv.width), py = (int)(pixel / (uint32_t)fv.width);
+    const R th = R(fv.tan_half), as = R(fv.aspect);
+    R v[3], fw[3], rt[3], up[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v[c] = g[c] - R(fv.eye[c]);
+        fw[c] = R(fv.fwd[c]);
+        rt[c] = R(fv.right[c]);
+        up[c] = R(fv.up[c]);
+    }
+    R dmin = R(INFINITY);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        // e = 0, 1: the planes x = const (they contain up); 2, 3: y = const
+        R a[3], n[3];
+        if (e < 2) {
+            const R xe = (R(2) * R(px + e) / R(fv.width) - R(1)) * th * as;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[c] = fw[c] + xe * rt[c];
+            cross3(a, up, n);
+        } else {
+            const R ye = (R(1) - R(2) * R(py + e - 2) / R(fv.height)) * th;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[c] = fw[c] + ye * up[c];
+            cross3(rt, a, n);
+        }
+        dmin = fmin(dmin, fabs(dot3(v, n)) / sqrt(dot3(n, n)));
+    }
+    return dmin;
+}
+
 // Three waves per SIMD: the FP32 kernels fit in 168 VGPRs without spilling.
 //
 // Each workgroup works on one block at a time: with LDS, the block's control
@@ -189,7 +225,8 @@ __device__ __forceinline__ R derived_field(const PatchView<R> &pv, const Arrays<
 // its waves refill their lanes from that block's cursor (one atomic per wave),
 // and when the block has no segments left it drains and moves on to the next
 // block with work, cyclically in class order.
-template <int P, bool RAT, typename R, bool LDS, int METHOD, int FIELD = 0>
+// DIAG: the pixel-accuracy record of the views with a dp buffer.
+template <int P, bool RAT, typename R, bool LDS, int METHOD, int FIELD = 0, bool DIAG = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_integrate(
     Model m, const ViewRec *views, int n_views, Seg<R> *segs, const u32 *order, const u32 *pperm,
     int q_begin, int q_end, const u32 *pbase, const u32 *pcount, u32 *pcur, int max_cp, u64 *ctr) {
@@ -249,6 +286,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     int shrink = 0, newton_it = 0;
     R delta = 0, rho_in = 0;
     u32 fl = 0;
+    // root finding with the frustum stop: the current sample's tolerance
+    R rf_tol = R(0);
+    // pixel-accuracy record (DIAG): the segment's largest Delta P, the ray
+    // parameter of its last sample (the entry's first) and of its exit, pixel
+    float dg_dp = 0.f;
+    R dg_t = R(0), dg_tout = R(0);
+    u32 dg_pix = 0, c_dpo = 0, c_ord = 0;
     // frequent events are counted per lane and summed per wave at the end; rare
     // ones (iteration cap, singular ends, restarts) with one atomic each
     u32 c_steps = 0, c_rej = 0, c_samp = 0, c_w = 0, c_fp64 = 0, c_sub = 0;
@@ -333,6 +377,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     hmin = sizeof(R) == 4 ? R(vls[vid].h_min) : R(fv.h_mind);
                     vscale = sizeof(R) == 4 ? R(vls[vid].scale) : R(fv.scaled);
                     L = sg.t_out - sg.t_in;
+                    if constexpr (DIAG) {
+                        dg_dp = 0.f;
+                        dg_t = R(sg.t_in);
+                        dg_tout = R(sg.t_out);
+                        dg_pix = sg.pixel;
+                    }
                     s = R(0);
                     h = L < hmax ? L : hmax;
                     rho_out = sg.rho_out;
@@ -404,6 +454,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             rho_cur = derived_field<P, RAT, FIELD, R>(pv, ar, disp_arr, p, grho, Jd);
         }
         const R m_cur = dot3(grho, k1);
+        // Eq. (deltaP) and the depth order for a sample at phi(p) = xg (DIAG)
+        auto diag_sample = [&](const R (&xg)[3]) __attribute__((always_inline)) {
+            if constexpr (DIAG) {
+                const FrameParams &fv = views[vid].fp;
+                R v[3], z = R(0), sx = R(0), sy = R(0), t = R(0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    v[c] = xg[c] - R(fv.eye[c]);
+                    z += v[c] * R(fv.fwd[c]);
+                    sx += v[c] * R(fv.right[c]);
+                    sy += v[c] * R(fv.up[c]);
+                    t += v[c] * d[c];
+                }
+                const R th = R(fv.tan_half), as = R(fv.aspect);
+                const R X = (sx / (z * th * as) + R(1)) * R(0.5) * R(fv.width);
+                const R Y = (R(1) - sy / (z * th)) * R(0.5) * R(fv.height);
+                const R cx = R(dg_pix % (u32)fv.width) + R(0.5), cy = R(dg_pix / (u32)fv.width) + R(0.5);
+                const R dp = R(2) * fmax(fabs(X - cx), fabs(Y - cy));
+                dg_dp = fmaxf(dg_dp, float(dp));
+                c_dpo += dp > R(1) ? 1u : 0u;
+                if (t < dg_t) {
+                    fl |= IVR_FLAG_DEPTH_ORDER;
+                    ++c_ord;
+                }
+                dg_t = t;
+            }
+        };
         // Root finding: the next sample.  Its step follows the same bounds as the
         // ODE's (h_max, rho's change); its preimage is predicted along W = J^-1 d
         // and found by Newton (shrink -3); the last interval closes with the exit.
@@ -432,6 +509,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             h_prev = hh;
             shrink = -3;
             newton_it = 0;
+            if (fp.newton_stop == IVR_NEWTON_STOP_FRUSTUM) rf_tol = frustum_distance(views[vid].fp, segs[sid].pixel, gin);
             if (++iters >= 20000) {
                 count_rare(C_RK_ITER_CAP);
                 fl |= IVR_FLAG_ITER_CAP;
@@ -444,10 +522,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             // converged the point is sampled (again)
             const R tolx = (sizeof(R) == 4 ? R(2e-6) : R(1e-12)) * vscale;
             if (METHOD == kRootFinding && shrink == -3) {
-                if (res2 <= tolx * tolx || newton_it >= 12 || !isfinite(k1[0] + k1[1] + k1[2])) {
+                // the frustum stop: within the distance of the sample to the
+                // boundary of its pixel's frustum (never below tolx)
+                const R tol_s = fp.newton_stop == IVR_NEWTON_STOP_FRUSTUM ? fmax(tolx, rf_tol) : tolx;
+                if (res2 <= tol_s * tol_s || newton_it >= 12 || !isfinite(k1[0] + k1[1] + k1[2])) {
                     // the sample: rho and d rho/ds = grad rho . J^-1 d at the preimage
                     // (where Newton stopped if it did not converge: counted, flagged)
-                    if (!(res2 <= tolx * tolx)) {
+                    if (!(res2 <= tol_s * tol_s)) {
                         fl |= IVR_FLAG_RESTART_FAIL;
                         count_rare(C_RESTART_FAIL);
                     }
@@ -455,6 +536,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     const R m_t = dot3(grho, wt);
                     composite(fp, views[vid].fp, vls[vid], rho_prev, m_prev, rho_cur, m_t, h_prev, C, A, c_sub);
                     ++c_samp;
+                    diag_sample(xw);
                     rho_prev = rho_cur;
                     m_prev = m_t;
                     if (A >= R(1) - early || (fl & kEndSample)) done = true;
@@ -592,6 +674,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             } else {
                 composite(fp, views[vid].fp, vls[vid], rho_prev, m_prev, rho_cur, m_cur, h_prev, C, A, c_sub);
                 ++c_samp;
+                diag_sample(xw);
                 rho_prev = rho_cur;
                 m_prev = m_cur;
                 pending = false;
@@ -816,6 +899,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             // record (read at the refill; only its pixel is needed after this)
             *reinterpret_cast<float4 *>(segs + sid) = make_float4(float(C[0]), float(C[1]), float(C[2]), float(A));
             active = false;
+            if constexpr (DIAG) {
+                if (dg_tout < dg_t) {   // the exit before the last sample
+                    fl |= IVR_FLAG_DEPTH_ORDER;
+                    ++c_ord;
+                }
+                float *dpv = views[vid].dp;
+                if (dpv) atomicMax(reinterpret_cast<unsigned int *>(dpv + dg_pix), __float_as_uint(dg_dp));
+            }
             fl &= kPublicFlags;
             if (fl) {
                 uint32_t *fv = views[vid].flags;
@@ -832,13 +923,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         flush_counter(ctr, C_W_EVALS, c_w);
         flush_counter(ctr, C_FP64_SOLVES, c_fp64);
         flush_counter(ctr, C_SUBSAMPLES, c_sub);
+        if constexpr (DIAG) {
+            flush_counter(ctr, C_DP_OVER, c_dpo);
+            flush_counter(ctr, C_ORDER_BAD, c_ord);
+        }
     }
 }
 
 // LDS budget of the staged block per integrator workgroup.
 constexpr size_t kLdsBlockBytes = 48 * 1024;
 
-template <int P, bool RAT, typename R, bool LDS, int METHOD, int FIELD = 0>
+template <int P, bool RAT, typename R, bool LDS, int METHOD, int FIELD = 0, bool DIAG = false>
 static hipError_t launch_integrate_t(const Model &m, const ViewRec *views, int n_views, const void *segs,
                                      const IntegrateArgs &a, unsigned long long *ctr,
                                      int n_cu, const LaunchCfg &lc, hipStream_t st) {
@@ -849,11 +944,11 @@ static hipError_t launch_integrate_t(const Model &m, const ViewRec *views, int n
                             : 0);
     const int block = lc.int_block;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<P, RAT, R, LDS, METHOD, FIELD>, block, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<P, RAT, R, LDS, METHOD, FIELD, DIAG>, block, lds) !=
             hipSuccess || nb < 1)
         nb = 1;
     if (lc.int_waves_cu > 0) nb = std::min(nb, std::max(1, lc.int_waves_cu / (block / 64)));
-    hipLaunchKernelGGL((k_integrate<P, RAT, R, LDS, METHOD, FIELD>), dim3(n_cu * nb), dim3(block), lds, st, m, views,
+    hipLaunchKernelGGL((k_integrate<P, RAT, R, LDS, METHOD, FIELD, DIAG>), dim3(n_cu * nb), dim3(block), lds, st, m, views,
                        n_views, (Seg<R> *)segs, a.order, a.pperm, a.q_begin, a.q_end, a.pbase,
                        a.pcount, a.pcur, LDS ? a.max_cp : 0, ctr);
     return hipGetLastError();

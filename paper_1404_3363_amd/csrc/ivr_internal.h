@@ -18,12 +18,16 @@ hipError_t launch_block_sort(const QueueState *qs, uint32_t seg_cap, const uint2
 
 // field: IVR_FIELD_*; the derived fields (with the ODE or root-finding
 // interior method only) run launch_integrate_field, in their own unit.
-hipError_t launch_integrate(bool fp64, int method, int field, int klass, const Model &m, const ViewRec *views,
-                            int n_views, void *segs, const IntegrateArgs &a, unsigned long long *ctr, int n_cu,
-                            const LaunchCfg &lc, hipStream_t st);
-hipError_t launch_integrate_field(bool fp64, int method, int field, int klass, const Model &m,
+// diag: the instrumented integrator that records the pixel accuracy (views'
+// dp buffers; scalar field, ODE or RF), also in that unit.
+hipError_t launch_integrate(bool fp64, int method, int field, bool diag, int klass, const Model &m,
+                            const ViewRec *views, int n_views, void *segs, const IntegrateArgs &a,
+                            unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st);
+hipError_t launch_integrate_field(bool fp64, int method, int field, bool diag, int klass, const Model &m,
                                   const ViewRec *views, int n_views, void *segs, const IntegrateArgs &a,
                                   unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st);
+// zeroes the views' dp buffers (before an instrumented integrator)
+hipError_t launch_dp_clear(const ViewRec *views, int n_views, uint32_t n_pixels, hipStream_t st);
 
 hipError_t launch_merge(const ViewRec *views, int n_views, uint32_t n_pixels, const uint2 *pixseg,
                         const void *segs, bool fp64, const QueueState *qs, uint32_t *totals, hipStream_t st);

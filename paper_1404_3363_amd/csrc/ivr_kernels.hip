@@ -1000,11 +1000,12 @@ hipError_t launch_block_sort(const QueueState *qs, uint32_t seg_cap, const uint2
     return hipGetLastError();
 }
 
-hipError_t launch_integrate(bool fp64, int method, int field, int klass, const Model &m, const ViewRec *views,
-                            int n_views, void *segs, const IntegrateArgs &a, unsigned long long *ctr, int n_cu,
-                            const LaunchCfg &lc, hipStream_t st) {
-    if (field != IVR_FIELD_SCALAR)
-        return launch_integrate_field(fp64, method, field, klass, m, views, n_views, segs, a, ctr, n_cu, lc, st);
+hipError_t launch_integrate(bool fp64, int method, int field, bool diag, int klass, const Model &m,
+                            const ViewRec *views, int n_views, void *segs, const IntegrateArgs &a,
+                            unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st) {
+    if (field != IVR_FIELD_SCALAR || diag)
+        return launch_integrate_field(fp64, method, field, diag, klass, m, views, n_views, segs, a, ctr, n_cu, lc,
+                                      st);
     switch (klass) {
     case 0: return launch_integrate_pr<1, false>(fp64, method, m, views, n_views, segs, a, ctr, n_cu, lc, st);
     case 1: return launch_integrate_pr<1, true>(fp64, method, m, views, n_views, segs, a, ctr, n_cu, lc, st);
@@ -1014,6 +1015,20 @@ hipError_t launch_integrate(bool fp64, int method, int field, int klass, const M
     case 5: return launch_integrate_pr<3, true>(fp64, method, m, views, n_views, segs, a, ctr, n_cu, lc, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+// The views' pixel-accuracy records start at zero (no samples: Delta P 0).
+__global__ __launch_bounds__(256) void k_dp_clear(const ViewRec *views, int n_views, u32 n_pixels) {
+    const u32 g = blockIdx.x * 256u + threadIdx.x;
+    if (g >= n_pixels) return;
+    const int v = view_of_pixel(views, n_views, g);
+    float *dp = views[v].dp;
+    if (dp) dp[g - views[v].pix_begin] = 0.f;
+}
+
+hipError_t launch_dp_clear(const ViewRec *views, int n_views, uint32_t n_pixels, hipStream_t st) {
+    hipLaunchKernelGGL(k_dp_clear, dim3((n_pixels + 255) / 256), dim3(256), 0, st, views, n_views, n_pixels);
+    return hipGetLastError();
 }
 
 hipError_t launch_merge(const ViewRec *views, int n_views, uint32_t n_pixels, const uint2 *pixseg,

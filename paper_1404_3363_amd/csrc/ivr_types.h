@@ -118,7 +118,7 @@ enum Counter : int {
     C_RAYS = 0, C_SEGMENTS, C_FRAGMENTS, C_ANOMALIES, C_FRAG_OVF, C_SEG_OVF, C_BOX_TESTS,
     C_FACE_NEWTON, C_FACE_NEWTON_ITER, C_FP64_POLISH, C_RK_STEPS, C_RK_REJECTED, C_SAMPLES,
     C_W_EVALS, C_FP64_SOLVES, C_RK_ITER_CAP, C_MLP_QUERIES, C_SUBSAMPLES, C_DEGENERATE,
-    C_MLP_RESTARTS, C_DRIFT_RESTARTS, C_RESTART_FAIL, C_COUNT
+    C_MLP_RESTARTS, C_DRIFT_RESTARTS, C_RESTART_FAIL, C_DP_OVER, C_ORDER_BAD, C_COUNT
 };
 
 // Bookkeeping written by the fragment kernel.
@@ -186,6 +186,7 @@ struct FrameParams {
     int32_t n_super, max_frag, max_newton, collect, hermite, seed_mode;
     int32_t interior;               // IVR_INTERIOR_*
     int32_t field;                  // IVR_FIELD_*
+    int32_t newton_stop;            // IVR_NEWTON_STOP_*
     // Sec. "Cutting and Near Clip Planes": cutting plane (cut != 0) keeping
     // cut_n . (g - g0) >= 0, with cut_s0 = cut_n . (eye - g0) for this view; near
     // plane near_clip in front of the eye along fwd (0: none)
@@ -213,6 +214,8 @@ struct alignas(16) ViewRec {
     float *rgba;                        // width*height*4, caller-owned
     float *depth;                       // width*height or null
     uint32_t *flags;                    // width*height IVR_FLAG_* bits or null
+    float *dp;                          // width*height largest Delta P, or null
+    void *pad2;
 };
 
 // What the integrator keeps per view in LDS: on interval k (x[k] <= n < x[k+1])

@@ -17,11 +17,12 @@ LIB_PATH = os.path.join(_HERE, "libivr.so")
 
 IVR_OK, IVR_EINVAL, IVR_ENOMEM, IVR_EDEVICE, IVR_ESTATE, IVR_EOVERFLOW = 0, -1, -2, -3, -4, -5
 FLAGS = {"anomaly": 1, "fragment_overflow": 2, "segment_overflow": 4, "iter_cap": 8,
-         "drift_restart": 16, "restart_fail": 32, "degenerate": 64}
+         "drift_restart": 16, "restart_fail": 32, "degenerate": 64, "depth_order": 128}
 PRECISION = {"fp32": 0, "fp64": 1}
 SEED = {"plain": 0, "mlp": 1, "box": 2}
 RHO_INTERP = {"linear": 0, "hermite": 1}
 FIELDS = {"scalar": 0, "param_quality": 1, "von_mises": 2}
+NEWTON_STOP = {"tol": 0, "frustum": 1}
 INTERIOR = {"ode": 0, "rf": 1, "rk1": 2, "rk2": 3, "rk3": 4, "rk4": 5, "rk4_38": 6, "rkf5": 7, "irk1": 8}
 
 EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_upload_models",
@@ -60,12 +61,13 @@ class RenderOpts(C.Structure):
                 ("cand_per_pixel", C.c_int32), ("det_singular", C.c_double),
                 ("drift_tol", C.c_double), ("interior", C.c_int32), ("cut", C.c_int32),
                 ("cut_point", C.c_double * 3), ("cut_normal", C.c_double * 3), ("near_clip", C.c_double),
-                ("field", C.c_int32)]
+                ("newton_stop", C.c_int32), ("field", C.c_int32)]
 
 
 class ViewDesc(C.Structure):
     _fields_ = [("cam", CameraDesc), ("tf", C.c_void_p), ("model", C.c_int32),
-                ("rgba_dev", C.c_void_p), ("depth_dev", C.c_void_p), ("flags_dev", C.c_void_p)]
+                ("rgba_dev", C.c_void_p), ("depth_dev", C.c_void_p), ("flags_dev", C.c_void_p),
+                ("dp_dev", C.c_void_p)]
 
 
 class TuneReport(C.Structure):
@@ -78,7 +80,7 @@ STAT_FIELDS = ["rays", "segments", "fragments", "anomalies", "fragment_overflow"
                "segment_overflow", "box_tests", "face_newton", "face_newton_iter",
                "fp64_polish_iter", "rk_steps", "rk_rejected", "samples", "w_evals",
                "fp64_solves", "rk_iter_cap", "mlp_queries", "subsamples", "degenerate",
-               "mlp_restarts", "drift_restarts", "restart_fail"]
+               "mlp_restarts", "drift_restarts", "restart_fail", "dp_over", "order_violations"]
 
 
 class MlpOpts(C.Structure):
@@ -178,6 +180,8 @@ def default_opts(**kw) -> RenderOpts:
             v = INTERIOR[v]
         if k == "field" and isinstance(v, str):
             v = FIELDS[v]
+        if k == "newton_stop" and isinstance(v, str):
+            v = NEWTON_STOP[v]
         if k == "cut_plane":   # (point, normal) or None
             o.cut = 0 if v is None else 1
             if v is not None:
@@ -352,7 +356,7 @@ class Renderer:
                                  "on the renderer's device")
         return rgba, depth
 
-    def _batch_args(self, views, tf, opts, kw, outputs, flags=False):
+    def _batch_args(self, views, tf, opts, kw, outputs, flags=False, pixel_accuracy=False):
         if opts is None:
             opts = default_opts(**kw)
         elif kw:
@@ -361,13 +365,17 @@ class Renderer:
         for i, v in enumerate(views):
             cam, vtf, model = v[0], v[1] if len(v) > 1 else None, v[2] if len(v) > 2 else 0
             rgba, depth = self._outputs(cam, *(outputs[i][:2] if outputs else (None, None)))
+            item = [rgba, depth]
             if flags:
                 fl = self.torch.empty((cam.height, cam.width), dtype=self.torch.int32,
                                       device=rgba.device)
                 descs[i].flags_dev = fl.data_ptr()
-                outs.append((rgba, depth, fl))
-            else:
-                outs.append((rgba, depth))
+                item.append(fl)
+            if pixel_accuracy:
+                dpb = self.torch.empty((cam.height, cam.width), dtype=self.torch.float32, device=rgba.device)
+                descs[i].dp_dev = dpb.data_ptr()
+                item.append(dpb)
+            outs.append(tuple(item))
             d = descs[i]
             d.cam = camera_desc(cam)
             if vtf is not None:
@@ -381,11 +389,12 @@ class Renderer:
         return opts, descs, outs, btf, keep
 
     def render_batch(self, views, tf=None, opts: Optional[RenderOpts] = None, outputs=None,
-                     stats: bool = False, flags: bool = False, **kw):
+                     stats: bool = False, flags: bool = False, pixel_accuracy: bool = False, **kw):
         """views: sequence of (camera, transfer_function or None, model index).
-        Returns [(rgba, depth)] per view, [(rgba, depth, flags)] with flags (int32
-        IVR_FLAG_* bits per pixel), and the batch counters with stats."""
-        opts, descs, outs, btf, keep = self._batch_args(views, tf, opts, kw, outputs, flags)
+        Returns [(rgba, depth)] per view, plus flags (int32 IVR_FLAG_* bits per
+        pixel) with flags and the per-pixel largest Delta P (float) with
+        pixel_accuracy, in that order, and the batch counters with stats."""
+        opts, descs, outs, btf, keep = self._batch_args(views, tf, opts, kw, outputs, flags, pixel_accuracy)
         st = Stats() if stats else None
         rc = self.lib.ivr_render_batch(self.ctx, descs, len(views),
                                        C.byref(btf.desc) if btf is not None else None,

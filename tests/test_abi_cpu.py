@@ -70,9 +70,9 @@ def test_struct_layouts_match_header():
     from paper_1404_3363_amd import ivr
     assert ctypes.sizeof(ivr.PatchDesc) == 6 * 4 + 3 * 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(ivr.CameraDesc) == 10 * 8 + 8
-    assert ctypes.sizeof(ivr.Stats) == len(ivr.STAT_FIELDS) * 8 + 3 * 8 == 22 * 8 + 3 * 8
+    assert ctypes.sizeof(ivr.Stats) == len(ivr.STAT_FIELDS) * 8 + 3 * 8 == 24 * 8 + 3 * 8
     # ivr_view: camera, tf pointer, model (padded), three device pointers
-    assert ctypes.sizeof(ivr.ViewDesc) == 88 + 8 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(ivr.ViewDesc) == 88 + 8 + 8 + 8 + 8 + 8 + 8
     assert ivr.ViewDesc.model.offset == 96 and ivr.ViewDesc.rgba_dev.offset == 104
     assert ctypes.sizeof(ivr.TuneReport) == 6 * 4 + 32 * 8 + 2 * 8
 

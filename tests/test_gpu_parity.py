@@ -932,3 +932,74 @@ def test_derived_fields_closed_form_and_errors(renderer):
     renderer.upload(sc.patches)
     with pytest.raises(IvrError):
         renderer.render(cam, make_config(1).tf, field="param_quality", interior="rk2")
+
+
+# ------------------------------------------------------------------ pixel accuracy (Definition, Eq. (deltaP))
+
+def _render_dp(r, sc, cam, tf=None, **kw):
+    import torch
+    r.upload(sc.patches)
+    outs, st = r.render_batch([(cam, tf or sc.tf, 0)], stats=True, flags=True, pixel_accuracy=True, **kw)
+    torch.cuda.synchronize()
+    rgba, depth, fl, dp = outs[0]
+    return (rgba.cpu().numpy().reshape(-1, 4).astype(np.float64), depth.cpu().numpy().reshape(-1),
+            fl.cpu().numpy().reshape(-1), dp.cpu().numpy().reshape(-1).astype(np.float64), st)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_pixel_accuracy_record_follows_the_method_mode(renderer, k):
+    """The instrumented integrator's per-pixel largest Delta P (Eq. (deltaP)) of the
+    interior samples, in FP64 with the drift check off, equals the oracle method
+    mode's for the same method (adaptive RKF45) to binary32 rounding, and neither
+    finds a sample out of depth order; the image is the one the plain integrator
+    gives.  Root finding puts the samples on the ray (Delta P at rounding level)."""
+    sc = make_config(k)
+    cam = sc.cameras[0]
+    tol = 1e-6 if k == 1 else 1e-5
+    img, depth, fl, dp, st = _render_dp(renderer, sc, cam, precision="fp64", rk_tol=tol, drift_tol=0.0)
+    plain, _, _ = _render(renderer, sc.patches, cam, sc.tf, precision="fp64", rk_tol=tol, drift_tol=0.0)
+    _, _, rec = oracle.render_method(sc, cam, sc.tf, rk_tol=tol, pixel_accuracy=True)
+    dd = float(np.abs(dp - rec["delta_p"]).max())
+    print(f"[pixel] config{k} ODE fp64: max Delta P gpu {dp.max():.3e} oracle {rec['delta_p'].max():.3e}, "
+          f"|difference| {dd:.2e}; samples over 1: {st['dp_over']}, order violations {st['order_violations']}",
+          flush=True)
+    assert dd <= 1e-6 * max(1.0, float(dp.max()))
+    assert st["order_violations"] == 0 and rec["order_violations"].max() == 0 and not (fl & 128).any()
+    assert np.abs(img - plain).max() == 0.0
+    _, _, _, dp_rf, st_rf = _render_dp(renderer, sc, cam, precision="fp64", interior="rf")
+    print(f"[pixel] config{k} RF fp64: max Delta P {dp_rf.max():.2e}", flush=True)
+    assert dp_rf.max() < 1e-6 and st_rf["dp_over"] == 0
+
+
+def test_default_render_is_pixel_accurate(renderer):
+    """The default FP32 render of the bent beam (config 3, 480x270): every interior
+    sample projects into its pixel (Delta P <= 1) in depth order."""
+    sc = make_config(3, 480, 270)
+    cam = sc.cameras[0]
+    img, depth, fl, dp, st = _render_dp(renderer, sc, cam)
+    print(f"[pixel] config3 fp32 defaults: max Delta P {dp.max():.3e}, 99.9th percentile "
+          f"{np.percentile(dp, 99.9):.3e}, samples over 1: {st['dp_over']}, order violations "
+          f"{st['order_violations']}", flush=True)
+    assert dp.max() <= 1.0 and st["dp_over"] == 0 and st["order_violations"] == 0
+
+
+def test_frustum_newton_stop(renderer):
+    """Root finding with the paper's pixel-accurate Newton stop (residual at most the
+    sample's distance to its pixel frustum's boundary): every sample lies in its
+    pixel (Delta P <= 1), with fewer Newton iterations than the fixed tolerance;
+    the image difference from the fixed-tolerance render is reported.  The
+    instrumented integrator is refused for a fixed-step method."""
+    from paper_1404_3363_amd import IvrError
+    sc = make_config(3, 480, 270)
+    cam = sc.cameras[0]
+    img_t, _, _, dp_t, st_t = _render_dp(renderer, sc, cam, interior="rf")
+    img_f, depth, _, dp_f, st_f = _render_dp(renderer, sc, cam, interior="rf", newton_stop="frustum")
+    pix = _sample(cam, depth, 384, 128, 431)
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    print(f"[pixel] RF tolerance stop: evaluations {st_t['w_evals']}, max Delta P {dp_t.max():.2e}, "
+          f"max err {np.abs(img_t[pix] - ref.rgba).max():.2e} | frustum stop: evaluations {st_f['w_evals']}, "
+          f"max Delta P {dp_f.max():.2e}, max err {np.abs(img_f[pix] - ref.rgba).max():.2e}", flush=True)
+    assert dp_f.max() <= 1.0 and st_f["dp_over"] == 0
+    assert st_f["w_evals"] < st_t["w_evals"]
+    with pytest.raises(IvrError):
+        _render_dp(renderer, sc, cam, interior="rk2")
