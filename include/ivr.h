@@ -425,6 +425,26 @@ ivr_status ivr_mlp_infer(ivr_ctx *ctx, const int32_t *patch, const float *x, int
  * forgets them.  At most 4096 renders are kept (IVR_EOVERFLOW past that). */
 ivr_status ivr_phase_times(ivr_ctx *ctx, double *ms_out, int32_t cap, int32_t *n_out);
 
+/* Summary of an image comparison. */
+typedef struct {
+    double max;                 /* largest per-pixel difference                  */
+    double mean;                /* mean over the pixels                          */
+    uint64_t over;              /* pixels whose difference exceeds the threshold */
+} ivr_delta_e_summary;
+
+/* Image quality as the paper measures it: the CIE's year-2000 colour difference
+ * (CIEDE2000, CIE 142-2001; 1 is a just noticeable difference, the paper
+ * accepts up to 5) between two premultiplied RGBA device images of n_pixels
+ * (4 floats each, as ivr_render writes them), each composited over the
+ * background colour (3 values in [0,1]; NULL: white) and read as sRGB
+ * (IEC 61966-2-1) with the D65 white, in FP64 on the device.  de_dev (device,
+ * n_pixels floats, or NULL) receives the per-pixel difference; *summary (host,
+ * or NULL) the largest, the mean and the count above `threshold`, which waits
+ * for the stream.  IVR_EINVAL for a NULL image or n_pixels < 0. */
+ivr_status ivr_delta_e2000(ivr_ctx *ctx, const float *rgba_a_dev, const float *rgba_b_dev, int64_t n_pixels,
+                           const double *background, double threshold, float *de_dev,
+                           ivr_delta_e_summary *summary);
+
 /* Device memory the context holds: the uploaded model (control nets, boxes,
  * basis tables) and the frame buffers, which are sized from counts (segment
  * slots at 2.5 per pixel or 1.2 times the most per pixel a render needed,

@@ -32,6 +32,7 @@ struct ivr_ctx {
     float *d_rho32 = nullptr;
     double4 *d_cp64 = nullptr;
     double *d_rho64 = nullptr;
+    DeltaESum *d_desum = nullptr;         // image-comparison summary (ivr_delta_e2000)
     float4 *d_disp32 = nullptr;           // displacement (w u, w) per control point, or null
     double4 *d_disp64 = nullptr;
     bool all_disp = false;                // every block carries a displacement spline
@@ -853,6 +854,7 @@ void ivr_destroy(ivr_ctx *c) {
     if (c->h_views) (void)hipHostFree(c->h_views);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->h_totals) (void)hipHostFree(c->h_totals);
+    if (c->d_desum) (void)hipFree(c->d_desum);
     if (c->views_copied) (void)hipEventDestroy(c->views_copied);
     if (c->capture) (void)hipStreamDestroy(c->capture);
     for (auto &e : c->ev)
@@ -1946,6 +1948,35 @@ ivr_status ivr_autotune(ivr_ctx *c, const ivr_view *views, int32_t n_views, cons
     rep.int_waves_cu = best.int_waves_cu;
     rep.ms_after = bf + bi;
     if (report) *report = rep;
+    c->err.clear();
+    return IVR_OK;
+}
+
+ivr_status ivr_delta_e2000(ivr_ctx *c, const float *a, const float *b, int64_t n, const double *background,
+                           double threshold, float *de_dev, ivr_delta_e_summary *summary) {
+    if (!c) return IVR_EINVAL;
+    if (!a || !b || n < 0) return fail(c, IVR_EINVAL, "images are NULL or n_pixels < 0");
+    if (summary) *summary = ivr_delta_e_summary{0.0, 0.0, 0};
+    if (n == 0) return IVR_OK;
+    const double bg[3] = {background ? background[0] : 1.0, background ? background[1] : 1.0,
+                          background ? background[2] : 1.0};
+    if (summary) {
+        if (!c->d_desum && hipMalloc((void **)&c->d_desum, sizeof(DeltaESum)) != hipSuccess)
+            return fail(c, IVR_ENOMEM, "device allocation failed");
+        IVR_HIP(c, hipMemsetAsync(c->d_desum, 0, sizeof(DeltaESum), c->stream));
+    }
+    IVR_HIP(c, launch_delta_e(a, b, (uint64_t)n, bg, threshold, de_dev, summary ? c->d_desum : nullptr, c->n_cu,
+                              c->stream));
+    if (summary) {
+        DeltaESum h;
+        IVR_HIP(c, hipMemcpyAsync(&h, c->d_desum, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        IVR_HIP(c, hipStreamSynchronize(c->stream));
+        float mx;
+        std::memcpy(&mx, &h.max_bits, sizeof mx);
+        summary->max = mx;
+        summary->mean = h.sum / (double)n;
+        summary->over = h.over;
+    }
     c->err.clear();
     return IVR_OK;
 }

@@ -26,6 +26,10 @@ hipError_t launch_integrate(bool fp64, int method, int field, bool diag, int kla
 hipError_t launch_integrate_field(bool fp64, int method, int field, bool diag, int klass, const Model &m,
                                   const ViewRec *views, int n_views, void *segs, const IntegrateArgs &a,
                                   unsigned long long *ctr, int n_cu, const LaunchCfg &lc, hipStream_t st);
+// CIEDE2000 of two premultiplied RGBA images over bg (per pixel into out if
+// given; the summary accumulated into *sum, which the caller clears)
+hipError_t launch_delta_e(const float *a, const float *b, uint64_t n, const double (&bg)[3], double threshold,
+                          float *out, DeltaESum *sum, int n_cu, hipStream_t st);
 // zeroes the views' dp buffers (before an instrumented integrator)
 hipError_t launch_dp_clear(const ViewRec *views, int n_views, uint32_t n_pixels, hipStream_t st);
 

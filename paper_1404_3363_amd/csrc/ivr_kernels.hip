@@ -1017,6 +1017,116 @@ hipError_t launch_integrate(bool fp64, int method, int field, bool diag, int kla
     }
 }
 
+// ---------------------------------------------------------------- image comparison
+// CIEDE2000 colour difference (CIE 142-2001) of two premultiplied RGBA images
+// composited over a background, read as sRGB (IEC 61966-2-1), in FP64: the
+// measure the paper compares renders with (1 just noticeable, 5 accepted).
+__device__ __forceinline__ void srgb_lab(const float4 px, const double (&bg)[3], double (&lab)[3]) {
+    const double c[3] = {px.x + (1.0 - px.w) * bg[0], px.y + (1.0 - px.w) * bg[1], px.z + (1.0 - px.w) * bg[2]};
+    double lin[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double v = fmin(1.0, fmax(0.0, c[k]));
+        lin[k] = v <= 0.04045 ? v / 12.92 : pow((v + 0.055) / 1.055, 2.4);
+    }
+    // linear sRGB -> XYZ (D65), relative to the white the same matrix gives (1, 1, 1)
+    const double X = (0.4124 * lin[0] + 0.3576 * lin[1] + 0.1805 * lin[2]) / (0.4124 + 0.3576 + 0.1805);
+    const double Y = (0.2126 * lin[0] + 0.7152 * lin[1] + 0.0722 * lin[2]);
+    const double Z = (0.0193 * lin[0] + 0.1192 * lin[1] + 0.9505 * lin[2]) / (0.0193 + 0.1192 + 0.9505);
+    const double e = 216.0 / 24389.0, kf = 24389.0 / 27.0;   // (6/29)^3, (29/3)^3
+    auto f = [&](double t) { return t > e ? cbrt(t) : (kf * t + 16.0) / 116.0; };
+    const double fx = f(X), fy = f(Y), fz = f(Z);
+    lab[0] = 116.0 * fy - 16.0;
+    lab[1] = 500.0 * (fx - fy);
+    lab[2] = 200.0 * (fy - fz);
+}
+
+__device__ double ciede2000(const double (&p)[3], const double (&q)[3]) {
+    constexpr double kDeg = 3.14159265358979323846 / 180.0;
+    const double c25 = 6103515625.0;   // 25^7
+    const double cm = 0.5 * (hypot(p[1], p[2]) + hypot(q[1], q[2]));
+    const double cm7 = pow(cm, 7.0);
+    const double g = 0.5 * (1.0 - sqrt(cm7 / (cm7 + c25)));
+    const double ap = (1.0 + g) * p[1], aq = (1.0 + g) * q[1];
+    const double cp = hypot(ap, p[2]), cq = hypot(aq, q[2]);
+    double hp = (ap == 0.0 && p[2] == 0.0) ? 0.0 : atan2(p[2], ap) / kDeg;
+    double hq = (aq == 0.0 && q[2] == 0.0) ? 0.0 : atan2(q[2], aq) / kDeg;
+    if (hp < 0.0) hp += 360.0;
+    if (hq < 0.0) hq += 360.0;
+    const bool achrom = cp * cq == 0.0;
+    double dh = hq - hp;
+    if (dh > 180.0) dh -= 360.0;
+    else if (dh < -180.0) dh += 360.0;
+    if (achrom) dh = 0.0;
+    const double dL = q[0] - p[0], dC = cq - cp;
+    const double dH = 2.0 * sqrt(cp * cq) * sin(0.5 * dh * kDeg);
+    const double lm = 0.5 * (p[0] + q[0]), cpm = 0.5 * (cp + cq);
+    double hm = hp + hq;
+    if (!achrom) {
+        if (fabs(hp - hq) <= 180.0) hm *= 0.5;
+        else hm = hm < 360.0 ? 0.5 * (hm + 360.0) : 0.5 * (hm - 360.0);
+    }
+    const double t = 1.0 - 0.17 * cos((hm - 30.0) * kDeg) + 0.24 * cos(2.0 * hm * kDeg) +
+                     0.32 * cos((3.0 * hm + 6.0) * kDeg) - 0.20 * cos((4.0 * hm - 63.0) * kDeg);
+    const double dth = 30.0 * exp(-((hm - 275.0) / 25.0) * ((hm - 275.0) / 25.0));
+    const double cpm7 = pow(cpm, 7.0);
+    const double rc = 2.0 * sqrt(cpm7 / (cpm7 + c25));
+    const double l50 = (lm - 50.0) * (lm - 50.0);
+    const double sl = 1.0 + 0.015 * l50 / sqrt(20.0 + l50), sc = 1.0 + 0.045 * cpm, sh = 1.0 + 0.015 * cpm * t;
+    const double rt = -sin(2.0 * dth * kDeg) * rc;
+    const double a = dL / sl, b = dC / sc, c = dH / sh;
+    return sqrt(a * a + b * b + c * c + rt * b * c);
+}
+
+// Per pixel difference (optional) and the summary: largest (as float bits),
+// sum, and the count above `threshold`.
+__global__ __launch_bounds__(256) void k_delta_e(const float4 *a, const float4 *b, u64 n, double bg0, double bg1,
+                                                 double bg2, double threshold, float *out, DeltaESum *sum) {
+    __shared__ double s_sum[256];
+    __shared__ unsigned s_max[256];
+    __shared__ unsigned long long s_cnt[256];
+    const double bg[3] = {bg0, bg1, bg2};
+    double acc = 0.0;
+    unsigned mx = 0;
+    unsigned long long cnt = 0;
+    for (u64 i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (u64)gridDim.x * 256ull) {
+        double la[3], lb[3];
+        srgb_lab(a[i], bg, la);
+        srgb_lab(b[i], bg, lb);
+        const double de = ciede2000(la, lb);
+        if (out) out[i] = (float)de;
+        acc += de;
+        mx = max(mx, __float_as_uint((float)de));
+        cnt += de > threshold ? 1ull : 0ull;
+    }
+    s_sum[threadIdx.x] = acc;
+    s_max[threadIdx.x] = mx;
+    s_cnt[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
+            s_max[threadIdx.x] = max(s_max[threadIdx.x], s_max[threadIdx.x + off]);
+            s_cnt[threadIdx.x] += s_cnt[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && sum) {
+        atomicAdd(&sum->sum, s_sum[0]);
+        atomicMax(&sum->max_bits, s_max[0]);
+        atomicAdd(&sum->over, s_cnt[0]);
+    }
+}
+
+hipError_t launch_delta_e(const float *a, const float *b, uint64_t n, const double (&bg)[3], double threshold,
+                          float *out, DeltaESum *sum, int n_cu, hipStream_t st) {
+    const uint64_t want = (n + 255) / 256;
+    const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)n_cu * 8));
+    hipLaunchKernelGGL(k_delta_e, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float4 *>(a),
+                       reinterpret_cast<const float4 *>(b), (u64)n, bg[0], bg[1], bg[2], threshold, out, sum);
+    return hipGetLastError();
+}
+
 // The views' pixel-accuracy records start at zero (no samples: Delta P 0).
 __global__ __launch_bounds__(256) void k_dp_clear(const ViewRec *views, int n_views, u32 n_pixels) {
     const u32 g = blockIdx.x * 256u + threadIdx.x;

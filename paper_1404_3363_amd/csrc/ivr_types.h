@@ -113,6 +113,14 @@ struct Model {
     double scaled;
 };
 
+// Summary of an image comparison (ivr_delta_e2000), accumulated on the device.
+struct DeltaESum {
+    double sum;
+    unsigned long long over;
+    unsigned int max_bits;   // float bits of the largest difference (non-negative)
+    unsigned int pad;
+};
+
 // Device-side counters, one 64-bit slot each (ivr_stats order).
 enum Counter : int {
     C_RAYS = 0, C_SEGMENTS, C_FRAGMENTS, C_ANOMALIES, C_FRAG_OVF, C_SEG_OVF, C_BOX_TESTS,

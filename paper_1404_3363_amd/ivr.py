@@ -29,7 +29,7 @@ EXPORTS = ["ivr_create", "ivr_default_opts", "ivr_upload_patches", "ivr_upload_m
            "ivr_render", "ivr_render_noalloc", "ivr_render_batch", "ivr_autotune", "ivr_set_launch",
            "ivr_phase_times", "ivr_last_error", "ivr_destroy", "ivr_default_mlp_opts",
            "ivr_train_inverse_mlp", "ivr_mlp_forward_backward", "ivr_mlp_get_weights",
-           "ivr_mlp_infer", "ivr_device_bytes"]
+           "ivr_mlp_infer", "ivr_device_bytes", "ivr_delta_e2000"]
 MLP_PARAMS = 4611
 
 
@@ -94,6 +94,10 @@ class MlpReport(C.Structure):
                 ("ms_train", C.c_double)]
 
 
+class DeltaESummary(C.Structure):
+    _fields_ = [("max", C.c_double), ("mean", C.c_double), ("over", C.c_uint64)]
+
+
 class Stats(C.Structure):
     _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [
         ("ms_fragments", C.c_double), ("ms_integrate", C.c_double), ("ms_merge", C.c_double)]
@@ -148,6 +152,9 @@ def load_library() -> C.CDLL:
     L.ivr_phase_times.restype = C.c_int32
     L.ivr_device_bytes.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
     L.ivr_device_bytes.restype = C.c_int32
+    L.ivr_delta_e2000.argtypes = [vp, vp, vp, C.c_int64, C.POINTER(C.c_double), C.c_double, vp,
+                                  C.POINTER(DeltaESummary)]
+    L.ivr_delta_e2000.restype = C.c_int32
     L.ivr_last_error.argtypes = [vp]
     L.ivr_last_error.restype = C.c_char_p
     L.ivr_destroy.argtypes = [vp]
@@ -326,6 +333,26 @@ class Renderer:
                                            x.ctypes.data_as(C.POINTER(C.c_float)), len(x),
                                            out.ctypes.data_as(C.POINTER(C.c_float))))
         return out
+
+    def delta_e2000(self, rgba_a, rgba_b, background=(1.0, 1.0, 1.0), threshold: float = 5.0,
+                    per_pixel: bool = False):
+        """CIEDE2000 between two premultiplied RGBA device images (float32, 4 values
+        per pixel, same size) composited over `background`: {"max", "mean",
+        "over"} (pixels above threshold), and the per-pixel tensor with
+        per_pixel."""
+        a = rgba_a.contiguous()
+        b = rgba_b.contiguous()
+        if a.dtype != self.torch.float32 or b.dtype != self.torch.float32 or a.numel() != b.numel() or \
+                a.numel() % 4:
+            raise ValueError("two float32 RGBA images of the same size")
+        n = a.numel() // 4
+        out = self.torch.empty(n, dtype=self.torch.float32, device=a.device) if per_pixel else None
+        bg = (C.c_double * 3)(*[float(v) for v in background])
+        sm = DeltaESummary()
+        self._check(self.lib.ivr_delta_e2000(self.ctx, a.data_ptr(), b.data_ptr(), n, bg, float(threshold),
+                                             out.data_ptr() if out is not None else None, C.byref(sm)))
+        res = {"max": sm.max, "mean": sm.mean, "over": int(sm.over)}
+        return (res, out) if per_pixel else res
 
     def device_bytes(self) -> dict:
         """Device memory held by the uploaded model and by the frame buffers."""

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_symbols():
     src = open(os.path.join(ROOT, "include", "ivr.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ivr_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(ivr_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -47,7 +47,8 @@ def test_struct_layouts_match_the_compiled_header(tmp_path):
     mirrors = {"ivr_patch_desc": ivr.PatchDesc, "ivr_camera": ivr.CameraDesc, "ivr_render_opts": ivr.RenderOpts,
                "ivr_transfer_fn": ivr.TransferDesc,
                "ivr_stats": ivr.Stats, "ivr_view": ivr.ViewDesc, "ivr_tune_report": ivr.TuneReport,
-               "ivr_mlp_opts": ivr.MlpOpts, "ivr_mlp_report": ivr.MlpReport}
+               "ivr_mlp_opts": ivr.MlpOpts, "ivr_mlp_report": ivr.MlpReport,
+               "ivr_delta_e_summary": ivr.DeltaESummary}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ivr.h"', "int main(void) {"]
     for cname, py in mirrors.items():
         lines.append(f'    printf("{cname} %zu\\n", sizeof({cname}));')

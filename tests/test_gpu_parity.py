@@ -1001,5 +1001,51 @@ def test_frustum_newton_stop(renderer):
           f"max Delta P {dp_f.max():.2e}, max err {np.abs(img_f[pix] - ref.rgba).max():.2e}", flush=True)
     assert dp_f.max() <= 1.0 and st_f["dp_over"] == 0
     assert st_f["w_evals"] < st_t["w_evals"]
+    # the paper's image criterion: colour difference to the reference at most 5
+    import torch
+    de = renderer.delta_e2000(torch.tensor(img_f, dtype=torch.float32, device="cuda"),
+                              torch.tensor(img_t, dtype=torch.float32, device="cuda"))
+    print(f"[pixel] frustum vs tolerance stop: CIEDE2000 max {de['max']:.3f} mean {de['mean']:.4f}", flush=True)
+    assert de["max"] <= 5.0
     with pytest.raises(IvrError):
         _render_dp(renderer, sc, cam, interior="rk2")
+
+
+# ------------------------------------------------------------------ CIEDE2000 image comparison
+
+def test_delta_e2000_matches_the_oracle(renderer):
+    """The device CIEDE2000 between two seeded premultiplied RGBA images (random
+    colours and opacities, identical pixels, grays, transparent pixels) equals the
+    oracle's per pixel (FP64 on both sides, binary32 output), and the summary's
+    largest, mean and count above 5 agree."""
+    import torch
+    from oracle import color
+    rng = np.random.default_rng(77)
+    n = 100_000
+    A = rng.uniform(0, 1, (n, 4))
+    A[:, :3] *= A[:, 3:4]                          # premultiplied
+    B = A + rng.normal(0, 0.03, A.shape)
+    B = np.clip(B, 0, 1)
+    B[:, :3] = np.minimum(B[:, :3], B[:, 3:4])
+    B[:1000] = A[:1000]                            # identical
+    g = rng.uniform(0, 1, (1000, 1))
+    A[1000:2000] = np.column_stack([g, g, g, np.ones(1000)])
+    B[1000:2000] = np.column_stack([g + 0.01, g + 0.01, g + 0.01, np.ones(1000)]).clip(0, 1)
+    A[2000:2100, 3] = 0.0
+    A[2000:2100, :3] = 0.0
+    dev = torch.device("cuda", 0)
+    ta = torch.tensor(A, dtype=torch.float32, device=dev)
+    tb = torch.tensor(B, dtype=torch.float32, device=dev)
+    for bg in ((1.0, 1.0, 1.0), (0.0, 0.0, 0.0)):
+        summ, per = renderer.delta_e2000(ta, tb, background=bg, threshold=5.0, per_pixel=True)
+        torch.cuda.synchronize()
+        got = per.cpu().numpy().astype(np.float64)
+        ref = color.delta_e_images(ta.cpu().numpy(), tb.cpu().numpy(), bg)
+        err = float(np.abs(got - ref).max())
+        print(f"[deltaE] background {bg}: max |gpu - oracle| {err:.2e}; max {summ['max']:.3f} "
+              f"mean {summ['mean']:.4f} over 5: {summ['over']}", flush=True)
+        assert err <= 1e-5 * max(1.0, float(ref.max()))
+        assert got[:1000].max() == 0.0
+        assert abs(summ["max"] - ref.max()) <= 1e-5 * ref.max()
+        assert abs(summ["mean"] - ref.mean()) <= 1e-9 * max(1.0, ref.mean())
+        assert summ["over"] == int((ref > 5.0).sum())

@@ -1168,3 +1168,30 @@ def test_method_mode_pixel_accuracy(oracle_lib):
     _, _, rk1 = oracle.render_method(sc, cam, sc.tf, pixels=pix, method="rk1", c_perp=0.0, h_max=sc.scale / 8,
                                      rho_step=10.0, pixel_accuracy=True)
     assert rk1["delta_p"].max() > 1.0
+
+
+# ------------------------------------------------------------------ CIEDE2000 (image comparison)
+
+def test_ciede2000_reference_values_and_identities(oracle_lib):
+    """The comparison measure: sRGB white, black and mid-gray in CIELAB are
+    (100, 0, 0), (0, 0, 0) and (53.39, 0, 0); sRGB red (53.24, 80.09, 67.20);
+    two grays whose lightness averages 50 differ by exactly their lightness
+    difference; the difference is 0 for equal colours, symmetric, and the images'
+    compositing over the background gives the background where alpha is 0.
+    (The chromatic terms beyond these cases are not pinned by published data.)"""
+    from oracle import color
+    lab = color.srgb_to_lab([[1, 1, 1], [0, 0, 0], [0.5, 0.5, 0.5], [1, 0, 0]])
+    assert np.abs(lab[0] - [100, 0, 0]).max() < 1e-9 and np.abs(lab[1]).max() < 1e-12
+    assert abs(lab[2, 0] - 53.389) < 1e-3 and np.abs(lab[2, 1:]).max() < 1e-9
+    # the quoted red takes the white (0.95047, 1, 1.08883); here the matrix's own
+    # white (0.9505, 1, 1.089), which moves it by at most 0.03
+    assert np.abs(lab[3] - [53.24, 80.09, 67.20]).max() < 0.03
+    assert abs(color.ciede2000([[45, 0, 0]], [[55, 0, 0]])[0] - 10.0) < 1e-12
+    rng = np.random.default_rng(91)
+    a = np.column_stack([rng.uniform(0, 100, 500), rng.uniform(-80, 80, 500), rng.uniform(-80, 80, 500)])
+    b = a + rng.normal(0, 5, a.shape)
+    assert np.abs(color.ciede2000(a, a)).max() == 0.0
+    assert np.abs(color.ciede2000(a, b) - color.ciede2000(b, a)).max() < 1e-10
+    img = np.column_stack([rng.uniform(0, 1, (8, 3)), np.zeros(8)])
+    img[:, :3] = 0.0
+    assert np.abs(color.composite(img, (0.2, 0.4, 0.6)) - [0.2, 0.4, 0.6]).max() == 0.0
