@@ -249,6 +249,62 @@ def interior_ab(r, steps, warmup, seed=11):
     return {"unit": "Mrays/s", **out}
 
 
+def _field_tf(sc, field, seed=5):
+    """The scene's transfer function over the 2nd..98th percentile of a derived
+    field at seeded points of every block (by the oracle)."""
+    import oracle
+    from scenes.configs import TransferFunction
+    rng = np.random.default_rng(seed)
+    vals = [oracle.field_value(P, p, field) for P in sc.patches
+            for p in rng.uniform(0, 1, (max(2, 256 // len(sc.patches)), 3))]
+    lo, hi = np.percentile(vals, [2, 98])
+    return TransferFunction(sc.tf.x, sc.tf.rgba, sc.tf.extinction, (float(lo), float(hi)))
+
+
+def extensions(r, steps, warmup, seed=13):
+    """The derived fields (Sec. "Parametrization Quality of Geometry", Eq.
+    (vonMises)) and the pixel-accuracy tools on config 3 at 1920x1080: Mrays/s and
+    the largest RGBA error against the oracle on 512 covered pixels; the largest
+    Delta P (Eq. (deltaP)) of the default render and of root finding with the
+    frustum Newton stop, its Mrays/s, and its CIEDE2000 against the tolerance stop."""
+    import torch
+    import oracle
+    from scenes import make_config, with_displacement
+    base = make_config(3)
+    B = np.array([[0.01, 0.004, 0.0], [0.002, -0.006, 0.003], [0.0, 0.001, 0.008]])
+    sc = with_displacement(base, B=B, amplitude=0.02 * base.scale)
+    cam = sc.cameras[0]
+    r.upload(sc.patches)
+    out = {"workload": "config3 1920x1080 with a displacement spline (linear part plus a seeded smooth field)",
+           "unit": "Mrays/s"}
+    for field in ("param_quality", "von_mises"):
+        tf = _field_tf(sc, field)
+        sc_f = type(sc)(sc.name, sc.patches, tf, sc.cameras, sc.bbox, sc.params)
+        v, ms, st, rgba = time_renders(r, sc_f, cam, steps, warmup, field=field, rho_step=0.05)
+        img = rgba.cpu().numpy().reshape(-1, 4).astype(np.float64)
+        cov = np.flatnonzero(img[:, 3] > 0)
+        pix = np.random.default_rng(seed).choice(cov, min(512, len(cov)), replace=False)
+        ref = oracle.render(sc_f, cam, tf, pixels=pix, field=field, nthreads=CPU_SHARE)
+        out[field] = {"value": round(v, 3), "ms_per_step": round(ms, 4), "rho_step": 0.05,
+                      "max_abs_rgba_vs_oracle": float(np.abs(img[pix] - ref.rgba).max())}
+    r.upload(base.patches)
+    res = {}
+    for name, kw in (("ode_default", {}), ("rf_tolerance_stop", {"interior": "rf"}),
+                     ("rf_frustum_stop", {"interior": "rf", "newton_stop": "frustum"})):
+        outs, st = r.render_batch([(cam, base.tf, 0)], stats=True, pixel_accuracy=True, **kw)
+        torch.cuda.synchronize()
+        v, ms, _, rgba = time_renders(r, base, cam, steps, warmup, **kw)
+        res[name] = {"value": round(v, 3), "max_delta_p": float(outs[0][2].max().item()),
+                     "samples_delta_p_over_1": st["dp_over"], "order_violations": st["order_violations"],
+                     "w_evals": st["w_evals"], "rgba": outs[0][0]}
+    de = r.delta_e2000(res["rf_frustum_stop"]["rgba"], res["rf_tolerance_stop"]["rgba"])
+    for v in res.values():
+        v.pop("rgba")
+    out["pixel_accuracy"] = res
+    out["ciede2000_frustum_vs_tolerance_stop"] = {"max": de["max"], "mean": de["mean"], "over_5": de["over"]}
+    return out
+
+
 def batch_views(r, steps, warmup, seed=9):
     """The batched-views workload: the 256-block NURBS channel and the 512-block
     mixed-degree lattice, 32 views with resolutions from {256^2, 512^2, 1024^2,
@@ -409,6 +465,7 @@ def main():
         out["mlp_vs_plain"] = mlp_vs_plain(r, args.steps, args.warmup)
     if not args.no_ab:
         out["interior_methods"] = interior_ab(r, args.steps, args.warmup)
+        out["extensions"] = extensions(r, args.steps, args.warmup)
     if not args.no_batch:
         out["batch_views"] = batch_views(r, max(args.steps // 4, 3), 2)
     print(json.dumps(out))

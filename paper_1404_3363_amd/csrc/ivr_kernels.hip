@@ -565,6 +565,13 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         if (base + wrun > mq.c_cap) {   // the list is full: the solve pass traverses again
             c_more = ncand > 0 || c_more;
             ncand = 0;
+            // the wave's rows that still fall inside the list carry no query: a
+            // block index outside the model tells the seed kernel to skip them
+            if (mlp) {
+                const u32 end = min(base + wrun, mq.c_cap);
+                for (u32 r = base + (u32)lane; r < end; r += 64u)
+                    mq.query[r] = make_float4(0.f, 0.f, 0.f, __int_as_float(m.npatch));
+            }
         }
         const u32 excl = wave_incl_scan((u32)ncand, lane) - (u32)ncand;
         for (int k = 0; k < ncand; ++k) {
