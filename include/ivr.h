@@ -384,10 +384,12 @@ ivr_status ivr_set_launch(ivr_ctx *ctx, int32_t tile_w, int32_t xcd_chunk, int32
  * weights). */
 typedef struct {
     int32_t samples_per_patch;  /* forward-map samples per block          [65536] */
-    int32_t steps;              /* Adam steps (minibatch 128 per block)    [2000] */
+    int32_t steps;              /* Adam steps                              [2000] */
     double lr;                  /* Adam step size                          [1e-3] */
     uint32_t seed;              /* sample and initialisation seed          [5005] */
     int32_t log_every;          /* record the loss every this many steps    [100] */
+    int32_t batch;              /* minibatch rows per block and step: a
+                                   multiple of 16 in 16..128              [128] */
 } ivr_mlp_opts;
 
 typedef struct {
@@ -406,7 +408,8 @@ void ivr_default_mlp_opts(ivr_mlp_opts *o);
 ivr_status ivr_train_inverse_mlp(ivr_ctx *ctx, const ivr_mlp_opts *opts, ivr_mlp_report *report);
 
 /* Gradient check of the training kernels: one forward/backward pass of the
- * device code on n = 128 rows with the given parameters (kMlpParams = 4611 floats
+ * device code on n rows (a multiple of 16 in 16..128, the minibatch sizes the
+ * training takes) with the given parameters (kMlpParams = 4611 floats
  * in the layout W1[3][64] b1[64] W2[64][64] b2[64] W3[64][3] b3[3]), normalised
  * inputs x (n*3) and targets p (n*3), all host arrays.  Writes the loss
  * (mean over rows of |y - p|^2) and the 4611 gradient entries.  Synchronous. */

@@ -2022,6 +2022,7 @@ void ivr_default_mlp_opts(ivr_mlp_opts *o) {
     o->lr = 1e-3;
     o->seed = 5005;
     o->log_every = 100;
+    o->batch = kMlpBatch;
 }
 
 static Model model_of(ivr_ctx *c) {
@@ -2046,6 +2047,8 @@ ivr_status ivr_train_inverse_mlp(ivr_ctx *c, const ivr_mlp_opts *opts, ivr_mlp_r
     if (o.steps < 1 || o.steps > 1000000) return fail(c, IVR_EINVAL, "steps outside 1..1000000");
     if (!(o.lr > 0 && o.lr < 1)) return fail(c, IVR_EINVAL, "lr outside (0,1)");
     if (o.log_every < 1) return fail(c, IVR_EINVAL, "log_every must be >= 1");
+    if (o.batch < 16 || o.batch > kMlpBatch || o.batch % 16)
+        return fail(c, IVR_EINVAL, "batch must be a multiple of 16 in 16..128");
     IVR_HIP(c, hipSetDevice(c->device));
     const int np = c->npatch;
     free_mlp(c);
@@ -2095,7 +2098,7 @@ ivr_status ivr_train_inverse_mlp(ivr_ctx *c, const ivr_mlp_opts *opts, ivr_mlp_r
     }
     const Model m = model_of(c);
     MlpTrainParams tp;
-    tp.steps = o.steps; tp.samples = ns; tp.log_every = o.log_every; tp.npatch = np;
+    tp.steps = o.steps; tp.samples = ns; tp.log_every = o.log_every; tp.npatch = np; tp.batch = o.batch;
     tp.lr = (float)o.lr; tp.beta1 = 0.9f; tp.beta2 = 0.999f; tp.eps = 1e-8f; tp.seed = o.seed * 2654435761u + 17u;
     hipError_t e = hipEventRecord(c->ev[0], c->stream);
     if (e == hipSuccess) e = launch_mlp_samples(m, c->mlp, np, ns, o.seed, xs, ps, c->stream);
@@ -2139,7 +2142,7 @@ ivr_status ivr_train_inverse_mlp(ivr_ctx *c, const ivr_mlp_opts *opts, ivr_mlp_r
 ivr_status ivr_mlp_forward_backward(ivr_ctx *c, const float *params, const float *x, const float *p,
                                     int32_t n, float *loss, float *grad) {
     if (!c || !params || !x || !p || !loss || !grad) return fail(c, IVR_EINVAL, "NULL argument");
-    if (n != kMlpBatch) return fail(c, IVR_EINVAL, "n must be 128");
+    if (n < 16 || n > kMlpBatch || n % 16) return fail(c, IVR_EINVAL, "n must be a multiple of 16 in 16..128");
     IVR_HIP(c, hipSetDevice(c->device));
     float *dw = nullptr, *dx = nullptr, *dp = nullptr, *dout = nullptr;
     auto cleanup = [&]() { dfree(dw); dfree(dx); dfree(dp); dfree(dout); };
@@ -2151,6 +2154,7 @@ ivr_status ivr_mlp_forward_backward(ivr_ctx *c, const float *params, const float
     MlpState st = {dw, nullptr, nullptr, nullptr, nullptr};
     MlpTrainParams tp;
     std::memset(&tp, 0, sizeof tp);
+    tp.batch = n;
     hipError_t e = hipMemcpy(dw, params, kMlpParams * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dx, x, n * 12, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dp, p, n * 12, hipMemcpyHostToDevice);

@@ -26,6 +26,7 @@ struct MlpState {
 
 struct MlpTrainParams {
     int32_t steps, samples, log_every, npatch;
+    int32_t batch;   // live rows of the kMlpBatch computed (the rest carry no gradient)
     float lr, beta1, beta2, eps;
     uint32_t seed;
 };

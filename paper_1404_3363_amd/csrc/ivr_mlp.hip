@@ -1,7 +1,8 @@
 // Learned initialiser kernels (gfx950): forward-map sampling, BF16 MFMA training
 // (forward, backward, Adam with FP32 master weights) and inference.
 //
-// Training layout, one workgroup of 4 waves per block, minibatch of 128:
+// Training layout, one workgroup of 4 waves per block, 128 rows computed per
+// step (a smaller minibatch leaves the rows past it without gradient):
 //   layer 1 (3 -> 64) and layer 3 (64 -> 3) are thin and run on the VALU;
 //   layer 2 (64 -> 64) forward Z2 = H1 W2, and backward dW2 = H1^T dZ2 and
 //   dH1 = dZ2 W2^T run on v_mfma_f32_16x16x16_bf16 with FP32 accumulation.
@@ -114,7 +115,10 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpState st, MlpTrainParams t
             float x[3], p[3];
             if (MODE) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) { x[c] = gc_x[tid * 3 + c]; p[c] = gc_p[tid * 3 + c]; }
+                for (int c = 0; c < 3; ++c) {
+                    x[c] = tid < tp.batch ? gc_x[tid * 3 + c] : 0.f;
+                    p[c] = tid < tp.batch ? gc_p[tid * 3 + c] : 0.f;
+                }
             } else {
                 const uint32_t h = pcg_hash(tp.seed ^ pcg_hash((uint32_t)(q * 7919 + step) * 131u + (uint32_t)tid));
                 const size_t o = (size_t)q * tp.samples + (h % (uint32_t)tp.samples);
@@ -171,8 +175,9 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpState st, MlpTrainParams t
                     float s = 0.f;
 #pragma unroll
                     for (int ct = 0; ct < 4; ++ct) s += h2[rb][ct][j] * sW3[(ct * 16 + lr16) * 3 + c];
-                    const float e = red16(s) + sb3[c] - sP[i * 3 + c];
-                    dy[rb][j][c] = e * (2.0f / kMlpBatch);
+                    // rows past the minibatch (batch < kMlpBatch) carry no gradient
+                    const float e = i < tp.batch ? red16(s) + sb3[c] - sP[i * 3 + c] : 0.f;
+                    dy[rb][j][c] = e * (2.0f / (float)tp.batch);
                     lossp += e * e;
                 }
             }
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpState st, MlpTrainParams t
             for (int i = tid; i < 192; i += 256) { gc_out[kOffW1 + i] = gW1[i]; gc_out[kOffW3 + i] = gW3[i]; }
             for (int i = tid; i < 64; i += 256) { gc_out[kOffB1 + i] = gb1[i]; gc_out[kOffB2 + i] = gb2[i]; }
             if (tid < 3) gc_out[kOffB3 + tid] = gb3[tid];
-            if (tid == 0) gc_out[kMlpParams] = sLoss / kMlpBatch;
+            if (tid == 0) gc_out[kMlpParams] = sLoss / (float)tp.batch;
             return;
         }
         // Adam on the FP32 master weights
@@ -320,7 +325,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpState st, MlpTrainParams t
         }
         __syncthreads();
         if (tid == 0 && tp.log_every > 0 && step % tp.log_every == 0 && step / tp.log_every < nlog)
-            loss_log[(size_t)q * nlog + step / tp.log_every] = sLoss / kMlpBatch;
+            loss_log[(size_t)q * nlog + step / tp.log_every] = sLoss / (float)tp.batch;
         for (int i = tid; i < 192; i += 256) { gW1[i] = 0.f; gW3[i] = 0.f; }
         for (int i = tid; i < 64; i += 256) { gb1[i] = 0.f; gb2[i] = 0.f; }
         if (tid < 4) gb3[tid] = 0.f;

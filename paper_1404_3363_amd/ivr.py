@@ -85,7 +85,7 @@ STAT_FIELDS = ["rays", "segments", "fragments", "anomalies", "fragment_overflow"
 
 class MlpOpts(C.Structure):
     _fields_ = [("samples_per_patch", C.c_int32), ("steps", C.c_int32), ("lr", C.c_double),
-                ("seed", C.c_uint32), ("log_every", C.c_int32)]
+                ("seed", C.c_uint32), ("log_every", C.c_int32), ("batch", C.c_int32)]
 
 
 class MlpReport(C.Structure):

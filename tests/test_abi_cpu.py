@@ -33,6 +33,11 @@ def test_default_opts_match_header():
     assert o.early_term == 1e-4 and o.max_newton_iter == 16
     assert o.tf_step == 0.025 and o.rho_step == 0.1 and o.cand_per_pixel == 8
     assert o.det_singular == 1e-6 and o.det_fp64_threshold == 1e-6 and o.drift_tol == 1e-4
+    assert o.interior == 0 and o.field == 0 and o.newton_stop == 0 and o.cut == 0 and o.near_clip == 0.0
+    from paper_1404_3363_amd import ivr
+    mo = ivr.MlpOpts()
+    ivr.load_library().ivr_default_mlp_opts(ctypes.byref(mo))
+    assert mo.samples_per_patch == 65536 and mo.steps == 2000 and mo.batch == 128
 
 
 def test_struct_layouts_match_the_compiled_header(tmp_path):
