@@ -29,7 +29,8 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6    # 256 CUs x 64 lanes x 2 flops x 2.4 GHz wit
 
 
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "render_config3_1080p_counters.md")
-KERNEL_SOURCES = ["paper_1404_3363_amd/csrc/ivr_kernels.hip", "paper_1404_3363_amd/csrc/ivr_spline.h",
+KERNEL_SOURCES = ["paper_1404_3363_amd/csrc/ivr_kernels.hip", "paper_1404_3363_amd/csrc/ivr_integrate.h",
+                  "paper_1404_3363_amd/csrc/ivr_device.h", "paper_1404_3363_amd/csrc/ivr_spline.h",
                   "paper_1404_3363_amd/csrc/ivr_types.h", "paper_1404_3363_amd/csrc/ivr_mlp_dev.h"]
 
 
