@@ -248,9 +248,10 @@ __device__ void face_root(const Model &m, const DevPatch &Pd, const FaceElem &E,
         // (a, b) the FP32 tangents are taken again at the new point.  A step of at
         // most 1e-5 in (a, b) and 1e-5 scale in t leaves a residual below the 1e-9
         // scale acceptance bound and is taken without evaluating it again.
+        //   An FP64 Newton root stopped at the refinement's own tolerance already.
         double A = a, B = b, T = t, S2[3], F2[3], Sa2[3], Sb2[3];
-        bool ok = false;
-        for (int k = 0; k < 4; ++k) {
+        bool ok = sizeof(RN) == 8;
+        for (int k = 0; k < 4 && !ok; ++k) {
             eval_face<P, RAT, double, false>(fv64, ar64, A, B, S2, Sa2, Sb2);
 #pragma unroll
             for (int q = 0; q < 3; ++q) F2[q] = S2[q] - od[q] - T * dd[q];
@@ -437,9 +438,19 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         return q < kFragLds ? s_fi[q * 64 + lane] : fr[q].info;
     };
     // a crossing of the same block and facing within tol of depth t is there already
+    // f(q, t, info) for every crossing in the order found: the LDS part and the
+    // scratch part in loops of their own, so that every load names its memory
+    // (one loop over both would load through flat addresses)
+    auto each_frag = [&](auto &&f) __attribute__((always_inline)) {
+        const int nl = min(nfr, kFragLds);
+        for (int q = 0; q < nl; ++q) f(q, s_ft[q * 64 + lane], s_fi[q * 64 + lane]);
+        for (int q = kFragLds; q < nfr; ++q) f(q, fr[q].t, fr[q].info);
+    };
     auto known = [&](u32 info, R t, R tol) __attribute__((always_inline)) -> bool {
         bool dup = false;
-        for (int q = 0; q < nfr; ++q) dup |= ((fi(q) ^ info) & ~0xEu) == 0u && fabs(ft(q) - t) <= tol;
+        each_frag([&](int, R tq, u32 iq) __attribute__((always_inline)) {
+            dup |= ((iq ^ info) & ~0xEu) == 0u && fabs(tq - t) <= tol;
+        });
         return dup;
     };
     auto push = [&](u32 info, R t, R a, R b) __attribute__((always_inline)) {
@@ -701,36 +712,34 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         else if (sd < 0.0) khi = R(-fp.cut_s0 / sd);
         else if (fp.cut_s0 < 0.0) khi = -INFINITY;
     }
-    auto t_in_of = [&](int q) __attribute__((always_inline)) -> R {
-        return q == kRayStart ? klo : fmax(ft(q), klo);
-    };
     unsigned char pin[kSegCap], pout[kSegCap];
+    R ptin[kSegCap];   // the pairs' kept entry depths
+    u32 pblk[kSegCap]; // and blocks
     int npair = 0;
     u64 used = 0;
     const R teq = R(1e-6 * fp.scaled);
     for (;;) {
         int ib = -1;
         R tb = R(0);
-        for (int q = 0; q < nfr; ++q) {
-            const R tq = ft(q);
-            if (!((used >> q) & 1ull) && !(fi(q) & 1u) && (ib < 0 || tq < tb)) {
+        u32 pb = 0;
+        each_frag([&](int q, R tq, u32 iq) __attribute__((always_inline)) {
+            if (!((used >> q) & 1ull) && !(iq & 1u) && (ib < 0 || tq < tb)) {
                 ib = q;
                 tb = tq;
+                pb = iq >> 4;
             }
-        }
+        });
         if (ib < 0) break;
         used |= 1ull << ib;
-        const u32 pb = fi(ib) >> 4;
         int ifr = -1;
         R tf = R(0);
-        for (int q = 0; q < nfr; ++q) {
-            const u32 iq = fi(q);
-            const R tq = ft(q);
+        each_frag([&](int q, R tq, u32 iq) __attribute__((always_inline)) {
             if (!((used >> q) & 1ull) && (iq & 1u) && (iq >> 4) == pb && tq <= tb + teq && (ifr < 0 || tq < tf)) {
                 ifr = q;
                 tf = tq;
             }
-        }
+        });
+        R t_in = klo;
         if (ifr < 0) {
             if (!(fp.near_clip > 0.0)) {
                 ++c_anom;
@@ -739,19 +748,23 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             ifr = kRayStart;
         } else {
             used |= 1ull << ifr;
+            t_in = fmax(tf, klo);
         }
-        const R t_in = t_in_of(ifr);
         if (!(fmin(tb, khi) > t_in)) continue;   // nothing of it is kept
         if (npair >= kSegCap) { ++c_sovf; continue; }
         // keep the pairs ordered by (kept) entry depth
         int q = npair++;
-        while (q > 0 && t_in_of(pin[q - 1]) > t_in) {
+        while (q > 0 && ptin[q - 1] > t_in) {
             pin[q] = pin[q - 1];
             pout[q] = pout[q - 1];
+            ptin[q] = ptin[q - 1];
+            pblk[q] = pblk[q - 1];
             --q;
         }
         pin[q] = (unsigned char)ifr;
         pout[q] = (unsigned char)ib;
+        ptin[q] = t_in;
+        pblk[q] = pb;
     }
     for (int q = 0; q < nfr; ++q) c_anom += !((used >> q) & 1ull);
 
@@ -776,7 +789,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         const int qi = pin[k], qo = pout[k];
         const u32 info_o = fi(qo);
         Seg<R> s;
-        s.t_in = t_in_of(qi);
+        s.t_in = ptin[k];
         s.t_out = fmin(ft(qo), khi);
         R pi_[3], po_[3];
         if (qi != kRayStart && ft(qi) >= klo) {
@@ -814,13 +827,13 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             int kk = -1;
             for (int k = 0; k < nseg; ++k)
                 if (!((ranked >> k) & 1u)) { kk = k; break; }
-            const int myp = kk >= 0 ? (int)(fi(pout[kk]) >> 4) : -1;
+            const int myp = kk >= 0 ? (int)pblk[kk] : -1;
             const u64 any = __ballot(myp >= 0);
             if (any == 0) break;
             const int leader = __ffsll((long long)any) - 1;
             const int p = __shfl(myp, leader);
             u32 cnt = 0;
-            for (int k = 0; k < nseg; ++k) cnt += (!((ranked >> k) & 1u) && (int)(fi(pout[k]) >> 4) == p) ? 1u : 0u;
+            for (int k = 0; k < nseg; ++k) cnt += (!((ranked >> k) & 1u) && (int)pblk[k] == p) ? 1u : 0u;
             const u32 ci = wave_incl_scan(cnt, lane);
             const u32 ctot = __shfl(ci, 63);
             u32 b = 0;
@@ -828,7 +841,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
             b = __shfl(b, leader);
             u32 r = b + ci - cnt;
             for (int k = 0; k < nseg; ++k)
-                if (!((ranked >> k) & 1u) && (int)(fi(pout[k]) >> 4) == p) {
+                if (!((ranked >> k) & 1u) && (int)pblk[k] == p) {
                     seg_kr[first + k] = make_uint2((u32)p, r++);
                     ranked |= 1u << k;
                 }
@@ -836,7 +849,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     }
     if (valid) {
         pixseg[vr.pix_begin + pixel] = make_uint2(first, (u32)nseg);
-        if (vr.depth) vr.depth[pixel] = nseg ? float(t_in_of(pin[0])) : INFINITY;
+        if (vr.depth) vr.depth[pixel] = nseg ? float(ptin[0]) : INFINITY;
         // the pixel's flags start here; the integrator ORs in its segments' flags
         if (vr.flags)
             vr.flags[pixel] = (c_anom ? (u32)IVR_FLAG_ANOMALY : 0u) | (c_fovf ? (u32)IVR_FLAG_FRAGMENT_OVERFLOW : 0u) |
