@@ -116,6 +116,97 @@ __device__ __forceinline__ bool obb_hit(const Box3 &E, const float (&o)[3], cons
     return tmin <= tmax;
 }
 
+// The view frustum of a pixel tile: the four planes through the eye that
+// contain the rays of its corner pixels, normals pointing inwards.  Every ray of
+// the tile lies inside (the rays' directions are affine in the pixel
+// coordinates), so a box wholly outside one plane is missed by all of them.
+struct TileFrustum {
+    float n[4][3];
+    float e[3];
+};
+
+// The plane through the eye that holds directions u and v, its normal turned so
+// that its product with the camera axis a has the sign sg.
+__device__ __forceinline__ void frustum_plane(const double (&u)[3], const double (&v)[3], double a0, double a1,
+                                              double a2, double sg, float (&n)[3]) {
+    const double x = u[1] * v[2] - u[2] * v[1], y = u[2] * v[0] - u[0] * v[2], z = u[0] * v[1] - u[1] * v[0];
+    const double s = (x * a0 + y * a1 + z * a2) * sg < 0.0 ? -1.0 : 1.0;
+    n[0] = float(s * x);
+    n[1] = float(s * y);
+    n[2] = float(s * z);
+}
+
+// Planes left, right, top, bottom: the pixel column grows along the camera's
+// right axis, the row index against its up axis.  A tile one pixel wide (or
+// high) has no top and bottom (left and right) planes: their two rays are one,
+// and the rounding of their cross product (contracted to FMAs) would leave a
+// normal of random direction; those normals are zero, which culls nothing.
+__device__ __forceinline__ TileFrustum tile_frustum(const FrameParams &fp, int x0, int y0, int x1, int y1) {
+    double c00[3], c10[3], c01[3], c11[3];
+    ray_dir(fp, x0, y0, c00);
+    ray_dir(fp, x1, y0, c10);
+    ray_dir(fp, x0, y1, c01);
+    ray_dir(fp, x1, y1, c11);
+    const double r0 = fp.right[0], r1 = fp.right[1], r2 = fp.right[2];
+    const double u0 = fp.up[0], u1 = fp.up[1], u2 = fp.up[2];
+    TileFrustum F;
+    frustum_plane(c00, c01, r0, r1, r2, 1.0, F.n[0]);
+    frustum_plane(c10, c11, r0, r1, r2, -1.0, F.n[1]);
+    frustum_plane(c00, c10, u0, u1, u2, -1.0, F.n[2]);
+    frustum_plane(c01, c11, u0, u1, u2, 1.0, F.n[3]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (y0 == y1) F.n[0][q] = F.n[1][q] = 0.f;
+        if (x0 == x1) F.n[2][q] = F.n[3][q] = 0.f;
+    }
+    F.e[0] = float(fp.eye[0]);
+    F.e[1] = float(fp.eye[1]);
+    F.e[2] = float(fp.eye[2]);
+    return F;
+}
+
+// True when the axis-aligned box [lo, hi] lies wholly outside a plane of F, by
+// more than 1e-5 of the size of the terms (FP32 rounding stays far below).
+__device__ __forceinline__ bool frustum_misses_box(const TileFrustum &F, const float *lo, const float *hi) {
+    bool out = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float mx = 0.f, sz = 0.f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float a = lo[q] - F.e[q], b = hi[q] - F.e[q];
+            mx += fmaxf(F.n[i][q] * a, F.n[i][q] * b);
+            sz += fabsf(F.n[i][q]) * fmaxf(fabsf(a), fabsf(b));
+        }
+        out |= mx < -1e-5f * sz;
+    }
+    return out;
+}
+
+// The same for an oriented box (centre c, unit axes ax, half extents ext).
+template <typename Box3>
+__device__ __forceinline__ bool frustum_misses_obb(const TileFrustum &F, const Box3 &B) {
+    bool out = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float mx = 0.f, sz = 0.f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float a = B.c[q] - F.e[q];
+            mx += F.n[i][q] * a;
+            sz += fabsf(F.n[i][q] * a);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float r = B.ext[k] * fabsf(F.n[i][0] * B.ax[k][0] + F.n[i][1] * B.ax[k][1] + F.n[i][2] * B.ax[k][2]);
+            mx += r;
+            sz += r;
+        }
+        out |= mx < -1e-5f * sz;
+    }
+    return out;
+}
+
 // Front facing: the sign of (J^-1 d) along the face's inward normal.  By
 // Cramer's rule it equals the sign of d . (S_a x S_b) times the face's side,
 // the orientation of (a, b, n) and the block's orientation (sign of det J).
@@ -507,40 +598,57 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     // The traversal: on_hit(e, he) for every face element e of a tile the wave
     // tests (he: the lane's ray hits its box), after_block(pi, nc0) after each
     // block the wave's rays may hit, with nc0 the lane's candidate count before it.
+    // The blocks and face tiles that no ray of the pixel tile can hit are culled
+    // first, 64 at a time (a lane a box) against the tile's frustum: what remains
+    // is tested ray by ray in the same order, so the candidates and their order
+    // are those of testing every box.
     auto traverse = [&](bool act, auto &&on_hit, auto &&after_block) __attribute__((always_inline)) {
-        for (int pi = vr.patch_begin; pi < vr.patch_end; ++pi) {
-            const DevPatch &Pd = m.patches[pi];
-            ++c_box;
-            const bool hp = act && slab(of, inv, Pd.box, Pd.box + 3);
-            if (__ballot(hp) == 0) continue;
-            const int nc0 = ncand;
-            for (int f = 0; f < 6; ++f) {
-                if ((Pd.face_skip >> f) & 1) continue;   // tested from the neighbouring block
-                c_box += hp;
-                const bool hf = hp && slab(of, inv, Pd.fbox[f], Pd.fbox[f] + 3);
-                if (__ballot(hf) == 0) continue;
-                for (int ti = Pd.tile_off[f]; ti < Pd.tile_off[f + 1]; ++ti) {
-                    const FaceTile &T = m.tiles[ti];
-                    c_box += hf;
-                    const bool ht = hf && obb_hit(T, of, df);
-                    if (__ballot(ht) == 0) continue;
-                    const bool split = T.sub_end > T.sub_begin;
-                    for (int si = split ? T.sub_begin : ti; si < (split ? T.sub_end : ti + 1); ++si) {
-                        const FaceTile &S = m.tiles[si];
-                        bool hs = ht;
-                        if (split) {
-                            c_box += ht;
-                            hs = ht && obb_hit(S, of, df);
-                            if (__ballot(hs) == 0) continue;
-                        }
-                        for (int e = S.elem_begin; e < S.elem_end; ++e) {
-                            c_box += hs;
-                            on_hit((u32)e, hs && obb_hit(m.elems[e], of, df));
+        const TileFrustum fru = tile_frustum(fp, (int)(tl % vr.tiles_x) * lc.tile_w, (int)(tl / vr.tiles_x) * th,
+                                             min((int)(tl % vr.tiles_x + 1) * lc.tile_w, fp.width) - 1,
+                                             min((int)(tl / vr.tiles_x + 1) * th, fp.height) - 1);
+        for (int pb0 = vr.patch_begin; pb0 < vr.patch_end; pb0 += 64) {
+            const int pj = pb0 + lane;
+            const bool pnear = pj < vr.patch_end && !frustum_misses_box(fru, m.patches[pj].box, m.patches[pj].box + 3);
+            for (u64 bm = __ballot(pnear); bm != 0ull; bm &= bm - 1ull) {
+                const int pi = pb0 + __ffsll((long long)bm) - 1;
+                const DevPatch &Pd = m.patches[pi];
+                ++c_box;
+                const bool hp = act && slab(of, inv, Pd.box, Pd.box + 3);
+                if (__ballot(hp) == 0) continue;
+                const int nc0 = ncand;
+                for (int f = 0; f < 6; ++f) {
+                    if ((Pd.face_skip >> f) & 1) continue;   // tested from the neighbouring block
+                    c_box += hp;
+                    const bool hf = hp && slab(of, inv, Pd.fbox[f], Pd.fbox[f] + 3);
+                    if (__ballot(hf) == 0) continue;
+                    for (int t0 = Pd.tile_off[f]; t0 < Pd.tile_off[f + 1]; t0 += 64) {
+                        const int tj = t0 + lane;
+                        const bool tnear = tj < Pd.tile_off[f + 1] && !frustum_misses_obb(fru, m.tiles[tj]);
+                        for (u64 tm = __ballot(tnear); tm != 0ull; tm &= tm - 1ull) {
+                            const int ti = t0 + __ffsll((long long)tm) - 1;
+                            const FaceTile &T = m.tiles[ti];
+                            c_box += hf;
+                            const bool ht = hf && obb_hit(T, of, df);
+                            if (__ballot(ht) == 0) continue;
+                            const bool split = T.sub_end > T.sub_begin;
+                            for (int si = split ? T.sub_begin : ti; si < (split ? T.sub_end : ti + 1); ++si) {
+                                const FaceTile &S = m.tiles[si];
+                                bool hs = ht;
+                                if (split) {
+                                    c_box += ht;
+                                    hs = ht && obb_hit(S, of, df);
+                                    if (__ballot(hs) == 0) continue;
+                                }
+                                for (int e = S.elem_begin; e < S.elem_end; ++e) {
+                                    c_box += hs;
+                                    on_hit((u32)e, hs && obb_hit(m.elems[e], of, df));
+                                }
+                            }
                         }
                     }
                 }
+                after_block(pi, nc0);
             }
-            after_block(pi, nc0);
         }
     };
     auto no_block = [&](int, int) __attribute__((always_inline)) {};
