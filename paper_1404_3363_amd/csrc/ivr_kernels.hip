@@ -78,6 +78,12 @@ struct RootRec {
     uint32_t info, tinfo;
 };
 
+// A direction component as a divisor: zero (and anything below 1e-30 in size)
+// becomes +-1e-30, so that a ray parallel to a slab gets a finite, enormous
+// interval (no hit from outside the slab, no limit inside it) rather than a NaN
+// that the min/max would skip.
+__device__ __forceinline__ float safe_divisor(float x) { return copysignf(fmaxf(fabsf(x), 1e-30f), x); }
+
 // Ray (t >= 0) against an oriented box; [tmin, tmax] is the ray's interval inside.
 template <typename Box3>
 __device__ __forceinline__ bool obb_hit(const Box3 &E, const float (&o)[3], const float (&d)[3],
@@ -89,7 +95,7 @@ __device__ __forceinline__ bool obb_hit(const Box3 &E, const float (&o)[3], cons
     for (int r = 0; r < 3; ++r) {
         const float po = E.ax[r][0] * oc[0] + E.ax[r][1] * oc[1] + E.ax[r][2] * oc[2];
         const float pd = E.ax[r][0] * d[0] + E.ax[r][1] * d[1] + E.ax[r][2] * d[2];
-        const float inv = __builtin_amdgcn_rcpf(pd);
+        const float inv = __builtin_amdgcn_rcpf(safe_divisor(pd));
         const float t0 = (-E.ext[r] - po) * inv, t1 = (E.ext[r] - po) * inv;
         tmin = fmaxf(tmin, fminf(t0, t1));
         tmax = fminf(tmax, fmaxf(t0, t1));
@@ -108,7 +114,7 @@ __device__ __forceinline__ bool obb_hit(const Box3 &E, const float (&o)[3], cons
     for (int r = 0; r < 3; ++r) {
         const float po = E.ax[r][0] * oc[0] + E.ax[r][1] * oc[1] + E.ax[r][2] * oc[2];
         const float pd = E.ax[r][0] * d[0] + E.ax[r][1] * d[1] + E.ax[r][2] * d[2];
-        const float inv = __builtin_amdgcn_rcpf(pd);
+        const float inv = __builtin_amdgcn_rcpf(safe_divisor(pd));
         const float mid = -po * inv, ai = fabsf(inv);
         tmin = fmaxf(tmin, fmaf(-E.ext[r], ai, mid));
         tmax = fminf(tmax, fmaf(E.ext[r], ai, mid));
@@ -504,7 +510,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     for (int q = 0; q < 3; ++q) {
         of[q] = float(od[q]);
         df[q] = float(dd[q]);
-        inv[q] = 1.0f / df[q];
+        inv[q] = 1.0f / safe_divisor(df[q]);
     }
     u32 c_anom = 0, c_fovf = 0, c_sovf = 0, c_box = 0, c_newton = 0, c_iter = 0, c_pol = 0, c_mlp = 0;
 
@@ -598,10 +604,10 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     // The traversal: on_hit(e, he) for every face element e of a tile the wave
     // tests (he: the lane's ray hits its box), after_block(pi, nc0) after each
     // block the wave's rays may hit, with nc0 the lane's candidate count before it.
-    // The blocks and face tiles that no ray of the pixel tile can hit are culled
-    // first, 64 at a time (a lane a box) against the tile's frustum: what remains
-    // is tested ray by ray in the same order, so the candidates and their order
-    // are those of testing every box.
+    // The blocks, face tiles and elements that no ray of the pixel tile can hit
+    // are culled first, 64 at a time (a lane a box) against the tile's frustum:
+    // what remains is tested ray by ray in the same order, so the candidates and
+    // their order are those of testing every box.
     auto traverse = [&](bool act, auto &&on_hit, auto &&after_block) __attribute__((always_inline)) {
         const TileFrustum fru = tile_frustum(fp, (int)(tl % vr.tiles_x) * lc.tile_w, (int)(tl / vr.tiles_x) * th,
                                              min((int)(tl % vr.tiles_x + 1) * lc.tile_w, fp.width) - 1,
@@ -630,16 +636,25 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
                             c_box += hf;
                             const bool ht = hf && obb_hit(T, of, df);
                             if (__ballot(ht) == 0) continue;
+                            // the tile's elements (at most kTile^2) against the frustum, one a lane
+                            const int e0 = T.elem_begin;
+                            const u64 emask =
+                                __ballot(lane < T.elem_end - e0 && !frustum_misses_obb(fru, m.elems[e0 + lane]));
+                            if (emask == 0ull) continue;
                             const bool split = T.sub_end > T.sub_begin;
                             for (int si = split ? T.sub_begin : ti; si < (split ? T.sub_end : ti + 1); ++si) {
                                 const FaceTile &S = m.tiles[si];
+                                const u64 smask = (emask >> (S.elem_begin - e0)) &
+                                                  ((1ull << (S.elem_end - S.elem_begin)) - 1ull);
+                                if (smask == 0ull) continue;
                                 bool hs = ht;
                                 if (split) {
                                     c_box += ht;
                                     hs = ht && obb_hit(S, of, df);
                                     if (__ballot(hs) == 0) continue;
                                 }
-                                for (int e = S.elem_begin; e < S.elem_end; ++e) {
+                                for (u64 em = smask; em != 0ull; em &= em - 1ull) {
+                                    const int e = S.elem_begin + __ffsll((long long)em) - 1;
                                     c_box += hs;
                                     on_hit((u32)e, hs && obb_hit(m.elems[e], of, df));
                                 }

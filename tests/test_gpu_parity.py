@@ -187,6 +187,32 @@ def test_rays_through_block_edges_and_corners(renderer, view):
     assert abs(depth[centre] - ref.depth[centre]) <= DEPTH_REL_TOL * ref.depth[centre]
 
 
+@pytest.mark.parametrize("tile_w", [16, 32])
+def test_tile_frustum_culling_keeps_every_candidate(renderer, tile_w):
+    """The traversal culls blocks and element tiles against each pixel tile's
+    frustum.  On the 65x65 edge-lattice views, where the last tile column and
+    row are partial (one pixel wide or high for 8x8 tiles), tiles of 16x4 and
+    32x2 pixels give the image and depth of 8x8 tiles bit for bit, with the same
+    Newton solves: the per-ray candidates do not depend on the tile's shape."""
+    import torch
+    sc = make_edge_lattice()
+    renderer.upload(sc.patches)
+    try:
+        for view, cam in enumerate(sc.cameras):
+            renderer.set_launch(8)
+            a, da, sa = renderer.render(cam, sc.tf, stats=True, precision="fp32")
+            renderer.set_launch(tile_w)
+            b, db, sb = renderer.render(cam, sc.tf, stats=True, precision="fp32")
+            torch.cuda.synchronize()
+            print(f"[parity] edge lattice view {view} tiles {tile_w}x{64 // tile_w}: box tests "
+                  f"{sb['box_tests']} (8x8: {sa['box_tests']}), solves {sb['face_newton']}", flush=True)
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), view
+            assert np.array_equal(da.cpu().numpy(), db.cpu().numpy()), view
+            assert sb["face_newton"] == sa["face_newton"] and sb["anomalies"] == 0 and sa["anomalies"] == 0
+    finally:
+        renderer.set_launch()
+
+
 def test_degenerate_face_constant_field_closed_form(renderer):
     """Constant rho on the degenerate-face cube: alpha = 1 - exp(-kappa L) with L
     the ray-box chord of the unit cube, for both views."""
