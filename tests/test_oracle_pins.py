@@ -226,6 +226,29 @@ def test_affine_patch_is_affine(oracle_lib):
             assert np.allclose(J, A, atol=1e-12)
 
 
+def test_projected_newton_stops_on_the_boundary(oracle_lib):
+    """Sec. "Degeneracies and Points Outside Domain": every Newton iterate is kept
+    in P, so a point outside the block's image leaves the iterate on P's
+    boundary.  For an axis-scaled affine block phi(p) = diag(a) p + b that point
+    is the target's preimage clipped to [0,1]^3 (the nearest point of the image
+    is there too), and no root is reported; targets inside give the exact
+    preimage."""
+    a = np.array([2.0, 3.0, 0.5])
+    b = np.array([1.0, -1.0, 0.2])
+    P = affine_patch(np.diag(a), b, (3, 2, 3), (6, 4, 5))
+    rng = np.random.default_rng(17)
+    for pstar in np.concatenate([rng.uniform(-0.6, 1.6, (24, 3)), rng.uniform(0.05, 0.95, (8, 3))]):
+        g = a * pstar + b
+        inside = bool(((pstar >= 0) & (pstar <= 1)).all())
+        for seed in ((0.5, 0.5, 0.5), (0.1, 0.9, 0.3)):
+            rc, p, it = oracle.invert(P, g, seed=seed)
+            if inside:
+                assert rc == 0 and np.allclose(p, pstar, atol=1e-12), (pstar, p)
+            else:
+                assert rc != 0, pstar
+                assert np.allclose(p, np.clip(pstar, 0.0, 1.0), atol=1e-12), (pstar, p)
+
+
 def test_jacobian_matches_central_differences(oracle_lib, eval_patches):
     rng = np.random.default_rng(3)
     for name, P in eval_patches.items():
