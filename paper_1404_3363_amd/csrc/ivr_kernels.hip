@@ -534,7 +534,6 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
     auto fi = [&](int q) __attribute__((always_inline)) -> u32 {
         return q < kFragLds ? s_fi[q * 64 + lane] : fr[q].info;
     };
-    // a crossing of the same block and facing within tol of depth t is there already
     // f(q, t, info) for every crossing in the order found: the LDS part and the
     // scratch part in loops of their own, so that every load names its memory
     // (one loop over both would load through flat addresses)
@@ -543,6 +542,7 @@ __global__ __launch_bounds__(64) void k_fragments(Model m, const ViewRec *views,
         for (int q = 0; q < nl; ++q) f(q, s_ft[q * 64 + lane], s_fi[q * 64 + lane]);
         for (int q = kFragLds; q < nfr; ++q) f(q, fr[q].t, fr[q].info);
     };
+    // a crossing of the same block and facing within tol of depth t is there already
     auto known = [&](u32 info, R t, R tol) __attribute__((always_inline)) -> bool {
         bool dup = false;
         each_frag([&](int, R tq, u32 iq) __attribute__((always_inline)) {
