@@ -294,6 +294,21 @@ def test_config4_nurbs_channel_1080p_sampled(renderer):
     assert st["fragment_overflow"] == 0 and st["segment_overflow"] == 0
 
 
+def test_config4_nurbs_channel_1080p_stratified(renderer):
+    """The NURBS channel (256 curved rational blocks, non-uniform weights) at
+    1920x1080 against the oracle on a stratified sample of 16384 pixels that
+    holds a pixel of every 8x8 silhouette tile."""
+    sc = make_config(4)
+    cam = sc.cameras[0]
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp32")
+    pix, sil = _stratified_with_silhouette_tiles(cam, depth, 16384, 43)
+    print(f"[parity] config4 stratified sample: {len(pix)} pixels, {len(sil)} silhouette tiles", flush=True)
+    assert len(pix) >= 16000 and len(sil) > 300
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    _compare("config4 1920x1080 stratified", img, depth, ref, pix, sc.scale)
+    assert st["anomalies"] == 0
+
+
 @pytest.mark.parametrize("k", [3, 4])
 def test_every_ray_pairs_cleanly_at_1080p(renderer, k):
     """All views of the multi-block models at 1920x1080 (6.2M rays): every
