@@ -310,6 +310,22 @@ def test_config4_nurbs_channel_1080p_stratified(renderer):
 
 
 @pytest.mark.parametrize("k", [3, 4])
+def test_multiblock_fp64_stratified(renderer, k):
+    """The FP64 path (FP64 face roots, pairing and integrator) on the multi-block
+    models, shared faces and NURBS blocks included, at 480x270 against the oracle on
+    a stratified sample of 4096 pixels with every 8x8 silhouette tile; every
+    crossing paired."""
+    sc = make_config(k, 480, 270)
+    cam = sc.cameras[0]
+    img, depth, st = _render(renderer, sc.patches, cam, sc.tf, precision="fp64")
+    pix, sil = _stratified_with_silhouette_tiles(cam, depth, 4096, 50 + k)
+    print(f"[parity] config{k} fp64 stratified sample: {len(pix)} pixels, {len(sil)} silhouette tiles", flush=True)
+    ref = oracle.render(sc, cam, sc.tf, pixels=pix)
+    _compare(f"config{k} fp64 480x270 stratified", img, depth, ref, pix, sc.scale)
+    assert st["anomalies"] == 0 and st["fragment_overflow"] == 0 and st["segment_overflow"] == 0
+
+
+@pytest.mark.parametrize("k", [3, 4])
 def test_every_ray_pairs_cleanly_at_1080p(renderer, k):
     """All views of the multi-block models at 1920x1080 (6.2M rays): every
     crossing is paired (rays through block edges and corners, grazing rays)."""
