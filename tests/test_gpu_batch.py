@@ -48,16 +48,19 @@ def _views(c1, c3):
     return [(cams[0], c1.tf, 0), (cams[1], tf2, 0), (cams[2], c3.tf, 1), (cams[3], c3.tf, 1)]
 
 
-def test_batch_equals_views_rendered_alone(renderer):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_equals_views_rendered_alone(renderer, precision):
+    """Four views of two models and four sizes in one graph replay give, bit for
+    bit, the images of the same views rendered alone (FP32 and FP64 paths)."""
     import torch
     c1, c3 = _small_models()
     renderer.upload_models([c1.patches, c3.patches])
     views = _views(c1, c3)
-    print("[batch] 4 views, 2 models, graph replay", flush=True)
-    outs = renderer.render_batch(views)
+    print(f"[batch] 4 views, 2 models, graph replay, {precision}", flush=True)
+    outs = renderer.render_batch(views, precision=precision)
     torch.cuda.synchronize()
     for i, v in enumerate(views):
-        alone, st = renderer.render_batch([v], stats=True)
+        alone, st = renderer.render_batch([v], stats=True, precision=precision)
         torch.cuda.synchronize()
         a_rgba, a_depth = _np(alone[0][0]), _np(alone[0][1])
         b_rgba, b_depth = _np(outs[i][0]), _np(outs[i][1])
