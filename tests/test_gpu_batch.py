@@ -71,6 +71,27 @@ def test_batch_equals_views_rendered_alone(renderer, precision):
         assert st["segments"] > 0 and st["anomalies"] == 0
 
 
+@pytest.mark.parametrize("opts", [dict(interior="rf"), dict(interior="rk4"), dict(field="param_quality"),
+                                  dict(cut_plane=((0.5, 0.5, 0.5), (0.6, -0.3, 0.74)), near_clip=0.5)],
+                         ids=["rf", "rk4", "param_quality", "planes"])
+def test_batch_options_equal_views_rendered_alone(renderer, opts):
+    """The batch path with the root-finding and fixed-step interior methods, the
+    parametrisation-quality field and the cutting and near-clip planes: each view
+    of the graph replay equals, bit for bit, the view rendered alone."""
+    import torch
+    c1, c3 = _small_models()
+    renderer.upload_models([c1.patches, c3.patches])
+    views = _views(c1, c3)
+    outs = renderer.render_batch(views, **opts)
+    torch.cuda.synchronize()
+    for i, v in enumerate(views):
+        alone, st = renderer.render_batch([v], stats=True, **opts)
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(alone[0][0]), _np(outs[i][0])), (opts, i)
+        assert np.array_equal(_np(alone[0][1]), _np(outs[i][1])), (opts, i)
+        assert st["anomalies"] == 0 and st["restart_fail"] == 0, (opts, i, st)
+
+
 def test_graph_replays_follow_the_view_table(renderer):
     """Three replays of one captured batch with the cameras moved between them and
     eager work (a single-view render, a synchronisation) in between; every replay
