@@ -60,6 +60,22 @@ def test_noalloc_fp64_matches_render(renderer):
     assert sa["segments"] == sb["segments"] and sb["segment_overflow"] == 0
 
 
+@pytest.mark.parametrize("opts", [dict(interior="rf", cut_plane=((0.5, 0.5, 0.5), (0.6, -0.3, 0.74)), near_clip=0.5),
+                                  dict(field="param_quality")], ids=["rf_planes", "param_quality"])
+def test_noalloc_matches_render_with_options(renderer, opts):
+    """Root finding with clip planes, and the parametrisation-quality field: the
+    scratch-array entry gives the allocating entry's image and counters."""
+    sc = make_config(3, 320, 180)
+    cam = sc.cameras[0]
+    renderer.upload(sc.patches)
+    (a, da, sa), (b, db, sb) = _both(renderer, sc, cam, **opts)
+    hit = np.isfinite(da)
+    assert (np.isfinite(db) == hit).all() and np.array_equal(da[hit], db[hit])
+    assert float(np.abs(a - b).max()) <= 1e-6
+    for key in ("rays", "segments", "fragments", "anomalies", "w_evals", "samples"):
+        assert sa[key] == sb[key], key
+
+
 def test_noalloc_refuses_what_does_not_fit(renderer):
     from paper_1404_3363_amd.ivr import IvrError, IVR_EOVERFLOW, IVR_EINVAL
     from scenes import camera_from_angles
