@@ -213,6 +213,43 @@ def test_tile_frustum_culling_keeps_every_candidate(renderer, tile_w):
         renderer.set_launch()
 
 
+def test_face_with_more_than_64_element_tiles(renderer):
+    """A cubic block of 40^3 control points has 37 x 37 elements per face in 100
+    element tiles, more than one 64-lane culling pass per face.  With an affine map
+    and a constant field every pixel is the closed form alpha = 1 - exp(-kappa L)
+    of the ray's chord L through the parallelepiped, with the chord's entry as
+    depth; the pixels that miss it stay empty."""
+    from scenes import affine_patch
+    A = np.array([[1.1, 0.2, 0.0], [-0.1, 0.95, 0.15], [0.05, 0.0, 1.05]])
+    b0 = np.array([-0.3, 0.1, 0.2])
+    P = affine_patch(A, b0, (3, 3, 3), (40, 40, 40), scalar=lambda g: np.full(len(g), 0.5))
+    cam = camera_from_angles(A @ np.full(3, 0.5) + b0, 3.2, 40.0, 25.0, 96, 96)
+    tf = TransferFunction(np.array([0.0, 0.5, 1.0]), np.array([[0.1, 0.2, 0.9, 0.1], [0.9, 0.5, 0.1, 0.6],
+                                                                [0.3, 0.8, 0.4, 0.9]]), 3.0, (0.0, 1.0))
+    img, depth, st = _render(renderer, [P], cam, tf, precision="fp32")
+    E = np.array([np.interp(0.5, tf.x, tf.rgba[:, c]) for c in range(4)])
+    Ainv = np.linalg.inv(A)
+    worst, worst_depth, hits = 0.0, 0.0, 0
+    for pix in range(cam.width * cam.height):
+        o, d = oracle.camera_ray(cam, pix % cam.width + 0.5, pix // cam.width + 0.5)
+        po, pd = Ainv @ (o - b0), Ainv @ d
+        t0, t1 = -np.inf, np.inf
+        for c in range(3):
+            a_, b_ = (0 - po[c]) / pd[c], (1 - po[c]) / pd[c]
+            t0, t1 = max(t0, min(a_, b_)), min(t1, max(a_, b_))
+        if not (t1 > max(t0, 0.0)):
+            assert img[pix, 3] == 0.0 and np.isinf(depth[pix]), pix
+            continue
+        hits += 1
+        a = 1.0 - math.exp(-tf.extinction * E[3] * (t1 - t0))
+        worst = max(worst, float(np.abs(img[pix] - np.concatenate([E[:3] * a, [a]])).max()))
+        worst_depth = max(worst_depth, abs(depth[pix] - t0) / t0)
+    print(f"[parity] 40^3 affine block: {hits} rays, max err {worst:.2e}, depth rel {worst_depth:.2e}, "
+          f"solves {st['face_newton']}", flush=True)
+    assert hits > 2000 and worst <= 1e-5 and worst_depth <= DEPTH_REL_TOL
+    assert st["anomalies"] == 0 and st["fragment_overflow"] == 0
+
+
 def test_degenerate_face_constant_field_closed_form(renderer):
     """Constant rho on the degenerate-face cube: alpha = 1 - exp(-kappa L) with L
     the ray-box chord of the unit cube, for both views."""
