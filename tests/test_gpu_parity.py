@@ -484,6 +484,37 @@ def test_error_codes(renderer):
         assert e.value.code == -1, opt
 
 
+_BAD_OPTIONS = [
+    {"precision": 5}, {"rk_tol": 0.0}, {"rk_tol": float("nan")}, {"h_max": float("nan")}, {"c_perp": -1.0},
+    {"n_super": 0}, {"n_super": 65}, {"det_fp64_threshold": -1.0}, {"det_singular": -1.0}, {"drift_tol": -1.0},
+    {"interior": 9}, {"interior": -1}, {"near_clip": -1.0}, {"near_clip": float("inf")},
+    {"cut_plane": ((0.5, 0.5, 0.5), (0.0, 0.0, 0.0))}, {"cut_plane": ((float("nan"), 0.5, 0.5), (1.0, 0.0, 0.0))},
+    {"max_fragments": 1}, {"max_fragments": 65}, {"rho_interp": 7}, {"seed_mode": 9}, {"early_term": 1.0},
+    {"early_term": -0.1}, {"max_newton_iter": 0}, {"max_newton_iter": 101}, {"field": 3}, {"newton_stop": 2},
+    {"field": "param_quality", "interior": "rk4"},
+]
+
+
+def test_options_out_of_range_are_refused(renderer):
+    """Every option outside its documented range is refused with IVR_EINVAL before
+    anything is launched, and the context renders as before afterwards."""
+    import torch
+    from paper_1404_3363_amd import IvrError
+    sc = make_config(1)
+    cam = sc.cameras[0]
+    renderer.upload(sc.patches)
+    before, d0, _ = renderer.render(cam, sc.tf, stats=True)
+    torch.cuda.synchronize()
+    before = before.cpu().numpy().copy()
+    for opt in _BAD_OPTIONS:
+        with pytest.raises(IvrError) as e:
+            renderer.render(cam, sc.tf, **opt)
+        assert e.value.code == -1, opt
+    after, d1, _ = renderer.render(cam, sc.tf, stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(before, after.cpu().numpy())
+
+
 def test_sampling_options_follow_their_definitions(renderer):
     """h_max and rho_step bound the RK steps, tf_step the supersampling sub-steps:
     tighter bounds take more steps / sub-steps and the image stays within the bar."""
