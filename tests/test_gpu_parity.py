@@ -515,6 +515,56 @@ def test_options_out_of_range_are_refused(renderer):
     assert np.array_equal(before, after.cpu().numpy())
 
 
+def _bad_patches():
+    """Blocks that break one documented rule each (arrays sized for what the
+    library reads before it refuses them)."""
+    import dataclasses
+    from scenes import affine_patch
+    P = make_config(1).patches[0]
+    out = []
+    for deg in ((0, 2, 2), (4, 2, 2)):
+        out.append(("degree", dataclasses.replace(P, degree=deg)))
+    out.append(("ncp", dataclasses.replace(P, ncp=(2, 4, 4))))
+    k = [np.array(x, dtype=np.float64) for x in P.knots]
+    out.append(("not clamped", dataclasses.replace(P, knots=[np.array([0, 0, 0.1, 0.5, 1, 1, 1.0]), k[1], k[2]])))
+    out.append(("empty span", dataclasses.replace(P, knots=[np.zeros(7), k[1], k[2]])))
+    Q = affine_patch(np.eye(3), np.zeros(3), (2, 2, 2), (6, 4, 4))
+    out.append(("multiplicity", dataclasses.replace(Q, knots=[np.array([0, 0, 0, 0.5, 0.5, 0.5, 1, 1, 1.0])] +
+                                                       list(Q.knots[1:]))))
+    cp = P.cp.copy(); cp[5, 1] = np.nan
+    out.append(("nan point", dataclasses.replace(P, cp=cp)))
+    sc = P.scalar.copy(); sc[7] = np.nan
+    out.append(("nan scalar", dataclasses.replace(P, scalar=sc)))
+    cp = P.cp.copy(); cp[3, 3] = 0.0
+    out.append(("zero weight", dataclasses.replace(P, cp=cp, rational=True)))
+    du = np.zeros((len(P.scalar), 3)); du[9, 2] = np.inf
+    out.append(("displacement", dataclasses.replace(P, displacement=du)))
+    return out
+
+
+def test_invalid_blocks_are_refused(renderer):
+    """Every block that breaks a documented rule (degree 1..3, ncp >= degree+1,
+    clamped non-decreasing knots with a non-empty span and interior multiplicity
+    at most the degree, finite points and field, positive NURBS weights, finite
+    displacement) is refused with IVR_EINVAL, and the model uploaded before stays
+    in place."""
+    import torch
+    from paper_1404_3363_amd import IvrError
+    sc = make_config(1)
+    cam = sc.cameras[0]
+    renderer.upload(sc.patches)
+    before, _, _ = renderer.render(cam, sc.tf, stats=True)
+    torch.cuda.synchronize()
+    before = before.cpu().numpy().copy()
+    for name, bad in _bad_patches():
+        with pytest.raises(IvrError) as e:
+            renderer.upload([bad])
+        assert e.value.code == -1, name
+    after, _, _ = renderer.render(cam, sc.tf, stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(before, after.cpu().numpy())
+
+
 def test_sampling_options_follow_their_definitions(renderer):
     """h_max and rho_step bound the RK steps, tf_step the supersampling sub-steps:
     tighter bounds take more steps / sub-steps and the image stays within the bar."""
