@@ -565,6 +565,32 @@ def test_invalid_blocks_are_refused(renderer):
     assert np.array_equal(before, after.cpu().numpy())
 
 
+def test_invalid_cameras_are_refused(renderer):
+    """Cameras outside the documented ranges (image 1..16384 pixels a side, field
+    of view in (0, 179) degrees, finite vectors, eye apart from the target, up not
+    along the view) are refused with IVR_EINVAL; the next valid render is as before."""
+    import dataclasses
+    import torch
+    from paper_1404_3363_amd import IvrError
+    sc = make_config(1)
+    cam = sc.cameras[0]
+    renderer.upload(sc.patches)
+    before, _, _ = renderer.render(cam, sc.tf, stats=True)
+    torch.cuda.synchronize()
+    before = before.cpu().numpy().copy()
+    view = np.asarray(cam.target, dtype=np.float64) - np.asarray(cam.eye, dtype=np.float64)
+    bad = [dict(width=0), dict(width=4, height=20000), dict(fov_y_deg=0.0), dict(fov_y_deg=179.5),
+           dict(eye=np.array([np.nan, 0.0, 0.0])), dict(eye=np.asarray(cam.target, dtype=np.float64)),
+           dict(up=view)]
+    for kw in bad:
+        with pytest.raises(IvrError) as e:
+            renderer.render(dataclasses.replace(cam, **kw), sc.tf)
+        assert e.value.code == -1, kw
+    after, _, _ = renderer.render(cam, sc.tf, stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(before, after.cpu().numpy())
+
+
 def test_sampling_options_follow_their_definitions(renderer):
     """h_max and rho_step bound the RK steps, tf_step the supersampling sub-steps:
     tighter bounds take more steps / sub-steps and the image stays within the bar."""
